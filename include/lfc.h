@@ -1,0 +1,214 @@
+/*
+ * lfc.h -- C ABI of liblfc.so, an MI355X (gfx950) implementation of the
+ * decode-and-render path of RLFC (Pratapa & Manocha, "RLFC: Random Access
+ * Light Field Compression using Key Views and Bounded Integer Sequence
+ * Encoding", I3D 2019, arXiv 1805.06019).
+ *
+ * Conventions for every call:
+ *  - Pointers prefixed d_ are device pointers (hipMalloc'd or torch CUDA
+ *    tensors) on the current device; every other pointer is host memory.
+ *  - The caller owns every buffer it passes.  Output buffers must not alias
+ *    inputs.
+ *  - Every call returns an lfc_status; on a non-OK status the call has no
+ *    effect on its outputs (host-side checks happen before any launch) and
+ *    lfc_last_error() returns a message (thread-local).  No C++ exception
+ *    crosses this interface.
+ *  - Device work is enqueued on the stream argument and the call returns
+ *    without waiting, except lfc_open and lfc_check, which synchronise it.
+ *  - All multi-byte integers of the stream format are little-endian.
+ */
+#ifndef LFC_H
+#define LFC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LFC_OK = 0,
+  LFC_E_INVALID = -1,      /* bad argument (null pointer, size, layout, parameter) */
+  LFC_E_CORRUPT = -2,      /* stream fails validation */
+  LFC_E_NOMEM = -3,        /* host or device allocation failed */
+  LFC_E_HIP = -4,          /* a HIP runtime call or kernel launch failed */
+  LFC_E_RANGE = -5,        /* a residual needs a BISE range above 4096 values */
+  LFC_E_UNSUPPORTED = -6   /* valid request this build cannot serve */
+} lfc_status;
+
+#define LFC_MAX_LEVELS 6
+
+/*
+ * Encoding parameters -- the "enc" argument of CompressLFI (Alg. 1).
+ *  grid_u, grid_v  views per row (u, the column index) and rows of views (v);
+ *                  view index vi = v * grid_u + u.  1..4096 each.
+ *  width, height   pixels per view, 1..65536 each.
+ *  block           B, side of the square residual blocks (Sec. 3.2): 2, 4 or 8.
+ *  levels          L, tree height counting the original views as level 0
+ *                  (Sec. 3.1, Table 2): 1..6.  Level L-1 holds the stored
+ *                  key views (RKV); levels 0..L-2 hold residual views (SRV).
+ *  cluster[l-1]    side c_l of the square clusters that group level l-1 into
+ *                  level l (eq. 1), l = 1..L-1; 2..8.  Clusters tile the grid
+ *                  from (0,0) and are truncated at its edges.
+ *  pix_threshold   residual samples with |r| below it are zeroed (Sec. 3.2).
+ *  blk_threshold   blocks whose sum of |r| is not above it are dropped (Sec. 3.2).
+ *  quant_bits      q: kept residuals are quantised with step 2^q, 0..4 (Sec. 3.2).
+ *  range_mask      allowed BISE range codes, bit k for code k (0..25); 0 = all.
+ */
+typedef struct {
+  int32_t grid_u, grid_v;
+  int32_t width, height;
+  int32_t block;
+  int32_t levels;
+  int32_t cluster[LFC_MAX_LEVELS];
+  int32_t pix_threshold;
+  int32_t blk_threshold;
+  int32_t quant_bits;
+  uint32_t range_mask;
+} lfc_params;
+
+/*
+ * A novel camera (Sec. 3.6): (u, v) is a position on the camera plane in
+ * grid units (u along a row of views, 0..grid_u-1; values outside are
+ * clamped); (s, t) pans the image plane by that many source pixels.
+ */
+typedef struct {
+  float u, v, s, t;
+} lfc_view;
+
+/* Opaque handle: one compressed light field resident in device memory. */
+typedef struct lfc_lf lfc_lf;
+
+/* Facts about an opened light field. */
+typedef struct {
+  lfc_params params;
+  int32_t padded_width, padded_height;   /* width, height rounded up to B */
+  int32_t n_blocks;                      /* NB = (padded_width/B)*(padded_height/B) */
+  int32_t n_groups;                      /* 3*NB: one per (spatial block, channel) */
+  int32_t n_srv;                         /* residual-view nodes in the tree */
+  int32_t n_top;                         /* stored key views */
+  uint64_t stream_bytes;                 /* size of the stream it was opened from */
+  uint64_t device_bytes;                 /* device memory held by the handle */
+  uint64_t present_blocks;               /* stored residual blocks over all groups */
+} lfc_info_t;
+
+enum { LFC_LAYOUT_BLOCKS = 0, LFC_LAYOUT_IMAGES = 1 };
+
+/*
+ * CompressLFI (Alg. 1; Sec. 3.1-3.4), on the host.
+ *  rgb      host, uint8 [grid_v][grid_u][height][width][3], RGB.
+ *  p        parameters as above.
+ *  *stream_out receives a library-allocated host buffer holding the stream
+ *           (header, RKVStream, BlockOffsets, SRVStream); free it with
+ *           lfc_free.  *bytes_out receives its size.
+ * Errors: LFC_E_INVALID (null pointer, parameter out of range),
+ * LFC_E_RANGE (a residual block needs more than 4096 BISE values, or a
+ * reconstruction leaves int16), LFC_E_NOMEM.
+ */
+lfc_status lfc_encode(const uint8_t *rgb, const lfc_params *p, void **stream_out,
+                      size_t *bytes_out);
+
+/* Quality and rate of an encoding, from the encoder's own reconstruction
+ * (which every decode reproduces exactly). */
+typedef struct {
+  double psnr;             /* PSNR_YCoCg of eq. 4 from eq. 5 (peak 255, 100 dB cap), mean over views */
+  double psnr_y, psnr_co, psnr_cg;  /* per-channel PSNR, mean over views */
+  uint64_t present_blocks; /* stored residual blocks */
+  uint64_t code_hist[26];  /* stored residual blocks per BISE range code */
+  uint64_t stream_bytes;   /* size of the stream */
+} lfc_encode_stats;
+
+/*
+ * lfc_encode that also reports quality and rate (Sec. 4, eqs. 4-5), for
+ * choosing thresholds.  stream_out and bytes_out may both be NULL to get the
+ * statistics only; stats may be NULL.  Errors as lfc_encode.
+ */
+lfc_status lfc_encode_ex(const uint8_t *rgb, const lfc_params *p, void **stream_out, size_t *bytes_out,
+                         lfc_encode_stats *stats);
+
+/* Frees a buffer returned by lfc_encode.  NULL is ignored. */
+void lfc_free(void *ptr);
+
+/*
+ * Checks a stream on the host without touching a device: header, section
+ * sizes, monotone offsets, every group's bitmap, range codes and payload
+ * length, and every BISE digit field.  p_out (may be NULL) receives the
+ * stream's parameters.  Errors: LFC_E_INVALID (null pointer),
+ * LFC_E_CORRUPT.
+ */
+lfc_status lfc_validate(const void *stream, size_t bytes, lfc_params *p_out);
+
+/*
+ * Decoder initialisation (Alg. 2 "Initialization"; Sec. 3.5, which computes
+ * block and parent locations once at start-up).  Validates the stream as
+ * lfc_validate does, builds the per-group block directory and the tree
+ * tables, copies everything to the current device on stream s and waits for
+ * the copies.  The host stream may be freed after the call returns.
+ * *out receives the handle.  Errors: LFC_E_INVALID, LFC_E_CORRUPT,
+ * LFC_E_NOMEM, LFC_E_HIP.
+ */
+lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, lfc_lf **out);
+
+/* Fills *info.  Errors: LFC_E_INVALID. */
+lfc_status lfc_info(const lfc_lf *lf, lfc_info_t *info);
+
+/*
+ * DecompressLFIBlock (Alg. 2) for a batch of blocks, decoded in parallel
+ * (Sec. 3.6): each output block is the top key-view block plus the dequantised
+ * residual blocks of its ancestors down to level 0 (Sec. 3.5), as int16 YCoCg-R
+ * samples (Sec. 4), not clamped.
+ *  d_req    device int32 [n][2] = {view index vi, block index b}, b row-major
+ *           over the padded image's B x B blocks; or NULL for every block.
+ *  n        number of requests; with d_req == NULL it must equal
+ *           grid_u*grid_v*n_blocks (BLOCKS) or grid_u*grid_v (IMAGES).
+ *           n == 0 with the BLOCKS layout does nothing (d_req may then be
+ *           NULL, as an empty tensor's pointer is).
+ *  layout   LFC_LAYOUT_BLOCKS: d_out is int16 [n][3][B][B], request order
+ *           (d_req == NULL: order vi-major then b).
+ *           LFC_LAYOUT_IMAGES (requires d_req == NULL): d_out is int16
+ *           [grid_u*grid_v][3][padded_height][padded_width].
+ * A request with vi or b out of range yields zeros and raises the handle's
+ * device error flag, reported by lfc_check.  Errors: LFC_E_INVALID,
+ * LFC_E_UNSUPPORTED (whole-field decode of a tree too large for on-chip
+ * tables), LFC_E_HIP.
+ */
+lfc_status lfc_decode_blocks(const lfc_lf *lf, const int32_t *d_req, int64_t n, int32_t layout,
+                             int16_t *d_out, hipStream_t s);
+
+/*
+ * Novel-view rendering (Sec. 3.6): every output pixel is the quadrilinear
+ * interpolation, over the two nearest camera columns, the two nearest
+ * camera rows and the 2 x 2 nearest source pixels, of decoded samples
+ * converted to RGB (inverse YCoCg-R, clamped to 0..255).  Source pixel
+ * coordinates of output pixel (X, Y) are s + (X+0.5)*width/out_w - 0.5 and
+ * t + (Y+0.5)*height/out_h - 0.5, clamped to the image.  The blocks under
+ * each output tile are decoded on the fly.
+ *  d_views  device lfc_view [n].
+ *  d_out    device float32 [n][3][out_h][out_w], RGB / 255.
+ * Errors: LFC_E_INVALID (null pointer, n < 0, out_w or out_h < 1 or
+ * > 16384), LFC_E_HIP.
+ */
+lfc_status lfc_render_views(const lfc_lf *lf, const lfc_view *d_views, int32_t n, int32_t out_w,
+                            int32_t out_h, float *d_out, hipStream_t s);
+
+/*
+ * Waits for stream s, then reads and clears the handle's device error flag.
+ * Returns LFC_E_INVALID if a decode since the last check saw an
+ * out-of-range request, LFC_E_HIP on a runtime error, else LFC_OK.
+ */
+lfc_status lfc_check(const lfc_lf *lf, hipStream_t s);
+
+/* Frees the handle and its device memory.  Work using it must have
+ * completed.  NULL is ignored. */
+lfc_status lfc_close(lfc_lf *lf);
+
+/* Message for the last non-OK status returned on this thread. */
+const char *lfc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

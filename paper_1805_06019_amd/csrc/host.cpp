@@ -1,0 +1,859 @@
+// Host side of liblfc.so: parameters and geometry, the encoder (CompressLFI,
+// Alg. 1), the stream validator, and decoder initialisation (Alg. 2
+// "Initialization"), which also builds the block directory used for random
+// access.  See include/lfc.h for the contract of every exported call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <new>
+#include <thread>
+
+#include "internal.h"
+
+namespace lfc {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_last_error;
+
+lfc_status fail(lfc_status st, const std::string &msg) {
+  g_last_error = msg;
+  return st;
+}
+
+static std::string fmt(const char *f, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, f);
+  vsnprintf(buf, sizeof buf, f, ap);
+  va_end(ap);
+  return buf;
+}
+
+// ---------------------------------------------------------------------------
+// small parallel-for over [0, n) with a shared atomic cursor
+// ---------------------------------------------------------------------------
+
+static int worker_count() {
+  unsigned hw = std::thread::hardware_concurrency();
+  int n = hw ? (int)hw : 1;
+  if (const char *e = getenv("OMP_NUM_THREADS")) {
+    int v = atoi(e);
+    if (v > 0) n = std::min(n, v);
+  }
+  return std::max(1, std::min(n, 16));
+}
+
+static void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, int64_t)> &fn) {
+  const int nt = worker_count();
+  if (nt == 1 || n <= grain) {
+    fn(0, n);
+    return;
+  }
+  std::atomic<int64_t> next{0};
+  auto work = [&] {
+    for (;;) {
+      int64_t a = next.fetch_add(grain);
+      if (a >= n) break;
+      fn(a, std::min(n, a + grain));
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; t++) pool.emplace_back(work);
+  work();
+  for (auto &t : pool) t.join();
+}
+
+// ---------------------------------------------------------------------------
+// geometry, range codes, tree
+// ---------------------------------------------------------------------------
+
+lfc_status make_geometry(const lfc_params &p, Geometry &g, std::string *why) {
+  auto bad = [&](const std::string &m) {
+    if (why) *why = m;
+    return LFC_E_INVALID;
+  };
+  if (p.grid_u < 1 || p.grid_v < 1 || p.grid_u > 4096 || p.grid_v > 4096) return bad("grid_u/grid_v must be 1..4096");
+  if (p.width < 1 || p.height < 1 || p.width > 65536 || p.height > 65536) return bad("width/height must be 1..65536");
+  if (p.block != 2 && p.block != 4 && p.block != 8) return bad("block must be 2, 4 or 8");
+  if (p.levels < 1 || p.levels > kMaxLevels) return bad("levels must be 1..6");
+  if (p.pix_threshold < 0 || p.blk_threshold < 0) return bad("thresholds must be >= 0");
+  if (p.quant_bits < 0 || p.quant_bits > 4) return bad("quant_bits must be 0..4");
+  if (p.range_mask & ~kAllCodes) return bad("range_mask has bits above code 25");
+  g = Geometry();
+  g.U = p.grid_u;
+  g.V = p.grid_v;
+  g.W = p.width;
+  g.H = p.height;
+  g.B = p.block;
+  g.S = p.block * p.block;
+  g.L = p.levels;
+  g.q = p.quant_bits;
+  g.wp = (p.width + p.block - 1) / p.block * p.block;
+  g.hp = (p.height + p.block - 1) / p.block * p.block;
+  g.nbx = g.wp / g.B;
+  g.nby = g.hp / g.B;
+  if ((int64_t)g.nbx * g.nby * 3 > (int64_t)1 << 30) return bad("image too large");
+  if ((int64_t)g.U * g.V * g.hp * g.wp * 3 > ((int64_t)1 << 40)) return bad("light field too large");
+  g.nb = g.nbx * g.nby;
+  g.ng = 3 * g.nb;
+  g.lu[0] = g.U;
+  g.lv[0] = g.V;
+  for (int l = 1; l < g.L; l++) {
+    int c = p.cluster[l - 1];
+    if (c < 2 || c > 8) return bad("cluster sides must be 2..8");
+    g.c[l] = c;
+    g.lu[l] = (g.lu[l - 1] + c - 1) / c;
+    g.lv[l] = (g.lv[l - 1] + c - 1) / c;
+  }
+  int64_t nsrv = 0;
+  for (int l = 0; l + 1 < g.L; l++) nsrv += (int64_t)g.lu[l] * g.lv[l];
+  if (nsrv > (1 << 20)) return bad("tree too large");
+  g.n_srv = (int)nsrv;
+  g.n_top = g.lu[g.L - 1] * g.lv[g.L - 1];
+  g.nbw = (g.n_srv + 31) / 32;
+  return LFC_OK;
+}
+
+// Range code k: 0..11 plain bits m = k+1; 12..18 trits m = k-12; 19..25
+// quints m = k-19.  A block is the digit plane (one base-3 field per 5 values
+// or base-5 field per 3 values) followed by S fields of m low bits.
+struct RangeCode {
+  int kind;    // 0 bits, 1 trit, 2 quint
+  int m;
+  int bound;   // number of representable values
+};
+
+static RangeCode range_code(int k) {
+  if (k < 12) return {0, k + 1, 1 << (k + 1)};
+  if (k < 19) return {1, k - 12, 3 << (k - 12)};
+  return {2, k - 19, 5 << (k - 19)};
+}
+
+static int digit_plane_bits(int kind, int S) {
+  if (kind == 1) return (8 * S + 4) / 5;   // ceil(8S/5): 5 trits in 8 bits
+  if (kind == 2) return (7 * S + 2) / 3;   // ceil(7S/3): 3 quints in 7 bits
+  return 0;
+}
+
+int bise_block_bits(int code, int S) {
+  RangeCode r = range_code(code);
+  return S * r.m + digit_plane_bits(r.kind, S);
+}
+
+// Breadth-first serial numbering of the tree (Sec. 3.4): the top-level nodes
+// in row-major order, then, level by level, the children of each dequeued
+// node in row-major order within its cluster.
+void build_tree_tables(const Geometry &g, TreeTables &t) {
+  const int L = g.L, nv = g.nv();
+  t.serial.assign(L, {});
+  for (int l = 0; l < L; l++) t.serial[l].assign((size_t)g.lu[l] * g.lv[l], -1);
+  std::vector<std::pair<int, int>> fifo;
+  fifo.reserve((size_t)g.n_srv + g.n_top);
+  for (int i = 0; i < g.n_top; i++) fifo.push_back({L - 1, i});
+  int32_t counter = 0;
+  for (size_t head = 0; head < fifo.size(); head++) {
+    auto [l, id] = fifo[head];
+    if (l < L - 1) t.serial[l][id] = counter++;
+    if (l == 0) continue;
+    const int c = g.c[l], px = id % g.lu[l], py = id / g.lu[l];
+    for (int yy = py * c; yy < std::min(py * c + c, g.lv[l - 1]); yy++)
+      for (int xx = px * c; xx < std::min(px * c + c, g.lu[l - 1]); xx++)
+        fifo.push_back({l - 1, yy * g.lu[l - 1] + xx});
+  }
+  const int depth = std::max(L - 1, 0), stride = std::max(depth, 1);
+  t.path.assign((size_t)nv * stride, 0);
+  t.root.assign(nv, 0);
+  for (int vi = 0; vi < nv; vi++) {
+    int x = vi % g.U, y = vi / g.U;
+    for (int l = 0; l < L; l++) {
+      if (l > 0) {
+        x /= g.c[l];
+        y /= g.c[l];
+      }
+      const int id = y * g.lu[l] + x;
+      if (l < L - 1) t.path[(size_t)vi * stride + l] = t.serial[l][id];
+      else t.root[vi] = id;
+    }
+  }
+  // leaves in serial order, each with its root and its path from the top down
+  std::vector<int32_t> order(nv);
+  for (int vi = 0; vi < nv; vi++) order[vi] = vi;
+  if (L > 1)
+    std::sort(order.begin(), order.end(),
+              [&](int a, int b) { return t.path[(size_t)a * stride] < t.path[(size_t)b * stride]; });
+  t.leaf.assign((size_t)nv * (L + 1), 0);
+  for (int k = 0; k < nv; k++) {
+    const int vi = order[k];
+    int32_t *rec = &t.leaf[(size_t)k * (L + 1)];
+    rec[0] = vi;
+    rec[1] = t.root[vi];
+    for (int i = 0; i < L - 1; i++) rec[2 + i] = t.path[(size_t)vi * stride + (L - 2 - i)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// encoder
+// ---------------------------------------------------------------------------
+
+// ORs a value of at most 32 bits into a zeroed word array at bit position pos.
+static inline void put_field(uint32_t *w, uint64_t pos, uint32_t v) {
+  const uint64_t x = (uint64_t)v << (pos & 31);
+  w[pos >> 5] |= (uint32_t)x;
+  if (x >> 32) w[(pos >> 5) + 1] |= (uint32_t)(x >> 32);
+}
+
+static inline int32_t floor_div(int64_t x, int64_t d) {
+  return (int32_t)(x >= 0 ? x / d : -((-x + d - 1) / d));
+}
+
+static inline uint16_t zz_encode(int32_t v) { return (uint16_t)(((uint32_t)v << 1) ^ (uint32_t)(v >> 31)); }
+
+// BISE packing of one block (Sec. 3.3): digit plane, then low-bit plane.
+static uint64_t pack_block(uint32_t *w, uint64_t pos, const uint16_t *z, int S, int code) {
+  const RangeCode rc = range_code(code);
+  if (rc.kind) {
+    const int glen = rc.kind == 1 ? 5 : 3, radix = rc.kind == 1 ? 3 : 5, full = rc.kind == 1 ? 8 : 7;
+    for (int i0 = 0; i0 < S; i0 += glen) {
+      const int k = std::min(glen, S - i0);
+      uint32_t num = 0;
+      for (int r = k - 1; r >= 0; r--) num = num * radix + (uint32_t)(z[i0 + r] >> rc.m);
+      put_field(w, pos, num);
+      pos += (full * k + glen - 1) / glen;
+    }
+  }
+  const uint32_t lowmask = (1u << rc.m) - 1u;
+  for (int i = 0; i < S; i++, pos += rc.m)
+    if (rc.m) put_field(w, pos, z[i] & lowmask);
+  return pos;
+}
+
+static void put_header(uint8_t *h, const Geometry &g, const lfc_params &p, uint32_t mask,
+                       uint64_t rkv_off, uint64_t off_off, uint64_t srv_off) {
+  std::memset(h, 0, kHeaderBytes);
+  std::memcpy(h, "RLFC", 4);
+  const uint16_t ver[2] = {1, (uint16_t)kHeaderBytes};
+  std::memcpy(h + 4, ver, 4);
+  int32_t f[23] = {g.U, g.V, g.W, g.H, g.wp, g.hp, g.B, g.L, g.q, 3, 0, 0, 0, 0, 0, 0,
+                   p.pix_threshold, p.blk_threshold, (int32_t)mask, g.n_srv, g.n_top, g.nb, g.ng};
+  for (int l = 1; l < g.L; l++) f[10 + l - 1] = g.c[l];
+  std::memcpy(h + 8, f, sizeof f);
+  const uint64_t o[3] = {rkv_off, off_off, srv_off};
+  std::memcpy(h + 104, o, sizeof o);
+}
+
+static lfc_status encode_impl(const uint8_t *rgb, const lfc_params &p, std::vector<uint8_t> *out,
+                              lfc_encode_stats *stats) {
+  Geometry g;
+  std::string why;
+  if (make_geometry(p, g, &why) != LFC_OK) return fail(LFC_E_INVALID, "lfc_encode: " + why);
+  const uint32_t mask = p.range_mask ? p.range_mask : kAllCodes;
+  const int B = g.B, S = g.S, L = g.L, q = g.q, nv = g.nv();
+  const int64_t plane = (int64_t)g.hp * g.wp, img = 3 * plane;
+
+  // Level 0: padded YCoCg-R planes [nv][3][hp][wp] (Sec. 4), edge replication.
+  std::vector<std::vector<int16_t>> lvl(L);
+  lvl[0].resize((size_t)nv * img);
+  parallel_for((int64_t)nv * g.hp, 64, [&](int64_t a, int64_t e) {
+    for (int64_t r = a; r < e; r++) {
+      const int vi = (int)(r / g.hp), y = (int)(r % g.hp);
+      const int sy = std::min(y, g.H - 1);
+      int16_t *dst = &lvl[0][(size_t)vi * img + (size_t)y * g.wp];
+      for (int x = 0; x < g.wp; x++) {
+        const uint8_t *px = rgb + (((size_t)vi * g.H + sy) * g.W + std::min(x, g.W - 1)) * 3;
+        const int co = px[0] - px[2];
+        const int t = px[2] + (co >> 1);
+        const int cg = px[1] - t;
+        dst[x] = (int16_t)(t + (cg >> 1));
+        dst[x + plane] = (int16_t)co;
+        dst[x + 2 * plane] = (int16_t)cg;
+      }
+    }
+  });
+
+  // Stage I: RKV^l = cluster mean of level l-1 with binomial weights (eqs. 1-2),
+  // rounded to nearest (half up) over the members that exist.
+  for (int l = 1; l < L; l++) {
+    const int c = g.c[l], nodes = g.lu[l] * g.lv[l];
+    int64_t pascal[9] = {1};
+    for (int i = 1; i < c; i++)
+      for (int k = i; k >= 1; k--) pascal[k] += pascal[k - 1];
+    lvl[l].resize((size_t)nodes * img);
+    parallel_for((int64_t)nodes * 3 * g.hp, 16, [&](int64_t a, int64_t e) {
+      for (int64_t r = a; r < e; r++) {
+        const int node = (int)(r / (3 * g.hp)), ch = (int)(r / g.hp % 3), y = (int)(r % g.hp);
+        const int nx = node % g.lu[l], ny = node / g.lu[l];
+        const int16_t *src[64];
+        int64_t wgt[64];
+        int cnt = 0;
+        int64_t wsum = 0;
+        for (int yy = ny * c; yy < std::min(ny * c + c, g.lv[l - 1]); yy++)
+          for (int xx = nx * c; xx < std::min(nx * c + c, g.lu[l - 1]); xx++) {
+            src[cnt] = &lvl[l - 1][(size_t)(yy * g.lu[l - 1] + xx) * img + (size_t)ch * plane + (size_t)y * g.wp];
+            wgt[cnt] = pascal[xx - nx * c] * pascal[yy - ny * c];
+            wsum += wgt[cnt++];
+          }
+        int16_t *dst = &lvl[l][(size_t)node * img + (size_t)ch * plane + (size_t)y * g.wp];
+        for (int x = 0; x < g.wp; x++) {
+          int64_t acc = wsum / 2;
+          for (int k = 0; k < cnt; k++) acc += wgt[k] * src[k][x];
+          dst[x] = (int16_t)floor_div(acc, wsum);
+        }
+      }
+    });
+  }
+
+  TreeTables tt;
+  build_tree_tables(g, tt);
+
+  // allowed ranges by increasing size; a block takes the first that holds its values
+  std::vector<std::pair<int, int>> ranges;
+  for (int k = 0; k < kNumCodes; k++)
+    if ((mask >> k) & 1u) ranges.push_back({range_code(k).bound, k});
+  std::sort(ranges.begin(), ranges.end());
+
+  // Stage II: closed-loop residual tree, top down (eq. 3 and the re-computed
+  // RKVs of Sec. 3.2).  code_tab[g*n_srv + s] = range code or -1,
+  // zv[(g*n_srv + s)*S + i] = zigzagged quantised residuals.
+  const size_t nsg = (size_t)g.ng * g.n_srv;
+  std::vector<int8_t> code_tab(std::max<size_t>(nsg, 1), -1);
+  std::vector<uint16_t> zv(std::max<size_t>(nsg * S, 1), 0);
+  std::vector<std::vector<int16_t>> rec(L);
+  std::atomic<int> err{0};
+  for (int l = L - 2; l >= 0; l--) {
+    const int nodes = g.lu[l] * g.lv[l], cp = g.c[l + 1];
+    rec[l].resize((size_t)nodes * img);
+    const std::vector<int16_t> &prec = (l + 1 == L - 1) ? lvl[L - 1] : rec[l + 1];
+    parallel_for((int64_t)nodes * g.nb, 256, [&](int64_t a, int64_t e) {
+      for (int64_t r = a; r < e && !err.load(std::memory_order_relaxed); r++) {
+        const int node = (int)(r / g.nb), b = (int)(r % g.nb);
+        const int nx = node % g.lu[l], ny = node / g.lu[l];
+        const int parent = (ny / cp) * g.lu[l + 1] + nx / cp;
+        const int sidx = tt.serial[l][node];
+        const int bx = b % g.nbx, by = b / g.nbx;
+        for (int ch = 0; ch < 3; ch++) {
+          const size_t base = (size_t)ch * plane + (size_t)by * B * g.wp + (size_t)bx * B;
+          const int16_t *own = &lvl[l][(size_t)node * img + base];
+          const int16_t *par = &prec[(size_t)parent * img + base];
+          int16_t *dst = &rec[l][(size_t)node * img + base];
+          int32_t qv[64];
+          int64_t energy = 0;
+          for (int i = 0; i < S; i++) {
+            const size_t d = (size_t)(i / B) * g.wp + i % B;
+            int32_t v = (int32_t)own[d] - (int32_t)par[d];
+            if (std::abs(v) < p.pix_threshold) v = 0;   // pixel-level threshold
+            qv[i] = v;
+            energy += std::abs(v);
+          }
+          bool keep = energy > p.blk_threshold;          // block-energy threshold
+          uint32_t zmax = 0;
+          if (keep) {
+            bool nz = false;
+            for (int i = 0; i < S; i++) {
+              if (q) {
+                const int32_t mag = (std::abs(qv[i]) + (1 << (q - 1))) >> q;
+                qv[i] = qv[i] < 0 ? -mag : mag;
+              }
+              nz |= qv[i] != 0;
+              zmax = std::max<uint32_t>(zmax, zz_encode(qv[i]));
+            }
+            keep = nz;
+          }
+          int code = -1;
+          if (keep) {
+            for (const auto &rg : ranges)
+              if ((uint32_t)rg.first > zmax) {
+                code = rg.second;
+                break;
+              }
+            if (code < 0) {
+              err.store(1);
+              return;
+            }
+            const size_t key = (size_t)(3 * b + ch) * g.n_srv + sidx;
+            code_tab[key] = (int8_t)code;
+            for (int i = 0; i < S; i++) zv[key * S + i] = zz_encode(qv[i]);
+          }
+          for (int i = 0; i < S; i++) {
+            const size_t d = (size_t)(i / B) * g.wp + i % B;
+            const int32_t v = (int32_t)par[d] + (keep ? qv[i] * (1 << q) : 0);
+            if (v < -32768 || v > 32767) {
+              err.store(2);
+              return;
+            }
+            dst[d] = (int16_t)v;
+          }
+        }
+      }
+    });
+    if (err.load()) break;
+    if (l + 1 < L - 1) std::vector<int16_t>().swap(rec[l + 1]);  // no longer needed
+  }
+  if (err.load() == 1) return fail(LFC_E_RANGE, "lfc_encode: a residual block needs a BISE range the mask does not allow");
+  if (err.load() == 2) return fail(LFC_E_RANGE, "lfc_encode: a reconstructed sample leaves int16");
+  if (stats) {
+    // eq. 5 per view and channel on the unpadded area, eq. 4, mean over views
+    const std::vector<int16_t> &r0 = L > 1 ? rec[0] : lvl[0];
+    std::vector<double> ps((size_t)nv * 3);
+    parallel_for(nv * 3, 1, [&](int64_t a, int64_t e) {
+      for (int64_t r = a; r < e; r++) {
+        const size_t o = (size_t)r * plane;
+        double se = 0;
+        for (int y = 0; y < g.H; y++)
+          for (int x = 0; x < g.W; x++) {
+            const double d = (double)r0[o + (size_t)y * g.wp + x] - (double)lvl[0][o + (size_t)y * g.wp + x];
+            se += d * d;
+          }
+        const double mse = se / ((double)g.W * g.H);
+        ps[r] = mse > 0 ? std::min(100.0, 10.0 * std::log10(255.0 * 255.0 / mse)) : 100.0;
+      }
+    });
+    double sy = 0, sco = 0, scg = 0, sall = 0;
+    for (int vi = 0; vi < nv; vi++) {
+      sy += ps[3 * vi];
+      sco += ps[3 * vi + 1];
+      scg += ps[3 * vi + 2];
+      sall += (6 * ps[3 * vi] + ps[3 * vi + 1] + ps[3 * vi + 2]) / 8;
+    }
+    stats->psnr = sall / nv;
+    stats->psnr_y = sy / nv;
+    stats->psnr_co = sco / nv;
+    stats->psnr_cg = scg / nv;
+    std::fill(stats->code_hist, stats->code_hist + kNumCodes, 0);
+    stats->present_blocks = 0;
+    for (size_t i = 0; i < nsg; i++)
+      if (code_tab[i] >= 0) {
+        stats->code_hist[code_tab[i]]++;
+        stats->present_blocks++;
+      }
+  }
+  for (int l = 0; l < L - 1; l++) std::vector<int16_t>().swap(lvl[l]);
+  rec.clear();
+
+  // Stage III: location-gathered SRV stream (Sec. 3.4, Alg. 1).  Group
+  // g = 3*b + c holds, for every node with a stored block at location b,
+  // channel c: a bitmap of the nodes, their 5-bit range codes, then their
+  // BISE payloads, in serial order.  An empty group stores nothing.
+  std::vector<uint64_t> gwords(g.ng + 1, 0);
+  parallel_for(g.ng, 64, [&](int64_t a, int64_t e) {
+    for (int64_t gi = a; gi < e; gi++) {
+      uint64_t present = 0, bits = 0;
+      const int8_t *ct = &code_tab[(size_t)gi * g.n_srv];
+      for (int s = 0; s < g.n_srv; s++)
+        if (ct[s] >= 0) {
+          present++;
+          bits += bise_block_bits(ct[s], S);
+        }
+      gwords[gi] = present ? g.nbw + (5 * present + 31) / 32 + (bits + 31) / 32 : 0;
+    }
+  });
+  std::vector<uint32_t> offsets(g.ng + 1);
+  uint64_t acc = 0;
+  for (int gi = 0; gi < g.ng; gi++) {
+    offsets[gi] = (uint32_t)acc;
+    acc += gwords[gi];
+    if (acc > 0xFFFFFFF0ull) return fail(LFC_E_RANGE, "lfc_encode: stream exceeds 2^32 words");
+  }
+  offsets[g.ng] = (uint32_t)acc;
+  const uint64_t srv_words = acc + 2;
+  const uint64_t rkv_bytes = (uint64_t)g.n_top * g.nb * 3 * S * 2;
+  const uint64_t rkv_off = kHeaderBytes, off_off = rkv_off + rkv_bytes;
+  const uint64_t srv_off = off_off + 4ull * (g.ng + 1);
+  if (stats) stats->stream_bytes = srv_off + 4 * srv_words;
+  if (!out) return LFC_OK;
+  try {
+    out->assign(srv_off + 4 * srv_words, 0);
+  } catch (const std::bad_alloc &) {
+    return fail(LFC_E_NOMEM, "lfc_encode: out of host memory");
+  }
+  put_header(out->data(), g, p, mask, rkv_off, off_off, srv_off);
+  // RKVStream: the top level, stored raw as int16 [n_top][nb][3][B*B]
+  {
+    int16_t *dst = reinterpret_cast<int16_t *>(out->data() + rkv_off);
+    const std::vector<int16_t> &top = lvl[L - 1];
+    parallel_for((int64_t)g.n_top * g.nb, 1024, [&](int64_t a, int64_t e) {
+      for (int64_t r = a; r < e; r++) {
+        const int n = (int)(r / g.nb), b = (int)(r % g.nb), bx = b % g.nbx, by = b / g.nbx;
+        for (int ch = 0; ch < 3; ch++)
+          for (int i = 0; i < S; i++)
+            dst[(size_t)r * 3 * S + ch * S + i] =
+                top[(size_t)n * img + (size_t)ch * plane + (size_t)(by * B + i / B) * g.wp + bx * B + i % B];
+      }
+    });
+  }
+  std::memcpy(out->data() + off_off, offsets.data(), 4ull * (g.ng + 1));
+  uint32_t *srv = reinterpret_cast<uint32_t *>(out->data() + srv_off);
+  parallel_for(g.ng, 64, [&](int64_t a, int64_t e) {
+    for (int64_t gi = a; gi < e; gi++) {
+      if (!gwords[gi]) continue;
+      uint32_t *w = srv + offsets[gi];
+      const int8_t *ct = &code_tab[(size_t)gi * g.n_srv];
+      uint64_t present = 0;
+      for (int s = 0; s < g.n_srv; s++)
+        if (ct[s] >= 0) {
+          w[s >> 5] |= 1u << (s & 31);
+          present++;
+        }
+      uint64_t cpos = 32ull * g.nbw;
+      uint64_t ppos = 32ull * (g.nbw + (5 * present + 31) / 32);
+      for (int s = 0; s < g.n_srv; s++) {
+        if (ct[s] < 0) continue;
+        put_field(w, cpos, (uint32_t)ct[s]);
+        cpos += 5;
+        ppos = pack_block(w, ppos, &zv[((size_t)gi * g.n_srv + s) * S], S, ct[s]);
+      }
+    }
+  });
+  return LFC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// stream validation and the block directory
+// ---------------------------------------------------------------------------
+
+struct Parsed {
+  lfc_params p{};
+  Geometry g;
+  const uint8_t *rkv = nullptr;
+  size_t rkv_bytes = 0;
+  std::vector<uint32_t> off, srv;       // aligned copies; srv ends with the 2 zero words
+  std::vector<uint32_t> dbase, poff;    // directory (built on request)
+  uint64_t present = 0;
+};
+
+static inline uint32_t read_bits(const std::vector<uint32_t> &w, uint64_t pos, int n) {
+  const uint64_t i = pos >> 5;
+  uint64_t x = w[i];
+  if (i + 1 < w.size()) x |= (uint64_t)w[i + 1] << 32;
+  return (uint32_t)(x >> (pos & 31)) & (n == 32 ? 0xFFFFFFFFu : ((1u << n) - 1u));
+}
+
+template <typename T>
+static T rd(const uint8_t *p) {
+  T v;
+  std::memcpy(&v, p, sizeof v);
+  return v;
+}
+
+static lfc_status parse_validate(const void *stream, size_t bytes, Parsed &ps, bool build_dir) {
+  const uint8_t *s = static_cast<const uint8_t *>(stream);
+  auto corrupt = [](const std::string &m) { return fail(LFC_E_CORRUPT, "stream: " + m); };
+  if (bytes < (size_t)kHeaderBytes) return corrupt("shorter than the header");
+  if (std::memcmp(s, "RLFC", 4) != 0) return corrupt("bad magic");
+  if (rd<uint16_t>(s + 4) != 1 || rd<uint16_t>(s + 6) != kHeaderBytes) return corrupt("unsupported version");
+  lfc_params &p = ps.p;
+  p.grid_u = rd<int32_t>(s + 8);
+  p.grid_v = rd<int32_t>(s + 12);
+  p.width = rd<int32_t>(s + 16);
+  p.height = rd<int32_t>(s + 20);
+  p.block = rd<int32_t>(s + 32);
+  p.levels = rd<int32_t>(s + 36);
+  p.quant_bits = rd<int32_t>(s + 40);
+  if (p.levels < 1 || p.levels > kMaxLevels) return corrupt("levels");
+  for (int i = 0; i < kMaxLevels; i++) {
+    p.cluster[i] = rd<int32_t>(s + 48 + 4 * i);
+    if (i >= p.levels - 1 && p.cluster[i] != 0) return corrupt("unused cluster entries must be 0");
+  }
+  p.pix_threshold = rd<int32_t>(s + 72);
+  p.blk_threshold = rd<int32_t>(s + 76);
+  p.range_mask = rd<uint32_t>(s + 80);
+  if (p.range_mask == 0) return corrupt("empty range mask");
+  std::string why;
+  if (make_geometry(p, ps.g, &why) != LFC_OK) return corrupt("parameters: " + why);
+  const Geometry &g = ps.g;
+  if (rd<int32_t>(s + 24) != g.wp || rd<int32_t>(s + 28) != g.hp || rd<int32_t>(s + 44) != 3)
+    return corrupt("padded size or channel count");
+  if (rd<int32_t>(s + 84) != g.n_srv || rd<int32_t>(s + 88) != g.n_top || rd<int32_t>(s + 92) != g.nb ||
+      rd<int32_t>(s + 96) != g.ng || rd<uint32_t>(s + 100) != 0)
+    return corrupt("derived sizes");
+  const uint64_t rkv_off = rd<uint64_t>(s + 104), off_off = rd<uint64_t>(s + 112), srv_off = rd<uint64_t>(s + 120);
+  ps.rkv_bytes = (size_t)g.n_top * g.nb * 3 * g.S * 2;
+  if (rkv_off != (uint64_t)kHeaderBytes || off_off != rkv_off + ps.rkv_bytes ||
+      srv_off != off_off + 4ull * (g.ng + 1))
+    return corrupt("section offsets");
+  if (bytes < srv_off + 8 || (bytes - srv_off) % 4) return corrupt("truncated");
+  ps.rkv = s + rkv_off;
+  const uint64_t srv_words = (bytes - srv_off) / 4;
+  ps.off.resize(g.ng + 1);
+  std::memcpy(ps.off.data(), s + off_off, 4ull * (g.ng + 1));
+  if (ps.off[0] != 0) return corrupt("first offset");
+  for (int gi = 0; gi < g.ng; gi++)
+    if (ps.off[gi + 1] < ps.off[gi]) return corrupt(fmt("offsets decrease at group %d", gi));
+  if ((uint64_t)ps.off[g.ng] + 2 != srv_words) return corrupt("SRV section length");
+  ps.srv.resize(srv_words);
+  std::memcpy(ps.srv.data(), s + srv_off, 4 * srv_words);
+  if (ps.srv[srv_words - 1] || ps.srv[srv_words - 2]) return corrupt("tail words");
+
+  // every group: bitmap, codes, payload length, padding and digit fields
+  const int S = g.S;
+  const uint32_t mask = p.range_mask;
+  std::vector<uint32_t> count(g.ng, 0);
+  std::atomic<int64_t> bad_group{-1};
+  parallel_for(g.ng, 256, [&](int64_t a, int64_t e) {
+    for (int64_t gi = a; gi < e; gi++) {
+      const uint64_t o0 = ps.off[gi], len = ps.off[gi + 1] - o0;
+      if (!len) continue;
+      auto bad = [&] {
+        int64_t cur = -1;
+        bad_group.compare_exchange_strong(cur, gi);
+      };
+      if (g.nbw == 0 || len < (uint64_t)g.nbw || len > (1u << 22)) { bad(); continue; }
+      const uint32_t *bm = &ps.srv[o0];
+      uint64_t P = 0;
+      for (int w = 0; w < g.nbw; w++) P += __builtin_popcount(bm[w]);
+      if ((g.n_srv & 31) && (bm[g.nbw - 1] >> (g.n_srv & 31))) { bad(); continue; }
+      const uint64_t ncw = (5 * P + 31) / 32;
+      if (P == 0 || len < g.nbw + ncw) { bad(); continue; }
+      const uint64_t base = 32 * o0, cbit = base + 32ull * g.nbw;
+      uint64_t bits = 0;
+      bool ok = true;
+      for (uint64_t r = 0; r < P && ok; r++) {
+        const uint32_t k = read_bits(ps.srv, cbit + 5 * r, 5);
+        if (k >= (uint32_t)kNumCodes || !((mask >> k) & 1u)) ok = false;
+        else bits += bise_block_bits((int)k, S);
+      }
+      if (!ok || len != g.nbw + ncw + (bits + 31) / 32) { bad(); continue; }
+      // padding after the codes and after the payload must be zero
+      for (uint64_t pos = cbit + 5 * P; pos < base + 32ull * (g.nbw + ncw) && ok; pos++)
+        ok = !read_bits(ps.srv, pos, 1);
+      for (uint64_t pos = base + 32ull * (g.nbw + ncw) + bits; pos < base + 32 * len && ok; pos++)
+        ok = !read_bits(ps.srv, pos, 1);
+      // digit fields below radix^k
+      uint64_t pp = base + 32ull * (g.nbw + ncw);
+      for (uint64_t r = 0; r < P && ok; r++) {
+        const RangeCode rc = range_code((int)read_bits(ps.srv, cbit + 5 * r, 5));
+        if (rc.kind) {
+          const int glen = rc.kind == 1 ? 5 : 3, radix = rc.kind == 1 ? 3 : 5, full = rc.kind == 1 ? 8 : 7;
+          uint64_t fp = pp;
+          for (int i0 = 0; i0 < S && ok; i0 += glen) {
+            const int k = std::min(glen, S - i0), wdt = (full * k + glen - 1) / glen;
+            uint32_t lim = 1;
+            for (int j = 0; j < k; j++) lim *= radix;
+            ok = read_bits(ps.srv, fp, wdt) < lim;
+            fp += wdt;
+          }
+        }
+        pp += S * rc.m + digit_plane_bits(rc.kind, S);
+      }
+      if (!ok) { bad(); continue; }
+      count[gi] = (uint32_t)P;
+    }
+  });
+  if (bad_group.load() >= 0) return corrupt(fmt("group %lld is malformed", (long long)bad_group.load()));
+  ps.present = 0;
+  for (int gi = 0; gi < g.ng; gi++) ps.present += count[gi];
+  if (!build_dir) return LFC_OK;
+  if (ps.present > 0xFFFFFFF0ull) return fail(LFC_E_UNSUPPORTED, "more than 2^32 stored blocks");
+
+  // Directory for random access (built once, as Sec. 3.5 locates blocks at
+  // initialisation): dbase[g][w] = index in poff of the first stored node of
+  // bitmap word w; poff[i] = (payload bit offset within the group << 5) | code.
+  std::vector<uint32_t> pbase(g.ng + 1, 0);
+  for (int gi = 0; gi < g.ng; gi++) pbase[gi + 1] = pbase[gi] + count[gi];
+  ps.dbase.assign((size_t)g.ng * g.nbw, 0);
+  ps.poff.assign(std::max<uint64_t>(ps.present, 1), 0);
+  parallel_for(g.ng, 256, [&](int64_t a, int64_t e) {
+    for (int64_t gi = a; gi < e; gi++) {
+      uint32_t idx = pbase[gi];
+      const uint64_t o0 = ps.off[gi];
+      const bool empty = ps.off[gi + 1] == o0;
+      for (int w = 0; w < g.nbw; w++) {
+        ps.dbase[(size_t)gi * g.nbw + w] = idx;
+        if (!empty) idx += __builtin_popcount(ps.srv[o0 + w]);
+      }
+      if (empty) continue;
+      const uint64_t P = count[gi], base = 32 * o0;
+      const uint64_t cbit = base + 32ull * g.nbw;
+      uint64_t rel = 32ull * (g.nbw + (5 * P + 31) / 32);
+      for (uint64_t r = 0; r < P; r++) {
+        const uint32_t k = read_bits(ps.srv, cbit + 5 * r, 5);
+        ps.poff[pbase[gi] + r] = (uint32_t)(rel << 5) | k;
+        rel += bise_block_bits((int)k, S);
+      }
+    }
+  });
+  return LFC_OK;
+}
+
+}  // namespace lfc
+
+// ---------------------------------------------------------------------------
+// exported calls
+// ---------------------------------------------------------------------------
+
+using namespace lfc;
+
+extern "C" const char *lfc_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" lfc_status lfc_encode_ex(const uint8_t *rgb, const lfc_params *p, void **stream_out, size_t *bytes_out,
+                                    lfc_encode_stats *stats) {
+  if (!rgb || !p || (!stream_out) != (!bytes_out)) return fail(LFC_E_INVALID, "lfc_encode: null argument");
+  if (stream_out) {
+    *stream_out = nullptr;
+    *bytes_out = 0;
+  }
+  std::vector<uint8_t> buf;
+  lfc_status st;
+  try {
+    st = encode_impl(rgb, *p, stream_out ? &buf : nullptr, stats);
+  } catch (const std::bad_alloc &) {
+    return fail(LFC_E_NOMEM, "lfc_encode: out of host memory");
+  }
+  if (st != LFC_OK || !stream_out) return st;
+  void *mem = std::malloc(buf.size());
+  if (!mem) return fail(LFC_E_NOMEM, "lfc_encode: out of host memory");
+  std::memcpy(mem, buf.data(), buf.size());
+  *stream_out = mem;
+  *bytes_out = buf.size();
+  return LFC_OK;
+}
+
+extern "C" lfc_status lfc_encode(const uint8_t *rgb, const lfc_params *p, void **stream_out, size_t *bytes_out) {
+  if (!stream_out || !bytes_out) return fail(LFC_E_INVALID, "lfc_encode: null argument");
+  return lfc_encode_ex(rgb, p, stream_out, bytes_out, nullptr);
+}
+
+extern "C" void lfc_free(void *ptr) { std::free(ptr); }
+
+extern "C" lfc_status lfc_validate(const void *stream, size_t bytes, lfc_params *p_out) {
+  if (!stream) return fail(LFC_E_INVALID, "lfc_validate: null stream");
+  Parsed ps;
+  lfc_status st;
+  try {
+    st = parse_validate(stream, bytes, ps, false);
+  } catch (const std::bad_alloc &) {
+    return fail(LFC_E_NOMEM, "lfc_validate: out of host memory");
+  }
+  if (st == LFC_OK && p_out) *p_out = ps.p;
+  return st;
+}
+
+static size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, lfc_lf **out) {
+  if (!stream || !out) return fail(LFC_E_INVALID, "lfc_open: null argument");
+  *out = nullptr;
+  Parsed ps;
+  TreeTables tt;
+  try {
+    lfc_status st = parse_validate(stream, bytes, ps, true);
+    if (st != LFC_OK) return st;
+    build_tree_tables(ps.g, tt);
+  } catch (const std::bad_alloc &) {
+    return fail(LFC_E_NOMEM, "lfc_open: out of host memory");
+  }
+  const Geometry &g = ps.g;
+  // sections of the single device allocation
+  struct Part {
+    const void *src;
+    size_t bytes;
+    size_t at;
+  };
+  static const uint32_t zeros[64] = {0};
+  Part parts[9] = {
+      {ps.rkv, ps.rkv_bytes, 0},
+      {ps.off.data(), ps.off.size() * 4, 0},
+      {ps.srv.data(), ps.srv.size() * 4, 0},
+      {ps.dbase.data(), ps.dbase.size() * 4, 0},
+      {ps.poff.data(), ps.poff.size() * 4, 0},
+      {tt.path.data(), tt.path.size() * 4, 0},
+      {tt.root.data(), tt.root.size() * 4, 0},
+      {tt.leaf.data(), tt.leaf.size() * 4, 0},
+      {zeros, 4, 0},
+  };
+  size_t total = 0;
+  for (auto &pt : parts) {
+    pt.at = total;
+    // the SRV section gets 64 spare zero words so wide bit-window reads stay inside
+    total += align256(pt.bytes + (&pt == &parts[2] ? 256 : 0));
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(LFC_E_HIP, "lfc_open: no current device");
+  void *base = nullptr;
+  hipError_t he = hipMalloc(&base, total);
+  if (he != hipSuccess) return fail(he == hipErrorOutOfMemory ? LFC_E_NOMEM : LFC_E_HIP,
+                                    std::string("lfc_open: hipMalloc: ") + hipGetErrorString(he));
+  char *d = static_cast<char *>(base);
+  for (auto &pt : parts) {
+    if (pt.bytes) he = hipMemcpyAsync(d + pt.at, pt.src, pt.bytes, hipMemcpyHostToDevice, s);
+    if (he == hipSuccess && &pt == &parts[2])
+      he = hipMemcpyAsync(d + pt.at + pt.bytes, zeros, 256, hipMemcpyHostToDevice, s);
+    if (he != hipSuccess) break;
+  }
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(base);
+    return fail(LFC_E_HIP, std::string("lfc_open: copy to device: ") + hipGetErrorString(he));
+  }
+  lfc_lf *lf = new (std::nothrow) lfc_lf;
+  if (!lf) {
+    (void)hipFree(base);
+    return fail(LFC_E_NOMEM, "lfc_open: out of host memory");
+  }
+  lf->params = ps.p;
+  lf->geo = g;
+  lf->device = dev;
+  lf->stream_bytes = bytes;
+  lf->present = ps.present;
+  lf->d_base = base;
+  lf->d_bytes = total;
+  lf->d_rkv = reinterpret_cast<const int16_t *>(d + parts[0].at);
+  lf->d_off = reinterpret_cast<const uint32_t *>(d + parts[1].at);
+  lf->d_srv = reinterpret_cast<const uint32_t *>(d + parts[2].at);
+  lf->d_dbase = reinterpret_cast<const uint32_t *>(d + parts[3].at);
+  lf->d_poff = reinterpret_cast<const uint32_t *>(d + parts[4].at);
+  lf->d_path = reinterpret_cast<const int32_t *>(d + parts[5].at);
+  lf->d_root = reinterpret_cast<const int32_t *>(d + parts[6].at);
+  lf->d_leaf = reinterpret_cast<const int32_t *>(d + parts[7].at);
+  lf->d_err = reinterpret_cast<int32_t *>(d + parts[8].at);
+  *out = lf;
+  return LFC_OK;
+}
+
+extern "C" lfc_status lfc_info(const lfc_lf *lf, lfc_info_t *info) {
+  if (!lf || !info) return fail(LFC_E_INVALID, "lfc_info: null argument");
+  info->params = lf->params;
+  info->padded_width = lf->geo.wp;
+  info->padded_height = lf->geo.hp;
+  info->n_blocks = lf->geo.nb;
+  info->n_groups = lf->geo.ng;
+  info->n_srv = lf->geo.n_srv;
+  info->n_top = lf->geo.n_top;
+  info->stream_bytes = lf->stream_bytes;
+  info->device_bytes = lf->d_bytes;
+  info->present_blocks = lf->present;
+  return LFC_OK;
+}
+
+extern "C" lfc_status lfc_check(const lfc_lf *lf, hipStream_t s) {
+  if (!lf) return fail(LFC_E_INVALID, "lfc_check: null handle");
+  hipError_t he = hipStreamSynchronize(s);
+  int32_t flag = 0;
+  if (he == hipSuccess) he = hipMemcpy(&flag, lf->d_err, 4, hipMemcpyDeviceToHost);
+  if (he != hipSuccess) return fail(LFC_E_HIP, std::string("lfc_check: ") + hipGetErrorString(he));
+  if (flag) {
+    const int32_t zero = 0;
+    he = hipMemcpy(lf->d_err, &zero, 4, hipMemcpyHostToDevice);
+    if (he != hipSuccess) return fail(LFC_E_HIP, std::string("lfc_check: ") + hipGetErrorString(he));
+    return fail(LFC_E_INVALID, "a decode request named a view or block out of range");
+  }
+  return LFC_OK;
+}
+
+extern "C" lfc_status lfc_close(lfc_lf *lf) {
+  if (!lf) return LFC_OK;
+  hipError_t he = hipFree(lf->d_base);
+  delete lf;
+  if (he != hipSuccess) return fail(LFC_E_HIP, std::string("lfc_close: ") + hipGetErrorString(he));
+  return LFC_OK;
+}

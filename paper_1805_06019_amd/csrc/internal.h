@@ -1,0 +1,66 @@
+// Internal declarations shared by the host side (host.cpp) and the HIP
+// kernels (kernels.hip) of liblfc.so.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lfc.h"
+
+namespace lfc {
+
+constexpr int kMaxLevels = LFC_MAX_LEVELS;
+constexpr int kNumCodes = 26;           // BISE range codes 0..25
+constexpr uint32_t kAllCodes = (1u << kNumCodes) - 1u;
+constexpr int kHeaderBytes = 128;
+
+// Geometry derived from the parameters (grid sizes per tree level, padded
+// image, blocks, groups).
+struct Geometry {
+  int U = 0, V = 0, W = 0, H = 0, B = 0, S = 0, L = 0, q = 0;
+  int wp = 0, hp = 0, nbx = 0, nby = 0, nb = 0, ng = 0;
+  int n_srv = 0, n_top = 0, nbw = 0;    // nbw: bitmap words per group
+  int lu[kMaxLevels] = {0}, lv[kMaxLevels] = {0}, c[kMaxLevels] = {0};
+  int nv() const { return U * V; }
+};
+
+// Fills g from p; returns LFC_OK or LFC_E_INVALID with the reason in *why.
+lfc_status make_geometry(const lfc_params &p, Geometry &g, std::string *why);
+
+// Tree tables.  path[vi*(L-1) + l] is the serial (BFS) index of the level-l
+// ancestor of view vi, root[vi] the top-level node, leaf records list the
+// views in the BFS order of level 0 as {vi, root, s_{L-2}, ..., s_0}.
+struct TreeTables {
+  std::vector<int32_t> path, root, leaf;
+  std::vector<std::vector<int32_t>> serial;  // [level][node id] -> BFS index (-1 on top)
+};
+void build_tree_tables(const Geometry &g, TreeTables &t);
+
+// Bits of a BISE block of S values under range code k.
+int bise_block_bits(int code, int S);
+
+// Records a failure for lfc_last_error and returns st.
+lfc_status fail(lfc_status st, const std::string &msg);
+
+}  // namespace lfc
+
+// Device-resident compressed light field.
+struct lfc_lf {
+  lfc_params params;
+  lfc::Geometry geo;
+  int device = 0;
+  uint64_t stream_bytes = 0, present = 0;
+  void *d_base = nullptr;      // one allocation holding everything below
+  size_t d_bytes = 0;
+  const int16_t *d_rkv = nullptr;    // [n_top][nb][3][S]
+  const uint32_t *d_off = nullptr;   // [ng+1] group start words
+  const uint32_t *d_srv = nullptr;   // SRV words, zero-padded at the end
+  const uint32_t *d_dbase = nullptr; // [ng][nbw] directory index of each bitmap word's first node
+  const uint32_t *d_poff = nullptr;  // [present] (payload bit offset in group << 5) | code
+  const int32_t *d_path = nullptr;   // [nv][L-1]
+  const int32_t *d_root = nullptr;   // [nv]
+  const int32_t *d_leaf = nullptr;   // [nv][L+1]
+  int32_t *d_err = nullptr;          // device error flag
+};

@@ -1,0 +1,659 @@
+// HIP kernels for gfx950 (CDNA4, wave64) and the exported launch calls
+// lfc_decode_blocks and lfc_render_views.
+//
+// Decoding a block (Alg. 2, Sec. 3.5) is: read the top-level key-view block,
+// then for every level below, locate the node's residual block inside the
+// group of its spatial location (one level of indirection through the
+// block offsets, Sec. 3.4), unpack its BISE values (Sec. 3.3), undo the
+// zigzag and the quantiser step, and add it.  All integer work; no MFMA.
+//
+// Work mapping: one lane owns one row of B samples of one block of one
+// channel, so a wave covers a 64-pixel-wide strip of B rows and its stores
+// are full 128-byte row segments.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+
+#include "internal.h"
+
+namespace {
+
+using lfc::kMaxLevels;
+constexpr uint32_t kAbsent = 0xFFFFFFFFu;
+constexpr int kLutEntries = 384;  // 256 trit-field values, then 128 quint-field values
+constexpr int kThreads = 256;
+
+// Range code k: 0..11 bits (m = k+1), 12..18 trits (m = k-12), 19..25 quints (m = k-19).
+__device__ __forceinline__ uint32_t code_kind(uint32_t k) { return k < 12u ? 0u : (k < 19u ? 1u : 2u); }
+__device__ __forceinline__ uint32_t code_m(uint32_t k) { return k < 12u ? k + 1u : (k < 19u ? k - 12u : k - 19u); }
+
+template <int S>
+struct Planes {
+  static constexpr uint32_t trit = (8 * S + 4) / 5;    // digit-plane bits, trit blocks
+  static constexpr uint32_t quint = (7 * S + 2) / 3;   // digit-plane bits, quint blocks
+  static constexpr uint32_t trit_last = S / 5, quint_last = S / 3;  // index of a partial last group
+  static constexpr uint32_t trit_pw = (8 * (S % 5) + 4) / 5, quint_pw = (7 * (S % 3) + 2) / 3;
+};
+
+template <int S>
+__device__ __forceinline__ uint32_t block_bits(uint32_t code) {
+  const uint32_t kind = code_kind(code), m = code_m(code);
+  return S * m + (kind == 0u ? 0u : (kind == 1u ? Planes<S>::trit : Planes<S>::quint));
+}
+
+// Digits of a trit field (entries 0..255: five 2-bit digits) or of a quint
+// field (entries 256..383: three 3-bit digits).  Out-of-range fields map to 0;
+// streams holding them are rejected before upload.
+__device__ __forceinline__ uint16_t lut_entry(int t) {
+  uint32_t v = 0;
+  if (t < 256) {
+    if (t < 243)
+      for (int r = 0, x = t; r < 5; r++, x /= 3) v |= (uint32_t)(x % 3) << (2 * r);
+  } else {
+    const int q = t - 256;
+    if (q < 125)
+      for (int r = 0, x = q; r < 3; r++, x /= 5) v |= (uint32_t)(x % 5) << (3 * r);
+  }
+  return (uint16_t)v;
+}
+
+// 64 bits of a group's bit stream starting at bit pos (bit p is bit p%32 of word p/32).
+__device__ __forceinline__ uint64_t window64(const uint32_t *gw, uint32_t pos) {
+  const uint32_t *p = gw + (pos >> 5);
+  const uint32_t a = p[0], b = p[1], c = p[2];
+  const uint32_t sh = pos & 31u;
+  const uint32_t lo = __builtin_amdgcn_alignbit(b, a, sh);
+  const uint32_t hi = __builtin_amdgcn_alignbit(c, b, sh);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Residuals of row y (values y*B .. y*B+B-1 in raster order) of the block whose
+// directory entry is e = (payload bit offset in the group << 5) | code:
+// BISE unpack, zigzag undo, times 2^q.
+template <int B>
+__device__ __forceinline__ void decode_row(const uint32_t *gw, uint32_t e, int y, int q,
+                                           const uint16_t *lut, int32_t d[B]) {
+  constexpr int S = B * B;
+  const uint32_t code = e & 31u, rel = e >> 5;
+  const uint32_t kind = code_kind(code), m = code_m(code);
+  const uint32_t hdr = kind == 0u ? 0u : (kind == 1u ? Planes<S>::trit : Planes<S>::quint);
+  const uint32_t i0 = (uint32_t)y * B;
+  const uint32_t lmask = (1u << m) - 1u;
+  uint32_t low[B];
+  {
+    const uint64_t w = window64(gw, rel + hdr + i0 * m);
+#pragma unroll
+    for (int k = 0; k < (B < 4 ? B : 4); k++) low[k] = (uint32_t)(w >> (k * m)) & lmask;
+    if constexpr (B > 4) {
+      const uint64_t w2 = window64(gw, rel + hdr + (i0 + 4) * m);
+#pragma unroll
+      for (int k = 4; k < B; k++) low[k] = (uint32_t)(w2 >> ((k - 4) * m)) & lmask;
+    }
+  }
+  uint32_t dig[B];
+#pragma unroll
+  for (int k = 0; k < B; k++) dig[k] = 0;
+  if (kind != 0u) {
+    const bool trit = kind == 1u;
+    const uint32_t fw = trit ? 8u : 7u;
+    const uint32_t g0 = trit ? i0 / 5u : i0 / 3u;
+    const uint64_t dw = window64(gw, rel + g0 * fw);
+    const uint32_t last = trit ? Planes<S>::trit_last : Planes<S>::quint_last;
+    const uint32_t pw = trit ? Planes<S>::trit_pw : Planes<S>::quint_pw;
+    const uint32_t lbase = trit ? 0u : 256u, dbits = trit ? 2u : 3u, dmask = trit ? 3u : 7u;
+#pragma unroll
+    for (int k = 0; k < B; k++) {
+      const uint32_t i = i0 + k;
+      const uint32_t gi = trit ? i / 5u : i / 3u;
+      const uint32_t r = i - gi * (trit ? 5u : 3u);
+      const uint32_t width = gi == last ? pw : fw;
+      const uint32_t f = (uint32_t)(dw >> ((gi - g0) * fw)) & ((1u << width) - 1u);
+      dig[k] = ((uint32_t)lut[lbase + f] >> (r * dbits)) & dmask;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < B; k++) {
+    const uint32_t u = (dig[k] << m) | low[k];
+    const int32_t r = (int32_t)(u >> 1) ^ -(int32_t)(u & 1u);
+    d[k] = r * (1 << q);
+  }
+}
+
+template <int B>
+__device__ __forceinline__ void load_row(const int16_t *p, int32_t x[B]) {
+  if constexpr (B == 2) {
+    const uint32_t v = *reinterpret_cast<const uint32_t *>(p);
+    x[0] = (int16_t)(v & 0xFFFFu);
+    x[1] = (int16_t)(v >> 16);
+  } else if constexpr (B == 4) {
+    const uint2 v = *reinterpret_cast<const uint2 *>(p);
+    x[0] = (int16_t)(v.x & 0xFFFFu); x[1] = (int16_t)(v.x >> 16);
+    x[2] = (int16_t)(v.y & 0xFFFFu); x[3] = (int16_t)(v.y >> 16);
+  } else {
+    const uint4 v = *reinterpret_cast<const uint4 *>(p);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      x[2 * k] = (int16_t)(w[k] & 0xFFFFu);
+      x[2 * k + 1] = (int16_t)(w[k] >> 16);
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t pack2(int32_t a, int32_t b) {
+  return ((uint32_t)a & 0xFFFFu) | ((uint32_t)b << 16);
+}
+
+template <int B>
+__device__ __forceinline__ void store_row(int16_t *p, const int32_t x[B]) {
+  if constexpr (B == 2) {
+    *reinterpret_cast<uint32_t *>(p) = pack2(x[0], x[1]);
+  } else if constexpr (B == 4) {
+    *reinterpret_cast<uint2 *>(p) = make_uint2(pack2(x[0], x[1]), pack2(x[2], x[3]));
+  } else {
+    *reinterpret_cast<uint4 *>(p) =
+        make_uint4(pack2(x[0], x[1]), pack2(x[2], x[3]), pack2(x[4], x[5]), pack2(x[6], x[7]));
+  }
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// whole light field, images layout
+// ---------------------------------------------------------------------------
+
+struct LFArgs {
+  const int16_t *rkv;
+  const uint32_t *off;
+  const uint32_t *srv;
+  const int32_t *leaf;   // [nv][L+1] = {vi, root, s_{L-2}, ..., s_0} in serial order
+  int16_t *out;          // [nv][3][hp][wp]
+  int nbx, n_srv, nbw, nv, L, q, wp, hp, nb;
+};
+
+// One workgroup = one channel c, one row of blocks by, one strip of 64/B
+// consecutive blocks.  Phase A: each wave walks the groups of some blocks of
+// the strip and writes, for every tree node, where its residual block starts
+// (or that it is absent) into LDS.  Phase B: each wave takes a run of leaves
+// in serial order (consecutive leaves share ancestors) and keeps the
+// reconstruction of every level of the current path in registers, so a
+// parent's residual is decoded once per subtree.
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_decode_lf(LFArgs a) {
+  constexpr int S = B * B, NBLK = 64 / B;
+  extern __shared__ uint32_t smem[];
+  uint16_t *lut = reinterpret_cast<uint16_t *>(smem);          // 384 x u16 = 192 words
+  uint32_t *s_o0 = smem + kLutEntries / 2;                      // NBLK words (64 reserved)
+  uint32_t *desc = smem + kLutEntries / 2 + 64;                 // [NBLK][n_srv]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int strip = blockIdx.x, by = blockIdx.y, c = blockIdx.z;
+  for (int t = tid; t < kLutEntries; t += kThreads) lut[t] = lut_entry(t);
+
+  // Phase A: node descriptors of the strip's groups
+  for (int j = wave; j < NBLK; j += kThreads / 64) {
+    const int bx = strip * NBLK + j;
+    uint32_t *dj = desc + j * a.n_srv;
+    uint32_t o0 = 0, o1 = 0;
+    if (bx < a.nbx) {
+      const int g = 3 * (by * a.nbx + bx) + c;
+      o0 = a.off[g];
+      o1 = a.off[g + 1];
+    }
+    if (lane == 0) s_o0[j] = o0;
+    if (o0 == o1) {
+      for (int s = lane; s < a.n_srv; s += 64) dj[s] = kAbsent;
+      continue;
+    }
+    const uint32_t *gw = a.srv + o0;
+    uint32_t cnt = 0;
+    for (int w = lane; w < a.nbw; w += 64) cnt += __popc(gw[w]);
+    cnt = wave_sum(cnt);
+    const uint32_t code_bit0 = 32u * a.nbw;
+    uint32_t rank_base = 0, bit_base = 32u * (a.nbw + (5u * cnt + 31u) / 32u);
+    for (int s0 = 0; s0 < a.n_srv; s0 += 64) {
+      const int s = s0 + lane;
+      const bool pres = s < a.n_srv && ((gw[s >> 5] >> (s & 31)) & 1u);
+      const uint64_t bal = __ballot(pres);
+      const uint32_t rank = rank_base + __popcll(bal & ((1ull << lane) - 1ull));
+      uint32_t code = 0, size = 0;
+      if (pres) {
+        code = (uint32_t)window64(gw, code_bit0 + 5u * rank) & 31u;
+        size = block_bits<S>(code);
+      }
+      const uint32_t incl = wave_inclusive_scan(size, lane);
+      if (s < a.n_srv) dj[s] = pres ? (((bit_base + incl - size) << 5) | code) : kAbsent;
+      rank_base += __popcll(bal);
+      bit_base += __shfl(incl, 63);
+    }
+  }
+  __syncthreads();
+
+  // Phase B: leaves
+  const int j = lane % NBLK, y = lane / NBLK;
+  const int bx = strip * NBLK + j;
+  const bool active = bx < a.nbx;
+  const int b = by * a.nbx + (active ? bx : 0);
+  const uint32_t *dj = desc + j * a.n_srv;
+  const uint32_t *gw = a.srv + s_o0[j];
+  const int top = kMaxLevels - a.L;          // level t = top holds the key view
+  int32_t T[kMaxLevels][B];
+  int cache[kMaxLevels];
+#pragma unroll
+  for (int t = 0; t < kMaxLevels; t++) cache[t] = -1;
+  const int per = (a.nv + 3) / 4;
+  const int k0 = wave * per, k1 = min(a.nv, k0 + per);
+  const int rl = a.L + 1;
+  for (int k = k0; k < k1; k++) {
+    const int32_t *rec = a.leaf + k * rl;
+    bool changed = false;
+#pragma unroll
+    for (int t = 0; t < kMaxLevels; t++) {
+      if (t < top) continue;
+      if (t == top) {
+        const int root = rec[1];
+        changed = root != cache[t];
+        if (changed) {
+          cache[t] = root;
+          if (active) load_row<B>(a.rkv + ((size_t)(root * a.nb + b) * 3 + c) * S + y * B, T[t]);
+          else
+#pragma unroll
+            for (int i = 0; i < B; i++) T[t][i] = 0;
+        }
+      } else {
+        const int s = rec[2 + t - top - 1];
+        changed = changed || s != cache[t];
+        if (changed) {
+          cache[t] = s;
+          const uint32_t e = dj[s];
+          int32_t d[B];
+          if (e != kAbsent) decode_row<B>(gw, e, y, a.q, lut, d);
+          else
+#pragma unroll
+            for (int i = 0; i < B; i++) d[i] = 0;
+#pragma unroll
+          for (int i = 0; i < B; i++) T[t][i] = (t > 0 ? T[t - 1][i] : 0) + d[i];
+        }
+      }
+    }
+    if (active) {
+      const int vi = rec[0];
+      store_row<B>(a.out + ((size_t)(vi * 3 + c) * a.hp + by * B + y) * a.wp + bx * B, T[kMaxLevels - 1]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// random access: one (view, block) at a time through the directory
+// ---------------------------------------------------------------------------
+
+struct RAArgs {
+  const int16_t *rkv;
+  const uint32_t *off;
+  const uint32_t *srv;
+  const uint32_t *dbase;
+  const uint32_t *poff;
+  const int32_t *path;
+  const int32_t *root;
+  int nb, nbx, nv, nbw, L, q;
+};
+
+// Row y of block b, channel c, of view vi (Alg. 2): key-view row plus the
+// residual rows of the view's ancestors.
+template <int B>
+__device__ __forceinline__ void gather_row(const RAArgs &a, int vi, int b, int c, int y, const uint16_t *lut,
+                                           int32_t x[B]) {
+  constexpr int S = B * B;
+  const int root = a.root[vi];
+  load_row<B>(a.rkv + ((size_t)(root * a.nb + b) * 3 + c) * S + y * B, x);
+  const int g = 3 * b + c;
+  const uint32_t o0 = a.off[g], o1 = a.off[g + 1];
+  if (o0 == o1) return;
+  const uint32_t *gw = a.srv + o0;
+  const int depth = a.L - 1;
+  for (int l = depth - 1; l >= 0; --l) {
+    const int s = a.path[vi * depth + l];
+    const uint32_t bm = gw[s >> 5];
+    const uint32_t bit = (uint32_t)s & 31u;
+    if ((bm >> bit) & 1u) {
+      const uint32_t idx = a.dbase[(size_t)g * a.nbw + (s >> 5)] + __popc(bm & ((1u << bit) - 1u));
+      int32_t d[B];
+      decode_row<B>(gw, a.poff[idx], y, a.q, lut, d);
+#pragma unroll
+      for (int i = 0; i < B; i++) x[i] += d[i];
+    }
+  }
+}
+
+struct BlocksArgs {
+  RAArgs ra;
+  const int32_t *req;  // [n][2] or null
+  int16_t *out;        // [n][3][S]
+  int32_t *err;
+  int64_t n;
+};
+
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_decode_blocks(BlocksArgs a) {
+  constexpr int S = B * B, LPR = 3 * B, RPW = 64 / LPR;
+  __shared__ uint16_t lut[kLutEntries];
+  for (int t = threadIdx.x; t < kLutEntries; t += kThreads) lut[t] = lut_entry(t);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
+  const int slot = lane / LPR, sub = lane % LPR;
+  if (slot >= RPW) return;
+  const int64_t r = wave * RPW + slot;
+  if (r >= a.n) return;
+  const int c = sub / B, y = sub % B;
+  int vi, b;
+  if (a.req) {
+    vi = a.req[2 * r];
+    b = a.req[2 * r + 1];
+  } else {
+    vi = (int)(r / a.ra.nb);
+    b = (int)(r % a.ra.nb);
+  }
+  int32_t x[B];
+  if (vi < 0 || vi >= a.ra.nv || b < 0 || b >= a.ra.nb) {
+    if (sub == 0) atomicOr(a.err, 1);
+#pragma unroll
+    for (int i = 0; i < B; i++) x[i] = 0;
+  } else {
+    gather_row<B>(a.ra, vi, b, c, y, lut, x);
+  }
+  store_row<B>(a.out + ((size_t)r * 3 + c) * S + y * B, x);
+}
+
+// ---------------------------------------------------------------------------
+// novel views: footprint decode into LDS, then quadrilinear interpolation
+// ---------------------------------------------------------------------------
+
+struct RenderArgs {
+  RAArgs ra;
+  const lfc_view *views;
+  float *out;  // [n][3][ho][wo]
+  int wo, ho, U, V, W, H, TX, TY, fbx_max, fby_max;
+};
+
+// lower grid index, upper index and fraction of x on [0, n-1], after clamping
+__device__ __forceinline__ void cell(float x, int n, int &i0, int &i1, float &f) {
+  x = fminf(fmaxf(x, 0.0f), (float)(n - 1));
+  if (n == 1) {
+    i0 = i1 = 0;
+    f = 0.0f;
+    return;
+  }
+  int i = (int)floorf(x);
+  i = min(max(i, 0), n - 2);
+  i0 = i;
+  i1 = i + 1;
+  f = x - (float)i;
+}
+
+__device__ __forceinline__ float lerpf(float a, float b, float f) { return a + f * (b - a); }
+
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
+  extern __shared__ uint32_t smem[];
+  uint16_t *lut = reinterpret_cast<uint16_t *>(smem);
+  uint32_t *rgb = smem + kLutEntries / 2;      // [4][fby_max*B][fbx_max*B], packed R | G<<8 | B<<16
+  const int tid = threadIdx.x;
+  for (int t = tid; t < kLutEntries; t += kThreads) lut[t] = lut_entry(t);
+  const int n = blockIdx.z;
+  const lfc_view vw = a.views[n];
+  int iu0, iu1, jv0, jv1;
+  float fu, fv;
+  cell(vw.u, a.U, iu0, iu1, fu);
+  cell(vw.v, a.V, jv0, jv1, fv);
+  const float sxs = (float)a.W / (float)a.wo, tys = (float)a.H / (float)a.ho;
+  const int tx0 = blockIdx.x * a.TX, ty0 = blockIdx.y * a.TY;
+  const int tx1 = min(tx0 + a.TX, a.wo) - 1, ty1 = min(ty0 + a.TY, a.ho) - 1;
+  // source footprint of the tile, one pixel wider on each side than needed
+  const float sa = fminf(fmaxf(vw.s + ((float)tx0 + 0.5f) * sxs - 0.5f, 0.0f), (float)(a.W - 1));
+  const float sb = fminf(fmaxf(vw.s + ((float)tx1 + 0.5f) * sxs - 0.5f, 0.0f), (float)(a.W - 1));
+  const float ta = fminf(fmaxf(vw.t + ((float)ty0 + 0.5f) * tys - 0.5f, 0.0f), (float)(a.H - 1));
+  const float tb = fminf(fmaxf(vw.t + ((float)ty1 + 0.5f) * tys - 0.5f, 0.0f), (float)(a.H - 1));
+  const int xlo = max((int)floorf(sa) - 1, 0), xhi = min((int)floorf(sb) + 2, a.W - 1);
+  const int ylo = max((int)floorf(ta) - 1, 0), yhi = min((int)floorf(tb) + 2, a.H - 1);
+  const int fbx0 = xlo / B, fby0 = ylo / B;
+  const int FBX = min(xhi / B - fbx0 + 1, a.fbx_max), FBY = min(yhi / B - fby0 + 1, a.fby_max);
+  const int FW = a.fbx_max * B, FH = a.fby_max * B;
+  int vis[4];
+  vis[0] = jv0 * a.U + iu0;
+  vis[1] = jv0 * a.U + iu1;
+  vis[2] = jv1 * a.U + iu0;
+  vis[3] = jv1 * a.U + iu1;
+  __syncthreads();
+
+  // decode the footprint: item = (view k, block row fy, block column fx, row y)
+  const int per_view = FBY * FBX * B;
+  for (int it = tid; it < 4 * per_view; it += kThreads) {
+    const int k = it / per_view, rem = it - k * per_view;
+    const int fy = rem / (FBX * B), rem2 = rem - fy * FBX * B;
+    const int fx = rem2 / B, y = rem2 - fx * B;
+    const int b = (fby0 + fy) * a.ra.nbx + fbx0 + fx;
+    int32_t Y[B], Co[B], Cg[B];
+    gather_row<B>(a.ra, vis[k], b, 0, y, lut, Y);
+    gather_row<B>(a.ra, vis[k], b, 1, y, lut, Co);
+    gather_row<B>(a.ra, vis[k], b, 2, y, lut, Cg);
+    uint32_t *dst = rgb + (k * FH + fy * B + y) * FW + fx * B;
+#pragma unroll
+    for (int i = 0; i < B; i++) {
+      // inverse YCoCg-R (Sec. 4), clamped to 8 bits
+      const int32_t t = Y[i] - (Cg[i] >> 1);
+      const int32_t G = Cg[i] + t;
+      const int32_t Bc = t - (Co[i] >> 1);
+      const int32_t R = Bc + Co[i];
+      dst[i] = (uint32_t)min(max(R, 0), 255) | ((uint32_t)min(max(G, 0), 255) << 8) |
+               ((uint32_t)min(max(Bc, 0), 255) << 16);
+    }
+  }
+  __syncthreads();
+
+  // quadrilinear interpolation of every output pixel of the tile
+  const size_t plane = (size_t)a.ho * a.wo;
+  float *outn = a.out + (size_t)n * 3 * plane;
+  for (int p = tid; p < a.TX * a.TY; p += kThreads) {
+    const int X = tx0 + p % a.TX, Yp = ty0 + p / a.TX;
+    if (X >= a.wo || Yp >= a.ho) continue;
+    int x0, x1, y0, y1;
+    float fs, ft;
+    cell(vw.s + ((float)X + 0.5f) * sxs - 0.5f, a.W, x0, x1, fs);
+    cell(vw.t + ((float)Yp + 0.5f) * tys - 0.5f, a.H, y0, y1, ft);
+    const int lx0 = min(max(x0 - fbx0 * B, 0), FW - 1), lx1 = min(max(x1 - fbx0 * B, 0), FW - 1);
+    const int ly0 = min(max(y0 - fby0 * B, 0), FH - 1), ly1 = min(max(y1 - fby0 * B, 0), FH - 1);
+    uint32_t P[4][4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const uint32_t *img = rgb + k * FH * FW;
+      P[k][0] = img[ly0 * FW + lx0];
+      P[k][1] = img[ly0 * FW + lx1];
+      P[k][2] = img[ly1 * FW + lx0];
+      P[k][3] = img[ly1 * FW + lx1];
+    }
+#pragma unroll
+    for (int ch = 0; ch < 3; ch++) {
+      float lt[4];
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        const float p00 = (float)((P[k][0] >> (8 * ch)) & 255u), p01 = (float)((P[k][1] >> (8 * ch)) & 255u);
+        const float p10 = (float)((P[k][2] >> (8 * ch)) & 255u), p11 = (float)((P[k][3] >> (8 * ch)) & 255u);
+        lt[k] = lerpf(lerpf(p00, p01, fs), lerpf(p10, p11, fs), ft);
+      }
+      // k = 0: (u0, v0), 1: (u1, v0), 2: (u0, v1), 3: (u1, v1)
+      const float lv0 = lerpf(lt[0], lt[2], fv), lv1 = lerpf(lt[1], lt[3], fv);
+      outn[ch * plane + (size_t)Yp * a.wo + X] = lerpf(lv0, lv1, fu) / 255.0f;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host-side checks and launches
+// ---------------------------------------------------------------------------
+
+using lfc::fail;
+
+lfc_status check_device(const lfc_lf *lf, const char *who) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(LFC_E_HIP, std::string(who) + ": no current device");
+  if (dev != lf->device)
+    return fail(LFC_E_INVALID, std::string(who) + ": the current device is not the one the light field was opened on");
+  return LFC_OK;
+}
+
+// the device buffer at p must hold at least need bytes inside one allocation
+lfc_status check_buffer(const void *p, size_t need, size_t align, const char *who, const char *what) {
+  if (!p) return fail(LFC_E_INVALID, std::string(who) + ": null " + what);
+  if (reinterpret_cast<uintptr_t>(p) % align)
+    return fail(LFC_E_INVALID, std::string(who) + ": " + what + " is not " + std::to_string(align) + "-byte aligned");
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void *>(p)) != hipSuccess || !base) {
+    (void)hipGetLastError();
+    return fail(LFC_E_INVALID, std::string(who) + ": " + what + " is not device memory");
+  }
+  const size_t off = static_cast<const char *>(p) - static_cast<const char *>(base);
+  if (off + need > size) return fail(LFC_E_INVALID, std::string(who) + ": " + what + " is too small");
+  return LFC_OK;
+}
+
+RAArgs ra_args(const lfc_lf *lf) {
+  const lfc::Geometry &g = lf->geo;
+  return RAArgs{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_dbase, lf->d_poff, lf->d_path, lf->d_root,
+                g.nb, g.nbx, g.nv(), g.nbw, g.L, g.q};
+}
+
+lfc_status launched(const char *who) {
+  const hipError_t he = hipGetLastError();
+  if (he != hipSuccess) return fail(LFC_E_HIP, std::string(who) + ": launch failed: " + hipGetErrorString(he));
+  return LFC_OK;
+}
+
+template <int B>
+lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s) {
+  const lfc::Geometry &g = lf->geo;
+  constexpr int NBLK = 64 / B;
+  const size_t lds = 4 * ((size_t)kLutEntries / 2 + 64 + (size_t)NBLK * g.n_srv);
+  if (lds > 64 * 1024)
+    return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: tree too large for the whole-field kernel; use BLOCKS layout");
+  LFArgs a{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_leaf, out, g.nbx, g.n_srv, g.nbw, g.nv(), g.L, g.q, g.wp, g.hp, g.nb};
+  dim3 grid((g.nbx + NBLK - 1) / NBLK, g.nby, 3);
+  hipLaunchKernelGGL(k_decode_lf<B>, grid, dim3(kThreads), lds, s, a);
+  return launched("lfc_decode_blocks");
+}
+
+template <int B>
+lfc_status decode_list(const lfc_lf *lf, const int32_t *req, int64_t n, int16_t *out, hipStream_t s) {
+  constexpr int RPW = 64 / (3 * B);
+  BlocksArgs a{ra_args(lf), req, out, lf->d_err, n};
+  const int64_t waves = (n + RPW - 1) / RPW;
+  const int64_t blocks = (waves + kThreads / 64 - 1) / (kThreads / 64);
+  if (blocks > 0x7FFFFFFF) return fail(LFC_E_INVALID, "lfc_decode_blocks: too many requests");
+  hipLaunchKernelGGL(k_decode_blocks<B>, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+  return launched("lfc_decode_blocks");
+}
+
+// Tile of output pixels per workgroup, and the largest footprint (in blocks)
+// any tile can need; shrinks the tile until the footprint fits 64 KB of LDS.
+struct RenderPlan {
+  int TX, TY, fbx, fby;
+  size_t lds;
+};
+
+bool plan_render(const lfc::Geometry &g, int wo, int ho, RenderPlan &pl) {
+  const double sxs = (double)g.W / wo, tys = (double)g.H / ho;
+  int TX = 64, TY = 16;
+  for (;;) {
+    // footprint span: (T-1)*scale pixels plus the 1-pixel widening on each
+    // side, the interpolation neighbour and float slack, then block alignment
+    const int fbx = ((int)std::ceil((TX - 1) * sxs) + 5 + g.B - 1) / g.B + 2;
+    const int fby = ((int)std::ceil((TY - 1) * tys) + 5 + g.B - 1) / g.B + 2;
+    const size_t lds = 4 * ((size_t)kLutEntries / 2 + (size_t)4 * fbx * g.B * fby * g.B);
+    if (lds <= 64 * 1024) {
+      pl = RenderPlan{TX, TY, fbx, fby, lds};
+      return true;
+    }
+    if (TY > 2) TY /= 2;
+    else if (TX > 8) TX /= 2;
+    else return false;
+  }
+}
+
+template <int B>
+lfc_status render(const lfc_lf *lf, const lfc_view *views, int32_t n, int32_t wo, int32_t ho, float *out,
+                  hipStream_t s) {
+  const lfc::Geometry &g = lf->geo;
+  RenderPlan pl;
+  if (!plan_render(g, wo, ho, pl))
+    return fail(LFC_E_UNSUPPORTED, "lfc_render_views: output too strongly minified for the tile footprint");
+  RenderArgs a{ra_args(lf), views, out, wo, ho, g.U, g.V, g.W, g.H, pl.TX, pl.TY, pl.fbx, pl.fby};
+  dim3 grid((wo + pl.TX - 1) / pl.TX, (ho + pl.TY - 1) / pl.TY, n);
+  hipLaunchKernelGGL(k_render<B>, grid, dim3(kThreads), pl.lds, s, a);
+  return launched("lfc_render_views");
+}
+
+}  // namespace
+
+extern "C" lfc_status lfc_decode_blocks(const lfc_lf *lf, const int32_t *d_req, int64_t n, int32_t layout,
+                                        int16_t *d_out, hipStream_t s) {
+  const char *who = "lfc_decode_blocks";
+  if (!lf) return fail(LFC_E_INVALID, "lfc_decode_blocks: null handle");
+  if (lfc_status st = check_device(lf, who)) return st;
+  const lfc::Geometry &g = lf->geo;
+  if (n < 0) return fail(LFC_E_INVALID, "lfc_decode_blocks: n < 0");
+  if (layout == LFC_LAYOUT_IMAGES) {
+    if (d_req) return fail(LFC_E_INVALID, "lfc_decode_blocks: the images layout decodes every block (d_req must be NULL)");
+    if (n != g.nv()) return fail(LFC_E_INVALID, "lfc_decode_blocks: images layout needs n == grid_u*grid_v");
+    if (lfc_status st = check_buffer(d_out, (size_t)g.nv() * 3 * g.hp * g.wp * 2, 16, who, "d_out")) return st;
+    switch (g.B) {
+      case 2: return decode_images<2>(lf, d_out, s);
+      case 4: return decode_images<4>(lf, d_out, s);
+      default: return decode_images<8>(lf, d_out, s);
+    }
+  }
+  if (layout != LFC_LAYOUT_BLOCKS) return fail(LFC_E_INVALID, "lfc_decode_blocks: unknown layout");
+  if (n == 0) return LFC_OK;
+  if (!d_req && n != (int64_t)g.nv() * g.nb)
+    return fail(LFC_E_INVALID, "lfc_decode_blocks: with d_req NULL, n must be grid_u*grid_v*n_blocks");
+  if (d_req)
+    if (lfc_status st = check_buffer(d_req, (size_t)n * 8, 4, who, "d_req")) return st;
+  if (lfc_status st = check_buffer(d_out, (size_t)n * 3 * g.S * 2, 16, who, "d_out")) return st;
+  switch (g.B) {
+    case 2: return decode_list<2>(lf, d_req, n, d_out, s);
+    case 4: return decode_list<4>(lf, d_req, n, d_out, s);
+    default: return decode_list<8>(lf, d_req, n, d_out, s);
+  }
+}
+
+extern "C" lfc_status lfc_render_views(const lfc_lf *lf, const lfc_view *d_views, int32_t n, int32_t out_w,
+                                       int32_t out_h, float *d_out, hipStream_t s) {
+  const char *who = "lfc_render_views";
+  if (!lf) return fail(LFC_E_INVALID, "lfc_render_views: null handle");
+  if (lfc_status st = check_device(lf, who)) return st;
+  if (n < 0 || n > 65535) return fail(LFC_E_INVALID, "lfc_render_views: n must be 0..65535");
+  if (out_w < 1 || out_h < 1 || out_w > 16384 || out_h > 16384)
+    return fail(LFC_E_INVALID, "lfc_render_views: out_w and out_h must be 1..16384");
+  if (n == 0) return LFC_OK;
+  if (lfc_status st = check_buffer(d_views, (size_t)n * sizeof(lfc_view), 4, who, "d_views")) return st;
+  if (lfc_status st = check_buffer(d_out, (size_t)n * 3 * out_h * out_w * 4, 4, who, "d_out")) return st;
+  switch (lf->geo.B) {
+    case 2: return render<2>(lf, d_views, n, out_w, out_h, d_out, s);
+    case 4: return render<4>(lf, d_views, n, out_w, out_h, d_out, s);
+    default: return render<8>(lf, d_views, n, out_w, out_h, d_out, s);
+  }
+}

@@ -1,0 +1,260 @@
+"""Python binding of liblfc.so (C ABI in include/lfc.h).
+
+Argument marshalling only: every decode and render step runs in the HIP
+kernels of the library.  Device buffers are torch CUDA tensors passed by
+pointer, work goes on torch's current stream.  The functions raise
+``LFCError`` on a non-OK status and raise at load time if the library has
+not been built; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblfc.so")
+MAX_LEVELS = 6
+LAYOUT_BLOCKS = 0
+LAYOUT_IMAGES = 1
+
+STATUS = {0: "LFC_OK", -1: "LFC_E_INVALID", -2: "LFC_E_CORRUPT", -3: "LFC_E_NOMEM", -4: "LFC_E_HIP",
+          -5: "LFC_E_RANGE", -6: "LFC_E_UNSUPPORTED"}
+
+
+class LFCError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class c_params(C.Structure):
+    _fields_ = [
+        ("grid_u", C.c_int32), ("grid_v", C.c_int32),
+        ("width", C.c_int32), ("height", C.c_int32),
+        ("block", C.c_int32), ("levels", C.c_int32),
+        ("cluster", C.c_int32 * MAX_LEVELS),
+        ("pix_threshold", C.c_int32), ("blk_threshold", C.c_int32),
+        ("quant_bits", C.c_int32), ("range_mask", C.c_uint32),
+    ]
+
+
+class c_info(C.Structure):
+    _fields_ = [
+        ("params", c_params),
+        ("padded_width", C.c_int32), ("padded_height", C.c_int32),
+        ("n_blocks", C.c_int32), ("n_groups", C.c_int32),
+        ("n_srv", C.c_int32), ("n_top", C.c_int32),
+        ("stream_bytes", C.c_uint64), ("device_bytes", C.c_uint64),
+        ("present_blocks", C.c_uint64),
+    ]
+
+
+class c_stats(C.Structure):
+    _fields_ = [
+        ("psnr", C.c_double), ("psnr_y", C.c_double), ("psnr_co", C.c_double), ("psnr_cg", C.c_double),
+        ("present_blocks", C.c_uint64), ("code_hist", C.c_uint64 * 26), ("stream_bytes", C.c_uint64),
+    ]
+
+
+@dataclass
+class Params:
+    """Encoding parameters; see lfc_params in include/lfc.h."""
+    grid_u: int
+    grid_v: int
+    width: int
+    height: int
+    block: int = 4
+    levels: int = 2
+    cluster: tuple = (2,)
+    pix_threshold: int = 0
+    blk_threshold: int = 0
+    quant_bits: int = 0
+    range_mask: int = 0
+
+    def to_c(self) -> c_params:
+        p = c_params()
+        p.grid_u, p.grid_v, p.width, p.height = self.grid_u, self.grid_v, self.width, self.height
+        p.block, p.levels = self.block, self.levels
+        for i in range(MAX_LEVELS):
+            p.cluster[i] = self.cluster[i] if i < len(self.cluster) else 0
+        p.pix_threshold, p.blk_threshold = self.pix_threshold, self.blk_threshold
+        p.quant_bits, p.range_mask = self.quant_bits, self.range_mask
+        return p
+
+    @staticmethod
+    def from_c(p: c_params) -> "Params":
+        return Params(p.grid_u, p.grid_v, p.width, p.height, p.block, p.levels,
+                      tuple(p.cluster[i] for i in range(max(p.levels - 1, 0))), p.pix_threshold,
+                      p.blk_threshold, p.quant_bits, p.range_mask)
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Loads liblfc.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+        L.lfc_encode.argtypes = [vp, C.POINTER(c_params), C.POINTER(vp), C.POINTER(sz)]
+        L.lfc_encode_ex.argtypes = [vp, C.POINTER(c_params), C.POINTER(vp), C.POINTER(sz), C.POINTER(c_stats)]
+        L.lfc_free.argtypes = [vp]
+        L.lfc_free.restype = None
+        L.lfc_validate.argtypes = [vp, sz, C.POINTER(c_params)]
+        L.lfc_open.argtypes = [vp, sz, vp, C.POINTER(vp)]
+        L.lfc_info.argtypes = [vp, C.POINTER(c_info)]
+        L.lfc_decode_blocks.argtypes = [vp, vp, i64, i32, vp, vp]
+        L.lfc_render_views.argtypes = [vp, vp, i32, i32, i32, vp, vp]
+        L.lfc_check.argtypes = [vp, vp]
+        L.lfc_close.argtypes = [vp]
+        L.lfc_last_error.argtypes = []
+        L.lfc_last_error.restype = C.c_char_p
+        for f in ("lfc_encode", "lfc_encode_ex", "lfc_validate", "lfc_open", "lfc_info", "lfc_decode_blocks",
+                  "lfc_render_views", "lfc_check", "lfc_close"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int) -> None:
+    if st != 0:
+        raise LFCError(st, load().lfc_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def lfc_encode(rgb: np.ndarray, params: Params) -> bytes:
+    """CompressLFI on the host: rgb uint8 [grid_v][grid_u][height][width][3]."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+    if rgb.shape != (params.grid_v, params.grid_u, params.height, params.width, 3):
+        raise ValueError(f"rgb shape {rgb.shape} does not match the parameters")
+    out, n = C.c_void_p(), C.c_size_t()
+    _check(load().lfc_encode(rgb.ctypes.data, C.byref(params.to_c()), C.byref(out), C.byref(n)))
+    try:
+        return C.string_at(out.value, n.value)
+    finally:
+        load().lfc_free(out)
+
+
+def lfc_encode_ex(rgb: np.ndarray, params: Params, want_stream: bool = True):
+    """lfc_encode plus the encoder's quality/rate statistics (eqs. 4-5).
+    Returns (stream or None, stats dict)."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+    if rgb.shape != (params.grid_v, params.grid_u, params.height, params.width, 3):
+        raise ValueError(f"rgb shape {rgb.shape} does not match the parameters")
+    st = c_stats()
+    out, n = C.c_void_p(), C.c_size_t()
+    if want_stream:
+        _check(load().lfc_encode_ex(rgb.ctypes.data, C.byref(params.to_c()), C.byref(out), C.byref(n),
+                                    C.byref(st)))
+    else:
+        _check(load().lfc_encode_ex(rgb.ctypes.data, C.byref(params.to_c()), None, None, C.byref(st)))
+    data = None
+    if want_stream:
+        try:
+            data = C.string_at(out.value, n.value)
+        finally:
+            load().lfc_free(out)
+    stats = dict(psnr=st.psnr, psnr_y=st.psnr_y, psnr_co=st.psnr_co, psnr_cg=st.psnr_cg,
+                 present_blocks=st.present_blocks, code_hist=list(st.code_hist), stream_bytes=st.stream_bytes)
+    return data, stats
+
+
+def lfc_validate(stream: bytes) -> Params:
+    p = c_params()
+    buf = np.frombuffer(stream, dtype=np.uint8)
+    _check(load().lfc_validate(buf.ctypes.data, buf.size, C.byref(p)))
+    return Params.from_c(p)
+
+
+class LightField:
+    """An opened, device-resident compressed light field (wraps lfc_lf*)."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+        self.info = lfc_info(self)
+
+    @property
+    def params(self) -> Params:
+        return Params.from_c(self.info.params)
+
+    def close(self) -> None:
+        if self.handle:
+            lfc_close(self)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lfc_open(stream: bytes, cuda_stream=None) -> LightField:
+    buf = np.frombuffer(stream, dtype=np.uint8)
+    h = C.c_void_p()
+    _check(load().lfc_open(buf.ctypes.data, buf.size, _stream_ptr(cuda_stream), C.byref(h)))
+    return LightField(h.value)
+
+
+def lfc_info(lf: LightField) -> c_info:
+    info = c_info()
+    _check(load().lfc_info(lf.handle, C.byref(info)))
+    return info
+
+
+def lfc_decode_blocks(lf: LightField, req=None, layout: int = LAYOUT_BLOCKS, out=None, cuda_stream=None):
+    """Decodes blocks on the GPU.  req: int32 CUDA tensor [n][2] = (view, block)
+    or None for every block.  Returns the int16 CUDA output tensor."""
+    import torch
+    i = lf.info
+    nv = i.params.grid_u * i.params.grid_v
+    B = i.params.block
+    if layout == LAYOUT_IMAGES:
+        n = nv
+        shape = (nv, 3, i.padded_height, i.padded_width)
+    else:
+        n = req.shape[0] if req is not None else nv * i.n_blocks
+        shape = (n, 3, B, B)
+    if req is not None:
+        assert req.dtype == torch.int32 and req.is_cuda and req.is_contiguous() and req.dim() == 2
+    if out is None:
+        out = torch.empty(shape, dtype=torch.int16, device="cuda")
+    assert out.dtype == torch.int16 and out.is_cuda and out.is_contiguous() and tuple(out.shape) == shape
+    _check(load().lfc_decode_blocks(lf.handle, req.data_ptr() if req is not None else None, n, layout,
+                                    out.data_ptr(), _stream_ptr(cuda_stream)))
+    return out
+
+
+def lfc_render_views(lf: LightField, views, out_w: int, out_h: int, out=None, cuda_stream=None):
+    """Renders novel views: views float32 CUDA tensor [n][4] = (u, v, s, t).
+    Returns float32 CUDA [n][3][out_h][out_w], RGB / 255."""
+    import torch
+    assert views.dtype == torch.float32 and views.is_cuda and views.is_contiguous() and views.shape[-1] == 4
+    n = views.shape[0]
+    if out is None:
+        out = torch.empty((n, 3, out_h, out_w), dtype=torch.float32, device="cuda")
+    assert out.dtype == torch.float32 and out.is_cuda and out.is_contiguous()
+    assert tuple(out.shape) == (n, 3, out_h, out_w)
+    _check(load().lfc_render_views(lf.handle, views.data_ptr(), n, out_w, out_h, out.data_ptr(),
+                                   _stream_ptr(cuda_stream)))
+    return out
+
+
+def lfc_check(lf: LightField, cuda_stream=None) -> None:
+    _check(load().lfc_check(lf.handle, _stream_ptr(cuda_stream)))
+
+
+def lfc_close(lf: LightField) -> None:
+    h, lf.handle = lf.handle, None
+    if h:
+        _check(load().lfc_close(h))
