@@ -1,0 +1,272 @@
+"""Benchmark of the RLFC decode-and-render path on one MI355X.
+
+One step = one whole-light-field decode (images layout) of the 17x17 x
+512x512 RGB workload coded at 40 dB PSNR_YCoCg: every block of every view,
+through the key view and the residuals of both tree levels.  The same run
+also times, on the same light field, a batched render of 64 novel 512x512
+views per launch, single-view renders launched one per request (the plain
+kernel; p50/p99 latency), 10^6 random block accesses, the 50 dB coding of
+the same light field, and the 64-view render of the 9x9 lenslet-like light
+field.  Inputs are resident in device memory before any timed region.
+
+Prints one JSON line.  ``value`` is decoded samples per second of the step.
+``roofline`` prices the whole-field kernel's algorithmic bytes per launch
+(int16 output, key-view blocks, block offsets and the compressed SRV
+section read once) against 8 TB/s of HBM.  ``cpu_baseline`` is the oracle's
+whole-field decoder on the host's cores (bounded sample).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_1805_06019_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_decode_lf_full40.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def time_launches(fn, n, torch):
+    """Per-launch durations (ms) from events recorded on the launch stream."""
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) for a, b in ev])
+
+
+def cpu_baseline(stream: bytes, nv: int, hp: int, wp: int, nb: int, min_cpu_s: float = 10.0):
+    """The oracle's whole-field decoder, blocks split over the host's threads."""
+    import threading
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    out = np.zeros((nv, 3, hp, wp), dtype=np.int16)
+    chunks = np.linspace(0, nb, threads + 1).astype(int)
+    passes, wall, t_start = 0, 0.0, time.time()
+    while True:
+        t0 = time.perf_counter()
+        ths = [threading.Thread(target=oracle.decode_all, args=(stream, int(chunks[i]), int(chunks[i + 1]), out))
+               for i in range(threads) if chunks[i] < chunks[i + 1]]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        wall += time.perf_counter() - t0
+        passes += 1
+        if wall * threads >= min_cpu_s or time.time() - t_start > 60:
+            break
+    samples = passes * nv * 3 * hp * wp
+    return out, dict(value=samples / wall / 1e9, unit="Gsamples/s", cores=threads, kind="oracle",
+                     sample=f"{passes} whole-field decode pass(es) of the 17x17x512x512 40 dB stream, "
+                            f"blocks split over {threads} threads, {wall:.2f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="skip the secondary measurements")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(groups and views shard with no exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1805_06019_amd import lfc, synth
+    from paper_1805_06019_amd.workloads import WORKLOADS
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    lfc.load()
+
+    # -- setup: synthetic light field, host encode, upload (untimed) --------
+    w40 = WORKLOADS["full40"]
+    t0 = time.time()
+    rgb = synth.light_field(w40.spec)
+    log(f"generated {w40.spec} in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    stream40, st40 = lfc.lfc_encode_ex(rgb, w40.params())
+    log(f"encoded full40 in {time.time() - t0:.1f}s: {len(stream40) / 1e6:.1f} MB, {st40['psnr']:.3f} dB")
+    lf = lfc.lfc_open(stream40)
+    info = lf.info
+    nv, hp, wp, nb = 289, info.padded_height, info.padded_width, info.n_blocks
+    samples = nv * 3 * hp * wp
+    out = torch.empty((nv, 3, hp, wp), dtype=torch.int16, device="cuda")
+
+    def step():
+        lfc.lfc_decode_blocks(lf, None, lfc.LAYOUT_IMAGES, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # -- timed region: exactly K steps ---------------------------------------
+    t_begin, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_begin.record()
+    for _ in range(args.steps):
+        step()
+    t_end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = t_begin.elapsed_time(t_end)
+    ms_per_step = ms_total / args.steps
+    value = samples / (ms_per_step * 1e-3) / 1e9
+    lfc.lfc_check(lf)
+    log(f"whole-field decode: {ms_per_step:.4f} ms/step, {value:.1f} Gsamples/s (host wall {wall:.3f}s)")
+
+    # per-launch durations of the dominant kernel, on its own stream
+    per_launch = time_launches(step, max(args.steps, 20), torch)
+    srv_bytes = 4 * (int(np.frombuffer(stream40, dtype=np.uint32, count=1,
+                                       offset=int(np.frombuffer(stream40, dtype=np.uint64, count=1, offset=112)[0])
+                                       + 4 * info.n_groups)[0]) + 2)
+    alg_bytes = (samples * 2                       # int16 output written once
+                 + info.n_top * nb * 3 * 16 * 2    # key-view blocks
+                 + 4 * (info.n_groups + 1)         # block offsets
+                 + srv_bytes                       # compressed SRV section
+                 + 4 * nv * 4)                     # leaf schedule
+    achieved = alg_bytes / (per_launch.mean() * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(),
+                    kernel="k_decode_lf<4>", algorithmic_bytes_per_launch=alg_bytes,
+                    launch_ms_mean=round(float(per_launch.mean()), 5),
+                    launch_ms_p50=round(float(np.median(per_launch)), 5))
+
+    # cold L2/MALL: a 1 GiB write between launches, outside the timed events
+    flush = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+    cold = []
+    for _ in range(10):
+        flush.fill_(1)
+        cold.append(time_launches(step, 1, torch)[0])
+    del flush
+    roofline["launch_ms_cold_mean"] = round(float(np.mean(cold)), 5)
+    roofline["frac_cold"] = round(alg_bytes / (np.mean(cold) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+
+    extra = {}
+    if not args.quick:
+        # batched render: 64 novel 512x512 views per launch (fused decode)
+        views = torch.from_numpy(synth.novel_views(64, 17, 17, seed=302)).cuda()
+        img = torch.empty((64, 3, 512, 512), dtype=torch.float32, device="cuda")
+        rfn = lambda: lfc.lfc_render_views(lf, views, 512, 512, out=img)
+        for _ in range(3):
+            rfn()
+        r = time_launches(rfn, 10, torch)
+        out_bytes = 64 * 3 * 512 * 512 * 4
+        extra["render_full40"] = dict(views_per_launch=64, ms_per_launch=round(float(r.mean()), 4),
+                                      views_per_s=round(64 / (r.mean() * 1e-3), 1),
+                                      output_write_frac_of_hbm=round(out_bytes / (r.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+        # plain kernel: one launch per 512x512 view request
+        one = torch.from_numpy(synth.novel_views(200, 17, 17, seed=303)).cuda()
+        img1 = torch.empty((1, 3, 512, 512), dtype=torch.float32, device="cuda")
+        for i in range(5):
+            lfc.lfc_render_views(lf, one[i:i + 1], 512, 512, out=img1)
+        lat = np.array([time_launches(lambda i=i: lfc.lfc_render_views(lf, one[i:i + 1], 512, 512, out=img1),
+                                      1, torch)[0] for i in range(200)])
+        extra["view_latency_plain"] = dict(requests=200, p50_ms=round(float(np.percentile(lat, 50)), 4),
+                                           p99_ms=round(float(np.percentile(lat, 99)), 4),
+                                           views_per_s=round(1000.0 / lat.mean(), 1))
+        extra["render_full40"]["speedup_vs_plain"] = round(extra["render_full40"]["views_per_s"]
+                                                           / extra["view_latency_plain"]["views_per_s"], 2)
+        del img
+        # 10^6 uniformly random (view, block) accesses, all three channels
+        req = torch.from_numpy(synth.block_requests(1_000_000, nv, nb, seed=202)).cuda()
+        blk = torch.empty((1_000_000, 3, 4, 4), dtype=torch.int16, device="cuda")
+        afn = lambda: lfc.lfc_decode_blocks(lf, req, lfc.LAYOUT_BLOCKS, out=blk)
+        afn()
+        a = time_launches(afn, 10, torch)
+        extra["random_access"] = dict(requests=1_000_000, ms=round(float(a.mean()), 4),
+                                      ns_per_access=round(float(a.mean()) * 1e6 / 1e6, 3),
+                                      gsamples_per_s=round(48e6 / (a.mean() * 1e-3) / 1e9, 2))
+        lfc.lfc_check(lf)
+        del blk, req
+        # 50 dB coding of the same light field
+        w50 = WORKLOADS["full50"]
+        stream50, st50 = lfc.lfc_encode_ex(rgb, w50.params())
+        lf50 = lfc.lfc_open(stream50)
+        out50 = torch.empty_like(out)
+        d50 = time_launches(lambda: lfc.lfc_decode_blocks(lf50, None, lfc.LAYOUT_IMAGES, out=out50), 20, torch)
+        del out50
+        extra["full50"] = dict(psnr_db=round(st50["psnr"], 3), bpp=round(8 * len(stream50) / (nv * 512 * 512), 4),
+                               ms_per_decode=round(float(d50.mean()), 4),
+                               gsamples_per_s=round(samples / (d50.mean() * 1e-3) / 1e9, 1))
+        lf50.close()
+        # lenslet-like 9x9 x 625x434, 64 views per launch
+        wl = WORKLOADS["lenslet40"]
+        rgbl = synth.light_field(wl.spec)
+        streaml, stl = lfc.lfc_encode_ex(rgbl, wl.params())
+        lfl = lfc.lfc_open(streaml)
+        vl = torch.from_numpy(synth.novel_views(64, 9, 9, seed=302)).cuda()
+        imgl = torch.empty((64, 3, 512, 512), dtype=torch.float32, device="cuda")
+        lfn = lambda: lfc.lfc_render_views(lfl, vl, 512, 512, out=imgl)
+        lfn()
+        rl = time_launches(lfn, 10, torch)
+        extra["render_lenslet40"] = dict(psnr_db=round(stl["psnr"], 3), views_per_launch=64,
+                                         ms_per_launch=round(float(rl.mean()), 4),
+                                         views_per_s=round(64 / (rl.mean() * 1e-3), 1))
+        lfl.close()
+        del imgl
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host")
+        ref, cpu = cpu_baseline(stream40, nv, hp, wp, nb)
+        ok = bool(np.array_equal(ref, out.cpu().numpy()))
+        cpu["matches_gpu"] = ok
+        if not ok:
+            log("WARNING: oracle and GPU whole-field decodes differ")
+
+    rec = dict(
+        metric="decoded Gsamples/s", value=round(value, 2), unit="Gsamples/s", n_gpus=1,
+        steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_per_step, 5), higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="int32", data="synthetic",
+        config=dict(workload="full40: whole-field decode of 17x17 views x 512x512 RGB, 3-level tree "
+                             "(17->9->3), 4x4 blocks, q=2, T_blk=67",
+                    psnr_db=round(st40["psnr"], 3), bpp=round(8 * len(stream40) / (nv * 512 * 512), 4),
+                    samples_per_step=samples, stream_bytes=len(stream40),
+                    present_blocks=int(st40["present_blocks"])),
+        roofline=roofline, cpu_baseline=cpu, **extra)
+    print(json.dumps(rec), flush=True)
+    lf.close()
+
+
+if __name__ == "__main__":
+    main()

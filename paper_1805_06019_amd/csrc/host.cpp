@@ -185,19 +185,32 @@ void build_tree_tables(const Geometry &g, TreeTables &t) {
       else t.root[vi] = id;
     }
   }
-  // leaves in serial order, each with its root and its path from the top down
+  // runs of sibling leaves in serial order
   std::vector<int32_t> order(nv);
   for (int vi = 0; vi < nv; vi++) order[vi] = vi;
   if (L > 1)
     std::sort(order.begin(), order.end(),
               [&](int a, int b) { return t.path[(size_t)a * stride] < t.path[(size_t)b * stride]; });
-  t.leaf.assign((size_t)nv * (L + 1), 0);
-  for (int k = 0; k < nv; k++) {
-    const int vi = order[k];
-    int32_t *rec = &t.leaf[(size_t)k * (L + 1)];
-    rec[0] = vi;
-    rec[1] = t.root[vi];
-    for (int i = 0; i < L - 1; i++) rec[2 + i] = t.path[(size_t)vi * stride + (L - 2 - i)];
+  auto same_ancestors = [&](int a, int b) {
+    if (t.root[a] != t.root[b]) return false;
+    for (int l = 1; l < L - 1; l++)
+      if (t.path[(size_t)a * stride + l] != t.path[(size_t)b * stride + l]) return false;
+    return L > 1;
+  };
+  t.batch.clear();
+  for (int k = 0; k < nv;) {
+    int n = 1;
+    while (n < kBatch && k + n < nv && same_ancestors(order[k], order[k + n])) n++;
+    int32_t rec[kBatchWords];
+    for (int i = 0; i < kBatchWords; i++) rec[i] = (i >= 1 && i <= 9) ? -1 : 0;
+    rec[0] = n;
+    for (int i = 0; i < n; i++) rec[1 + i] = order[k + i];
+    const int v0 = order[k];
+    rec[5] = t.root[v0];
+    for (int l = L - 2, i = 0; l >= 1; l--, i++) rec[6 + i] = t.path[(size_t)v0 * stride + l];
+    rec[10] = L > 1 ? t.path[(size_t)v0 * stride] : -1;
+    t.batch.insert(t.batch.end(), rec, rec + kBatchWords);
+    k += n;
   }
 }
 
@@ -767,7 +780,7 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
       {ps.poff.data(), ps.poff.size() * 4, 0},
       {tt.path.data(), tt.path.size() * 4, 0},
       {tt.root.data(), tt.root.size() * 4, 0},
-      {tt.leaf.data(), tt.leaf.size() * 4, 0},
+      {tt.batch.data(), tt.batch.size() * 4, 0},
       {zeros, 4, 0},
   };
   size_t total = 0;
@@ -814,8 +827,21 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
   lf->d_poff = reinterpret_cast<const uint32_t *>(d + parts[4].at);
   lf->d_path = reinterpret_cast<const int32_t *>(d + parts[5].at);
   lf->d_root = reinterpret_cast<const int32_t *>(d + parts[6].at);
-  lf->d_leaf = reinterpret_cast<const int32_t *>(d + parts[7].at);
+  lf->d_batch = reinterpret_cast<const int32_t *>(d + parts[7].at);
+  lf->n_batch = (int)(tt.batch.size() / kBatchWords);
   lf->d_err = reinterpret_cast<int32_t *>(d + parts[8].at);
+  // LDS staging of the whole-field kernel is sized by the largest strip
+  const int nblk = 64 / g.B;
+  for (int c = 0; c < 3; c++)
+    for (int by = 0; by < g.nby; by++)
+      for (int bx0 = 0; bx0 < g.nbx; bx0 += nblk) {
+        uint64_t words = 0;
+        for (int bx = bx0; bx < std::min(bx0 + nblk, g.nbx); bx++) {
+          const int gi = 3 * (by * g.nbx + bx) + c;
+          words += ps.off[gi + 1] - ps.off[gi];
+        }
+        lf->max_strip_words = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(lf->max_strip_words, words), 1u << 30);
+      }
   *out = lf;
   return LFC_OK;
 }

@@ -30,10 +30,16 @@ struct Geometry {
 lfc_status make_geometry(const lfc_params &p, Geometry &g, std::string *why);
 
 // Tree tables.  path[vi*(L-1) + l] is the serial (BFS) index of the level-l
-// ancestor of view vi, root[vi] the top-level node, leaf records list the
-// views in the BFS order of level 0 as {vi, root, s_{L-2}, ..., s_0}.
+// ancestor of view vi, root[vi] the top-level node.  batch holds the views in
+// the serial order of level 0, cut into runs of at most kBatch siblings (views
+// with the same ancestors), one kBatchWords-word record per run:
+//   [0] n, [1..4] view indices (-1 unused), [5] root, [6..9] serial indices of
+//   the ancestors from level L-2 down to level 1 (-1 unused), [10] serial
+//   index of the first view of the run (the others follow it), [11..15] 0.
+constexpr int kBatch = 4;
+constexpr int kBatchWords = 16;
 struct TreeTables {
-  std::vector<int32_t> path, root, leaf;
+  std::vector<int32_t> path, root, batch;
   std::vector<std::vector<int32_t>> serial;  // [level][node id] -> BFS index (-1 on top)
 };
 void build_tree_tables(const Geometry &g, TreeTables &t);
@@ -61,6 +67,8 @@ struct lfc_lf {
   const uint32_t *d_poff = nullptr;  // [present] (payload bit offset in group << 5) | code
   const int32_t *d_path = nullptr;   // [nv][L-1]
   const int32_t *d_root = nullptr;   // [nv]
-  const int32_t *d_leaf = nullptr;   // [nv][L+1]
+  const int32_t *d_batch = nullptr;  // [n_batch][kBatchWords]
+  int n_batch = 0;
   int32_t *d_err = nullptr;          // device error flag
+  uint32_t max_strip_words = 0;      // largest sum of group lengths over a strip of 64/B blocks of one channel
 };

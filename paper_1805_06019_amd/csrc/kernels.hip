@@ -12,7 +12,9 @@
 // are full 128-byte row segments.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <string>
 
 #include "internal.h"
@@ -163,109 +165,188 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   return v;
 }
 
-__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t t = __shfl_up(v, o);
-    if (lane >= o) v += t;
-  }
+// Inclusive prefix sum over the 64 lanes with DPP row shifts and row
+// broadcasts (no LDS traffic): shifts by 1, 2, 4, 8 scan each row of 16
+// lanes, then lane 15 of each row is added to the next row and lane 31 to the
+// upper half.  Lanes without a source add 0.
+__device__ __forceinline__ uint32_t wave_scan_dpp(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
   return v;
 }
+
 
 // ---------------------------------------------------------------------------
 // whole light field, images layout
 // ---------------------------------------------------------------------------
 
+constexpr int kLFThreads = 512;
+constexpr int kLFWaves = kLFThreads / 64;
+constexpr int kLFHeadWords = 400;     // LDS words before the descriptors (LUT, group extents)
+constexpr int kStagePad = 8;          // zero words after the staged groups
+
 struct LFArgs {
   const int16_t *rkv;
   const uint32_t *off;
   const uint32_t *srv;
-  const int32_t *leaf;   // [nv][L+1] = {vi, root, s_{L-2}, ..., s_0} in serial order
+  const int32_t *batch;  // [nbatch][kBatchWords] runs of sibling leaves (see internal.h)
   int16_t *out;          // [nv][3][hp][wp]
-  int nbx, n_srv, nbw, nv, L, q, wp, hp, nb;
+  int nbx, n_srv, nbw, nv, L, q, wp, hp, nb, nbatch;
+  int stage_cap;         // LDS words available for the strip's groups
 };
 
-// One workgroup = one channel c, one row of blocks by, one strip of 64/B
-// consecutive blocks.  Phase A: each wave walks the groups of some blocks of
-// the strip and writes, for every tree node, where its residual block starts
-// (or that it is absent) into LDS.  Phase B: each wave takes a run of leaves
-// in serial order (consecutive leaves share ancestors) and keeps the
-// reconstruction of every level of the current path in registers, so a
-// parent's residual is decoded once per subtree.
+// Words of one row's BISE fields, read before any of them is used so that the
+// reads of several blocks are in flight together.
 template <int B>
-__global__ __launch_bounds__(kThreads) void k_decode_lf(LFArgs a) {
-  constexpr int S = B * B, NBLK = 64 / B;
-  extern __shared__ uint32_t smem[];
-  uint16_t *lut = reinterpret_cast<uint16_t *>(smem);          // 384 x u16 = 192 words
-  uint32_t *s_o0 = smem + kLutEntries / 2;                      // NBLK words (64 reserved)
-  uint32_t *desc = smem + kLutEntries / 2 + 64;                 // [NBLK][n_srv]
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int strip = blockIdx.x, by = blockIdx.y, c = blockIdx.z;
-  for (int t = tid; t < kLutEntries; t += kThreads) lut[t] = lut_entry(t);
+struct RowWords {
+  uint32_t l[3];     // low-bit plane, values i0..i0+3
+  uint32_t l2[3];    // low-bit plane, values i0+4..i0+7 (B == 8)
+  uint32_t dg[3];    // digit plane, from the group holding value i0
+};
 
-  // Phase A: node descriptors of the strip's groups
-  for (int j = wave; j < NBLK; j += kThreads / 64) {
-    const int bx = strip * NBLK + j;
-    uint32_t *dj = desc + j * a.n_srv;
-    uint32_t o0 = 0, o1 = 0;
-    if (bx < a.nbx) {
-      const int g = 3 * (by * a.nbx + bx) + c;
-      o0 = a.off[g];
-      o1 = a.off[g + 1];
-    }
-    if (lane == 0) s_o0[j] = o0;
-    if (o0 == o1) {
-      for (int s = lane; s < a.n_srv; s += 64) dj[s] = kAbsent;
-      continue;
-    }
-    const uint32_t *gw = a.srv + o0;
-    uint32_t cnt = 0;
-    for (int w = lane; w < a.nbw; w += 64) cnt += __popc(gw[w]);
-    cnt = wave_sum(cnt);
-    const uint32_t code_bit0 = 32u * a.nbw;
-    uint32_t rank_base = 0, bit_base = 32u * (a.nbw + (5u * cnt + 31u) / 32u);
-    for (int s0 = 0; s0 < a.n_srv; s0 += 64) {
-      const int s = s0 + lane;
-      const bool pres = s < a.n_srv && ((gw[s >> 5] >> (s & 31)) & 1u);
-      const uint64_t bal = __ballot(pres);
-      const uint32_t rank = rank_base + __popcll(bal & ((1ull << lane) - 1ull));
-      uint32_t code = 0, size = 0;
-      if (pres) {
-        code = (uint32_t)window64(gw, code_bit0 + 5u * rank) & 31u;
-        size = block_bits<S>(code);
-      }
-      const uint32_t incl = wave_inclusive_scan(size, lane);
-      if (s < a.n_srv) dj[s] = pres ? (((bit_base + incl - size) << 5) | code) : kAbsent;
-      rank_base += __popcll(bal);
-      bit_base += __shfl(incl, 63);
+template <int B>
+__device__ __forceinline__ void fetch_row(const uint32_t *gw, uint32_t e, int y, RowWords<B> &w) {
+  constexpr int S = B * B;
+  const uint32_t code = e & 31u, rel = e >> 5;
+  const uint32_t kind = code_kind(code), m = code_m(code);
+  const uint32_t hdr = kind == 0u ? 0u : (kind == 1u ? Planes<S>::trit : Planes<S>::quint);
+  const uint32_t i0 = (uint32_t)y * B;
+  const uint32_t p = rel + hdr + i0 * m;
+  const uint32_t *q = gw + (p >> 5);
+  w.l[0] = q[0];
+  w.l[1] = q[1];
+  w.l[2] = q[2];
+  if constexpr (B > 4) {
+    const uint32_t *q2 = gw + ((p + 4u * m) >> 5);
+    w.l2[0] = q2[0];
+    w.l2[1] = q2[1];
+    w.l2[2] = q2[2];
+  }
+  // plain-bit blocks have no digit plane: this reads their first words, unused
+  const uint32_t pd = rel + (kind == 1u ? (i0 / 5u) * 8u : (kind == 2u ? (i0 / 3u) * 7u : 0u));
+  const uint32_t *qd = gw + (pd >> 5);
+  w.dg[0] = qd[0];
+  w.dg[1] = qd[1];
+  w.dg[2] = qd[2];
+}
+
+__device__ __forceinline__ uint64_t join64(const uint32_t v[3], uint32_t sh) {
+  return ((uint64_t)__builtin_amdgcn_alignbit(v[2], v[1], sh) << 32) | __builtin_amdgcn_alignbit(v[1], v[0], sh);
+}
+
+template <int B>
+__device__ __forceinline__ void finish_row(const RowWords<B> &w, uint32_t e, int y, int q, const uint16_t *lut,
+                                           int32_t d[B]) {
+  constexpr int S = B * B;
+  const uint32_t code = e & 31u, rel = e >> 5;
+  const uint32_t kind = code_kind(code), m = code_m(code);
+  const uint32_t hdr = kind == 0u ? 0u : (kind == 1u ? Planes<S>::trit : Planes<S>::quint);
+  const uint32_t i0 = (uint32_t)y * B;
+  const uint32_t lmask = (1u << m) - 1u;
+  const uint32_t p = rel + hdr + i0 * m;
+  uint32_t low[B];
+  {
+    const uint64_t v = join64(w.l, p & 31u);
+#pragma unroll
+    for (int k = 0; k < (B < 4 ? B : 4); k++) low[k] = (uint32_t)(v >> (k * m)) & lmask;
+    if constexpr (B > 4) {
+      const uint64_t v2 = join64(w.l2, (p + 4u * m) & 31u);
+#pragma unroll
+      for (int k = 4; k < B; k++) low[k] = (uint32_t)(v2 >> ((k - 4) * m)) & lmask;
     }
   }
-  __syncthreads();
+  uint32_t dig[B];
+#pragma unroll
+  for (int k = 0; k < B; k++) dig[k] = 0;
+  if (kind != 0u) {
+    const bool trit = kind == 1u;
+    const uint32_t fw = trit ? 8u : 7u;
+    const uint32_t g0 = trit ? i0 / 5u : i0 / 3u;
+    const uint64_t dw = join64(w.dg, (rel + g0 * fw) & 31u);
+    const uint32_t last = trit ? Planes<S>::trit_last : Planes<S>::quint_last;
+    const uint32_t pw = trit ? Planes<S>::trit_pw : Planes<S>::quint_pw;
+    const uint32_t lbase = trit ? 0u : 256u, dbits = trit ? 2u : 3u, dmask = trit ? 3u : 7u;
+#pragma unroll
+    for (int k = 0; k < B; k++) {
+      const uint32_t i = i0 + k;
+      const uint32_t gi = trit ? i / 5u : i / 3u;
+      const uint32_t r = i - gi * (trit ? 5u : 3u);
+      const uint32_t width = gi == last ? pw : fw;
+      const uint32_t f = (uint32_t)(dw >> ((gi - g0) * fw)) & ((1u << width) - 1u);
+      dig[k] = ((uint32_t)lut[lbase + f] >> (r * dbits)) & dmask;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < B; k++) {
+    const uint32_t u = (dig[k] << m) | low[k];
+    const int32_t r = (int32_t)(u >> 1) ^ -(int32_t)(u & 1u);
+    d[k] = r * (1 << q);
+  }
+}
 
-  // Phase B: leaves
+// Where every node's residual block starts in group gw (or that it is absent):
+// bitmap rank by ballot, 5-bit code, wave prefix sum of the block sizes.
+template <int S>
+__device__ __forceinline__ void scan_group(const uint32_t *gw, uint32_t len, uint32_t *dj, int n_srv, int nbw,
+                                           int lane) {
+  uint32_t cnt = 0;
+  for (int w = lane; w < nbw; w += 64) cnt += __popc(gw[w]);
+  cnt = wave_sum(cnt);
+  const uint32_t code_bit0 = 32u * nbw;
+  uint32_t rank_base = 0, bit_base = 32u * (nbw + (5u * cnt + 31u) / 32u);
+  for (int s0 = 0; s0 < n_srv; s0 += 64) {
+    const int s = s0 + lane;
+    const bool pres = s < n_srv && ((gw[s >> 5] >> (s & 31)) & 1u);
+    const uint64_t bal = __ballot(pres);
+    const uint32_t rank = rank_base + __popcll(bal & ((1ull << lane) - 1ull));
+    uint32_t code = 0, size = 0;
+    if (pres) {
+      code = (uint32_t)window64(gw, code_bit0 + 5u * rank) & 31u;
+      size = block_bits<S>(code);
+    }
+    const uint32_t incl = wave_scan_dpp(size);
+    // a block starts inside its group; the clamp keeps every later read there
+    const uint32_t at = min(bit_base + incl - size, 32u * len);
+    if (s < n_srv) dj[s] = pres ? ((at << 5) | code) : kAbsent;
+    rank_base += __popcll(bal);
+    bit_base += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+  }
+}
+
+// Phase B of the whole-field kernel for one wave: a run of sibling batches in
+// serial order (one 64-byte scalar record each).  The reconstruction of every
+// ancestor level of the current batch is kept in registers (T[t], t =
+// top..4), so a parent's residual is decoded once per subtree; the siblings of
+// a batch are decoded together, all their reads issued before any use.
+template <int B>
+__device__ __forceinline__ void lf_leaves(const LFArgs &a, const uint32_t *gw, const uint32_t *dj,
+                                          const uint16_t *lut, int wave, int lane) {
+  constexpr int S = B * B, NBLK = 64 / B;
   const int j = lane % NBLK, y = lane / NBLK;
-  const int bx = strip * NBLK + j;
+  const int bx = blockIdx.x * NBLK + j, by = blockIdx.y, c = blockIdx.z;
   const bool active = bx < a.nbx;
   const int b = by * a.nbx + (active ? bx : 0);
-  const uint32_t *dj = desc + j * a.n_srv;
-  const uint32_t *gw = a.srv + s_o0[j];
-  const int top = kMaxLevels - a.L;          // level t = top holds the key view
-  int32_t T[kMaxLevels][B];
-  int cache[kMaxLevels];
+  const int top = kMaxLevels - a.L;
+  const size_t row = (size_t)(by * B + y) * a.wp + bx * B;
+  const size_t vstride = (size_t)3 * a.hp * a.wp, cplane = (size_t)c * a.hp * a.wp;
+  int32_t T[kMaxLevels - 1][B];
+  int cache[kMaxLevels - 1];
 #pragma unroll
-  for (int t = 0; t < kMaxLevels; t++) cache[t] = -1;
-  const int per = (a.nv + 3) / 4;
-  const int k0 = wave * per, k1 = min(a.nv, k0 + per);
-  const int rl = a.L + 1;
-  for (int k = k0; k < k1; k++) {
-    const int32_t *rec = a.leaf + k * rl;
+  for (int t = 0; t < kMaxLevels - 1; t++) cache[t] = -1;
+  const int per = (a.nbatch + kLFWaves - 1) / kLFWaves;
+  const int q0 = wave * per, q1 = min(a.nbatch, q0 + per);
+  for (int qb = q0; qb < q1; qb++) {
+    const int32_t *rec = a.batch + (size_t)qb * lfc::kBatchWords;
     bool changed = false;
 #pragma unroll
-    for (int t = 0; t < kMaxLevels; t++) {
+    for (int t = 0; t < kMaxLevels - 1; t++) {
       if (t < top) continue;
       if (t == top) {
-        const int root = rec[1];
+        const int root = rec[5];
         changed = root != cache[t];
         if (changed) {
           cache[t] = root;
@@ -275,7 +356,7 @@ __global__ __launch_bounds__(kThreads) void k_decode_lf(LFArgs a) {
             for (int i = 0; i < B; i++) T[t][i] = 0;
         }
       } else {
-        const int s = rec[2 + t - top - 1];
+        const int s = rec[6 + t - top - 1];
         changed = changed || s != cache[t];
         if (changed) {
           cache[t] = s;
@@ -286,15 +367,113 @@ __global__ __launch_bounds__(kThreads) void k_decode_lf(LFArgs a) {
 #pragma unroll
             for (int i = 0; i < B; i++) d[i] = 0;
 #pragma unroll
-          for (int i = 0; i < B; i++) T[t][i] = (t > 0 ? T[t - 1][i] : 0) + d[i];
+          for (int i = 0; i < B; i++) T[t][i] = T[t > 0 ? t - 1 : 0][i] + d[i];
         }
       }
     }
-    if (active) {
-      const int vi = rec[0];
-      store_row<B>(a.out + ((size_t)(vi * 3 + c) * a.hp + by * B + y) * a.wp + bx * B, T[kMaxLevels - 1]);
+    const int nsib = rec[0], s0 = rec[10];
+    uint32_t e[lfc::kBatch];
+    RowWords<B> w[lfc::kBatch];
+#pragma unroll
+    for (int i = 0; i < lfc::kBatch; i++) e[i] = i < nsib ? dj[s0 + i] : kAbsent;
+#pragma unroll
+    for (int i = 0; i < lfc::kBatch; i++)
+      if (e[i] != kAbsent) fetch_row<B>(gw, e[i], y, w[i]);
+#pragma unroll
+    for (int i = 0; i < lfc::kBatch; i++) {
+      if (i < nsib) {
+        int32_t x[B];
+        if (e[i] != kAbsent) finish_row<B>(w[i], e[i], y, a.q, lut, x);
+        else
+#pragma unroll
+          for (int t = 0; t < B; t++) x[t] = 0;
+#pragma unroll
+        for (int t = 0; t < B; t++) x[t] += T[kMaxLevels - 2][t];
+        if (active) store_row<B>(a.out + (size_t)rec[1 + i] * vstride + cplane + row, x);
+      }
     }
   }
+}
+
+// One workgroup = one channel c, one row of blocks by, one strip of 64/B
+// consecutive blocks (64 pixels).  Phase A copies the strip's groups into
+// LDS when they fit (else phase B reads them from global memory) and writes,
+// for every tree node and block, where its residual block starts.  Phase B
+// walks the leaves (lf_leaves), 8 waves splitting them.
+template <int B>
+__global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
+  constexpr int S = B * B, NBLK = 64 / B;
+  extern __shared__ uint32_t smem[];
+  uint16_t *lut = reinterpret_cast<uint16_t *>(smem);  // 384 x u16 = 192 words
+  uint32_t *s_o0 = smem + 192;                         // group start word in the SRV section
+  uint32_t *s_len = smem + 256;                        // group length in words
+  uint32_t *s_so = smem + 320;                         // group start in the staging area, and the total
+  uint32_t *desc = smem + kLFHeadWords;                // [NBLK][n_srv]
+  uint32_t *stage = desc + NBLK * a.n_srv;             // [stage_cap + kStagePad]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int t = tid; t < kLutEntries; t += kLFThreads) lut[t] = lut_entry(t);
+  if (tid < NBLK) {
+    const int bx = blockIdx.x * NBLK + tid;
+    uint32_t o0 = 0, o1 = 0;
+    if (bx < a.nbx) {
+      const int g = 3 * (blockIdx.y * a.nbx + bx) + blockIdx.z;
+      o0 = a.off[g];
+      o1 = a.off[g + 1];
+    }
+    s_o0[tid] = o0;
+    s_len[tid] = o1 - o0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t acc = 0;
+    for (int j = 0; j < NBLK; j++) {
+      s_so[j] = acc;
+      acc += s_len[j];
+    }
+    s_so[NBLK] = acc;
+  }
+  __syncthreads();
+  const uint32_t total = s_so[NBLK];
+  const bool staged = total <= (uint32_t)a.stage_cap;
+  if (staged) {
+    for (int j = wave; j < NBLK; j += kLFWaves) {
+      const uint32_t *src = a.srv + s_o0[j];
+      uint32_t *dst = stage + s_so[j];
+      const uint32_t n = s_len[j];
+      for (uint32_t i = lane; i < n; i += 64) dst[i] = src[i];
+    }
+    if (tid < kStagePad) stage[total + tid] = 0;
+  }
+  __syncthreads();
+  for (int j = wave; j < NBLK; j += kLFWaves) {
+    uint32_t *dj = desc + j * a.n_srv;
+    if (s_len[j] == 0) {
+      for (int s = lane; s < a.n_srv; s += 64) dj[s] = kAbsent;
+      continue;
+    }
+    if (staged) scan_group<S>(stage + s_so[j], s_len[j], dj, a.n_srv, a.nbw, lane);
+    else scan_group<S>(a.srv + s_o0[j], s_len[j], dj, a.n_srv, a.nbw, lane);
+  }
+  __syncthreads();
+  const int j = lane % NBLK;
+  if (a.L == 1) {
+    // no residual levels: every view is a stored key view
+    const int y = lane / NBLK, bx = blockIdx.x * NBLK + j;
+    if (bx >= a.nbx) return;
+    const int b = blockIdx.y * a.nbx + bx;
+    const int per = (a.nbatch + kLFWaves - 1) / kLFWaves;
+    for (int qb = wave * per; qb < min(a.nbatch, wave * per + per); qb++) {
+      const int32_t *rec = a.batch + (size_t)qb * lfc::kBatchWords;
+      int32_t x[B];
+      load_row<B>(a.rkv + ((size_t)(rec[5] * a.nb + b) * 3 + blockIdx.z) * S + y * B, x);
+      store_row<B>(a.out + ((size_t)(rec[1] * 3 + blockIdx.z) * a.hp + blockIdx.y * B + y) * a.wp + bx * B, x);
+    }
+    return;
+  }
+  const uint32_t *dj = desc + j * a.n_srv;
+  if (staged) lf_leaves<B>(a, stage + s_so[j], dj, lut, wave, lane);
+  else lf_leaves<B>(a, a.srv + s_o0[j], dj, lut, wave, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -544,16 +723,33 @@ lfc_status launched(const char *who) {
   return LFC_OK;
 }
 
+int max_lds_bytes() {
+  static int cached = 0;
+  if (!cached) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+      v = 64 * 1024;
+    cached = v < 64 * 1024 ? v : 64 * 1024;
+  }
+  return cached;
+}
+
 template <int B>
 lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s) {
   const lfc::Geometry &g = lf->geo;
   constexpr int NBLK = 64 / B;
-  const size_t lds = 4 * ((size_t)kLutEntries / 2 + 64 + (size_t)NBLK * g.n_srv);
-  if (lds > 64 * 1024)
+  const int64_t fixed = kLFHeadWords + (int64_t)NBLK * g.n_srv + kStagePad;
+  const int64_t avail = max_lds_bytes() / 4 - fixed;
+  if (avail < 0)
     return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: tree too large for the whole-field kernel; use BLOCKS layout");
-  LFArgs a{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_leaf, out, g.nbx, g.n_srv, g.nbw, g.nv(), g.L, g.q, g.wp, g.hp, g.nb};
+  int64_t cap = std::min<int64_t>(avail, lf->max_strip_words);
+  if (const char *e = getenv("LFC_STAGE_CAP_WORDS")) cap = std::min<int64_t>(cap, std::max(0, atoi(e)));
+  const size_t lds = 4 * (size_t)(fixed + cap);
+  LFArgs a{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_batch, out, g.nbx, g.n_srv, g.nbw, g.nv(), g.L, g.q, g.wp, g.hp,
+           g.nb, lf->n_batch, (int)cap};
   dim3 grid((g.nbx + NBLK - 1) / NBLK, g.nby, 3);
-  hipLaunchKernelGGL(k_decode_lf<B>, grid, dim3(kThreads), lds, s, a);
+  hipLaunchKernelGGL(k_decode_lf<B>, grid, dim3(kLFThreads), lds, s, a);
   return launched("lfc_decode_blocks");
 }
 

@@ -8,6 +8,8 @@ images, block sizes 2/4/8, tree heights 1-4, empty and out-of-range requests,
 and the full 17x17x512x512 workload in the launch configuration the
 benchmark times.
 """
+import ctypes as C
+
 import numpy as np
 import pytest
 import torch
@@ -53,6 +55,23 @@ def test_whole_field_images_layout(gpu, case):
     # repeatable: a second run is bit-identical
     out2 = lfc.lfc_decode_blocks(lf, None, lfc.LAYOUT_IMAGES)
     assert torch.equal(out, out2)
+
+
+@pytest.mark.parametrize("cap", ["0", "40"])
+@pytest.mark.parametrize("case", [GEOMS[0], GEOMS[3], GEOMS[5], GEOMS[6]],
+                         ids=["8x8x64x64-B4-L2", "17x17x20x12-B4-L3", "5x4x72x24-B8-L2", "6x3x130x10-B2-L3"])
+def test_whole_field_without_lds_staging(gpu, case, cap, monkeypatch):
+    # LFC_STAGE_CAP_WORDS bounds the LDS the whole-field kernel may use for a
+    # strip's groups: 0 reads every strip from global memory, a small cap mixes
+    # staged and unstaged strips in one launch
+    U, V, W, H, kw = case
+    say("images without staging", case, cap)
+    rgb = make_lf(U, V, W, H, seed=U * 13 + W)
+    enc = oracle_encode(rgb, **kw)
+    lf = gpu_open(enc.stream)
+    monkeypatch.setenv("LFC_STAGE_CAP_WORDS", cap)
+    got = lfc.lfc_decode_blocks(lf, None, lfc.LAYOUT_IMAGES).cpu().numpy()
+    assert np.array_equal(got, enc.r0)
 
 
 @pytest.mark.parametrize("case", GEOMS[:8], ids=[f"{c[0]}x{c[1]}x{c[2]}x{c[3]}-B{c[4]['block']}-L{c[4]['levels']}"
@@ -106,10 +125,18 @@ def test_empty_request_list_and_argument_errors(gpu):
     out = lfc.lfc_decode_blocks(lf, empty, lfc.LAYOUT_BLOCKS)
     assert out.shape == (0, 3, 4, 4)
     lib = lfc.load()
-    small = torch.zeros(16, dtype=torch.int16, device="cuda")
     s = torch.cuda.current_stream().cuda_stream
-    # output too small for the whole field
-    assert lib.lfc_decode_blocks(lf.handle, None, 16, lfc.LAYOUT_IMAGES, small.data_ptr(), s) == -1
+    # output too small for the whole field: an exact-size raw allocation (a
+    # small torch tensor lives inside a larger caching-allocator segment, and
+    # the library can only see the allocation that holds the pointer)
+    hip = C.CDLL("libamdhip64.so")
+    small = C.c_void_p()
+    assert hip.hipMalloc(C.byref(small), C.c_size_t(4096)) == 0
+    try:
+        assert lib.lfc_decode_blocks(lf.handle, None, 16, lfc.LAYOUT_IMAGES, small.value, s) == -1
+        assert lib.lfc_decode_blocks(lf.handle, None, 16 * 16, lfc.LAYOUT_BLOCKS, small.value, s) == -1
+    finally:
+        hip.hipFree(small)
     # wrong count for the images layout, unknown layout, host pointer as output
     big = torch.zeros(16 * 3 * 16 * 16, dtype=torch.int16, device="cuda")
     assert lib.lfc_decode_blocks(lf.handle, None, 15, lfc.LAYOUT_IMAGES, big.data_ptr(), s) == -1

@@ -8,6 +8,8 @@ single-row camera grid, a single view, cameras outside the grid, and the
 batched render workload (64 novel 512x512 views per launch on the 8x8x64x64
 light field and on the 9x9 lenslet-like 625x434 light field).
 """
+import ctypes as C
+
 import numpy as np
 import pytest
 import torch
@@ -75,9 +77,18 @@ def test_render_argument_errors(gpu):
     views = torch.zeros((2, 4), dtype=torch.float32, device="cuda")
     out = torch.zeros((2, 3, 8, 8), dtype=torch.float32, device="cuda")
     assert lib.lfc_render_views(lf.handle, views.data_ptr(), 2, 0, 8, out.data_ptr(), s) == -1
-    assert lib.lfc_render_views(lf.handle, views.data_ptr(), 2, 16, 16, out.data_ptr(), s) == -1  # too small
     assert lib.lfc_render_views(lf.handle, views.data_ptr(), -1, 8, 8, out.data_ptr(), s) == -1
     assert lib.lfc_render_views(lf.handle, views.data_ptr(), 0, 8, 8, out.data_ptr(), s) == 0
+    # an output too small for 2 x 3 x 64 x 64 floats: exact-size raw allocation
+    hip = C.CDLL("libamdhip64.so")
+    small = C.c_void_p()
+    assert hip.hipMalloc(C.byref(small), C.c_size_t(2 * 3 * 8 * 8 * 4)) == 0
+    try:
+        assert lib.lfc_render_views(lf.handle, views.data_ptr(), 2, 64, 64, small.value, s) == -1
+        assert lib.lfc_render_views(lf.handle, views.data_ptr(), 2, 8, 8, small.value, s) == 0
+    finally:
+        torch.cuda.synchronize()
+        hip.hipFree(small)
     torch.cuda.synchronize()
 
 
