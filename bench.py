@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -117,6 +119,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     lfc.load()
+    dev_props = torch.cuda.get_device_properties(0)
 
     # -- setup: synthetic light field, host encode, upload (untimed) --------
     w40 = WORKLOADS["full40"]
@@ -245,6 +248,14 @@ def main():
         lfl.close()
         del imgl
 
+    if args.calib_copy:
+        src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
@@ -263,7 +274,11 @@ def main():
                     psnr_db=round(st40["psnr"], 3), bpp=round(8 * len(stream40) / (nv * 512 * 512), 4),
                     samples_per_step=samples, stream_bytes=len(stream40),
                     present_blocks=int(st40["present_blocks"])),
-        roofline=roofline, cpu_baseline=cpu, **extra)
+        roofline=roofline, cpu_baseline=cpu, device=dict(name=dev_props.name, cus=dev_props.multi_processor_count,
+                                                        gcn_arch=getattr(dev_props, "gcnArchName", ""),
+                                                        lds_per_block=getattr(dev_props, "shared_memory_per_block", None),
+                                                        lds_per_cu=getattr(dev_props, "shared_memory_per_multiprocessor", None)),
+        **extra)
     print(json.dumps(rec), flush=True)
     lf.close()
 

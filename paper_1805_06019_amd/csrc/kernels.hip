@@ -9,13 +9,17 @@
 //
 // Work mapping: one lane owns one row of B samples of one block of one
 // channel, so a wave covers a 64-pixel-wide strip of B rows and its stores
-// are full 128-byte row segments.
+// are full 128-byte row segments.  Samples travel as packed int16 pairs:
+// the residual tail (zigzag undo, step 2^q, adding the parent) runs on both
+// halves of a register at once, and the sums wrap modulo 2^16 exactly as the
+// final int16 store of a 32-bit sum would.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <string>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -34,8 +38,6 @@ template <int S>
 struct Planes {
   static constexpr uint32_t trit = (8 * S + 4) / 5;    // digit-plane bits, trit blocks
   static constexpr uint32_t quint = (7 * S + 2) / 3;   // digit-plane bits, quint blocks
-  static constexpr uint32_t trit_last = S / 5, quint_last = S / 3;  // index of a partial last group
-  static constexpr uint32_t trit_pw = (8 * (S % 5) + 4) / 5, quint_pw = (7 * (S % 3) + 2) / 3;
 };
 
 template <int S>
@@ -70,92 +72,160 @@ __device__ __forceinline__ uint64_t window64(const uint32_t *gw, uint32_t pos) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Residuals of row y (values y*B .. y*B+B-1 in raster order) of the block whose
-// directory entry is e = (payload bit offset in the group << 5) | code:
-// BISE unpack, zigzag undo, times 2^q.
+__device__ __forceinline__ uint64_t join64(const uint32_t v[3], uint32_t sh) {
+  return ((uint64_t)__builtin_amdgcn_alignbit(v[2], v[1], sh) << 32) | __builtin_amdgcn_alignbit(v[1], v[0], sh);
+}
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+
+// two samples at once: a + b modulo 2^16 per half
+__device__ __forceinline__ uint32_t add_pk(uint32_t a, uint32_t b) { return as_u32(as_u16x2(a) + as_u16x2(b)); }
+
+// two zigzagged values (0,1,2,3,.. -> 0,-1,1,-2,..) back to signed, times 2^q
+__device__ __forceinline__ uint32_t unzigzag_pk(uint32_t pr, int q) {
+  const u16x2 x = as_u16x2(pr);
+  const u16x2 one = {1, 1};
+  const u16x2 zero = {0, 0};
+  u16x2 r = (x >> one) ^ (zero - (x & one));
+  const u16x2 sh = {(unsigned short)q, (unsigned short)q};
+  return as_u32(r << sh);
+}
+
+// Where the digits of row y (values y*B .. y*B+B-1) sit in a trit or quint
+// block: bits 0..7 the bit offset of the row's first digit field in the
+// digit plane, bits 8..15 the offset of the row's first digit in the
+// concatenated digits of those fields, bits 16+4i the width of the row's i-th
+// field (the last group of a block can be short; 0 = no such field).
+// Computed once per lane.
 template <int B>
-__device__ __forceinline__ void decode_row(const uint32_t *gw, uint32_t e, int y, int q,
-                                           const uint16_t *lut, int32_t d[B]) {
+__device__ __forceinline__ uint32_t digit_plan(int y, bool trit) {
+  constexpr int S = B * B;
+  const int glen = trit ? 5 : 3, fw = trit ? 8 : 7, dbits = trit ? 2 : 3;
+  const int rem = S % glen, last = S / glen;
+  const int pw = trit ? (8 * rem + 4) / 5 : (7 * rem + 2) / 3;
+  const int i0 = y * B, a = i0 / glen, a_end = (i0 + B - 1) / glen;
+  uint32_t plan = (uint32_t)(a * fw) | ((uint32_t)((i0 - a * glen) * dbits) << 8);
+  for (int i = 0; i <= a_end - a && i < 4; i++)
+    plan |= (uint32_t)((rem && a + i == last) ? pw : fw) << (16 + 4 * i);
+  return plan;
+}
+
+// Words of one row's BISE fields, read before any of them is used so that the
+// reads of several blocks can be in flight together.
+template <int B>
+struct RowWords {
+  uint32_t l[3];     // low-bit plane from value i0
+  uint32_t l2[3];    // low-bit plane from value i0+4 (B == 8)
+  uint32_t dg[2];    // the row's digit fields
+};
+
+template <int B>
+__device__ __forceinline__ void fetch_row(const uint32_t *gw, uint32_t e, uint32_t plan_t, uint32_t plan_q, int y,
+                                          RowWords<B> &w) {
   constexpr int S = B * B;
   const uint32_t code = e & 31u, rel = e >> 5;
-  const uint32_t kind = code_kind(code), m = code_m(code);
-  const uint32_t hdr = kind == 0u ? 0u : (kind == 1u ? Planes<S>::trit : Planes<S>::quint);
-  const uint32_t i0 = (uint32_t)y * B;
+  const bool is_bits = code < 12u, is_trit = code - 12u < 7u;
+  const uint32_t m = is_bits ? code + 1u : (is_trit ? code - 12u : code - 19u);
+  const uint32_t hdr = is_bits ? 0u : (is_trit ? Planes<S>::trit : Planes<S>::quint);
+  const uint32_t p = rel + hdr + (uint32_t)(y * B) * m;
+  const uint32_t *q = gw + (p >> 5);
+  w.l[0] = q[0];
+  w.l[1] = q[1];
+  w.l[2] = q[2];
+  if constexpr (B > 4) {
+    const uint32_t *q2 = gw + ((p + 4u * m) >> 5);
+    w.l2[0] = q2[0];
+    w.l2[1] = q2[1];
+    w.l2[2] = q2[2];
+  }
+  const uint32_t pd = rel + (is_bits ? 0u : ((is_trit ? plan_t : plan_q) & 0xffu));
+  const uint32_t *qd = gw + (pd >> 5);
+  w.dg[0] = qd[0];
+  w.dg[1] = qd[1];
+}
+
+// BISE unpack of the row (digit << m | low bits), zigzag undo, times 2^q:
+// d holds the B residuals as B/2 packed int16 pairs.
+template <int B>
+__device__ __forceinline__ void finish_row(const RowWords<B> &w, uint32_t e, uint32_t plan_t, uint32_t plan_q, int y,
+                                           int q, const uint16_t *lut, uint32_t d[B / 2]) {
+  constexpr int S = B * B, NF = B == 8 ? 4 : 2;
+  using DigitWord = std::conditional_t<B == 8, uint64_t, uint32_t>;
+  const uint32_t code = e & 31u, rel = e >> 5;
+  const bool is_bits = code < 12u, is_trit = code - 12u < 7u;
+  const uint32_t m = is_bits ? code + 1u : (is_trit ? code - 12u : code - 19u);
+  const uint32_t hdr = is_bits ? 0u : (is_trit ? Planes<S>::trit : Planes<S>::quint);
+  const uint32_t p = rel + hdr + (uint32_t)(y * B) * m;
   const uint32_t lmask = (1u << m) - 1u;
   uint32_t low[B];
   {
-    const uint64_t w = window64(gw, rel + hdr + i0 * m);
+    const uint64_t v = join64(w.l, p & 31u);
 #pragma unroll
-    for (int k = 0; k < (B < 4 ? B : 4); k++) low[k] = (uint32_t)(w >> (k * m)) & lmask;
+    for (int k = 0; k < (B < 4 ? B : 4); k++) low[k] = (uint32_t)(v >> (k * m)) & lmask;
     if constexpr (B > 4) {
-      const uint64_t w2 = window64(gw, rel + hdr + (i0 + 4) * m);
+      const uint64_t v2 = join64(w.l2, (p + 4u * m) & 31u);
 #pragma unroll
-      for (int k = 4; k < B; k++) low[k] = (uint32_t)(w2 >> ((k - 4) * m)) & lmask;
+      for (int k = 4; k < B; k++) low[k] = (uint32_t)(v2 >> ((k - 4) * m)) & lmask;
     }
   }
-  uint32_t dig[B];
+  // the row's digit fields through the LUT, concatenated, then one digit per value
+  const uint32_t plan = is_trit ? plan_t : plan_q;
+  const uint32_t pd = rel + (is_bits ? 0u : (plan & 0xffu));
+  const uint32_t win = __builtin_amdgcn_alignbit(w.dg[1], w.dg[0], pd & 31u);
+  const uint32_t fw = is_trit ? 8u : 7u, gb = is_trit ? 10u : 9u, db = is_trit ? 2u : 3u;
+  const uint32_t lb = is_trit ? 0u : 256u;
+  DigitWord D = 0;
 #pragma unroll
-  for (int k = 0; k < B; k++) dig[k] = 0;
-  if (kind != 0u) {
-    const bool trit = kind == 1u;
-    const uint32_t fw = trit ? 8u : 7u;
-    const uint32_t g0 = trit ? i0 / 5u : i0 / 3u;
-    const uint64_t dw = window64(gw, rel + g0 * fw);
-    const uint32_t last = trit ? Planes<S>::trit_last : Planes<S>::quint_last;
-    const uint32_t pw = trit ? Planes<S>::trit_pw : Planes<S>::quint_pw;
-    const uint32_t lbase = trit ? 0u : 256u, dbits = trit ? 2u : 3u, dmask = trit ? 3u : 7u;
-#pragma unroll
-    for (int k = 0; k < B; k++) {
-      const uint32_t i = i0 + k;
-      const uint32_t gi = trit ? i / 5u : i / 3u;
-      const uint32_t r = i - gi * (trit ? 5u : 3u);
-      const uint32_t width = gi == last ? pw : fw;
-      const uint32_t f = (uint32_t)(dw >> ((gi - g0) * fw)) & ((1u << width) - 1u);
-      dig[k] = ((uint32_t)lut[lbase + f] >> (r * dbits)) & dmask;
-    }
+  for (int i = 0; i < NF; i++) {
+    const uint32_t f = __builtin_amdgcn_ubfe(win, i * fw, (plan >> (16 + 4 * i)) & 15u);
+    D |= (DigitWord)lut[lb + f] << (i * gb);
   }
+  const DigitWord rowd = D >> ((plan >> 8) & 0xffu);
+  const uint32_t dmask = is_bits ? 0u : (is_trit ? 3u : 7u);
+  uint32_t u[B];
 #pragma unroll
-  for (int k = 0; k < B; k++) {
-    const uint32_t u = (dig[k] << m) | low[k];
-    const int32_t r = (int32_t)(u >> 1) ^ -(int32_t)(u & 1u);
-    d[k] = r * (1 << q);
-  }
+  for (int k = 0; k < B; k++) u[k] = ((((uint32_t)(rowd >> (k * db))) & dmask) << m) | low[k];
+#pragma unroll
+  for (int i = 0; i < B / 2; i++) d[i] = unzigzag_pk(u[2 * i] | (u[2 * i + 1] << 16), q);
 }
 
 template <int B>
-__device__ __forceinline__ void load_row(const int16_t *p, int32_t x[B]) {
+__device__ __forceinline__ void decode_row(const uint32_t *gw, uint32_t e, uint32_t plan_t, uint32_t plan_q, int y,
+                                           int q, const uint16_t *lut, uint32_t d[B / 2]) {
+  RowWords<B> w;
+  fetch_row<B>(gw, e, plan_t, plan_q, y, w);
+  finish_row<B>(w, e, plan_t, plan_q, y, q, lut, d);
+}
+
+// a row of B int16 samples as B/2 packed words
+template <int B>
+__device__ __forceinline__ void load_row(const int16_t *p, uint32_t x[B / 2]) {
   if constexpr (B == 2) {
-    const uint32_t v = *reinterpret_cast<const uint32_t *>(p);
-    x[0] = (int16_t)(v & 0xFFFFu);
-    x[1] = (int16_t)(v >> 16);
+    x[0] = *reinterpret_cast<const uint32_t *>(p);
   } else if constexpr (B == 4) {
     const uint2 v = *reinterpret_cast<const uint2 *>(p);
-    x[0] = (int16_t)(v.x & 0xFFFFu); x[1] = (int16_t)(v.x >> 16);
-    x[2] = (int16_t)(v.y & 0xFFFFu); x[3] = (int16_t)(v.y >> 16);
+    x[0] = v.x;
+    x[1] = v.y;
   } else {
     const uint4 v = *reinterpret_cast<const uint4 *>(p);
-    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-      x[2 * k] = (int16_t)(w[k] & 0xFFFFu);
-      x[2 * k + 1] = (int16_t)(w[k] >> 16);
-    }
+    x[0] = v.x;
+    x[1] = v.y;
+    x[2] = v.z;
+    x[3] = v.w;
   }
 }
 
-__device__ __forceinline__ uint32_t pack2(int32_t a, int32_t b) {
-  return ((uint32_t)a & 0xFFFFu) | ((uint32_t)b << 16);
-}
-
 template <int B>
-__device__ __forceinline__ void store_row(int16_t *p, const int32_t x[B]) {
+__device__ __forceinline__ void store_row(int16_t *p, const uint32_t x[B / 2]) {
   if constexpr (B == 2) {
-    *reinterpret_cast<uint32_t *>(p) = pack2(x[0], x[1]);
+    *reinterpret_cast<uint32_t *>(p) = x[0];
   } else if constexpr (B == 4) {
-    *reinterpret_cast<uint2 *>(p) = make_uint2(pack2(x[0], x[1]), pack2(x[2], x[3]));
+    *reinterpret_cast<uint2 *>(p) = make_uint2(x[0], x[1]);
   } else {
-    *reinterpret_cast<uint4 *>(p) =
-        make_uint4(pack2(x[0], x[1]), pack2(x[2], x[3]), pack2(x[4], x[5]), pack2(x[6], x[7]));
+    *reinterpret_cast<uint4 *>(p) = make_uint4(x[0], x[1], x[2], x[3]);
   }
 }
 
@@ -179,7 +249,6 @@ __device__ __forceinline__ uint32_t wave_scan_dpp(uint32_t v) {
   return v;
 }
 
-
 // ---------------------------------------------------------------------------
 // whole light field, images layout
 // ---------------------------------------------------------------------------
@@ -198,95 +267,6 @@ struct LFArgs {
   int nbx, n_srv, nbw, nv, L, q, wp, hp, nb, nbatch;
   int stage_cap;         // LDS words available for the strip's groups
 };
-
-// Words of one row's BISE fields, read before any of them is used so that the
-// reads of several blocks are in flight together.
-template <int B>
-struct RowWords {
-  uint32_t l[3];     // low-bit plane, values i0..i0+3
-  uint32_t l2[3];    // low-bit plane, values i0+4..i0+7 (B == 8)
-  uint32_t dg[3];    // digit plane, from the group holding value i0
-};
-
-template <int B>
-__device__ __forceinline__ void fetch_row(const uint32_t *gw, uint32_t e, int y, RowWords<B> &w) {
-  constexpr int S = B * B;
-  const uint32_t code = e & 31u, rel = e >> 5;
-  const uint32_t kind = code_kind(code), m = code_m(code);
-  const uint32_t hdr = kind == 0u ? 0u : (kind == 1u ? Planes<S>::trit : Planes<S>::quint);
-  const uint32_t i0 = (uint32_t)y * B;
-  const uint32_t p = rel + hdr + i0 * m;
-  const uint32_t *q = gw + (p >> 5);
-  w.l[0] = q[0];
-  w.l[1] = q[1];
-  w.l[2] = q[2];
-  if constexpr (B > 4) {
-    const uint32_t *q2 = gw + ((p + 4u * m) >> 5);
-    w.l2[0] = q2[0];
-    w.l2[1] = q2[1];
-    w.l2[2] = q2[2];
-  }
-  // plain-bit blocks have no digit plane: this reads their first words, unused
-  const uint32_t pd = rel + (kind == 1u ? (i0 / 5u) * 8u : (kind == 2u ? (i0 / 3u) * 7u : 0u));
-  const uint32_t *qd = gw + (pd >> 5);
-  w.dg[0] = qd[0];
-  w.dg[1] = qd[1];
-  w.dg[2] = qd[2];
-}
-
-__device__ __forceinline__ uint64_t join64(const uint32_t v[3], uint32_t sh) {
-  return ((uint64_t)__builtin_amdgcn_alignbit(v[2], v[1], sh) << 32) | __builtin_amdgcn_alignbit(v[1], v[0], sh);
-}
-
-template <int B>
-__device__ __forceinline__ void finish_row(const RowWords<B> &w, uint32_t e, int y, int q, const uint16_t *lut,
-                                           int32_t d[B]) {
-  constexpr int S = B * B;
-  const uint32_t code = e & 31u, rel = e >> 5;
-  const uint32_t kind = code_kind(code), m = code_m(code);
-  const uint32_t hdr = kind == 0u ? 0u : (kind == 1u ? Planes<S>::trit : Planes<S>::quint);
-  const uint32_t i0 = (uint32_t)y * B;
-  const uint32_t lmask = (1u << m) - 1u;
-  const uint32_t p = rel + hdr + i0 * m;
-  uint32_t low[B];
-  {
-    const uint64_t v = join64(w.l, p & 31u);
-#pragma unroll
-    for (int k = 0; k < (B < 4 ? B : 4); k++) low[k] = (uint32_t)(v >> (k * m)) & lmask;
-    if constexpr (B > 4) {
-      const uint64_t v2 = join64(w.l2, (p + 4u * m) & 31u);
-#pragma unroll
-      for (int k = 4; k < B; k++) low[k] = (uint32_t)(v2 >> ((k - 4) * m)) & lmask;
-    }
-  }
-  uint32_t dig[B];
-#pragma unroll
-  for (int k = 0; k < B; k++) dig[k] = 0;
-  if (kind != 0u) {
-    const bool trit = kind == 1u;
-    const uint32_t fw = trit ? 8u : 7u;
-    const uint32_t g0 = trit ? i0 / 5u : i0 / 3u;
-    const uint64_t dw = join64(w.dg, (rel + g0 * fw) & 31u);
-    const uint32_t last = trit ? Planes<S>::trit_last : Planes<S>::quint_last;
-    const uint32_t pw = trit ? Planes<S>::trit_pw : Planes<S>::quint_pw;
-    const uint32_t lbase = trit ? 0u : 256u, dbits = trit ? 2u : 3u, dmask = trit ? 3u : 7u;
-#pragma unroll
-    for (int k = 0; k < B; k++) {
-      const uint32_t i = i0 + k;
-      const uint32_t gi = trit ? i / 5u : i / 3u;
-      const uint32_t r = i - gi * (trit ? 5u : 3u);
-      const uint32_t width = gi == last ? pw : fw;
-      const uint32_t f = (uint32_t)(dw >> ((gi - g0) * fw)) & ((1u << width) - 1u);
-      dig[k] = ((uint32_t)lut[lbase + f] >> (r * dbits)) & dmask;
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < B; k++) {
-    const uint32_t u = (dig[k] << m) | low[k];
-    const int32_t r = (int32_t)(u >> 1) ^ -(int32_t)(u & 1u);
-    d[k] = r * (1 << q);
-  }
-}
 
 // Where every node's residual block starts in group gw (or that it is absent):
 // bitmap rank by ballot, 5-bit code, wave prefix sum of the block sizes.
@@ -317,15 +297,35 @@ __device__ __forceinline__ void scan_group(const uint32_t *gw, uint32_t len, uin
   }
 }
 
+// LDS written by some lanes of a wave and read by others of the same wave:
+// order the accesses (LDS instructions of one wave complete in order).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Per-wave LDS scratch of phase B: the list of stored (sibling, lane) rows
+// and their decoded residuals.
+template <int B>
+struct PhaseBScratch {
+  static constexpr int kListWords = lfc::kBatch * 64 / 2;      // u16 items
+  static constexpr int kResWords = lfc::kBatch * 64 * (B / 2);
+  static constexpr int kWords = kListWords + kResWords;
+};
+
 // Phase B of the whole-field kernel for one wave: a run of sibling batches in
 // serial order (one 64-byte scalar record each).  The reconstruction of every
 // ancestor level of the current batch is kept in registers (T[t], t =
-// top..4), so a parent's residual is decoded once per subtree; the siblings of
-// a batch are decoded together, all their reads issued before any use.
+// top..4), so a parent's residual is decoded once per subtree.  For the
+// leaves, the rows whose block is stored are first listed in LDS and decoded
+// densely (about a third of them at 40 dB), then every lane adds its row's
+// residual, if any, to the parent and stores.
 template <int B>
-__device__ __forceinline__ void lf_leaves(const LFArgs &a, const uint32_t *gw, const uint32_t *dj,
+__device__ __forceinline__ void lf_leaves(const LFArgs &a, const uint32_t *base, const uint32_t *goff,
+                                          const uint32_t *desc, const uint32_t *plans, uint32_t *scratch,
                                           const uint16_t *lut, int wave, int lane) {
-  constexpr int S = B * B, NBLK = 64 / B;
+  constexpr int S = B * B, NBLK = 64 / B, H = B / 2;
   const int j = lane % NBLK, y = lane / NBLK;
   const int bx = blockIdx.x * NBLK + j, by = blockIdx.y, c = blockIdx.z;
   const bool active = bx < a.nbx;
@@ -333,7 +333,13 @@ __device__ __forceinline__ void lf_leaves(const LFArgs &a, const uint32_t *gw, c
   const int top = kMaxLevels - a.L;
   const size_t row = (size_t)(by * B + y) * a.wp + bx * B;
   const size_t vstride = (size_t)3 * a.hp * a.wp, cplane = (size_t)c * a.hp * a.wp;
-  int32_t T[kMaxLevels - 1][B];
+  const uint32_t *dj = desc + j * a.n_srv;
+  const uint32_t *gw = base + goff[j];
+  const uint32_t plan_t = plans[2 * y], plan_q = plans[2 * y + 1];
+  uint16_t *list = reinterpret_cast<uint16_t *>(scratch + wave * PhaseBScratch<B>::kWords);
+  uint32_t *res = scratch + wave * PhaseBScratch<B>::kWords + PhaseBScratch<B>::kListWords;
+  const uint64_t lanes_below = (1ull << lane) - 1ull;
+  uint32_t T[kMaxLevels - 1][H];
   int cache[kMaxLevels - 1];
 #pragma unroll
   for (int t = 0; t < kMaxLevels - 1; t++) cache[t] = -1;
@@ -353,7 +359,7 @@ __device__ __forceinline__ void lf_leaves(const LFArgs &a, const uint32_t *gw, c
           if (active) load_row<B>(a.rkv + ((size_t)(root * a.nb + b) * 3 + c) * S + y * B, T[t]);
           else
 #pragma unroll
-            for (int i = 0; i < B; i++) T[t][i] = 0;
+            for (int i = 0; i < H; i++) T[t][i] = 0;
         }
       } else {
         const int s = rec[6 + t - top - 1];
@@ -361,37 +367,52 @@ __device__ __forceinline__ void lf_leaves(const LFArgs &a, const uint32_t *gw, c
         if (changed) {
           cache[t] = s;
           const uint32_t e = dj[s];
-          int32_t d[B];
-          if (e != kAbsent) decode_row<B>(gw, e, y, a.q, lut, d);
+          uint32_t d[H];
+          if (e != kAbsent) decode_row<B>(gw, e, plan_t, plan_q, y, a.q, lut, d);
           else
 #pragma unroll
-            for (int i = 0; i < B; i++) d[i] = 0;
+            for (int i = 0; i < H; i++) d[i] = 0;
 #pragma unroll
-          for (int i = 0; i < B; i++) T[t][i] = T[t > 0 ? t - 1 : 0][i] + d[i];
+          for (int i = 0; i < H; i++) T[t][i] = add_pk(T[t > 0 ? t - 1 : 0][i], d[i]);
         }
       }
     }
     const int nsib = rec[0], s0 = rec[10];
-    uint32_t e[lfc::kBatch];
-    RowWords<B> w[lfc::kBatch];
+    bool stored[lfc::kBatch];
+    uint32_t cnt = 0;
 #pragma unroll
-    for (int i = 0; i < lfc::kBatch; i++) e[i] = i < nsib ? dj[s0 + i] : kAbsent;
+    for (int i = 0; i < lfc::kBatch; i++) {
+      stored[i] = i < nsib && dj[s0 + i] != kAbsent;
+      const uint64_t bal = __ballot(stored[i]);
+      if (stored[i]) list[cnt + __popcll(bal & lanes_below)] = (uint16_t)(i * 64 + lane);
+      cnt += __popcll(bal);
+    }
+    wave_lds_sync();
+    for (uint32_t p0 = 0; p0 < cnt; p0 += 64) {
+      if (p0 + lane < cnt) {
+        const uint32_t item = list[p0 + lane];
+        const int i2 = item >> 6, l2 = item & 63, j2 = l2 % NBLK, y2 = l2 / NBLK;
+        uint32_t d[H];
+        decode_row<B>(base + goff[j2], desc[j2 * a.n_srv + s0 + i2], plans[2 * y2], plans[2 * y2 + 1], y2, a.q,
+                      lut, d);
 #pragma unroll
-    for (int i = 0; i < lfc::kBatch; i++)
-      if (e[i] != kAbsent) fetch_row<B>(gw, e[i], y, w[i]);
+        for (int h = 0; h < H; h++) res[item * H + h] = d[h];
+      }
+    }
+    wave_lds_sync();
 #pragma unroll
     for (int i = 0; i < lfc::kBatch; i++) {
       if (i < nsib) {
-        int32_t x[B];
-        if (e[i] != kAbsent) finish_row<B>(w[i], e[i], y, a.q, lut, x);
-        else
+        uint32_t x[H];
 #pragma unroll
-          for (int t = 0; t < B; t++) x[t] = 0;
+        for (int h = 0; h < H; h++) x[h] = T[kMaxLevels - 2][h];
+        if (stored[i])
 #pragma unroll
-        for (int t = 0; t < B; t++) x[t] += T[kMaxLevels - 2][t];
+          for (int h = 0; h < H; h++) x[h] = add_pk(x[h], res[(i * 64 + lane) * H + h]);
         if (active) store_row<B>(a.out + (size_t)rec[1 + i] * vstride + cplane + row, x);
       }
     }
+    wave_lds_sync();
   }
 }
 
@@ -408,11 +429,14 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
   uint32_t *s_o0 = smem + 192;                         // group start word in the SRV section
   uint32_t *s_len = smem + 256;                        // group length in words
   uint32_t *s_so = smem + 320;                         // group start in the staging area, and the total
+  uint32_t *plans = smem + 384;                        // [B][2] digit plans per row (trit, quint)
   uint32_t *desc = smem + kLFHeadWords;                // [NBLK][n_srv]
-  uint32_t *stage = desc + NBLK * a.n_srv;             // [stage_cap + kStagePad]
+  uint32_t *scratch = desc + NBLK * a.n_srv;           // [kLFWaves][PhaseBScratch<B>::kWords]
+  uint32_t *stage = scratch + kLFWaves * PhaseBScratch<B>::kWords;  // [stage_cap + kStagePad]
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   for (int t = tid; t < kLutEntries; t += kLFThreads) lut[t] = lut_entry(t);
+  if (tid < 2 * B) plans[tid] = digit_plan<B>(tid >> 1, (tid & 1) == 0);
   if (tid < NBLK) {
     const int bx = blockIdx.x * NBLK + tid;
     uint32_t o0 = 0, o1 = 0;
@@ -441,7 +465,15 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
       const uint32_t *src = a.srv + s_o0[j];
       uint32_t *dst = stage + s_so[j];
       const uint32_t n = s_len[j];
-      for (uint32_t i = lane; i < n; i += 64) dst[i] = src[i];
+      for (uint32_t i = lane; i < n; i += 256) {
+        // four loads in flight per lane before the stores
+        uint32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) v[u] = i + 64 * u < n ? src[i + 64 * u] : 0u;
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+          if (i + 64 * u < n) dst[i + 64 * u] = v[u];
+      }
     }
     if (tid < kStagePad) stage[total + tid] = 0;
   }
@@ -465,15 +497,14 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
     const int per = (a.nbatch + kLFWaves - 1) / kLFWaves;
     for (int qb = wave * per; qb < min(a.nbatch, wave * per + per); qb++) {
       const int32_t *rec = a.batch + (size_t)qb * lfc::kBatchWords;
-      int32_t x[B];
+      uint32_t x[B / 2];
       load_row<B>(a.rkv + ((size_t)(rec[5] * a.nb + b) * 3 + blockIdx.z) * S + y * B, x);
       store_row<B>(a.out + ((size_t)(rec[1] * 3 + blockIdx.z) * a.hp + blockIdx.y * B + y) * a.wp + bx * B, x);
     }
     return;
   }
-  const uint32_t *dj = desc + j * a.n_srv;
-  if (staged) lf_leaves<B>(a, stage + s_so[j], dj, lut, wave, lane);
-  else lf_leaves<B>(a, a.srv + s_o0[j], dj, lut, wave, lane);
+  if (staged) lf_leaves<B>(a, stage, s_so, desc, plans, scratch, lut, wave, lane);
+  else lf_leaves<B>(a, a.srv, s_o0, desc, plans, scratch, lut, wave, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -492,10 +523,10 @@ struct RAArgs {
 };
 
 // Row y of block b, channel c, of view vi (Alg. 2): key-view row plus the
-// residual rows of the view's ancestors.
+// residual rows of the view's ancestors, as B/2 packed int16 pairs.
 template <int B>
-__device__ __forceinline__ void gather_row(const RAArgs &a, int vi, int b, int c, int y, const uint16_t *lut,
-                                           int32_t x[B]) {
+__device__ __forceinline__ void gather_row(const RAArgs &a, int vi, int b, int c, int y, uint32_t plan_t,
+                                           uint32_t plan_q, const uint16_t *lut, uint32_t x[B / 2]) {
   constexpr int S = B * B;
   const int root = a.root[vi];
   load_row<B>(a.rkv + ((size_t)(root * a.nb + b) * 3 + c) * S + y * B, x);
@@ -510,10 +541,10 @@ __device__ __forceinline__ void gather_row(const RAArgs &a, int vi, int b, int c
     const uint32_t bit = (uint32_t)s & 31u;
     if ((bm >> bit) & 1u) {
       const uint32_t idx = a.dbase[(size_t)g * a.nbw + (s >> 5)] + __popc(bm & ((1u << bit) - 1u));
-      int32_t d[B];
-      decode_row<B>(gw, a.poff[idx], y, a.q, lut, d);
+      uint32_t d[B / 2];
+      decode_row<B>(gw, a.poff[idx], plan_t, plan_q, y, a.q, lut, d);
 #pragma unroll
-      for (int i = 0; i < B; i++) x[i] += d[i];
+      for (int i = 0; i < B / 2; i++) x[i] = add_pk(x[i], d[i]);
     }
   }
 }
@@ -547,13 +578,13 @@ __global__ __launch_bounds__(kThreads) void k_decode_blocks(BlocksArgs a) {
     vi = (int)(r / a.ra.nb);
     b = (int)(r % a.ra.nb);
   }
-  int32_t x[B];
+  uint32_t x[B / 2];
   if (vi < 0 || vi >= a.ra.nv || b < 0 || b >= a.ra.nb) {
     if (sub == 0) atomicOr(a.err, 1);
 #pragma unroll
-    for (int i = 0; i < B; i++) x[i] = 0;
+    for (int i = 0; i < B / 2; i++) x[i] = 0;
   } else {
-    gather_row<B>(a.ra, vi, b, c, y, lut, x);
+    gather_row<B>(a.ra, vi, b, c, y, digit_plan<B>(y, true), digit_plan<B>(y, false), lut, x);
   }
   store_row<B>(a.out + ((size_t)r * 3 + c) * S + y * B, x);
 }
@@ -585,6 +616,9 @@ __device__ __forceinline__ void cell(float x, int n, int &i0, int &i1, float &f)
 }
 
 __device__ __forceinline__ float lerpf(float a, float b, float f) { return a + f * (b - a); }
+
+__device__ __forceinline__ int32_t lo16(uint32_t w) { return (int32_t)(int16_t)(w & 0xFFFFu); }
+__device__ __forceinline__ int32_t hi16(uint32_t w) { return (int32_t)(int16_t)(w >> 16); }
 
 template <int B>
 __global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
@@ -626,18 +660,22 @@ __global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
     const int fy = rem / (FBX * B), rem2 = rem - fy * FBX * B;
     const int fx = rem2 / B, y = rem2 - fx * B;
     const int b = (fby0 + fy) * a.ra.nbx + fbx0 + fx;
-    int32_t Y[B], Co[B], Cg[B];
-    gather_row<B>(a.ra, vis[k], b, 0, y, lut, Y);
-    gather_row<B>(a.ra, vis[k], b, 1, y, lut, Co);
-    gather_row<B>(a.ra, vis[k], b, 2, y, lut, Cg);
+    const uint32_t plan_t = digit_plan<B>(y, true), plan_q = digit_plan<B>(y, false);
+    uint32_t Y[B / 2], Co[B / 2], Cg[B / 2];
+    gather_row<B>(a.ra, vis[k], b, 0, y, plan_t, plan_q, lut, Y);
+    gather_row<B>(a.ra, vis[k], b, 1, y, plan_t, plan_q, lut, Co);
+    gather_row<B>(a.ra, vis[k], b, 2, y, plan_t, plan_q, lut, Cg);
     uint32_t *dst = rgb + (k * FH + fy * B + y) * FW + fx * B;
 #pragma unroll
     for (int i = 0; i < B; i++) {
+      const int32_t yv = (i & 1) ? hi16(Y[i / 2]) : lo16(Y[i / 2]);
+      const int32_t co = (i & 1) ? hi16(Co[i / 2]) : lo16(Co[i / 2]);
+      const int32_t cg = (i & 1) ? hi16(Cg[i / 2]) : lo16(Cg[i / 2]);
       // inverse YCoCg-R (Sec. 4), clamped to 8 bits
-      const int32_t t = Y[i] - (Cg[i] >> 1);
-      const int32_t G = Cg[i] + t;
-      const int32_t Bc = t - (Co[i] >> 1);
-      const int32_t R = Bc + Co[i];
+      const int32_t t = yv - (cg >> 1);
+      const int32_t G = cg + t;
+      const int32_t Bc = t - (co >> 1);
+      const int32_t R = Bc + co;
       dst[i] = (uint32_t)min(max(R, 0), 255) | ((uint32_t)min(max(G, 0), 255) << 8) |
                ((uint32_t)min(max(Bc, 0), 255) << 16);
     }
@@ -739,7 +777,7 @@ template <int B>
 lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s) {
   const lfc::Geometry &g = lf->geo;
   constexpr int NBLK = 64 / B;
-  const int64_t fixed = kLFHeadWords + (int64_t)NBLK * g.n_srv + kStagePad;
+  const int64_t fixed = kLFHeadWords + (int64_t)NBLK * g.n_srv + kLFWaves * PhaseBScratch<B>::kWords + kStagePad;
   const int64_t avail = max_lds_bytes() / 4 - fixed;
   if (avail < 0)
     return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: tree too large for the whole-field kernel; use BLOCKS layout");
