@@ -214,6 +214,47 @@ void build_tree_tables(const Geometry &g, TreeTables &t) {
   }
 }
 
+// Consecutive batches grouped so that their leaves and every ancestor level
+// fit the residual tile of the whole-field kernel.
+void build_chunks(const Geometry &g, const std::vector<int32_t> &batch, std::vector<int32_t> &chunks) {
+  chunks.clear();
+  const int nb = (int)(batch.size() / kBatchWords), L = g.L;
+  if (L < 2) return;
+  const int budget = kChunkResBytes / (128 * g.B);
+  for (int q = 0; q < nb;) {
+    int lo[kMaxLevels], hi[kMaxLevels], n = 0, total = 0;
+    for (int l = 0; l < L - 1; l++) lo[l] = hi[l] = -1;
+    while (q + n < nb) {
+      const int32_t *r = &batch[(size_t)(q + n) * kBatchWords];
+      int nlo[kMaxLevels], nhi[kMaxLevels], t = 0;
+      for (int l = 0; l < L - 1; l++) {
+        const int first = l == 0 ? r[10] : r[6 + (L - 2 - l)];
+        const int last = l == 0 ? r[10] + r[0] - 1 : first;
+        nlo[l] = lo[l] < 0 ? first : std::min(lo[l], first);
+        nhi[l] = std::max(hi[l], last);
+        t += nhi[l] - nlo[l] + 1;
+      }
+      if (n > 0 && t > budget) break;
+      for (int l = 0; l < L - 1; l++) {
+        lo[l] = nlo[l];
+        hi[l] = nhi[l];
+      }
+      total = t;
+      n++;
+    }
+    int32_t rec[kChunkWords] = {0};
+    rec[0] = q;
+    rec[1] = n;
+    rec[2] = total;
+    for (int l = 0; l < L - 1; l++) {
+      rec[3 + 2 * l] = lo[l];
+      rec[4 + 2 * l] = hi[l] - lo[l] + 1;
+    }
+    chunks.insert(chunks.end(), rec, rec + kChunkWords);
+    q += n;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // encoder
 // ---------------------------------------------------------------------------
@@ -540,6 +581,7 @@ struct Parsed {
   size_t rkv_bytes = 0;
   std::vector<uint32_t> off, srv;       // aligned copies; srv ends with the 2 zero words
   std::vector<uint32_t> dbase, poff;    // directory (built on request)
+  std::vector<uint32_t> pbase;          // [ng+1] index in poff of each group's first stored block
   uint64_t present = 0;
 };
 
@@ -670,7 +712,8 @@ static lfc_status parse_validate(const void *stream, size_t bytes, Parsed &ps, b
   // Directory for random access (built once, as Sec. 3.5 locates blocks at
   // initialisation): dbase[g][w] = index in poff of the first stored node of
   // bitmap word w; poff[i] = (payload bit offset within the group << 5) | code.
-  std::vector<uint32_t> pbase(g.ng + 1, 0);
+  std::vector<uint32_t> &pbase = ps.pbase;
+  pbase.assign(g.ng + 1, 0);
   for (int gi = 0; gi < g.ng; gi++) pbase[gi + 1] = pbase[gi] + count[gi];
   ps.dbase.assign((size_t)g.ng * g.nbw, 0);
   ps.poff.assign(std::max<uint64_t>(ps.present, 1), 0);
@@ -772,7 +815,9 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
     size_t at;
   };
   static const uint32_t zeros[64] = {0};
-  Part parts[9] = {
+  std::vector<int32_t> chunks;
+  build_chunks(ps.g, tt.batch, chunks);
+  Part parts[11] = {
       {ps.rkv, ps.rkv_bytes, 0},
       {ps.off.data(), ps.off.size() * 4, 0},
       {ps.srv.data(), ps.srv.size() * 4, 0},
@@ -782,6 +827,8 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
       {tt.root.data(), tt.root.size() * 4, 0},
       {tt.batch.data(), tt.batch.size() * 4, 0},
       {zeros, 4, 0},
+      {chunks.data(), chunks.size() * 4, 0},
+      {ps.pbase.data(), ps.pbase.size() * 4, 0},
   };
   size_t total = 0;
   for (auto &pt : parts) {
@@ -829,16 +876,21 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
   lf->d_root = reinterpret_cast<const int32_t *>(d + parts[6].at);
   lf->d_batch = reinterpret_cast<const int32_t *>(d + parts[7].at);
   lf->n_batch = (int)(tt.batch.size() / kBatchWords);
+  lf->d_chunk = reinterpret_cast<const int32_t *>(d + parts[9].at);
+  lf->d_pbase = reinterpret_cast<const uint32_t *>(d + parts[10].at);
+  lf->n_chunk = (int)(chunks.size() / kChunkWords);
+  for (int i = 0; i < lf->n_chunk; i++) lf->max_chunk_nodes = std::max(lf->max_chunk_nodes, chunks[(size_t)i * kChunkWords + 2]);
   lf->d_err = reinterpret_cast<int32_t *>(d + parts[8].at);
-  // LDS staging of the whole-field kernel is sized by the largest strip
+  // LDS staging of the whole-field kernel is sized by the largest strip:
+  // group words, directory entries and directory rows
   const int nblk = 64 / g.B;
   for (int c = 0; c < 3; c++)
     for (int by = 0; by < g.nby; by++)
       for (int bx0 = 0; bx0 < g.nbx; bx0 += nblk) {
-        uint64_t words = 0;
+        uint64_t words = (uint64_t)nblk * g.nbw;   // directory rows
         for (int bx = bx0; bx < std::min(bx0 + nblk, g.nbx); bx++) {
           const int gi = 3 * (by * g.nbx + bx) + c;
-          words += ps.off[gi + 1] - ps.off[gi];
+          words += ps.off[gi + 1] - ps.off[gi] + ps.pbase[gi + 1] - ps.pbase[gi];
         }
         lf->max_strip_words = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(lf->max_strip_words, words), 1u << 30);
       }

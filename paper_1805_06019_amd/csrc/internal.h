@@ -38,6 +38,15 @@ lfc_status make_geometry(const lfc_params &p, Geometry &g, std::string *why);
 //   index of the first view of the run (the others follow it), [11..15] 0.
 constexpr int kBatch = 4;
 constexpr int kBatchWords = 16;
+// Chunks of consecutive batches decoded together by the whole-field kernel:
+//   [0] first batch, [1] batches, [2] nodes in all, then for each level
+//   l = 0..L-2: [3+2l] first serial index, [4+2l] node count (the nodes of a
+//   level under a run of consecutive leaves are consecutive).
+constexpr int kChunkWords = 16;
+// residual-tile budget of one chunk, in nodes: LDS bytes / (64/B blocks * B*B
+// samples * 2 bytes) = kChunkResBytes / (128 B)
+constexpr int kChunkResBytes = 32 * 1024;
+void build_chunks(const Geometry &g, const std::vector<int32_t> &batch, std::vector<int32_t> &chunks);
 struct TreeTables {
   std::vector<int32_t> path, root, batch;
   std::vector<std::vector<int32_t>> serial;  // [level][node id] -> BFS index (-1 on top)
@@ -65,10 +74,14 @@ struct lfc_lf {
   const uint32_t *d_srv = nullptr;   // SRV words, zero-padded at the end
   const uint32_t *d_dbase = nullptr; // [ng][nbw] directory index of each bitmap word's first node
   const uint32_t *d_poff = nullptr;  // [present] (payload bit offset in group << 5) | code
+  const uint32_t *d_pbase = nullptr; // [ng+1] index in d_poff of each group's first stored block
   const int32_t *d_path = nullptr;   // [nv][L-1]
   const int32_t *d_root = nullptr;   // [nv]
   const int32_t *d_batch = nullptr;  // [n_batch][kBatchWords]
   int n_batch = 0;
+  const int32_t *d_chunk = nullptr;  // [n_chunk][kChunkWords]
+  int n_chunk = 0, max_chunk_nodes = 0;
   int32_t *d_err = nullptr;          // device error flag
-  uint32_t max_strip_words = 0;      // largest sum of group lengths over a strip of 64/B blocks of one channel
+  uint32_t max_strip_words = 0;      // largest group words + directory entries + directory rows of a strip
+                                     // of 64/B blocks of one channel
 };

@@ -229,282 +229,408 @@ __device__ __forceinline__ void store_row(int16_t *p, const uint32_t x[B / 2]) {
   }
 }
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
-// Inclusive prefix sum over the 64 lanes with DPP row shifts and row
-// broadcasts (no LDS traffic): shifts by 1, 2, 4, 8 scan each row of 16
-// lanes, then lane 15 of each row is added to the next row and lane 31 to the
-// upper half.  Lanes without a source add 0.
-__device__ __forceinline__ uint32_t wave_scan_dpp(uint32_t v) {
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
-  return v;
-}
-
 // ---------------------------------------------------------------------------
 // whole light field, images layout
 // ---------------------------------------------------------------------------
 
 constexpr int kLFThreads = 512;
 constexpr int kLFWaves = kLFThreads / 64;
-constexpr int kLFHeadWords = 400;     // LDS words before the descriptors (LUT, group extents)
-constexpr int kStagePad = 8;          // zero words after the staged groups
+constexpr int kLFHeadWords = 704;     // LDS words before the residual tile (LUT, per-block extents)
+constexpr int kStagePad = 8;          // zero words after the staged group words
 
 struct LFArgs {
   const int16_t *rkv;
   const uint32_t *off;
   const uint32_t *srv;
-  const int32_t *batch;  // [nbatch][kBatchWords] runs of sibling leaves (see internal.h)
-  int16_t *out;          // [nv][3][hp][wp]
-  int nbx, n_srv, nbw, nv, L, q, wp, hp, nb, nbatch;
-  int stage_cap;         // LDS words available for the strip's groups
+  const uint32_t *dbase;   // directory: [ng][nbw] index of each bitmap word's first stored node
+  const uint32_t *poff;    // directory: entry per stored block
+  const uint32_t *pbase;   // [ng+1] first directory entry of each group
+  const int32_t *batch;    // [nbatch][kBatchWords] runs of sibling leaves (see internal.h)
+  const int32_t *chunk;    // [nchunk][kChunkWords] runs of batches decoded together
+  int16_t *out;            // [nv][3][hp][wp]
+  int nbx, n_srv, nbw, nv, L, q, wp, hp, nb, nbatch, nchunk, max_chunk_nodes;
+  int stage_cap;           // LDS words available for staging the strip
+  int vec_store;           // output rows may be stored 16 bytes at a time
+  int n_top, key_words;    // key views; LDS words of the strip's key-view rows (0: not staged)
 };
 
-// Where every node's residual block starts in group gw (or that it is absent):
-// bitmap rank by ballot, 5-bit code, wave prefix sum of the block sizes.
-template <int S>
-__device__ __forceinline__ void scan_group(const uint32_t *gw, uint32_t len, uint32_t *dj, int n_srv, int nbw,
-                                           int lane) {
-  uint32_t cnt = 0;
-  for (int w = lane; w < nbw; w += 64) cnt += __popc(gw[w]);
-  cnt = wave_sum(cnt);
-  const uint32_t code_bit0 = 32u * nbw;
-  uint32_t rank_base = 0, bit_base = 32u * (nbw + (5u * cnt + 31u) / 32u);
-  for (int s0 = 0; s0 < n_srv; s0 += 64) {
-    const int s = s0 + lane;
-    const bool pres = s < n_srv && ((gw[s >> 5] >> (s & 31)) & 1u);
-    const uint64_t bal = __ballot(pres);
-    const uint32_t rank = rank_base + __popcll(bal & ((1ull << lane) - 1ull));
-    uint32_t code = 0, size = 0;
-    if (pres) {
-      code = (uint32_t)window64(gw, code_bit0 + 5u * rank) & 31u;
-      size = block_bits<S>(code);
+// A whole block of a known kind (0 plain bits, 1 trit, 2 quint) decoded by one
+// lane: d holds the B*B residuals as packed int16 pairs, row-major.  With the
+// kind and the row fixed at compile time, every field position except the
+// m-dependent low-bit offsets is a constant.
+template <int B, int KIND>
+__device__ __forceinline__ void decode_block_k(const uint32_t *gw, uint32_t e, int q, const uint16_t *lut,
+                                               uint32_t d[B * B / 2]) {
+  constexpr int S = B * B;
+  constexpr uint32_t HDR = KIND == 0 ? 0u : (KIND == 1 ? Planes<S>::trit : Planes<S>::quint);
+  constexpr uint32_t FW = KIND == 1 ? 8u : 7u, GB = KIND == 1 ? 10u : 9u, DB = KIND == 1 ? 2u : 3u;
+  constexpr uint32_t LB = KIND == 1 ? 0u : 256u, DMASK = KIND == 1 ? 3u : 7u;
+  using DigitWord = std::conditional_t<B == 8, uint64_t, uint32_t>;
+  const uint32_t code = e & 31u, rel = e >> 5;
+  const uint32_t m = KIND == 0 ? code + 1u : (KIND == 1 ? code - 12u : code - 19u);
+  const uint32_t lmask = (1u << m) - 1u;
+#pragma unroll
+  for (int y = 0; y < B; y++) {
+    uint32_t u[B];
+    const uint32_t p = rel + HDR + (uint32_t)(y * B) * m;
+    {
+      const uint64_t v = window64(gw, p);
+#pragma unroll
+      for (int k = 0; k < (B < 4 ? B : 4); k++) u[k] = (uint32_t)(v >> (k * m)) & lmask;
+      if constexpr (B > 4) {
+        const uint64_t v2 = window64(gw, p + 4u * m);
+#pragma unroll
+        for (int k = 4; k < B; k++) u[k] = (uint32_t)(v2 >> ((k - 4) * m)) & lmask;
+      }
     }
-    const uint32_t incl = wave_scan_dpp(size);
-    // a block starts inside its group; the clamp keeps every later read there
-    const uint32_t at = min(bit_base + incl - size, 32u * len);
-    if (s < n_srv) dj[s] = pres ? ((at << 5) | code) : kAbsent;
-    rank_base += __popcll(bal);
-    bit_base += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    if constexpr (KIND != 0) {
+      const uint32_t plan = digit_plan<B>(y, KIND == 1);   // a constant once unrolled
+      const uint32_t pd = rel + (plan & 0xffu);
+      const uint32_t *qd = gw + (pd >> 5);
+      const uint32_t win = __builtin_amdgcn_alignbit(qd[1], qd[0], pd & 31u);
+      DigitWord D = 0;
+#pragma unroll
+      for (int i = 0; i < (B == 8 ? 4 : 2); i++) {
+        const uint32_t wdt = (plan >> (16 + 4 * i)) & 15u;
+        if (wdt) D |= (DigitWord)lut[LB + ((win >> (i * FW)) & ((1u << wdt) - 1u))] << (i * GB);
+      }
+      const DigitWord rowd = D >> ((plan >> 8) & 0xffu);
+#pragma unroll
+      for (int k = 0; k < B; k++) u[k] |= (((uint32_t)(rowd >> (k * DB))) & DMASK) << m;
+    }
+#pragma unroll
+    for (int i = 0; i < B / 2; i++) d[y * (B / 2) + i] = unzigzag_pk(u[2 * i] | (u[2 * i + 1] << 16), q);
   }
 }
 
-// LDS written by some lanes of a wave and read by others of the same wave:
-// order the accesses (LDS instructions of one wave complete in order).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// A whole block of any kind decoded by one lane, with the generic row
+// decoder (one code for the three kinds, the row plans constant).
+template <int B>
+__device__ __forceinline__ void decode_block(const uint32_t *gw, uint32_t e, int q, const uint16_t *lut,
+                                             uint32_t d[B * B / 2]) {
+#pragma unroll
+  for (int y = 0; y < B; y++)
+    decode_row<B>(gw, e, digit_plan<B>(y, true), digit_plan<B>(y, false), y, q, lut, d + y * (B / 2));
 }
 
-// Per-wave LDS scratch of phase B: the list of stored (sibling, lane) rows
-// and their decoded residuals.
-template <int B>
-struct PhaseBScratch {
-  static constexpr int kListWords = lfc::kBatch * 64 / 2;      // u16 items
-  static constexpr int kResWords = lfc::kBatch * 64 * (B / 2);
-  static constexpr int kWords = kListWords + kResWords;
+// n words from global memory into LDS, without a round trip through
+// registers: lane i of each wave-wide load writes dst[i0 + i].
+__device__ __forceinline__ void lds_copy(uint32_t *dst, const uint32_t *src, uint32_t n, int lane) {
+  for (uint32_t i0 = 0; i0 < n; i0 += 64)
+    if (i0 + (uint32_t)lane < n)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(src + i0 + lane),
+                                       (__attribute__((address_space(3))) void *)(dst + i0), 4, 0, 0);
+}
+
+// Directory entry (payload offset << 5 | code) of node s in a staged or
+// global group, or kAbsent: bitmap bit, rank by popcount from the word's
+// directory base, then the entry.  pb re-bases directory indices onto pe.
+__device__ __forceinline__ uint32_t strip_entry(const uint32_t *words, const uint32_t *dir, const uint32_t *pe,
+                                                uint32_t wo, uint32_t dr, uint32_t pb, int s) {
+  const uint32_t bm = words[wo + (s >> 5)];
+  const uint32_t bit = (uint32_t)s & 31u;
+  if (!((bm >> bit) & 1u)) return kAbsent;
+  return pe[dir[dr + (s >> 5)] - pb + __popc(bm & ((1u << bit) - 1u))];
+}
+
+// Tables that every lane of a wave reads at the same address (tree runs,
+// chunk records) are read through the scalar unit: a vector load would make
+// the wave wait for all of its outstanding stores as well.
+typedef const __attribute__((address_space(4))) int32_t *uniform_i32;
+__device__ __forceinline__ uniform_i32 as_uniform(const int32_t *p) { return (uniform_i32)p; }
+
+// A chunk record held in scalar registers: runs [q0, q0+nq), nn nodes, and
+// for each level from the leaves up its first serial index and node count.
+struct ChunkRec {
+  int q0, nq, nn;
+  int lo[lfc::kMaxLevels - 1], cnt[lfc::kMaxLevels - 1];
 };
 
-// Phase B of the whole-field kernel for one wave: a run of sibling batches in
-// serial order (one 64-byte scalar record each).  The reconstruction of every
-// ancestor level of the current batch is kept in registers (T[t], t =
-// top..4), so a parent's residual is decoded once per subtree.  For the
-// leaves, the rows whose block is stored are first listed in LDS and decoded
-// densely (about a third of them at 40 dB), then every lane adds its row's
-// residual, if any, to the parent and stores.
+__device__ __forceinline__ ChunkRec read_chunk(const int32_t *chunk, int ci, int L) {
+  const uniform_i32 cr = as_uniform(chunk + (size_t)ci * lfc::kChunkWords);
+  ChunkRec r;
+  r.q0 = cr[0];
+  r.nq = cr[1];
+  r.nn = cr[2];
+#pragma unroll
+  for (int l = 0; l < lfc::kMaxLevels - 1; l++) {
+    r.lo[l] = l < L - 1 ? cr[3 + 2 * l] : 0;
+    r.cnt[l] = l < L - 1 ? cr[4 + 2 * l] : 0;
+  }
+  return r;
+}
+
+// Serial index of local node ln of a chunk (levels stored from the leaves up).
+__device__ __forceinline__ int chunk_node(const ChunkRec &cr, int ln) {
+  int o = 0, s = -1;
+#pragma unroll
+  for (int l = 0; l < lfc::kMaxLevels - 1; l++) {
+    if (ln >= o && ln < o + cr.cnt[l]) s = cr.lo[l] + (ln - o);
+    o += cr.cnt[l];
+  }
+  return s;
+}
+
+// The part of one pass of phase B that touches the strip's data, for data in
+// LDS (staged) or in global memory.
 template <int B>
-__device__ __forceinline__ void lf_leaves(const LFArgs &a, const uint32_t *base, const uint32_t *goff,
-                                          const uint32_t *desc, const uint32_t *plans, uint32_t *scratch,
-                                          const uint16_t *lut, int wave, int lane) {
+__device__ __forceinline__ void lf_chunk_decode(const LFArgs &a, const ChunkRec &cr, const uint32_t *words,
+                                                const uint32_t *dir, const uint32_t *pe, const uint32_t *s_wo,
+                                                const uint32_t *s_dr, const uint32_t *s_pb, const uint32_t *s_len,
+                                                uint32_t *s_cnt, uint16_t *items, int item_cap, uint32_t *tile,
+                                                const uint16_t *lut, int tid, int wave, int lane) {
   constexpr int S = B * B, NBLK = 64 / B, H = B / 2;
-  const int j = lane % NBLK, y = lane / NBLK;
-  const int bx = blockIdx.x * NBLK + j, by = blockIdx.y, c = blockIdx.z;
-  const bool active = bx < a.nbx;
-  const int b = by * a.nbx + (active ? bx : 0);
-  const int top = kMaxLevels - a.L;
-  const size_t row = (size_t)(by * B + y) * a.wp + bx * B;
-  const size_t vstride = (size_t)3 * a.hp * a.wp, cplane = (size_t)c * a.hp * a.wp;
-  const uint32_t *dj = desc + j * a.n_srv;
-  const uint32_t *gw = base + goff[j];
-  const uint32_t plan_t = plans[2 * y], plan_q = plans[2 * y + 1];
-  uint16_t *list = reinterpret_cast<uint16_t *>(scratch + wave * PhaseBScratch<B>::kWords);
-  uint32_t *res = scratch + wave * PhaseBScratch<B>::kWords + PhaseBScratch<B>::kListWords;
-  const uint64_t lanes_below = (1ull << lane) - 1ull;
-  uint32_t T[kMaxLevels - 1][H];
-  int cache[kMaxLevels - 1];
+  const int nn = cr.nn;
+  // (2) list the stored (node, block) pairs, one list per range kind
+  for (int c0 = wave * 64; c0 < nn * NBLK; c0 += kLFThreads) {
+    const int idx = c0 + lane;
+    const int ln = idx / NBLK, jj = idx % NBLK;
+    uint32_t e = kAbsent;
+    if (idx < nn * NBLK && s_len[jj]) e = strip_entry(words, dir, pe, s_wo[jj], s_dr[jj], s_pb[jj], chunk_node(cr, ln));
+    const uint32_t kind = e == kAbsent ? 3u : code_kind(e & 31u);
 #pragma unroll
-  for (int t = 0; t < kMaxLevels - 1; t++) cache[t] = -1;
-  const int per = (a.nbatch + kLFWaves - 1) / kLFWaves;
-  const int q0 = wave * per, q1 = min(a.nbatch, q0 + per);
-  for (int qb = q0; qb < q1; qb++) {
-    const int32_t *rec = a.batch + (size_t)qb * lfc::kBatchWords;
-    bool changed = false;
-#pragma unroll
-    for (int t = 0; t < kMaxLevels - 1; t++) {
-      if (t < top) continue;
-      if (t == top) {
-        const int root = rec[5];
-        changed = root != cache[t];
-        if (changed) {
-          cache[t] = root;
-          if (active) load_row<B>(a.rkv + ((size_t)(root * a.nb + b) * 3 + c) * S + y * B, T[t]);
-          else
-#pragma unroll
-            for (int i = 0; i < H; i++) T[t][i] = 0;
-        }
-      } else {
-        const int s = rec[6 + t - top - 1];
-        changed = changed || s != cache[t];
-        if (changed) {
-          cache[t] = s;
-          const uint32_t e = dj[s];
-          uint32_t d[H];
-          if (e != kAbsent) decode_row<B>(gw, e, plan_t, plan_q, y, a.q, lut, d);
-          else
-#pragma unroll
-            for (int i = 0; i < H; i++) d[i] = 0;
-#pragma unroll
-          for (int i = 0; i < H; i++) T[t][i] = add_pk(T[t > 0 ? t - 1 : 0][i], d[i]);
-        }
-      }
+    for (uint32_t K = 0; K < 3; K++) {
+      const uint64_t bal = __ballot(kind == K);
+      if (!bal) continue;
+      uint32_t at = 0;
+      if (lane == 0) at = atomicAdd(&s_cnt[K], (uint32_t)__popcll(bal));
+      at = (uint32_t)__builtin_amdgcn_readfirstlane((int)at);
+      if (kind == K) items[K * item_cap + at + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)((ln << 5) | jj);
     }
-    const int nsib = rec[0], s0 = rec[10];
-    bool stored[lfc::kBatch];
-    uint32_t cnt = 0;
+  }
+  __syncthreads();
+  // (3) decode every listed block, once, whole, into the tile; the three
+  // lists are laid end to end so a wave mostly sees a single kind
+  const uint32_t n0 = s_cnt[0], n1 = s_cnt[1], n2 = s_cnt[2];
+  for (uint32_t it = tid; it < n0 + n1 + n2; it += kLFThreads) {
+    const uint32_t K = it < n0 ? 0u : (it < n0 + n1 ? 1u : 2u);
+    const uint32_t id = items[K * item_cap + it - (K == 0 ? 0u : (K == 1 ? n0 : n0 + n1))];
+    const int ln = (int)(id >> 5), jj = (int)(id & 31u);
+    const uint32_t e = strip_entry(words, dir, pe, s_wo[jj], s_dr[jj], s_pb[jj], chunk_node(cr, ln));
+    const uint32_t *gw = words + s_wo[jj];
+    uint32_t d[S / 2];
+    if (K == 0) decode_block_k<B, 0>(gw, e, a.q, lut, d);
+    else if (K == 1) decode_block_k<B, 1>(gw, e, a.q, lut, d);
+    else decode_block_k<B, 2>(gw, e, a.q, lut, d);
 #pragma unroll
-    for (int i = 0; i < lfc::kBatch; i++) {
-      stored[i] = i < nsib && dj[s0 + i] != kAbsent;
-      const uint64_t bal = __ballot(stored[i]);
-      if (stored[i]) list[cnt + __popcll(bal & lanes_below)] = (uint16_t)(i * 64 + lane);
-      cnt += __popcll(bal);
-    }
-    wave_lds_sync();
-    for (uint32_t p0 = 0; p0 < cnt; p0 += 64) {
-      if (p0 + lane < cnt) {
-        const uint32_t item = list[p0 + lane];
-        const int i2 = item >> 6, l2 = item & 63, j2 = l2 % NBLK, y2 = l2 / NBLK;
-        uint32_t d[H];
-        decode_row<B>(base + goff[j2], desc[j2 * a.n_srv + s0 + i2], plans[2 * y2], plans[2 * y2 + 1], y2, a.q,
-                      lut, d);
+    for (int yy = 0; yy < B; yy++)
 #pragma unroll
-        for (int h = 0; h < H; h++) res[item * H + h] = d[h];
-      }
-    }
-    wave_lds_sync();
-#pragma unroll
-    for (int i = 0; i < lfc::kBatch; i++) {
-      if (i < nsib) {
-        uint32_t x[H];
-#pragma unroll
-        for (int h = 0; h < H; h++) x[h] = T[kMaxLevels - 2][h];
-        if (stored[i])
-#pragma unroll
-          for (int h = 0; h < H; h++) x[h] = add_pk(x[h], res[(i * 64 + lane) * H + h]);
-        if (active) store_row<B>(a.out + (size_t)rec[1 + i] * vstride + cplane + row, x);
-      }
-    }
-    wave_lds_sync();
+      for (int h = 0; h < H; h++) tile[((ln * B + yy) * NBLK + jj) * H + h] = d[yy * H + h];
   }
 }
 
 // One workgroup = one channel c, one row of blocks by, one strip of 64/B
-// consecutive blocks (64 pixels).  Phase A copies the strip's groups into
-// LDS when they fit (else phase B reads them from global memory) and writes,
-// for every tree node and block, where its residual block starts.  Phase B
-// walks the leaves (lf_leaves), 8 waves splitting them.
+// consecutive blocks (64 pixels).  Phase A copies into LDS, when they fit,
+// the strip's groups with their directory rows and entries (else these are
+// read from global memory).  Phase B walks the leaves in serial order, chunk
+// by chunk: (1) zero the residual tile; (2) list the (node, block) pairs
+// whose block is stored, by range kind; (3) decode each listed block once,
+// whole, one lane per block, into the tile; (4) per sibling batch: key-view
+// row + ancestor rows + leaf row, stored 16 bytes per lane.
 template <int B>
 __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
-  constexpr int S = B * B, NBLK = 64 / B;
+  constexpr int S = B * B, NBLK = 64 / B, H = B / 2;
+  constexpr int NODE_WORDS = B * NBLK * H;             // tile words per node: [B rows][NBLK blocks][H]
+  constexpr int PB = 8 / B;                            // blocks per 16-byte row segment (1 for B = 8)
+  constexpr int LPS = 8 * B;                           // lanes per sibling: 8 segments x B rows
+  constexpr int SPP = 64 / LPS;                        // siblings stored per pass
   extern __shared__ uint32_t smem[];
   uint16_t *lut = reinterpret_cast<uint16_t *>(smem);  // 384 x u16 = 192 words
   uint32_t *s_o0 = smem + 192;                         // group start word in the SRV section
   uint32_t *s_len = smem + 256;                        // group length in words
-  uint32_t *s_so = smem + 320;                         // group start in the staging area, and the total
-  uint32_t *plans = smem + 384;                        // [B][2] digit plans per row (trit, quint)
-  uint32_t *desc = smem + kLFHeadWords;                // [NBLK][n_srv]
-  uint32_t *scratch = desc + NBLK * a.n_srv;           // [kLFWaves][PhaseBScratch<B>::kWords]
-  uint32_t *stage = scratch + kLFWaves * PhaseBScratch<B>::kWords;  // [stage_cap + kStagePad]
+  uint32_t *s_P = smem + 320;                          // stored blocks of the group
+  uint32_t *s_wo = smem + 384;                         // group words: offset from the words base
+  uint32_t *s_dr = smem + 448;                         // directory row: offset from the dir base
+  uint32_t *s_pb = smem + 512;                         // directory entries: re-basing of the indices
+  uint32_t *s_cnt = smem + 576;                        // [0..2] list sizes, [3] staged, [4] group base
+  uint32_t *s_pe = smem + 640;                         // directory entries of the group: staged offset
+  uint32_t *tile = smem + kLFHeadWords;                // [max_chunk_nodes][NODE_WORDS]
+  const int item_cap = a.max_chunk_nodes * NBLK;
+  uint16_t *items = reinterpret_cast<uint16_t *>(tile + a.max_chunk_nodes * NODE_WORDS);  // [3][item_cap]
+  uint32_t *keys = tile + a.max_chunk_nodes * NODE_WORDS + ((3 * item_cap + 7) / 8) * 4;  // [n_top][B][NBLK][H]
+  uint32_t *stage = keys + a.key_words;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   for (int t = tid; t < kLutEntries; t += kLFThreads) lut[t] = lut_entry(t);
-  if (tid < 2 * B) plans[tid] = digit_plan<B>(tid >> 1, (tid & 1) == 0);
   if (tid < NBLK) {
     const int bx = blockIdx.x * NBLK + tid;
-    uint32_t o0 = 0, o1 = 0;
+    uint32_t o0 = 0, o1 = 0, pb0 = 0, pb1 = 0;
     if (bx < a.nbx) {
       const int g = 3 * (blockIdx.y * a.nbx + bx) + blockIdx.z;
       o0 = a.off[g];
       o1 = a.off[g + 1];
+      pb0 = a.pbase[g];
+      pb1 = a.pbase[g + 1];
+      s_dr[tid] = (uint32_t)g * a.nbw;
+    } else {
+      s_dr[tid] = 0;
     }
     s_o0[tid] = o0;
     s_len[tid] = o1 - o0;
+    s_P[tid] = pb1 - pb0;
+    s_pb[tid] = pb0;
   }
   __syncthreads();
   if (tid == 0) {
-    uint32_t acc = 0;
+    uint32_t words = 0, entries = 0;
     for (int j = 0; j < NBLK; j++) {
-      s_so[j] = acc;
-      acc += s_len[j];
+      words += s_len[j];
+      entries += s_P[j];
     }
-    s_so[NBLK] = acc;
-  }
-  __syncthreads();
-  const uint32_t total = s_so[NBLK];
-  const bool staged = total <= (uint32_t)a.stage_cap;
-  if (staged) {
-    for (int j = wave; j < NBLK; j += kLFWaves) {
-      const uint32_t *src = a.srv + s_o0[j];
-      uint32_t *dst = stage + s_so[j];
-      const uint32_t n = s_len[j];
-      for (uint32_t i = lane; i < n; i += 256) {
-        // four loads in flight per lane before the stores
-        uint32_t v[4];
-#pragma unroll
-        for (int u = 0; u < 4; u++) v[u] = i + 64 * u < n ? src[i + 64 * u] : 0u;
-#pragma unroll
-        for (int u = 0; u < 4; u++)
-          if (i + 64 * u < n) dst[i + 64 * u] = v[u];
+    const uint32_t need = words + kStagePad + entries + (uint32_t)NBLK * a.nbw;
+    const bool staged = need <= (uint32_t)a.stage_cap;
+    s_cnt[3] = staged;
+    uint32_t wacc = 0, pacc = words + kStagePad;
+    for (int j = 0; j < NBLK; j++) {
+      if (staged) {
+        s_wo[j] = wacc;
+        s_pe[j] = pacc;
+        s_pb[j] = s_pb[j] - pacc;           // entry index - s_pb = position in the staged entries
+        wacc += s_len[j];
+        pacc += s_P[j];
+      } else {
+        s_wo[j] = s_o0[j];
+        s_pb[j] = 0;                        // global directory indices
       }
     }
-    if (tid < kStagePad) stage[total + tid] = 0;
+    if (staged)
+      for (int j = 0; j < NBLK; j++) s_dr[j + 32] = pacc + (uint32_t)j * a.nbw;  // staged directory rows
+    s_cnt[4] = words;
   }
   __syncthreads();
-  for (int j = wave; j < NBLK; j += kLFWaves) {
-    uint32_t *dj = desc + j * a.n_srv;
-    if (s_len[j] == 0) {
-      for (int s = lane; s < a.n_srv; s += 64) dj[s] = kAbsent;
-      continue;
+  const bool staged = s_cnt[3] != 0;
+  if (staged) {
+    // every copy goes straight from global memory to LDS, all in flight at once
+    for (int j = wave; j < NBLK; j += kLFWaves) {
+      if (!s_len[j]) continue;
+      lds_copy(stage + s_wo[j], a.srv + s_o0[j], s_len[j], lane);
+      lds_copy(stage + s_pe[j], a.poff + (s_pb[j] + s_pe[j]), s_P[j], lane);
+      lds_copy(stage + s_dr[j + 32], a.dbase + s_dr[j], (uint32_t)a.nbw, lane);
     }
-    if (staged) scan_group<S>(stage + s_so[j], s_len[j], dj, a.n_srv, a.nbw, lane);
-    else scan_group<S>(a.srv + s_o0[j], s_len[j], dj, a.n_srv, a.nbw, lane);
   }
+  if (a.key_words) {
+    // the strip's key-view rows, laid out as the tile: [root][row][block][H]
+    const uint32_t *rk = reinterpret_cast<const uint32_t *>(a.rkv);
+    for (int t0 = wave * 64; t0 < a.key_words; t0 += kLFThreads) {
+      const int t = t0 + lane, h = t % H, j = (t / H) % NBLK, y = (t / (H * NBLK)) % B, r = t / (H * NBLK * B);
+      const int bx = blockIdx.x * NBLK + j;
+      if (t < a.key_words && bx < a.nbx)
+        __builtin_amdgcn_global_load_lds(
+            (const __attribute__((address_space(1))) void *)(rk + ((size_t)(r * a.nb + blockIdx.y * a.nbx + bx) * 3 +
+                                                                   blockIdx.z) * (S / 2) + y * H + h),
+            (__attribute__((address_space(3))) void *)(keys + t0), 4, 0, 0);
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  if (staged && tid < kStagePad) stage[s_cnt[4] + tid] = 0;
   __syncthreads();
-  const int j = lane % NBLK;
+  if (staged && tid < NBLK) s_dr[tid] = s_dr[tid + 32];
+  __syncthreads();
+
+  const int by = blockIdx.y, c = blockIdx.z;
+  const size_t vstride = (size_t)3 * a.hp * a.wp, cplane = (size_t)c * a.hp * a.wp;
   if (a.L == 1) {
     // no residual levels: every view is a stored key view
-    const int y = lane / NBLK, bx = blockIdx.x * NBLK + j;
+    const int j = lane % NBLK, y = lane / NBLK, bx = blockIdx.x * NBLK + j;
     if (bx >= a.nbx) return;
-    const int b = blockIdx.y * a.nbx + bx;
+    const int b = by * a.nbx + bx;
     const int per = (a.nbatch + kLFWaves - 1) / kLFWaves;
     for (int qb = wave * per; qb < min(a.nbatch, wave * per + per); qb++) {
-      const int32_t *rec = a.batch + (size_t)qb * lfc::kBatchWords;
-      uint32_t x[B / 2];
-      load_row<B>(a.rkv + ((size_t)(rec[5] * a.nb + b) * 3 + blockIdx.z) * S + y * B, x);
-      store_row<B>(a.out + ((size_t)(rec[1] * 3 + blockIdx.z) * a.hp + blockIdx.y * B + y) * a.wp + bx * B, x);
+      const uniform_i32 rec = as_uniform(a.batch + (size_t)qb * lfc::kBatchWords);
+      uint32_t x[H];
+      load_row<B>(a.rkv + ((size_t)(rec[5] * a.nb + b) * 3 + c) * S + y * B, x);
+      store_row<B>(a.out + (size_t)rec[1] * vstride + cplane + (size_t)(by * B + y) * a.wp + bx * B, x);
     }
     return;
   }
-  if (staged) lf_leaves<B>(a, stage, s_so, desc, plans, scratch, lut, wave, lane);
-  else lf_leaves<B>(a, a.srv, s_o0, desc, plans, scratch, lut, wave, lane);
+  // store-side lane mapping: sibling slot, row, segment of PB blocks
+  const int so = lane / LPS, r = lane % LPS, y = r / 8, jq = r % 8;
+  const int bx0 = blockIdx.x * NBLK + jq * PB;
+  const int nact = max(0, min(PB, a.nbx - bx0));       // blocks of the segment inside the image
+  const bool wide = nact == PB && a.vec_store;          // a 16-byte store is aligned
+  const size_t row = (size_t)(by * B + y) * a.wp + (size_t)bx0 * B;
+  const int L = a.L;
+  int root_cached = -1;
+  uint32_t key[4] = {0, 0, 0, 0};
+  for (int ci = 0; ci < a.nchunk; ci++) {
+    const ChunkRec cr = read_chunk(a.chunk, ci, L);
+    // (1) zero the tile, reset the lists
+    for (int w4 = tid; w4 < cr.nn * NODE_WORDS / 4; w4 += kLFThreads)
+      reinterpret_cast<uint4 *>(tile)[w4] = make_uint4(0u, 0u, 0u, 0u);
+    if (tid < 3) s_cnt[tid] = 0;
+    __syncthreads();
+    if (staged) lf_chunk_decode<B>(a, cr, stage, stage, stage, s_wo, s_dr, s_pb, s_len, s_cnt, items, item_cap, tile,
+                                   lut, tid, wave, lane);
+    else lf_chunk_decode<B>(a, cr, a.srv, a.dbase, a.poff, s_wo, s_dr, s_pb, s_len, s_cnt, items, item_cap, tile,
+                            lut, tid, wave, lane);
+    __syncthreads();
+    // (4) gather and store, waves splitting the chunk's batches
+    const int per = (cr.nq + kLFWaves - 1) / kLFWaves;
+    for (int qb = cr.q0 + wave * per; qb < cr.q0 + min(cr.nq, wave * per + per); qb++) {
+      const uniform_i32 rec = as_uniform(a.batch + (size_t)qb * lfc::kBatchWords);
+      const int root = rec[5];
+      uint32_t anc[4];
+      if (a.key_words) {
+        const uint4 k4 = reinterpret_cast<const uint4 *>(keys)[(((root * B + y) * NBLK + jq * PB) * H) / 4];
+        anc[0] = k4.x;
+        anc[1] = k4.y;
+        anc[2] = k4.z;
+        anc[3] = k4.w;
+      } else {
+        if (root != root_cached) {
+          root_cached = root;
+#pragma unroll
+          for (int k = 0; k < PB; k++)
+            if (k < nact) load_row<B>(a.rkv + ((size_t)(root * a.nb + by * a.nbx + bx0 + k) * 3 + c) * S + y * B,
+                                      key + k * H);
+        }
+#pragma unroll
+        for (int h = 0; h < 4; h++) anc[h] = key[h];
+      }
+      int o = cr.cnt[0];   // local nodes of level 0 come first
+#pragma unroll
+      for (int l = 1; l < lfc::kMaxLevels - 1; l++) {
+        if (l < L - 1) {
+          const int ln = o + (rec[6 + (L - 2 - l)] - cr.lo[l]);
+          const uint4 t4 = reinterpret_cast<const uint4 *>(tile)[(((ln * B + y) * NBLK + jq * PB) * H) / 4];
+          anc[0] = add_pk(anc[0], t4.x);
+          anc[1] = add_pk(anc[1], t4.y);
+          anc[2] = add_pk(anc[2], t4.z);
+          anc[3] = add_pk(anc[3], t4.w);
+          o += cr.cnt[l];
+        }
+      }
+      const int nsib = rec[0], ls0 = rec[10] - cr.lo[0];
+      const int v0 = rec[1], v1 = rec[2], v2 = rec[3], v3 = rec[4];
+      // sibling i of the run: its leaf row plus the ancestors, to view vi
+      auto leaf = [&](int i, uint32_t x[4]) -> int16_t * {
+        const uint4 t4 = reinterpret_cast<const uint4 *>(tile)[((((ls0 + i) * B + y) * NBLK + jq * PB) * H) / 4];
+        x[0] = add_pk(anc[0], t4.x);
+        x[1] = add_pk(anc[1], t4.y);
+        x[2] = add_pk(anc[2], t4.z);
+        x[3] = add_pk(anc[3], t4.w);
+        const int vi = i == 0 ? v0 : (i == 1 ? v1 : (i == 2 ? v2 : v3));
+        return a.out + (size_t)vi * vstride + cplane + row;
+      };
+      // two loops, so that the 16-byte stores stay whole
+      if (wide) {
+        for (int i = so; i < nsib; i += SPP) {
+          uint32_t x[4];
+          int16_t *dst = leaf(i, x);
+          *reinterpret_cast<uint4 *>(dst) = make_uint4(x[0], x[1], x[2], x[3]);
+        }
+      } else if (nact > 0) {
+        for (int i = so; i < nsib; i += SPP) {
+          uint32_t x[4];
+          int16_t *dst = leaf(i, x);
+#pragma unroll
+          for (int k = 0; k < PB; k++)
+            if (k < nact) store_row<B>(dst + k * B, x + k * H);
+        }
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -620,11 +746,31 @@ __device__ __forceinline__ float lerpf(float a, float b, float f) { return a + f
 __device__ __forceinline__ int32_t lo16(uint32_t w) { return (int32_t)(int16_t)(w & 0xFFFFu); }
 __device__ __forceinline__ int32_t hi16(uint32_t w) { return (int32_t)(int16_t)(w >> 16); }
 
+// The residual-block entry (payload offset << 5 | code) of node s in group g,
+// or kAbsent, through the directory built at initialisation.
+__device__ __forceinline__ uint32_t locate(const RAArgs &a, int g, int s, const uint32_t **gw_out) {
+  const uint32_t o0 = a.off[g], o1 = a.off[g + 1];
+  if (o0 == o1) return kAbsent;
+  const uint32_t *gw = a.srv + o0;
+  const uint32_t bm = gw[s >> 5], bit = (uint32_t)s & 31u;
+  if (!((bm >> bit) & 1u)) return kAbsent;
+  *gw_out = gw;
+  return a.poff[a.dbase[(size_t)g * a.nbw + (s >> 5)] + __popc(bm & ((1u << bit) - 1u))];
+}
+
+// One workgroup per (view, output tile).  The tile's source footprint in the
+// four nearest views is reconstructed in LDS: first the key-view rows, then,
+// level by level, every distinct stored residual block of the footprint is
+// located, decoded whole by one lane and added for each of the four views
+// whose path passes through that node (neighbouring views often share
+// ancestors).  The sums are converted to RGB (inverse YCoCg-R, clamped) in
+// place, then every output pixel interpolates its 16 taps in FP32.
 template <int B>
 __global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
+  constexpr int S = B * B, SLOT = 3 * S / 2;   // words per (view, block): 3 channels of packed int16
   extern __shared__ uint32_t smem[];
   uint16_t *lut = reinterpret_cast<uint16_t *>(smem);
-  uint32_t *rgb = smem + kLutEntries / 2;      // [4][fby_max*B][fbx_max*B], packed R | G<<8 | B<<16
+  uint32_t *acc = smem + kLutEntries / 2;       // [4][fbx_max*fby_max][SLOT]
   const int tid = threadIdx.x;
   for (int t = tid; t < kLutEntries; t += kThreads) lut[t] = lut_entry(t);
   const int n = blockIdx.z;
@@ -645,46 +791,85 @@ __global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
   const int ylo = max((int)floorf(ta) - 1, 0), yhi = min((int)floorf(tb) + 2, a.H - 1);
   const int fbx0 = xlo / B, fby0 = ylo / B;
   const int FBX = min(xhi / B - fbx0 + 1, a.fbx_max), FBY = min(yhi / B - fby0 + 1, a.fby_max);
-  const int FW = a.fbx_max * B, FH = a.fby_max * B;
+  const int FB = FBX * FBY, FBM = a.fbx_max * a.fby_max;
   int vis[4];
   vis[0] = jv0 * a.U + iu0;
   vis[1] = jv0 * a.U + iu1;
   vis[2] = jv1 * a.U + iu0;
   vis[3] = jv1 * a.U + iu1;
+  const int depth = a.ra.L - 1;
   __syncthreads();
 
-  // decode the footprint: item = (view k, block row fy, block column fx, row y)
-  const int per_view = FBY * FBX * B;
-  for (int it = tid; it < 4 * per_view; it += kThreads) {
-    const int k = it / per_view, rem = it - k * per_view;
-    const int fy = rem / (FBX * B), rem2 = rem - fy * FBX * B;
-    const int fx = rem2 / B, y = rem2 - fx * B;
-    const int b = (fby0 + fy) * a.ra.nbx + fbx0 + fx;
-    const uint32_t plan_t = digit_plan<B>(y, true), plan_q = digit_plan<B>(y, false);
-    uint32_t Y[B / 2], Co[B / 2], Cg[B / 2];
-    gather_row<B>(a.ra, vis[k], b, 0, y, plan_t, plan_q, lut, Y);
-    gather_row<B>(a.ra, vis[k], b, 1, y, plan_t, plan_q, lut, Co);
-    gather_row<B>(a.ra, vis[k], b, 2, y, plan_t, plan_q, lut, Cg);
-    uint32_t *dst = rgb + (k * FH + fy * B + y) * FW + fx * B;
+  // (1) key-view rows: item = (view k, block, channel, row)
+  for (int it = tid; it < 4 * FB * 3 * B; it += kThreads) {
+    const int y = it % B, r1 = it / B, c = r1 % 3, r2 = r1 / 3, bb = r2 % FB, k = r2 / FB;
+    const int b = (fby0 + bb / FBX) * a.ra.nbx + fbx0 + bb % FBX;
+    uint32_t x[B / 2];
+    load_row<B>(a.ra.rkv + ((size_t)(a.ra.root[vis[k]] * a.ra.nb + b) * 3 + c) * S + y * B, x);
 #pragma unroll
-    for (int i = 0; i < B; i++) {
-      const int32_t yv = (i & 1) ? hi16(Y[i / 2]) : lo16(Y[i / 2]);
-      const int32_t co = (i & 1) ? hi16(Co[i / 2]) : lo16(Co[i / 2]);
-      const int32_t cg = (i & 1) ? hi16(Cg[i / 2]) : lo16(Cg[i / 2]);
+    for (int h = 0; h < B / 2; h++) acc[(k * FBM + bb) * SLOT + c * (S / 2) + y * (B / 2) + h] = x[h];
+  }
+  __syncthreads();
+
+  // (2) residual levels, one at a time (each (view, block, channel) slot gets
+  // one block per level, so the adds never race)
+  for (int l = depth - 1; l >= 0; --l) {
+    int node[4], owner[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) node[k] = a.ra.path[vis[k] * depth + l];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      owner[k] = k;
+      for (int k2 = k - 1; k2 >= 0; --k2)
+        if (node[k2] == node[k]) owner[k] = k2;
+    }
+    for (int it = tid; it < 4 * FB * 3; it += kThreads) {
+      const int c = it % 3, r1 = it / 3, bb = r1 % FB, k = r1 / FB;
+      if (owner[k] != k) continue;
+      const int b = (fby0 + bb / FBX) * a.ra.nbx + fbx0 + bb % FBX;
+      const uint32_t *gw = nullptr;
+      const uint32_t e = locate(a.ra, 3 * b + c, node[k], &gw);
+      if (e == kAbsent) continue;
+      uint32_t d[S / 2];
+      decode_block<B>(gw, e, a.ra.q, lut, d);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; k2++) {
+        if (owner[k2] != k) continue;
+        uint32_t *slot = acc + (k2 * FBM + bb) * SLOT + c * (S / 2);
+#pragma unroll
+        for (int h = 0; h < S / 2; h++) slot[h] = add_pk(slot[h], d[h]);
+      }
+    }
+    __syncthreads();
+  }
+
+  // (3) YCoCg-R -> RGB in place: item = (view, block)
+  for (int it = tid; it < 4 * FB; it += kThreads) {
+    const int k = it / FB, bb = it % FB;
+    uint32_t *slot = acc + (k * FBM + bb) * SLOT;
+    uint32_t v[SLOT];
+#pragma unroll
+    for (int w = 0; w < SLOT; w++) v[w] = slot[w];
+#pragma unroll
+    for (int i = 0; i < S; i++) {
+      const int32_t yv = (i & 1) ? hi16(v[i / 2]) : lo16(v[i / 2]);
+      const int32_t co = (i & 1) ? hi16(v[S / 2 + i / 2]) : lo16(v[S / 2 + i / 2]);
+      const int32_t cg = (i & 1) ? hi16(v[S + i / 2]) : lo16(v[S + i / 2]);
       // inverse YCoCg-R (Sec. 4), clamped to 8 bits
       const int32_t t = yv - (cg >> 1);
       const int32_t G = cg + t;
       const int32_t Bc = t - (co >> 1);
       const int32_t R = Bc + co;
-      dst[i] = (uint32_t)min(max(R, 0), 255) | ((uint32_t)min(max(G, 0), 255) << 8) |
-               ((uint32_t)min(max(Bc, 0), 255) << 16);
+      slot[i] = (uint32_t)min(max(R, 0), 255) | ((uint32_t)min(max(G, 0), 255) << 8) |
+                ((uint32_t)min(max(Bc, 0), 255) << 16);
     }
   }
   __syncthreads();
 
-  // quadrilinear interpolation of every output pixel of the tile
+  // (4) quadrilinear interpolation of every output pixel of the tile
   const size_t plane = (size_t)a.ho * a.wo;
   float *outn = a.out + (size_t)n * 3 * plane;
+  const int FW = FBX * B, FH = FBY * B;
   for (int p = tid; p < a.TX * a.TY; p += kThreads) {
     const int X = tx0 + p % a.TX, Yp = ty0 + p / a.TX;
     if (X >= a.wo || Yp >= a.ho) continue;
@@ -694,14 +879,19 @@ __global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
     cell(vw.t + ((float)Yp + 0.5f) * tys - 0.5f, a.H, y0, y1, ft);
     const int lx0 = min(max(x0 - fbx0 * B, 0), FW - 1), lx1 = min(max(x1 - fbx0 * B, 0), FW - 1);
     const int ly0 = min(max(y0 - fby0 * B, 0), FH - 1), ly1 = min(max(y1 - fby0 * B, 0), FH - 1);
+    // word of footprint pixel (lx, ly) within a view's part of the tile
+    const int i00 = ((ly0 / B) * FBX + lx0 / B) * SLOT + (ly0 % B) * B + lx0 % B;
+    const int i01 = ((ly0 / B) * FBX + lx1 / B) * SLOT + (ly0 % B) * B + lx1 % B;
+    const int i10 = ((ly1 / B) * FBX + lx0 / B) * SLOT + (ly1 % B) * B + lx0 % B;
+    const int i11 = ((ly1 / B) * FBX + lx1 / B) * SLOT + (ly1 % B) * B + lx1 % B;
     uint32_t P[4][4];
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-      const uint32_t *img = rgb + k * FH * FW;
-      P[k][0] = img[ly0 * FW + lx0];
-      P[k][1] = img[ly0 * FW + lx1];
-      P[k][2] = img[ly1 * FW + lx0];
-      P[k][3] = img[ly1 * FW + lx1];
+      const uint32_t *img = acc + k * FBM * SLOT;
+      P[k][0] = img[i00];
+      P[k][1] = img[i01];
+      P[k][2] = img[i10];
+      P[k][3] = img[i11];
     }
 #pragma unroll
     for (int ch = 0; ch < 3; ch++) {
@@ -768,24 +958,32 @@ int max_lds_bytes() {
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
       v = 64 * 1024;
-    cached = v < 64 * 1024 ? v : 64 * 1024;
+    cached = v;
   }
   return cached;
 }
 
+// LDS of the whole-field kernel: the fixed part (LUT and extents, residual
+// tile, block lists) plus staging for the strip's groups with their directory
+// rows and entries, up to 80 KB so that two workgroups share a compute unit.
 template <int B>
 lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s) {
   const lfc::Geometry &g = lf->geo;
-  constexpr int NBLK = 64 / B;
-  const int64_t fixed = kLFHeadWords + (int64_t)NBLK * g.n_srv + kLFWaves * PhaseBScratch<B>::kWords + kStagePad;
-  const int64_t avail = max_lds_bytes() / 4 - fixed;
-  if (avail < 0)
+  constexpr int NBLK = 64 / B, NODE_WORDS = B * NBLK * (B / 2);
+  const int64_t nodes = std::max(lf->max_chunk_nodes, 1);
+  // key-view rows of a strip, when they take at most 16 KB
+  const int64_t key_words = (int64_t)g.n_top * NBLK * (B * B / 2) <= 4096 ? (int64_t)g.n_top * NBLK * (B * B / 2) : 0;
+  const int64_t fixed = kLFHeadWords + nodes * NODE_WORDS + ((3 * nodes * NBLK + 7) / 8) * 4 + key_words;
+  const int64_t limit = max_lds_bytes() / 4;
+  if (fixed > limit)
     return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: tree too large for the whole-field kernel; use BLOCKS layout");
-  int64_t cap = std::min<int64_t>(avail, lf->max_strip_words);
+  const int64_t target = std::min<int64_t>(limit, std::max<int64_t>(80 * 1024 / 4, fixed));
+  int64_t cap = std::min<int64_t>(target - fixed, (int64_t)lf->max_strip_words + kStagePad);
   if (const char *e = getenv("LFC_STAGE_CAP_WORDS")) cap = std::min<int64_t>(cap, std::max(0, atoi(e)));
   const size_t lds = 4 * (size_t)(fixed + cap);
-  LFArgs a{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_batch, out, g.nbx, g.n_srv, g.nbw, g.nv(), g.L, g.q, g.wp, g.hp,
-           g.nb, lf->n_batch, (int)cap};
+  LFArgs a{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_dbase, lf->d_poff, lf->d_pbase, lf->d_batch, lf->d_chunk, out,
+           g.nbx, g.n_srv, g.nbw, g.nv(), g.L, g.q, g.wp, g.hp, g.nb, lf->n_batch, lf->n_chunk, (int)nodes, (int)cap,
+           (int)(g.wp % 8 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0), g.n_top, (int)key_words};
   dim3 grid((g.nbx + NBLK - 1) / NBLK, g.nby, 3);
   hipLaunchKernelGGL(k_decode_lf<B>, grid, dim3(kLFThreads), lds, s, a);
   return launched("lfc_decode_blocks");
@@ -817,7 +1015,7 @@ bool plan_render(const lfc::Geometry &g, int wo, int ho, RenderPlan &pl) {
     // side, the interpolation neighbour and float slack, then block alignment
     const int fbx = ((int)std::ceil((TX - 1) * sxs) + 5 + g.B - 1) / g.B + 2;
     const int fby = ((int)std::ceil((TY - 1) * tys) + 5 + g.B - 1) / g.B + 2;
-    const size_t lds = 4 * ((size_t)kLutEntries / 2 + (size_t)4 * fbx * g.B * fby * g.B);
+    const size_t lds = 4 * ((size_t)kLutEntries / 2 + (size_t)4 * fbx * fby * (3 * g.B * g.B / 2));
     if (lds <= 64 * 1024) {
       pl = RenderPlan{TX, TY, fbx, fby, lds};
       return true;
