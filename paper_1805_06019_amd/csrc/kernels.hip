@@ -322,17 +322,6 @@ __device__ __forceinline__ void lds_copy(uint32_t *dst, const uint32_t *src, uin
                                        (__attribute__((address_space(3))) void *)(dst + i0), 4, 0, 0);
 }
 
-// Directory entry (payload offset << 5 | code) of node s in a staged or
-// global group, or kAbsent: bitmap bit, rank by popcount from the word's
-// directory base, then the entry.  pb re-bases directory indices onto pe.
-__device__ __forceinline__ uint32_t strip_entry(const uint32_t *words, const uint32_t *dir, const uint32_t *pe,
-                                                uint32_t wo, uint32_t dr, uint32_t pb, int s) {
-  const uint32_t bm = words[wo + (s >> 5)];
-  const uint32_t bit = (uint32_t)s & 31u;
-  if (!((bm >> bit) & 1u)) return kAbsent;
-  return pe[dir[dr + (s >> 5)] - pb + __popc(bm & ((1u << bit) - 1u))];
-}
-
 // Tables that every lane of a wave reads at the same address (tree runs,
 // chunk records) are read through the scalar unit: a vector load would make
 // the wave wait for all of its outstanding stores as well.
@@ -371,46 +360,97 @@ __device__ __forceinline__ int chunk_node(const ChunkRec &cr, int ln) {
   return s;
 }
 
-// The part of one pass of phase B that touches the strip's data, for data in
-// LDS (staged) or in global memory.
+// Pairs (node, block) of one chunk handled per lane: enough for the largest
+// chunk the host builds (256/B nodes of 64/B blocks over 512 lanes).
 template <int B>
-__device__ __forceinline__ void lf_chunk_decode(const LFArgs &a, const ChunkRec &cr, const uint32_t *words,
-                                                const uint32_t *dir, const uint32_t *pe, const uint32_t *s_wo,
-                                                const uint32_t *s_dr, const uint32_t *s_pb, const uint32_t *s_len,
-                                                uint32_t *s_cnt, uint16_t *items, int item_cap, uint32_t *tile,
-                                                const uint16_t *lut, int tid, int wave, int lane) {
-  constexpr int S = B * B, NBLK = 64 / B, H = B / 2;
-  const int nn = cr.nn;
-  // (2) list the stored (node, block) pairs, one list per range kind
-  for (int c0 = wave * 64; c0 < nn * NBLK; c0 += kLFThreads) {
-    const int idx = c0 + lane;
-    const int ln = idx / NBLK, jj = idx % NBLK;
-    uint32_t e = kAbsent;
-    if (idx < nn * NBLK && s_len[jj]) e = strip_entry(words, dir, pe, s_wo[jj], s_dr[jj], s_pb[jj], chunk_node(cr, ln));
-    const uint32_t kind = e == kAbsent ? 3u : code_kind(e & 31u);
+constexpr int kListIters = 32 / (B * B) > 1 ? 32 / (B * B) : 1;
+
+// Where one pass of phase B finds the strip's data: payload words at
+// pw + s_po[j], bitmap words at bw + s_bo[j], bitmap-word bases at
+// dir + s_dr[j], directory entries at pe + (index - s_pb[j]); each in LDS or
+// in global memory depending on how much of the strip was staged.
+struct StripView {
+  const uint32_t *pw, *s_po, *bw, *s_bo, *dir, *s_dr, *pe, *s_pb;
+};
+
+// Steps (2) and (3) of a pass: list the chunk's stored (node, block) pairs
+// sorted by range kind, then decode each listed block once, whole, one lane
+// per block, into the tile.  The list takes two passes over the pairs and no
+// atomics: per-wave counts by ballot, a barrier, then every wave writes its
+// items at its own offsets.
+template <int B>
+__device__ __forceinline__ void lf_chunk_decode(const LFArgs &a, const ChunkRec &cr, const StripView &sv,
+                                                const uint32_t *s_len, uint32_t *s_wc, uint32_t *it_e,
+                                                uint16_t *it_id, uint32_t *tile, const uint16_t *lut, int tid,
+                                                int wave, int lane) {
+  constexpr int S = B * B, NBLK = 64 / B, H = B / 2, IT = kListIters<B>;
+  const int np = cr.nn * NBLK;
+  const uint64_t below = (1ull << lane) - 1ull;
+  uint32_t ent[IT], rk[IT];
+  uint32_t run0 = 0, run1 = 0, run2 = 0;
 #pragma unroll
-    for (uint32_t K = 0; K < 3; K++) {
-      const uint64_t bal = __ballot(kind == K);
-      if (!bal) continue;
-      uint32_t at = 0;
-      if (lane == 0) at = atomicAdd(&s_cnt[K], (uint32_t)__popcll(bal));
-      at = (uint32_t)__builtin_amdgcn_readfirstlane((int)at);
-      if (kind == K) items[K * item_cap + at + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)((ln << 5) | jj);
+  for (int k = 0; k < IT; k++) {
+    const int idx = k * kLFThreads + wave * 64 + lane;
+    uint32_t e = kAbsent;
+    if (idx < np) {
+      const int ln = idx / NBLK, jj = idx % NBLK;
+      if (s_len[jj]) {
+        const int s = chunk_node(cr, ln);
+        const uint32_t bm = sv.bw[sv.s_bo[jj] + (s >> 5)];
+        const uint32_t bit = (uint32_t)s & 31u;
+        if ((bm >> bit) & 1u)
+          e = sv.pe[sv.dir[sv.s_dr[jj] + (s >> 5)] - sv.s_pb[jj] + __popc(bm & ((1u << bit) - 1u))];
+      }
+    }
+    const uint32_t kind = e == kAbsent ? 3u : code_kind(e & 31u);
+    const uint64_t b0 = __ballot(kind == 0u), b1 = __ballot(kind == 1u), b2 = __ballot(kind == 2u);
+    const uint32_t r = kind == 0u ? run0 + (uint32_t)__popcll(b0 & below)
+                                  : (kind == 1u ? run1 + (uint32_t)__popcll(b1 & below)
+                                                : run2 + (uint32_t)__popcll(b2 & below));
+    ent[k] = e;
+    rk[k] = (r << 2) | kind;
+    run0 += (uint32_t)__popcll(b0);
+    run1 += (uint32_t)__popcll(b1);
+    run2 += (uint32_t)__popcll(b2);
+  }
+  if (lane == 0) {
+    s_wc[wave] = run0;
+    s_wc[kLFWaves + wave] = run1;
+    s_wc[2 * kLFWaves + wave] = run2;
+  }
+  __syncthreads();
+  uint32_t n0 = 0, n1 = 0, n2 = 0, o0 = 0, o1 = 0, o2 = 0;
+#pragma unroll
+  for (int w = 0; w < kLFWaves; w++) {
+    const uint32_t c0 = s_wc[w], c1 = s_wc[kLFWaves + w], c2 = s_wc[2 * kLFWaves + w];
+    if (w < wave) {
+      o0 += c0;
+      o1 += c1;
+      o2 += c2;
+    }
+    n0 += c0;
+    n1 += c1;
+    n2 += c2;
+  }
+#pragma unroll
+  for (int k = 0; k < IT; k++) {
+    const uint32_t kind = rk[k] & 3u;
+    if (kind != 3u) {
+      const int idx = k * kLFThreads + wave * 64 + lane;
+      const uint32_t at = (rk[k] >> 2) + (kind == 0u ? o0 : (kind == 1u ? n0 + o1 : n0 + n1 + o2));
+      it_e[at] = ent[k];
+      it_id[at] = (uint16_t)(((idx / NBLK) << 5) | (idx % NBLK));
     }
   }
   __syncthreads();
-  // (3) decode every listed block, once, whole, into the tile; the three
-  // lists are laid end to end so a wave mostly sees a single kind
-  const uint32_t n0 = s_cnt[0], n1 = s_cnt[1], n2 = s_cnt[2];
+  // the three kinds are laid end to end, so a wave mostly sees a single kind
   for (uint32_t it = tid; it < n0 + n1 + n2; it += kLFThreads) {
-    const uint32_t K = it < n0 ? 0u : (it < n0 + n1 ? 1u : 2u);
-    const uint32_t id = items[K * item_cap + it - (K == 0 ? 0u : (K == 1 ? n0 : n0 + n1))];
+    const uint32_t e = it_e[it], id = it_id[it];
     const int ln = (int)(id >> 5), jj = (int)(id & 31u);
-    const uint32_t e = strip_entry(words, dir, pe, s_wo[jj], s_dr[jj], s_pb[jj], chunk_node(cr, ln));
-    const uint32_t *gw = words + s_wo[jj];
+    const uint32_t *gw = sv.pw + sv.s_po[jj];
     uint32_t d[S / 2];
-    if (K == 0) decode_block_k<B, 0>(gw, e, a.q, lut, d);
-    else if (K == 1) decode_block_k<B, 1>(gw, e, a.q, lut, d);
+    if (it < n0) decode_block_k<B, 0>(gw, e, a.q, lut, d);
+    else if (it < n0 + n1) decode_block_k<B, 1>(gw, e, a.q, lut, d);
     else decode_block_k<B, 2>(gw, e, a.q, lut, d);
 #pragma unroll
     for (int yy = 0; yy < B; yy++)
@@ -420,13 +460,15 @@ __device__ __forceinline__ void lf_chunk_decode(const LFArgs &a, const ChunkRec 
 }
 
 // One workgroup = one channel c, one row of blocks by, one strip of 64/B
-// consecutive blocks (64 pixels).  Phase A copies into LDS, when they fit,
-// the strip's groups with their directory rows and entries (else these are
-// read from global memory).  Phase B walks the leaves in serial order, chunk
-// by chunk: (1) zero the residual tile; (2) list the (node, block) pairs
-// whose block is stored, by range kind; (3) decode each listed block once,
-// whole, one lane per block, into the tile; (4) per sibling batch: key-view
-// row + ancestor rows + leaf row, stored 16 bytes per lane.
+// consecutive blocks (64 pixels).  Phase A copies into LDS what fits of the
+// strip's data: its groups, directory entries and bitmap-word bases (tier
+// 1), else the same without the payload words (tier 2), else nothing (tier
+// 3: all read from global memory), plus the strip's key-view rows.  Phase B
+// walks the leaves in serial order, chunk by chunk: (1) zero the residual
+// tile; (2) list the (node, block) pairs whose block is stored, by range
+// kind; (3) decode each listed block once, whole, one lane per block, into
+// the tile; (4) per sibling run: key-view row + ancestor rows + leaf row,
+// stored 16 bytes per lane.
 template <int B>
 __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
   constexpr int S = B * B, NBLK = 64 / B, H = B / 2;
@@ -439,15 +481,17 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
   uint32_t *s_o0 = smem + 192;                         // group start word in the SRV section
   uint32_t *s_len = smem + 256;                        // group length in words
   uint32_t *s_P = smem + 320;                          // stored blocks of the group
-  uint32_t *s_wo = smem + 384;                         // group words: offset from the words base
+  uint32_t *s_wo = smem + 384;                         // staged group words (tier 1) or bitmap (tier 2)
   uint32_t *s_dr = smem + 448;                         // directory row: offset from the dir base
   uint32_t *s_pb = smem + 512;                         // directory entries: re-basing of the indices
-  uint32_t *s_cnt = smem + 576;                        // [0..2] list sizes, [3] staged, [4] group base
+  uint32_t *s_cnt = smem + 576;                        // [3] tier, [4] staged group words
+  uint32_t *s_wc = smem + 584;                         // [3][kLFWaves] per-wave list counts
   uint32_t *s_pe = smem + 640;                         // directory entries of the group: staged offset
   uint32_t *tile = smem + kLFHeadWords;                // [max_chunk_nodes][NODE_WORDS]
   const int item_cap = a.max_chunk_nodes * NBLK;
-  uint16_t *items = reinterpret_cast<uint16_t *>(tile + a.max_chunk_nodes * NODE_WORDS);  // [3][item_cap]
-  uint32_t *keys = tile + a.max_chunk_nodes * NODE_WORDS + ((3 * item_cap + 7) / 8) * 4;  // [n_top][B][NBLK][H]
+  uint32_t *it_e = tile + a.max_chunk_nodes * NODE_WORDS;               // [item_cap] listed entries
+  uint16_t *it_id = reinterpret_cast<uint16_t *>(it_e + item_cap);      // [item_cap] node << 5 | block
+  uint32_t *keys = it_e + item_cap + ((item_cap + 7) / 8) * 4;          // [n_top][B][NBLK][H]
   uint32_t *stage = keys + a.key_words;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -477,13 +521,16 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
       words += s_len[j];
       entries += s_P[j];
     }
-    const uint32_t need = words + kStagePad + entries + (uint32_t)NBLK * a.nbw;
-    const bool staged = need <= (uint32_t)a.stage_cap;
-    s_cnt[3] = staged;
-    uint32_t wacc = 0, pacc = words + kStagePad;
+    const uint32_t rows = (uint32_t)NBLK * a.nbw;
+    const uint32_t tier = words + kStagePad + entries + rows <= (uint32_t)a.stage_cap ? 1u
+                          : (rows + entries + rows <= (uint32_t)a.stage_cap ? 2u : 3u);
+    s_cnt[3] = tier;
+    // tier 1: [group words][pad][entries][directory rows]
+    // tier 2: [bitmap words, nbw per block][entries][directory rows]
+    uint32_t wacc = 0, pacc = tier == 1u ? words + kStagePad : rows;
     for (int j = 0; j < NBLK; j++) {
-      if (staged) {
-        s_wo[j] = wacc;
+      if (tier < 3u) {
+        s_wo[j] = tier == 1u ? wacc : (uint32_t)j * a.nbw;
         s_pe[j] = pacc;
         s_pb[j] = s_pb[j] - pacc;           // entry index - s_pb = position in the staged entries
         wacc += s_len[j];
@@ -493,17 +540,17 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
         s_pb[j] = 0;                        // global directory indices
       }
     }
-    if (staged)
+    if (tier < 3u)
       for (int j = 0; j < NBLK; j++) s_dr[j + 32] = pacc + (uint32_t)j * a.nbw;  // staged directory rows
-    s_cnt[4] = words;
+    s_cnt[4] = tier == 1u ? words : 0u;
   }
   __syncthreads();
-  const bool staged = s_cnt[3] != 0;
-  if (staged) {
+  const uint32_t tier = s_cnt[3];
+  if (tier < 3u) {
     // every copy goes straight from global memory to LDS, all in flight at once
     for (int j = wave; j < NBLK; j += kLFWaves) {
       if (!s_len[j]) continue;
-      lds_copy(stage + s_wo[j], a.srv + s_o0[j], s_len[j], lane);
+      lds_copy(stage + s_wo[j], a.srv + s_o0[j], tier == 1u ? s_len[j] : (uint32_t)a.nbw, lane);
       lds_copy(stage + s_pe[j], a.poff + (s_pb[j] + s_pe[j]), s_P[j], lane);
       lds_copy(stage + s_dr[j + 32], a.dbase + s_dr[j], (uint32_t)a.nbw, lane);
     }
@@ -522,9 +569,9 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
     }
   }
   __builtin_amdgcn_s_waitcnt(0);
-  if (staged && tid < kStagePad) stage[s_cnt[4] + tid] = 0;
+  if (tier == 1u && tid < kStagePad) stage[s_cnt[4] + tid] = 0;
   __syncthreads();
-  if (staged && tid < NBLK) s_dr[tid] = s_dr[tid + 32];
+  if (tier < 3u && tid < NBLK) s_dr[tid] = s_dr[tid + 32];
   __syncthreads();
 
   const int by = blockIdx.y, c = blockIdx.z;
@@ -557,12 +604,17 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
     // (1) zero the tile, reset the lists
     for (int w4 = tid; w4 < cr.nn * NODE_WORDS / 4; w4 += kLFThreads)
       reinterpret_cast<uint4 *>(tile)[w4] = make_uint4(0u, 0u, 0u, 0u);
-    if (tid < 3) s_cnt[tid] = 0;
     __syncthreads();
-    if (staged) lf_chunk_decode<B>(a, cr, stage, stage, stage, s_wo, s_dr, s_pb, s_len, s_cnt, items, item_cap, tile,
-                                   lut, tid, wave, lane);
-    else lf_chunk_decode<B>(a, cr, a.srv, a.dbase, a.poff, s_wo, s_dr, s_pb, s_len, s_cnt, items, item_cap, tile,
-                            lut, tid, wave, lane);
+    if (tier == 1u) {
+      const StripView sv{stage, s_wo, stage, s_wo, stage, s_dr, stage, s_pb};
+      lf_chunk_decode<B>(a, cr, sv, s_len, s_wc, it_e, it_id, tile, lut, tid, wave, lane);
+    } else if (tier == 2u) {
+      const StripView sv{a.srv, s_o0, stage, s_wo, stage, s_dr, stage, s_pb};
+      lf_chunk_decode<B>(a, cr, sv, s_len, s_wc, it_e, it_id, tile, lut, tid, wave, lane);
+    } else {
+      const StripView sv{a.srv, s_o0, a.srv, s_o0, a.dbase, s_dr, a.poff, s_pb};
+      lf_chunk_decode<B>(a, cr, sv, s_len, s_wc, it_e, it_id, tile, lut, tid, wave, lane);
+    }
     __syncthreads();
     // (4) gather and store, waves splitting the chunk's batches
     const int per = (cr.nq + kLFWaves - 1) / kLFWaves;
@@ -973,7 +1025,10 @@ lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s) {
   const int64_t nodes = std::max(lf->max_chunk_nodes, 1);
   // key-view rows of a strip, when they take at most 16 KB
   const int64_t key_words = (int64_t)g.n_top * NBLK * (B * B / 2) <= 4096 ? (int64_t)g.n_top * NBLK * (B * B / 2) : 0;
-  const int64_t fixed = kLFHeadWords + nodes * NODE_WORDS + ((3 * nodes * NBLK + 7) / 8) * 4 + key_words;
+  const int64_t items = nodes * NBLK;
+  if (items > (int64_t)kListIters<B> * kLFThreads)
+    return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: chunk larger than the whole-field kernel lists");
+  const int64_t fixed = kLFHeadWords + nodes * NODE_WORDS + items + ((items + 7) / 8) * 4 + key_words;
   const int64_t limit = max_lds_bytes() / 4;
   if (fixed > limit)
     return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: tree too large for the whole-field kernel; use BLOCKS layout");

@@ -15,7 +15,7 @@ import pytest
 import torch
 
 import oracle
-from helpers import blocks_of, make_lf, oracle_encode, say
+from helpers import blocks_of, make_lf, oracle_encode, say, strip_stage_words
 from paper_1805_06019_amd import lfc, synth
 from paper_1805_06019_amd.workloads import WORKLOADS
 
@@ -57,19 +57,29 @@ def test_whole_field_images_layout(gpu, case):
     assert torch.equal(out, out2)
 
 
-@pytest.mark.parametrize("cap", ["0", "40"])
+@pytest.mark.parametrize("tiers", ["global", "no-payload", "mixed"])
 @pytest.mark.parametrize("case", [GEOMS[0], GEOMS[3], GEOMS[5], GEOMS[6]],
                          ids=["8x8x64x64-B4-L2", "17x17x20x12-B4-L3", "5x4x72x24-B8-L2", "6x3x130x10-B2-L3"])
-def test_whole_field_without_lds_staging(gpu, case, cap, monkeypatch):
-    # LFC_STAGE_CAP_WORDS bounds the LDS the whole-field kernel may use for a
-    # strip's groups: 0 reads every strip from global memory, a small cap mixes
-    # staged and unstaged strips in one launch
+def test_whole_field_staging_tiers(gpu, case, tiers, monkeypatch):
+    # LFC_STAGE_CAP_WORDS bounds the LDS the whole-field kernel may use to
+    # stage a strip: 0 reads everything from global memory; a cap that holds
+    # bitmaps and directory but not the payload of most strips stages those
+    # only; the median strip's full need mixes the tiers in one launch
     U, V, W, H, kw = case
-    say("images without staging", case, cap)
     rgb = make_lf(U, V, W, H, seed=U * 13 + W)
     enc = oracle_encode(rgb, **kw)
+    t1, t2 = strip_stage_words(enc.stream, oracle.Params(grid_u=U, grid_v=V, width=W, height=H, **kw))
+    if tiers == "global":
+        cap = 0
+    elif tiers == "no-payload":
+        # the cap that puts the most strips in the middle tier
+        cap = max((int(c) for c in t2), key=lambda c: int(np.sum((t2 <= c) & (t1 > c))))
+        assert np.sum((t2 <= cap) & (t1 > cap)) > 0
+    else:
+        cap = int(np.median(t1))
+    say("images staging", case, tiers, cap)
     lf = gpu_open(enc.stream)
-    monkeypatch.setenv("LFC_STAGE_CAP_WORDS", cap)
+    monkeypatch.setenv("LFC_STAGE_CAP_WORDS", str(cap))
     got = lfc.lfc_decode_blocks(lf, None, lfc.LAYOUT_IMAGES).cpu().numpy()
     assert np.array_equal(got, enc.r0)
 
