@@ -216,8 +216,10 @@ void build_tree_tables(const Geometry &g, TreeTables &t) {
 
 // Consecutive batches grouped so that their leaves and every ancestor level
 // fit the residual tile of the whole-field kernel.
-void build_chunks(const Geometry &g, const std::vector<int32_t> &batch, std::vector<int32_t> &chunks) {
+void build_chunks(const Geometry &g, std::vector<int32_t> &batch, std::vector<int32_t> &chunks,
+                  std::vector<int32_t> &nodes) {
   chunks.clear();
+  nodes.clear();
   const int nb = (int)(batch.size() / kBatchWords), L = g.L;
   if (L < 2) return;
   const int budget = kChunkResBytes / (128 * g.B);
@@ -246,9 +248,21 @@ void build_chunks(const Geometry &g, const std::vector<int32_t> &batch, std::vec
     rec[0] = q;
     rec[1] = n;
     rec[2] = total;
-    for (int l = 0; l < L - 1; l++) {
-      rec[3 + 2 * l] = lo[l];
-      rec[4 + 2 * l] = hi[l] - lo[l] + 1;
+    rec[3] = (int32_t)nodes.size();
+    int base[kMaxLevels];
+    for (int l = 0, o = 0; l < L - 1; l++) {
+      rec[4 + 2 * l] = lo[l];
+      rec[5 + 2 * l] = hi[l] - lo[l] + 1;
+      base[l] = o;
+      for (int s = lo[l]; s <= hi[l]; s++) nodes.push_back(s);
+      o += hi[l] - lo[l] + 1;
+    }
+    // where each run finds its nodes in the chunk's list
+    for (int k = q; k < q + n; k++) {
+      int32_t *r = &batch[(size_t)k * kBatchWords];
+      r[11] = base[0] + (r[10] - lo[0]);
+      for (int i = 0; i < 4; i++) r[12 + i] = -1;
+      for (int l = 1; l < L - 1; l++) r[12 + (L - 2 - l)] = base[l] + (r[6 + (L - 2 - l)] - lo[l]);
     }
     chunks.insert(chunks.end(), rec, rec + kChunkWords);
     q += n;
@@ -815,9 +829,9 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
     size_t at;
   };
   static const uint32_t zeros[64] = {0};
-  std::vector<int32_t> chunks;
-  build_chunks(ps.g, tt.batch, chunks);
-  Part parts[11] = {
+  std::vector<int32_t> chunks, nmap;
+  build_chunks(ps.g, tt.batch, chunks, nmap);
+  Part parts[12] = {
       {ps.rkv, ps.rkv_bytes, 0},
       {ps.off.data(), ps.off.size() * 4, 0},
       {ps.srv.data(), ps.srv.size() * 4, 0},
@@ -829,6 +843,7 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
       {zeros, 4, 0},
       {chunks.data(), chunks.size() * 4, 0},
       {ps.pbase.data(), ps.pbase.size() * 4, 0},
+      {nmap.data(), nmap.size() * 4, 0},
   };
   size_t total = 0;
   for (auto &pt : parts) {
@@ -878,6 +893,8 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
   lf->n_batch = (int)(tt.batch.size() / kBatchWords);
   lf->d_chunk = reinterpret_cast<const int32_t *>(d + parts[9].at);
   lf->d_pbase = reinterpret_cast<const uint32_t *>(d + parts[10].at);
+  lf->d_nmap = reinterpret_cast<const int32_t *>(d + parts[11].at);
+  lf->n_nmap = (int)nmap.size();
   lf->n_chunk = (int)(chunks.size() / kChunkWords);
   for (int i = 0; i < lf->n_chunk; i++) lf->max_chunk_nodes = std::max(lf->max_chunk_nodes, chunks[(size_t)i * kChunkWords + 2]);
   lf->d_err = reinterpret_cast<int32_t *>(d + parts[8].at);

@@ -35,18 +35,24 @@ lfc_status make_geometry(const lfc_params &p, Geometry &g, std::string *why);
 // with the same ancestors), one kBatchWords-word record per run:
 //   [0] n, [1..4] view indices (-1 unused), [5] root, [6..9] serial indices of
 //   the ancestors from level L-2 down to level 1 (-1 unused), [10] serial
-//   index of the first view of the run (the others follow it), [11..15] 0.
+//   index of the first view of the run (the others follow it), [11] the first
+//   view's position in the node list of its chunk, [12..15] the positions of
+//   the ancestors [6..9] in that list (-1 unused); [11..15] are filled in by
+//   build_chunks.
 constexpr int kBatch = 4;
 constexpr int kBatchWords = 16;
-// Chunks of consecutive batches decoded together by the whole-field kernel:
-//   [0] first batch, [1] batches, [2] nodes in all, then for each level
-//   l = 0..L-2: [3+2l] first serial index, [4+2l] node count (the nodes of a
-//   level under a run of consecutive leaves are consecutive).
+// Chunks of consecutive runs decoded together by the whole-field kernel:
+//   [0] first run, [1] runs, [2] nodes in all, [3] offset of the chunk's node
+//   list (serial indices, leaves first) in the node-list table, then for each
+//   level l = 0..L-2 from the leaves up: [4+2l] first serial index, [5+2l]
+//   node count (the nodes of a level under a run of consecutive leaves are
+//   consecutive).
 constexpr int kChunkWords = 16;
 // residual-tile budget of one chunk, in nodes: LDS bytes / (64/B blocks * B*B
 // samples * 2 bytes) = kChunkResBytes / (128 B)
 constexpr int kChunkResBytes = 32 * 1024;
-void build_chunks(const Geometry &g, const std::vector<int32_t> &batch, std::vector<int32_t> &chunks);
+void build_chunks(const Geometry &g, std::vector<int32_t> &batch, std::vector<int32_t> &chunks,
+                  std::vector<int32_t> &nodes);
 struct TreeTables {
   std::vector<int32_t> path, root, batch;
   std::vector<std::vector<int32_t>> serial;  // [level][node id] -> BFS index (-1 on top)
@@ -80,6 +86,8 @@ struct lfc_lf {
   const int32_t *d_batch = nullptr;  // [n_batch][kBatchWords]
   int n_batch = 0;
   const int32_t *d_chunk = nullptr;  // [n_chunk][kChunkWords]
+  const int32_t *d_nmap = nullptr;   // [n_nmap] node lists of the chunks
+  int n_nmap = 0;
   int n_chunk = 0, max_chunk_nodes = 0;
   int32_t *d_err = nullptr;          // device error flag
   uint32_t max_strip_words = 0;      // largest group words + directory entries + directory rows of a strip

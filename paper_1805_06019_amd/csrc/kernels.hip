@@ -235,7 +235,7 @@ __device__ __forceinline__ void store_row(int16_t *p, const uint32_t x[B / 2]) {
 
 constexpr int kLFThreads = 512;
 constexpr int kLFWaves = kLFThreads / 64;
-constexpr int kLFHeadWords = 704;     // LDS words before the residual tile (LUT, per-block extents)
+constexpr int kLFHeadWords = 832;     // LDS words before the residual tile (LUT, extents, node masks)
 constexpr int kStagePad = 8;          // zero words after the staged group words
 
 struct LFArgs {
@@ -247,11 +247,13 @@ struct LFArgs {
   const uint32_t *pbase;   // [ng+1] first directory entry of each group
   const int32_t *batch;    // [nbatch][kBatchWords] runs of sibling leaves (see internal.h)
   const int32_t *chunk;    // [nchunk][kChunkWords] runs of batches decoded together
+  const int32_t *nmap;     // [n_nmap] node lists of the chunks
   int16_t *out;            // [nv][3][hp][wp]
   int nbx, n_srv, nbw, nv, L, q, wp, hp, nb, nbatch, nchunk, max_chunk_nodes;
   int stage_cap;           // LDS words available for staging the strip
   int vec_store;           // output rows may be stored 16 bytes at a time
   int n_top, key_words;    // key views; LDS words of the strip's key-view rows (0: not staged)
+  int n_nmap;
 };
 
 // A whole block of a known kind (0 plain bits, 1 trit, 2 quint) decoded by one
@@ -328,36 +330,24 @@ __device__ __forceinline__ void lds_copy(uint32_t *dst, const uint32_t *src, uin
 typedef const __attribute__((address_space(4))) int32_t *uniform_i32;
 __device__ __forceinline__ uniform_i32 as_uniform(const int32_t *p) { return (uniform_i32)p; }
 
-// A chunk record held in scalar registers: runs [q0, q0+nq), nn nodes, and
-// for each level from the leaves up its first serial index and node count.
+// A chunk record held in scalar registers: runs [q0, q0+nq), nn nodes, whose
+// serial indices are listed from nbase on in the node-list table.
 struct ChunkRec {
-  int q0, nq, nn;
-  int lo[lfc::kMaxLevels - 1], cnt[lfc::kMaxLevels - 1];
+  int q0, nq, nn, nbase;
 };
 
-__device__ __forceinline__ ChunkRec read_chunk(const int32_t *chunk, int ci, int L) {
+__device__ __forceinline__ ChunkRec read_chunk(const int32_t *chunk, int ci) {
   const uniform_i32 cr = as_uniform(chunk + (size_t)ci * lfc::kChunkWords);
-  ChunkRec r;
-  r.q0 = cr[0];
-  r.nq = cr[1];
-  r.nn = cr[2];
-#pragma unroll
-  for (int l = 0; l < lfc::kMaxLevels - 1; l++) {
-    r.lo[l] = l < L - 1 ? cr[3 + 2 * l] : 0;
-    r.cnt[l] = l < L - 1 ? cr[4 + 2 * l] : 0;
-  }
-  return r;
+  return ChunkRec{cr[0], cr[1], cr[2], cr[3]};
 }
 
-// Serial index of local node ln of a chunk (levels stored from the leaves up).
-__device__ __forceinline__ int chunk_node(const ChunkRec &cr, int ln) {
-  int o = 0, s = -1;
-#pragma unroll
-  for (int l = 0; l < lfc::kMaxLevels - 1; l++) {
-    if (ln >= o && ln < o + cr.cnt[l]) s = cr.lo[l] + (ln - o);
-    o += cr.cnt[l];
-  }
-  return s;
+// Residual tile of a chunk: per node and block row, the row's 64 samples as
+// eight 16-byte slots of 8/B blocks each.  The slot index is XORed with the
+// node's low bits, so lanes writing the same block of different nodes hit
+// different LDS banks; a slot is still read whole.
+template <int B>
+__device__ __forceinline__ int tile_slot(int ln, int y, int slot) {
+  return (ln * B + y) * 8 + (slot ^ (ln & 7));
 }
 
 // Pairs (node, block) of one chunk handled per lane: enough for the largest
@@ -380,7 +370,8 @@ struct StripView {
 // items at its own offsets.
 template <int B>
 __device__ __forceinline__ void lf_chunk_decode(const LFArgs &a, const ChunkRec &cr, const StripView &sv,
-                                                const uint32_t *s_len, uint32_t *s_wc, uint32_t *it_e,
+                                                const int32_t *nmap, const uint32_t *s_len, uint32_t *s_wc,
+                                                uint32_t *s_mask, uint32_t *it_e,
                                                 uint16_t *it_id, uint32_t *tile, const uint16_t *lut, int tid,
                                                 int wave, int lane) {
   constexpr int S = B * B, NBLK = 64 / B, H = B / 2, IT = kListIters<B>;
@@ -395,7 +386,7 @@ __device__ __forceinline__ void lf_chunk_decode(const LFArgs &a, const ChunkRec 
     if (idx < np) {
       const int ln = idx / NBLK, jj = idx % NBLK;
       if (s_len[jj]) {
-        const int s = chunk_node(cr, ln);
+        const int s = nmap[cr.nbase + ln];
         const uint32_t bm = sv.bw[sv.s_bo[jj] + (s >> 5)];
         const uint32_t bit = (uint32_t)s & 31u;
         if ((bm >> bit) & 1u)
@@ -409,6 +400,12 @@ __device__ __forceinline__ void lf_chunk_decode(const LFArgs &a, const ChunkRec 
                                                 : run2 + (uint32_t)__popcll(b2 & below));
     ent[k] = e;
     rk[k] = (r << 2) | kind;
+    // which blocks of each of the wave's nodes are stored
+    const uint64_t pres = b0 | b1 | b2;
+    if (lane < 64 / NBLK) {
+      const int node = (k * kLFThreads + wave * 64) / NBLK + lane;
+      if (node < cr.nn) s_mask[node] = (uint32_t)(pres >> (lane * NBLK)) & (NBLK == 32 ? ~0u : (1u << NBLK) - 1u);
+    }
     run0 += (uint32_t)__popcll(b0);
     run1 += (uint32_t)__popcll(b1);
     run2 += (uint32_t)__popcll(b2);
@@ -455,7 +452,7 @@ __device__ __forceinline__ void lf_chunk_decode(const LFArgs &a, const ChunkRec 
 #pragma unroll
     for (int yy = 0; yy < B; yy++)
 #pragma unroll
-      for (int h = 0; h < H; h++) tile[((ln * B + yy) * NBLK + jj) * H + h] = d[yy * H + h];
+      for (int h = 0; h < H; h++) tile[tile_slot<B>(ln, yy, jj / (8 / B)) * 4 + (jj % (8 / B)) * H + h] = d[yy * H + h];
   }
 }
 
@@ -487,12 +484,14 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
   uint32_t *s_cnt = smem + 576;                        // [3] tier, [4] staged group words
   uint32_t *s_wc = smem + 584;                         // [3][kLFWaves] per-wave list counts
   uint32_t *s_pe = smem + 640;                         // directory entries of the group: staged offset
+  uint32_t *s_mask = smem + 704;                       // [max_chunk_nodes] stored blocks of each tile node
   uint32_t *tile = smem + kLFHeadWords;                // [max_chunk_nodes][NODE_WORDS]
   const int item_cap = a.max_chunk_nodes * NBLK;
   uint32_t *it_e = tile + a.max_chunk_nodes * NODE_WORDS;               // [item_cap] listed entries
   uint16_t *it_id = reinterpret_cast<uint16_t *>(it_e + item_cap);      // [item_cap] node << 5 | block
   uint32_t *keys = it_e + item_cap + ((item_cap + 7) / 8) * 4;          // [n_top][B][NBLK][H]
-  uint32_t *stage = keys + a.key_words;
+  int32_t *nmap = reinterpret_cast<int32_t *>(keys + a.key_words);     // [n_nmap] node lists of the chunks
+  uint32_t *stage = keys + a.key_words + a.n_nmap;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   for (int t = tid; t < kLutEntries; t += kLFThreads) lut[t] = lut_entry(t);
@@ -555,6 +554,8 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
       lds_copy(stage + s_dr[j + 32], a.dbase + s_dr[j], (uint32_t)a.nbw, lane);
     }
   }
+  if (wave == kLFWaves - 1) lds_copy(reinterpret_cast<uint32_t *>(nmap), reinterpret_cast<const uint32_t *>(a.nmap),
+                                     (uint32_t)a.n_nmap, lane);
   if (a.key_words) {
     // the strip's key-view rows, laid out as the tile: [root][row][block][H]
     const uint32_t *rk = reinterpret_cast<const uint32_t *>(a.rkv);
@@ -575,7 +576,8 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
   __syncthreads();
 
   const int by = blockIdx.y, c = blockIdx.z;
-  const size_t vstride = (size_t)3 * a.hp * a.wp, cplane = (size_t)c * a.hp * a.wp;
+  const uint32_t vstride = 3u * (uint32_t)a.hp * (uint32_t)a.wp;
+  const uint64_t cplane = (uint64_t)c * a.hp * a.wp;
   if (a.L == 1) {
     // no residual levels: every view is a stored key view
     const int j = lane % NBLK, y = lane / NBLK, bx = blockIdx.x * NBLK + j;
@@ -595,25 +597,21 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
   const int bx0 = blockIdx.x * NBLK + jq * PB;
   const int nact = max(0, min(PB, a.nbx - bx0));       // blocks of the segment inside the image
   const bool wide = nact == PB && a.vec_store;          // a 16-byte store is aligned
-  const size_t row = (size_t)(by * B + y) * a.wp + (size_t)bx0 * B;
+  const uint64_t lane_off = cplane + (uint64_t)(by * B + y) * a.wp + (uint64_t)bx0 * B;
   const int L = a.L;
   int root_cached = -1;
   uint32_t key[4] = {0, 0, 0, 0};
   for (int ci = 0; ci < a.nchunk; ci++) {
-    const ChunkRec cr = read_chunk(a.chunk, ci, L);
-    // (1) zero the tile, reset the lists
-    for (int w4 = tid; w4 < cr.nn * NODE_WORDS / 4; w4 += kLFThreads)
-      reinterpret_cast<uint4 *>(tile)[w4] = make_uint4(0u, 0u, 0u, 0u);
-    __syncthreads();
+    const ChunkRec cr = read_chunk(a.chunk, ci);
     if (tier == 1u) {
       const StripView sv{stage, s_wo, stage, s_wo, stage, s_dr, stage, s_pb};
-      lf_chunk_decode<B>(a, cr, sv, s_len, s_wc, it_e, it_id, tile, lut, tid, wave, lane);
+      lf_chunk_decode<B>(a, cr, sv, nmap, s_len, s_wc, s_mask, it_e, it_id, tile, lut, tid, wave, lane);
     } else if (tier == 2u) {
       const StripView sv{a.srv, s_o0, stage, s_wo, stage, s_dr, stage, s_pb};
-      lf_chunk_decode<B>(a, cr, sv, s_len, s_wc, it_e, it_id, tile, lut, tid, wave, lane);
+      lf_chunk_decode<B>(a, cr, sv, nmap, s_len, s_wc, s_mask, it_e, it_id, tile, lut, tid, wave, lane);
     } else {
       const StripView sv{a.srv, s_o0, a.srv, s_o0, a.dbase, s_dr, a.poff, s_pb};
-      lf_chunk_decode<B>(a, cr, sv, s_len, s_wc, it_e, it_id, tile, lut, tid, wave, lane);
+      lf_chunk_decode<B>(a, cr, sv, nmap, s_len, s_wc, s_mask, it_e, it_id, tile, lut, tid, wave, lane);
     }
     __syncthreads();
     // (4) gather and store, waves splitting the chunk's batches
@@ -639,30 +637,24 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
 #pragma unroll
         for (int h = 0; h < 4; h++) anc[h] = key[h];
       }
-      int o = cr.cnt[0];   // local nodes of level 0 come first
+      // the lane's tile slot of node ln, with the entries of absent blocks as 0
+      auto add_node = [&](int ln, uint32_t x[4]) {
+        const uint4 t4 = reinterpret_cast<const uint4 *>(tile)[tile_slot<B>(ln, y, jq)];
+        const uint32_t bits = s_mask[ln] >> (jq * PB);
+        const uint32_t t[4] = {t4.x, t4.y, t4.z, t4.w};
 #pragma unroll
-      for (int l = 1; l < lfc::kMaxLevels - 1; l++) {
-        if (l < L - 1) {
-          const int ln = o + (rec[6 + (L - 2 - l)] - cr.lo[l]);
-          const uint4 t4 = reinterpret_cast<const uint4 *>(tile)[(((ln * B + y) * NBLK + jq * PB) * H) / 4];
-          anc[0] = add_pk(anc[0], t4.x);
-          anc[1] = add_pk(anc[1], t4.y);
-          anc[2] = add_pk(anc[2], t4.z);
-          anc[3] = add_pk(anc[3], t4.w);
-          o += cr.cnt[l];
-        }
-      }
-      const int nsib = rec[0], ls0 = rec[10] - cr.lo[0];
+        for (int w = 0; w < 4; w++) x[w] = add_pk(x[w], ((bits >> (w / H)) & 1u) ? t[w] : 0u);
+      };
+      for (int k = 0; k < L - 2; k++) add_node(rec[12 + k], anc);
+      const int nsib = rec[0], ls0 = rec[11];
       const int v0 = rec[1], v1 = rec[2], v2 = rec[3], v3 = rec[4];
-      // sibling i of the run: its leaf row plus the ancestors, to view vi
+      // sibling i of the run: its leaf row plus the ancestors
       auto leaf = [&](int i, uint32_t x[4]) -> int16_t * {
-        const uint4 t4 = reinterpret_cast<const uint4 *>(tile)[((((ls0 + i) * B + y) * NBLK + jq * PB) * H) / 4];
-        x[0] = add_pk(anc[0], t4.x);
-        x[1] = add_pk(anc[1], t4.y);
-        x[2] = add_pk(anc[2], t4.z);
-        x[3] = add_pk(anc[3], t4.w);
-        const int vi = i == 0 ? v0 : (i == 1 ? v1 : (i == 2 ? v2 : v3));
-        return a.out + (size_t)vi * vstride + cplane + row;
+#pragma unroll
+        for (int w = 0; w < 4; w++) x[w] = anc[w];
+        add_node(ls0 + i, x);
+        const uint32_t vi = (uint32_t)(i == 0 ? v0 : (i == 1 ? v1 : (i == 2 ? v2 : v3)));
+        return a.out + ((uint64_t)vi * vstride + lane_off);
       };
       // two loops, so that the 16-byte stores stay whole
       if (wide) {
@@ -1026,9 +1018,11 @@ lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s) {
   // key-view rows of a strip, when they take at most 16 KB
   const int64_t key_words = (int64_t)g.n_top * NBLK * (B * B / 2) <= 4096 ? (int64_t)g.n_top * NBLK * (B * B / 2) : 0;
   const int64_t items = nodes * NBLK;
+  if ((int64_t)3 * g.hp * g.wp >= ((int64_t)1 << 32))
+    return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: view too large for the whole-field kernel");
   if (items > (int64_t)kListIters<B> * kLFThreads)
     return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: chunk larger than the whole-field kernel lists");
-  const int64_t fixed = kLFHeadWords + nodes * NODE_WORDS + items + ((items + 7) / 8) * 4 + key_words;
+  const int64_t fixed = kLFHeadWords + nodes * NODE_WORDS + items + ((items + 7) / 8) * 4 + key_words + lf->n_nmap;
   const int64_t limit = max_lds_bytes() / 4;
   if (fixed > limit)
     return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: tree too large for the whole-field kernel; use BLOCKS layout");
@@ -1036,9 +1030,9 @@ lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s) {
   int64_t cap = std::min<int64_t>(target - fixed, (int64_t)lf->max_strip_words + kStagePad);
   if (const char *e = getenv("LFC_STAGE_CAP_WORDS")) cap = std::min<int64_t>(cap, std::max(0, atoi(e)));
   const size_t lds = 4 * (size_t)(fixed + cap);
-  LFArgs a{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_dbase, lf->d_poff, lf->d_pbase, lf->d_batch, lf->d_chunk, out,
+  LFArgs a{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_dbase, lf->d_poff, lf->d_pbase, lf->d_batch, lf->d_chunk, lf->d_nmap, out,
            g.nbx, g.n_srv, g.nbw, g.nv(), g.L, g.q, g.wp, g.hp, g.nb, lf->n_batch, lf->n_chunk, (int)nodes, (int)cap,
-           (int)(g.wp % 8 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0), g.n_top, (int)key_words};
+           (int)(g.wp % 8 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0), g.n_top, (int)key_words, lf->n_nmap};
   dim3 grid((g.nbx + NBLK - 1) / NBLK, g.nby, 3);
   hipLaunchKernelGGL(k_decode_lf<B>, grid, dim3(kLFThreads), lds, s, a);
   return launched("lfc_decode_blocks");
