@@ -195,6 +195,101 @@ lfc_status lfc_render_views(const lfc_lf *lf, const lfc_view *d_views, int32_t n
                             int32_t out_h, float *d_out, hipStream_t s);
 
 /*
+ * Batched rendering across light fields.  Views are independent of each
+ * other (any block of any view decodes on its own, Sec. 3.5, and a view is
+ * rendered from the blocks under its footprint, Sec. 3.6), so requests for
+ * several light fields and output sizes share one launch per block size in
+ * use.  Each result is bit-identical to lfc_render_views of that request
+ * alone.
+ */
+typedef struct {
+  int32_t lf;               /* index into the lfs array of the call */
+  int32_t out_w, out_h;     /* output size, 1..16384 each */
+  lfc_view view;            /* camera and image-plane offset, as lfc_render_views */
+} lfc_render_request;
+
+typedef struct lfc_batch lfc_batch;   /* staging for request tables; opaque */
+
+/* A batch context for the current device.  Errors: LFC_E_INVALID, LFC_E_NOMEM, LFC_E_HIP. */
+lfc_status lfc_batch_create(lfc_batch **out);
+
+/*
+ *  lfs     host array of n_lf open handles, all on the current device.
+ *  reqs    host array of n requests (n >= 0); reqs[i].lf indexes lfs.
+ *  d_outs  host array of n device pointers, 4-byte aligned; d_outs[i]
+ *          receives float32 [3][out_h][out_w], RGB / 255.
+ * The request table is packed on the host and copied to the device on s;
+ * the context double-buffers it, so two calls may be in flight, and a third
+ * waits for the first to finish its copy.  The staging grows on demand (a
+ * call with more requests than any before allocates).  Errors:
+ * LFC_E_INVALID (null pointer, index or size out of range, more than 65535
+ * requests of one block size), LFC_E_UNSUPPORTED, LFC_E_NOMEM, LFC_E_HIP.
+ */
+lfc_status lfc_batch_render(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf, const lfc_render_request *reqs,
+                            int32_t n, float *const *d_outs, hipStream_t s);
+
+/* Waits for the context's work and frees it.  NULL is ignored. */
+lfc_status lfc_batch_destroy(lfc_batch *b);
+
+/*
+ * Serving loop over resident light fields (the access pattern the paper
+ * designs for: many novel views of compressed light fields kept in GPU
+ * memory, Sec. 1 and 3.5).  Requests are queued on submit; one engine thread
+ * launches every queued request it can admit as one batch whenever one of
+ * `streams` launch slots is free (continuous batching), up to max_batch per
+ * launch.  Results live in a device pool of out_pool_bytes; a request whose
+ * output does not fit waits, in arrival order, until released results make
+ * room (memory admission).  max_batch = 1 with one stream is one plain
+ * launch per request.
+ */
+typedef struct lfc_server lfc_server;
+
+typedef struct {
+  int32_t max_batch;        /* requests per launch, 1..65535 */
+  int32_t streams;          /* launches in flight, 1..8; each on a stream of its own */
+  int64_t out_pool_bytes;   /* device bytes for results, >= 256 */
+} lfc_server_config;
+
+typedef struct {
+  int64_t submitted, completed, batches;
+  int64_t max_batch_seen;   /* most requests in one launch */
+  int64_t admission_waits;  /* times the head of the queue waited for pool room */
+  int64_t pool_bytes_in_use;
+} lfc_server_stats;
+
+/* Copies the lfs array (the handles must outlive the server).  Errors:
+ * LFC_E_INVALID, LFC_E_NOMEM, LFC_E_HIP. */
+lfc_status lfc_server_create(const lfc_lf *const *lfs, int32_t n_lf, const lfc_server_config *cfg,
+                             lfc_server **out);
+
+/* Queues one request; *ticket identifies it.  Thread-safe.  Errors:
+ * LFC_E_INVALID (bad index or size, or an output larger than the pool). */
+lfc_status lfc_server_submit(lfc_server *sv, const lfc_render_request *req, uint64_t *ticket);
+
+/* Blocks until the request is done (timeout_ms < 0: no limit); *d_img is
+ * then its result in the pool (device float32 [3][out_h][out_w]) and
+ * *latency_ms the time from submit to completion.  The result stays valid
+ * until lfc_server_release.  Errors: LFC_E_INVALID (unknown ticket, or the
+ * timeout passed), the launch's status if it failed. */
+lfc_status lfc_server_wait(lfc_server *sv, uint64_t ticket, int32_t timeout_ms, const float **d_img,
+                           double *latency_ms);
+
+/* Returns the request's result memory to the pool and forgets the ticket. */
+lfc_status lfc_server_release(lfc_server *sv, uint64_t ticket);
+
+/* Submits reqs[i] at arrival_ms[i] after the call starts (non-decreasing
+ * times), results discarded on completion, and returns once all are done
+ * with latency_ms[i] (host array of n) from each arrival to completion. */
+lfc_status lfc_server_replay(lfc_server *sv, const lfc_render_request *reqs, const double *arrival_ms, int32_t n,
+                             double *latency_ms);
+
+lfc_status lfc_server_get_stats(lfc_server *sv, lfc_server_stats *st);
+
+/* Stops the engine after the queued work, waits for it and frees the
+ * server.  NULL is ignored. */
+lfc_status lfc_server_destroy(lfc_server *sv);
+
+/*
  * Waits for stream s, then reads and clears the handle's device error flag.
  * Returns LFC_E_INVALID if a decode since the last check saw an
  * out-of-range request, LFC_E_HIP on a runtime error, else LFC_OK.

@@ -18,10 +18,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <string>
 #include <type_traits>
 
 #include "internal.h"
+#include "serve.h"
 
 namespace {
 
@@ -809,22 +811,22 @@ __device__ __forceinline__ uint32_t locate(const RAArgs &a, int g, int s, const 
 // whose path passes through that node (neighbouring views often share
 // ancestors).  The sums are converted to RGB (inverse YCoCg-R, clamped) in
 // place, then every output pixel interpolates its 16 taps in FP32.
+// One output tile (tile column tbx, tile row tby) of view vw into outn
+// ([3][ho][wo] floats); smem holds the LUT and the footprint accumulators.
 template <int B>
-__global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
+__device__ __forceinline__ void render_tile(const RenderArgs &a, const lfc_view vw, float *outn, int tbx, int tby,
+                                            uint32_t *smem) {
   constexpr int S = B * B, SLOT = 3 * S / 2;   // words per (view, block): 3 channels of packed int16
-  extern __shared__ uint32_t smem[];
   uint16_t *lut = reinterpret_cast<uint16_t *>(smem);
   uint32_t *acc = smem + kLutEntries / 2;       // [4][fbx_max*fby_max][SLOT]
   const int tid = threadIdx.x;
   for (int t = tid; t < kLutEntries; t += kThreads) lut[t] = lut_entry(t);
-  const int n = blockIdx.z;
-  const lfc_view vw = a.views[n];
   int iu0, iu1, jv0, jv1;
   float fu, fv;
   cell(vw.u, a.U, iu0, iu1, fu);
   cell(vw.v, a.V, jv0, jv1, fv);
   const float sxs = (float)a.W / (float)a.wo, tys = (float)a.H / (float)a.ho;
-  const int tx0 = blockIdx.x * a.TX, ty0 = blockIdx.y * a.TY;
+  const int tx0 = tbx * a.TX, ty0 = tby * a.TY;
   const int tx1 = min(tx0 + a.TX, a.wo) - 1, ty1 = min(ty0 + a.TY, a.ho) - 1;
   // source footprint of the tile, one pixel wider on each side than needed
   const float sa = fminf(fmaxf(vw.s + ((float)tx0 + 0.5f) * sxs - 0.5f, 0.0f), (float)(a.W - 1));
@@ -912,7 +914,6 @@ __global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
 
   // (4) quadrilinear interpolation of every output pixel of the tile
   const size_t plane = (size_t)a.ho * a.wo;
-  float *outn = a.out + (size_t)n * 3 * plane;
   const int FW = FBX * B, FH = FBY * B;
   for (int p = tid; p < a.TX * a.TY; p += kThreads) {
     const int X = tx0 + p % a.TX, Yp = ty0 + p / a.TX;
@@ -951,6 +952,31 @@ __global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
       outn[ch * plane + (size_t)Yp * a.wo + X] = lerpf(lv0, lv1, fu) / 255.0f;
     }
   }
+}
+
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
+  extern __shared__ uint32_t smem[];
+  const int n = blockIdx.z;
+  render_tile<B>(a, a.views[n], a.out + (size_t)n * 3 * a.ho * a.wo, blockIdx.x, blockIdx.y, smem);
+}
+
+// Many render requests in one launch, possibly of different light fields and
+// output sizes: workgroup (x, r) renders tile x of request r, and exits when
+// the request has fewer tiles.
+struct RenderReq {
+  RenderArgs a;        // the request's light field, output size, tiling and output (views unused)
+  lfc_view view;
+  int ntx, ntiles;     // tile columns, tiles
+};
+
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_render_multi(const RenderReq *reqs) {
+  extern __shared__ uint32_t smem[];
+  const RenderReq &r = reqs[blockIdx.y];
+  const int t = blockIdx.x;
+  if (t >= r.ntiles) return;
+  render_tile<B>(r.a, r.view, r.a.out, t % r.ntx, t / r.ntx, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1062,8 +1088,10 @@ bool plan_render(const lfc::Geometry &g, int wo, int ho, RenderPlan &pl) {
   for (;;) {
     // footprint span: (T-1)*scale pixels plus the 1-pixel widening on each
     // side, the interpolation neighbour and float slack, then block alignment
-    const int fbx = ((int)std::ceil((TX - 1) * sxs) + 5 + g.B - 1) / g.B + 2;
-    const int fby = ((int)std::ceil((TY - 1) * tys) + 5 + g.B - 1) / g.B + 2;
+    // a tile never spans more than the output
+    const int tw = std::min(TX, wo), th = std::min(TY, ho);
+    const int fbx = ((int)std::ceil((tw - 1) * sxs) + 5 + g.B - 1) / g.B + 2;
+    const int fby = ((int)std::ceil((th - 1) * tys) + 5 + g.B - 1) / g.B + 2;
     const size_t lds = 4 * ((size_t)kLutEntries / 2 + (size_t)4 * fbx * fby * (3 * g.B * g.B / 2));
     if (lds <= 64 * 1024) {
       pl = RenderPlan{TX, TY, fbx, fby, lds};
@@ -1138,3 +1166,42 @@ extern "C" lfc_status lfc_render_views(const lfc_lf *lf, const lfc_view *d_views
     default: return render<8>(lf, d_views, n, out_w, out_h, d_out, s);
   }
 }
+
+namespace lfc {
+
+size_t render_req_bytes() { return sizeof(RenderReq); }
+
+int lf_device(const lfc_lf *lf) { return lf->device; }
+
+lfc_status render_req_fill(const lfc_lf *lf, const lfc_view &v, int wo, int ho, float *out, void *dst, int *block,
+                           int *ntiles, size_t *lds) {
+  const Geometry &g = lf->geo;
+  RenderPlan pl;
+  if (!plan_render(g, wo, ho, pl))
+    return fail(LFC_E_UNSUPPORTED, "lfc_batch_render: output too strongly minified for the tile footprint");
+  RenderReq r{};
+  r.a = RenderArgs{ra_args(lf), nullptr, out, wo, ho, g.U, g.V, g.W, g.H, pl.TX, pl.TY, pl.fbx, pl.fby};
+  r.view = v;
+  r.ntx = (wo + pl.TX - 1) / pl.TX;
+  r.ntiles = r.ntx * ((ho + pl.TY - 1) / pl.TY);
+  std::memcpy(dst, &r, sizeof r);
+  *block = g.B;
+  *ntiles = r.ntiles;
+  *lds = pl.lds;
+  return LFC_OK;
+}
+
+lfc_status render_multi_launch(int block, const void *d_reqs, int n, int max_tiles, size_t lds, hipStream_t s) {
+  if (n <= 0) return LFC_OK;
+  if (n > 65535) return fail(LFC_E_INVALID, "lfc_batch_render: at most 65535 requests of one block size per batch");
+  const RenderReq *r = static_cast<const RenderReq *>(d_reqs);
+  dim3 grid((unsigned)max_tiles, (unsigned)n);
+  switch (block) {
+    case 2: hipLaunchKernelGGL(k_render_multi<2>, grid, dim3(kThreads), lds, s, r); break;
+    case 4: hipLaunchKernelGGL(k_render_multi<4>, grid, dim3(kThreads), lds, s, r); break;
+    default: hipLaunchKernelGGL(k_render_multi<8>, grid, dim3(kThreads), lds, s, r); break;
+  }
+  return launched("lfc_batch_render");
+}
+
+}  // namespace lfc

@@ -1,0 +1,558 @@
+// Batched rendering across light fields and the serving loop built on it.
+//
+// lfc_batch packs render requests into a table on the host, copies it to the
+// device on the caller's stream and launches one multi-request render per
+// block size.  lfc_server keeps a queue of requests, a device pool for their
+// results and one engine thread that admits and launches batches on a few
+// streams, polls their completion events and wakes the waiters.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+#include "serve.h"
+
+using lfc::fail;
+
+namespace {
+
+constexpr int kSlots = 2;   // request tables in flight per batch context
+
+struct Slot {
+  char *host = nullptr;     // pinned
+  char *dev = nullptr;
+  size_t cap = 0;           // bytes of each
+  hipEvent_t copied = nullptr;
+  bool used = false;
+};
+
+}  // namespace
+
+struct lfc_batch {
+  int device = 0;
+  Slot slot[kSlots];
+  int next = 0;
+};
+
+namespace {
+
+void free_slot(Slot &sl) {
+  if (sl.host) (void)hipHostFree(sl.host);
+  if (sl.dev) (void)hipFree(sl.dev);
+  sl.host = sl.dev = nullptr;
+  sl.cap = 0;
+}
+
+lfc_status grow_slot(Slot &sl, size_t need) {
+  if (need <= sl.cap) return LFC_OK;
+  size_t cap = std::max<size_t>(need, 64 * lfc::render_req_bytes());
+  cap = std::max(cap, sl.cap * 2);
+  if (sl.used && hipEventSynchronize(sl.copied) != hipSuccess) return fail(LFC_E_HIP, "lfc_batch_render: event wait");
+  free_slot(sl);
+  if (hipHostMalloc(reinterpret_cast<void **>(&sl.host), cap, hipHostMallocDefault) != hipSuccess) {
+    sl.host = nullptr;
+    return fail(LFC_E_NOMEM, "lfc_batch_render: pinned staging");
+  }
+  if (hipMalloc(reinterpret_cast<void **>(&sl.dev), cap) != hipSuccess) {
+    sl.dev = nullptr;
+    free_slot(sl);
+    return fail(LFC_E_NOMEM, "lfc_batch_render: device staging");
+  }
+  sl.cap = cap;
+  return LFC_OK;
+}
+
+}  // namespace
+
+extern "C" lfc_status lfc_batch_create(lfc_batch **out) {
+  if (!out) return fail(LFC_E_INVALID, "lfc_batch_create: null out");
+  *out = nullptr;
+  lfc_batch *b = new (std::nothrow) lfc_batch;
+  if (!b) return fail(LFC_E_NOMEM, "lfc_batch_create: out of host memory");
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    delete b;
+    return fail(LFC_E_HIP, "lfc_batch_create: no current device");
+  }
+  for (Slot &sl : b->slot) {
+    if (hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming) != hipSuccess) {
+      (void)lfc_batch_destroy(b);
+      return fail(LFC_E_HIP, "lfc_batch_create: event");
+    }
+  }
+  *out = b;
+  return LFC_OK;
+}
+
+extern "C" lfc_status lfc_batch_destroy(lfc_batch *b) {
+  if (!b) return LFC_OK;
+  for (Slot &sl : b->slot) {
+    if (sl.copied) {
+      if (sl.used) (void)hipEventSynchronize(sl.copied);
+      (void)hipEventDestroy(sl.copied);
+    }
+    free_slot(sl);
+  }
+  delete b;
+  return LFC_OK;
+}
+
+extern "C" lfc_status lfc_batch_render(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf,
+                                       const lfc_render_request *reqs, int32_t n, float *const *d_outs,
+                                       hipStream_t s) {
+  const char *who = "lfc_batch_render";
+  if (!b) return fail(LFC_E_INVALID, "lfc_batch_render: null batch");
+  if (n < 0) return fail(LFC_E_INVALID, "lfc_batch_render: n < 0");
+  if (n == 0) return LFC_OK;
+  if (!lfs || n_lf < 1 || !reqs || !d_outs) return fail(LFC_E_INVALID, "lfc_batch_render: null array");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
+    return fail(LFC_E_INVALID, "lfc_batch_render: the current device is not the batch's");
+  for (int i = 0; i < n_lf; i++)
+    if (!lfs[i] || lfc::lf_device(lfs[i]) != dev)
+      return fail(LFC_E_INVALID, "lfc_batch_render: null handle or handle of another device");
+  // pack, grouped by block size (one launch each)
+  const size_t rb = lfc::render_req_bytes();
+  std::vector<char> packed((size_t)n * rb);
+  struct Group {
+    int count = 0, max_tiles = 0;
+    size_t lds = 0;
+  } grp[9];
+  std::vector<int> bs(n), order;
+  order.reserve(n);
+  for (int i = 0; i < n; i++) {
+    const lfc_render_request &r = reqs[i];
+    if (r.lf < 0 || r.lf >= n_lf) return fail(LFC_E_INVALID, "lfc_batch_render: request lf index out of range");
+    if (r.out_w < 1 || r.out_h < 1 || r.out_w > 16384 || r.out_h > 16384)
+      return fail(LFC_E_INVALID, "lfc_batch_render: out_w and out_h must be 1..16384");
+    if (!d_outs[i] || reinterpret_cast<uintptr_t>(d_outs[i]) % 4)
+      return fail(LFC_E_INVALID, "lfc_batch_render: null or unaligned output pointer");
+    int block = 0, nt = 0;
+    size_t lds = 0;
+    if (lfc_status st = lfc::render_req_fill(lfs[r.lf], r.view, r.out_w, r.out_h, d_outs[i], &packed[(size_t)i * rb],
+                                             &block, &nt, &lds))
+      return st;
+    bs[i] = block;
+    Group &gp = grp[block];
+    gp.count++;
+    gp.max_tiles = std::max(gp.max_tiles, nt);
+    gp.lds = std::max(gp.lds, lds);
+  }
+  for (int block : {2, 4, 8})
+    if (grp[block].count > 65535)
+      return fail(LFC_E_INVALID, "lfc_batch_render: more than 65535 requests of one block size");
+  for (int block : {2, 4, 8})
+    for (int i = 0; i < n; i++)
+      if (bs[i] == block) order.push_back(i);
+  Slot &sl = b->slot[b->next];
+  if (lfc_status st = grow_slot(sl, (size_t)n * rb)) return st;
+  // the slot's previous table must have reached the device before it is rewritten
+  if (sl.used && hipEventSynchronize(sl.copied) != hipSuccess) return fail(LFC_E_HIP, "lfc_batch_render: event wait");
+  for (int k = 0; k < n; k++) std::memcpy(sl.host + (size_t)k * rb, &packed[(size_t)order[k] * rb], rb);
+  if (hipMemcpyAsync(sl.dev, sl.host, (size_t)n * rb, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipEventRecord(sl.copied, s) != hipSuccess)
+    return fail(LFC_E_HIP, std::string(who) + ": copy of the request table");
+  sl.used = true;
+  b->next = (b->next + 1) % kSlots;
+  int at = 0;
+  for (int block : {2, 4, 8}) {
+    const Group &gp = grp[block];
+    if (!gp.count) continue;
+    if (lfc_status st = lfc::render_multi_launch(block, sl.dev + (size_t)at * rb, gp.count, gp.max_tiles, gp.lds, s))
+      return st;
+    at += gp.count;
+  }
+  return LFC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// serving loop
+// ---------------------------------------------------------------------------
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_between(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+// First-fit allocator over [0, size) with coalescing, 256-byte granules.
+class Pool {
+ public:
+  void reset(size_t size) {
+    free_.clear();
+    free_[0] = size;
+    used_ = 0;
+  }
+  bool alloc(size_t bytes, size_t *off) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const size_t rest = it->second - bytes, at = it->first + bytes;
+      free_.erase(it);
+      if (rest) free_[at] = rest;
+      used_ += bytes;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+
+ private:
+  std::map<size_t, size_t> free_;
+  size_t used_ = 0;
+};
+
+enum class State { Queued, Running, Done, Failed };
+
+struct Ticket {
+  lfc_render_request req;
+  size_t bytes = 0, off = 0;
+  State state = State::Queued;
+  lfc_status status = LFC_OK;
+  bool discard = false;        // released by the engine on completion (replay)
+  double *latency_out = nullptr;
+  Clock::time_point t_submit, t_done;
+};
+
+struct Lane {                  // one launch slot: a stream, its batch context, its batch in flight
+  hipStream_t stream = nullptr;
+  lfc_batch *batch = nullptr;
+  hipEvent_t done = nullptr;
+  std::vector<uint64_t> running;
+};
+
+}  // namespace
+
+struct lfc_server {
+  std::vector<const lfc_lf *> lfs;
+  lfc_server_config cfg{};
+  int device = 0;
+  char *d_pool = nullptr;
+  Pool pool;
+  std::vector<Lane> lanes;
+  std::mutex mu;
+  std::condition_variable cv_engine, cv_done;
+  std::deque<uint64_t> queue;
+  std::unordered_map<uint64_t, Ticket> tickets;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  int64_t replay_left = 0;
+  uint64_t releases = 0;     // pool releases by clients, to wake a blocked engine
+  uint64_t last_blocked = 0; // the last queue head counted as waiting for room
+  lfc_server_stats stats{};
+  std::thread engine;
+  std::string engine_error;
+};
+
+namespace {
+
+size_t result_bytes(const lfc_render_request &r) { return (size_t)3 * r.out_w * r.out_h * sizeof(float); }
+
+// Completes the lane's batch (its event has fired).  Caller holds mu.
+void finish_lane(lfc_server *sv, Lane &ln, lfc_status st) {
+  const Clock::time_point now = Clock::now();
+  for (uint64_t id : ln.running) {
+    auto it = sv->tickets.find(id);
+    if (it == sv->tickets.end()) continue;
+    Ticket &t = it->second;
+    t.t_done = now;
+    t.status = st;
+    t.state = st == LFC_OK ? State::Done : State::Failed;
+    sv->stats.completed++;
+    if (t.discard) {
+      if (t.latency_out) *t.latency_out = ms_between(t.t_submit, now);
+      sv->pool.release(t.off, t.bytes);
+      sv->tickets.erase(it);
+      sv->replay_left--;
+    }
+  }
+  ln.running.clear();
+  sv->cv_done.notify_all();
+}
+
+void engine_loop(lfc_server *sv) {
+  (void)hipSetDevice(sv->device);
+  std::vector<const lfc_lf *> &lfs = sv->lfs;
+  std::vector<lfc_render_request> reqs;
+  std::vector<float *> outs;
+  std::vector<uint64_t> ids;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  for (;;) {
+    // completions
+    bool busy = false;
+    for (Lane &ln : sv->lanes) {
+      if (ln.running.empty()) continue;
+      const hipError_t q = hipEventQuery(ln.done);
+      if (q == hipSuccess) finish_lane(sv, ln, LFC_OK);
+      else if (q == hipErrorNotReady) busy = true;
+      else finish_lane(sv, ln, LFC_E_HIP);
+    }
+    // admission and launch on a free lane
+    Lane *free_lane = nullptr;
+    for (Lane &ln : sv->lanes)
+      if (ln.running.empty()) {
+        free_lane = &ln;
+        break;
+      }
+    bool blocked = false;   // the head of the queue waits for pool room
+    if (free_lane && !sv->queue.empty()) {
+      reqs.clear();
+      outs.clear();
+      ids.clear();
+      while (!sv->queue.empty() && (int)ids.size() < sv->cfg.max_batch) {
+        Ticket &t = sv->tickets[sv->queue.front()];
+        if (!sv->pool.alloc(t.bytes, &t.off)) {
+          if (ids.empty()) {
+            if (sv->last_blocked != sv->queue.front()) sv->stats.admission_waits++;
+            sv->last_blocked = sv->queue.front();
+            blocked = true;
+          }
+          break;
+        }
+        t.state = State::Running;
+        ids.push_back(sv->queue.front());
+        reqs.push_back(t.req);
+        outs.push_back(reinterpret_cast<float *>(sv->d_pool + t.off));
+        sv->queue.pop_front();
+      }
+      if (!ids.empty()) {
+        Lane &ln = *free_lane;
+        ln.running = ids;
+        sv->stats.batches++;
+        sv->stats.max_batch_seen = std::max<int64_t>(sv->stats.max_batch_seen, (int64_t)ids.size());
+        lk.unlock();
+        lfc_status st = lfc_batch_render(ln.batch, lfs.data(), (int32_t)lfs.size(), reqs.data(), (int32_t)reqs.size(),
+                                         outs.data(), ln.stream);
+        if (st == LFC_OK && hipEventRecord(ln.done, ln.stream) != hipSuccess) st = LFC_E_HIP;
+        lk.lock();
+        if (st != LFC_OK) {
+          sv->engine_error = lfc_last_error();
+          finish_lane(sv, ln, st);
+        }
+        continue;
+      }
+    }
+    if (busy) {
+      // launches in flight: poll their events without holding the lock
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
+      continue;
+    }
+    if (sv->stop && (sv->queue.empty() || blocked)) {
+      // nothing in flight: whatever is still queued can never be admitted
+      for (uint64_t id : sv->queue) {
+        Ticket &t = sv->tickets[id];
+        t.state = State::Failed;
+        t.status = LFC_E_INVALID;
+        if (t.discard) sv->replay_left--;
+      }
+      sv->queue.clear();
+      sv->engine_error = "the server stopped before the request was admitted";
+      sv->cv_done.notify_all();
+      break;
+    }
+    const uint64_t seen = sv->releases;
+    sv->cv_engine.wait(lk, [&] {
+      return sv->stop || (!sv->queue.empty() && !blocked) || sv->releases != seen;
+    });
+  }
+}
+
+lfc_status submit_locked(lfc_server *sv, const lfc_render_request &r, bool discard, double *lat_out, uint64_t *id) {
+  if (r.lf < 0 || r.lf >= (int32_t)sv->lfs.size())
+    return fail(LFC_E_INVALID, "lfc_server_submit: lf index out of range");
+  if (r.out_w < 1 || r.out_h < 1 || r.out_w > 16384 || r.out_h > 16384)
+    return fail(LFC_E_INVALID, "lfc_server_submit: out_w and out_h must be 1..16384");
+  const size_t bytes = result_bytes(r);
+  if (((bytes + 255) & ~(size_t)255) > (size_t)sv->cfg.out_pool_bytes)
+    return fail(LFC_E_INVALID, "lfc_server_submit: result larger than the output pool");
+  const uint64_t t_id = sv->next_ticket++;
+  Ticket &t = sv->tickets[t_id];
+  t.req = r;
+  t.bytes = bytes;
+  t.discard = discard;
+  t.latency_out = lat_out;
+  t.t_submit = Clock::now();
+  sv->queue.push_back(t_id);
+  sv->stats.submitted++;
+  if (id) *id = t_id;
+  return LFC_OK;
+}
+
+}  // namespace
+
+extern "C" lfc_status lfc_server_create(const lfc_lf *const *lfs, int32_t n_lf, const lfc_server_config *cfg,
+                                        lfc_server **out) {
+  if (!out) return fail(LFC_E_INVALID, "lfc_server_create: null out");
+  *out = nullptr;
+  if (!lfs || n_lf < 1 || !cfg) return fail(LFC_E_INVALID, "lfc_server_create: null argument or no light field");
+  if (cfg->max_batch < 1 || cfg->max_batch > 65535 || cfg->streams < 1 || cfg->streams > 8 ||
+      cfg->out_pool_bytes < 256)
+    return fail(LFC_E_INVALID, "lfc_server_create: max_batch 1..65535, streams 1..8, out_pool_bytes >= 256");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(LFC_E_HIP, "lfc_server_create: no current device");
+  for (int i = 0; i < n_lf; i++)
+    if (!lfs[i] || lfc::lf_device(lfs[i]) != dev)
+      return fail(LFC_E_INVALID, "lfc_server_create: null handle or handle of another device");
+  lfc_server *sv = new (std::nothrow) lfc_server;
+  if (!sv) return fail(LFC_E_NOMEM, "lfc_server_create: out of host memory");
+  sv->lfs.assign(lfs, lfs + n_lf);
+  sv->cfg = *cfg;
+  sv->device = dev;
+  if (hipMalloc(reinterpret_cast<void **>(&sv->d_pool), (size_t)cfg->out_pool_bytes) != hipSuccess) {
+    delete sv;
+    return fail(LFC_E_NOMEM, "lfc_server_create: output pool");
+  }
+  sv->pool.reset((size_t)cfg->out_pool_bytes);
+  sv->lanes.resize(cfg->streams);
+  for (Lane &ln : sv->lanes) {
+    if (hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess || lfc_batch_create(&ln.batch)) {
+      sv->stop = true;
+      (void)lfc_server_destroy(sv);
+      return fail(LFC_E_HIP, "lfc_server_create: stream, event or batch context");
+    }
+  }
+  sv->engine = std::thread(engine_loop, sv);
+  *out = sv;
+  return LFC_OK;
+}
+
+extern "C" lfc_status lfc_server_submit(lfc_server *sv, const lfc_render_request *req, uint64_t *ticket) {
+  if (!sv || !req || !ticket) return fail(LFC_E_INVALID, "lfc_server_submit: null argument");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (lfc_status st = submit_locked(sv, *req, false, nullptr, ticket)) return st;
+  sv->cv_engine.notify_one();
+  return LFC_OK;
+}
+
+extern "C" lfc_status lfc_server_wait(lfc_server *sv, uint64_t ticket, int32_t timeout_ms, const float **d_img,
+                                      double *latency_ms) {
+  if (!sv) return fail(LFC_E_INVALID, "lfc_server_wait: null server");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->tickets.find(ticket);
+  if (it == sv->tickets.end() || it->second.discard) return fail(LFC_E_INVALID, "lfc_server_wait: unknown ticket");
+  auto ready = [&] {
+    const State s = sv->tickets[ticket].state;
+    return s == State::Done || s == State::Failed;
+  };
+  if (timeout_ms < 0) sv->cv_done.wait(lk, ready);
+  else if (!sv->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready))
+    return fail(LFC_E_INVALID, "lfc_server_wait: timed out");
+  const Ticket &t = sv->tickets[ticket];
+  if (t.state == State::Failed)
+    return fail(t.status, "lfc_server_wait: the request's launch failed: " + sv->engine_error);
+  if (d_img) *d_img = reinterpret_cast<const float *>(sv->d_pool + t.off);
+  if (latency_ms) *latency_ms = ms_between(t.t_submit, t.t_done);
+  return LFC_OK;
+}
+
+extern "C" lfc_status lfc_server_release(lfc_server *sv, uint64_t ticket) {
+  if (!sv) return fail(LFC_E_INVALID, "lfc_server_release: null server");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->tickets.find(ticket);
+  if (it == sv->tickets.end() || it->second.discard) return fail(LFC_E_INVALID, "lfc_server_release: unknown ticket");
+  Ticket &t = it->second;
+  if (t.state == State::Queued || t.state == State::Running)
+    return fail(LFC_E_INVALID, "lfc_server_release: the request has not completed");
+  sv->pool.release(t.off, t.bytes);
+  sv->tickets.erase(it);
+  sv->releases++;
+  sv->cv_engine.notify_one();
+  return LFC_OK;
+}
+
+extern "C" lfc_status lfc_server_replay(lfc_server *sv, const lfc_render_request *reqs, const double *arrival_ms,
+                                        int32_t n, double *latency_ms) {
+  if (!sv || n < 0 || (n > 0 && (!reqs || !arrival_ms || !latency_ms)))
+    return fail(LFC_E_INVALID, "lfc_server_replay: null argument or n < 0");
+  for (int i = 0; i < n; i++) {
+    if (i && arrival_ms[i] < arrival_ms[i - 1]) return fail(LFC_E_INVALID, "lfc_server_replay: arrivals not sorted");
+    const lfc_render_request &r = reqs[i];
+    if (r.lf < 0 || r.lf >= (int32_t)sv->lfs.size() || r.out_w < 1 || r.out_h < 1 || r.out_w > 16384 ||
+        r.out_h > 16384 || ((result_bytes(r) + 255) & ~(size_t)255) > (size_t)sv->cfg.out_pool_bytes)
+      return fail(LFC_E_INVALID, "lfc_server_replay: request out of range");
+  }
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->replay_left += n;
+  }
+  const Clock::time_point t0 = Clock::now();
+  for (int i = 0; i < n; i++) {
+    const Clock::time_point due = t0 + std::chrono::duration_cast<Clock::duration>(
+                                           std::chrono::duration<double, std::milli>(arrival_ms[i]));
+    for (;;) {
+      const Clock::time_point now = Clock::now();
+      if (now >= due) break;
+      if (due - now > std::chrono::microseconds(200)) std::this_thread::sleep_for(due - now - std::chrono::microseconds(100));
+      else std::this_thread::yield();
+    }
+    std::lock_guard<std::mutex> lk(sv->mu);
+    lfc_status st = submit_locked(sv, reqs[i], true, &latency_ms[i], nullptr);
+    if (st != LFC_OK) return st;
+    // latency counts from the scheduled arrival, so a late submit is not hidden
+    sv->tickets[sv->next_ticket - 1].t_submit = due;
+    sv->cv_engine.notify_one();
+  }
+  std::unique_lock<std::mutex> lk(sv->mu);
+  sv->cv_done.wait(lk, [&] { return sv->replay_left <= 0; });
+  return LFC_OK;
+}
+
+extern "C" lfc_status lfc_server_get_stats(lfc_server *sv, lfc_server_stats *st) {
+  if (!sv || !st) return fail(LFC_E_INVALID, "lfc_server_get_stats: null argument");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  *st = sv->stats;
+  st->pool_bytes_in_use = (int64_t)sv->pool.used();
+  return LFC_OK;
+}
+
+extern "C" lfc_status lfc_server_destroy(lfc_server *sv) {
+  if (!sv) return LFC_OK;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv_engine.notify_all();
+  if (sv->engine.joinable()) sv->engine.join();
+  for (Lane &ln : sv->lanes) {
+    if (ln.stream) (void)hipStreamSynchronize(ln.stream);
+    if (ln.batch) (void)lfc_batch_destroy(ln.batch);
+    if (ln.done) (void)hipEventDestroy(ln.done);
+    if (ln.stream) (void)hipStreamDestroy(ln.stream);
+  }
+  if (sv->d_pool) (void)hipFree(sv->d_pool);
+  delete sv;
+  return LFC_OK;
+}

@@ -1,0 +1,32 @@
+// Internal interface between the batched render launcher (kernels.hip) and
+// the batching and serving runtime (serve.cpp).  A render request is packed
+// into an opaque record of render_req_bytes() bytes on the host, copied to
+// the device with the others of its batch, and rendered by one launch per
+// block size.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/lfc.h"
+
+namespace lfc {
+
+size_t render_req_bytes();
+
+// Packs request (view v of lf at wo x ho into out, [3][ho][wo] floats) into
+// dst; reports the light field's block size, the request's tile count and
+// the LDS bytes its tiles need.
+lfc_status render_req_fill(const lfc_lf *lf, const lfc_view &v, int wo, int ho, float *out, void *dst, int *block,
+                           int *ntiles, size_t *lds);
+
+// One launch over n packed requests already in device memory (all of block
+// size `block`): max_tiles workgroups per request, lds bytes each.
+lfc_status render_multi_launch(int block, const void *d_reqs, int n, int max_tiles, size_t lds, hipStream_t s);
+
+// The device a light field was opened on.
+int lf_device(const lfc_lf *lf);
+
+}  // namespace lfc

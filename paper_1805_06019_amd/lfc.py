@@ -59,6 +59,23 @@ class c_stats(C.Structure):
     ]
 
 
+class c_view(C.Structure):
+    _fields_ = [("u", C.c_float), ("v", C.c_float), ("s", C.c_float), ("t", C.c_float)]
+
+
+class c_render_request(C.Structure):
+    _fields_ = [("lf", C.c_int32), ("out_w", C.c_int32), ("out_h", C.c_int32), ("view", c_view)]
+
+
+class c_server_config(C.Structure):
+    _fields_ = [("max_batch", C.c_int32), ("streams", C.c_int32), ("out_pool_bytes", C.c_int64)]
+
+
+class c_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("batches", C.c_int64),
+                ("max_batch_seen", C.c_int64), ("admission_waits", C.c_int64), ("pool_bytes_in_use", C.c_int64)]
+
+
 @dataclass
 class Params:
     """Encoding parameters; see lfc_params in include/lfc.h."""
@@ -115,8 +132,21 @@ def load() -> C.CDLL:
         L.lfc_close.argtypes = [vp]
         L.lfc_last_error.argtypes = []
         L.lfc_last_error.restype = C.c_char_p
+        u64p, dp = C.POINTER(C.c_uint64), C.POINTER(C.c_double)
+        L.lfc_batch_create.argtypes = [C.POINTER(vp)]
+        L.lfc_batch_render.argtypes = [vp, C.POINTER(vp), i32, C.POINTER(c_render_request), i32, C.POINTER(vp), vp]
+        L.lfc_batch_destroy.argtypes = [vp]
+        L.lfc_server_create.argtypes = [C.POINTER(vp), i32, C.POINTER(c_server_config), C.POINTER(vp)]
+        L.lfc_server_submit.argtypes = [vp, C.POINTER(c_render_request), u64p]
+        L.lfc_server_wait.argtypes = [vp, C.c_uint64, i32, C.POINTER(vp), dp]
+        L.lfc_server_release.argtypes = [vp, C.c_uint64]
+        L.lfc_server_replay.argtypes = [vp, C.POINTER(c_render_request), dp, i32, dp]
+        L.lfc_server_get_stats.argtypes = [vp, C.POINTER(c_server_stats)]
+        L.lfc_server_destroy.argtypes = [vp]
         for f in ("lfc_encode", "lfc_encode_ex", "lfc_validate", "lfc_open", "lfc_info", "lfc_decode_blocks",
-                  "lfc_render_views", "lfc_check", "lfc_close"):
+                  "lfc_render_views", "lfc_check", "lfc_close", "lfc_batch_create", "lfc_batch_render",
+                  "lfc_batch_destroy", "lfc_server_create", "lfc_server_submit", "lfc_server_wait",
+                  "lfc_server_release", "lfc_server_replay", "lfc_server_get_stats", "lfc_server_destroy"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -258,3 +288,114 @@ def lfc_close(lf: LightField) -> None:
     h, lf.handle = lf.handle, None
     if h:
         _check(load().lfc_close(h))
+
+
+def _requests(reqs) -> "C.Array":
+    """reqs: sequence of (lf index, out_w, out_h, (u, v, s, t))."""
+    arr = (c_render_request * len(reqs))()
+    for k, (li, w, h, v) in enumerate(reqs):
+        arr[k].lf, arr[k].out_w, arr[k].out_h = int(li), int(w), int(h)
+        arr[k].view.u, arr[k].view.v, arr[k].view.s, arr[k].view.t = (float(x) for x in v)
+    return arr
+
+
+def _handles(lfs) -> "C.Array":
+    return (C.c_void_p * len(lfs))(*[lf.handle for lf in lfs])
+
+
+class Batch:
+    """Staging for batched renders across light fields (wraps lfc_batch*)."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        _check(load().lfc_batch_create(C.byref(h)))
+        self.handle = h.value
+
+    def render(self, lfs, reqs, outs=None, cuda_stream=None):
+        """Renders reqs = [(lf index, out_w, out_h, (u, v, s, t))] of the light
+        fields lfs in one launch per block size.  Returns the float32 CUDA
+        outputs [3][out_h][out_w], one per request."""
+        import torch
+        if outs is None:
+            outs = [torch.empty((3, h, w), dtype=torch.float32, device="cuda") for _, w, h, _ in reqs]
+        for o, (_, w, h, _) in zip(outs, reqs):
+            assert o.dtype == torch.float32 and o.is_cuda and o.is_contiguous() and tuple(o.shape) == (3, h, w)
+        ptrs = (C.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        _check(load().lfc_batch_render(self.handle, _handles(lfs), len(lfs), _requests(reqs), len(reqs), ptrs,
+                                       _stream_ptr(cuda_stream)))
+        return outs
+
+    def close(self) -> None:
+        h, self.handle = self.handle, None
+        if h:
+            _check(load().lfc_batch_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop over resident light fields (wraps lfc_server*)."""
+
+    def __init__(self, lfs, max_batch: int = 64, streams: int = 2, out_pool_bytes: int = 1 << 30):
+        self.lfs = list(lfs)   # the handles must outlive the server
+        cfg = c_server_config(max_batch, streams, out_pool_bytes)
+        h = C.c_void_p()
+        _check(load().lfc_server_create(_handles(self.lfs), len(self.lfs), C.byref(cfg), C.byref(h)))
+        self.handle = h.value
+
+    def submit(self, lf: int, out_w: int, out_h: int, view) -> int:
+        t = C.c_uint64()
+        _check(load().lfc_server_submit(self.handle, _requests([(lf, out_w, out_h, view)]), C.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        """Returns (device pointer of the float32 [3][out_h][out_w] result, latency ms)."""
+        p, lat = C.c_void_p(), C.c_double()
+        _check(load().lfc_server_wait(self.handle, ticket, timeout_ms, C.byref(p), C.byref(lat)))
+        return p.value, lat.value
+
+    def fetch(self, ticket: int, out_w: int, out_h: int, timeout_ms: int = -1):
+        """Waits, copies the result into a new CUDA tensor, releases it."""
+        import torch
+        ptr, lat = self.wait(ticket, timeout_ms)
+        out = torch.empty((3, out_h, out_w), dtype=torch.float32, device="cuda")
+        hip = C.CDLL("libamdhip64.so")
+        hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        st = hip.hipMemcpy(out.data_ptr(), ptr, out.numel() * 4, 3)   # device to device
+        self.release(ticket)
+        if st != 0:
+            raise LFCError(-4, f"hipMemcpy failed ({st})")
+        return out, lat
+
+    def release(self, ticket: int) -> None:
+        _check(load().lfc_server_release(self.handle, ticket))
+
+    def replay(self, reqs, arrival_ms) -> np.ndarray:
+        """Submits reqs[i] at arrival_ms[i] (from now), discards the results,
+        returns the latencies (ms) from arrival to completion."""
+        n = len(reqs)
+        arr = np.ascontiguousarray(arrival_ms, dtype=np.float64)
+        lat = np.zeros(n, dtype=np.float64)
+        _check(load().lfc_server_replay(self.handle, _requests(reqs), arr.ctypes.data_as(C.POINTER(C.c_double)), n,
+                                        lat.ctypes.data_as(C.POINTER(C.c_double))))
+        return lat
+
+    def stats(self) -> dict:
+        st = c_server_stats()
+        _check(load().lfc_server_get_stats(self.handle, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in c_server_stats._fields_}
+
+    def close(self) -> None:
+        h, self.handle = self.handle, None
+        if h:
+            _check(load().lfc_server_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,128 @@
+"""Summaries of rocprofv3 output databases for the committed profiles.
+
+    python -m paper_1805_06019_amd.prof_summary trace <kernel_trace.db> [command]
+    python -m paper_1805_06019_amd.prof_summary traffic <fetch.db> <write.db> <out.json> [command]
+
+``trace`` prints a markdown table of per-kernel dispatch counts and durations.
+``traffic`` reads one FETCH_SIZE run and one WRITE_SIZE run (KiB per
+dispatch), scales each by what the same counter reads for a device-to-device
+copy of 256 MiB in the same run (the copy moves exactly 256 MiB each way),
+and writes the per-launch HBM bytes of the whole-field decode kernel,
+together with a hash of the kernel source it was measured on.
+"""
+from __future__ import annotations
+
+import collections
+import hashlib
+import json
+import os
+import re
+import sqlite3
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+COPY_BYTES = 256 << 20
+DECODE_KERNEL = "k_decode_lf<4>"
+
+
+def kernel_source_hash() -> str:
+    """Hash of the source of the whole-field decode kernel: the device code
+    of kernels.hip up to the random-access section, its host launcher, and
+    internal.h (a change elsewhere, e.g. in the render kernels, keeps it)."""
+    with open(os.path.join(HERE, "csrc", "kernels.hip")) as fh:
+        src = fh.read()
+    device = src[:src.index("// random access: one (view, block) at a time")]
+    i = src.index("lfc_status decode_images(")
+    launcher = src[i:src.index("\n}\n", i)]
+    h = hashlib.sha256()
+    h.update(device.encode())
+    h.update(launcher.encode())
+    with open(os.path.join(HERE, "csrc", "internal.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    m = re.search(r"(k_\w+)(?:<(\d)>|ILi(\d)E)", name)
+    if m:
+        return f"{m.group(1)}<{m.group(2) or m.group(3)}>"
+    return name[:60]
+
+
+def trace_rows(db: str):
+    con = sqlite3.connect(db)
+    q = ("select name, count(*), avg(duration), min(duration), max(duration), grid_x, grid_y, grid_z, "
+         "workgroup_x, lds_size, vgpr_count, sgpr_count from kernels group by name order by sum(duration) desc")
+    return list(con.execute(q))
+
+
+def counter_per_dispatch(db: str, counter: str):
+    """{kernel short name: [value per dispatch]} for one counter."""
+    con = sqlite3.connect(db)
+    table = [r[0] for r in con.execute("select name from sqlite_master where type in ('table','view')")
+             if "counters_collection" in r[0]][0]
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    for name, disp, cname, val in con.execute(
+            f"select kernel_name, dispatch_id, counter_name, value from {table}"):
+        if cname == counter:
+            per[name][disp] += val
+    return {n: list(d.values()) for n, d in per.items()}
+
+
+def copy_kernel_value(per: dict) -> float:
+    """The counter for the 256 MiB device-to-device copy: the largest
+    dispatch of a copy kernel."""
+    best = 0.0
+    for name, vals in per.items():
+        if "copy" in name.lower():
+            best = max(best, max(vals))
+    if best <= 0:
+        raise SystemExit("no copy kernel in the counter run (run bench.py with --calib-copy)")
+    return best
+
+
+def decode_values(per: dict):
+    vals = []
+    for name, v in per.items():
+        if short_name(name) == DECODE_KERNEL:
+            vals += v
+    if not vals:
+        raise SystemExit(f"no {DECODE_KERNEL} dispatch in the counter run")
+    return vals
+
+
+def main(argv):
+    if len(argv) < 3:
+        raise SystemExit(__doc__)
+    mode = argv[1]
+    if mode == "trace":
+        print("| kernel | calls | avg us | min us | max us | grid | wg | lds B | vgpr | sgpr |")
+        print("|---|---|---|---|---|---|---|---|---|---|")
+        for r in trace_rows(argv[2]):
+            print(f"| {short_name(r[0])} | {r[1]} | {r[2] / 1e3:.2f} | {r[3] / 1e3:.2f} | {r[4] / 1e3:.2f} | "
+                  f"{r[5]}x{r[6]}x{r[7]} | {r[8]} | {r[9]} | {r[10]} | {r[11]} |")
+    elif mode == "traffic":
+        fetch = counter_per_dispatch(argv[2], "FETCH_SIZE")
+        write = counter_per_dispatch(argv[3], "WRITE_SIZE")
+        f_copy, w_copy = copy_kernel_value(fetch), copy_kernel_value(write)
+        f_scale, w_scale = f_copy * 1024 / COPY_BYTES, w_copy * 1024 / COPY_BYTES
+        fv, wv = decode_values(fetch), decode_values(write)
+        f_bytes = sum(fv) / len(fv) * 1024 / f_scale
+        w_bytes = sum(wv) / len(wv) * 1024 / w_scale
+        rec = dict(kernel=DECODE_KERNEL, kernel_source_hash=kernel_source_hash(),
+                   bytes_per_launch=round(f_bytes + w_bytes), fetch_bytes_per_launch=round(f_bytes),
+                   write_bytes_per_launch=round(w_bytes), dispatches=[len(fv), len(wv)],
+                   fetch_kib_per_dispatch=round(sum(fv) / len(fv), 1), write_kib_per_dispatch=round(sum(wv) / len(wv), 1),
+                   copy_fetch_kib=round(f_copy, 1), copy_write_kib=round(w_copy, 1),
+                   copy_fetch_factor=round(f_scale, 4), copy_write_factor=round(w_scale, 4),
+                   command=argv[5] if len(argv) > 5 else "")
+        with open(argv[4], "w") as fh:
+            json.dump(rec, fh, indent=1)
+            fh.write("\n")
+        print(json.dumps(rec, indent=1))
+    else:
+        raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    main(sys.argv)

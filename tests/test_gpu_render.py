@@ -3,7 +3,7 @@ oracle's renderer run on the oracle's decoded light field.
 
 The bar is a maximum absolute error of 1e-5 on RGB/255 outputs: the GPU may
 contract multiply-adds, the oracle evaluates every lerp in source order.
-Covers magnification and minification, ragged tiles, block sizes 2/4/8, a
+Covers magnification and minification (down to one output pixel), ragged tiles, block sizes 2/4/8, a
 single-row camera grid, a single view, cameras outside the grid, and the
 batched render workload (64 novel 512x512 views per launch on the 8x8x64x64
 light field and on the 9x9 lenslet-like 625x434 light field).
@@ -40,6 +40,9 @@ CASES = [
     (9, 1, 40, 30, dict(block=4, levels=2, cluster=(3,)), 41, 31, 0.5),
     (1, 1, 24, 20, dict(block=4, levels=1, cluster=()), 48, 40, 0.5),
     (4, 4, 200, 120, dict(block=4, levels=2, cluster=(2,), blk_threshold=10), 50, 30, 4.0),
+    # strong minification: a whole view into one or a few output pixels
+    (4, 4, 200, 120, dict(block=4, levels=2, cluster=(2,), blk_threshold=10), 1, 1, 4.0),
+    (6, 3, 130, 10, dict(block=2, levels=3, cluster=(2, 2), blk_threshold=3), 3, 2, 1.0),
 ]
 
 

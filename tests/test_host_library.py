@@ -207,3 +207,25 @@ def test_encoder_statistics_match_oracle(case):
     assert st["code_hist"] == list(enc.hist) and st["present_blocks"] == enc.hist.sum()
     none, st2 = lfc.lfc_encode_ex(lf, lfc.Params(**ok), want_stream=False)
     assert none is None and st2 == st
+
+
+def test_batch_and_server_argument_errors_on_host():
+    # checks that come before any device call
+    lib = lfc.load()
+    assert lib.lfc_batch_render(None, None, 0, None, 1, None, None) == -1
+    assert lib.lfc_batch_destroy(None) == 0
+    assert lib.lfc_server_destroy(None) == 0
+    fake = (C.c_void_p * 1)(1)
+    out = C.c_void_p()
+    for max_batch, streams, pool in ((0, 1, 1 << 20), (8, 0, 1 << 20), (8, 9, 1 << 20), (8, 1, 16)):
+        cfg = lfc.c_server_config(max_batch, streams, pool)
+        assert lib.lfc_server_create(fake, 1, C.byref(cfg), C.byref(out)) == -1
+    cfg = lfc.c_server_config(8, 1, 1 << 20)
+    assert lib.lfc_server_create(None, 1, C.byref(cfg), C.byref(out)) == -1
+    assert lib.lfc_server_create(fake, 0, C.byref(cfg), C.byref(out)) == -1
+    t = C.c_uint64()
+    assert lib.lfc_server_submit(None, None, C.byref(t)) == -1
+    assert lib.lfc_server_wait(None, 1, 0, None, None) == -1
+    assert lib.lfc_server_release(None, 1) == -1
+    assert lib.lfc_server_replay(None, None, None, 0, None) == -1
+    assert lib.lfc_server_get_stats(None, None) == -1
