@@ -179,6 +179,21 @@ lfc_status lfc_decode_blocks(const lfc_lf *lf, const int32_t *d_req, int64_t n, 
                              int16_t *d_out, hipStream_t s);
 
 /*
+ * Progressive decompression (Sec. 3.6): the tree traversal of
+ * DecompressLFIBlock (Alg. 2) stopped at tree level `level`, which yields the
+ * filtered key-view value of the view's ancestor on that level: for each
+ * (view, block) request, the key-view block plus the residual blocks of the
+ * view's ancestors on levels L-2 down to `level`.  level 0 equals
+ * lfc_decode_blocks; level L-1 is the key view alone.
+ *  d_req, n, d_out  as lfc_decode_blocks with LFC_LAYOUT_BLOCKS.
+ *  level            0..levels-1.
+ * Out-of-range requests yield zeros and raise the device error flag.
+ * Errors: LFC_E_INVALID, LFC_E_HIP.
+ */
+lfc_status lfc_decode_progressive(const lfc_lf *lf, const int32_t *d_req, int64_t n, int32_t level,
+                                  int16_t *d_out, hipStream_t s);
+
+/*
  * Novel-view rendering (Sec. 3.6): every output pixel is the quadrilinear
  * interpolation, over the two nearest camera columns, the two nearest
  * camera rows and the 2 x 2 nearest source pixels, of decoded samples

@@ -117,6 +117,7 @@ def lib() -> C.CDLL:
         L.orc_free.restype = None
         L.orc_read_header.argtypes = [vp, i64, C.POINTER(_Params), C.POINTER(_Geom)]
         L.orc_decode_block.argtypes = [vp, i64, i32, i32, vp]
+        L.orc_decode_block_level.argtypes = [vp, i64, i32, i32, i32, vp]
         L.orc_decode_all.argtypes = [vp, i64, i32, i32, vp]
         L.orc_render.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, i32, i32, i32, vp]
         L.orc_psnr.argtypes = [vp, vp, i32, i32, i32, i32, i32]
@@ -286,6 +287,16 @@ def decode_block(stream: bytes, vi: int, b: int) -> np.ndarray:
     s = _sbuf(stream)
     out = np.zeros((3, p.block, p.block), dtype=np.int16)
     _check(lib().orc_decode_block(_ptr(s), s.size, vi, b, _ptr(out)), "orc_decode_block")
+    return out
+
+
+def decode_block_level(stream: bytes, vi: int, b: int, level: int) -> np.ndarray:
+    """Progressive decompression (Sec. 3.6): block b of view vi reconstructed
+    only down to tree level `level`."""
+    p, _ = read_header(stream)
+    s = _sbuf(stream)
+    out = np.zeros((3, p.block, p.block), dtype=np.int16)
+    _check(lib().orc_decode_block_level(_ptr(s), s.size, vi, b, level, _ptr(out)), "orc_decode_block_level")
     return out
 
 

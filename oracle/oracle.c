@@ -770,6 +770,37 @@ int orc_decode_block(const uint8_t *stream, int64_t bytes, int32_t vi, int32_t b
   return ORC_OK;
 }
 
+/* Progressive decompression (Sec. 3.6): the same traversal as
+ * orc_decode_block, stopped at tree level `level` -- the key-view block plus
+ * the residuals of the view's ancestors on levels L-2 down to `level`, which
+ * is the reconstruction of its level-`level` ancestor. */
+int orc_decode_block_level(const uint8_t *stream, int64_t bytes, int32_t vi, int32_t b, int32_t level,
+                           int16_t *out) {
+  stream_view v;
+  int st = parse_stream(stream, bytes, &v);
+  if (st) return st;
+  if (vi < 0 || vi >= v.p.grid_u * v.p.grid_v || b < 0 || b >= v.g.nb) return ORC_E_INVALID;
+  if (level < 0 || level >= v.p.levels) return ORC_E_INVALID;
+  tree_t t;
+  st = tree_build(&v.p, &v.g, &t);
+  if (st) return st;
+  const int S = v.p.block * v.p.block, L = v.p.levels;
+  int root = ancestor(&t, vi, L - 1);
+  for (int c = 0; c < 3; c++) {
+    int32_t x[64], d[64];
+    for (int i = 0; i < S; i++) x[i] = v.rkv[(((int64_t)root * v.g.nb + b) * 3 + c) * S + i];
+    for (int l = L - 2; l >= level; l--) {
+      int s = t.srv_of[l][ancestor(&t, vi, l)];
+      st = read_residual(&v, 3 * b + c, s, d);
+      if (st) { tree_free(&t); return st; }
+      for (int i = 0; i < S; i++) x[i] += d[i];
+    }
+    for (int i = 0; i < S; i++) out[c * S + i] = (int16_t)x[i];
+  }
+  tree_free(&t);
+  return ORC_OK;
+}
+
 /* ------------------------------------------------------------------ */
 /* whole light field, one location (group) at a time                  */
 /* ------------------------------------------------------------------ */

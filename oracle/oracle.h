@@ -100,6 +100,11 @@ int orc_read_header(const uint8_t *stream, int64_t bytes, orc_params *p, orc_geo
  * out is [3][B*B] int16. */
 int orc_decode_block(const uint8_t *stream, int64_t bytes, int32_t vi, int32_t b, int16_t *out);
 
+/* Progressive decompression (Sec. 3.6): the traversal of orc_decode_block
+ * stopped at tree level `level` (0 = the view, L-1 = its key view). */
+int orc_decode_block_level(const uint8_t *stream, int64_t bytes, int32_t vi, int32_t b, int32_t level,
+                           int16_t *out);
+
 /* Whole light field, group by group (Sec. 3.5), for blocks [b0, b1).
  * out is [U*V][3][hp][wp] int16. */
 int orc_decode_all(const uint8_t *stream, int64_t bytes, int32_t b0, int32_t b1, int16_t *out);

@@ -695,9 +695,11 @@ struct RAArgs {
 };
 
 // Row y of block b, channel c, of view vi (Alg. 2): key-view row plus the
-// residual rows of the view's ancestors, as B/2 packed int16 pairs.
+// residual rows of the view's ancestors on levels L-2 down to stop (0: the
+// view itself; a higher stop is progressive decompression, Sec. 3.6), as B/2
+// packed int16 pairs.
 template <int B>
-__device__ __forceinline__ void gather_row(const RAArgs &a, int vi, int b, int c, int y, uint32_t plan_t,
+__device__ __forceinline__ void gather_row(const RAArgs &a, int vi, int b, int c, int y, int stop, uint32_t plan_t,
                                            uint32_t plan_q, const uint16_t *lut, uint32_t x[B / 2]) {
   constexpr int S = B * B;
   const int root = a.root[vi];
@@ -707,7 +709,7 @@ __device__ __forceinline__ void gather_row(const RAArgs &a, int vi, int b, int c
   if (o0 == o1) return;
   const uint32_t *gw = a.srv + o0;
   const int depth = a.L - 1;
-  for (int l = depth - 1; l >= 0; --l) {
+  for (int l = depth - 1; l >= stop; --l) {
     const int s = a.path[vi * depth + l];
     const uint32_t bm = gw[s >> 5];
     const uint32_t bit = (uint32_t)s & 31u;
@@ -727,6 +729,7 @@ struct BlocksArgs {
   int16_t *out;        // [n][3][S]
   int32_t *err;
   int64_t n;
+  int stop;            // lowest tree level whose residuals are added
 };
 
 template <int B>
@@ -756,7 +759,7 @@ __global__ __launch_bounds__(kThreads) void k_decode_blocks(BlocksArgs a) {
 #pragma unroll
     for (int i = 0; i < B / 2; i++) x[i] = 0;
   } else {
-    gather_row<B>(a.ra, vi, b, c, y, digit_plan<B>(y, true), digit_plan<B>(y, false), lut, x);
+    gather_row<B>(a.ra, vi, b, c, y, a.stop, digit_plan<B>(y, true), digit_plan<B>(y, false), lut, x);
   }
   store_row<B>(a.out + ((size_t)r * 3 + c) * S + y * B, x);
 }
@@ -1065,9 +1068,9 @@ lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s) {
 }
 
 template <int B>
-lfc_status decode_list(const lfc_lf *lf, const int32_t *req, int64_t n, int16_t *out, hipStream_t s) {
+lfc_status decode_list(const lfc_lf *lf, const int32_t *req, int64_t n, int16_t *out, hipStream_t s, int stop = 0) {
   constexpr int RPW = 64 / (3 * B);
-  BlocksArgs a{ra_args(lf), req, out, lf->d_err, n};
+  BlocksArgs a{ra_args(lf), req, out, lf->d_err, n, stop};
   const int64_t waves = (n + RPW - 1) / RPW;
   const int64_t blocks = (waves + kThreads / 64 - 1) / (kThreads / 64);
   if (blocks > 0x7FFFFFFF) return fail(LFC_E_INVALID, "lfc_decode_blocks: too many requests");
@@ -1146,6 +1149,27 @@ extern "C" lfc_status lfc_decode_blocks(const lfc_lf *lf, const int32_t *d_req, 
     case 2: return decode_list<2>(lf, d_req, n, d_out, s);
     case 4: return decode_list<4>(lf, d_req, n, d_out, s);
     default: return decode_list<8>(lf, d_req, n, d_out, s);
+  }
+}
+
+extern "C" lfc_status lfc_decode_progressive(const lfc_lf *lf, const int32_t *d_req, int64_t n, int32_t level,
+                                             int16_t *d_out, hipStream_t s) {
+  const char *who = "lfc_decode_progressive";
+  if (!lf) return fail(LFC_E_INVALID, "lfc_decode_progressive: null handle");
+  if (lfc_status st = check_device(lf, who)) return st;
+  const lfc::Geometry &g = lf->geo;
+  if (n < 0) return fail(LFC_E_INVALID, "lfc_decode_progressive: n < 0");
+  if (level < 0 || level >= g.L) return fail(LFC_E_INVALID, "lfc_decode_progressive: level must be 0..levels-1");
+  if (n == 0) return LFC_OK;
+  if (!d_req && n != (int64_t)g.nv() * g.nb)
+    return fail(LFC_E_INVALID, "lfc_decode_progressive: with d_req NULL, n must be grid_u*grid_v*n_blocks");
+  if (d_req)
+    if (lfc_status st = check_buffer(d_req, (size_t)n * 8, 4, who, "d_req")) return st;
+  if (lfc_status st = check_buffer(d_out, (size_t)n * 3 * g.S * 2, 16, who, "d_out")) return st;
+  switch (g.B) {
+    case 2: return decode_list<2>(lf, d_req, n, d_out, s, level);
+    case 4: return decode_list<4>(lf, d_req, n, d_out, s, level);
+    default: return decode_list<8>(lf, d_req, n, d_out, s, level);
   }
 }
 

@@ -127,6 +127,7 @@ def load() -> C.CDLL:
         L.lfc_open.argtypes = [vp, sz, vp, C.POINTER(vp)]
         L.lfc_info.argtypes = [vp, C.POINTER(c_info)]
         L.lfc_decode_blocks.argtypes = [vp, vp, i64, i32, vp, vp]
+        L.lfc_decode_progressive.argtypes = [vp, vp, i64, i32, vp, vp]
         L.lfc_render_views.argtypes = [vp, vp, i32, i32, i32, vp, vp]
         L.lfc_check.argtypes = [vp, vp]
         L.lfc_close.argtypes = [vp]
@@ -144,7 +145,7 @@ def load() -> C.CDLL:
         L.lfc_server_get_stats.argtypes = [vp, C.POINTER(c_server_stats)]
         L.lfc_server_destroy.argtypes = [vp]
         for f in ("lfc_encode", "lfc_encode_ex", "lfc_validate", "lfc_open", "lfc_info", "lfc_decode_blocks",
-                  "lfc_render_views", "lfc_check", "lfc_close", "lfc_batch_create", "lfc_batch_render",
+                  "lfc_render_views", "lfc_check", "lfc_close", "lfc_decode_progressive", "lfc_batch_create", "lfc_batch_render",
                   "lfc_batch_destroy", "lfc_server_create", "lfc_server_submit", "lfc_server_wait",
                   "lfc_server_release", "lfc_server_replay", "lfc_server_get_stats", "lfc_server_destroy"):
             getattr(L, f).restype = C.c_int
@@ -262,6 +263,23 @@ def lfc_decode_blocks(lf: LightField, req=None, layout: int = LAYOUT_BLOCKS, out
     assert out.dtype == torch.int16 and out.is_cuda and out.is_contiguous() and tuple(out.shape) == shape
     _check(load().lfc_decode_blocks(lf.handle, req.data_ptr() if req is not None else None, n, layout,
                                     out.data_ptr(), _stream_ptr(cuda_stream)))
+    return out
+
+
+def lfc_decode_progressive(lf: LightField, req, level: int, out=None, cuda_stream=None):
+    """Progressive decompression: blocks [n][3][B][B] reconstructed down to
+    tree level `level` only.  req: int32 CUDA tensor [n][2] or None (all)."""
+    import torch
+    i = lf.info
+    B = i.params.block
+    n = req.shape[0] if req is not None else i.params.grid_u * i.params.grid_v * i.n_blocks
+    if req is not None:
+        assert req.dtype == torch.int32 and req.is_cuda and req.is_contiguous() and req.dim() == 2
+    if out is None:
+        out = torch.empty((n, 3, B, B), dtype=torch.int16, device="cuda")
+    assert out.dtype == torch.int16 and out.is_cuda and out.is_contiguous() and tuple(out.shape) == (n, 3, B, B)
+    _check(load().lfc_decode_progressive(lf.handle, req.data_ptr() if req is not None else None, n, level,
+                                         out.data_ptr(), _stream_ptr(cuda_stream)))
     return out
 
 

@@ -13,12 +13,14 @@ import sys
 import time
 
 from . import lfc, synth
-from .workloads import FULL_SPEC, LENSLET_SPEC, TINY_SPEC
+from .workloads import FULL_SPEC, LENSLET_SPEC, TINY_SPEC, serve_large_spec, serve_small_spec
 
 BASE = {
     "tiny": (TINY_SPEC, dict(block=4, levels=2, cluster=(2,))),
     "full": (FULL_SPEC, dict(block=4, levels=3, cluster=(2, 3))),
     "lenslet": (LENSLET_SPEC, dict(block=4, levels=3, cluster=(2, 2))),
+    "serve_small": (serve_small_spec(401), dict(block=4, levels=2, cluster=(2,))),
+    "serve_large": (serve_large_spec(409), dict(block=4, levels=3, cluster=(2, 3))),
 }
 
 

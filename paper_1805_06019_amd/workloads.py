@@ -40,6 +40,19 @@ TINY_SPEC = LFSpec(8, 8, 64, 64, layers=3, disparity=2.0, noise_sigma=2.0, seed=
 FULL_SPEC = LFSpec(17, 17, 512, 512, layers=6, disparity=3.0, noise_sigma=1.5, seed=201)
 LENSLET_SPEC = LFSpec(9, 9, 625, 434, layers=4, disparity=1.0, noise_sigma=1.0, seed=301, vignetting=True)
 
+# the serving mix: four light fields of each geometry, seeds 401-412
+def serve_small_spec(seed: int) -> LFSpec:      # 8x8 views of 256x256, as the tiny workload
+    return LFSpec(8, 8, 256, 256, layers=3, disparity=2.0, noise_sigma=2.0, seed=seed)
+
+
+def serve_lenslet_spec(seed: int) -> LFSpec:    # 9x9 lenslet-like views of 625x434
+    return LFSpec(9, 9, 625, 434, layers=4, disparity=1.0, noise_sigma=1.0, seed=seed, vignetting=True)
+
+
+def serve_large_spec(seed: int) -> LFSpec:      # 17x17 views of 1024x1024, as the full workload
+    return LFSpec(17, 17, 1024, 1024, layers=6, disparity=3.0, noise_sigma=1.5, seed=seed)
+
+
 WORKLOADS = {
     # 8x8 views of 64x64, 2-level tree with a key view per 2x2 group, block threshold 2
     "tiny": Workload("tiny", TINY_SPEC, 4, 2, (2,), blk_threshold=2),

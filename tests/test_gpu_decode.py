@@ -4,9 +4,10 @@ Bit-exact: every decoded int16 sample equals the oracle's closed-loop
 reconstruction R^0, which its own decoders reproduce (pinned in
 test_oracle_codec.py).  Covers the whole-field kernel (images layout), the
 random-access kernel (blocks layout, all blocks or a request list), ragged
-images, block sizes 2/4/8, tree heights 1-4, empty and out-of-range requests,
-and the full 17x17x512x512 workload in the launch configuration the
-benchmark times.
+images, block sizes 2/4/8, tree heights 1-6, empty and out-of-range requests,
+the staging tiers of the whole-field kernel, progressive decompression at
+every tree level (Sec. 3.6), and the full 17x17x512x512 workload in the
+launch configuration the benchmark times.
 """
 import ctypes as C
 
@@ -200,4 +201,44 @@ def test_full_size_whole_field_and_random_access(gpu, full40):
     blk = lfc.lfc_decode_blocks(lf, torch.from_numpy(req).cuda(), lfc.LAYOUT_BLOCKS).cpu().numpy()
     expect = blocks_of(enc.r0, 4)
     assert np.array_equal(blk, expect[req[:, 0], req[:, 1]])
+    lfc.lfc_check(lf)
+
+
+@pytest.mark.parametrize("case", GEOMS[:8], ids=[f"{c[0]}x{c[1]}x{c[2]}x{c[3]}-B{c[4]['block']}-L{c[4]['levels']}"
+                                                 for c in GEOMS[:8]])
+def test_progressive_decode_matches_oracle(gpu, case):
+    # Sec. 3.6: the traversal stopped at level k, every level of the tree
+    U, V, W, H, kw = case
+    say("progressive", case)
+    rgb = make_lf(U, V, W, H, seed=U * 13 + W)
+    enc = oracle_encode(rgb, **kw)
+    lf = gpu_open(enc.stream)
+    nv, nb = U * V, lf.info.n_blocks
+    req = synth.block_requests(64, nv, nb, seed=U + W)
+    dreq = torch.from_numpy(req).cuda()
+    full = lfc.lfc_decode_blocks(lf, dreq, lfc.LAYOUT_BLOCKS)
+    for k in range(kw["levels"]):
+        got = lfc.lfc_decode_progressive(lf, dreq, k).cpu().numpy()
+        want = np.stack([oracle.decode_block_level(enc.stream, int(v), int(b), k) for v, b in req])
+        assert np.array_equal(got, want), k
+        if k == 0:
+            assert np.array_equal(got, full.cpu().numpy())
+    lfc.lfc_check(lf)
+
+
+def test_progressive_decode_full_size_and_errors(gpu, full40):
+    _, _, enc = full40
+    lf = gpu_open(enc.stream)
+    nv, nb = 289, lf.info.n_blocks
+    req = synth.block_requests(100_000, nv, nb, seed=303)
+    dreq = torch.from_numpy(req).cuda()
+    got = lfc.lfc_decode_progressive(lf, dreq, 1).cpu().numpy()
+    for i in np.random.default_rng(5).integers(0, len(req), 100):
+        assert np.array_equal(got[i], oracle.decode_block_level(enc.stream, int(req[i, 0]), int(req[i, 1]), 1))
+    lib = lfc.load()
+    s = torch.cuda.current_stream().cuda_stream
+    out = torch.empty((4, 3, 4, 4), dtype=torch.int16, device="cuda")
+    assert lib.lfc_decode_progressive(lf.handle, dreq.data_ptr(), 4, 3, out.data_ptr(), s) == -1
+    assert lib.lfc_decode_progressive(lf.handle, dreq.data_ptr(), 4, -1, out.data_ptr(), s) == -1
+    assert lib.lfc_decode_progressive(lf.handle, dreq.data_ptr(), 0, 2, out.data_ptr(), s) == 0
     lfc.lfc_check(lf)
