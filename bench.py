@@ -6,13 +6,16 @@ through the key view and the residuals of both tree levels.  The same run
 also times, on the same light field, a batched render of 64 novel 512x512
 views per launch, single-view renders launched one per request (the plain
 kernel; p50/p99 latency), 10^6 random block accesses, the 50 dB coding of
-the same light field, and the 64-view render of the 9x9 lenslet-like light
-field.  Inputs are resident in device memory before any timed region.
+the same light field, the 64-view render of the 9x9 lenslet-like light
+field, and the serving loop over 12 resident light fields (Poisson arrivals,
+batched server vs one plain launch per request).  Inputs are resident in
+device memory before any timed region.
 
 Prints one JSON line.  ``value`` is decoded samples per second of the step.
 ``roofline`` prices the whole-field kernel's algorithmic bytes per launch
-(int16 output, key-view blocks, block offsets and the compressed SRV
-section read once) against 8 TB/s of HBM.  ``cpu_baseline`` is the oracle's
+(int16 output, key-view blocks, block offsets, the compressed SRV section
+and the rank directory read once) against 8 TB/s of HBM; ``traffic`` is the
+kernel's measured HBM bytes per launch from the committed counter runs.  ``cpu_baseline`` is the oracle's
 whole-field decoder on the host's cores (bounded sample).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
@@ -20,7 +23,6 @@ whole-field decoder on the host's cores (bounded sample).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -38,17 +40,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("kernels.hip", "internal.h"):
-        with open(os.path.join(ROOT, "paper_1805_06019_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic():
     """HBM bytes per launch from the committed rocprofv3 counter runs, if they
     were taken on the current kernel source; else None."""
+    from paper_1805_06019_amd.prof_summary import kernel_source_hash
     path = os.path.join(ROOT, "profiles", "traffic_decode_lf_full40.json")
     if not os.path.exists(path):
         return None
@@ -97,6 +92,79 @@ def cpu_baseline(stream: bytes, nv: int, hp: int, wp: int, nb: int, min_cpu_s: f
                             f"blocks split over {threads} threads, {wall:.2f} s wall")
 
 
+def serving(lfc, synth, torch, n_req: int = 20000):
+    """Serving loop over 12 resident light fields (4 of 8x8x256^2, 4 lenslet-like
+    9x9x625x434, 4 of 17x17x1024^2, each coded at about 40 dB): Poisson arrivals
+    of novel-view requests, half 512^2 and half 1024^2, uniform over the light
+    fields, replayed against the batching server and against one plain launch
+    per request; p50/p99 latency from arrival to completion per arrival rate,
+    and the saturation throughput of both."""
+    from paper_1805_06019_amd.workloads import (WORKLOADS, serve_large_spec, serve_lenslet_spec,
+                                                serve_small_spec)
+    t0 = time.time()
+    kinds = [(serve_small_spec, range(401, 405), WORKLOADS["serve_small40"]),
+             (serve_lenslet_spec, range(405, 409), WORKLOADS["serve_lenslet40"]),
+             (serve_large_spec, range(409, 413), WORKLOADS["serve_large40"])]
+    lfs, grids, psnr = [], [], []
+    for mk, seeds, enc in kinds:
+        for sd in seeds:
+            spec = mk(sd)
+            rgb = synth.light_field(spec)
+            stream, st = lfc.lfc_encode_ex(rgb, enc.params(grid_u=spec.grid_u, grid_v=spec.grid_v,
+                                                           width=spec.width, height=spec.height))
+            del rgb
+            lfs.append(lfc.lfc_open(stream))
+            grids.append((spec.grid_u, spec.grid_v))
+            psnr.append(round(st["psnr"], 2))
+    log(f"serving: 12 light fields generated, coded and opened in {time.time() - t0:.1f}s")
+    rng = np.random.default_rng(402)
+    li = rng.integers(0, len(lfs), n_req)
+    big = rng.random(n_req) < 0.5
+    reqs = []
+    for k in range(n_req):
+        U, V = grids[li[k]]
+        side = 1024 if big[k] else 512
+        reqs.append((int(li[k]), side, side, (rng.uniform(0, U - 1), rng.uniform(0, V - 1),
+                                              rng.uniform(-1, 1), rng.uniform(-1, 1))))
+    pool = 4 << 30
+    res = dict(light_fields=len(lfs), psnr_db=psnr, requests=n_req, sizes="50% 512x512, 50% 1024x1024",
+               batched=dict(max_batch=64, streams=2), plain=dict(max_batch=1, streams=1), points=[])
+
+    def run(max_batch, streams, arrivals):
+        sv = lfc.Server(lfs, max_batch=max_batch, streams=streams, out_pool_bytes=pool)
+        t = time.perf_counter()
+        lat = sv.replay(reqs, arrivals)
+        wall = time.perf_counter() - t
+        st = sv.stats()
+        sv.close()
+        return lat, wall, st
+
+    # saturation: every request queued at once
+    zero = np.zeros(n_req)
+    sat = {}
+    for name, mb, ns in (("batched", 64, 2), ("plain", 1, 1)):
+        lat, wall, st = run(mb, ns, zero)
+        sat[name] = round(n_req / wall, 1)
+        log(f"serving {name} saturation: {n_req / wall:.0f} views/s, {st['batches']} launches")
+    res["saturation_views_per_s"] = sat
+    res["saturation_speedup"] = round(sat["batched"] / sat["plain"], 2)
+    # Poisson arrivals at fractions of the plain kernel's saturation rate, and beyond it
+    for frac in (0.5, 0.9, 2.0):
+        lam = frac * sat["plain"]
+        arrivals = np.cumsum(rng.exponential(1000.0 / lam, n_req))
+        point = dict(rate_per_s=round(lam, 1))
+        for name, mb, ns in (("batched", 64, 2), ("plain", 1, 1)):
+            lat, wall, st = run(mb, ns, arrivals)
+            point[name] = dict(p50_ms=round(float(np.percentile(lat, 50)), 3),
+                               p99_ms=round(float(np.percentile(lat, 99)), 3),
+                               views_per_s=round(n_req / wall, 1), mean_batch=round(n_req / st["batches"], 2))
+        res["points"].append(point)
+        log(f"serving at {lam:.0f}/s: {point}")
+    for lf in lfs:
+        lf.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +172,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -162,10 +231,12 @@ def main():
     srv_bytes = 4 * (int(np.frombuffer(stream40, dtype=np.uint32, count=1,
                                        offset=int(np.frombuffer(stream40, dtype=np.uint64, count=1, offset=112)[0])
                                        + 4 * info.n_groups)[0]) + 2)
+    nbw = (info.n_srv + 31) // 32
     alg_bytes = (samples * 2                       # int16 output written once
                  + info.n_top * nb * 3 * 16 * 2    # key-view blocks
                  + 4 * (info.n_groups + 1)         # block offsets
                  + srv_bytes                       # compressed SRV section
+                 + 4 * info.n_groups * nbw         # rank directory: one word per bitmap word
                  + 4 * nv * 4)                     # leaf schedule
     achieved = alg_bytes / (per_launch.mean() * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -247,6 +318,8 @@ def main():
                                          views_per_s=round(64 / (rl.mean() * 1e-3), 1))
         lfl.close()
         del imgl
+        if not args.no_serving:
+            extra["serving"] = serving(lfc, synth, torch)
 
     if args.calib_copy:
         src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
@@ -268,7 +341,7 @@ def main():
     rec = dict(
         metric="decoded Gsamples/s", value=round(value, 2), unit="Gsamples/s", n_gpus=1,
         steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_per_step, 5), higher_is_better=True,
-        scaling="weak", vs_baseline=None, dtype="int32", data="synthetic",
+        scaling="weak", vs_baseline=None, dtype="int16", data="synthetic",
         config=dict(workload="full40: whole-field decode of 17x17 views x 512x512 RGB, 3-level tree "
                              "(17->9->3), 4x4 blocks, q=2, T_blk=67",
                     psnr_db=round(st40["psnr"], 3), bpp=round(8 * len(stream40) / (nv * 512 * 512), 4),

@@ -70,4 +70,15 @@ WORKLOADS = {
     #   q=0: 106 -> 40.056 dB 9.135 bpp; q=1: 103 -> 40.014 dB 8.633 bpp; q=2: 96 -> 40.085 dB 8.140 bpp
     "lenslet40": Workload("lenslet40", LENSLET_SPEC, 4, 3, (2, 2), blk_threshold=96, quant_bits=2,
                           note="40.085 dB, 8.140 bpp"),
+    # serving mix (seeds 401-412); the operating point is tuned on the first seed of each geometry
+    # python -m paper_1805_06019_amd.tune serve_small 40:
+    #   q=0: 88 -> 40.004 dB 14.682 bpp; q=1: 87 -> 40.020 dB 14.339 bpp; q=2: 86 -> 40.025 dB 13.972 bpp
+    "serve_small40": Workload("serve_small40", serve_small_spec(401), 4, 2, (2,), blk_threshold=86, quant_bits=2,
+                              note="40.025 dB, 13.972 bpp"),
+    "serve_lenslet40": Workload("serve_lenslet40", serve_lenslet_spec(405), 4, 3, (2, 2), blk_threshold=96,
+                                quant_bits=2, note="the lenslet40 operating point"),
+    # python -m paper_1805_06019_amd.tune serve_large 40:
+    #   q=0: 68 -> 40.052 dB 8.700 bpp; q=1: 67 -> 40.058 dB 7.655 bpp; q=2: 65 -> 40.024 dB 6.579 bpp
+    "serve_large40": Workload("serve_large40", serve_large_spec(409), 4, 3, (2, 3), blk_threshold=65, quant_bits=2,
+                              note="40.024 dB, 6.579 bpp"),
 }
