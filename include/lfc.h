@@ -156,6 +156,16 @@ lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, lfc_lf **ou
 lfc_status lfc_info(const lfc_lf *lf, lfc_info_t *info);
 
 /*
+ * LDS words the whole-field decode needs to stage each strip (64/B blocks of
+ * one block row and channel, strips ordered channel, block row, strip):
+ * need[2i] = its groups plus its part of the decode schedule, need[2i+1] =
+ * the schedule alone.  Fills min(n, strips) pairs (need may be NULL) and
+ * returns the number of strips, or a negative lfc_status.  For tuning and
+ * tests: the environment variable LFC_STAGE_CAP_WORDS caps the staging.
+ */
+int64_t lfc_stage_needs(const lfc_lf *lf, uint32_t *need, int64_t n);
+
+/*
  * DecompressLFIBlock (Alg. 2) for a batch of blocks, decoded in parallel
  * (Sec. 3.6): each output block is the top key-view block plus the dequantised
  * residual blocks of its ancestors down to level 0 (Sec. 3.5), as int16 YCoCg-R

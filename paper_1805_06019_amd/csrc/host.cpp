@@ -269,6 +269,81 @@ void build_chunks(const Geometry &g, std::vector<int32_t> &batch, std::vector<in
   }
 }
 
+// Decode schedule of the whole-field kernel, derived once from the directory:
+// per strip (channel c, block row by, strip sx of 64/B blocks) and chunk, the
+// stored (node, block) pairs sorted by range kind with their directory
+// entries, and per node of the chunk a mask of its stored blocks.
+//   strip record: [0..nchunk] offsets of the chunk records from the strip's
+//   start (the last one is the strip's length); chunk record: n0, n01, n
+//   (ends of the plain-bit, trit and quint items), masks[nodes], entries[n],
+//   then the pairs (node << 5 | block) as 16-bit values, two per word.
+static void build_schedule(const Geometry &g, const std::vector<uint32_t> &off, const std::vector<uint32_t> &srv,
+                           const std::vector<uint32_t> &dbase, const std::vector<uint32_t> &poff,
+                           const std::vector<int32_t> &chunks, const std::vector<int32_t> &nodes,
+                           std::vector<uint32_t> &sched, std::vector<uint32_t> &strip_off) {
+  const int nblk = 64 / g.B, nsx = (g.nbx + nblk - 1) / nblk, nstrip = 3 * g.nby * nsx;
+  const int nck = (int)(chunks.size() / kChunkWords);
+  std::vector<std::vector<uint32_t>> per((size_t)nstrip);
+  parallel_for(nstrip, 8, [&](int64_t a, int64_t e) {
+    std::vector<uint32_t> ent[3];
+    std::vector<uint16_t> ids[3];
+    for (int64_t st = a; st < e; st++) {
+      const int sx = (int)(st % nsx), by = (int)((st / nsx) % g.nby), c = (int)(st / ((int64_t)nsx * g.nby));
+      std::vector<uint32_t> &w = per[(size_t)st];
+      w.assign((size_t)nck + 1, 0);
+      for (int k = 0; k < nck; k++) {
+        w[(size_t)k] = (uint32_t)w.size();
+        const int32_t *cr = &chunks[(size_t)k * kChunkWords];
+        const int nn = cr[2], base = cr[3];
+        std::vector<uint32_t> mask((size_t)nn, 0);
+        for (int kind = 0; kind < 3; kind++) {
+          ent[kind].clear();
+          ids[kind].clear();
+        }
+        for (int ln = 0; ln < nn; ln++) {
+          const int s = nodes[(size_t)base + ln];
+          for (int jj = 0; jj < nblk; jj++) {
+            const int bx = sx * nblk + jj;
+            if (bx >= g.nbx) continue;
+            const size_t gi = 3 * ((size_t)by * g.nbx + bx) + c;
+            const uint32_t o0 = off[gi], o1 = off[gi + 1];
+            if (o0 == o1) continue;
+            const uint32_t bm = srv[o0 + (s >> 5)], bit = (uint32_t)s & 31u;
+            if (!((bm >> bit) & 1u)) continue;
+            const uint32_t en = poff[dbase[gi * g.nbw + (s >> 5)] + (uint32_t)__builtin_popcount(bm & ((1u << bit) - 1u))];
+            const uint32_t code = en & 31u;
+            const int kind = code < 12 ? 0 : (code < 19 ? 1 : 2);
+            ent[kind].push_back(en);
+            ids[kind].push_back((uint16_t)((ln << 5) | jj));
+            mask[(size_t)ln] |= 1u << jj;
+          }
+        }
+        const uint32_t n0 = (uint32_t)ent[0].size(), n01 = n0 + (uint32_t)ent[1].size();
+        const uint32_t n = n01 + (uint32_t)ent[2].size();
+        w.push_back(n0);
+        w.push_back(n01);
+        w.push_back(n);
+        w.insert(w.end(), mask.begin(), mask.end());
+        for (int kind = 0; kind < 3; kind++) w.insert(w.end(), ent[kind].begin(), ent[kind].end());
+        std::vector<uint16_t> all;
+        for (int kind = 0; kind < 3; kind++) all.insert(all.end(), ids[kind].begin(), ids[kind].end());
+        for (size_t i = 0; i < all.size(); i += 2)
+          w.push_back((uint32_t)all[i] | ((i + 1 < all.size() ? (uint32_t)all[i + 1] : 0u) << 16));
+      }
+      w[(size_t)nck] = (uint32_t)w.size();
+    }
+  });
+  strip_off.assign((size_t)nstrip + 1, 0);
+  size_t total = 0;
+  for (int st = 0; st < nstrip; st++) {
+    strip_off[(size_t)st] = (uint32_t)total;
+    total += per[(size_t)st].size();
+  }
+  strip_off[(size_t)nstrip] = (uint32_t)total;
+  sched.resize(total);
+  for (int st = 0; st < nstrip; st++) std::copy(per[(size_t)st].begin(), per[(size_t)st].end(), sched.begin() + strip_off[(size_t)st]);
+}
+
 // ---------------------------------------------------------------------------
 // encoder
 // ---------------------------------------------------------------------------
@@ -830,8 +905,14 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
   };
   static const uint32_t zeros[64] = {0};
   std::vector<int32_t> chunks, nmap;
-  build_chunks(ps.g, tt.batch, chunks, nmap);
-  Part parts[12] = {
+  std::vector<uint32_t> sched, strip_off;
+  try {
+    build_chunks(ps.g, tt.batch, chunks, nmap);
+    build_schedule(ps.g, ps.off, ps.srv, ps.dbase, ps.poff, chunks, nmap, sched, strip_off);
+  } catch (const std::bad_alloc &) {
+    return fail(LFC_E_NOMEM, "lfc_open: out of host memory");
+  }
+  Part parts[13] = {
       {ps.rkv, ps.rkv_bytes, 0},
       {ps.off.data(), ps.off.size() * 4, 0},
       {ps.srv.data(), ps.srv.size() * 4, 0},
@@ -843,7 +924,8 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
       {zeros, 4, 0},
       {chunks.data(), chunks.size() * 4, 0},
       {ps.pbase.data(), ps.pbase.size() * 4, 0},
-      {nmap.data(), nmap.size() * 4, 0},
+      {sched.data(), sched.size() * 4, 0},
+      {strip_off.data(), strip_off.size() * 4, 0},
   };
   size_t total = 0;
   for (auto &pt : parts) {
@@ -893,26 +975,37 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
   lf->n_batch = (int)(tt.batch.size() / kBatchWords);
   lf->d_chunk = reinterpret_cast<const int32_t *>(d + parts[9].at);
   lf->d_pbase = reinterpret_cast<const uint32_t *>(d + parts[10].at);
-  lf->d_nmap = reinterpret_cast<const int32_t *>(d + parts[11].at);
-  lf->n_nmap = (int)nmap.size();
+  lf->d_sched = reinterpret_cast<const uint32_t *>(d + parts[11].at);
+  lf->d_strip_off = reinterpret_cast<const uint32_t *>(d + parts[12].at);
   lf->n_chunk = (int)(chunks.size() / kChunkWords);
   for (int i = 0; i < lf->n_chunk; i++) lf->max_chunk_nodes = std::max(lf->max_chunk_nodes, chunks[(size_t)i * kChunkWords + 2]);
   lf->d_err = reinterpret_cast<int32_t *>(d + parts[8].at);
   // LDS staging of the whole-field kernel is sized by the largest strip:
-  // group words, directory entries and directory rows
-  const int nblk = 64 / g.B;
+  // group words plus the strip's decode schedule
+  const int nblk = 64 / g.B, nsx = (g.nbx + nblk - 1) / nblk;
   for (int c = 0; c < 3; c++)
     for (int by = 0; by < g.nby; by++)
-      for (int bx0 = 0; bx0 < g.nbx; bx0 += nblk) {
-        uint64_t words = (uint64_t)nblk * g.nbw;   // directory rows
-        for (int bx = bx0; bx < std::min(bx0 + nblk, g.nbx); bx++) {
+      for (int sx = 0; sx < nsx; sx++) {
+        const size_t st = ((size_t)c * g.nby + by) * nsx + sx;
+        uint64_t words = strip_off[st + 1] - strip_off[st];
+        for (int bx = sx * nblk; bx < std::min(sx * nblk + nblk, g.nbx); bx++) {
           const int gi = 3 * (by * g.nbx + bx) + c;
-          words += ps.off[gi + 1] - ps.off[gi] + ps.pbase[gi + 1] - ps.pbase[gi];
+          words += ps.off[gi + 1] - ps.off[gi];
         }
         lf->max_strip_words = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(lf->max_strip_words, words), 1u << 30);
+        lf->strip_need.push_back((uint32_t)std::min<uint64_t>(words, 1u << 30));
+        lf->strip_need.push_back(strip_off[st + 1] - strip_off[st]);
       }
   *out = lf;
   return LFC_OK;
+}
+
+extern "C" int64_t lfc_stage_needs(const lfc_lf *lf, uint32_t *need, int64_t n) {
+  if (!lf) return fail(LFC_E_INVALID, "lfc_stage_needs: null handle");
+  const int64_t strips = (int64_t)(lf->strip_need.size() / 2);
+  if (need)
+    for (int64_t i = 0; i < std::min(n, strips) * 2; i++) need[i] = lf->strip_need[(size_t)i];
+  return strips;
 }
 
 extern "C" lfc_status lfc_info(const lfc_lf *lf, lfc_info_t *info) {

@@ -86,10 +86,11 @@ struct lfc_lf {
   const int32_t *d_batch = nullptr;  // [n_batch][kBatchWords]
   int n_batch = 0;
   const int32_t *d_chunk = nullptr;  // [n_chunk][kChunkWords]
-  const int32_t *d_nmap = nullptr;   // [n_nmap] node lists of the chunks
-  int n_nmap = 0;
+  const uint32_t *d_sched = nullptr;     // decode schedule of the whole-field kernel (strip records)
+  const uint32_t *d_strip_off = nullptr; // [n_strips+1] word offset of each strip's record
   int n_chunk = 0, max_chunk_nodes = 0;
   int32_t *d_err = nullptr;          // device error flag
-  uint32_t max_strip_words = 0;      // largest group words + directory entries + directory rows of a strip
-                                     // of 64/B blocks of one channel
+  uint32_t max_strip_words = 0;      // largest group words + decode schedule of a strip of 64/B blocks of
+                                     // one channel
+  std::vector<uint32_t> strip_need;  // per strip: group words + schedule words, schedule words
 };

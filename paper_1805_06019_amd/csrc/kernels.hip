@@ -237,25 +237,22 @@ __device__ __forceinline__ void store_row(int16_t *p, const uint32_t x[B / 2]) {
 
 constexpr int kLFThreads = 512;
 constexpr int kLFWaves = kLFThreads / 64;
-constexpr int kLFHeadWords = 832;     // LDS words before the residual tile (LUT, extents, node masks)
+constexpr int kLFHeadWords = 448;     // LDS words before the residual tile (LUT, per-block extents)
 constexpr int kStagePad = 8;          // zero words after the staged group words
 
 struct LFArgs {
   const int16_t *rkv;
   const uint32_t *off;
   const uint32_t *srv;
-  const uint32_t *dbase;   // directory: [ng][nbw] index of each bitmap word's first stored node
-  const uint32_t *poff;    // directory: entry per stored block
-  const uint32_t *pbase;   // [ng+1] first directory entry of each group
-  const int32_t *batch;    // [nbatch][kBatchWords] runs of sibling leaves (see internal.h)
-  const int32_t *chunk;    // [nchunk][kChunkWords] runs of batches decoded together
-  const int32_t *nmap;     // [n_nmap] node lists of the chunks
-  int16_t *out;            // [nv][3][hp][wp]
-  int nbx, n_srv, nbw, nv, L, q, wp, hp, nb, nbatch, nchunk, max_chunk_nodes;
-  int stage_cap;           // LDS words available for staging the strip
-  int vec_store;           // output rows may be stored 16 bytes at a time
-  int n_top, key_words;    // key views; LDS words of the strip's key-view rows (0: not staged)
-  int n_nmap;
+  const uint32_t *sched;      // decode schedule: one record per strip (see build_schedule on the host)
+  const uint32_t *strip_off;  // [n_strips+1] word offset of each strip's record
+  const int32_t *batch;       // [nbatch][kBatchWords] runs of sibling leaves (see internal.h)
+  const int32_t *chunk;       // [nchunk][kChunkWords] runs of batches decoded together
+  int16_t *out;               // [nv][3][hp][wp]
+  int nbx, nv, L, q, wp, hp, nb, nbatch, nchunk, max_chunk_nodes;
+  int stage_cap;              // LDS words available for staging the strip
+  int vec_store;              // output rows may be stored 16 bytes at a time
+  int n_top, key_words;       // key views; LDS words of the strip's key-view rows (0: not staged)
 };
 
 // A whole block of a known kind (0 plain bits, 1 trit, 2 quint) decoded by one
@@ -352,212 +349,171 @@ __device__ __forceinline__ int tile_slot(int ln, int y, int slot) {
   return (ln * B + y) * 8 + (slot ^ (ln & 7));
 }
 
-// Pairs (node, block) of one chunk handled per lane: enough for the largest
-// chunk the host builds (256/B nodes of 64/B blocks over 512 lanes).
+// One chunk of phase B of the whole-field kernel.  sch is the chunk's record
+// of the decode schedule (n0, n01, n, per-node masks of the stored blocks,
+// directory entries, (node, block) pairs), in LDS or in global memory; the
+// payload of block j of the strip is at pw + s_po[j].  Step (3): every
+// listed block decoded once, whole, by one lane, with the decoder of its
+// range kind, into the tile; step (4): per sibling run, key-view row +
+// ancestor rows + leaf row (absent blocks masked), stored 16 bytes per lane.
 template <int B>
-constexpr int kListIters = 32 / (B * B) > 1 ? 32 / (B * B) : 1;
-
-// Where one pass of phase B finds the strip's data: payload words at
-// pw + s_po[j], bitmap words at bw + s_bo[j], bitmap-word bases at
-// dir + s_dr[j], directory entries at pe + (index - s_pb[j]); each in LDS or
-// in global memory depending on how much of the strip was staged.
-struct StripView {
-  const uint32_t *pw, *s_po, *bw, *s_bo, *dir, *s_dr, *pe, *s_pb;
-};
-
-// Steps (2) and (3) of a pass: list the chunk's stored (node, block) pairs
-// sorted by range kind, then decode each listed block once, whole, one lane
-// per block, into the tile.  The list takes two passes over the pairs and no
-// atomics: per-wave counts by ballot, a barrier, then every wave writes its
-// items at its own offsets.
-template <int B>
-__device__ __forceinline__ void lf_chunk_decode(const LFArgs &a, const ChunkRec &cr, const StripView &sv,
-                                                const int32_t *nmap, const uint32_t *s_len, uint32_t *s_wc,
-                                                uint32_t *s_mask, uint32_t *it_e,
-                                                uint16_t *it_id, uint32_t *tile, const uint16_t *lut, int tid,
-                                                int wave, int lane) {
-  constexpr int S = B * B, NBLK = 64 / B, H = B / 2, IT = kListIters<B>;
-  const int np = cr.nn * NBLK;
-  const uint64_t below = (1ull << lane) - 1ull;
-  uint32_t ent[IT], rk[IT];
-  uint32_t run0 = 0, run1 = 0, run2 = 0;
-#pragma unroll
-  for (int k = 0; k < IT; k++) {
-    const int idx = k * kLFThreads + wave * 64 + lane;
-    uint32_t e = kAbsent;
-    if (idx < np) {
-      const int ln = idx / NBLK, jj = idx % NBLK;
-      if (s_len[jj]) {
-        const int s = nmap[cr.nbase + ln];
-        const uint32_t bm = sv.bw[sv.s_bo[jj] + (s >> 5)];
-        const uint32_t bit = (uint32_t)s & 31u;
-        if ((bm >> bit) & 1u)
-          e = sv.pe[sv.dir[sv.s_dr[jj] + (s >> 5)] - sv.s_pb[jj] + __popc(bm & ((1u << bit) - 1u))];
-      }
-    }
-    const uint32_t kind = e == kAbsent ? 3u : code_kind(e & 31u);
-    const uint64_t b0 = __ballot(kind == 0u), b1 = __ballot(kind == 1u), b2 = __ballot(kind == 2u);
-    const uint32_t r = kind == 0u ? run0 + (uint32_t)__popcll(b0 & below)
-                                  : (kind == 1u ? run1 + (uint32_t)__popcll(b1 & below)
-                                                : run2 + (uint32_t)__popcll(b2 & below));
-    ent[k] = e;
-    rk[k] = (r << 2) | kind;
-    // which blocks of each of the wave's nodes are stored
-    const uint64_t pres = b0 | b1 | b2;
-    if (lane < 64 / NBLK) {
-      const int node = (k * kLFThreads + wave * 64) / NBLK + lane;
-      if (node < cr.nn) s_mask[node] = (uint32_t)(pres >> (lane * NBLK)) & (NBLK == 32 ? ~0u : (1u << NBLK) - 1u);
-    }
-    run0 += (uint32_t)__popcll(b0);
-    run1 += (uint32_t)__popcll(b1);
-    run2 += (uint32_t)__popcll(b2);
-  }
-  if (lane == 0) {
-    s_wc[wave] = run0;
-    s_wc[kLFWaves + wave] = run1;
-    s_wc[2 * kLFWaves + wave] = run2;
-  }
-  __syncthreads();
-  uint32_t n0 = 0, n1 = 0, n2 = 0, o0 = 0, o1 = 0, o2 = 0;
-#pragma unroll
-  for (int w = 0; w < kLFWaves; w++) {
-    const uint32_t c0 = s_wc[w], c1 = s_wc[kLFWaves + w], c2 = s_wc[2 * kLFWaves + w];
-    if (w < wave) {
-      o0 += c0;
-      o1 += c1;
-      o2 += c2;
-    }
-    n0 += c0;
-    n1 += c1;
-    n2 += c2;
-  }
-#pragma unroll
-  for (int k = 0; k < IT; k++) {
-    const uint32_t kind = rk[k] & 3u;
-    if (kind != 3u) {
-      const int idx = k * kLFThreads + wave * 64 + lane;
-      const uint32_t at = (rk[k] >> 2) + (kind == 0u ? o0 : (kind == 1u ? n0 + o1 : n0 + n1 + o2));
-      it_e[at] = ent[k];
-      it_id[at] = (uint16_t)(((idx / NBLK) << 5) | (idx % NBLK));
-    }
-  }
-  __syncthreads();
-  // the three kinds are laid end to end, so a wave mostly sees a single kind
-  for (uint32_t it = tid; it < n0 + n1 + n2; it += kLFThreads) {
-    const uint32_t e = it_e[it], id = it_id[it];
+__device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, int nn, int q0, int nq,
+                                         const uint32_t *pw, const uint32_t *s_po, uint32_t *tile,
+                                         const uint32_t *keys, const uint16_t *lut, int tid, int wave, int lane,
+                                         int so, int y, int jq, int bx0, int nact, bool wide, uint64_t lane_off,
+                                         uint32_t vstride) {
+  constexpr int S = B * B, NBLK = 64 / B, H = B / 2, PB = 8 / B, SPP = 64 / (8 * B);
+  const uint32_t n0 = sch[0], n01 = sch[1], n = sch[2];
+  const uint32_t *masks = sch + 3;
+  const uint32_t *ents = masks + nn;
+  const uint16_t *ids = reinterpret_cast<const uint16_t *>(ents + n);
+  // (3) decode; the three kinds are laid end to end, so a wave mostly sees one kind
+  for (uint32_t it = tid; it < n; it += kLFThreads) {
+    const uint32_t e = ents[it], id = ids[it];
     const int ln = (int)(id >> 5), jj = (int)(id & 31u);
-    const uint32_t *gw = sv.pw + sv.s_po[jj];
+    const uint32_t *gw = pw + s_po[jj];
     uint32_t d[S / 2];
     if (it < n0) decode_block_k<B, 0>(gw, e, a.q, lut, d);
-    else if (it < n0 + n1) decode_block_k<B, 1>(gw, e, a.q, lut, d);
+    else if (it < n01) decode_block_k<B, 1>(gw, e, a.q, lut, d);
     else decode_block_k<B, 2>(gw, e, a.q, lut, d);
 #pragma unroll
     for (int yy = 0; yy < B; yy++)
 #pragma unroll
-      for (int h = 0; h < H; h++) tile[tile_slot<B>(ln, yy, jj / (8 / B)) * 4 + (jj % (8 / B)) * H + h] = d[yy * H + h];
+      for (int h = 0; h < H; h++) tile[tile_slot<B>(ln, yy, jj / PB) * 4 + (jj % PB) * H + h] = d[yy * H + h];
   }
+  __syncthreads();
+  // (4) gather and store, waves splitting the chunk's runs
+  const int by = blockIdx.y, c = blockIdx.z, L = a.L;
+  int root_cached = -1;                      // key-view row read from global memory (keys not staged)
+  uint4 key = make_uint4(0u, 0u, 0u, 0u);
+  const int per = (nq + kLFWaves - 1) / kLFWaves;
+  for (int qb = q0 + wave * per; qb < q0 + min(nq, wave * per + per); qb++) {
+    const uniform_i32 rec = as_uniform(a.batch + (size_t)qb * lfc::kBatchWords);
+    const int root = rec[5];
+    uint32_t anc[4];
+    if (a.key_words) {
+      const uint4 k4 = reinterpret_cast<const uint4 *>(keys)[(((root * B + y) * NBLK + jq * PB) * H) / 4];
+      anc[0] = k4.x;
+      anc[1] = k4.y;
+      anc[2] = k4.z;
+      anc[3] = k4.w;
+    } else {
+      if (root != root_cached) {
+        root_cached = root;
+        uint32_t kk[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < PB; k++)
+          if (k < nact) load_row<B>(a.rkv + ((size_t)(root * a.nb + by * a.nbx + bx0 + k) * 3 + c) * S + y * B, kk + k * H);
+        key = make_uint4(kk[0], kk[1], kk[2], kk[3]);
+      }
+      anc[0] = key.x;
+      anc[1] = key.y;
+      anc[2] = key.z;
+      anc[3] = key.w;
+    }
+    // the lane's tile slot of node ln, with the entries of absent blocks as 0
+    auto add_node = [&](int ln, uint32_t x[4]) {
+      const uint4 t4 = reinterpret_cast<const uint4 *>(tile)[tile_slot<B>(ln, y, jq)];
+      const uint32_t bits = masks[ln] >> (jq * PB);
+      const uint32_t t[4] = {t4.x, t4.y, t4.z, t4.w};
+#pragma unroll
+      for (int w = 0; w < 4; w++) x[w] = add_pk(x[w], ((bits >> (w / H)) & 1u) ? t[w] : 0u);
+    };
+    for (int k = 0; k < L - 2; k++) add_node(rec[12 + k], anc);
+    const int nsib = rec[0], ls0 = rec[11];
+    const int v0 = rec[1], v1 = rec[2], v2 = rec[3], v3 = rec[4];
+    // sibling i of the run: its leaf row plus the ancestors
+    auto leaf = [&](int i, uint32_t x[4]) -> int16_t * {
+#pragma unroll
+      for (int w = 0; w < 4; w++) x[w] = anc[w];
+      add_node(ls0 + i, x);
+      const uint32_t vi = (uint32_t)(i == 0 ? v0 : (i == 1 ? v1 : (i == 2 ? v2 : v3)));
+      return a.out + ((uint64_t)vi * vstride + lane_off);
+    };
+    // two loops, so that the 16-byte stores stay whole
+    if (wide) {
+      for (int i = so; i < nsib; i += SPP) {
+        uint32_t x[4];
+        int16_t *dst = leaf(i, x);
+        *reinterpret_cast<uint4 *>(dst) = make_uint4(x[0], x[1], x[2], x[3]);
+      }
+    } else if (nact > 0) {
+      for (int i = so; i < nsib; i += SPP) {
+        uint32_t x[4];
+        int16_t *dst = leaf(i, x);
+#pragma unroll
+        for (int k = 0; k < PB; k++)
+          if (k < nact) store_row<B>(dst + k * B, x + k * H);
+      }
+    }
+  }
+  __syncthreads();
 }
 
 // One workgroup = one channel c, one row of blocks by, one strip of 64/B
 // consecutive blocks (64 pixels).  Phase A copies into LDS what fits of the
-// strip's data: its groups, directory entries and bitmap-word bases (tier
-// 1), else the same without the payload words (tier 2), else nothing (tier
-// 3: all read from global memory), plus the strip's key-view rows.  Phase B
-// walks the leaves in serial order, chunk by chunk: (1) zero the residual
-// tile; (2) list the (node, block) pairs whose block is stored, by range
-// kind; (3) decode each listed block once, whole, one lane per block, into
-// the tile; (4) per sibling run: key-view row + ancestor rows + leaf row,
-// stored 16 bytes per lane.
+// strip's data: its groups and its decode schedule (tier 1), else the
+// schedule only (tier 2: payload read through bit windows from global
+// memory), else nothing (tier 3), plus the strip's key-view rows.  Phase B
+// walks the leaves in serial order, chunk by chunk: decode every stored
+// residual block of the chunk once into the residual tile, then write the
+// chunk's leaves (key view + ancestors + leaf), 16 bytes per lane.
 template <int B>
 __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
   constexpr int S = B * B, NBLK = 64 / B, H = B / 2;
-  constexpr int NODE_WORDS = B * NBLK * H;             // tile words per node: [B rows][NBLK blocks][H]
   constexpr int PB = 8 / B;                            // blocks per 16-byte row segment (1 for B = 8)
   constexpr int LPS = 8 * B;                           // lanes per sibling: 8 segments x B rows
-  constexpr int SPP = 64 / LPS;                        // siblings stored per pass
   extern __shared__ uint32_t smem[];
   uint16_t *lut = reinterpret_cast<uint16_t *>(smem);  // 384 x u16 = 192 words
   uint32_t *s_o0 = smem + 192;                         // group start word in the SRV section
   uint32_t *s_len = smem + 256;                        // group length in words
-  uint32_t *s_P = smem + 320;                          // stored blocks of the group
-  uint32_t *s_wo = smem + 384;                         // staged group words (tier 1) or bitmap (tier 2)
-  uint32_t *s_dr = smem + 448;                         // directory row: offset from the dir base
-  uint32_t *s_pb = smem + 512;                         // directory entries: re-basing of the indices
-  uint32_t *s_cnt = smem + 576;                        // [3] tier, [4] staged group words
-  uint32_t *s_wc = smem + 584;                         // [3][kLFWaves] per-wave list counts
-  uint32_t *s_pe = smem + 640;                         // directory entries of the group: staged offset
-  uint32_t *s_mask = smem + 704;                       // [max_chunk_nodes] stored blocks of each tile node
-  uint32_t *tile = smem + kLFHeadWords;                // [max_chunk_nodes][NODE_WORDS]
-  const int item_cap = a.max_chunk_nodes * NBLK;
-  uint32_t *it_e = tile + a.max_chunk_nodes * NODE_WORDS;               // [item_cap] listed entries
-  uint16_t *it_id = reinterpret_cast<uint16_t *>(it_e + item_cap);      // [item_cap] node << 5 | block
-  uint32_t *keys = it_e + item_cap + ((item_cap + 7) / 8) * 4;          // [n_top][B][NBLK][H]
-  int32_t *nmap = reinterpret_cast<int32_t *>(keys + a.key_words);     // [n_nmap] node lists of the chunks
-  uint32_t *stage = keys + a.key_words + a.n_nmap;
+  uint32_t *s_wo = smem + 320;                         // staged group words
+  uint32_t *s_cnt = smem + 384;                        // [0] tier, [1] staged group words, [2] schedule words
+  uint32_t *tile = smem + kLFHeadWords;                // [max_chunk_nodes][B rows][8 slots][4]
+  uint32_t *keys = tile + a.max_chunk_nodes * B * 32;  // [n_top][B][NBLK][H]
+  uint32_t *stage = keys + a.key_words;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int st = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const uint32_t sched0 = a.strip_off[st], sched_len = a.strip_off[st + 1] - sched0;
   for (int t = tid; t < kLutEntries; t += kLFThreads) lut[t] = lut_entry(t);
   if (tid < NBLK) {
     const int bx = blockIdx.x * NBLK + tid;
-    uint32_t o0 = 0, o1 = 0, pb0 = 0, pb1 = 0;
+    uint32_t o0 = 0, o1 = 0;
     if (bx < a.nbx) {
       const int g = 3 * (blockIdx.y * a.nbx + bx) + blockIdx.z;
       o0 = a.off[g];
       o1 = a.off[g + 1];
-      pb0 = a.pbase[g];
-      pb1 = a.pbase[g + 1];
-      s_dr[tid] = (uint32_t)g * a.nbw;
-    } else {
-      s_dr[tid] = 0;
     }
     s_o0[tid] = o0;
     s_len[tid] = o1 - o0;
-    s_P[tid] = pb1 - pb0;
-    s_pb[tid] = pb0;
   }
   __syncthreads();
   if (tid == 0) {
-    uint32_t words = 0, entries = 0;
+    uint32_t words = 0;
     for (int j = 0; j < NBLK; j++) {
+      s_wo[j] = words;
       words += s_len[j];
-      entries += s_P[j];
     }
-    const uint32_t rows = (uint32_t)NBLK * a.nbw;
-    const uint32_t tier = words + kStagePad + entries + rows <= (uint32_t)a.stage_cap ? 1u
-                          : (rows + entries + rows <= (uint32_t)a.stage_cap ? 2u : 3u);
-    s_cnt[3] = tier;
-    // tier 1: [group words][pad][entries][directory rows]
-    // tier 2: [bitmap words, nbw per block][entries][directory rows]
-    uint32_t wacc = 0, pacc = tier == 1u ? words + kStagePad : rows;
-    for (int j = 0; j < NBLK; j++) {
-      if (tier < 3u) {
-        s_wo[j] = tier == 1u ? wacc : (uint32_t)j * a.nbw;
-        s_pe[j] = pacc;
-        s_pb[j] = s_pb[j] - pacc;           // entry index - s_pb = position in the staged entries
-        wacc += s_len[j];
-        pacc += s_P[j];
-      } else {
-        s_wo[j] = s_o0[j];
-        s_pb[j] = 0;                        // global directory indices
-      }
-    }
-    if (tier < 3u)
-      for (int j = 0; j < NBLK; j++) s_dr[j + 32] = pacc + (uint32_t)j * a.nbw;  // staged directory rows
-    s_cnt[4] = tier == 1u ? words : 0u;
+    // tier 1: [group words][pad][schedule]; tier 2: [schedule]
+    const uint32_t tier = words + kStagePad + sched_len <= (uint32_t)a.stage_cap ? 1u
+                          : (sched_len <= (uint32_t)a.stage_cap ? 2u : 3u);
+    s_cnt[0] = tier;
+    s_cnt[1] = tier == 1u ? words : 0u;
+    s_cnt[2] = tier == 1u ? words + kStagePad : 0u;
   }
   __syncthreads();
-  const uint32_t tier = s_cnt[3];
+  const uint32_t tier = s_cnt[0], sched_at = s_cnt[2];
+  // every copy goes straight from global memory to LDS, all in flight at once
+  if (tier == 1u)
+    for (int j = wave; j < NBLK; j += kLFWaves)
+      if (s_len[j]) lds_copy(stage + s_wo[j], a.srv + s_o0[j], s_len[j], lane);
   if (tier < 3u) {
-    // every copy goes straight from global memory to LDS, all in flight at once
-    for (int j = wave; j < NBLK; j += kLFWaves) {
-      if (!s_len[j]) continue;
-      lds_copy(stage + s_wo[j], a.srv + s_o0[j], tier == 1u ? s_len[j] : (uint32_t)a.nbw, lane);
-      lds_copy(stage + s_pe[j], a.poff + (s_pb[j] + s_pe[j]), s_P[j], lane);
-      lds_copy(stage + s_dr[j + 32], a.dbase + s_dr[j], (uint32_t)a.nbw, lane);
-    }
+    // the schedule, split over the waves in pieces of whole 64-word rows
+    const uint32_t rows = (sched_len + 63) / 64, per = (rows + kLFWaves - 1) / kLFWaves;
+    const uint32_t r0 = min(rows, (uint32_t)wave * per), r1 = min(rows, r0 + per);
+    if (r1 > r0) lds_copy(stage + sched_at + r0 * 64, a.sched + sched0 + r0 * 64, min(sched_len, r1 * 64) - r0 * 64, lane);
   }
-  if (wave == kLFWaves - 1) lds_copy(reinterpret_cast<uint32_t *>(nmap), reinterpret_cast<const uint32_t *>(a.nmap),
-                                     (uint32_t)a.n_nmap, lane);
   if (a.key_words) {
     // the strip's key-view rows, laid out as the tile: [root][row][block][H]
     const uint32_t *rk = reinterpret_cast<const uint32_t *>(a.rkv);
@@ -572,9 +528,7 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
     }
   }
   __builtin_amdgcn_s_waitcnt(0);
-  if (tier == 1u && tid < kStagePad) stage[s_cnt[4] + tid] = 0;
-  __syncthreads();
-  if (tier < 3u && tid < NBLK) s_dr[tid] = s_dr[tid + 32];
+  if (tier == 1u && tid < kStagePad) stage[s_cnt[1] + tid] = 0;
   __syncthreads();
 
   const int by = blockIdx.y, c = blockIdx.z;
@@ -600,82 +554,18 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
   const int nact = max(0, min(PB, a.nbx - bx0));       // blocks of the segment inside the image
   const bool wide = nact == PB && a.vec_store;          // a 16-byte store is aligned
   const uint64_t lane_off = cplane + (uint64_t)(by * B + y) * a.wp + (uint64_t)bx0 * B;
-  const int L = a.L;
-  int root_cached = -1;
-  uint32_t key[4] = {0, 0, 0, 0};
+  const uint32_t *gsched = a.sched + sched0;
   for (int ci = 0; ci < a.nchunk; ci++) {
     const ChunkRec cr = read_chunk(a.chunk, ci);
-    if (tier == 1u) {
-      const StripView sv{stage, s_wo, stage, s_wo, stage, s_dr, stage, s_pb};
-      lf_chunk_decode<B>(a, cr, sv, nmap, s_len, s_wc, s_mask, it_e, it_id, tile, lut, tid, wave, lane);
-    } else if (tier == 2u) {
-      const StripView sv{a.srv, s_o0, stage, s_wo, stage, s_dr, stage, s_pb};
-      lf_chunk_decode<B>(a, cr, sv, nmap, s_len, s_wc, s_mask, it_e, it_id, tile, lut, tid, wave, lane);
-    } else {
-      const StripView sv{a.srv, s_o0, a.srv, s_o0, a.dbase, s_dr, a.poff, s_pb};
-      lf_chunk_decode<B>(a, cr, sv, nmap, s_len, s_wc, s_mask, it_e, it_id, tile, lut, tid, wave, lane);
-    }
-    __syncthreads();
-    // (4) gather and store, waves splitting the chunk's batches
-    const int per = (cr.nq + kLFWaves - 1) / kLFWaves;
-    for (int qb = cr.q0 + wave * per; qb < cr.q0 + min(cr.nq, wave * per + per); qb++) {
-      const uniform_i32 rec = as_uniform(a.batch + (size_t)qb * lfc::kBatchWords);
-      const int root = rec[5];
-      uint32_t anc[4];
-      if (a.key_words) {
-        const uint4 k4 = reinterpret_cast<const uint4 *>(keys)[(((root * B + y) * NBLK + jq * PB) * H) / 4];
-        anc[0] = k4.x;
-        anc[1] = k4.y;
-        anc[2] = k4.z;
-        anc[3] = k4.w;
-      } else {
-        if (root != root_cached) {
-          root_cached = root;
-#pragma unroll
-          for (int k = 0; k < PB; k++)
-            if (k < nact) load_row<B>(a.rkv + ((size_t)(root * a.nb + by * a.nbx + bx0 + k) * 3 + c) * S + y * B,
-                                      key + k * H);
-        }
-#pragma unroll
-        for (int h = 0; h < 4; h++) anc[h] = key[h];
-      }
-      // the lane's tile slot of node ln, with the entries of absent blocks as 0
-      auto add_node = [&](int ln, uint32_t x[4]) {
-        const uint4 t4 = reinterpret_cast<const uint4 *>(tile)[tile_slot<B>(ln, y, jq)];
-        const uint32_t bits = s_mask[ln] >> (jq * PB);
-        const uint32_t t[4] = {t4.x, t4.y, t4.z, t4.w};
-#pragma unroll
-        for (int w = 0; w < 4; w++) x[w] = add_pk(x[w], ((bits >> (w / H)) & 1u) ? t[w] : 0u);
-      };
-      for (int k = 0; k < L - 2; k++) add_node(rec[12 + k], anc);
-      const int nsib = rec[0], ls0 = rec[11];
-      const int v0 = rec[1], v1 = rec[2], v2 = rec[3], v3 = rec[4];
-      // sibling i of the run: its leaf row plus the ancestors
-      auto leaf = [&](int i, uint32_t x[4]) -> int16_t * {
-#pragma unroll
-        for (int w = 0; w < 4; w++) x[w] = anc[w];
-        add_node(ls0 + i, x);
-        const uint32_t vi = (uint32_t)(i == 0 ? v0 : (i == 1 ? v1 : (i == 2 ? v2 : v3)));
-        return a.out + ((uint64_t)vi * vstride + lane_off);
-      };
-      // two loops, so that the 16-byte stores stay whole
-      if (wide) {
-        for (int i = so; i < nsib; i += SPP) {
-          uint32_t x[4];
-          int16_t *dst = leaf(i, x);
-          *reinterpret_cast<uint4 *>(dst) = make_uint4(x[0], x[1], x[2], x[3]);
-        }
-      } else if (nact > 0) {
-        for (int i = so; i < nsib; i += SPP) {
-          uint32_t x[4];
-          int16_t *dst = leaf(i, x);
-#pragma unroll
-          for (int k = 0; k < PB; k++)
-            if (k < nact) store_row<B>(dst + k * B, x + k * H);
-        }
-      }
-    }
-    __syncthreads();
+    if (tier == 1u)
+      lf_chunk<B>(a, stage + sched_at + stage[sched_at + ci], cr.nn, cr.q0, cr.nq, stage, s_wo, tile, keys, lut, tid,
+                  wave, lane, so, y, jq, bx0, nact, wide, lane_off, vstride);
+    else if (tier == 2u)
+      lf_chunk<B>(a, stage + stage[ci], cr.nn, cr.q0, cr.nq, a.srv, s_o0, tile, keys, lut, tid, wave, lane, so, y, jq,
+                  bx0, nact, wide, lane_off, vstride);
+    else
+      lf_chunk<B>(a, gsched + gsched[ci], cr.nn, cr.q0, cr.nq, a.srv, s_o0, tile, keys, lut, tid, wave, lane, so, y,
+                  jq, bx0, nact, wide, lane_off, vstride);
   }
 }
 
@@ -1037,21 +927,20 @@ int max_lds_bytes() {
 }
 
 // LDS of the whole-field kernel: the fixed part (LUT and extents, residual
-// tile, block lists) plus staging for the strip's groups with their directory
-// rows and entries, up to 80 KB so that two workgroups share a compute unit.
+// tile, key-view rows) plus staging for the strip's groups and decode
+// schedule, up to 80 KB so that two workgroups share a compute unit.
 template <int B>
 lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s) {
   const lfc::Geometry &g = lf->geo;
-  constexpr int NBLK = 64 / B, NODE_WORDS = B * NBLK * (B / 2);
+  constexpr int NBLK = 64 / B;
   const int64_t nodes = std::max(lf->max_chunk_nodes, 1);
   // key-view rows of a strip, when they take at most 16 KB
   const int64_t key_words = (int64_t)g.n_top * NBLK * (B * B / 2) <= 4096 ? (int64_t)g.n_top * NBLK * (B * B / 2) : 0;
-  const int64_t items = nodes * NBLK;
   if ((int64_t)3 * g.hp * g.wp >= ((int64_t)1 << 32))
     return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: view too large for the whole-field kernel");
-  if (items > (int64_t)kListIters<B> * kLFThreads)
-    return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: chunk larger than the whole-field kernel lists");
-  const int64_t fixed = kLFHeadWords + nodes * NODE_WORDS + items + ((items + 7) / 8) * 4 + key_words + lf->n_nmap;
+  if (nodes > 256 / B)
+    return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: chunk larger than the whole-field kernel's tile");
+  const int64_t fixed = kLFHeadWords + nodes * B * 32 + key_words;
   const int64_t limit = max_lds_bytes() / 4;
   if (fixed > limit)
     return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: tree too large for the whole-field kernel; use BLOCKS layout");
@@ -1059,9 +948,9 @@ lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s) {
   int64_t cap = std::min<int64_t>(target - fixed, (int64_t)lf->max_strip_words + kStagePad);
   if (const char *e = getenv("LFC_STAGE_CAP_WORDS")) cap = std::min<int64_t>(cap, std::max(0, atoi(e)));
   const size_t lds = 4 * (size_t)(fixed + cap);
-  LFArgs a{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_dbase, lf->d_poff, lf->d_pbase, lf->d_batch, lf->d_chunk, lf->d_nmap, out,
-           g.nbx, g.n_srv, g.nbw, g.nv(), g.L, g.q, g.wp, g.hp, g.nb, lf->n_batch, lf->n_chunk, (int)nodes, (int)cap,
-           (int)(g.wp % 8 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0), g.n_top, (int)key_words, lf->n_nmap};
+  LFArgs a{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_sched, lf->d_strip_off, lf->d_batch, lf->d_chunk, out,
+           g.nbx, g.nv(), g.L, g.q, g.wp, g.hp, g.nb, lf->n_batch, lf->n_chunk, (int)nodes, (int)cap,
+           (int)(g.wp % 8 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0), g.n_top, (int)key_words};
   dim3 grid((g.nbx + NBLK - 1) / NBLK, g.nby, 3);
   hipLaunchKernelGGL(k_decode_lf<B>, grid, dim3(kLFThreads), lds, s, a);
   return launched("lfc_decode_blocks");

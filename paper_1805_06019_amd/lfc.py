@@ -128,6 +128,8 @@ def load() -> C.CDLL:
         L.lfc_info.argtypes = [vp, C.POINTER(c_info)]
         L.lfc_decode_blocks.argtypes = [vp, vp, i64, i32, vp, vp]
         L.lfc_decode_progressive.argtypes = [vp, vp, i64, i32, vp, vp]
+        L.lfc_stage_needs.argtypes = [vp, vp, i64]
+        L.lfc_stage_needs.restype = i64
         L.lfc_render_views.argtypes = [vp, vp, i32, i32, i32, vp, vp]
         L.lfc_check.argtypes = [vp, vp]
         L.lfc_close.argtypes = [vp]
@@ -263,6 +265,18 @@ def lfc_decode_blocks(lf: LightField, req=None, layout: int = LAYOUT_BLOCKS, out
     assert out.dtype == torch.int16 and out.is_cuda and out.is_contiguous() and tuple(out.shape) == shape
     _check(load().lfc_decode_blocks(lf.handle, req.data_ptr() if req is not None else None, n, layout,
                                     out.data_ptr(), _stream_ptr(cuda_stream)))
+    return out
+
+
+def lfc_stage_needs(lf: LightField) -> np.ndarray:
+    """LDS words each strip of the whole-field decode needs: [strips][2] =
+    (groups + schedule, schedule alone)."""
+    L = load()
+    n = L.lfc_stage_needs(lf.handle, None, 0)
+    if n < 0:
+        _check(int(n))
+    out = np.zeros((n, 2), dtype=np.uint32)
+    L.lfc_stage_needs(lf.handle, out.ctypes.data, n)
     return out
 
 

@@ -16,7 +16,7 @@ import pytest
 import torch
 
 import oracle
-from helpers import blocks_of, make_lf, oracle_encode, say, strip_stage_words
+from helpers import blocks_of, make_lf, oracle_encode, say
 from paper_1805_06019_amd import lfc, synth
 from paper_1805_06019_amd.workloads import WORKLOADS
 
@@ -64,12 +64,14 @@ def test_whole_field_images_layout(gpu, case):
 def test_whole_field_staging_tiers(gpu, case, tiers, monkeypatch):
     # LFC_STAGE_CAP_WORDS bounds the LDS the whole-field kernel may use to
     # stage a strip: 0 reads everything from global memory; a cap that holds
-    # bitmaps and directory but not the payload of most strips stages those
+    # the schedule but not the payload of most strips stages the schedule
     # only; the median strip's full need mixes the tiers in one launch
     U, V, W, H, kw = case
     rgb = make_lf(U, V, W, H, seed=U * 13 + W)
     enc = oracle_encode(rgb, **kw)
-    t1, t2 = strip_stage_words(enc.stream, oracle.Params(grid_u=U, grid_v=V, width=W, height=H, **kw))
+    lf = gpu_open(enc.stream)
+    need = lfc.lfc_stage_needs(lf).astype(np.int64)
+    t1, t2 = need[:, 0] + 8, need[:, 1]
     if tiers == "global":
         cap = 0
     elif tiers == "no-payload":
@@ -79,7 +81,6 @@ def test_whole_field_staging_tiers(gpu, case, tiers, monkeypatch):
     else:
         cap = int(np.median(t1))
     say("images staging", case, tiers, cap)
-    lf = gpu_open(enc.stream)
     monkeypatch.setenv("LFC_STAGE_CAP_WORDS", str(cap))
     got = lfc.lfc_decode_blocks(lf, None, lfc.LAYOUT_IMAGES).cpu().numpy()
     assert np.array_equal(got, enc.r0)
