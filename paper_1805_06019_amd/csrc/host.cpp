@@ -912,7 +912,25 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
   } catch (const std::bad_alloc &) {
     return fail(LFC_E_NOMEM, "lfc_open: out of host memory");
   }
-  Part parts[13] = {
+  // the whole-field kernel takes strips costliest first (staged words as the
+  // cost), so that short strips fill the tail of the launch
+  std::vector<uint32_t> order(strip_off.size() - 1);
+  for (size_t i = 0; i < order.size(); i++) order[i] = (uint32_t)i;
+  {
+    const int nblk = 64 / ps.g.B, nsx = (ps.g.nbx + nblk - 1) / nblk;
+    std::vector<uint64_t> cost(order.size());
+    for (size_t st = 0; st < order.size(); st++) {
+      const int sx = (int)(st % nsx), by = (int)((st / nsx) % ps.g.nby), c = (int)(st / ((size_t)nsx * ps.g.nby));
+      uint64_t w = strip_off[st + 1] - strip_off[st];
+      for (int bx = sx * nblk; bx < std::min(sx * nblk + nblk, ps.g.nbx); bx++) {
+        const size_t gi = 3 * ((size_t)by * ps.g.nbx + bx) + c;
+        w += ps.off[gi + 1] - ps.off[gi];
+      }
+      cost[st] = w;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
+  }
+  Part parts[14] = {
       {ps.rkv, ps.rkv_bytes, 0},
       {ps.off.data(), ps.off.size() * 4, 0},
       {ps.srv.data(), ps.srv.size() * 4, 0},
@@ -926,6 +944,7 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
       {ps.pbase.data(), ps.pbase.size() * 4, 0},
       {sched.data(), sched.size() * 4, 0},
       {strip_off.data(), strip_off.size() * 4, 0},
+      {order.data(), order.size() * 4, 0},
   };
   size_t total = 0;
   for (auto &pt : parts) {
@@ -977,6 +996,7 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
   lf->d_pbase = reinterpret_cast<const uint32_t *>(d + parts[10].at);
   lf->d_sched = reinterpret_cast<const uint32_t *>(d + parts[11].at);
   lf->d_strip_off = reinterpret_cast<const uint32_t *>(d + parts[12].at);
+  lf->d_order = reinterpret_cast<const uint32_t *>(d + parts[13].at);
   lf->n_chunk = (int)(chunks.size() / kChunkWords);
   for (int i = 0; i < lf->n_chunk; i++) lf->max_chunk_nodes = std::max(lf->max_chunk_nodes, chunks[(size_t)i * kChunkWords + 2]);
   lf->d_err = reinterpret_cast<int32_t *>(d + parts[8].at);

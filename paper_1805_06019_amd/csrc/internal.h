@@ -88,6 +88,7 @@ struct lfc_lf {
   const int32_t *d_chunk = nullptr;  // [n_chunk][kChunkWords]
   const uint32_t *d_sched = nullptr;     // decode schedule of the whole-field kernel (strip records)
   const uint32_t *d_strip_off = nullptr; // [n_strips+1] word offset of each strip's record
+  const uint32_t *d_order = nullptr;     // [n_strips] strips in the order the whole-field kernel takes them
   int n_chunk = 0, max_chunk_nodes = 0;
   int32_t *d_err = nullptr;          // device error flag
   uint32_t max_strip_words = 0;      // largest group words + decode schedule of a strip of 64/B blocks of

@@ -246,6 +246,7 @@ struct LFArgs {
   const uint32_t *srv;
   const uint32_t *sched;      // decode schedule: one record per strip (see build_schedule on the host)
   const uint32_t *strip_off;  // [n_strips+1] word offset of each strip's record
+  const uint32_t *order;      // [n_strips] strip of each workgroup, costliest first
   const int32_t *batch;       // [nbatch][kBatchWords] runs of sibling leaves (see internal.h)
   const int32_t *chunk;       // [nchunk][kChunkWords] runs of batches decoded together
   int16_t *out;               // [nv][3][hp][wp]
@@ -361,7 +362,7 @@ __device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, i
                                          const uint32_t *pw, const uint32_t *s_po, uint32_t *tile,
                                          const uint32_t *keys, const uint16_t *lut, int tid, int wave, int lane,
                                          int so, int y, int jq, int bx0, int nact, bool wide, uint64_t lane_off,
-                                         uint32_t vstride) {
+                                         uint32_t vstride, int by, int c) {
   constexpr int S = B * B, NBLK = 64 / B, H = B / 2, PB = 8 / B, SPP = 64 / (8 * B);
   const uint32_t n0 = sch[0], n01 = sch[1], n = sch[2];
   const uint32_t *masks = sch + 3;
@@ -383,9 +384,10 @@ __device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, i
   }
   __syncthreads();
   // (4) gather and store, waves splitting the chunk's runs
-  const int by = blockIdx.y, c = blockIdx.z, L = a.L;
+  const int L = a.L;
   int root_cached = -1;                      // key-view row read from global memory (keys not staged)
   uint4 key = make_uint4(0u, 0u, 0u, 0u);
+  // waves take consecutive runs of the chunk
   const int per = (nq + kLFWaves - 1) / kLFWaves;
   for (int qb = q0 + wave * per; qb < q0 + min(nq, wave * per + per); qb++) {
     const uniform_i32 rec = as_uniform(a.batch + (size_t)qb * lfc::kBatchWords);
@@ -474,14 +476,17 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
   uint32_t *stage = keys + a.key_words;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int st = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  // the workgroup's strip (strips are taken costliest first, so the last
+  // workgroups to start are short ones)
+  const int st = (int)a.order[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x];
+  const int sx = st % (int)gridDim.x, by = (st / (int)gridDim.x) % (int)gridDim.y, c = st / ((int)gridDim.x * (int)gridDim.y);
   const uint32_t sched0 = a.strip_off[st], sched_len = a.strip_off[st + 1] - sched0;
   for (int t = tid; t < kLutEntries; t += kLFThreads) lut[t] = lut_entry(t);
   if (tid < NBLK) {
-    const int bx = blockIdx.x * NBLK + tid;
+    const int bx = sx * NBLK + tid;
     uint32_t o0 = 0, o1 = 0;
     if (bx < a.nbx) {
-      const int g = 3 * (blockIdx.y * a.nbx + bx) + blockIdx.z;
+      const int g = 3 * (by * a.nbx + bx) + c;
       o0 = a.off[g];
       o1 = a.off[g + 1];
     }
@@ -519,11 +524,11 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
     const uint32_t *rk = reinterpret_cast<const uint32_t *>(a.rkv);
     for (int t0 = wave * 64; t0 < a.key_words; t0 += kLFThreads) {
       const int t = t0 + lane, h = t % H, j = (t / H) % NBLK, y = (t / (H * NBLK)) % B, r = t / (H * NBLK * B);
-      const int bx = blockIdx.x * NBLK + j;
+      const int bx = sx * NBLK + j;
       if (t < a.key_words && bx < a.nbx)
         __builtin_amdgcn_global_load_lds(
-            (const __attribute__((address_space(1))) void *)(rk + ((size_t)(r * a.nb + blockIdx.y * a.nbx + bx) * 3 +
-                                                                   blockIdx.z) * (S / 2) + y * H + h),
+            (const __attribute__((address_space(1))) void *)(rk + ((size_t)(r * a.nb + by * a.nbx + bx) * 3 + c) *
+                                                                  (S / 2) + y * H + h),
             (__attribute__((address_space(3))) void *)(keys + t0), 4, 0, 0);
     }
   }
@@ -531,12 +536,11 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
   if (tier == 1u && tid < kStagePad) stage[s_cnt[1] + tid] = 0;
   __syncthreads();
 
-  const int by = blockIdx.y, c = blockIdx.z;
   const uint32_t vstride = 3u * (uint32_t)a.hp * (uint32_t)a.wp;
   const uint64_t cplane = (uint64_t)c * a.hp * a.wp;
   if (a.L == 1) {
     // no residual levels: every view is a stored key view
-    const int j = lane % NBLK, y = lane / NBLK, bx = blockIdx.x * NBLK + j;
+    const int j = lane % NBLK, y = lane / NBLK, bx = sx * NBLK + j;
     if (bx >= a.nbx) return;
     const int b = by * a.nbx + bx;
     const int per = (a.nbatch + kLFWaves - 1) / kLFWaves;
@@ -550,7 +554,7 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
   }
   // store-side lane mapping: sibling slot, row, segment of PB blocks
   const int so = lane / LPS, r = lane % LPS, y = r / 8, jq = r % 8;
-  const int bx0 = blockIdx.x * NBLK + jq * PB;
+  const int bx0 = sx * NBLK + jq * PB;
   const int nact = max(0, min(PB, a.nbx - bx0));       // blocks of the segment inside the image
   const bool wide = nact == PB && a.vec_store;          // a 16-byte store is aligned
   const uint64_t lane_off = cplane + (uint64_t)(by * B + y) * a.wp + (uint64_t)bx0 * B;
@@ -559,13 +563,13 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
     const ChunkRec cr = read_chunk(a.chunk, ci);
     if (tier == 1u)
       lf_chunk<B>(a, stage + sched_at + stage[sched_at + ci], cr.nn, cr.q0, cr.nq, stage, s_wo, tile, keys, lut, tid,
-                  wave, lane, so, y, jq, bx0, nact, wide, lane_off, vstride);
+                  wave, lane, so, y, jq, bx0, nact, wide, lane_off, vstride, by, c);
     else if (tier == 2u)
       lf_chunk<B>(a, stage + stage[ci], cr.nn, cr.q0, cr.nq, a.srv, s_o0, tile, keys, lut, tid, wave, lane, so, y, jq,
-                  bx0, nact, wide, lane_off, vstride);
+                  bx0, nact, wide, lane_off, vstride, by, c);
     else
       lf_chunk<B>(a, gsched + gsched[ci], cr.nn, cr.q0, cr.nq, a.srv, s_o0, tile, keys, lut, tid, wave, lane, so, y,
-                  jq, bx0, nact, wide, lane_off, vstride);
+                  jq, bx0, nact, wide, lane_off, vstride, by, c);
   }
 }
 
@@ -948,7 +952,7 @@ lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s) {
   int64_t cap = std::min<int64_t>(target - fixed, (int64_t)lf->max_strip_words + kStagePad);
   if (const char *e = getenv("LFC_STAGE_CAP_WORDS")) cap = std::min<int64_t>(cap, std::max(0, atoi(e)));
   const size_t lds = 4 * (size_t)(fixed + cap);
-  LFArgs a{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_sched, lf->d_strip_off, lf->d_batch, lf->d_chunk, out,
+  LFArgs a{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_sched, lf->d_strip_off, lf->d_order, lf->d_batch, lf->d_chunk, out,
            g.nbx, g.nv(), g.L, g.q, g.wp, g.hp, g.nb, lf->n_batch, lf->n_chunk, (int)nodes, (int)cap,
            (int)(g.wp % 8 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0), g.n_top, (int)key_words};
   dim3 grid((g.nbx + NBLK - 1) / NBLK, g.nby, 3);
