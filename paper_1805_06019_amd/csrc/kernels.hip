@@ -708,6 +708,34 @@ __device__ __forceinline__ uint32_t locate(const RAArgs &a, int g, int s, const 
 // whose path passes through that node (neighbouring views often share
 // ancestors).  The sums are converted to RGB (inverse YCoCg-R, clamped) in
 // place, then every output pixel interpolates its 16 taps in FP32.
+// Inverse YCoCg-R (Sec. 4) of one sample, clamped to 8 bits, packed R | G << 8 | B << 16.
+__device__ __forceinline__ uint32_t rgb_pack(int32_t yv, int32_t co, int32_t cg) {
+  const int32_t t = yv - (cg >> 1);
+  const int32_t G = cg + t;
+  const int32_t Bc = t - (co >> 1);
+  const int32_t R = Bc + co;
+  return (uint32_t)min(max(R, 0), 255) | ((uint32_t)min(max(G, 0), 255) << 8) | ((uint32_t)min(max(Bc, 0), 255) << 16);
+}
+
+// The quadrilinear interpolation of one output pixel from its 16 taps
+// P[k][0..3] = (y0,x0), (y0,x1), (y1,x0), (y1,x1) of view k = 0: (u0, v0),
+// 1: (u1, v0), 2: (u0, v1), 3: (u1, v1); lerps in s, t, v, u order.
+__device__ __forceinline__ void interp_store(const uint32_t P[4][4], float fs, float ft, float fu, float fv, float *o,
+                                             size_t plane) {
+#pragma unroll
+  for (int ch = 0; ch < 3; ch++) {
+    float lt[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const float p00 = (float)((P[k][0] >> (8 * ch)) & 255u), p01 = (float)((P[k][1] >> (8 * ch)) & 255u);
+      const float p10 = (float)((P[k][2] >> (8 * ch)) & 255u), p11 = (float)((P[k][3] >> (8 * ch)) & 255u);
+      lt[k] = lerpf(lerpf(p00, p01, fs), lerpf(p10, p11, fs), ft);
+    }
+    const float lv0 = lerpf(lt[0], lt[2], fv), lv1 = lerpf(lt[1], lt[3], fv);
+    o[ch * plane] = lerpf(lv0, lv1, fu) / 255.0f;
+  }
+}
+
 // One output tile (tile column tbx, tile row tby) of view vw into outn
 // ([3][ho][wo] floats); smem holds the LUT and the footprint accumulators.
 template <int B>
@@ -798,13 +826,7 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const lfc_view 
       const int32_t yv = (i & 1) ? hi16(v[i / 2]) : lo16(v[i / 2]);
       const int32_t co = (i & 1) ? hi16(v[S / 2 + i / 2]) : lo16(v[S / 2 + i / 2]);
       const int32_t cg = (i & 1) ? hi16(v[S + i / 2]) : lo16(v[S + i / 2]);
-      // inverse YCoCg-R (Sec. 4), clamped to 8 bits
-      const int32_t t = yv - (cg >> 1);
-      const int32_t G = cg + t;
-      const int32_t Bc = t - (co >> 1);
-      const int32_t R = Bc + co;
-      slot[i] = (uint32_t)min(max(R, 0), 255) | ((uint32_t)min(max(G, 0), 255) << 8) |
-                ((uint32_t)min(max(Bc, 0), 255) << 16);
+      slot[i] = rgb_pack(yv, co, cg);
     }
   }
   __syncthreads();
@@ -835,20 +857,48 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const lfc_view 
       P[k][2] = img[i10];
       P[k][3] = img[i11];
     }
-#pragma unroll
-    for (int ch = 0; ch < 3; ch++) {
-      float lt[4];
-#pragma unroll
-      for (int k = 0; k < 4; k++) {
-        const float p00 = (float)((P[k][0] >> (8 * ch)) & 255u), p01 = (float)((P[k][1] >> (8 * ch)) & 255u);
-        const float p10 = (float)((P[k][2] >> (8 * ch)) & 255u), p11 = (float)((P[k][3] >> (8 * ch)) & 255u);
-        lt[k] = lerpf(lerpf(p00, p01, fs), lerpf(p10, p11, fs), ft);
-      }
-      // k = 0: (u0, v0), 1: (u1, v0), 2: (u0, v1), 3: (u1, v1)
-      const float lv0 = lerpf(lt[0], lt[2], fv), lv1 = lerpf(lt[1], lt[3], fv);
-      outn[ch * plane + (size_t)Yp * a.wo + X] = lerpf(lv0, lv1, fu) / 255.0f;
-    }
+    interp_store(P, fs, ft, fu, fv, outn + (size_t)Yp * a.wo + X, plane);
   }
+}
+
+// Novel views from fully decoded source views (images layout, int16
+// YCoCg-R [nv][3][hp][wp]): one thread per output pixel, its 16 taps read
+// straight from the decoded planes, the same colour conversion and lerps as
+// render_tile.  Used when a batch of views needs about as many source blocks
+// as the whole light field holds.
+struct InterpArgs {
+  const int16_t *dec;
+  const lfc_view *views;
+  float *out;
+  int wo, ho, U, V, W, H, wp, hp;
+};
+
+__global__ __launch_bounds__(kThreads) void k_interp(InterpArgs a) {
+  const int X = blockIdx.x * kThreads + threadIdx.x, Yp = blockIdx.y, n = blockIdx.z;
+  if (X >= a.wo) return;
+  const lfc_view vw = a.views[n];
+  int iu0, iu1, jv0, jv1, x0, x1, y0, y1;
+  float fu, fv, fs, ft;
+  cell(vw.u, a.U, iu0, iu1, fu);
+  cell(vw.v, a.V, jv0, jv1, fv);
+  const float sxs = (float)a.W / (float)a.wo, tys = (float)a.H / (float)a.ho;
+  cell(vw.s + ((float)X + 0.5f) * sxs - 0.5f, a.W, x0, x1, fs);
+  cell(vw.t + ((float)Yp + 0.5f) * tys - 0.5f, a.H, y0, y1, ft);
+  const int vis[4] = {jv0 * a.U + iu0, jv0 * a.U + iu1, jv1 * a.U + iu0, jv1 * a.U + iu1};
+  const size_t cplane = (size_t)a.hp * a.wp;
+  const size_t o00 = (size_t)y0 * a.wp + x0, o01 = (size_t)y0 * a.wp + x1;
+  const size_t o10 = (size_t)y1 * a.wp + x0, o11 = (size_t)y1 * a.wp + x1;
+  uint32_t P[4][4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int16_t *yp = a.dec + (size_t)vis[k] * 3 * cplane, *cop = yp + cplane, *cgp = cop + cplane;
+    P[k][0] = rgb_pack(yp[o00], cop[o00], cgp[o00]);
+    P[k][1] = rgb_pack(yp[o01], cop[o01], cgp[o01]);
+    P[k][2] = rgb_pack(yp[o10], cop[o10], cgp[o10]);
+    P[k][3] = rgb_pack(yp[o11], cop[o11], cgp[o11]);
+  }
+  const size_t plane = (size_t)a.ho * a.wo;
+  interp_store(P, fs, ft, fu, fv, a.out + (size_t)n * 3 * plane + (size_t)Yp * a.wo + X, plane);
 }
 
 template <int B>
@@ -999,10 +1049,38 @@ bool plan_render(const lfc::Geometry &g, int wo, int ho, RenderPlan &pl) {
   }
 }
 
+// Decoding every source view once and interpolating from the decoded planes
+// pays off when the batch's footprints together cover about as many blocks as
+// the light field holds: each output pixel reads four views, and the
+// whole-field decode is several times cheaper per block than decoding tile
+// footprints.  LFC_RENDER_PATH=tiles|decoded overrides the choice.
+bool render_decoded(const lfc::Geometry &g, int32_t n, int32_t wo, int32_t ho) {
+  if (const char *e = getenv("LFC_RENDER_PATH")) {
+    if (!strcmp(e, "tiles")) return false;
+    if (!strcmp(e, "decoded")) return true;
+  }
+  return 20.0 * n * wo * ho >= (double)g.nv() * g.hp * g.wp;
+}
+
 template <int B>
 lfc_status render(const lfc_lf *lf, const lfc_view *views, int32_t n, int32_t wo, int32_t ho, float *out,
                   hipStream_t s) {
   const lfc::Geometry &g = lf->geo;
+  if (render_decoded(g, n, wo, ho)) {
+    // stream-ordered scratch for the decoded views (served from the pool after the first call)
+    int16_t *dec = nullptr;
+    const size_t bytes = (size_t)g.nv() * 3 * g.hp * g.wp * sizeof(int16_t);
+    if (hipMallocAsync(reinterpret_cast<void **>(&dec), bytes, s) != hipSuccess)
+      return fail(LFC_E_NOMEM, "lfc_render_views: scratch for the decoded views");
+    lfc_status st = decode_images<B>(lf, dec, s);
+    if (st == LFC_OK) {
+      InterpArgs ia{dec, views, out, wo, ho, g.U, g.V, g.W, g.H, g.wp, g.hp};
+      hipLaunchKernelGGL(k_interp, dim3((wo + kThreads - 1) / kThreads, ho, n), dim3(kThreads), 0, s, ia);
+      st = launched("lfc_render_views");
+    }
+    if (hipFreeAsync(dec, s) != hipSuccess && st == LFC_OK) st = fail(LFC_E_HIP, "lfc_render_views: scratch release");
+    return st;
+  }
   RenderPlan pl;
   if (!plan_render(g, wo, ho, pl))
     return fail(LFC_E_UNSUPPORTED, "lfc_render_views: output too strongly minified for the tile footprint");

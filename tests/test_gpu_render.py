@@ -3,6 +3,8 @@ oracle's renderer run on the oracle's decoded light field.
 
 The bar is a maximum absolute error of 1e-5 on RGB/255 outputs: the GPU may
 contract multiply-adds, the oracle evaluates every lerp in source order.
+Both renderers are covered (footprint decode per output tile, and whole-field
+decode followed by per-pixel interpolation) and must agree bit for bit.
 Covers magnification and minification (down to one output pixel), ragged tiles, block sizes 2/4/8, a
 single-row camera grid, a single view, cameras outside the grid, and the
 batched render workload (64 novel 512x512 views per launch on the 8x8x64x64
@@ -46,10 +48,14 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("path", ["tiles", "decoded"])
 @pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}x{c[2]}x{c[3]}-to-{c[5]}x{c[6]}" for c in CASES])
-def test_render_matches_oracle(gpu, case):
+def test_render_matches_oracle(gpu, case, path, monkeypatch):
+    # both renderers: footprint decode per output tile, and whole-field decode
+    # followed by per-pixel interpolation (chosen by batch size unless forced)
     U, V, W, H, kw, wo, ho, pan = case
-    say("render", case)
+    monkeypatch.setenv("LFC_RENDER_PATH", path)
+    say("render", case, path)
     rgb = make_lf(U, V, W, H, seed=U * 19 + W)
     enc = oracle_encode(rgb, **kw)
     views = synth.novel_views(6, U, V, seed=W + wo, pan=pan)
@@ -111,3 +117,17 @@ def test_batched_render_workload(gpu, name):
     views = synth.novel_views(64, s.grid_u, s.grid_v, seed=302)
     got, ref = render_both(enc, s.grid_u, s.grid_v, s.width, s.height, views, 512, 512)
     assert max_abs(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("case", CASES[:5], ids=[f"{c[0]}x{c[1]}x{c[2]}x{c[3]}-to-{c[5]}x{c[6]}" for c in CASES[:5]])
+def test_render_paths_are_bit_identical(gpu, case, monkeypatch):
+    U, V, W, H, kw, wo, ho, pan = case
+    rgb = make_lf(U, V, W, H, seed=U * 19 + W)
+    enc = oracle_encode(rgb, **kw)
+    lf = lfc.lfc_open(enc.stream)
+    views = torch.from_numpy(synth.novel_views(9, U, V, seed=W + 7, pan=pan)).cuda()
+    outs = []
+    for path in ("tiles", "decoded"):
+        monkeypatch.setenv("LFC_RENDER_PATH", path)
+        outs.append(lfc.lfc_render_views(lf, views, wo, ho))
+    assert torch.equal(outs[0], outs[1])
