@@ -253,6 +253,23 @@ lfc_status lfc_batch_create(lfc_batch **out);
 lfc_status lfc_batch_render(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf, const lfc_render_request *reqs,
                             int32_t n, float *const *d_outs, hipStream_t s);
 
+/*
+ * Random access (DecompressLFIBlock, Alg. 2) over several light fields in one
+ * launch: request i = d_req[3i..3i+2] = (index into lfs, view, block), every
+ * light field of the call with the same block size B.  d_out is int16
+ * [n][3][B][B] (16-byte aligned), as lfc_decode_blocks with LFC_LAYOUT_BLOCKS.
+ * Out-of-range requests yield zeros and raise the batch's error flag, read by
+ * lfc_batch_check.  The light-field table shares the request-table staging
+ * of lfc_batch_render.  Errors: LFC_E_INVALID, LFC_E_UNSUPPORTED (mixed block
+ * sizes), LFC_E_NOMEM, LFC_E_HIP.
+ */
+lfc_status lfc_batch_decode(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf, const int32_t *d_req, int64_t n,
+                            int16_t *d_out, hipStream_t s);
+
+/* Waits for stream s, then reads and clears the batch's error flag
+ * (LFC_E_INVALID if a batched decode saw an out-of-range request). */
+lfc_status lfc_batch_check(lfc_batch *b, hipStream_t s);
+
 /* Waits for the context's work and frees it.  NULL is ignored. */
 lfc_status lfc_batch_destroy(lfc_batch *b);
 

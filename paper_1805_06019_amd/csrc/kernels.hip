@@ -658,6 +658,43 @@ __global__ __launch_bounds__(kThreads) void k_decode_blocks(BlocksArgs a) {
   store_row<B>(a.out + ((size_t)r * 3 + c) * S + y * B, x);
 }
 
+// Random access over many light fields of one block size in one launch:
+// request r = (light field, view, block) indexes a table of the light
+// fields' device tables; otherwise as k_decode_blocks.
+struct MultiArgs {
+  const RAArgs *lfs;
+  int32_t n_lf;
+  const int32_t *req;  // [n][3]
+  int16_t *out;        // [n][3][S]
+  int32_t *err;
+  int64_t n;
+};
+
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_decode_multi(MultiArgs a) {
+  constexpr int S = B * B, LPR = 3 * B, RPW = 64 / LPR;
+  __shared__ uint16_t lut[kLutEntries];
+  for (int t = threadIdx.x; t < kLutEntries; t += kThreads) lut[t] = lut_entry(t);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
+  const int slot = lane / LPR, sub = lane % LPR;
+  if (slot >= RPW) return;
+  const int64_t r = wave * RPW + slot;
+  if (r >= a.n) return;
+  const int c = sub / B, y = sub % B;
+  const int li = a.req[3 * r], vi = a.req[3 * r + 1], b = a.req[3 * r + 2];
+  uint32_t x[B / 2];
+  if (li < 0 || li >= a.n_lf || vi < 0 || vi >= a.lfs[li].nv || b < 0 || b >= a.lfs[li].nb) {
+    if (sub == 0) atomicOr(a.err, 1);
+#pragma unroll
+    for (int i = 0; i < B / 2; i++) x[i] = 0;
+  } else {
+    gather_row<B>(a.lfs[li], vi, b, c, y, 0, digit_plan<B>(y, true), digit_plan<B>(y, false), lut, x);
+  }
+  store_row<B>(a.out + ((size_t)r * 3 + c) * S + y * B, x);
+}
+
 // ---------------------------------------------------------------------------
 // novel views: footprint decode into LDS, then quadrilinear interpolation
 // ---------------------------------------------------------------------------
@@ -1165,6 +1202,31 @@ extern "C" lfc_status lfc_render_views(const lfc_lf *lf, const lfc_view *d_views
 namespace lfc {
 
 size_t render_req_bytes() { return sizeof(RenderReq); }
+
+size_t lf_table_bytes() { return sizeof(RAArgs); }
+
+int lf_block(const lfc_lf *lf) { return lf->geo.B; }
+
+void lf_table_fill(const lfc_lf *lf, void *dst) {
+  const RAArgs r = ra_args(lf);
+  std::memcpy(dst, &r, sizeof r);
+}
+
+lfc_status decode_multi_launch(int block, const void *d_lfs, int n_lf, const int32_t *d_req, int64_t n, int16_t *out,
+                               int32_t *err, hipStream_t s) {
+  if (n <= 0) return LFC_OK;
+  MultiArgs a{static_cast<const RAArgs *>(d_lfs), n_lf, d_req, out, err, n};
+  const int rpw = 64 / (3 * block);
+  const int64_t waves = (n + rpw - 1) / rpw;
+  const int64_t blocks = (waves + kThreads / 64 - 1) / (kThreads / 64);
+  if (blocks > 0x7FFFFFFF) return fail(LFC_E_INVALID, "lfc_batch_decode: too many requests");
+  switch (block) {
+    case 2: hipLaunchKernelGGL(k_decode_multi<2>, dim3((unsigned)blocks), dim3(kThreads), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_decode_multi<4>, dim3((unsigned)blocks), dim3(kThreads), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_decode_multi<8>, dim3((unsigned)blocks), dim3(kThreads), 0, s, a); break;
+  }
+  return launched("lfc_batch_decode");
+}
 
 int lf_device(const lfc_lf *lf) { return lf->device; }
 

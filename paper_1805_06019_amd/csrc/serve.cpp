@@ -43,6 +43,7 @@ struct lfc_batch {
   int device = 0;
   Slot slot[kSlots];
   int next = 0;
+  int32_t *d_err = nullptr;   // set by a batched decode that saw an out-of-range request
 };
 
 namespace {
@@ -90,6 +91,11 @@ extern "C" lfc_status lfc_batch_create(lfc_batch **out) {
       return fail(LFC_E_HIP, "lfc_batch_create: event");
     }
   }
+  if (hipMalloc(reinterpret_cast<void **>(&b->d_err), sizeof(int32_t)) != hipSuccess ||
+      hipMemset(b->d_err, 0, sizeof(int32_t)) != hipSuccess) {
+    (void)lfc_batch_destroy(b);
+    return fail(LFC_E_NOMEM, "lfc_batch_create: error flag");
+  }
   *out = b;
   return LFC_OK;
 }
@@ -103,6 +109,7 @@ extern "C" lfc_status lfc_batch_destroy(lfc_batch *b) {
     }
     free_slot(sl);
   }
+  if (b->d_err) (void)hipFree(b->d_err);
   delete b;
   return LFC_OK;
 }
@@ -172,6 +179,48 @@ extern "C" lfc_status lfc_batch_render(lfc_batch *b, const lfc_lf *const *lfs, i
       return st;
     at += gp.count;
   }
+  return LFC_OK;
+}
+
+extern "C" lfc_status lfc_batch_decode(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf, const int32_t *d_req,
+                                       int64_t n, int16_t *d_out, hipStream_t s) {
+  if (!b) return fail(LFC_E_INVALID, "lfc_batch_decode: null batch");
+  if (n < 0) return fail(LFC_E_INVALID, "lfc_batch_decode: n < 0");
+  if (n == 0) return LFC_OK;
+  if (!lfs || n_lf < 1 || !d_req || !d_out) return fail(LFC_E_INVALID, "lfc_batch_decode: null argument");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
+    return fail(LFC_E_INVALID, "lfc_batch_decode: the current device is not the batch's");
+  int block = 0;
+  for (int i = 0; i < n_lf; i++) {
+    if (!lfs[i] || lfc::lf_device(lfs[i]) != dev)
+      return fail(LFC_E_INVALID, "lfc_batch_decode: null handle or handle of another device");
+    if (i == 0) block = lfc::lf_block(lfs[i]);
+    else if (lfc::lf_block(lfs[i]) != block)
+      return fail(LFC_E_UNSUPPORTED, "lfc_batch_decode: the light fields of one call must share the block size");
+  }
+  if (reinterpret_cast<uintptr_t>(d_req) % 4 || reinterpret_cast<uintptr_t>(d_out) % 16)
+    return fail(LFC_E_INVALID, "lfc_batch_decode: d_req must be 4-byte and d_out 16-byte aligned");
+  const size_t tb = lfc::lf_table_bytes();
+  Slot &sl = b->slot[b->next];
+  if (lfc_status st = grow_slot(sl, (size_t)n_lf * tb)) return st;
+  if (sl.used && hipEventSynchronize(sl.copied) != hipSuccess) return fail(LFC_E_HIP, "lfc_batch_decode: event wait");
+  for (int i = 0; i < n_lf; i++) lfc::lf_table_fill(lfs[i], sl.host + (size_t)i * tb);
+  if (hipMemcpyAsync(sl.dev, sl.host, (size_t)n_lf * tb, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipEventRecord(sl.copied, s) != hipSuccess)
+    return fail(LFC_E_HIP, "lfc_batch_decode: copy of the light-field table");
+  sl.used = true;
+  b->next = (b->next + 1) % kSlots;
+  return lfc::decode_multi_launch(block, sl.dev, n_lf, d_req, n, d_out, b->d_err, s);
+}
+
+extern "C" lfc_status lfc_batch_check(lfc_batch *b, hipStream_t s) {
+  if (!b) return fail(LFC_E_INVALID, "lfc_batch_check: null batch");
+  int32_t flag = 0;
+  if (hipStreamSynchronize(s) != hipSuccess || hipMemcpy(&flag, b->d_err, 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemset(b->d_err, 0, 4) != hipSuccess)
+    return fail(LFC_E_HIP, "lfc_batch_check: reading the error flag");
+  if (flag) return fail(LFC_E_INVALID, "lfc_batch_decode: a request was out of range (zeros written)");
   return LFC_OK;
 }
 

@@ -26,7 +26,16 @@ lfc_status render_req_fill(const lfc_lf *lf, const lfc_view &v, int wo, int ho, 
 // size `block`): max_tiles workgroups per request, lds bytes each.
 lfc_status render_multi_launch(int block, const void *d_reqs, int n, int max_tiles, size_t lds, hipStream_t s);
 
-// The device a light field was opened on.
+// The device a light field was opened on, and its block size.
 int lf_device(const lfc_lf *lf);
+int lf_block(const lfc_lf *lf);
+
+// A light field's device tables for random access, packed into lf_table_bytes()
+// bytes, and one launch decoding n (light field, view, block) requests of
+// light fields of block size `block` whose packed tables are at d_lfs.
+size_t lf_table_bytes();
+void lf_table_fill(const lfc_lf *lf, void *dst);
+lfc_status decode_multi_launch(int block, const void *d_lfs, int n_lf, const int32_t *d_req, int64_t n, int16_t *out,
+                               int32_t *err, hipStream_t s);
 
 }  // namespace lfc

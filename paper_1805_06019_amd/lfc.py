@@ -139,6 +139,8 @@ def load() -> C.CDLL:
         L.lfc_batch_create.argtypes = [C.POINTER(vp)]
         L.lfc_batch_render.argtypes = [vp, C.POINTER(vp), i32, C.POINTER(c_render_request), i32, C.POINTER(vp), vp]
         L.lfc_batch_destroy.argtypes = [vp]
+        L.lfc_batch_decode.argtypes = [vp, C.POINTER(vp), i32, vp, i64, vp, vp]
+        L.lfc_batch_check.argtypes = [vp, vp]
         L.lfc_server_create.argtypes = [C.POINTER(vp), i32, C.POINTER(c_server_config), C.POINTER(vp)]
         L.lfc_server_submit.argtypes = [vp, C.POINTER(c_render_request), u64p]
         L.lfc_server_wait.argtypes = [vp, C.c_uint64, i32, C.POINTER(vp), dp]
@@ -147,7 +149,8 @@ def load() -> C.CDLL:
         L.lfc_server_get_stats.argtypes = [vp, C.POINTER(c_server_stats)]
         L.lfc_server_destroy.argtypes = [vp]
         for f in ("lfc_encode", "lfc_encode_ex", "lfc_validate", "lfc_open", "lfc_info", "lfc_decode_blocks",
-                  "lfc_render_views", "lfc_check", "lfc_close", "lfc_decode_progressive", "lfc_batch_create", "lfc_batch_render",
+                  "lfc_render_views", "lfc_check", "lfc_close", "lfc_decode_progressive", "lfc_batch_create",
+                  "lfc_batch_decode", "lfc_batch_check", "lfc_batch_render",
                   "lfc_batch_destroy", "lfc_server_create", "lfc_server_submit", "lfc_server_wait",
                   "lfc_server_release", "lfc_server_replay", "lfc_server_get_stats", "lfc_server_destroy"):
             getattr(L, f).restype = C.c_int
@@ -356,6 +359,24 @@ class Batch:
         _check(load().lfc_batch_render(self.handle, _handles(lfs), len(lfs), _requests(reqs), len(reqs), ptrs,
                                        _stream_ptr(cuda_stream)))
         return outs
+
+    def decode(self, lfs, req, out=None, cuda_stream=None):
+        """Random access over several light fields (same block size): req
+        int32 CUDA tensor [n][3] = (light-field index, view, block).  Returns
+        int16 CUDA [n][3][B][B]."""
+        import torch
+        assert req.dtype == torch.int32 and req.is_cuda and req.is_contiguous() and req.dim() == 2
+        n = req.shape[0]
+        B = lfs[0].info.params.block
+        if out is None:
+            out = torch.empty((n, 3, B, B), dtype=torch.int16, device="cuda")
+        assert out.dtype == torch.int16 and out.is_cuda and out.is_contiguous() and tuple(out.shape) == (n, 3, B, B)
+        _check(load().lfc_batch_decode(self.handle, _handles(lfs), len(lfs), req.data_ptr(), n, out.data_ptr(),
+                                       _stream_ptr(cuda_stream)))
+        return out
+
+    def check(self, cuda_stream=None) -> None:
+        _check(load().lfc_batch_check(self.handle, _stream_ptr(cuda_stream)))
 
     def close(self) -> None:
         h, self.handle = self.handle, None

@@ -4,7 +4,8 @@ A batched request must give exactly the bytes that lfc_render_views gives
 for it alone (the same tile code runs, only the launch is shared), and
 through it the oracle's renderer to 1e-5.  The server must return every
 request's result unchanged whatever it is batched with, including when the
-output pool admits only a few results at a time.
+output pool admits only a few results at a time.  Batched random access over
+several light fields must equal each light field's own decode.
 """
 import ctypes as C
 
@@ -167,3 +168,36 @@ def test_server_workload_sizes(gpu):
         assert torch.equal(got, single([lf], r))
     sv.close()
     lf.close()
+
+
+def test_batch_decode_across_light_fields(fields):
+    # random access over two light fields of block size 4 in one launch
+    encs, lfs = fields
+    pick = [lfs[0], lfs[3]]
+    rng = np.random.default_rng(11)
+    rows = []
+    for _ in range(5000):
+        li = int(rng.integers(2))
+        lf = pick[li]
+        nv = lf.info.params.grid_u * lf.info.params.grid_v
+        rows.append((li, int(rng.integers(nv)), int(rng.integers(lf.info.n_blocks))))
+    req = torch.tensor(rows, dtype=torch.int32, device="cuda")
+    b = lfc.Batch()
+    got = b.decode(pick, req)
+    b.check()
+    for li in (0, 1):
+        sel = [i for i, r in enumerate(rows) if r[0] == li]
+        single = lfc.lfc_decode_blocks(pick[li], req[sel][:, 1:].contiguous(), lfc.LAYOUT_BLOCKS)
+        assert torch.equal(got[sel], single)
+    # out-of-range requests give zeros and raise the batch's flag
+    bad = torch.tensor([[2, 0, 0], [0, 10_000, 0], [1, 0, -1], [0, 0, 0]], dtype=torch.int32, device="cuda")
+    out = b.decode(pick, bad)
+    with pytest.raises(lfc.LFCError):
+        b.check()
+    assert not out[:3].any()
+    first = lfc.lfc_decode_blocks(pick[0], torch.zeros((1, 2), dtype=torch.int32, device="cuda"), lfc.LAYOUT_BLOCKS)
+    assert torch.equal(out[3], first[0])
+    b.check()   # cleared
+    with pytest.raises(lfc.LFCError):
+        b.decode([lfs[0], lfs[1]], req)   # block sizes 4 and 2
+    b.close()
