@@ -214,123 +214,140 @@ void build_tree_tables(const Geometry &g, TreeTables &t) {
   }
 }
 
-// Consecutive batches grouped so that their leaves and every ancestor level
-// fit the residual tile of the whole-field kernel.
-void build_chunks(const Geometry &g, std::vector<int32_t> &batch, std::vector<int32_t> &chunks,
-                  std::vector<int32_t> &nodes) {
-  chunks.clear();
-  nodes.clear();
-  const int nb = (int)(batch.size() / kBatchWords), L = g.L;
-  if (L < 2) return;
-  const int budget = kChunkResBytes / (128 * g.B);
-  for (int q = 0; q < nb;) {
-    int lo[kMaxLevels], hi[kMaxLevels], n = 0, total = 0;
-    for (int l = 0; l < L - 1; l++) lo[l] = hi[l] = -1;
-    while (q + n < nb) {
-      const int32_t *r = &batch[(size_t)(q + n) * kBatchWords];
-      int nlo[kMaxLevels], nhi[kMaxLevels], t = 0;
-      for (int l = 0; l < L - 1; l++) {
-        const int first = l == 0 ? r[10] : r[6 + (L - 2 - l)];
-        const int last = l == 0 ? r[10] + r[0] - 1 : first;
-        nlo[l] = lo[l] < 0 ? first : std::min(lo[l], first);
-        nhi[l] = std::max(hi[l], last);
-        t += nhi[l] - nlo[l] + 1;
-      }
-      if (n > 0 && t > budget) break;
-      for (int l = 0; l < L - 1; l++) {
-        lo[l] = nlo[l];
-        hi[l] = nhi[l];
-      }
-      total = t;
-      n++;
-    }
-    int32_t rec[kChunkWords] = {0};
-    rec[0] = q;
-    rec[1] = n;
-    rec[2] = total;
-    rec[3] = (int32_t)nodes.size();
-    int base[kMaxLevels];
-    for (int l = 0, o = 0; l < L - 1; l++) {
-      rec[4 + 2 * l] = lo[l];
-      rec[5 + 2 * l] = hi[l] - lo[l] + 1;
-      base[l] = o;
-      for (int s = lo[l]; s <= hi[l]; s++) nodes.push_back(s);
-      o += hi[l] - lo[l] + 1;
-    }
-    // where each run finds its nodes in the chunk's list
-    for (int k = q; k < q + n; k++) {
-      int32_t *r = &batch[(size_t)k * kBatchWords];
-      r[11] = base[0] + (r[10] - lo[0]);
-      for (int i = 0; i < 4; i++) r[12 + i] = -1;
-      for (int l = 1; l < L - 1; l++) r[12 + (L - 2 - l)] = base[l] + (r[6 + (L - 2 - l)] - lo[l]);
-    }
-    chunks.insert(chunks.end(), rec, rec + kChunkWords);
-    q += n;
-  }
-}
-
-// Decode schedule of the whole-field kernel, derived once from the directory:
-// per strip (channel c, block row by, strip sx of 64/B blocks) and chunk, the
-// stored (node, block) pairs sorted by range kind with their directory
-// entries, and per node of the chunk a mask of its stored blocks.
-//   strip record: [0..nchunk] offsets of the chunk records from the strip's
-//   start (the last one is the strip's length); chunk record: n0, n01, n
-//   (ends of the plain-bit, trit and quint items), masks[nodes], entries[n],
-//   then the pairs (node << 5 | block) as 16-bit values, two per word.
+// Decode schedule of the whole-field kernel, derived once from the directory.
+// Per strip (channel c, block row by, strip sx of 64/B blocks) the runs of
+// sibling leaves are cut into chunks whose stored blocks fit the kernel's
+// compact residual tile (cap blocks, stored blocks only); per
+// chunk: its runs, its nodes (leaves first, then ancestors), per node a mask
+// of the stored blocks and the tile slot of the first one (slots follow node
+// order, then block order), per run the positions of its first leaf and of
+// its ancestors in the node list, and the stored blocks sorted by range kind
+// with their directory entries and (slot << 5 | block).
+//   strip record: [0] chunks, [1..chunks] chunk record offsets from the
+//   strip's start, [chunks+1] the strip's length;
+//   chunk record: q0, nq, nn, n0, n01, n (first run, runs, nodes, ends of the
+//   plain-bit, trit and quint blocks), masks[nn], first slots[nn] (16-bit, two
+//   per word), runs[nq][3 words] (16-bit: first leaf, ancestors on levels
+//   L-2 .. 1; 0xFFFF unused), entries[n], items[n] (16-bit, two per word).
 static void build_schedule(const Geometry &g, const std::vector<uint32_t> &off, const std::vector<uint32_t> &srv,
                            const std::vector<uint32_t> &dbase, const std::vector<uint32_t> &poff,
-                           const std::vector<int32_t> &chunks, const std::vector<int32_t> &nodes,
-                           std::vector<uint32_t> &sched, std::vector<uint32_t> &strip_off) {
+                           const std::vector<int32_t> &batch, std::vector<uint32_t> &sched,
+                           std::vector<uint32_t> &strip_off, int cap) {
   const int nblk = 64 / g.B, nsx = (g.nbx + nblk - 1) / nblk, nstrip = 3 * g.nby * nsx;
-  const int nck = (int)(chunks.size() / kChunkWords);
+  const int nruns = (int)(batch.size() / kBatchWords), L = g.L;
   std::vector<std::vector<uint32_t>> per((size_t)nstrip);
   parallel_for(nstrip, 8, [&](int64_t a, int64_t e) {
-    std::vector<uint32_t> ent[3];
-    std::vector<uint16_t> ids[3];
+    std::vector<uint32_t> m((size_t)std::max(g.n_srv, 1));
+    std::vector<int> loc((size_t)std::max(g.n_srv, 1), -1);
     for (int64_t st = a; st < e; st++) {
       const int sx = (int)(st % nsx), by = (int)((st / nsx) % g.nby), c = (int)(st / ((int64_t)nsx * g.nby));
-      std::vector<uint32_t> &w = per[(size_t)st];
-      w.assign((size_t)nck + 1, 0);
-      for (int k = 0; k < nck; k++) {
-        w[(size_t)k] = (uint32_t)w.size();
-        const int32_t *cr = &chunks[(size_t)k * kChunkWords];
-        const int nn = cr[2], base = cr[3];
-        std::vector<uint32_t> mask((size_t)nn, 0);
-        for (int kind = 0; kind < 3; kind++) {
-          ent[kind].clear();
-          ids[kind].clear();
+      // stored blocks of every node in this strip
+      std::fill(m.begin(), m.end(), 0u);
+      for (int jj = 0; jj < nblk; jj++) {
+        const int bx = sx * nblk + jj;
+        if (bx >= g.nbx) continue;
+        const size_t gi = 3 * ((size_t)by * g.nbx + bx) + c;
+        if (off[gi] == off[gi + 1]) continue;
+        for (int w = 0; w < g.nbw; w++)
+          for (uint32_t bm = srv[off[gi] + w]; bm; bm &= bm - 1) m[(size_t)w * 32 + __builtin_ctz(bm)] |= 1u << jj;
+      }
+      std::vector<uint32_t> head(1, 0), body;
+      for (int q = 0; q < nruns;) {
+        // greedy: consecutive runs while their nodes' stored blocks fit the tile
+        std::vector<int> leaves, ancs;
+        int count = 0, k = 0;
+        while (q + k < nruns) {
+          const int32_t *r = &batch[(size_t)(q + k) * kBatchWords];
+          int add = 0;
+          std::vector<int> nl, na;
+          for (int i = 0; i < r[0]; i++) {
+            const int s = r[10] + i;
+            if (loc[(size_t)s] < 0) {
+              nl.push_back(s);
+              add += __builtin_popcount(m[(size_t)s]);
+            }
+          }
+          for (int i = 0; i < L - 2; i++) {
+            const int s = r[6 + i];
+            if (loc[(size_t)s] < 0 && std::find(na.begin(), na.end(), s) == na.end()) {
+              na.push_back(s);
+              add += __builtin_popcount(m[(size_t)s]);
+            }
+          }
+          if (k > 0 && (count + add > cap || leaves.size() + ancs.size() + nl.size() + na.size() > 65535)) break;
+          for (int s : nl) {
+            loc[(size_t)s] = 0;
+            leaves.push_back(s);
+          }
+          for (int s : na) {
+            loc[(size_t)s] = 0;
+            ancs.push_back(s);
+          }
+          count += add;
+          k++;
         }
-        for (int ln = 0; ln < nn; ln++) {
-          const int s = nodes[(size_t)base + ln];
-          for (int jj = 0; jj < nblk; jj++) {
-            const int bx = sx * nblk + jj;
-            if (bx >= g.nbx) continue;
-            const size_t gi = 3 * ((size_t)by * g.nbx + bx) + c;
-            const uint32_t o0 = off[gi], o1 = off[gi + 1];
-            if (o0 == o1) continue;
-            const uint32_t bm = srv[o0 + (s >> 5)], bit = (uint32_t)s & 31u;
-            if (!((bm >> bit) & 1u)) continue;
+        // local node order: leaves, then ancestors
+        std::vector<int> nodes(leaves);
+        nodes.insert(nodes.end(), ancs.begin(), ancs.end());
+        for (size_t i = 0; i < nodes.size(); i++) loc[(size_t)nodes[i]] = (int)i;
+        const int nn = (int)nodes.size();
+        std::vector<uint32_t> masks((size_t)nn), bases((size_t)nn);
+        uint32_t slot = 0;
+        for (int i = 0; i < nn; i++) {
+          masks[(size_t)i] = m[(size_t)nodes[(size_t)i]];
+          bases[(size_t)i] = slot;
+          slot += (uint32_t)__builtin_popcount(masks[(size_t)i]);
+        }
+        std::vector<uint32_t> ent[3], item[3];
+        for (int i = 0; i < nn; i++) {
+          const int s = nodes[(size_t)i];
+          for (uint32_t bits = masks[(size_t)i]; bits; bits &= bits - 1) {
+            const int jj = __builtin_ctz(bits);
+            const size_t gi = 3 * ((size_t)by * g.nbx + sx * nblk + jj) + c;
+            const uint32_t bm = srv[off[gi] + (s >> 5)], bit = (uint32_t)s & 31u;
             const uint32_t en = poff[dbase[gi * g.nbw + (s >> 5)] + (uint32_t)__builtin_popcount(bm & ((1u << bit) - 1u))];
             const uint32_t code = en & 31u;
             const int kind = code < 12 ? 0 : (code < 19 ? 1 : 2);
+            const uint32_t sl = bases[(size_t)i] + (uint32_t)__builtin_popcount(masks[(size_t)i] & ((1u << jj) - 1u));
             ent[kind].push_back(en);
-            ids[kind].push_back((uint16_t)((ln << 5) | jj));
-            mask[(size_t)ln] |= 1u << jj;
+            item[kind].push_back((sl << 5) | (uint32_t)jj);
           }
         }
         const uint32_t n0 = (uint32_t)ent[0].size(), n01 = n0 + (uint32_t)ent[1].size();
         const uint32_t n = n01 + (uint32_t)ent[2].size();
-        w.push_back(n0);
-        w.push_back(n01);
-        w.push_back(n);
-        w.insert(w.end(), mask.begin(), mask.end());
-        for (int kind = 0; kind < 3; kind++) w.insert(w.end(), ent[kind].begin(), ent[kind].end());
-        std::vector<uint16_t> all;
-        for (int kind = 0; kind < 3; kind++) all.insert(all.end(), ids[kind].begin(), ids[kind].end());
-        for (size_t i = 0; i < all.size(); i += 2)
-          w.push_back((uint32_t)all[i] | ((i + 1 < all.size() ? (uint32_t)all[i + 1] : 0u) << 16));
+        head.push_back((uint32_t)body.size());   // made absolute below
+        body.push_back((uint32_t)q);
+        body.push_back((uint32_t)k);
+        body.push_back((uint32_t)nn);
+        body.push_back(n0);
+        body.push_back(n01);
+        body.push_back(n);
+        body.insert(body.end(), masks.begin(), masks.end());
+        for (int i = 0; i < nn; i += 2)
+          body.push_back(bases[(size_t)i] | (i + 1 < nn ? bases[(size_t)i + 1] << 16 : 0u));
+        for (int j = 0; j < k; j++) {
+          const int32_t *r = &batch[(size_t)(q + j) * kBatchWords];
+          uint32_t h[4] = {(uint32_t)loc[(size_t)r[10]], 0xFFFFu, 0xFFFFu, 0xFFFFu};
+          for (int i = 0; i < L - 2; i++) h[1 + i] = (uint32_t)loc[(size_t)r[6 + i]];
+          body.push_back(h[0] | (h[1] << 16));
+          body.push_back(h[2] | (h[3] << 16));
+          body.push_back(L - 2 > 3 ? (uint32_t)loc[(size_t)r[9]] | 0xFFFF0000u : 0xFFFFFFFFu);
+        }
+        for (int kind = 0; kind < 3; kind++) body.insert(body.end(), ent[kind].begin(), ent[kind].end());
+        std::vector<uint32_t> all;
+        for (int kind = 0; kind < 3; kind++) all.insert(all.end(), item[kind].begin(), item[kind].end());
+        for (size_t i = 0; i < all.size(); i += 2) body.push_back(all[i] | (i + 1 < all.size() ? all[i + 1] << 16 : 0u));
+        for (int s : nodes) loc[(size_t)s] = -1;
+        q += k;
       }
-      w[(size_t)nck] = (uint32_t)w.size();
+      const uint32_t nck = (uint32_t)(head.size() - 1);
+      head[0] = nck;
+      const uint32_t hdr = nck + 2;
+      for (uint32_t i = 1; i <= nck; i++) head[i] += hdr;
+      head.push_back(hdr + (uint32_t)body.size());
+      std::vector<uint32_t> &w = per[(size_t)st];
+      w = head;
+      w.insert(w.end(), body.begin(), body.end());
     }
   });
   strip_off.assign((size_t)nstrip + 1, 0);
@@ -904,11 +921,13 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
     size_t at;
   };
   static const uint32_t zeros[64] = {0};
-  std::vector<int32_t> chunks, nmap;
   std::vector<uint32_t> sched, strip_off;
+  // tile capacity (LFC_TILE_BLOCKS overrides it for tuning): at least one run
+  // of kBatch leaves with four ancestors, 8 nodes of 64/B blocks
+  int tile_cap = tile_blocks(ps.g.B);
+  if (const char *e = getenv("LFC_TILE_BLOCKS")) tile_cap = std::min(2048, std::max(512 / ps.g.B, atoi(e) / 8 * 8));
   try {
-    build_chunks(ps.g, tt.batch, chunks, nmap);
-    build_schedule(ps.g, ps.off, ps.srv, ps.dbase, ps.poff, chunks, nmap, sched, strip_off);
+    build_schedule(ps.g, ps.off, ps.srv, ps.dbase, ps.poff, tt.batch, sched, strip_off, tile_cap);
   } catch (const std::bad_alloc &) {
     return fail(LFC_E_NOMEM, "lfc_open: out of host memory");
   }
@@ -930,7 +949,7 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
     }
     std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
   }
-  Part parts[14] = {
+  Part parts[13] = {
       {ps.rkv, ps.rkv_bytes, 0},
       {ps.off.data(), ps.off.size() * 4, 0},
       {ps.srv.data(), ps.srv.size() * 4, 0},
@@ -940,7 +959,6 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
       {tt.root.data(), tt.root.size() * 4, 0},
       {tt.batch.data(), tt.batch.size() * 4, 0},
       {zeros, 4, 0},
-      {chunks.data(), chunks.size() * 4, 0},
       {ps.pbase.data(), ps.pbase.size() * 4, 0},
       {sched.data(), sched.size() * 4, 0},
       {strip_off.data(), strip_off.size() * 4, 0},
@@ -978,6 +996,7 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
   }
   lf->params = ps.p;
   lf->geo = g;
+  lf->tile_cap = tile_cap;
   lf->device = dev;
   lf->stream_bytes = bytes;
   lf->present = ps.present;
@@ -992,13 +1011,10 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
   lf->d_root = reinterpret_cast<const int32_t *>(d + parts[6].at);
   lf->d_batch = reinterpret_cast<const int32_t *>(d + parts[7].at);
   lf->n_batch = (int)(tt.batch.size() / kBatchWords);
-  lf->d_chunk = reinterpret_cast<const int32_t *>(d + parts[9].at);
-  lf->d_pbase = reinterpret_cast<const uint32_t *>(d + parts[10].at);
-  lf->d_sched = reinterpret_cast<const uint32_t *>(d + parts[11].at);
-  lf->d_strip_off = reinterpret_cast<const uint32_t *>(d + parts[12].at);
-  lf->d_order = reinterpret_cast<const uint32_t *>(d + parts[13].at);
-  lf->n_chunk = (int)(chunks.size() / kChunkWords);
-  for (int i = 0; i < lf->n_chunk; i++) lf->max_chunk_nodes = std::max(lf->max_chunk_nodes, chunks[(size_t)i * kChunkWords + 2]);
+  lf->d_pbase = reinterpret_cast<const uint32_t *>(d + parts[9].at);
+  lf->d_sched = reinterpret_cast<const uint32_t *>(d + parts[10].at);
+  lf->d_strip_off = reinterpret_cast<const uint32_t *>(d + parts[11].at);
+  lf->d_order = reinterpret_cast<const uint32_t *>(d + parts[12].at);
   lf->d_err = reinterpret_cast<int32_t *>(d + parts[8].at);
   // LDS staging of the whole-field kernel is sized by the largest strip:
   // group words plus the strip's decode schedule

@@ -35,24 +35,13 @@ lfc_status make_geometry(const lfc_params &p, Geometry &g, std::string *why);
 // with the same ancestors), one kBatchWords-word record per run:
 //   [0] n, [1..4] view indices (-1 unused), [5] root, [6..9] serial indices of
 //   the ancestors from level L-2 down to level 1 (-1 unused), [10] serial
-//   index of the first view of the run (the others follow it), [11] the first
-//   view's position in the node list of its chunk, [12..15] the positions of
-//   the ancestors [6..9] in that list (-1 unused); [11..15] are filled in by
-//   build_chunks.
+//   index of the first view of the run (the others follow it), [11..15] unused.
 constexpr int kBatch = 4;
 constexpr int kBatchWords = 16;
-// Chunks of consecutive runs decoded together by the whole-field kernel:
-//   [0] first run, [1] runs, [2] nodes in all, [3] offset of the chunk's node
-//   list (serial indices, leaves first) in the node-list table, then for each
-//   level l = 0..L-2 from the leaves up: [4+2l] first serial index, [5+2l]
-//   node count (the nodes of a level under a run of consecutive leaves are
-//   consecutive).
-constexpr int kChunkWords = 16;
-// residual-tile budget of one chunk, in nodes: LDS bytes / (64/B blocks * B*B
-// samples * 2 bytes) = kChunkResBytes / (128 B)
-constexpr int kChunkResBytes = 32 * 1024;
-void build_chunks(const Geometry &g, std::vector<int32_t> &batch, std::vector<int32_t> &chunks,
-                  std::vector<int32_t> &nodes);
+// Default capacity, in stored residual blocks, of the whole-field kernel's
+// compact tile (32 KB of LDS; tile slots are 11-bit, beside a 5-bit block
+// index in 16-bit schedule items, so at most 2048).
+constexpr int tile_blocks(int B) { return B == 2 ? 2048 : (B == 4 ? 1024 : 256); }
 struct TreeTables {
   std::vector<int32_t> path, root, batch;
   std::vector<std::vector<int32_t>> serial;  // [level][node id] -> BFS index (-1 on top)
@@ -85,12 +74,11 @@ struct lfc_lf {
   const int32_t *d_root = nullptr;   // [nv]
   const int32_t *d_batch = nullptr;  // [n_batch][kBatchWords]
   int n_batch = 0;
-  const int32_t *d_chunk = nullptr;  // [n_chunk][kChunkWords]
   const uint32_t *d_sched = nullptr;     // decode schedule of the whole-field kernel (strip records)
   const uint32_t *d_strip_off = nullptr; // [n_strips+1] word offset of each strip's record
   const uint32_t *d_order = nullptr;     // [n_strips] strips in the order the whole-field kernel takes them
-  int n_chunk = 0, max_chunk_nodes = 0;
   int32_t *d_err = nullptr;          // device error flag
+  int tile_cap = 0;                  // blocks of the whole-field kernel's compact residual tile
   uint32_t max_strip_words = 0;      // largest group words + decode schedule of a strip of 64/B blocks of
                                      // one channel
   std::vector<uint32_t> strip_need;  // per strip: group words + schedule words, schedule words

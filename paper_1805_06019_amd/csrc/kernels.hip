@@ -248,12 +248,12 @@ struct LFArgs {
   const uint32_t *strip_off;  // [n_strips+1] word offset of each strip's record
   const uint32_t *order;      // [n_strips] strip of each workgroup, costliest first
   const int32_t *batch;       // [nbatch][kBatchWords] runs of sibling leaves (see internal.h)
-  const int32_t *chunk;       // [nchunk][kChunkWords] runs of batches decoded together
   int16_t *out;               // [nv][3][hp][wp]
-  int nbx, nv, L, q, wp, hp, nb, nbatch, nchunk, max_chunk_nodes;
+  int nbx, nv, L, q, wp, hp, nb, nbatch;
   int stage_cap;              // LDS words available for staging the strip
   int vec_store;              // output rows may be stored 16 bytes at a time
   int n_top, key_words;       // key views; LDS words of the strip's key-view rows (0: not staged)
+  int tile_cap;               // blocks of the compact residual tile
 };
 
 // A whole block of a known kind (0 plain bits, 1 trit, 2 quint) decoded by one
@@ -330,67 +330,53 @@ __device__ __forceinline__ void lds_copy(uint32_t *dst, const uint32_t *src, uin
 typedef const __attribute__((address_space(4))) int32_t *uniform_i32;
 __device__ __forceinline__ uniform_i32 as_uniform(const int32_t *p) { return (uniform_i32)p; }
 
-// A chunk record held in scalar registers: runs [q0, q0+nq), nn nodes, whose
-// serial indices are listed from nbase on in the node-list table.
-struct ChunkRec {
-  int q0, nq, nn, nbase;
-};
-
-__device__ __forceinline__ ChunkRec read_chunk(const int32_t *chunk, int ci) {
-  const uniform_i32 cr = as_uniform(chunk + (size_t)ci * lfc::kChunkWords);
-  return ChunkRec{cr[0], cr[1], cr[2], cr[3]};
-}
-
-// Residual tile of a chunk: per node and block row, the row's 64 samples as
-// eight 16-byte slots of 8/B blocks each.  The slot index is XORed with the
-// node's low bits, so lanes writing the same block of different nodes hit
-// different LDS banks; a slot is still read whole.
-template <int B>
-__device__ __forceinline__ int tile_slot(int ln, int y, int slot) {
-  return (ln * B + y) * 8 + (slot ^ (ln & 7));
-}
-
 // One chunk of phase B of the whole-field kernel.  sch is the chunk's record
-// of the decode schedule (n0, n01, n, per-node masks of the stored blocks,
-// directory entries, (node, block) pairs), in LDS or in global memory; the
-// payload of block j of the strip is at pw + s_po[j].  Step (3): every
-// listed block decoded once, whole, by one lane, with the decoder of its
-// range kind, into the tile; step (4): per sibling run, key-view row +
-// ancestor rows + leaf row (absent blocks masked), stored 16 bytes per lane.
+// of the decode schedule (runs, nodes, per-node masks of the stored blocks
+// and first tile slots, per-run node positions, directory entries and
+// (slot, block) items), in LDS or in global memory; the payload of block j of
+// the strip is at pw + s_po[j].  Step (3): every stored block decoded once,
+// whole, by one lane, with the decoder of its range kind, into its slot of
+// the compact tile; step (4): per sibling run, key-view row + ancestor rows +
+// leaf row (absent blocks add nothing), stored 16 bytes per lane.
 template <int B>
-__device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, int nn, int q0, int nq,
-                                         const uint32_t *pw, const uint32_t *s_po, uint32_t *tile,
-                                         const uint32_t *keys, const uint16_t *lut, int tid, int wave, int lane,
-                                         int so, int y, int jq, int bx0, int nact, bool wide, uint64_t lane_off,
-                                         uint32_t vstride, int by, int c) {
+__device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, const uint32_t *pw,
+                                         const uint32_t *s_po, uint32_t *tile, const uint32_t *keys,
+                                         const uint16_t *lut, int tid, int wave, int lane, int so, int y, int jq,
+                                         int bx0, int nact, bool wide, uint64_t lane_off, uint32_t vstride, int by,
+                                         int c) {
   constexpr int S = B * B, NBLK = 64 / B, H = B / 2, PB = 8 / B, SPP = 64 / (8 * B);
-  const uint32_t n0 = sch[0], n01 = sch[1], n = sch[2];
-  const uint32_t *masks = sch + 3;
-  const uint32_t *ents = masks + nn;
-  const uint16_t *ids = reinterpret_cast<const uint16_t *>(ents + n);
+  const int q0 = (int)sch[0], nq = (int)sch[1], nn = (int)sch[2];
+  const uint32_t n0 = sch[3], n01 = sch[4], n = sch[5];
+  const uint32_t *masks = sch + 6;
+  const uint16_t *firsts = reinterpret_cast<const uint16_t *>(masks + nn);
+  const uint32_t *runs = masks + nn + (nn + 1) / 2;
+  const uint32_t *ents = runs + 3 * nq;
+  const uint16_t *items = reinterpret_cast<const uint16_t *>(ents + n);
   // (3) decode; the three kinds are laid end to end, so a wave mostly sees one kind
   for (uint32_t it = tid; it < n; it += kLFThreads) {
-    const uint32_t e = ents[it], id = ids[it];
-    const int ln = (int)(id >> 5), jj = (int)(id & 31u);
-    const uint32_t *gw = pw + s_po[jj];
+    const uint32_t e = ents[it], t = items[it];
+    const uint32_t *gw = pw + s_po[t & 31u];
     uint32_t d[S / 2];
     if (it < n0) decode_block_k<B, 0>(gw, e, a.q, lut, d);
     else if (it < n01) decode_block_k<B, 1>(gw, e, a.q, lut, d);
     else decode_block_k<B, 2>(gw, e, a.q, lut, d);
+    uint32_t *dst = tile + (t >> 5) * (S / 2);
+    if constexpr (S / 2 >= 4) {
 #pragma unroll
-    for (int yy = 0; yy < B; yy++)
-#pragma unroll
-      for (int h = 0; h < H; h++) tile[tile_slot<B>(ln, yy, jj / PB) * 4 + (jj % PB) * H + h] = d[yy * H + h];
+      for (int w = 0; w < S / 2; w += 4)
+        *reinterpret_cast<uint4 *>(dst + w) = make_uint4(d[w], d[w + 1], d[w + 2], d[w + 3]);
+    } else {
+      *reinterpret_cast<uint2 *>(dst) = make_uint2(d[0], d[1]);
+    }
   }
   __syncthreads();
-  // (4) gather and store, waves splitting the chunk's runs
+  // (4) gather and store, waves taking consecutive runs of the chunk
   const int L = a.L;
   int root_cached = -1;                      // key-view row read from global memory (keys not staged)
   uint4 key = make_uint4(0u, 0u, 0u, 0u);
-  // waves take consecutive runs of the chunk
   const int per = (nq + kLFWaves - 1) / kLFWaves;
-  for (int qb = q0 + wave * per; qb < q0 + min(nq, wave * per + per); qb++) {
-    const uniform_i32 rec = as_uniform(a.batch + (size_t)qb * lfc::kBatchWords);
+  for (int qi = wave * per; qi < min(nq, wave * per + per); qi++) {
+    const uniform_i32 rec = as_uniform(a.batch + (size_t)(q0 + qi) * lfc::kBatchWords);
     const int root = rec[5];
     uint32_t anc[4];
     if (a.key_words) {
@@ -413,16 +399,36 @@ __device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, i
       anc[2] = key.z;
       anc[3] = key.w;
     }
-    // the lane's tile slot of node ln, with the entries of absent blocks as 0
+    // row y of the lane's PB blocks of node ln, for the blocks that are stored
     auto add_node = [&](int ln, uint32_t x[4]) {
-      const uint4 t4 = reinterpret_cast<const uint4 *>(tile)[tile_slot<B>(ln, y, jq)];
-      const uint32_t bits = masks[ln] >> (jq * PB);
-      const uint32_t t[4] = {t4.x, t4.y, t4.z, t4.w};
+      const uint32_t mk = masks[ln], f = firsts[ln];
 #pragma unroll
-      for (int w = 0; w < 4; w++) x[w] = add_pk(x[w], ((bits >> (w / H)) & 1u) ? t[w] : 0u);
+      for (int k = 0; k < PB; k++) {
+        const uint32_t j = (uint32_t)(jq * PB + k);
+        if ((mk >> j) & 1u) {
+          const uint32_t *row = tile + (f + (uint32_t)__popc(mk & ((1u << j) - 1u))) * (S / 2) + y * H;
+          if constexpr (H == 1) {
+            x[k] = add_pk(x[k], row[0]);
+          } else if constexpr (H == 2) {
+            const uint2 v = *reinterpret_cast<const uint2 *>(row);
+            x[2 * k] = add_pk(x[2 * k], v.x);
+            x[2 * k + 1] = add_pk(x[2 * k + 1], v.y);
+          } else {
+            const uint4 v = *reinterpret_cast<const uint4 *>(row);
+            x[0] = add_pk(x[0], v.x);
+            x[1] = add_pk(x[1], v.y);
+            x[2] = add_pk(x[2], v.z);
+            x[3] = add_pk(x[3], v.w);
+          }
+        }
+      }
     };
-    for (int k = 0; k < L - 2; k++) add_node(rec[12 + k], anc);
-    const int nsib = rec[0], ls0 = rec[11];
+    const uint32_t w0 = runs[3 * qi], w1 = runs[3 * qi + 1], w2 = runs[3 * qi + 2];
+    const uint32_t anc_ln[4] = {w0 >> 16, w1 & 0xFFFFu, w1 >> 16, w2 & 0xFFFFu};
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+      if (k < L - 2) add_node((int)anc_ln[k], anc);
+    const int nsib = rec[0], ls0 = (int)(w0 & 0xFFFFu);
     const int v0 = rec[1], v1 = rec[2], v2 = rec[3], v3 = rec[4];
     // sibling i of the run: its leaf row plus the ancestors
     auto leaf = [&](int i, uint32_t x[4]) -> int16_t * {
@@ -457,9 +463,10 @@ __device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, i
 // strip's data: its groups and its decode schedule (tier 1), else the
 // schedule only (tier 2: payload read through bit windows from global
 // memory), else nothing (tier 3), plus the strip's key-view rows.  Phase B
-// walks the leaves in serial order, chunk by chunk: decode every stored
-// residual block of the chunk once into the residual tile, then write the
-// chunk's leaves (key view + ancestors + leaf), 16 bytes per lane.
+// walks the strip's chunks (runs of sibling leaves in serial order whose
+// stored blocks fit the compact tile): decode every stored residual block of
+// the chunk once into the tile, then write the chunk's leaves (key view +
+// ancestors + leaf), 16 bytes per lane.
 template <int B>
 __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
   constexpr int S = B * B, NBLK = 64 / B, H = B / 2;
@@ -471,8 +478,8 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
   uint32_t *s_len = smem + 256;                        // group length in words
   uint32_t *s_wo = smem + 320;                         // staged group words
   uint32_t *s_cnt = smem + 384;                        // [0] tier, [1] staged group words, [2] schedule words
-  uint32_t *tile = smem + kLFHeadWords;                // [max_chunk_nodes][B rows][8 slots][4]
-  uint32_t *keys = tile + a.max_chunk_nodes * B * 32;  // [n_top][B][NBLK][H]
+  uint32_t *tile = smem + kLFHeadWords;                // compact tile: [tile_cap][S/2]
+  uint32_t *keys = tile + a.tile_cap * (S / 2);        // [n_top][B][NBLK][H]
   uint32_t *stage = keys + a.key_words;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -559,17 +566,18 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
   const bool wide = nact == PB && a.vec_store;          // a 16-byte store is aligned
   const uint64_t lane_off = cplane + (uint64_t)(by * B + y) * a.wp + (uint64_t)bx0 * B;
   const uint32_t *gsched = a.sched + sched0;
-  for (int ci = 0; ci < a.nchunk; ci++) {
-    const ChunkRec cr = read_chunk(a.chunk, ci);
+  const uint32_t *lsched = stage + sched_at;
+  const int nck = (int)(tier < 3u ? lsched[0] : gsched[0]);
+  for (int ci = 0; ci < nck; ci++) {
     if (tier == 1u)
-      lf_chunk<B>(a, stage + sched_at + stage[sched_at + ci], cr.nn, cr.q0, cr.nq, stage, s_wo, tile, keys, lut, tid,
-                  wave, lane, so, y, jq, bx0, nact, wide, lane_off, vstride, by, c);
+      lf_chunk<B>(a, lsched + lsched[1 + ci], stage, s_wo, tile, keys, lut, tid, wave, lane, so, y, jq, bx0, nact, wide,
+                  lane_off, vstride, by, c);
     else if (tier == 2u)
-      lf_chunk<B>(a, stage + stage[ci], cr.nn, cr.q0, cr.nq, a.srv, s_o0, tile, keys, lut, tid, wave, lane, so, y, jq,
-                  bx0, nact, wide, lane_off, vstride, by, c);
+      lf_chunk<B>(a, lsched + lsched[1 + ci], a.srv, s_o0, tile, keys, lut, tid, wave, lane, so, y, jq, bx0, nact, wide,
+                  lane_off, vstride, by, c);
     else
-      lf_chunk<B>(a, gsched + gsched[ci], cr.nn, cr.q0, cr.nq, a.srv, s_o0, tile, keys, lut, tid, wave, lane, so, y,
-                  jq, bx0, nact, wide, lane_off, vstride, by, c);
+      lf_chunk<B>(a, gsched + gsched[1 + ci], a.srv, s_o0, tile, keys, lut, tid, wave, lane, so, y, jq, bx0, nact, wide,
+                  lane_off, vstride, by, c);
   }
 }
 
@@ -1024,14 +1032,12 @@ template <int B>
 lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s) {
   const lfc::Geometry &g = lf->geo;
   constexpr int NBLK = 64 / B;
-  const int64_t nodes = std::max(lf->max_chunk_nodes, 1);
+
   // key-view rows of a strip, when they take at most 16 KB
   const int64_t key_words = (int64_t)g.n_top * NBLK * (B * B / 2) <= 4096 ? (int64_t)g.n_top * NBLK * (B * B / 2) : 0;
   if ((int64_t)3 * g.hp * g.wp >= ((int64_t)1 << 32))
     return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: view too large for the whole-field kernel");
-  if (nodes > 256 / B)
-    return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: chunk larger than the whole-field kernel's tile");
-  const int64_t fixed = kLFHeadWords + nodes * B * 32 + key_words;
+  const int64_t fixed = kLFHeadWords + (int64_t)lf->tile_cap * (B * B / 2) + key_words;
   const int64_t limit = max_lds_bytes() / 4;
   if (fixed > limit)
     return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: tree too large for the whole-field kernel; use BLOCKS layout");
@@ -1039,9 +1045,10 @@ lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s) {
   int64_t cap = std::min<int64_t>(target - fixed, (int64_t)lf->max_strip_words + kStagePad);
   if (const char *e = getenv("LFC_STAGE_CAP_WORDS")) cap = std::min<int64_t>(cap, std::max(0, atoi(e)));
   const size_t lds = 4 * (size_t)(fixed + cap);
-  LFArgs a{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_sched, lf->d_strip_off, lf->d_order, lf->d_batch, lf->d_chunk, out,
-           g.nbx, g.nv(), g.L, g.q, g.wp, g.hp, g.nb, lf->n_batch, lf->n_chunk, (int)nodes, (int)cap,
-           (int)(g.wp % 8 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0), g.n_top, (int)key_words};
+  LFArgs a{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_sched, lf->d_strip_off, lf->d_order, lf->d_batch, out,
+           g.nbx, g.nv(), g.L, g.q, g.wp, g.hp, g.nb, lf->n_batch, (int)cap,
+           (int)(g.wp % 8 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0), g.n_top, (int)key_words,
+           lf->tile_cap};
   dim3 grid((g.nbx + NBLK - 1) / NBLK, g.nby, 3);
   hipLaunchKernelGGL(k_decode_lf<B>, grid, dim3(kLFThreads), lds, s, a);
   return launched("lfc_decode_blocks");
