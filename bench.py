@@ -280,6 +280,31 @@ def main():
                                            views_per_s=round(1000.0 / lat.mean(), 1))
         extra["render_full40"]["speedup_vs_plain"] = round(extra["render_full40"]["views_per_s"]
                                                            / extra["view_latency_plain"]["views_per_s"], 2)
+        # measured tuning of the launch shape, then the tuned render captured in a HIP graph
+        best, tried = lfc.lfc_render_tune(lf, views, 512, 512, out=img, reps=5)
+        plan = lfc.RenderPlan(lf, views, 512, 512, out=img, cfg=best, graph=True)
+        for _ in range(3):
+            plan.launch()
+        g = time_launches(plan.launch, 10, torch)
+        plan.close()
+        extra["render_full40"]["tuned"] = dict(config=list(best), tried={f"{c[0]}:{c[1]}x{c[2]}": round(ms, 4)
+                                                                          for c, ms in tried})
+        extra["render_full40"]["graph"] = dict(ms_per_launch=round(float(g.mean()), 4),
+                                               views_per_s=round(64 / (g.mean() * 1e-3), 1))
+        # single-view requests through a graph-captured plan (views rewritten in place)
+        buf1 = one[:1].clone()
+        best1, _ = lfc.lfc_render_tune(lf, buf1, 512, 512, out=img1, reps=5)
+        plan1 = lfc.RenderPlan(lf, buf1, 512, 512, out=img1, cfg=best1, graph=True)
+        lat_g = []
+        for i in range(200):
+            buf1.copy_(one[i:i + 1])
+            lat_g.append(time_launches(plan1.launch, 1, torch)[0])
+        plan1.close()
+        lat_g = np.array(lat_g)
+        extra["view_latency_graph"] = dict(requests=200, config=list(best1),
+                                           p50_ms=round(float(np.percentile(lat_g, 50)), 4),
+                                           p99_ms=round(float(np.percentile(lat_g, 99)), 4),
+                                           views_per_s=round(1000.0 / lat_g.mean(), 1))
         del img
         # 10^6 uniformly random (view, block) accesses, all three channels
         req = torch.from_numpy(synth.block_requests(1_000_000, nv, nb, seed=202)).cuda()
@@ -316,6 +341,13 @@ def main():
         extra["render_lenslet40"] = dict(psnr_db=round(stl["psnr"], 3), views_per_launch=64,
                                          ms_per_launch=round(float(rl.mean()), 4),
                                          views_per_s=round(64 / (rl.mean() * 1e-3), 1))
+        bestl, _ = lfc.lfc_render_tune(lfl, vl, 512, 512, out=imgl, reps=5)
+        planl = lfc.RenderPlan(lfl, vl, 512, 512, out=imgl, cfg=bestl, graph=True)
+        planl.launch()
+        gl = time_launches(planl.launch, 10, torch)
+        planl.close()
+        extra["render_lenslet40"]["graph"] = dict(config=list(bestl), ms_per_launch=round(float(gl.mean()), 4),
+                                                  views_per_s=round(64 / (gl.mean() * 1e-3), 1))
         lfl.close()
         del imgl
         if not args.no_serving:

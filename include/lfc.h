@@ -210,7 +210,9 @@ lfc_status lfc_decode_progressive(const lfc_lf *lf, const int32_t *d_req, int64_
  * converted to RGB (inverse YCoCg-R, clamped to 0..255).  Source pixel
  * coordinates of output pixel (X, Y) are s + (X+0.5)*width/out_w - 0.5 and
  * t + (Y+0.5)*height/out_h - 0.5, clamped to the image.  The blocks under
- * each output tile are decoded on the fly.
+ * each output tile are decoded on the fly, or, for large batches, every
+ * source view is decoded once and the pixels interpolated from the decoded
+ * planes; both give the same bytes.
  *  d_views  device lfc_view [n].
  *  d_out    device float32 [n][3][out_h][out_w], RGB / 255.
  * Errors: LFC_E_INVALID (null pointer, n < 0, out_w or out_h < 1 or
@@ -218,6 +220,71 @@ lfc_status lfc_decode_progressive(const lfc_lf *lf, const int32_t *d_req, int64_
  */
 lfc_status lfc_render_views(const lfc_lf *lf, const lfc_view *d_views, int32_t n, int32_t out_w,
                             int32_t out_h, float *d_out, hipStream_t s);
+
+/*
+ * Launch shape of a render (results are the same bytes for every shape).
+ *  LFC_RENDER_AUTO     the library's choice (decode-then-interpolate when the
+ *                      batch's pixels are at least 1/20 of the light field's
+ *                      samples, else tiles of up to 64 x 16 pixels).
+ *  LFC_RENDER_TILES    one workgroup per output tile of tile_w x tile_h
+ *                      pixels decodes the tile's source footprint (0 x 0:
+ *                      64 x 16, shrunk until the footprint fits 64 KB).
+ *  LFC_RENDER_DECODED  decode every source view, then interpolate.
+ */
+enum { LFC_RENDER_AUTO = 0, LFC_RENDER_TILES = 1, LFC_RENDER_DECODED = 2 };
+typedef struct {
+  int32_t path;
+  int32_t tile_w, tile_h;   /* LFC_RENDER_TILES only, 1..1024 each, or both 0 */
+} lfc_render_config;
+
+/* lfc_render_views with an explicit launch shape (cfg NULL: automatic).
+ * Errors: as lfc_render_views, plus LFC_E_INVALID (unknown path, tile size)
+ * and LFC_E_UNSUPPORTED (the tile's source footprint exceeds 64 KB). */
+lfc_status lfc_render_views_ex(const lfc_lf *lf, const lfc_view *d_views, int32_t n, int32_t out_w,
+                               int32_t out_h, float *d_out, const lfc_render_config *cfg, hipStream_t s);
+
+/*
+ * Measured tuning of the render's launch shape for one (light field, batch
+ * size, output size): the decoded path and each tile shape of 32 x 8 up to
+ * 256 x 8 pixels whose footprint fits are run once, then timed over `reps`
+ * launches with events on stream s, on the caller's views (the output is
+ * overwritten).  Blocks until the timing is done.  res->cfg[res->best] is
+ * the fastest.  Allocates (and frees) the decoded path's scratch; when that
+ * fails only tile shapes are tried.
+ * Errors: as lfc_render_views, plus LFC_E_INVALID (n < 1, reps outside
+ * 1..1000, null res), LFC_E_UNSUPPORTED (no shape fits).
+ */
+#define LFC_TUNE_MAX 16
+typedef struct {
+  int32_t n_tried;
+  int32_t best;                          /* index of the fastest */
+  lfc_render_config cfg[LFC_TUNE_MAX];
+  float ms[LFC_TUNE_MAX];                /* mean ms per launch */
+} lfc_render_tuning;
+lfc_status lfc_render_tune(const lfc_lf *lf, const lfc_view *d_views, int32_t n, int32_t out_w, int32_t out_h,
+                           float *d_out, int32_t reps, lfc_render_tuning *res, hipStream_t s);
+
+/*
+ * A render plan: one render of n views at out_w x out_h with its launch
+ * shape fixed (cfg, NULL: automatic), its device pointers fixed, and, with
+ * graph != 0, its launches captured once into a HIP graph, so that each
+ * lfc_render_plan_launch is one graph launch.  The views are read at each
+ * launch, so the caller may rewrite d_views between launches.  The decoded
+ * path's scratch (the light field's decoded views) is allocated at creation
+ * and held by the plan.  Launches of one plan must not overlap (use one
+ * stream); the light field and both buffers must outlive the plan.
+ * lfc_render_plan_destroy waits for the device (it frees device memory).
+ * lfc_render_plan_info reports the resolved shape and whether a graph is used.
+ * Errors: as lfc_render_views_ex, plus LFC_E_NOMEM (scratch), LFC_E_HIP
+ * (capture or instantiation).
+ */
+typedef struct lfc_render_plan lfc_render_plan;
+lfc_status lfc_render_plan_create(const lfc_lf *lf, const lfc_render_config *cfg, const lfc_view *d_views,
+                                  int32_t n, int32_t out_w, int32_t out_h, float *d_out, int32_t graph,
+                                  lfc_render_plan **plan);
+lfc_status lfc_render_plan_launch(lfc_render_plan *plan, hipStream_t s);
+lfc_status lfc_render_plan_info(const lfc_render_plan *plan, lfc_render_config *cfg, int32_t *graph);
+void lfc_render_plan_destroy(lfc_render_plan *plan);
 
 /*
  * Batched rendering across light fields.  Views are independent of each

@@ -19,8 +19,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <new>
 #include <string>
 #include <type_traits>
+#include <vector>
 
 #include "internal.h"
 #include "serve.h"
@@ -1066,15 +1068,16 @@ lfc_status decode_list(const lfc_lf *lf, const int32_t *req, int64_t n, int16_t 
 }
 
 // Tile of output pixels per workgroup, and the largest footprint (in blocks)
-// any tile can need; shrinks the tile until the footprint fits 64 KB of LDS.
+// any tile can need; starting from TX x TY, shrinks the tile (if allowed)
+// until the footprint fits 64 KB of LDS.
 struct RenderPlan {
   int TX, TY, fbx, fby;
   size_t lds;
 };
 
-bool plan_render(const lfc::Geometry &g, int wo, int ho, RenderPlan &pl) {
+bool plan_render(const lfc::Geometry &g, int wo, int ho, RenderPlan &pl, int TX = 64, int TY = 16,
+                 bool shrink = true) {
   const double sxs = (double)g.W / wo, tys = (double)g.H / ho;
-  int TX = 64, TY = 16;
   for (;;) {
     // footprint span: (T-1)*scale pixels plus the 1-pixel widening on each
     // side, the interpolation neighbour and float slack, then block alignment
@@ -1087,6 +1090,7 @@ bool plan_render(const lfc::Geometry &g, int wo, int ho, RenderPlan &pl) {
       pl = RenderPlan{TX, TY, fbx, fby, lds};
       return true;
     }
+    if (!shrink) return false;
     if (TY > 2) TY /= 2;
     else if (TX > 8) TX /= 2;
     else return false;
@@ -1106,15 +1110,51 @@ bool render_decoded(const lfc::Geometry &g, int32_t n, int32_t wo, int32_t ho) {
   return 20.0 * n * wo * ho >= (double)g.nv() * g.hp * g.wp;
 }
 
-template <int B>
-lfc_status render(const lfc_lf *lf, const lfc_view *views, int32_t n, int32_t wo, int32_t ho, float *out,
-                  hipStream_t s) {
+// A render request resolved to one launch shape: decode-then-interpolate, or
+// per-tile footprint decode with a tile plan.
+struct RenderChoice {
+  bool decoded;
+  RenderPlan pl;
+};
+
+// cfg NULL or path LFC_RENDER_AUTO: the library's choice (render_decoded, and
+// the largest tile up to 64 x 16 whose footprint fits); LFC_RENDER_TILES with
+// tile_w x tile_h (0: 64 x 16, shrunk to fit) or LFC_RENDER_DECODED.
+lfc_status choose_render(const lfc_lf *lf, int32_t n, int32_t wo, int32_t ho, const lfc_render_config *cfg,
+                         RenderChoice &rc, const char *who) {
   const lfc::Geometry &g = lf->geo;
-  if (render_decoded(g, n, wo, ho)) {
-    // stream-ordered scratch for the decoded views (served from the pool after the first call)
-    int16_t *dec = nullptr;
-    const size_t bytes = (size_t)g.nv() * 3 * g.hp * g.wp * sizeof(int16_t);
-    if (hipMallocAsync(reinterpret_cast<void **>(&dec), bytes, s) != hipSuccess)
+  const int path = cfg ? cfg->path : LFC_RENDER_AUTO;
+  if (path != LFC_RENDER_AUTO && path != LFC_RENDER_TILES && path != LFC_RENDER_DECODED)
+    return fail(LFC_E_INVALID, std::string(who) + ": unknown render path");
+  rc.decoded = path == LFC_RENDER_AUTO ? render_decoded(g, n, wo, ho) : path == LFC_RENDER_DECODED;
+  if (rc.decoded) return LFC_OK;
+  int TX = 64, TY = 16;
+  bool shrink = true;
+  if (path == LFC_RENDER_TILES && (cfg->tile_w || cfg->tile_h)) {
+    if (cfg->tile_w < 1 || cfg->tile_h < 1 || cfg->tile_w > 1024 || cfg->tile_h > 1024)
+      return fail(LFC_E_INVALID, std::string(who) + ": tile_w and tile_h must be 1..1024 (or both 0)");
+    TX = cfg->tile_w;
+    TY = cfg->tile_h;
+    shrink = false;
+  }
+  if (!plan_render(g, wo, ho, rc.pl, TX, TY, shrink))
+    return fail(LFC_E_UNSUPPORTED, std::string(who) + (shrink ? ": output too strongly minified for the tile footprint"
+                                                             : ": the tile's source footprint exceeds 64 KB of LDS"));
+  return LFC_OK;
+}
+
+size_t decoded_bytes(const lfc::Geometry &g) { return (size_t)g.nv() * 3 * g.hp * g.wp * sizeof(int16_t); }
+
+// One render with a resolved choice.  The decoded path decodes into ws when
+// given, else into stream-ordered scratch (served from the pool after the
+// first call).
+template <int B>
+lfc_status render_with(const lfc_lf *lf, const lfc_view *views, int32_t n, int32_t wo, int32_t ho, float *out,
+                       const RenderChoice &rc, int16_t *ws, hipStream_t s) {
+  const lfc::Geometry &g = lf->geo;
+  if (rc.decoded) {
+    int16_t *dec = ws;
+    if (!dec && hipMallocAsync(reinterpret_cast<void **>(&dec), decoded_bytes(g), s) != hipSuccess)
       return fail(LFC_E_NOMEM, "lfc_render_views: scratch for the decoded views");
     lfc_status st = decode_images<B>(lf, dec, s);
     if (st == LFC_OK) {
@@ -1122,16 +1162,37 @@ lfc_status render(const lfc_lf *lf, const lfc_view *views, int32_t n, int32_t wo
       hipLaunchKernelGGL(k_interp, dim3((wo + kThreads - 1) / kThreads, ho, n), dim3(kThreads), 0, s, ia);
       st = launched("lfc_render_views");
     }
-    if (hipFreeAsync(dec, s) != hipSuccess && st == LFC_OK) st = fail(LFC_E_HIP, "lfc_render_views: scratch release");
+    if (!ws && hipFreeAsync(dec, s) != hipSuccess && st == LFC_OK)
+      st = fail(LFC_E_HIP, "lfc_render_views: scratch release");
     return st;
   }
-  RenderPlan pl;
-  if (!plan_render(g, wo, ho, pl))
-    return fail(LFC_E_UNSUPPORTED, "lfc_render_views: output too strongly minified for the tile footprint");
+  const RenderPlan &pl = rc.pl;
   RenderArgs a{ra_args(lf), views, out, wo, ho, g.U, g.V, g.W, g.H, pl.TX, pl.TY, pl.fbx, pl.fby};
   dim3 grid((wo + pl.TX - 1) / pl.TX, (ho + pl.TY - 1) / pl.TY, n);
   hipLaunchKernelGGL(k_render<B>, grid, dim3(kThreads), pl.lds, s, a);
   return launched("lfc_render_views");
+}
+
+lfc_status render_any(const lfc_lf *lf, const lfc_view *views, int32_t n, int32_t wo, int32_t ho, float *out,
+                      const RenderChoice &rc, int16_t *ws, hipStream_t s) {
+  switch (lf->geo.B) {
+    case 2: return render_with<2>(lf, views, n, wo, ho, out, rc, ws, s);
+    case 4: return render_with<4>(lf, views, n, wo, ho, out, rc, ws, s);
+    default: return render_with<8>(lf, views, n, wo, ho, out, rc, ws, s);
+  }
+}
+
+// Argument checks shared by the render entry points.
+lfc_status check_render(const lfc_lf *lf, const lfc_view *d_views, int32_t n, int32_t out_w, int32_t out_h,
+                        const float *d_out, const char *who) {
+  if (!lf) return fail(LFC_E_INVALID, std::string(who) + ": null handle");
+  if (lfc_status st = check_device(lf, who)) return st;
+  if (n < 0 || n > 65535) return fail(LFC_E_INVALID, std::string(who) + ": n must be 0..65535");
+  if (out_w < 1 || out_h < 1 || out_w > 16384 || out_h > 16384)
+    return fail(LFC_E_INVALID, std::string(who) + ": out_w and out_h must be 1..16384");
+  if (n == 0) return LFC_OK;
+  if (lfc_status st = check_buffer(d_views, (size_t)n * sizeof(lfc_view), 4, who, "d_views")) return st;
+  return check_buffer(d_out, (size_t)n * 3 * out_h * out_w * 4, 4, who, "d_out");
 }
 
 }  // namespace
@@ -1190,20 +1251,161 @@ extern "C" lfc_status lfc_decode_progressive(const lfc_lf *lf, const int32_t *d_
 
 extern "C" lfc_status lfc_render_views(const lfc_lf *lf, const lfc_view *d_views, int32_t n, int32_t out_w,
                                        int32_t out_h, float *d_out, hipStream_t s) {
+  return lfc_render_views_ex(lf, d_views, n, out_w, out_h, d_out, nullptr, s);
+}
+
+extern "C" lfc_status lfc_render_views_ex(const lfc_lf *lf, const lfc_view *d_views, int32_t n, int32_t out_w,
+                                          int32_t out_h, float *d_out, const lfc_render_config *cfg, hipStream_t s) {
   const char *who = "lfc_render_views";
-  if (!lf) return fail(LFC_E_INVALID, "lfc_render_views: null handle");
-  if (lfc_status st = check_device(lf, who)) return st;
-  if (n < 0 || n > 65535) return fail(LFC_E_INVALID, "lfc_render_views: n must be 0..65535");
-  if (out_w < 1 || out_h < 1 || out_w > 16384 || out_h > 16384)
-    return fail(LFC_E_INVALID, "lfc_render_views: out_w and out_h must be 1..16384");
+  if (lfc_status st = check_render(lf, d_views, n, out_w, out_h, d_out, who)) return st;
   if (n == 0) return LFC_OK;
-  if (lfc_status st = check_buffer(d_views, (size_t)n * sizeof(lfc_view), 4, who, "d_views")) return st;
-  if (lfc_status st = check_buffer(d_out, (size_t)n * 3 * out_h * out_w * 4, 4, who, "d_out")) return st;
-  switch (lf->geo.B) {
-    case 2: return render<2>(lf, d_views, n, out_w, out_h, d_out, s);
-    case 4: return render<4>(lf, d_views, n, out_w, out_h, d_out, s);
-    default: return render<8>(lf, d_views, n, out_w, out_h, d_out, s);
+  RenderChoice rc;
+  if (lfc_status st = choose_render(lf, n, out_w, out_h, cfg, rc, who)) return st;
+  return render_any(lf, d_views, n, out_w, out_h, d_out, rc, nullptr, s);
+}
+
+// Measured tuning: every candidate launch shape timed on the caller's views.
+extern "C" lfc_status lfc_render_tune(const lfc_lf *lf, const lfc_view *d_views, int32_t n, int32_t out_w,
+                                      int32_t out_h, float *d_out, int32_t reps, lfc_render_tuning *res,
+                                      hipStream_t s) {
+  const char *who = "lfc_render_tune";
+  if (!res) return fail(LFC_E_INVALID, "lfc_render_tune: null result");
+  if (lfc_status st = check_render(lf, d_views, n, out_w, out_h, d_out, who)) return st;
+  if (n < 1 || reps < 1 || reps > 1000) return fail(LFC_E_INVALID, "lfc_render_tune: need n >= 1 and reps 1..1000");
+  std::memset(res, 0, sizeof *res);
+  static const int kShapes[][2] = {{32, 8}, {32, 16}, {64, 8}, {64, 16}, {64, 32}, {128, 8}, {128, 16}, {256, 8}};
+  std::vector<lfc_render_config> cands;
+  cands.push_back(lfc_render_config{LFC_RENDER_DECODED, 0, 0});
+  for (const auto &sh : kShapes) {
+    RenderPlan pl;
+    if (plan_render(lf->geo, out_w, out_h, pl, sh[0], sh[1], false)) cands.push_back(lfc_render_config{LFC_RENDER_TILES, sh[0], sh[1]});
   }
+  int16_t *ws = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  lfc_status st = LFC_OK;
+  if (hipMalloc(reinterpret_cast<void **>(&ws), decoded_bytes(lf->geo)) != hipSuccess) {
+    ws = nullptr;
+    (void)hipGetLastError();      // clear the failed allocation's error
+    cands.erase(cands.begin());   // no room for the decoded views: tile shapes only
+  }
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = fail(LFC_E_HIP, "lfc_render_tune: events");
+  float best = 0.0f;
+  for (size_t i = 0; st == LFC_OK && i < cands.size() && res->n_tried < LFC_TUNE_MAX; i++) {
+    RenderChoice rc;
+    if (choose_render(lf, n, out_w, out_h, &cands[i], rc, who) != LFC_OK) continue;
+    st = render_any(lf, d_views, n, out_w, out_h, d_out, rc, ws, s);   // warm-up
+    if (st == LFC_OK && hipEventRecord(e0, s) != hipSuccess) st = fail(LFC_E_HIP, "lfc_render_tune: event record");
+    for (int r = 0; st == LFC_OK && r < reps; r++) st = render_any(lf, d_views, n, out_w, out_h, d_out, rc, ws, s);
+    float ms = 0.0f;
+    if (st == LFC_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      st = fail(LFC_E_HIP, "lfc_render_tune: timing");
+    if (st != LFC_OK) break;
+    const int k = res->n_tried++;
+    res->cfg[k] = cands[i];
+    res->ms[k] = ms / (float)reps;
+    if (k == 0 || res->ms[k] < best) {
+      best = res->ms[k];
+      res->best = k;
+    }
+  }
+  if (st == LFC_OK && res->n_tried == 0) st = fail(LFC_E_UNSUPPORTED, "lfc_render_tune: no launch shape fits this output");
+  if (hipStreamSynchronize(s) != hipSuccess && st == LFC_OK) st = fail(LFC_E_HIP, "lfc_render_tune: synchronize");
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (ws) (void)hipFree(ws);
+  return st;
+}
+
+// A render with everything fixed at creation, optionally captured in a graph.
+struct lfc_render_plan {
+  const lfc_lf *lf = nullptr;
+  const lfc_view *views = nullptr;
+  float *out = nullptr;
+  int32_t n = 0, w = 0, h = 0;
+  RenderChoice rc{};
+  int16_t *ws = nullptr;            // decoded views (decoded path)
+  hipStream_t cap = nullptr;        // stream the graph was captured on
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" void lfc_render_plan_destroy(lfc_render_plan *p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  if (p->ws) (void)hipFree(p->ws);
+  delete p;
+}
+
+extern "C" lfc_status lfc_render_plan_create(const lfc_lf *lf, const lfc_render_config *cfg, const lfc_view *d_views,
+                                             int32_t n, int32_t out_w, int32_t out_h, float *d_out, int32_t graph,
+                                             lfc_render_plan **out) {
+  const char *who = "lfc_render_plan_create";
+  if (!out) return fail(LFC_E_INVALID, "lfc_render_plan_create: null result");
+  *out = nullptr;
+  if (lfc_status st = check_render(lf, d_views, n, out_w, out_h, d_out, who)) return st;
+  if (n < 1) return fail(LFC_E_INVALID, "lfc_render_plan_create: n must be 1..65535");
+  lfc_render_plan *p = new (std::nothrow) lfc_render_plan;
+  if (!p) return fail(LFC_E_NOMEM, "lfc_render_plan_create: out of host memory");
+  p->lf = lf;
+  p->views = d_views;
+  p->out = d_out;
+  p->n = n;
+  p->w = out_w;
+  p->h = out_h;
+  lfc_status st = choose_render(lf, n, out_w, out_h, cfg, p->rc, who);
+  if (st == LFC_OK && p->rc.decoded) {
+    hipError_t he = hipMalloc(reinterpret_cast<void **>(&p->ws), decoded_bytes(lf->geo));
+    if (he != hipSuccess) {
+      p->ws = nullptr;
+      st = fail(he == hipErrorOutOfMemory ? LFC_E_NOMEM : LFC_E_HIP, "lfc_render_plan_create: decoded views");
+    }
+  }
+  if (st == LFC_OK && graph) {
+    (void)max_lds_bytes();   // device query done before the capture
+    if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
+      p->cap = nullptr;
+      st = fail(LFC_E_HIP, "lfc_render_plan_create: capture stream");
+    } else if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed) != hipSuccess) {
+      st = fail(LFC_E_HIP, "lfc_render_plan_create: begin capture");
+    } else {
+      st = render_any(lf, d_views, n, out_w, out_h, d_out, p->rc, p->ws, p->cap);
+      hipGraph_t g = nullptr;
+      const hipError_t he = hipStreamEndCapture(p->cap, &g);
+      p->graph = g;
+      if (st == LFC_OK && (he != hipSuccess || !g)) st = fail(LFC_E_HIP, "lfc_render_plan_create: end capture");
+      if (st == LFC_OK && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) {
+        p->exec = nullptr;
+        st = fail(LFC_E_HIP, "lfc_render_plan_create: graph instantiation");
+      }
+    }
+  }
+  if (st != LFC_OK) {
+    lfc_render_plan_destroy(p);
+    return st;
+  }
+  *out = p;
+  return LFC_OK;
+}
+
+extern "C" lfc_status lfc_render_plan_launch(lfc_render_plan *p, hipStream_t s) {
+  if (!p) return fail(LFC_E_INVALID, "lfc_render_plan_launch: null plan");
+  if (lfc_status st = check_device(p->lf, "lfc_render_plan_launch")) return st;
+  if (p->exec) {
+    if (hipGraphLaunch(p->exec, s) != hipSuccess) return fail(LFC_E_HIP, "lfc_render_plan_launch: graph launch");
+    return LFC_OK;
+  }
+  return render_any(p->lf, p->views, p->n, p->w, p->h, p->out, p->rc, p->ws, s);
+}
+
+extern "C" lfc_status lfc_render_plan_info(const lfc_render_plan *p, lfc_render_config *cfg, int32_t *graph) {
+  if (!p || !cfg || !graph) return fail(LFC_E_INVALID, "lfc_render_plan_info: null argument");
+  *cfg = p->rc.decoded ? lfc_render_config{LFC_RENDER_DECODED, 0, 0}
+                       : lfc_render_config{LFC_RENDER_TILES, p->rc.pl.TX, p->rc.pl.TY};
+  *graph = p->exec != nullptr;
+  return LFC_OK;
 }
 
 namespace lfc {

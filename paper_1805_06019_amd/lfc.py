@@ -67,6 +67,21 @@ class c_render_request(C.Structure):
     _fields_ = [("lf", C.c_int32), ("out_w", C.c_int32), ("out_h", C.c_int32), ("view", c_view)]
 
 
+class c_render_config(C.Structure):
+    _fields_ = [("path", C.c_int32), ("tile_w", C.c_int32), ("tile_h", C.c_int32)]
+
+
+TUNE_MAX = 16
+
+
+class c_render_tuning(C.Structure):
+    _fields_ = [("n_tried", C.c_int32), ("best", C.c_int32), ("cfg", c_render_config * TUNE_MAX),
+                ("ms", C.c_float * TUNE_MAX)]
+
+
+RENDER_AUTO, RENDER_TILES, RENDER_DECODED = 0, 1, 2
+
+
 class c_server_config(C.Structure):
     _fields_ = [("max_batch", C.c_int32), ("streams", C.c_int32), ("out_pool_bytes", C.c_int64)]
 
@@ -131,6 +146,14 @@ def load() -> C.CDLL:
         L.lfc_stage_needs.argtypes = [vp, vp, i64]
         L.lfc_stage_needs.restype = i64
         L.lfc_render_views.argtypes = [vp, vp, i32, i32, i32, vp, vp]
+        L.lfc_render_views_ex.argtypes = [vp, vp, i32, i32, i32, vp, C.POINTER(c_render_config), vp]
+        L.lfc_render_tune.argtypes = [vp, vp, i32, i32, i32, vp, i32, C.POINTER(c_render_tuning), vp]
+        L.lfc_render_plan_create.argtypes = [vp, C.POINTER(c_render_config), vp, i32, i32, i32, vp, i32,
+                                             C.POINTER(vp)]
+        L.lfc_render_plan_launch.argtypes = [vp, vp]
+        L.lfc_render_plan_info.argtypes = [vp, C.POINTER(c_render_config), C.POINTER(i32)]
+        L.lfc_render_plan_destroy.argtypes = [vp]
+        L.lfc_render_plan_destroy.restype = None
         L.lfc_check.argtypes = [vp, vp]
         L.lfc_close.argtypes = [vp]
         L.lfc_last_error.argtypes = []
@@ -149,7 +172,8 @@ def load() -> C.CDLL:
         L.lfc_server_get_stats.argtypes = [vp, C.POINTER(c_server_stats)]
         L.lfc_server_destroy.argtypes = [vp]
         for f in ("lfc_encode", "lfc_encode_ex", "lfc_validate", "lfc_open", "lfc_info", "lfc_decode_blocks",
-                  "lfc_render_views", "lfc_check", "lfc_close", "lfc_decode_progressive", "lfc_batch_create",
+                  "lfc_render_views", "lfc_render_views_ex", "lfc_render_tune", "lfc_render_plan_create",
+                  "lfc_render_plan_launch", "lfc_render_plan_info", "lfc_check", "lfc_close", "lfc_decode_progressive", "lfc_batch_create",
                   "lfc_batch_decode", "lfc_batch_check", "lfc_batch_render",
                   "lfc_batch_destroy", "lfc_server_create", "lfc_server_submit", "lfc_server_wait",
                   "lfc_server_release", "lfc_server_replay", "lfc_server_get_stats", "lfc_server_destroy"):
@@ -300,9 +324,7 @@ def lfc_decode_progressive(lf: LightField, req, level: int, out=None, cuda_strea
     return out
 
 
-def lfc_render_views(lf: LightField, views, out_w: int, out_h: int, out=None, cuda_stream=None):
-    """Renders novel views: views float32 CUDA tensor [n][4] = (u, v, s, t).
-    Returns float32 CUDA [n][3][out_h][out_w], RGB / 255."""
+def _render_buffers(views, out_w: int, out_h: int, out):
     import torch
     assert views.dtype == torch.float32 and views.is_cuda and views.is_contiguous() and views.shape[-1] == 4
     n = views.shape[0]
@@ -310,9 +332,72 @@ def lfc_render_views(lf: LightField, views, out_w: int, out_h: int, out=None, cu
         out = torch.empty((n, 3, out_h, out_w), dtype=torch.float32, device="cuda")
     assert out.dtype == torch.float32 and out.is_cuda and out.is_contiguous()
     assert tuple(out.shape) == (n, 3, out_h, out_w)
-    _check(load().lfc_render_views(lf.handle, views.data_ptr(), n, out_w, out_h, out.data_ptr(),
-                                   _stream_ptr(cuda_stream)))
+    return n, out
+
+
+def _config(cfg):
+    """None, or (path, tile_w, tile_h)."""
+    return None if cfg is None else C.byref(c_render_config(*cfg))
+
+
+def lfc_render_views(lf: LightField, views, out_w: int, out_h: int, out=None, cuda_stream=None, cfg=None):
+    """Renders novel views: views float32 CUDA tensor [n][4] = (u, v, s, t).
+    Returns float32 CUDA [n][3][out_h][out_w], RGB / 255.  cfg: None
+    (automatic) or (path, tile_w, tile_h) with path RENDER_TILES or
+    RENDER_DECODED."""
+    n, out = _render_buffers(views, out_w, out_h, out)
+    if cfg is None:
+        _check(load().lfc_render_views(lf.handle, views.data_ptr(), n, out_w, out_h, out.data_ptr(),
+                                       _stream_ptr(cuda_stream)))
+    else:
+        _check(load().lfc_render_views_ex(lf.handle, views.data_ptr(), n, out_w, out_h, out.data_ptr(),
+                                          _config(cfg), _stream_ptr(cuda_stream)))
     return out
+
+
+def lfc_render_tune(lf: LightField, views, out_w: int, out_h: int, out=None, reps: int = 5, cuda_stream=None):
+    """Times every render launch shape on these views; returns (best config,
+    [(config, ms per launch)]) with configs as (path, tile_w, tile_h)."""
+    n, out = _render_buffers(views, out_w, out_h, out)
+    res = c_render_tuning()
+    _check(load().lfc_render_tune(lf.handle, views.data_ptr(), n, out_w, out_h, out.data_ptr(), reps,
+                                  C.byref(res), _stream_ptr(cuda_stream)))
+    tried = [((res.cfg[i].path, res.cfg[i].tile_w, res.cfg[i].tile_h), float(res.ms[i])) for i in range(res.n_tried)]
+    return tried[res.best][0], tried
+
+
+class RenderPlan:
+    """One render with its launch shape and buffers fixed, optionally
+    captured in a HIP graph (launch() is then one graph launch).  The views
+    tensor is read at each launch; rewrite it in place between launches."""
+
+    def __init__(self, lf: LightField, views, out_w: int, out_h: int, out=None, cfg=None, graph: bool = True):
+        n, self.out = _render_buffers(views, out_w, out_h, out)
+        self.views, self.lf = views, lf
+        h = C.c_void_p()
+        _check(load().lfc_render_plan_create(lf.handle, _config(cfg), views.data_ptr(), n, out_w, out_h,
+                                             self.out.data_ptr(), int(graph), C.byref(h)))
+        self.handle = h.value
+
+    def launch(self, cuda_stream=None):
+        _check(load().lfc_render_plan_launch(self.handle, _stream_ptr(cuda_stream)))
+        return self.out
+
+    def info(self):
+        c, g = c_render_config(), C.c_int32()
+        _check(load().lfc_render_plan_info(self.handle, C.byref(c), C.byref(g)))
+        return (c.path, c.tile_w, c.tile_h), bool(g.value)
+
+    def close(self) -> None:
+        h, self.handle = self.handle, None
+        if h:
+            load().lfc_render_plan_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def lfc_check(lf: LightField, cuda_stream=None) -> None:

@@ -229,3 +229,20 @@ def test_batch_and_server_argument_errors_on_host():
     assert lib.lfc_server_release(None, 1) == -1
     assert lib.lfc_server_replay(None, None, None, 0, None) == -1
     assert lib.lfc_server_get_stats(None, None) == -1
+
+
+def test_render_plan_and_tune_argument_errors_on_host():
+    # checks that come before any device call
+    lib = lfc.load()
+    plan = C.c_void_p(123)
+    assert lib.lfc_render_plan_create(None, None, None, 1, 8, 8, None, 1, C.byref(plan)) == -1
+    assert plan.value is None   # cleared on failure
+    assert lib.lfc_render_plan_create(None, None, None, 1, 8, 8, None, 1, None) == -1
+    assert lib.lfc_render_plan_launch(None, None) == -1
+    cfg, g = lfc.c_render_config(), C.c_int32()
+    assert lib.lfc_render_plan_info(None, C.byref(cfg), C.byref(g)) == -1
+    lib.lfc_render_plan_destroy(None)
+    res = lfc.c_render_tuning()
+    assert lib.lfc_render_tune(None, None, 1, 8, 8, None, 5, C.byref(res), None) == -1
+    assert lib.lfc_render_tune(None, None, 1, 8, 8, None, 5, None, None) == -1
+    assert lib.lfc_render_views_ex(None, None, 0, 1, 1, None, None, None) == -1
