@@ -129,6 +129,129 @@ typedef struct {
 lfc_status lfc_encode_ex(const uint8_t *rgb, const lfc_params *p, void **stream_out, size_t *bytes_out,
                          lfc_encode_stats *stats);
 
+/*
+ * Learned encoder control.  The paper's encoder applies one pixel threshold
+ * and one block-energy threshold to every residual block (Sec. 3.2) and
+ * names the lack of finer control as a limitation (Sec. 6).  Here each
+ * residual block (node, spatial block, channel: a control row) gets its own
+ * decision; the decoder is unchanged, since the stream carries only the
+ * stored values and their range codes.
+ *
+ * Threshold classes 0..8 apply the pixel threshold 0, 2, 3, 4, 5, 6, 8, 12 or
+ * 16 (residuals of smaller magnitude become 0), then the quantiser; the
+ * block is stored if a value is nonzero.  Class 9 (LFC_CTL_DROP) drops it.
+ * Range classes are the BISE range codes 0..25, or 26 (LFC_CTL_ABSENT).
+ *
+ * Modes (params' pix_threshold and blk_threshold are used by GLOBAL only):
+ *  LFC_CTL_GLOBAL  the paper's global thresholds (= lfc_encode_ex).
+ *  LFC_CTL_SEARCH  exhaustive search: per row, the threshold class of least
+ *                  cost w_c * SSE * 2^16 + lambda_q16 * rate, where SSE is
+ *                  the squared error of the reconstructed block against the
+ *                  block being coded, w_c = 6 for Y and 1 for Co and Cg (the
+ *                  weights of eq. 4), rate = 5 + BISE payload bits (0 when
+ *                  absent); ties go to the lower class.  The block takes the
+ *                  smallest allowed range holding its values.
+ *  LFC_CTL_TABLE   replays classes[] and ranges[] (e.g. those an earlier
+ *                  call used): the threshold class, then the values clamped
+ *                  into the given range's bound and stored with that range
+ *                  code (absent if none is nonzero, or if the range class is
+ *                  26).
+ *  LFC_CTL_MLP     a per-block network (lfc_mlp_infer, on the GPU, weights
+ *                  d_mlp) predicts both classes from the row's 16 features;
+ *                  they are applied as in TABLE (a range the mask excludes
+ *                  is replaced by the values' own range).  Rows whose top
+ *                  threshold-class probability is below min_confidence, or
+ *                  whose prediction would leave int16, fall back to the
+ *                  search (counted in fallbacks).
+ * Rows are ordered by level from L-2 down to 0, then node (row-major in the
+ * level's grid), spatial block, channel; lfc_control_rows gives the count.
+ * The features of a row (float32, from the residuals v = block - parent
+ * reconstruction and the parent reconstruction p): level/4, [channel is Y],
+ * log2(1+mean|v|)/8, log2(1+max|v|)/8, log2(1+var|v|)/16, fractions of |v|
+ * at least 2, 4, 8 and 16, log2(1+mean horizontal |dp|)/8, log2(1+mean
+ * vertical |dp|)/8, log2(1+max |dp|)/8, log2(1+var p)/16, quant_bits/4,
+ * log2(1+lambda)/24 with lambda = lambda_q16/2^16, block/8.
+ */
+enum { LFC_CTL_GLOBAL = 0, LFC_CTL_SEARCH = 1, LFC_CTL_TABLE = 2, LFC_CTL_MLP = 3 };
+#define LFC_CTL_CLASSES 10
+#define LFC_CTL_DROP 9
+#define LFC_CTL_RANGES 27
+#define LFC_CTL_ABSENT 26
+#define LFC_CTL_FEATURES 16
+typedef struct {
+  int32_t mode;
+  float min_confidence;      /* MLP: search below this top probability (0: never) */
+  int64_t lambda_q16;        /* rate weight * 2^16, 0..2^52 (SEARCH, MLP, features) */
+  const void *d_mlp;         /* MLP: device weights, LFC_MLP_PARAMS bf16 */
+  hipStream_t stream;        /* MLP: stream of the inference launches */
+  int64_t rows;              /* length of every array below that is given */
+  int8_t *classes;           /* TABLE: in; else out (may be NULL): threshold class used */
+  int8_t *ranges;            /* TABLE: in; else out (may be NULL): range class used */
+  float *features;           /* out (may be NULL): [rows][16] */
+  int8_t *search_classes;    /* out (may be NULL): the search's threshold class */
+  int8_t *search_ranges;     /* out (may be NULL): the search's range class */
+  int64_t fallbacks;         /* out: rows the search decided in MLP mode */
+} lfc_control;
+
+/* Control rows of an encoding: sum over levels 0..L-2 of nodes * NB * 3;
+ * -1 for invalid parameters. */
+int64_t lfc_control_rows(const lfc_params *p);
+
+/*
+ * lfc_encode_ex under a control mode.  Host memory in and out; MLP mode also
+ * runs the network on the current device, on ctl->stream, and blocks until
+ * it is done.
+ * Errors: LFC_E_INVALID (null pointer, unknown mode, lambda out of range,
+ * rows mismatch, TABLE without both tables or with an entry out of range or
+ * a range the mask excludes, MLP without weights, GLOBAL with tables),
+ * LFC_E_RANGE (as lfc_encode; in TABLE mode also a reconstruction leaving
+ * int16), LFC_E_NOMEM, LFC_E_HIP (MLP inference).
+ */
+lfc_status lfc_encode_ctl(const uint8_t *rgb, const lfc_params *p, lfc_control *ctl, void **stream_out,
+                          size_t *bytes_out, lfc_encode_stats *stats);
+
+/*
+ * The per-block network: 16 features -> 64 ReLU -> 64 ReLU -> 37 logits
+ * (10 threshold classes, then 27 range classes).  Parameters, in this
+ * order: W1[64][16], b1[64], W2[64][64], b2[64], W3[37][64], b3[37]
+ * (LFC_MLP_PARAMS values).  Inference keeps them as bfloat16 and
+ * accumulates in float32; training keeps float32 master weights and Adam
+ * moments and re-rounds the bfloat16 copy after each update.
+ */
+#define LFC_MLP_PARAMS 7653
+
+/*
+ * Inference over n feature rows (device float32 [n][16]): per row the
+ * argmax of each head (ties to the lower class) into d_cls and d_rng
+ * (int8 [n]), the threshold head's top softmax probability into d_conf
+ * (float [n], may be NULL) and the 37 logits into d_logits (float [n][37],
+ * may be NULL).  d_w: device bf16 [LFC_MLP_PARAMS].
+ * Errors: LFC_E_INVALID (null pointer, n < 0), LFC_E_HIP.
+ */
+lfc_status lfc_mlp_infer(const uint16_t *d_w, const float *d_x, int64_t n, int8_t *d_cls, int8_t *d_rng,
+                         float *d_conf, float *d_logits, hipStream_t s);
+
+/*
+ * Mean gradient over a batch of n rows of the loss cross-entropy(threshold
+ * head, d_cls) + cross-entropy(range head, d_rng), at the bf16 weights d_w.
+ * d_part: device float [ceil(n/128)][LFC_MLP_PARAMS] scratch (per-workgroup
+ * partial sums); d_grad: device float [LFC_MLP_PARAMS] out; d_loss: device
+ * float [1] out, the mean loss.  Labels outside 0..9 / 0..26 are errors
+ * reported by a zero-gradient row and a loss of NaN.
+ * Errors: LFC_E_INVALID (null pointer, n < 1), LFC_E_HIP.
+ */
+lfc_status lfc_mlp_grad(const uint16_t *d_w, const float *d_x, const int8_t *d_cls, const int8_t *d_rng, int32_t n,
+                        float *d_part, float *d_grad, float *d_loss, hipStream_t s);
+
+/*
+ * One Adam step (bias-corrected, step >= 1) on the float32 master weights
+ * d_master with moments d_m, d_v (device float [LFC_MLP_PARAMS] each) and
+ * gradient d_grad, then d_w = the master rounded to bfloat16 (to nearest,
+ * ties to even).  Errors: LFC_E_INVALID (null pointer, step < 1), LFC_E_HIP.
+ */
+lfc_status lfc_mlp_adam(float *d_master, uint16_t *d_w, float *d_m, float *d_v, const float *d_grad, int32_t step,
+                        float lr, float beta1, float beta2, float eps, hipStream_t s);
+
 /* Frees a buffer returned by lfc_encode.  NULL is ignored. */
 void lfc_free(void *ptr);
 

@@ -36,6 +36,15 @@ class _Params(C.Structure):
     ]
 
 
+class _Control(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("lambda_q16", C.c_int64),
+                ("classes_in", C.c_void_p), ("ranges_in", C.c_void_p),
+                ("classes_out", C.c_void_p), ("ranges_out", C.c_void_p), ("features_out", C.c_void_p)]
+
+
+CTL_GLOBAL, CTL_SEARCH, CTL_TABLE = 0, 1, 2
+
+
 class _Geom(C.Structure):
     _fields_ = [
         ("wp", C.c_int32), ("hp", C.c_int32),
@@ -113,6 +122,8 @@ def lib() -> C.CDLL:
         L.orc_tree_tables.argtypes = [C.POINTER(_Params), vp, vp]
         L.orc_rkv_tree.argtypes = [vp, C.POINTER(_Params), vp]
         L.orc_encode.argtypes = [vp, C.POINTER(_Params), C.POINTER(C.c_void_p), C.POINTER(i64), vp, vp, vp]
+        L.orc_encode_ctl.argtypes = [vp, C.POINTER(_Params), C.POINTER(_Control), C.POINTER(C.c_void_p),
+                                     C.POINTER(i64), vp, vp, vp]
         L.orc_free.argtypes = [vp]
         L.orc_free.restype = None
         L.orc_read_header.argtypes = [vp, i64, C.POINTER(_Params), C.POINTER(_Geom)]
@@ -264,6 +275,47 @@ def encode(rgb: np.ndarray, p: Params, want_planes: bool = True) -> Encoded:
     finally:
         lib().orc_free(out)
     return Encoded(data, r0, ycc, hist)
+
+
+def control_rows(p: Params) -> int:
+    """Residual (node, block, channel) triples: one encoder decision each."""
+    g = geometry(p)
+    return sum(g.lu[l] * g.lv[l] for l in range(p.levels - 1)) * g.nb * 3
+
+
+def encode_ctl(rgb: np.ndarray, p: Params, mode: int, lambda_q16: int = 0, classes=None, ranges=None,
+               want_features: bool = False):
+    """Encoder under per-block control (see oracle.h): returns (Encoded,
+    threshold classes used, range classes used, features or None)."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+    assert rgb.shape == (p.grid_v, p.grid_u, p.height, p.width, 3), rgb.shape
+    g = geometry(p)
+    nv = p.grid_u * p.grid_v
+    rows = control_rows(p)
+    r0 = np.zeros((nv, 3, g.hp, g.wp), dtype=np.int16)
+    hist = np.zeros(26, dtype=np.int64)
+    cls_out = np.full(rows, -1, dtype=np.int8)
+    rng_out = np.full(rows, -1, dtype=np.int8)
+    feat = np.zeros((rows, 16), dtype=np.float32) if want_features else None
+    ctl = _Control()
+    ctl.mode, ctl.lambda_q16 = mode, lambda_q16
+    if mode == CTL_TABLE:
+        classes = np.ascontiguousarray(classes, dtype=np.int8)
+        ranges = np.ascontiguousarray(ranges, dtype=np.int8)
+        assert classes.size == rows and ranges.size == rows
+        ctl.classes_in, ctl.ranges_in = _ptr(classes), _ptr(ranges)
+    ctl.classes_out, ctl.ranges_out = _ptr(cls_out), _ptr(rng_out)
+    ctl.features_out = _ptr(feat) if feat is not None else None
+    out = C.c_void_p()
+    nbytes = C.c_int64()
+    st = lib().orc_encode_ctl(_ptr(rgb), C.byref(p.c()), C.byref(ctl), C.byref(out), C.byref(nbytes),
+                              _ptr(r0), None, _ptr(hist))
+    _check(st, "orc_encode_ctl")
+    try:
+        data = C.string_at(out.value, nbytes.value)
+    finally:
+        lib().orc_free(out)
+    return Encoded(data, r0, None, hist), cls_out, rng_out, feat
 
 
 def _sbuf(stream: bytes) -> np.ndarray:

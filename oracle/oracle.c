@@ -538,9 +538,140 @@ int orc_read_header(const uint8_t *stream, int64_t bytes, orc_params *p, orc_geo
 
 void orc_free(void *ptr) { free(ptr); }
 
+/* ------------------------------------------------------------------ */
+/* per-block encoder control (learned encoder control; the paper's     */
+/* encoder uses one pixel and one block-energy threshold, Sec. 3.2)    */
+/* ------------------------------------------------------------------ */
+
+/* pixel threshold of threshold classes 0..8; class 9 drops the block */
+static const int ctl_tau[9] = {0, 2, 3, 4, 5, 6, 8, 12, 16};
+
+/* One option for one block: the residual r = own - par under threshold class
+ * k, quantised; with range code `forced` >= 0 the values are limited to what
+ * that code can hold (zigzag value below its bound) and it becomes the code;
+ * otherwise the block takes the smallest allowed range.  Fills the values,
+ * the code (-1 absent), the squared error of the reconstruction par +
+ * value * 2^q against own, and the rate (5 code bits + BISE payload bits, or
+ * 0).  Returns 0 if the option is usable (a range exists and the
+ * reconstruction stays in int16). */
+static int ctl_option(const int32_t *own, const int32_t *par, int S, int q, uint32_t mask, int k, int forced,
+                      int32_t *vals, int *code, int64_t *sse, int64_t *rate) {
+  int usable = 1, any = 0;
+  int32_t zmax = 0;
+  for (int i = 0; i < S; i++) {
+    int32_t r = own[i] - par[i];
+    int32_t x;
+    if (k == 9 || forced == 26) {
+      x = 0;
+    } else {
+      if (iabs32(r) < ctl_tau[k]) r = 0;
+      x = orc_quantize(r, q);
+      if (forced >= 0) {
+        int bound;
+        orc_bise_range(forced, NULL, NULL, &bound);
+        /* largest |x| whose zigzag value is below the bound, per sign */
+        while (orc_zigzag(x) >= bound) x += x > 0 ? -1 : 1;
+      }
+    }
+    vals[i] = x;
+    if (x != 0) any = 1;
+    if (orc_zigzag(x) > zmax) zmax = orc_zigzag(x);
+  }
+  *code = -1;
+  if (any) {
+    if (forced >= 0 && forced < 26) {
+      *code = forced;
+    } else {
+      int bestn = 0;
+      for (int c = 0; c < 26; c++) {
+        int bound;
+        orc_bise_range(c, NULL, NULL, &bound);
+        if (((mask >> c) & 1u) && bound > zmax && (*code < 0 || bound < bestn)) {
+          *code = c;
+          bestn = bound;
+        }
+      }
+      if (*code < 0) usable = 0;
+    }
+  }
+  if (*code < 0)
+    for (int i = 0; i < S; i++) vals[i] = 0;
+  *rate = *code >= 0 ? 5 + orc_bise_bits(*code, S) : 0;
+  *sse = 0;
+  for (int i = 0; i < S; i++) {
+    int32_t rec = par[i] + vals[i] * (1 << q);
+    if (rec < -32768 || rec > 32767) usable = 0;
+    int64_t d = (int64_t)own[i] - rec;
+    *sse += d * d;
+  }
+  return usable;
+}
+
+/* the 16 features of a block decision (see oracle.h) */
+static void ctl_features(const int32_t *own, const int32_t *par, int B, int level, int c, int q, int64_t lambda_q16,
+                         float *f) {
+  int S = B * B;
+  double sum = 0, sum2 = 0, mx = 0, n2 = 0, n4 = 0, n8 = 0, n16 = 0;
+  for (int i = 0; i < S; i++) {
+    double a = iabs32(own[i] - par[i]);
+    sum += a;
+    sum2 += a * a;
+    if (a > mx) mx = a;
+    n2 += a >= 2;
+    n4 += a >= 4;
+    n8 += a >= 8;
+    n16 += a >= 16;
+  }
+  double hsum = 0, vsum = 0, gmx = 0, psum = 0, psum2 = 0;
+  for (int y = 0; y < B; y++)
+    for (int x = 0; x < B; x++) {
+      double pv = par[y * B + x];
+      psum += pv;
+      psum2 += pv * pv;
+      if (x + 1 < B) {
+        double d = fabs((double)par[y * B + x + 1] - pv);
+        hsum += d;
+        if (d > gmx) gmx = d;
+      }
+      if (y + 1 < B) {
+        double d = fabs((double)par[(y + 1) * B + x] - pv);
+        vsum += d;
+        if (d > gmx) gmx = d;
+      }
+    }
+  double mean = sum / S, var = sum2 / S - mean * mean, pmean = psum / S, pvar = psum2 / S - pmean * pmean;
+  if (var < 0) var = 0;
+  if (pvar < 0) pvar = 0;
+  double pairs = (double)B * (B - 1);
+  f[0] = (float)(level / 4.0);
+  f[1] = c == 0 ? 1.0f : 0.0f;
+  f[2] = (float)(log2(1.0 + mean) / 8.0);
+  f[3] = (float)(log2(1.0 + mx) / 8.0);
+  f[4] = (float)(log2(1.0 + var) / 16.0);
+  f[5] = (float)(n2 / S);
+  f[6] = (float)(n4 / S);
+  f[7] = (float)(n8 / S);
+  f[8] = (float)(n16 / S);
+  f[9] = (float)(log2(1.0 + hsum / pairs) / 8.0);
+  f[10] = (float)(log2(1.0 + vsum / pairs) / 8.0);
+  f[11] = (float)(log2(1.0 + gmx) / 8.0);
+  f[12] = (float)(log2(1.0 + pvar) / 16.0);
+  f[13] = (float)(q / 4.0);
+  f[14] = (float)(log2(1.0 + (double)lambda_q16 / 65536.0) / 24.0);
+  f[15] = (float)(B / 8.0);
+}
+
 int orc_encode(const uint8_t *rgb, const orc_params *pin, uint8_t **out, int64_t *bytes,
                int16_t *r0_out, int16_t *ycocg_out, int64_t *hist) {
+  return orc_encode_ctl(rgb, pin, NULL, out, bytes, r0_out, ycocg_out, hist);
+}
+
+int orc_encode_ctl(const uint8_t *rgb, const orc_params *pin, orc_control *ctl, uint8_t **out, int64_t *bytes,
+                   int16_t *r0_out, int16_t *ycocg_out, int64_t *hist) {
   if (!rgb || !pin || !out || !bytes) return ORC_E_INVALID;
+  int mode = ctl ? ctl->mode : ORC_CTL_GLOBAL;
+  if (mode < ORC_CTL_GLOBAL || mode > ORC_CTL_TABLE) return ORC_E_INVALID;
+  if (mode == ORC_CTL_TABLE && (!ctl->classes_in || !ctl->ranges_in)) return ORC_E_INVALID;
   orc_params p = *pin;
   orc_geom g;
   int st = orc_geometry(&p, &g);
@@ -568,6 +699,7 @@ int orc_encode(const uint8_t *rgb, const orc_params *pin, uint8_t **out, int64_t
   int8_t *code_of = (int8_t *)malloc((size_t)(nsb > 0 ? nsb : 1));
   uint16_t *zv = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)(nsb > 0 ? nsb * S : 1));
   if (!code_of || !zv) { st = ORC_E_NOMEM; goto done; }
+  int64_t row = 0; /* control row: levels top-down, node, block, channel */
   for (int l = L - 2; l >= 0; l--) {
     rec[l] = (int32_t *)malloc(sizeof(int32_t) * (size_t)(img * t.lu[l] * t.lv[l]));
     if (!rec[l]) { st = ORC_E_NOMEM; goto done; }
@@ -586,6 +718,55 @@ int orc_encode(const uint8_t *rgb, const orc_params *pin, uint8_t **out, int64_t
             int32_t r[64], qv[64];
             for (int i = 0; i < S; i++)
               pix[i] = (int64_t)c * plane + (int64_t)(by * B + i / B) * g.wp + (bx * B + i % B);
+            int64_t key = ((int64_t)s * g.nb + b) * 3 + c;
+            if (mode != ORC_CTL_GLOBAL) {
+              int32_t ob[64], pb[64];
+              for (int i = 0; i < S; i++) {
+                ob[i] = own[pix[i]];
+                pb[i] = par[pix[i]];
+              }
+              if (ctl->features_out) ctl_features(ob, pb, B, l, c, q, ctl->lambda_q16, ctl->features_out + row * 16);
+              int cls = -1, code = -1;
+              if (mode == ORC_CTL_SEARCH) {
+                /* least w_c * SSE * 2^16 + lambda_q16 * rate; the first class wins ties */
+                int64_t best = 0;
+                for (int k = 0; k < 10; k++) {
+                  int32_t vk[64];
+                  int ck;
+                  int64_t sse, rate;
+                  if (!ctl_option(ob, pb, S, q, mask, k, -1, vk, &ck, &sse, &rate)) continue;
+                  int64_t cost = (c == 0 ? 6 : 1) * sse * 65536 + ctl->lambda_q16 * rate;
+                  if (cls < 0 || cost < best) {
+                    best = cost;
+                    cls = k;
+                    code = ck;
+                    memcpy(qv, vk, sizeof(int32_t) * S);
+                  }
+                }
+              } else {
+                int64_t sse, rate;
+                cls = ctl->classes_in[row];
+                int rg = ctl->ranges_in[row];
+                if (cls < 0 || cls > 9 || rg < 0 || rg > 26 || (rg < 26 && !((mask >> rg) & 1u))) {
+                  st = ORC_E_INVALID;
+                  goto done;
+                }
+                if (!ctl_option(ob, pb, S, q, mask, cls, rg, qv, &code, &sse, &rate)) {
+                  st = ORC_E_RANGE;
+                  goto done;
+                }
+              }
+              if (ctl->classes_out) ctl->classes_out[row] = (int8_t)cls;
+              if (ctl->ranges_out) ctl->ranges_out[row] = (int8_t)(code < 0 ? 26 : code);
+              row++;
+              code_of[key] = (int8_t)code;
+              if (code >= 0) {
+                if (hist) hist[code]++;
+                for (int i = 0; i < S; i++) zv[key * S + i] = (uint16_t)orc_zigzag(qv[i]);
+              }
+              for (int i = 0; i < S; i++) dst[pix[i]] = par[pix[i]] + (code >= 0 ? qv[i] * (1 << q) : 0);
+              continue;
+            }
             /* residual and pixel-level threshold (reading C7) */
             int64_t energy = 0;
             for (int i = 0; i < S; i++) {
@@ -605,7 +786,6 @@ int orc_encode(const uint8_t *rgb, const orc_params *pin, uint8_t **out, int64_t
               }
               present = any;
             }
-            int64_t key = ((int64_t)s * g.nb + b) * 3 + c;
             code_of[key] = -1;
             if (present) {
               /* the smallest allowed range that holds every value (C10) */

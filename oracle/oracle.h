@@ -91,6 +91,34 @@ int orc_rkv_tree(const uint8_t *rgb, const orc_params *p, int32_t *out);
  * receives the per-range-code block counts. */
 int orc_encode(const uint8_t *rgb, const orc_params *p, uint8_t **out, int64_t *bytes,
                int16_t *r0, int16_t *ycocg, int64_t *hist);
+
+/* Per-block encoder control.  Threshold classes 0..8: pixel threshold 0, 2,
+ * 3, 4, 5, 6, 8, 12, 16, then the quantiser, the block stored if a value is
+ * nonzero; class 9: the block dropped.  Range classes: BISE codes 0..25, 26 =
+ * absent.  SEARCH takes, per (node, block, channel), the class of least
+ * w_c * SSE * 2^16 + lambda_q16 * rate (w = 6 for Y, 1 for Co, Cg; rate = 5
+ * + payload bits, 0 when absent; the first class wins ties) with the
+ * smallest allowed range.  TABLE applies given classes, the values limited
+ * to the given range's bound and stored with that code.  Rows: levels L-2
+ * down to 0, node (row-major), block, channel.  features_out gets 16 floats
+ * per row: level/4, [c == Y], log2(1+mean|r|)/8, log2(1+max|r|)/8,
+ * log2(1+var|r|)/16, fractions of |r| >= 2, 4, 8, 16, log2(1+mean
+ * horizontal |dp|)/8, log2(1+mean vertical |dp|)/8, log2(1+max|dp|)/8,
+ * log2(1+var p)/16, q/4, log2(1+lambda_q16/2^16)/24, B/8 (r = block -
+ * parent reconstruction p).  The pixel and block thresholds of the
+ * parameters are used by GLOBAL only. */
+#define ORC_CTL_GLOBAL 0
+#define ORC_CTL_SEARCH 1
+#define ORC_CTL_TABLE 2
+typedef struct {
+  int32_t mode;
+  int64_t lambda_q16;
+  const int8_t *classes_in, *ranges_in;  /* TABLE */
+  int8_t *classes_out, *ranges_out;      /* may be NULL */
+  float *features_out;                   /* may be NULL */
+} orc_control;
+int orc_encode_ctl(const uint8_t *rgb, const orc_params *p, orc_control *ctl, uint8_t **out, int64_t *bytes,
+                   int16_t *r0_out, int16_t *ycocg_out, int64_t *hist);
 void orc_free(void *ptr);
 
 /* Header of a stream. */

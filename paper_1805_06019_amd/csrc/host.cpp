@@ -411,8 +411,162 @@ static void put_header(uint8_t *h, const Geometry &g, const lfc_params &p, uint3
   std::memcpy(h + 104, o, sizeof o);
 }
 
+// Per-block encoder control (learned encoder control; the paper applies one
+// pixel threshold and one block-energy threshold to every block, Sec. 3.2).
+// A block's options are the threshold classes: a pixel threshold from
+// kCtlTau (then quantisation, the block stored if any value is nonzero), or
+// dropping the block.
+static const int kCtlTau[LFC_CTL_CLASSES - 1] = {0, 2, 3, 4, 5, 6, 8, 12, 16};
+
+struct Candidate {
+  int32_t qv[64];   // quantised values
+  int code;         // range code, -1 absent
+  int64_t sse;      // squared error of the reconstruction against the block
+  int64_t rate;     // 5-bit range code + BISE payload bits, 0 when absent
+  bool ok;          // reconstruction stays in int16 and a range holds the values
+};
+
+static inline int32_t quantize_sample(int32_t v, int q) {
+  if (!q) return v;
+  const int32_t mag = (std::abs(v) + (1 << (q - 1))) >> q;
+  return v < 0 ? -mag : mag;
+}
+
+// Threshold class k applied to residuals v (own - parent) of one block; with
+// `rng` >= 0 the values are clamped into that range code's bound and it is
+// used as the block's code; with rng < 0 the smallest allowed range holding
+// the values is chosen.
+static void apply_class(const int32_t *v, const int32_t *own, const int32_t *par, int S, int q, int k, int rng,
+                        const std::vector<std::pair<int, int>> &ranges, Candidate &cd) {
+  cd.code = -1;
+  cd.ok = true;
+  cd.rate = 0;
+  bool any = false;
+  if (k == LFC_CTL_DROP || rng == LFC_CTL_ABSENT) {
+    for (int i = 0; i < S; i++) cd.qv[i] = 0;
+  } else {
+    const int tau = kCtlTau[k];
+    int32_t lo = INT32_MIN, hi = INT32_MAX;
+    if (rng >= 0) {
+      const int bound = range_code(rng).bound;
+      lo = -(bound / 2);
+      hi = (bound - 1) / 2;
+    }
+    uint32_t zmax = 0;
+    for (int i = 0; i < S; i++) {
+      int32_t x = std::abs(v[i]) < tau ? 0 : v[i];
+      x = std::min(std::max(quantize_sample(x, q), lo), hi);
+      cd.qv[i] = x;
+      any |= x != 0;
+      zmax = std::max<uint32_t>(zmax, zz_encode(x));
+    }
+    if (any) {
+      if (rng >= 0) {
+        cd.code = rng;
+      } else {
+        for (const auto &rg : ranges)
+          if ((uint32_t)rg.first > zmax) {
+            cd.code = rg.second;
+            break;
+          }
+        if (cd.code < 0) cd.ok = false;
+      }
+    }
+  }
+  if (cd.code < 0)
+    for (int i = 0; i < S; i++) cd.qv[i] = 0;
+  else
+    cd.rate = 5 + bise_block_bits(cd.code, S);
+  cd.sse = 0;
+  for (int i = 0; i < S; i++) {
+    const int32_t r = par[i] + (cd.code >= 0 ? cd.qv[i] * (1 << q) : 0);
+    if (r < -32768 || r > 32767) cd.ok = false;
+    const int64_t d = (int64_t)own[i] - r;
+    cd.sse += d * d;
+  }
+}
+
+// Exhaustive search: the class of least cost w_c * SSE * 2^16 + lambda_q16 *
+// rate (w = 6 for Y, 1 for Co and Cg, the channel weights of eq. 4), ties to
+// the lower class.  Returns the class; cd holds its candidate.
+static int search_class(const int32_t *v, const int32_t *own, const int32_t *par, int S, int q, int ch,
+                        int64_t lambda_q16, const std::vector<std::pair<int, int>> &ranges, Candidate &cd) {
+  const int64_t wc = ch == 0 ? 6 : 1;
+  int best = -1;
+  int64_t bestj = 0;
+  Candidate tmp;
+  for (int k = 0; k < LFC_CTL_CLASSES; k++) {
+    apply_class(v, own, par, S, q, k, -1, ranges, tmp);
+    if (!tmp.ok) continue;
+    const int64_t j = wc * tmp.sse * 65536 + lambda_q16 * tmp.rate;
+    if (best < 0 || j < bestj) {
+      best = k;
+      bestj = j;
+      cd = tmp;
+    }
+  }
+  return best;   // LFC_CTL_DROP is always valid
+}
+
+// The 16 features of a block's decision (row-major B x B blocks): v the
+// residuals, par the parent's reconstruction.
+static void block_features(const int32_t *v, const int32_t *par, int B, int level, int ch, int q,
+                           int64_t lambda_q16, float *f) {
+  const int S = B * B;
+  double sa = 0, sa2 = 0, amax = 0, c2 = 0, c4 = 0, c8 = 0, c16 = 0;
+  double sp = 0, sp2 = 0, gx = 0, gy = 0, gmax = 0;
+  for (int i = 0; i < S; i++) {
+    const double a = std::abs(v[i]);
+    sa += a;
+    sa2 += a * a;
+    amax = std::max(amax, a);
+    c2 += a >= 2;
+    c4 += a >= 4;
+    c8 += a >= 8;
+    c16 += a >= 16;
+    sp += par[i];
+    sp2 += (double)par[i] * par[i];
+    const int x = i % B, y = i / B;
+    if (x + 1 < B) {
+      const double d = std::abs(par[i + 1] - par[i]);
+      gx += d;
+      gmax = std::max(gmax, d);
+    }
+    if (y + 1 < B) {
+      const double d = std::abs(par[i + B] - par[i]);
+      gy += d;
+      gmax = std::max(gmax, d);
+    }
+  }
+  const double mean = sa / S, var = std::max(0.0, sa2 / S - mean * mean);
+  const double pm = sp / S, pvar = std::max(0.0, sp2 / S - pm * pm);
+  const double ng = (double)B * (B - 1);
+  f[0] = (float)(level / 4.0);
+  f[1] = ch == 0 ? 1.0f : 0.0f;
+  f[2] = (float)(std::log2(1.0 + mean) / 8.0);
+  f[3] = (float)(std::log2(1.0 + amax) / 8.0);
+  f[4] = (float)(std::log2(1.0 + var) / 16.0);
+  f[5] = (float)(c2 / S);
+  f[6] = (float)(c4 / S);
+  f[7] = (float)(c8 / S);
+  f[8] = (float)(c16 / S);
+  f[9] = (float)(std::log2(1.0 + gx / ng) / 8.0);
+  f[10] = (float)(std::log2(1.0 + gy / ng) / 8.0);
+  f[11] = (float)(std::log2(1.0 + gmax) / 8.0);
+  f[12] = (float)(std::log2(1.0 + pvar) / 16.0);
+  f[13] = (float)(q / 4.0);
+  f[14] = (float)(std::log2(1.0 + (double)lambda_q16 / 65536.0) / 24.0);
+  f[15] = (float)(B / 8.0);
+}
+
+int64_t control_rows(const Geometry &g) {
+  int64_t rows = 0;
+  for (int l = 0; l < g.L - 1; l++) rows += (int64_t)g.lu[l] * g.lv[l] * g.nb * 3;
+  return rows;
+}
+
 static lfc_status encode_impl(const uint8_t *rgb, const lfc_params &p, std::vector<uint8_t> *out,
-                              lfc_encode_stats *stats) {
+                              lfc_encode_stats *stats, lfc_control *ctl) {
   Geometry g;
   std::string why;
   if (make_geometry(p, g, &why) != LFC_OK) return fail(LFC_E_INVALID, "lfc_encode: " + why);
@@ -489,77 +643,182 @@ static lfc_status encode_impl(const uint8_t *rgb, const lfc_params &p, std::vect
   std::vector<uint16_t> zv(std::max<size_t>(nsg * S, 1), 0);
   std::vector<std::vector<int16_t>> rec(L);
   std::atomic<int> err{0};
-  for (int l = L - 2; l >= 0; l--) {
+  const int mode = ctl ? ctl->mode : LFC_CTL_GLOBAL;
+  const int64_t lam = ctl ? ctl->lambda_q16 : 0;
+  std::atomic<int64_t> fallbacks{0};
+  std::vector<float> feat, pconf;
+  std::vector<int8_t> pcls, prng;
+  int64_t rowbase = 0;   // control row of the level's first (node, block, channel)
+  for (int l = L - 2; l >= 0 && !err.load(); l--) {
     const int nodes = g.lu[l] * g.lv[l], cp = g.c[l + 1];
     rec[l].resize((size_t)nodes * img);
     const std::vector<int16_t> &prec = (l + 1 == L - 1) ? lvl[L - 1] : rec[l + 1];
-    parallel_for((int64_t)nodes * g.nb, 256, [&](int64_t a, int64_t e) {
-      for (int64_t r = a; r < e && !err.load(std::memory_order_relaxed); r++) {
-        const int node = (int)(r / g.nb), b = (int)(r % g.nb);
-        const int nx = node % g.lu[l], ny = node / g.lu[l];
-        const int parent = (ny / cp) * g.lu[l + 1] + nx / cp;
-        const int sidx = tt.serial[l][node];
-        const int bx = b % g.nbx, by = b / g.nbx;
-        for (int ch = 0; ch < 3; ch++) {
-          const size_t base = (size_t)ch * plane + (size_t)by * B * g.wp + (size_t)bx * B;
-          const int16_t *own = &lvl[l][(size_t)node * img + base];
-          const int16_t *par = &prec[(size_t)parent * img + base];
-          int16_t *dst = &rec[l][(size_t)node * img + base];
-          int32_t qv[64];
-          int64_t energy = 0;
-          for (int i = 0; i < S; i++) {
-            const size_t d = (size_t)(i / B) * g.wp + i % B;
-            int32_t v = (int32_t)own[d] - (int32_t)par[d];
-            if (std::abs(v) < p.pix_threshold) v = 0;   // pixel-level threshold
-            qv[i] = v;
-            energy += std::abs(v);
-          }
-          bool keep = energy > p.blk_threshold;          // block-energy threshold
-          uint32_t zmax = 0;
-          if (keep) {
-            bool nz = false;
+    // one block of one channel: own samples, parent reconstruction, residuals
+    auto load = [&](int64_t pair, int ch, int32_t *own, int32_t *par, int32_t *v) {
+      const int node = (int)(pair / g.nb), b = (int)(pair % g.nb);
+      const int nx = node % g.lu[l], ny = node / g.lu[l];
+      const int parent = (ny / cp) * g.lu[l + 1] + nx / cp;
+      const int bx = b % g.nbx, by = b / g.nbx;
+      const size_t base = (size_t)ch * plane + (size_t)by * B * g.wp + (size_t)bx * B;
+      const int16_t *po = &lvl[l][(size_t)node * img + base];
+      const int16_t *pp = &prec[(size_t)parent * img + base];
+      for (int i = 0; i < S; i++) {
+        const size_t d = (size_t)(i / B) * g.wp + i % B;
+        own[i] = po[d];
+        par[i] = pp[d];
+        v[i] = own[i] - par[i];
+      }
+    };
+    const int64_t pairs = (int64_t)nodes * g.nb;
+    const int64_t chunk = mode == LFC_CTL_MLP ? std::min<int64_t>(pairs, (int64_t)1 << 19) : pairs;
+    for (int64_t c0 = 0; c0 < pairs && !err.load(); c0 += chunk) {
+      const int64_t c1 = std::min(pairs, c0 + chunk);
+      if (mode == LFC_CTL_MLP) {
+        // features of the chunk, then the network's classes on the GPU
+        const int64_t nr = (c1 - c0) * 3;
+        feat.resize((size_t)nr * LFC_CTL_FEATURES);
+        pcls.resize((size_t)nr);
+        prng.resize((size_t)nr);
+        pconf.resize((size_t)nr);
+        parallel_for(c1 - c0, 256, [&](int64_t a, int64_t e) {
+          int32_t own[64], par[64], v[64];
+          for (int64_t r = a; r < e; r++)
+            for (int ch = 0; ch < 3; ch++) {
+              load(c0 + r, ch, own, par, v);
+              block_features(v, par, B, l, ch, q, lam, &feat[(size_t)(r * 3 + ch) * LFC_CTL_FEATURES]);
+            }
+        });
+        if (lfc_status st = mlp_infer_rows(ctl->d_mlp, feat.data(), nr, pcls.data(), prng.data(), pconf.data(),
+                                           ctl->stream))
+          return st;
+      }
+      parallel_for(c1 - c0, 256, [&](int64_t a, int64_t e) {
+        int32_t own[64], par[64], v[64];
+        Candidate cd, cs;
+        for (int64_t r = a; r < e && !err.load(std::memory_order_relaxed); r++) {
+          const int64_t pair = c0 + r;
+          const int node = (int)(pair / g.nb), b = (int)(pair % g.nb);
+          const int sidx = tt.serial[l][node];
+          const int bx = b % g.nbx, by = b / g.nbx;
+          for (int ch = 0; ch < 3; ch++) {
+            load(pair, ch, own, par, v);
+            const int64_t row = rowbase + pair * 3 + ch;
+            if (mode == LFC_CTL_GLOBAL) {
+              // the paper's global thresholds: pixel level, then block energy
+              int64_t energy = 0;
+              for (int i = 0; i < S; i++) {
+                if (std::abs(v[i]) < p.pix_threshold) v[i] = 0;
+                energy += std::abs(v[i]);
+              }
+              bool keep = energy > p.blk_threshold;
+              uint32_t zmax = 0;
+              if (keep) {
+                bool nz = false;
+                for (int i = 0; i < S; i++) {
+                  v[i] = quantize_sample(v[i], q);
+                  nz |= v[i] != 0;
+                  zmax = std::max<uint32_t>(zmax, zz_encode(v[i]));
+                }
+                keep = nz;
+              }
+              cd.code = -1;
+              if (keep) {
+                for (const auto &rg : ranges)
+                  if ((uint32_t)rg.first > zmax) {
+                    cd.code = rg.second;
+                    break;
+                  }
+                if (cd.code < 0) {
+                  err.store(1);
+                  return;
+                }
+              }
+              for (int i = 0; i < S; i++) cd.qv[i] = keep ? v[i] : 0;
+            } else {
+              const bool need_search = mode == LFC_CTL_SEARCH || ctl->search_classes || ctl->search_ranges;
+              int sc = -1;
+              if (need_search) {
+                sc = search_class(v, own, par, S, q, ch, lam, ranges, cs);
+                if (ctl->search_classes) ctl->search_classes[row] = (int8_t)sc;
+                if (ctl->search_ranges) ctl->search_ranges[row] = (int8_t)(cs.code < 0 ? LFC_CTL_ABSENT : cs.code);
+              }
+              if (ctl->features && mode != LFC_CTL_MLP) block_features(v, par, B, l, ch, q, lam, ctl->features + row * LFC_CTL_FEATURES);
+              int cls;
+              if (mode == LFC_CTL_SEARCH) {
+                cls = sc;
+                cd = cs;
+              } else {
+                int rng;
+                bool fallback = false;
+                if (mode == LFC_CTL_TABLE) {
+                  cls = ctl->classes[row];
+                  rng = ctl->ranges[row];
+                  if (cls < 0 || cls >= LFC_CTL_CLASSES || rng < 0 || rng > LFC_CTL_ABSENT ||
+                      (rng < LFC_CTL_ABSENT && !((mask >> rng) & 1u))) {
+                    err.store(3);
+                    return;
+                  }
+                } else {
+                  const size_t pr = (size_t)((pair - c0) * 3 + ch);
+                  if (ctl->features)
+                    std::memcpy(ctl->features + row * LFC_CTL_FEATURES, &feat[pr * LFC_CTL_FEATURES],
+                                sizeof(float) * LFC_CTL_FEATURES);
+                  cls = pcls[pr];
+                  rng = prng[pr];
+                  fallback = !(pconf[pr] >= ctl->min_confidence);
+                  if (!fallback && rng < LFC_CTL_ABSENT && !((mask >> rng) & 1u)) {
+                    // a range the stream may not use: the values' own range
+                    apply_class(v, own, par, S, q, cls, -1, ranges, cd);
+                    rng = cd.code < 0 ? LFC_CTL_ABSENT : cd.code;
+                  }
+                }
+                if (!fallback) {
+                  apply_class(v, own, par, S, q, cls, rng, ranges, cd);
+                  if (!cd.ok) {
+                    if (mode == LFC_CTL_TABLE) {
+                      err.store(2);
+                      return;
+                    }
+                    fallback = true;
+                  }
+                }
+                if (fallback) {
+                  if (sc < 0) sc = search_class(v, own, par, S, q, ch, lam, ranges, cs);
+                  cls = sc;
+                  cd = cs;
+                  fallbacks.fetch_add(1, std::memory_order_relaxed);
+                }
+              }
+              if (ctl->classes && mode != LFC_CTL_TABLE) ctl->classes[row] = (int8_t)cls;
+              if (ctl->ranges && mode != LFC_CTL_TABLE) ctl->ranges[row] = (int8_t)(cd.code < 0 ? LFC_CTL_ABSENT : cd.code);
+            }
+            const bool keep = cd.code >= 0;
+            if (keep) {
+              const size_t key = (size_t)(3 * b + ch) * g.n_srv + sidx;
+              code_tab[key] = (int8_t)cd.code;
+              for (int i = 0; i < S; i++) zv[key * S + i] = zz_encode(cd.qv[i]);
+            }
+            int16_t *dst = &rec[l][(size_t)node * img + (size_t)ch * plane + (size_t)by * B * g.wp + (size_t)bx * B];
             for (int i = 0; i < S; i++) {
-              if (q) {
-                const int32_t mag = (std::abs(qv[i]) + (1 << (q - 1))) >> q;
-                qv[i] = qv[i] < 0 ? -mag : mag;
+              const int32_t x = par[i] + (keep ? cd.qv[i] * (1 << q) : 0);
+              if (x < -32768 || x > 32767) {
+                err.store(2);
+                return;
               }
-              nz |= qv[i] != 0;
-              zmax = std::max<uint32_t>(zmax, zz_encode(qv[i]));
+              dst[(size_t)(i / B) * g.wp + i % B] = (int16_t)x;
             }
-            keep = nz;
-          }
-          int code = -1;
-          if (keep) {
-            for (const auto &rg : ranges)
-              if ((uint32_t)rg.first > zmax) {
-                code = rg.second;
-                break;
-              }
-            if (code < 0) {
-              err.store(1);
-              return;
-            }
-            const size_t key = (size_t)(3 * b + ch) * g.n_srv + sidx;
-            code_tab[key] = (int8_t)code;
-            for (int i = 0; i < S; i++) zv[key * S + i] = zz_encode(qv[i]);
-          }
-          for (int i = 0; i < S; i++) {
-            const size_t d = (size_t)(i / B) * g.wp + i % B;
-            const int32_t v = (int32_t)par[d] + (keep ? qv[i] * (1 << q) : 0);
-            if (v < -32768 || v > 32767) {
-              err.store(2);
-              return;
-            }
-            dst[d] = (int16_t)v;
           }
         }
-      }
-    });
+      });
+    }
+    rowbase += pairs * 3;
     if (err.load()) break;
     if (l + 1 < L - 1) std::vector<int16_t>().swap(rec[l + 1]);  // no longer needed
   }
+  if (ctl) ctl->fallbacks = fallbacks.load();
   if (err.load() == 1) return fail(LFC_E_RANGE, "lfc_encode: a residual block needs a BISE range the mask does not allow");
   if (err.load() == 2) return fail(LFC_E_RANGE, "lfc_encode: a reconstructed sample leaves int16");
+  if (err.load() == 3) return fail(LFC_E_INVALID, "lfc_encode_ctl: a class table entry is out of range or names a range the mask excludes");
   if (stats) {
     // eq. 5 per view and channel on the unpadded area, eq. 4, mean over views
     const std::vector<int16_t> &r0 = L > 1 ? rec[0] : lvl[0];
@@ -866,13 +1125,60 @@ extern "C" lfc_status lfc_encode_ex(const uint8_t *rgb, const lfc_params *p, voi
   std::vector<uint8_t> buf;
   lfc_status st;
   try {
-    st = encode_impl(rgb, *p, stream_out ? &buf : nullptr, stats);
+    st = encode_impl(rgb, *p, stream_out ? &buf : nullptr, stats, nullptr);
   } catch (const std::bad_alloc &) {
     return fail(LFC_E_NOMEM, "lfc_encode: out of host memory");
   }
   if (st != LFC_OK || !stream_out) return st;
   void *mem = std::malloc(buf.size());
   if (!mem) return fail(LFC_E_NOMEM, "lfc_encode: out of host memory");
+  std::memcpy(mem, buf.data(), buf.size());
+  *stream_out = mem;
+  *bytes_out = buf.size();
+  return LFC_OK;
+}
+
+extern "C" int64_t lfc_control_rows(const lfc_params *p) {
+  if (!p) return -1;
+  Geometry g;
+  if (make_geometry(*p, g, nullptr) != LFC_OK) return -1;
+  return control_rows(g);
+}
+
+extern "C" lfc_status lfc_encode_ctl(const uint8_t *rgb, const lfc_params *p, lfc_control *ctl, void **stream_out,
+                                     size_t *bytes_out, lfc_encode_stats *stats) {
+  if (!rgb || !p || !ctl || (!stream_out) != (!bytes_out)) return fail(LFC_E_INVALID, "lfc_encode_ctl: null argument");
+  if (stream_out) {
+    *stream_out = nullptr;
+    *bytes_out = 0;
+  }
+  const int m = ctl->mode;
+  if (m != LFC_CTL_GLOBAL && m != LFC_CTL_SEARCH && m != LFC_CTL_TABLE && m != LFC_CTL_MLP)
+    return fail(LFC_E_INVALID, "lfc_encode_ctl: unknown mode");
+  if (ctl->lambda_q16 < 0 || ctl->lambda_q16 > ((int64_t)1 << 52))
+    return fail(LFC_E_INVALID, "lfc_encode_ctl: lambda_q16 must be 0..2^52");
+  Geometry g;
+  std::string why;
+  if (make_geometry(*p, g, &why) != LFC_OK) return fail(LFC_E_INVALID, "lfc_encode_ctl: " + why);
+  const bool tables = ctl->classes || ctl->ranges || ctl->features || ctl->search_classes || ctl->search_ranges;
+  if (tables && ctl->rows != control_rows(g))
+    return fail(LFC_E_INVALID, "lfc_encode_ctl: rows must equal lfc_control_rows(p)");
+  if (m == LFC_CTL_TABLE && (!ctl->classes || !ctl->ranges))
+    return fail(LFC_E_INVALID, "lfc_encode_ctl: TABLE mode needs classes and ranges");
+  if (m == LFC_CTL_MLP && !ctl->d_mlp) return fail(LFC_E_INVALID, "lfc_encode_ctl: MLP mode needs device weights");
+  if (m == LFC_CTL_GLOBAL && tables)
+    return fail(LFC_E_INVALID, "lfc_encode_ctl: the GLOBAL mode fills no tables");
+  ctl->fallbacks = 0;
+  std::vector<uint8_t> buf;
+  lfc_status st;
+  try {
+    st = encode_impl(rgb, *p, stream_out ? &buf : nullptr, stats, ctl);
+  } catch (const std::bad_alloc &) {
+    return fail(LFC_E_NOMEM, "lfc_encode_ctl: out of host memory");
+  }
+  if (st != LFC_OK || !stream_out) return st;
+  void *mem = std::malloc(buf.size());
+  if (!mem) return fail(LFC_E_NOMEM, "lfc_encode_ctl: out of host memory");
   std::memcpy(mem, buf.data(), buf.size());
   *stream_out = mem;
   *bytes_out = buf.size();

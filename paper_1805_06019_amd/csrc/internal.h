@@ -50,6 +50,12 @@ void build_tree_tables(const Geometry &g, TreeTables &t);
 
 // Bits of a BISE block of S values under range code k.
 int bise_block_bits(int code, int S);
+// Control rows of a geometry: every residual (node, block, channel).
+int64_t control_rows(const Geometry &g);
+// The encoder's per-block network on the GPU: n feature rows (host) to the
+// threshold class, range class and top threshold-class probability (host).
+lfc_status mlp_infer_rows(const void *d_w, const float *feat, int64_t n, int8_t *cls, int8_t *rng, float *conf,
+                          hipStream_t s);
 
 // Records a failure for lfc_last_error and returns st.
 lfc_status fail(lfc_status st, const std::string &msg);

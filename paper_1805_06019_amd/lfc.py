@@ -67,6 +67,18 @@ class c_render_request(C.Structure):
     _fields_ = [("lf", C.c_int32), ("out_w", C.c_int32), ("out_h", C.c_int32), ("view", c_view)]
 
 
+class c_control(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("min_confidence", C.c_float), ("lambda_q16", C.c_int64),
+                ("d_mlp", C.c_void_p), ("stream", C.c_void_p), ("rows", C.c_int64),
+                ("classes", C.c_void_p), ("ranges", C.c_void_p), ("features", C.c_void_p),
+                ("search_classes", C.c_void_p), ("search_ranges", C.c_void_p), ("fallbacks", C.c_int64)]
+
+
+CTL_GLOBAL, CTL_SEARCH, CTL_TABLE, CTL_MLP = 0, 1, 2, 3
+CTL_CLASSES, CTL_DROP, CTL_RANGES, CTL_ABSENT, CTL_FEATURES = 10, 9, 27, 26, 16
+MLP_PARAMS = 7653
+
+
 class c_render_config(C.Structure):
     _fields_ = [("path", C.c_int32), ("tile_w", C.c_int32), ("tile_h", C.c_int32)]
 
@@ -146,6 +158,13 @@ def load() -> C.CDLL:
         L.lfc_stage_needs.argtypes = [vp, vp, i64]
         L.lfc_stage_needs.restype = i64
         L.lfc_render_views.argtypes = [vp, vp, i32, i32, i32, vp, vp]
+        L.lfc_control_rows.argtypes = [C.POINTER(c_params)]
+        L.lfc_control_rows.restype = i64
+        L.lfc_encode_ctl.argtypes = [vp, C.POINTER(c_params), C.POINTER(c_control), C.POINTER(vp), C.POINTER(sz),
+                                     C.POINTER(c_stats)]
+        L.lfc_mlp_infer.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
+        L.lfc_mlp_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp]
+        L.lfc_mlp_adam.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
         L.lfc_render_views_ex.argtypes = [vp, vp, i32, i32, i32, vp, C.POINTER(c_render_config), vp]
         L.lfc_render_tune.argtypes = [vp, vp, i32, i32, i32, vp, i32, C.POINTER(c_render_tuning), vp]
         L.lfc_render_plan_create.argtypes = [vp, C.POINTER(c_render_config), vp, i32, i32, i32, vp, i32,
@@ -172,7 +191,8 @@ def load() -> C.CDLL:
         L.lfc_server_get_stats.argtypes = [vp, C.POINTER(c_server_stats)]
         L.lfc_server_destroy.argtypes = [vp]
         for f in ("lfc_encode", "lfc_encode_ex", "lfc_validate", "lfc_open", "lfc_info", "lfc_decode_blocks",
-                  "lfc_render_views", "lfc_render_views_ex", "lfc_render_tune", "lfc_render_plan_create",
+                  "lfc_render_views", "lfc_render_views_ex", "lfc_encode_ctl", "lfc_mlp_infer", "lfc_mlp_grad",
+                  "lfc_mlp_adam", "lfc_render_tune", "lfc_render_plan_create",
                   "lfc_render_plan_launch", "lfc_render_plan_info", "lfc_check", "lfc_close", "lfc_decode_progressive", "lfc_batch_create",
                   "lfc_batch_decode", "lfc_batch_check", "lfc_batch_render",
                   "lfc_batch_destroy", "lfc_server_create", "lfc_server_submit", "lfc_server_wait",
@@ -228,6 +248,104 @@ def lfc_encode_ex(rgb: np.ndarray, params: Params, want_stream: bool = True):
     stats = dict(psnr=st.psnr, psnr_y=st.psnr_y, psnr_co=st.psnr_co, psnr_cg=st.psnr_cg,
                  present_blocks=st.present_blocks, code_hist=list(st.code_hist), stream_bytes=st.stream_bytes)
     return data, stats
+
+
+def lfc_control_rows(params: Params) -> int:
+    n = load().lfc_control_rows(C.byref(params.to_c()))
+    if n < 0:
+        raise LFCError(-1, "invalid parameters")
+    return n
+
+
+def lfc_encode_ctl(rgb: np.ndarray, params: Params, mode: int, lambda_q16: int = 0, classes=None, ranges=None,
+                   mlp=None, min_confidence: float = 0.0, want_features: bool = False, want_search: bool = False,
+                   want_stream: bool = True, cuda_stream=None):
+    """Encoder under per-block control (include/lfc.h).  mlp: CUDA tensor of
+    LFC_MLP_PARAMS bfloat16 bits (int16/uint16) for CTL_MLP.  Returns (stream
+    or None, stats dict with the classes and ranges used, and the features,
+    search classes and ranges when asked for, and the fallback count)."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+    if rgb.shape != (params.grid_v, params.grid_u, params.height, params.width, 3):
+        raise ValueError(f"rgb shape {rgb.shape} does not match the parameters")
+    ctl = c_control()
+    ctl.mode, ctl.lambda_q16, ctl.min_confidence = mode, int(lambda_q16), float(min_confidence)
+    keep = {}
+    if mode != CTL_GLOBAL:
+        rows = lfc_control_rows(params)
+        ctl.rows = rows
+        if mode == CTL_TABLE:
+            keep["classes"] = np.ascontiguousarray(classes, dtype=np.int8)
+            keep["ranges"] = np.ascontiguousarray(ranges, dtype=np.int8)
+            if keep["classes"].size != rows or keep["ranges"].size != rows:
+                raise ValueError("classes and ranges need one entry per control row")
+        else:
+            keep["classes"] = np.full(rows, -1, dtype=np.int8)
+            keep["ranges"] = np.full(rows, -1, dtype=np.int8)
+        ctl.classes, ctl.ranges = keep["classes"].ctypes.data, keep["ranges"].ctypes.data
+        if want_features:
+            keep["features"] = np.zeros((rows, CTL_FEATURES), dtype=np.float32)
+            ctl.features = keep["features"].ctypes.data
+        if want_search:
+            keep["search_classes"] = np.full(rows, -1, dtype=np.int8)
+            keep["search_ranges"] = np.full(rows, -1, dtype=np.int8)
+            ctl.search_classes = keep["search_classes"].ctypes.data
+            ctl.search_ranges = keep["search_ranges"].ctypes.data
+    if mode == CTL_MLP and mlp is not None:
+        ctl.d_mlp = mlp.data_ptr()
+        ctl.stream = _stream_ptr(cuda_stream)
+    st = c_stats()
+    out, n = C.c_void_p(), C.c_size_t()
+    if want_stream:
+        _check(load().lfc_encode_ctl(rgb.ctypes.data, C.byref(params.to_c()), C.byref(ctl), C.byref(out),
+                                     C.byref(n), C.byref(st)))
+    else:
+        _check(load().lfc_encode_ctl(rgb.ctypes.data, C.byref(params.to_c()), C.byref(ctl), None, None,
+                                     C.byref(st)))
+    data = None
+    if want_stream:
+        try:
+            data = C.string_at(out.value, n.value)
+        finally:
+            load().lfc_free(out)
+    stats = dict(psnr=st.psnr, psnr_y=st.psnr_y, psnr_co=st.psnr_co, psnr_cg=st.psnr_cg,
+                 present_blocks=st.present_blocks, code_hist=list(st.code_hist), stream_bytes=st.stream_bytes,
+                 fallbacks=ctl.fallbacks, **keep)
+    return data, stats
+
+
+def mlp_infer(w, x, logits: bool = False, cuda_stream=None):
+    """Network inference on the GPU: w bf16 bits (CUDA int16/uint16
+    [LFC_MLP_PARAMS]), x float32 CUDA [n][16].  Returns (threshold class,
+    range class, confidence[, logits]) CUDA tensors."""
+    import torch
+    n = x.shape[0]
+    cls = torch.empty(n, dtype=torch.int8, device="cuda")
+    rng = torch.empty(n, dtype=torch.int8, device="cuda")
+    conf = torch.empty(n, dtype=torch.float32, device="cuda")
+    z = torch.empty((n, 37), dtype=torch.float32, device="cuda") if logits else None
+    _check(load().lfc_mlp_infer(w.data_ptr(), x.data_ptr(), n, cls.data_ptr(), rng.data_ptr(), conf.data_ptr(),
+                                z.data_ptr() if z is not None else None, _stream_ptr(cuda_stream)))
+    return (cls, rng, conf, z) if logits else (cls, rng, conf)
+
+
+def mlp_grad(w, x, cls, rng, part=None, cuda_stream=None):
+    """Mean loss and gradient over a batch (CUDA tensors); returns (grad
+    float32 [LFC_MLP_PARAMS], loss float32 [1])."""
+    import torch
+    n = x.shape[0]
+    nwg = (n + 127) // 128
+    if part is None or part.numel() < nwg * (MLP_PARAMS + 1):
+        part = torch.empty(nwg * (MLP_PARAMS + 1), dtype=torch.float32, device="cuda")
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(load().lfc_mlp_grad(w.data_ptr(), x.data_ptr(), cls.data_ptr(), rng.data_ptr(), n, part.data_ptr(),
+                               grad.data_ptr(), loss.data_ptr(), _stream_ptr(cuda_stream)))
+    return grad, loss
+
+
+def mlp_adam(master, w, m, v, grad, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, cuda_stream=None):
+    _check(load().lfc_mlp_adam(master.data_ptr(), w.data_ptr(), m.data_ptr(), v.data_ptr(), grad.data_ptr(), step,
+                               lr, beta1, beta2, eps, _stream_ptr(cuda_stream)))
 
 
 def lfc_validate(stream: bytes) -> Params:
