@@ -350,6 +350,30 @@ def main():
                                                   views_per_s=round(64 / (gl.mean() * 1e-3), 1))
         lfl.close()
         del imgl
+        # learned encoder control: the per-block network over every control
+        # row of the 40 dB field (features from the search mode), and its
+        # training step (batch gradient + Adam on 1024 rows)
+        from paper_1805_06019_amd import control
+        _, stc = lfc.lfc_encode_ctl(rgb, w40.params(), lfc.CTL_SEARCH, 1 << 20, want_features=True, want_stream=False)
+        feats = torch.from_numpy(stc["features"]).cuda()
+        del stc
+        tr = control.Trainer(seed=1)
+        lfc.mlp_infer(tr.w, feats)
+        mi = time_launches(lambda: lfc.mlp_infer(tr.w, feats), 5, torch)
+        rows = feats.shape[0]
+        flops = 2.0 * (16 * 64 + 64 * 64 + 64 * 37) * rows
+        xb, cb, rb = feats[:1024].contiguous(), torch.zeros(1024, dtype=torch.int8, device="cuda"), \
+            torch.zeros(1024, dtype=torch.int8, device="cuda")
+        tr.part = torch.empty(8 * (lfc.MLP_PARAMS + 1), dtype=torch.float32, device="cuda")
+        tr.step(xb, cb, rb)
+        ts = time_launches(lambda: tr.step(xb, cb, rb), 50, torch)
+        extra["encoder_control"] = dict(
+            infer_rows=int(rows), infer_ms=round(float(mi.mean()), 4),
+            infer_rows_per_s=round(rows / (mi.mean() * 1e-3), 1),
+            infer_tflops=round(flops / (mi.mean() * 1e-3) / 1e12, 2),
+            infer_frac_of_fp32_peak=round(flops / (mi.mean() * 1e-3) / 157.3e12, 4),
+            train_step_ms_1024_rows=round(float(ts.mean()), 4))
+        del feats, tr
         if not args.no_serving:
             extra["serving"] = serving(lfc, synth, torch)
 

@@ -132,7 +132,7 @@ lfc_status lfc_encode_ex(const uint8_t *rgb, const lfc_params *p, void **stream_
 /*
  * Learned encoder control.  The paper's encoder applies one pixel threshold
  * and one block-energy threshold to every residual block (Sec. 3.2) and
- * names the lack of finer control as a limitation (Sec. 6).  Here each
+ * names the lack of finer control as a limitation (Sec. 5).  Here each
  * residual block (node, spatial block, channel: a control row) gets its own
  * decision; the decoder is unchanged, since the stream carries only the
  * stored values and their range codes.

@@ -2,7 +2,7 @@
 network (the GPU kernels and the encoder modes are in liblfc, include/lfc.h).
 
 The paper's encoder uses one pixel threshold and one block-energy threshold
-for every block (Sec. 3.2) and notes the lack of finer control (Sec. 6).
+for every block (Sec. 3.2) and notes the lack of finer control (Sec. 5).
 Here every residual block gets its own threshold class (and range class),
 chosen by an exhaustive rate-distortion search (the labeller, the fallback
 and the judge) or predicted by a small network trained on the search's
