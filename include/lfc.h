@@ -353,16 +353,24 @@ lfc_status lfc_render_views(const lfc_lf *lf, const lfc_view *d_views, int32_t n
  *                      pixels decodes the tile's source footprint (0 x 0:
  *                      64 x 16, shrunk until the footprint fits 64 KB).
  *  LFC_RENDER_DECODED  decode every source view, then interpolate.
+ * disparity refocuses the render (the dynamic reparameterisation the paper
+ * names as compatible with its decoder, Sec. 3.6): a novel camera at grid
+ * position (u, v), clamped to the grid, samples source camera (iu, jv) at
+ * image-plane offset (s + d (iu - u), t + d (jv - v)), so that a scene
+ * plane whose image moves by -d pixels per camera step is in focus; d = 0 is
+ * the plain two-plane interpolation of lfc_render_views.
  */
 enum { LFC_RENDER_AUTO = 0, LFC_RENDER_TILES = 1, LFC_RENDER_DECODED = 2 };
 typedef struct {
   int32_t path;
   int32_t tile_w, tile_h;   /* LFC_RENDER_TILES only, 1..1024 each, or both 0 */
+  float disparity;          /* focal disparity d, finite, |d| <= 1e6 (0: none) */
 } lfc_render_config;
 
-/* lfc_render_views with an explicit launch shape (cfg NULL: automatic).
- * Errors: as lfc_render_views, plus LFC_E_INVALID (unknown path, tile size)
- * and LFC_E_UNSUPPORTED (the tile's source footprint exceeds 64 KB). */
+/* lfc_render_views with an explicit launch shape and focal disparity (cfg
+ * NULL: automatic, d = 0).  Errors: as lfc_render_views, plus LFC_E_INVALID
+ * (unknown path, tile size, disparity) and LFC_E_UNSUPPORTED (the tile's
+ * source footprint exceeds 64 KB). */
 lfc_status lfc_render_views_ex(const lfc_lf *lf, const lfc_view *d_views, int32_t n, int32_t out_w,
                                int32_t out_h, float *d_out, const lfc_render_config *cfg, hipStream_t s);
 

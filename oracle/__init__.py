@@ -131,6 +131,7 @@ def lib() -> C.CDLL:
         L.orc_decode_block_level.argtypes = [vp, i64, i32, i32, i32, vp]
         L.orc_decode_all.argtypes = [vp, i64, i32, i32, vp]
         L.orc_render.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, i32, i32, i32, vp]
+        L.orc_render_focal.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, i32, i32, i32, C.c_float, vp]
         L.orc_psnr.argtypes = [vp, vp, i32, i32, i32, i32, i32]
         L.orc_psnr.restype = C.c_double
         _lib = L
@@ -364,14 +365,19 @@ def decode_all(stream: bytes, b0: int = 0, b1: int | None = None, out: np.ndarra
     return out
 
 
-def render(lf: np.ndarray, U: int, V: int, W: int, H: int, views: np.ndarray, wo: int, ho: int):
+def render(lf: np.ndarray, U: int, V: int, W: int, H: int, views: np.ndarray, wo: int, ho: int,
+           disparity: float = 0.0):
+    """Sec. 3.6 two-plane interpolation; disparity != 0 refocuses it."""
     lf = np.ascontiguousarray(lf, dtype=np.int16)
     views = np.ascontiguousarray(views, dtype=np.float32).reshape(-1, 4)
     n = views.shape[0]
     hp, wp = lf.shape[2], lf.shape[3]
     out = np.zeros((n, 3, ho, wo), dtype=np.float32)
-    _check(lib().orc_render(_ptr(lf), U, V, W, H, wp, hp, _ptr(views), n, wo, ho, _ptr(out)),
-           "orc_render")
+    if disparity == 0.0:
+        st = lib().orc_render(_ptr(lf), U, V, W, H, wp, hp, _ptr(views), n, wo, ho, _ptr(out))
+    else:
+        st = lib().orc_render_focal(_ptr(lf), U, V, W, H, wp, hp, _ptr(views), n, wo, ho, disparity, _ptr(out))
+    _check(st, "orc_render")
     return out
 
 

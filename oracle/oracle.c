@@ -1062,6 +1062,16 @@ static void cell(float x, int n, int *i0, int *i1, float *f) {
 
 int orc_render(const int16_t *lf, int32_t U, int32_t V, int32_t W, int32_t H, int32_t wp,
                int32_t hp, const float *views, int32_t n, int32_t wo, int32_t ho, float *out) {
+  return orc_render_focal(lf, U, V, W, H, wp, hp, views, n, wo, ho, 0.0f, out);
+}
+
+/* Refocused rendering (the dynamic reparameterisation Sec. 3.6 names as
+ * compatible; reading C20): source camera (iu, jv) of a novel camera at
+ * (u, v), clamped to the grid, is sampled at image-plane position
+ * (sx + d (iu - u), ty + d (jv - v)); each source view gets its own taps
+ * and fractions.  d = 0 is orc_render. */
+int orc_render_focal(const int16_t *lf, int32_t U, int32_t V, int32_t W, int32_t H, int32_t wp, int32_t hp,
+                     const float *views, int32_t n, int32_t wo, int32_t ho, float d, float *out) {
   if (!lf || !views || !out || n < 0 || wo < 1 || ho < 1) return ORC_E_INVALID;
   const int64_t plane = (int64_t)hp * wp;
   const float sxs = (float)W / (float)wo, tys = (float)H / (float)ho;
@@ -1071,21 +1081,29 @@ int orc_render(const int16_t *lf, int32_t U, int32_t V, int32_t W, int32_t H, in
     float fu, fv;
     cell(u, U, &iu[0], &iu[1], &fu);
     cell(v, V, &jv[0], &jv[1], &fv);
+    /* the novel camera's position on the grid, clamped like the cell lookup */
+    float uc = u < 0.0f ? 0.0f : (u > (float)(U - 1) ? (float)(U - 1) : u);
+    float vc = v < 0.0f ? 0.0f : (v > (float)(V - 1) ? (float)(V - 1) : v);
     for (int Y = 0; Y < ho; Y++)
       for (int X = 0; X < wo; X++) {
         float sx = s + ((float)X + 0.5f) * sxs - 0.5f;
         float ty = t + ((float)Y + 0.5f) * tys - 0.5f;
-        int xs[2], ys[2];
-        float fs, ft;
-        cell(sx, W, &xs[0], &xs[1], &fs);
-        cell(ty, H, &ys[0], &ys[1], &ft);
+        int xs[2][2][2], ys[2][2][2]; /* [view a][view b][tap] */
+        float fsv[2][2], ftv[2][2];
+        for (int a = 0; a < 2; a++)
+          for (int bb = 0; bb < 2; bb++) {
+            float dx = d == 0.0f ? 0.0f : d * ((float)iu[a] - uc);
+            float dy = d == 0.0f ? 0.0f : d * ((float)jv[bb] - vc);
+            cell(sx + dx, W, &xs[a][bb][0], &xs[a][bb][1], &fsv[a][bb]);
+            cell(ty + dy, H, &ys[a][bb][0], &ys[a][bb][1], &ftv[a][bb]);
+          }
         float rgb_tap[2][2][2][2][3]; /* [view a][view b][row][col][channel] */
         for (int a = 0; a < 2; a++)
           for (int bb = 0; bb < 2; bb++)
             for (int r = 0; r < 2; r++)
               for (int cc = 0; cc < 2; cc++) {
                 int vi = jv[bb] * U + iu[a];
-                int64_t o = (int64_t)vi * 3 * plane + (int64_t)ys[r] * wp + xs[cc];
+                int64_t o = (int64_t)vi * 3 * plane + (int64_t)ys[a][bb][r] * wp + xs[a][bb][cc];
                 int32_t R, G, Bc;
                 ycocg_to_rgb(lf[o], lf[o + plane], lf[o + 2 * plane], &R, &G, &Bc);
                 rgb_tap[a][bb][r][cc][0] = (float)clamp255(R);
@@ -1097,9 +1115,9 @@ int orc_render(const int16_t *lf, int32_t U, int32_t V, int32_t W, int32_t H, in
           for (int a = 0; a < 2; a++) {
             float lt[2];
             for (int bb = 0; bb < 2; bb++) {
-              float l0 = lerpf(rgb_tap[a][bb][0][0][ch], rgb_tap[a][bb][0][1][ch], fs);
-              float l1 = lerpf(rgb_tap[a][bb][1][0][ch], rgb_tap[a][bb][1][1][ch], fs);
-              lt[bb] = lerpf(l0, l1, ft);
+              float l0 = lerpf(rgb_tap[a][bb][0][0][ch], rgb_tap[a][bb][0][1][ch], fsv[a][bb]);
+              float l1 = lerpf(rgb_tap[a][bb][1][0][ch], rgb_tap[a][bb][1][1][ch], fsv[a][bb]);
+              lt[bb] = lerpf(l0, l1, ftv[a][bb]);
             }
             lv[a] = lerpf(lt[0], lt[1], fv);
           }

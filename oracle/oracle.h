@@ -142,6 +142,10 @@ int orc_decode_all(const uint8_t *stream, int64_t bytes, int32_t b0, int32_t b1,
  * out [n][3][ho][wo] RGB / 255. */
 int orc_render(const int16_t *lf, int32_t U, int32_t V, int32_t W, int32_t H, int32_t wp,
                int32_t hp, const float *views, int32_t n, int32_t wo, int32_t ho, float *out);
+/* orc_render refocused at disparity d: source camera (iu, jv) sampled at
+ * (sx + d (iu - u), ty + d (jv - v)), (u, v) clamped to the grid. */
+int orc_render_focal(const int16_t *lf, int32_t U, int32_t V, int32_t W, int32_t H, int32_t wp, int32_t hp,
+                     const float *views, int32_t n, int32_t wo, int32_t ho, float d, float *out);
 
 /* PSNR_YCoCg (eqs. 4-5), averaged over the views.  Both inputs
  * [U*V][3][hp][wp]; only the W x H area counts. */

@@ -714,6 +714,7 @@ struct RenderArgs {
   const lfc_view *views;
   float *out;  // [n][3][ho][wo]
   int wo, ho, U, V, W, H, TX, TY, fbx_max, fby_max;
+  float disp;  // focal disparity: image-plane shift per unit of camera-grid offset
 };
 
 // lower grid index, upper index and fraction of x on [0, n-1], after clamping
@@ -767,8 +768,22 @@ __device__ __forceinline__ uint32_t rgb_pack(int32_t yv, int32_t co, int32_t cg)
 // The quadrilinear interpolation of one output pixel from its 16 taps
 // P[k][0..3] = (y0,x0), (y0,x1), (y1,x0), (y1,x1) of view k = 0: (u0, v0),
 // 1: (u1, v0), 2: (u0, v1), 3: (u1, v1); lerps in s, t, v, u order.
-__device__ __forceinline__ void interp_store(const uint32_t P[4][4], float fs, float ft, float fu, float fv, float *o,
-                                             size_t plane) {
+// Camera-plane position (clamped to the grid) and the image-plane shift of
+// source view k (0: lower column/row, 1: upper) for focal disparity d: a
+// novel camera focused at disparity d samples source camera (iu, jv) at
+// (s + d (iu - u), t + d (jv - v)).
+// FOCAL false compiles the plain render, where every source view shares one
+// footprint and one set of fractions.
+template <bool FOCAL>
+__device__ __forceinline__ float focal_shift(float d, float x, int n, int i) {
+  if constexpr (!FOCAL) return 0.0f;
+  return d * ((float)i - fminf(fmaxf(x, 0.0f), (float)(n - 1)));
+}
+
+// quadrilinear interpolation of the 16 RGB taps P[view][tap] (taps 00, 01,
+// 10, 11 of each view, at that view's fractions fs[k], ft[k])
+__device__ __forceinline__ void interp_store(const uint32_t P[4][4], const float fs[4], const float ft[4], float fu,
+                                             float fv, float *o, size_t plane) {
 #pragma unroll
   for (int ch = 0; ch < 3; ch++) {
     float lt[4];
@@ -776,7 +791,7 @@ __device__ __forceinline__ void interp_store(const uint32_t P[4][4], float fs, f
     for (int k = 0; k < 4; k++) {
       const float p00 = (float)((P[k][0] >> (8 * ch)) & 255u), p01 = (float)((P[k][1] >> (8 * ch)) & 255u);
       const float p10 = (float)((P[k][2] >> (8 * ch)) & 255u), p11 = (float)((P[k][3] >> (8 * ch)) & 255u);
-      lt[k] = lerpf(lerpf(p00, p01, fs), lerpf(p10, p11, fs), ft);
+      lt[k] = lerpf(lerpf(p00, p01, fs[k]), lerpf(p10, p11, fs[k]), ft[k]);
     }
     const float lv0 = lerpf(lt[0], lt[2], fv), lv1 = lerpf(lt[1], lt[3], fv);
     o[ch * plane] = lerpf(lv0, lv1, fu) / 255.0f;
@@ -785,7 +800,7 @@ __device__ __forceinline__ void interp_store(const uint32_t P[4][4], float fs, f
 
 // One output tile (tile column tbx, tile row tby) of view vw into outn
 // ([3][ho][wo] floats); smem holds the LUT and the footprint accumulators.
-template <int B>
+template <int B, bool FOCAL>
 __device__ __forceinline__ void render_tile(const RenderArgs &a, const lfc_view vw, float *outn, int tbx, int tby,
                                             uint32_t *smem) {
   constexpr int S = B * B, SLOT = 3 * S / 2;   // words per (view, block): 3 channels of packed int16
@@ -800,28 +815,42 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const lfc_view 
   const float sxs = (float)a.W / (float)a.wo, tys = (float)a.H / (float)a.ho;
   const int tx0 = tbx * a.TX, ty0 = tby * a.TY;
   const int tx1 = min(tx0 + a.TX, a.wo) - 1, ty1 = min(ty0 + a.TY, a.ho) - 1;
-  // source footprint of the tile, one pixel wider on each side than needed
-  const float sa = fminf(fmaxf(vw.s + ((float)tx0 + 0.5f) * sxs - 0.5f, 0.0f), (float)(a.W - 1));
-  const float sb = fminf(fmaxf(vw.s + ((float)tx1 + 0.5f) * sxs - 0.5f, 0.0f), (float)(a.W - 1));
-  const float ta = fminf(fmaxf(vw.t + ((float)ty0 + 0.5f) * tys - 0.5f, 0.0f), (float)(a.H - 1));
-  const float tb = fminf(fmaxf(vw.t + ((float)ty1 + 0.5f) * tys - 0.5f, 0.0f), (float)(a.H - 1));
-  const int xlo = max((int)floorf(sa) - 1, 0), xhi = min((int)floorf(sb) + 2, a.W - 1);
-  const int ylo = max((int)floorf(ta) - 1, 0), yhi = min((int)floorf(tb) + 2, a.H - 1);
-  const int fbx0 = xlo / B, fby0 = ylo / B;
-  const int FBX = min(xhi / B - fbx0 + 1, a.fbx_max), FBY = min(yhi / B - fby0 + 1, a.fby_max);
-  const int FB = FBX * FBY, FBM = a.fbx_max * a.fby_max;
   int vis[4];
   vis[0] = jv0 * a.U + iu0;
   vis[1] = jv0 * a.U + iu1;
   vis[2] = jv1 * a.U + iu0;
   vis[3] = jv1 * a.U + iu1;
+  // per source view: image-plane shift (focal disparity) and the tile's
+  // source footprint, one pixel wider on each side than needed
+  float shx[4], shy[4];
+  int fbx0[4], fby0[4], FBX[4], FBY[4], FB[4];
+  int FBmax = 0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    shx[k] = focal_shift<FOCAL>(a.disp, vw.u, a.U, (k & 1) ? iu1 : iu0);
+    shy[k] = focal_shift<FOCAL>(a.disp, vw.v, a.V, (k & 2) ? jv1 : jv0);
+    const float sa = fminf(fmaxf(vw.s + ((float)tx0 + 0.5f) * sxs - 0.5f + shx[k], 0.0f), (float)(a.W - 1));
+    const float sb = fminf(fmaxf(vw.s + ((float)tx1 + 0.5f) * sxs - 0.5f + shx[k], 0.0f), (float)(a.W - 1));
+    const float ta = fminf(fmaxf(vw.t + ((float)ty0 + 0.5f) * tys - 0.5f + shy[k], 0.0f), (float)(a.H - 1));
+    const float tb = fminf(fmaxf(vw.t + ((float)ty1 + 0.5f) * tys - 0.5f + shy[k], 0.0f), (float)(a.H - 1));
+    const int xlo = max((int)floorf(sa) - 1, 0), xhi = min((int)floorf(sb) + 2, a.W - 1);
+    const int ylo = max((int)floorf(ta) - 1, 0), yhi = min((int)floorf(tb) + 2, a.H - 1);
+    fbx0[k] = xlo / B;
+    fby0[k] = ylo / B;
+    FBX[k] = min(xhi / B - fbx0[k] + 1, a.fbx_max);
+    FBY[k] = min(yhi / B - fby0[k] + 1, a.fby_max);
+    FB[k] = FBX[k] * FBY[k];
+    FBmax = max(FBmax, FB[k]);
+  }
+  const int FBM = a.fbx_max * a.fby_max;
   const int depth = a.ra.L - 1;
   __syncthreads();
 
   // (1) key-view rows: item = (view k, block, channel, row)
-  for (int it = tid; it < 4 * FB * 3 * B; it += kThreads) {
-    const int y = it % B, r1 = it / B, c = r1 % 3, r2 = r1 / 3, bb = r2 % FB, k = r2 / FB;
-    const int b = (fby0 + bb / FBX) * a.ra.nbx + fbx0 + bb % FBX;
+  for (int it = tid; it < 4 * FBmax * 3 * B; it += kThreads) {
+    const int y = it % B, r1 = it / B, c = r1 % 3, r2 = r1 / 3, bb = r2 % FBmax, k = r2 / FBmax;
+    if (bb >= FB[k]) continue;
+    const int b = (fby0[k] + bb / FBX[k]) * a.ra.nbx + fbx0[k] + bb % FBX[k];
     uint32_t x[B / 2];
     load_row<B>(a.ra.rkv + ((size_t)(a.ra.root[vis[k]] * a.ra.nb + b) * 3 + c) * S + y * B, x);
 #pragma unroll
@@ -837,14 +866,17 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const lfc_view 
     for (int k = 0; k < 4; k++) node[k] = a.ra.path[vis[k] * depth + l];
 #pragma unroll
     for (int k = 0; k < 4; k++) {
+      // views with one ancestor share its decoded blocks when their
+      // footprints coincide (no focal shift)
       owner[k] = k;
-      for (int k2 = k - 1; k2 >= 0; --k2)
-        if (node[k2] == node[k]) owner[k] = k2;
+      if (!FOCAL)
+        for (int k2 = k - 1; k2 >= 0; --k2)
+          if (node[k2] == node[k]) owner[k] = k2;
     }
-    for (int it = tid; it < 4 * FB * 3; it += kThreads) {
-      const int c = it % 3, r1 = it / 3, bb = r1 % FB, k = r1 / FB;
-      if (owner[k] != k) continue;
-      const int b = (fby0 + bb / FBX) * a.ra.nbx + fbx0 + bb % FBX;
+    for (int it = tid; it < 4 * FBmax * 3; it += kThreads) {
+      const int c = it % 3, r1 = it / 3, bb = r1 % FBmax, k = r1 / FBmax;
+      if (owner[k] != k || bb >= FB[k]) continue;
+      const int b = (fby0[k] + bb / FBX[k]) * a.ra.nbx + fbx0[k] + bb % FBX[k];
       const uint32_t *gw = nullptr;
       const uint32_t e = locate(a.ra, 3 * b + c, node[k], &gw);
       if (e == kAbsent) continue;
@@ -862,8 +894,9 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const lfc_view 
   }
 
   // (3) YCoCg-R -> RGB in place: item = (view, block)
-  for (int it = tid; it < 4 * FB; it += kThreads) {
-    const int k = it / FB, bb = it % FB;
+  for (int it = tid; it < 4 * FBmax; it += kThreads) {
+    const int k = it / FBmax, bb = it % FBmax;
+    if (bb >= FB[k]) continue;
     uint32_t *slot = acc + (k * FBM + bb) * SLOT;
     uint32_t v[SLOT];
 #pragma unroll
@@ -880,29 +913,26 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const lfc_view 
 
   // (4) quadrilinear interpolation of every output pixel of the tile
   const size_t plane = (size_t)a.ho * a.wo;
-  const int FW = FBX * B, FH = FBY * B;
   for (int p = tid; p < a.TX * a.TY; p += kThreads) {
     const int X = tx0 + p % a.TX, Yp = ty0 + p / a.TX;
     if (X >= a.wo || Yp >= a.ho) continue;
-    int x0, x1, y0, y1;
-    float fs, ft;
-    cell(vw.s + ((float)X + 0.5f) * sxs - 0.5f, a.W, x0, x1, fs);
-    cell(vw.t + ((float)Yp + 0.5f) * tys - 0.5f, a.H, y0, y1, ft);
-    const int lx0 = min(max(x0 - fbx0 * B, 0), FW - 1), lx1 = min(max(x1 - fbx0 * B, 0), FW - 1);
-    const int ly0 = min(max(y0 - fby0 * B, 0), FH - 1), ly1 = min(max(y1 - fby0 * B, 0), FH - 1);
-    // word of footprint pixel (lx, ly) within a view's part of the tile
-    const int i00 = ((ly0 / B) * FBX + lx0 / B) * SLOT + (ly0 % B) * B + lx0 % B;
-    const int i01 = ((ly0 / B) * FBX + lx1 / B) * SLOT + (ly0 % B) * B + lx1 % B;
-    const int i10 = ((ly1 / B) * FBX + lx0 / B) * SLOT + (ly1 % B) * B + lx0 % B;
-    const int i11 = ((ly1 / B) * FBX + lx1 / B) * SLOT + (ly1 % B) * B + lx1 % B;
+    const float sx = vw.s + ((float)X + 0.5f) * sxs - 0.5f, ty = vw.t + ((float)Yp + 0.5f) * tys - 0.5f;
     uint32_t P[4][4];
+    float fs[4], ft[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) {
+      int x0, x1, y0, y1;
+      cell(sx + shx[k], a.W, x0, x1, fs[k]);
+      cell(ty + shy[k], a.H, y0, y1, ft[k]);
+      const int FW = FBX[k] * B, FH = FBY[k] * B;
+      const int lx0 = min(max(x0 - fbx0[k] * B, 0), FW - 1), lx1 = min(max(x1 - fbx0[k] * B, 0), FW - 1);
+      const int ly0 = min(max(y0 - fby0[k] * B, 0), FH - 1), ly1 = min(max(y1 - fby0[k] * B, 0), FH - 1);
+      // word of footprint pixel (lx, ly) within the view's part of the tile
       const uint32_t *img = acc + k * FBM * SLOT;
-      P[k][0] = img[i00];
-      P[k][1] = img[i01];
-      P[k][2] = img[i10];
-      P[k][3] = img[i11];
+      P[k][0] = img[((ly0 / B) * FBX[k] + lx0 / B) * SLOT + (ly0 % B) * B + lx0 % B];
+      P[k][1] = img[((ly0 / B) * FBX[k] + lx1 / B) * SLOT + (ly0 % B) * B + lx1 % B];
+      P[k][2] = img[((ly1 / B) * FBX[k] + lx0 / B) * SLOT + (ly1 % B) * B + lx0 % B];
+      P[k][3] = img[((ly1 / B) * FBX[k] + lx1 / B) * SLOT + (ly1 % B) * B + lx1 % B];
     }
     interp_store(P, fs, ft, fu, fv, outn + (size_t)Yp * a.wo + X, plane);
   }
@@ -918,26 +948,30 @@ struct InterpArgs {
   const lfc_view *views;
   float *out;
   int wo, ho, U, V, W, H, wp, hp;
+  float disp;   // focal disparity (as RenderArgs)
 };
 
+template <bool FOCAL>
 __global__ __launch_bounds__(kThreads) void k_interp(InterpArgs a) {
   const int X = blockIdx.x * kThreads + threadIdx.x, Yp = blockIdx.y, n = blockIdx.z;
   if (X >= a.wo) return;
   const lfc_view vw = a.views[n];
   int iu0, iu1, jv0, jv1, x0, x1, y0, y1;
-  float fu, fv, fs, ft;
+  float fu, fv;
   cell(vw.u, a.U, iu0, iu1, fu);
   cell(vw.v, a.V, jv0, jv1, fv);
   const float sxs = (float)a.W / (float)a.wo, tys = (float)a.H / (float)a.ho;
-  cell(vw.s + ((float)X + 0.5f) * sxs - 0.5f, a.W, x0, x1, fs);
-  cell(vw.t + ((float)Yp + 0.5f) * tys - 0.5f, a.H, y0, y1, ft);
+  const float sx = vw.s + ((float)X + 0.5f) * sxs - 0.5f, ty = vw.t + ((float)Yp + 0.5f) * tys - 0.5f;
   const int vis[4] = {jv0 * a.U + iu0, jv0 * a.U + iu1, jv1 * a.U + iu0, jv1 * a.U + iu1};
   const size_t cplane = (size_t)a.hp * a.wp;
-  const size_t o00 = (size_t)y0 * a.wp + x0, o01 = (size_t)y0 * a.wp + x1;
-  const size_t o10 = (size_t)y1 * a.wp + x0, o11 = (size_t)y1 * a.wp + x1;
   uint32_t P[4][4];
+  float fs[4], ft[4];
 #pragma unroll
   for (int k = 0; k < 4; k++) {
+    cell(sx + focal_shift<FOCAL>(a.disp, vw.u, a.U, (k & 1) ? iu1 : iu0), a.W, x0, x1, fs[k]);
+    cell(ty + focal_shift<FOCAL>(a.disp, vw.v, a.V, (k & 2) ? jv1 : jv0), a.H, y0, y1, ft[k]);
+    const size_t o00 = (size_t)y0 * a.wp + x0, o01 = (size_t)y0 * a.wp + x1;
+    const size_t o10 = (size_t)y1 * a.wp + x0, o11 = (size_t)y1 * a.wp + x1;
     const int16_t *yp = a.dec + (size_t)vis[k] * 3 * cplane, *cop = yp + cplane, *cgp = cop + cplane;
     P[k][0] = rgb_pack(yp[o00], cop[o00], cgp[o00]);
     P[k][1] = rgb_pack(yp[o01], cop[o01], cgp[o01]);
@@ -948,11 +982,11 @@ __global__ __launch_bounds__(kThreads) void k_interp(InterpArgs a) {
   interp_store(P, fs, ft, fu, fv, a.out + (size_t)n * 3 * plane + (size_t)Yp * a.wo + X, plane);
 }
 
-template <int B>
+template <int B, bool FOCAL>
 __global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
   extern __shared__ uint32_t smem[];
   const int n = blockIdx.z;
-  render_tile<B>(a, a.views[n], a.out + (size_t)n * 3 * a.ho * a.wo, blockIdx.x, blockIdx.y, smem);
+  render_tile<B, FOCAL>(a, a.views[n], a.out + (size_t)n * 3 * a.ho * a.wo, blockIdx.x, blockIdx.y, smem);
 }
 
 // Many render requests in one launch, possibly of different light fields and
@@ -970,7 +1004,7 @@ __global__ __launch_bounds__(kThreads) void k_render_multi(const RenderReq *reqs
   const RenderReq &r = reqs[blockIdx.y];
   const int t = blockIdx.x;
   if (t >= r.ntiles) return;
-  render_tile<B>(r.a, r.view, r.a.out, t % r.ntx, t / r.ntx, smem);
+  render_tile<B, false>(r.a, r.view, r.a.out, t % r.ntx, t / r.ntx, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1115,6 +1149,7 @@ bool render_decoded(const lfc::Geometry &g, int32_t n, int32_t wo, int32_t ho) {
 struct RenderChoice {
   bool decoded;
   RenderPlan pl;
+  float disp;   // focal disparity
 };
 
 // cfg NULL or path LFC_RENDER_AUTO: the library's choice (render_decoded, and
@@ -1126,6 +1161,9 @@ lfc_status choose_render(const lfc_lf *lf, int32_t n, int32_t wo, int32_t ho, co
   const int path = cfg ? cfg->path : LFC_RENDER_AUTO;
   if (path != LFC_RENDER_AUTO && path != LFC_RENDER_TILES && path != LFC_RENDER_DECODED)
     return fail(LFC_E_INVALID, std::string(who) + ": unknown render path");
+  rc.disp = cfg ? cfg->disparity : 0.0f;
+  if (!std::isfinite(rc.disp) || std::fabs(rc.disp) > 1.0e6f)
+    return fail(LFC_E_INVALID, std::string(who) + ": disparity must be finite, |d| <= 1e6");
   rc.decoded = path == LFC_RENDER_AUTO ? render_decoded(g, n, wo, ho) : path == LFC_RENDER_DECODED;
   if (rc.decoded) return LFC_OK;
   int TX = 64, TY = 16;
@@ -1158,8 +1196,12 @@ lfc_status render_with(const lfc_lf *lf, const lfc_view *views, int32_t n, int32
       return fail(LFC_E_NOMEM, "lfc_render_views: scratch for the decoded views");
     lfc_status st = decode_images<B>(lf, dec, s);
     if (st == LFC_OK) {
-      InterpArgs ia{dec, views, out, wo, ho, g.U, g.V, g.W, g.H, g.wp, g.hp};
-      hipLaunchKernelGGL(k_interp, dim3((wo + kThreads - 1) / kThreads, ho, n), dim3(kThreads), 0, s, ia);
+      InterpArgs ia{dec, views, out, wo, ho, g.U, g.V, g.W, g.H, g.wp, g.hp, rc.disp};
+      const dim3 grid((wo + kThreads - 1) / kThreads, ho, n);
+      if (rc.disp != 0.0f)
+        hipLaunchKernelGGL(k_interp<true>, grid, dim3(kThreads), 0, s, ia);
+      else
+        hipLaunchKernelGGL(k_interp<false>, grid, dim3(kThreads), 0, s, ia);
       st = launched("lfc_render_views");
     }
     if (!ws && hipFreeAsync(dec, s) != hipSuccess && st == LFC_OK)
@@ -1167,9 +1209,12 @@ lfc_status render_with(const lfc_lf *lf, const lfc_view *views, int32_t n, int32
     return st;
   }
   const RenderPlan &pl = rc.pl;
-  RenderArgs a{ra_args(lf), views, out, wo, ho, g.U, g.V, g.W, g.H, pl.TX, pl.TY, pl.fbx, pl.fby};
+  RenderArgs a{ra_args(lf), views, out, wo, ho, g.U, g.V, g.W, g.H, pl.TX, pl.TY, pl.fbx, pl.fby, rc.disp};
   dim3 grid((wo + pl.TX - 1) / pl.TX, (ho + pl.TY - 1) / pl.TY, n);
-  hipLaunchKernelGGL(k_render<B>, grid, dim3(kThreads), pl.lds, s, a);
+  if (rc.disp != 0.0f)
+    hipLaunchKernelGGL((k_render<B, true>), grid, dim3(kThreads), pl.lds, s, a);
+  else
+    hipLaunchKernelGGL((k_render<B, false>), grid, dim3(kThreads), pl.lds, s, a);
   return launched("lfc_render_views");
 }
 
@@ -1275,10 +1320,11 @@ extern "C" lfc_status lfc_render_tune(const lfc_lf *lf, const lfc_view *d_views,
   std::memset(res, 0, sizeof *res);
   static const int kShapes[][2] = {{32, 8}, {32, 16}, {64, 8}, {64, 16}, {64, 32}, {128, 8}, {128, 16}, {256, 8}};
   std::vector<lfc_render_config> cands;
-  cands.push_back(lfc_render_config{LFC_RENDER_DECODED, 0, 0});
+  cands.push_back(lfc_render_config{LFC_RENDER_DECODED, 0, 0, 0.0f});
   for (const auto &sh : kShapes) {
     RenderPlan pl;
-    if (plan_render(lf->geo, out_w, out_h, pl, sh[0], sh[1], false)) cands.push_back(lfc_render_config{LFC_RENDER_TILES, sh[0], sh[1]});
+    if (plan_render(lf->geo, out_w, out_h, pl, sh[0], sh[1], false))
+      cands.push_back(lfc_render_config{LFC_RENDER_TILES, sh[0], sh[1], 0.0f});
   }
   int16_t *ws = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1402,8 +1448,8 @@ extern "C" lfc_status lfc_render_plan_launch(lfc_render_plan *p, hipStream_t s) 
 
 extern "C" lfc_status lfc_render_plan_info(const lfc_render_plan *p, lfc_render_config *cfg, int32_t *graph) {
   if (!p || !cfg || !graph) return fail(LFC_E_INVALID, "lfc_render_plan_info: null argument");
-  *cfg = p->rc.decoded ? lfc_render_config{LFC_RENDER_DECODED, 0, 0}
-                       : lfc_render_config{LFC_RENDER_TILES, p->rc.pl.TX, p->rc.pl.TY};
+  *cfg = p->rc.decoded ? lfc_render_config{LFC_RENDER_DECODED, 0, 0, p->rc.disp}
+                       : lfc_render_config{LFC_RENDER_TILES, p->rc.pl.TX, p->rc.pl.TY, p->rc.disp};
   *graph = p->exec != nullptr;
   return LFC_OK;
 }
@@ -1446,7 +1492,7 @@ lfc_status render_req_fill(const lfc_lf *lf, const lfc_view &v, int wo, int ho, 
   if (!plan_render(g, wo, ho, pl))
     return fail(LFC_E_UNSUPPORTED, "lfc_batch_render: output too strongly minified for the tile footprint");
   RenderReq r{};
-  r.a = RenderArgs{ra_args(lf), nullptr, out, wo, ho, g.U, g.V, g.W, g.H, pl.TX, pl.TY, pl.fbx, pl.fby};
+  r.a = RenderArgs{ra_args(lf), nullptr, out, wo, ho, g.U, g.V, g.W, g.H, pl.TX, pl.TY, pl.fbx, pl.fby, 0.0f};
   r.view = v;
   r.ntx = (wo + pl.TX - 1) / pl.TX;
   r.ntiles = r.ntx * ((ho + pl.TY - 1) / pl.TY);

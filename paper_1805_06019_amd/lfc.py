@@ -80,7 +80,7 @@ MLP_PARAMS = 7653
 
 
 class c_render_config(C.Structure):
-    _fields_ = [("path", C.c_int32), ("tile_w", C.c_int32), ("tile_h", C.c_int32)]
+    _fields_ = [("path", C.c_int32), ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("disparity", C.c_float)]
 
 
 TUNE_MAX = 16
@@ -453,23 +453,30 @@ def _render_buffers(views, out_w: int, out_h: int, out):
     return n, out
 
 
-def _config(cfg):
-    """None, or (path, tile_w, tile_h)."""
-    return None if cfg is None else C.byref(c_render_config(*cfg))
+def _config(cfg, disparity: float = 0.0):
+    """None, or (path, tile_w, tile_h[, disparity]); a nonzero disparity
+    alone gives the automatic shape refocused."""
+    if cfg is None and disparity == 0.0:
+        return None
+    c = c_render_config(*(cfg if cfg is not None else (RENDER_AUTO, 0, 0)))
+    if disparity != 0.0:
+        c.disparity = disparity
+    return C.byref(c)
 
 
-def lfc_render_views(lf: LightField, views, out_w: int, out_h: int, out=None, cuda_stream=None, cfg=None):
+def lfc_render_views(lf: LightField, views, out_w: int, out_h: int, out=None, cuda_stream=None, cfg=None,
+                     disparity: float = 0.0):
     """Renders novel views: views float32 CUDA tensor [n][4] = (u, v, s, t).
     Returns float32 CUDA [n][3][out_h][out_w], RGB / 255.  cfg: None
     (automatic) or (path, tile_w, tile_h) with path RENDER_TILES or
-    RENDER_DECODED."""
+    RENDER_DECODED; disparity refocuses (include/lfc.h)."""
     n, out = _render_buffers(views, out_w, out_h, out)
-    if cfg is None:
+    if cfg is None and disparity == 0.0:
         _check(load().lfc_render_views(lf.handle, views.data_ptr(), n, out_w, out_h, out.data_ptr(),
                                        _stream_ptr(cuda_stream)))
     else:
         _check(load().lfc_render_views_ex(lf.handle, views.data_ptr(), n, out_w, out_h, out.data_ptr(),
-                                          _config(cfg), _stream_ptr(cuda_stream)))
+                                          _config(cfg, disparity), _stream_ptr(cuda_stream)))
     return out
 
 
@@ -489,11 +496,12 @@ class RenderPlan:
     captured in a HIP graph (launch() is then one graph launch).  The views
     tensor is read at each launch; rewrite it in place between launches."""
 
-    def __init__(self, lf: LightField, views, out_w: int, out_h: int, out=None, cfg=None, graph: bool = True):
+    def __init__(self, lf: LightField, views, out_w: int, out_h: int, out=None, cfg=None, graph: bool = True,
+                 disparity: float = 0.0):
         n, self.out = _render_buffers(views, out_w, out_h, out)
         self.views, self.lf = views, lf
         h = C.c_void_p()
-        _check(load().lfc_render_plan_create(lf.handle, _config(cfg), views.data_ptr(), n, out_w, out_h,
+        _check(load().lfc_render_plan_create(lf.handle, _config(cfg, disparity), views.data_ptr(), n, out_w, out_h,
                                              self.out.data_ptr(), int(graph), C.byref(h)))
         self.handle = h.value
 

@@ -131,3 +131,49 @@ def test_render_paths_are_bit_identical(gpu, case, monkeypatch):
         monkeypatch.setenv("LFC_RENDER_PATH", path)
         outs.append(lfc.lfc_render_views(lf, views, wo, ho))
     assert torch.equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("path", ["tiles", "decoded"])
+@pytest.mark.parametrize("d", [-2.0, 0.7, 3.0])
+@pytest.mark.parametrize("case", [CASES[0], CASES[2], CASES[3], CASES[4], CASES[5], CASES[8]],
+                         ids=["8x8-512", "B8", "B2", "9x9", "row", "minified"])
+def test_refocused_render_matches_oracle(gpu, case, d, path):
+    # reading C20: each source view sampled at its own image-plane shift
+    U, V, W, H, kw, wo, ho, pan = case
+    say("refocus", case[:4], d, path)
+    rgb = make_lf(U, V, W, H, seed=U * 19 + W)
+    enc = oracle_encode(rgb, **kw)
+    lf = lfc.lfc_open(enc.stream)
+    views = synth.novel_views(5, U, V, seed=U + W, pan=pan)
+    mode = lfc.RENDER_TILES if path == "tiles" else lfc.RENDER_DECODED
+    got = lfc.lfc_render_views(lf, torch.from_numpy(views).cuda(), wo, ho, cfg=(mode, 0, 0, d)).cpu().numpy()
+    ref = oracle.render(enc.r0, U, V, W, H, views, wo, ho, disparity=d)
+    assert max_abs(got, ref) <= TOL
+    lf.close()
+
+
+def test_refocus_on_a_plane_is_sharp_on_the_gpu(gpu):
+    # views of one plane moving by 2 pixels per camera step, coded losslessly:
+    # focused at d = -2, a camera between grid positions sees the plane's pixels
+    U, V, W, H, delta = 4, 4, 64, 40, 2
+    r = np.random.default_rng(5)
+    base = r.integers(0, 256, (H + delta * (V - 1), W + delta * (U - 1), 3), dtype=np.uint8)
+    rgb = np.zeros((V, U, H, W, 3), dtype=np.uint8)
+    for j in range(V):
+        for i in range(U):
+            rgb[j, i] = base[delta * j: delta * j + H, delta * i: delta * i + W]
+    enc = oracle_encode(rgb, block=4, levels=2, cluster=(2,))
+    lf = lfc.lfc_open(enc.stream)
+    u, v = 1.5, 0.5
+    views = torch.tensor([[u, v, 0.0, 0.0]], dtype=torch.float32, device="cuda")
+    want = base[int(delta * v) + 1: int(delta * v) + H - 1, int(delta * u) + 1: int(delta * u) + W - 1]
+    want = want.transpose(2, 0, 1).astype(np.float32) / 255.0
+    for mode in (lfc.RENDER_TILES, lfc.RENDER_DECODED):
+        got = lfc.lfc_render_views(lf, views, W, H, cfg=(mode, 0, 0, -float(delta)))[0].cpu().numpy()
+        assert np.array_equal(got[:, 1:H - 1, 1:W - 1], want), mode
+    plan = lfc.RenderPlan(lf, views, W, H, disparity=-float(delta))
+    assert np.array_equal(plan.launch()[0].cpu().numpy()[:, 1:H - 1, 1:W - 1], want)
+    plan.close()
+    with pytest.raises(lfc.LFCError):
+        lfc.lfc_render_views(lf, views, W, H, disparity=float("nan"))
+    lf.close()

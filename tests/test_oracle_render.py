@@ -63,3 +63,56 @@ def test_multilinear_field_is_exact(wo, ho):
         assert np.all(np.abs(out[k, 0] * 255.0 - val) <= 2e-3)
         # (the middle channel was halved and floored, so it is not multilinear)
         assert np.all(np.abs(out[k, 2] * 255.0 - (255 - val)) <= 2e-3)
+
+
+# -- refocusing (reading C20) -------------------------------------------------
+
+def lambertian_plane(U, V, W, H, delta, seed):
+    """Views of one textured plane whose image moves by delta pixels per
+    camera step: view (i, j) at pixel (x, y) shows base[y + delta j, x + delta i]."""
+    r = np.random.default_rng(seed)
+    base = r.integers(0, 256, (H + delta * (V - 1), W + delta * (U - 1), 3), dtype=np.uint8)
+    lf = np.zeros((V, U, H, W, 3), dtype=np.uint8)
+    for j in range(V):
+        for i in range(U):
+            lf[j, i] = base[delta * j: delta * j + H, delta * i: delta * i + W]
+    return lf, base
+
+
+def test_refocus_on_a_plane_reproduces_it_sharply():
+    # focused at d = -delta, the four source views agree on every ray: a
+    # camera half-way between grid positions (u = 1.5, v = 2.5 with delta = 2)
+    # sees base[y + delta v, x + delta u], an integer pixel of the plane
+    U, V, W, H, delta = 4, 4, 24, 20, 2
+    lf, base = lambertian_plane(U, V, W, H, delta, 5)
+    dec = encode_decode(lf, U, V, W, H)
+    u, v = 1.5, 2.5
+    out = oracle.render(dec, U, V, W, H, np.array([[u, v, 0, 0]], dtype=np.float32), W, H,
+                        disparity=-float(delta))[0]
+    ox, oy = int(delta * u), int(delta * v)
+    # interior pixels, where every source view's sample lies inside its image
+    want = base[oy + 1: oy + H - 1, ox + 1: ox + W - 1].transpose(2, 0, 1).astype(np.float32) / 255.0
+    assert np.array_equal(out[:, 1:H - 1, 1:W - 1], want)
+    # without refocusing the same camera blends four different pixels
+    plain = oracle.render(dec, U, V, W, H, np.array([[u, v, 0, 0]], dtype=np.float32), W, H)[0]
+    assert not np.array_equal(plain[:, 1:H - 1, 1:W - 1], want)
+
+
+def test_refocus_leaves_grid_cameras_and_zero_disparity_unchanged():
+    U, V, W, H = 4, 3, 16, 12
+    lf = synth.light_field(synth.LFSpec(U, V, W, H, 3, 1.0, 2.0, 19), threads=1)
+    dec = encode_decode(lf, U, V, W, H)
+    # a camera on the grid weights one source view by 1 and its own shift is 0;
+    # below the last row and column the other weights are exactly 0 (lerp at
+    # fraction 0), on them the lerp at fraction 1 rounds
+    grid = np.array([[u, v, 0.25, -0.5] for v in range(V) for u in range(U)], dtype=np.float32)
+    inner = (grid[:, 0] < U - 1) & (grid[:, 1] < V - 1)
+    for d in (-3.0, 0.7, 5.0):
+        got = oracle.render(dec, U, V, W, H, grid, 20, 9, disparity=d)
+        ref = oracle.render(dec, U, V, W, H, grid, 20, 9)
+        assert np.array_equal(got[inner], ref[inner])
+        assert np.abs(got - ref).max() <= 1e-6
+    views = synth.novel_views(6, U, V, seed=4, pan=2.0)
+    a = oracle.render(dec, U, V, W, H, views, 20, 9)
+    b = oracle.render(dec, U, V, W, H, views, 20, 9, disparity=1e-30)   # the general path, vanishing shift
+    assert np.array_equal(a, b)
