@@ -221,7 +221,7 @@ lfc_status lfc_encode_ctl(const uint8_t *rgb, const lfc_params *p, lfc_control *
 #define LFC_MLP_PARAMS 7653
 
 /*
- * Inference over n feature rows (device float32 [n][16]): per row the
+ * Inference over n feature rows (device float32 [n][16], 16-byte aligned): per row the
  * argmax of each head (ties to the lower class) into d_cls and d_rng
  * (int8 [n]), the threshold head's top softmax probability into d_conf
  * (float [n], may be NULL) and the 37 logits into d_logits (float [n][37],

@@ -4,10 +4,13 @@
 // 16 features -> 64 ReLU -> 64 ReLU -> 37 logits (10 threshold classes, 27
 // range classes).  Parameters W1[64][16], b1[64], W2[64][64], b2[64],
 // W3[37][64], b3[37]; inference and gradients read them as bfloat16 and
-// accumulate in float32.  The network is tiny (7,653 parameters), so every
-// workgroup keeps all of them in LDS as float32 and streams rows; the
-// gradient kernel keeps a tile of 128 rows' activations in LDS as well and
-// forms each weight gradient as a 128-long dot product over the tile.
+// accumulate in float32.  The network is tiny (7,653 parameters).
+// Inference runs one row per lane with the parameters, unpacked once per
+// call to float32, read through the scalar unit (they are the same for every
+// lane), so each multiply-add takes its weight from a scalar register; the
+// gradient kernel keeps all parameters and a tile of 128 rows' activations
+// in LDS and forms each weight gradient as a 128-long dot product over the
+// tile.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,10 +43,17 @@ __device__ __forceinline__ void load_weights(const uint16_t *w, float *sw) {
 }
 
 // ---------------------------------------------------------------------------
-// inference: one row per lane, all parameters in LDS (read as broadcasts)
+// inference: one row per lane, parameters through the scalar unit
 // ---------------------------------------------------------------------------
+typedef const __attribute__((address_space(4))) float *uniform_f32;
+
+__global__ __launch_bounds__(kThreads) void k_mlp_unpack(const uint16_t *w, float *wf) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i < kParams) wf[i] = bf16_to_f32(w[i]);
+}
+
 struct InferArgs {
-  const uint16_t *w;
+  const float *wf;   // the parameters as float32 (k_mlp_unpack)
   const float *x;
   int64_t n;
   int8_t *cls, *rng;
@@ -51,10 +61,12 @@ struct InferArgs {
 };
 
 __global__ __launch_bounds__(kThreads) void k_mlp_infer(InferArgs a) {
-  __shared__ float sw[kParams];
-  load_weights(a.w, sw);
-  __syncthreads();
-  for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < a.n; r += (int64_t)gridDim.x * kThreads) {
+  const uniform_f32 sw = (uniform_f32)a.wf;
+  {
+    // one row per lane and no loop over rows, so that the parameter loads stay
+    // at their uses instead of being hoisted out of a loop into registers
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r >= a.n) return;
     float x[kIn];
     const float4 *xr = reinterpret_cast<const float4 *>(a.x + r * kIn);
 #pragma unroll
@@ -81,33 +93,38 @@ __global__ __launch_bounds__(kThreads) void k_mlp_infer(InferArgs a) {
       for (int k = 0; k < kH; k++) acc += sw[oW2 + j * kH + k] * h1[k];
       h2[j] = fmaxf(acc, 0.0f);
     }
-    // heads: running argmax (ties to the lower class) and the threshold
-    // head's softmax denominator relative to its maximum
-    float best_t = 0.0f, best_r = 0.0f, zt[kCls];
-    int ct = 0, cr = 0;
+    float z[kOut];
 #pragma unroll
     for (int o = 0; o < kOut; o++) {
       float acc = sw[oB3 + o];
 #pragma unroll
       for (int k = 0; k < kH; k++) acc += sw[oW3 + o * kH + k] * h2[k];
-      if (a.logits) a.logits[r * kOut + o] = acc;
-      if (o < kCls) {
-        zt[o] = acc;
-        if (o == 0 || acc > best_t) {
-          best_t = acc;
-          ct = o;
-        }
-      } else if (o == kCls || acc > best_r) {
-        best_r = acc;
-        cr = o - kCls;
-      }
+      z[o] = acc;
     }
+    if (a.logits)
+#pragma unroll
+      for (int o = 0; o < kOut; o++) a.logits[r * kOut + o] = z[o];
+    // heads: argmax (ties to the lower class)
+    float best_t = z[0], best_r = z[kCls];
+    int ct = 0, cr = 0;
+#pragma unroll
+    for (int o = 1; o < kCls; o++)
+      if (z[o] > best_t) {
+        best_t = z[o];
+        ct = o;
+      }
+#pragma unroll
+    for (int o = 1; o < kRng; o++)
+      if (z[kCls + o] > best_r) {
+        best_r = z[kCls + o];
+        cr = o;
+      }
     a.cls[r] = (int8_t)ct;
     a.rng[r] = (int8_t)cr;
     if (a.conf) {
       float den = 0.0f;
 #pragma unroll
-      for (int o = 0; o < kCls; o++) den += expf(zt[o] - best_t);
+      for (int o = 0; o < kCls; o++) den += expf(z[o] - best_t);
       a.conf[r] = 1.0f / den;
     }
   }
@@ -303,10 +320,23 @@ constexpr size_t kGradLds = sizeof(float) * (kParams + kTile * (kIn + 2 * kH + k
 lfc_status infer_launch(const uint16_t *w, const float *x, int64_t n, int8_t *cls, int8_t *rng, float *conf,
                         float *logits, hipStream_t s) {
   if (n == 0) return LFC_OK;
-  const int64_t blocks = std::min<int64_t>((n + kThreads - 1) / kThreads, 4096);
-  InferArgs a{w, x, n, cls, rng, conf, logits};
-  hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
-  return mlp_launched("lfc_mlp_infer");
+  if (n > (int64_t)0x7FFFFFFF * kThreads) return lfc::fail(LFC_E_INVALID, "lfc_mlp_infer: too many rows");
+  // the float32 parameters live in stream-ordered scratch for this call
+  float *wf = nullptr;
+  if (hipMallocAsync(reinterpret_cast<void **>(&wf), sizeof(float) * kParams, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return lfc::fail(LFC_E_NOMEM, "lfc_mlp_infer: scratch for the parameters");
+  }
+  hipLaunchKernelGGL(k_mlp_unpack, dim3((kParams + kThreads - 1) / kThreads), dim3(kThreads), 0, s, w, wf);
+  lfc_status st = mlp_launched("lfc_mlp_infer");
+  if (st == LFC_OK) {
+    const int64_t blocks = (n + kThreads - 1) / kThreads;   // n < 2^31 * 256, checked by the callers
+    InferArgs a{wf, x, n, cls, rng, conf, logits};
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+    st = mlp_launched("lfc_mlp_infer");
+  }
+  if (hipFreeAsync(wf, s) != hipSuccess && st == LFC_OK) st = lfc::fail(LFC_E_HIP, "lfc_mlp_infer: scratch release");
+  return st;
 }
 
 }  // namespace
