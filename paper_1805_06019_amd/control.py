@@ -5,7 +5,7 @@ The paper's encoder uses one pixel threshold and one block-energy threshold
 for every block (Sec. 3.2) and notes the lack of finer control (Sec. 5).
 Here every residual block gets its own threshold class (and range class),
 chosen by an exhaustive rate-distortion search (the labeller, the fallback
-and the judge) or predicted by a small network trained on the search's
+and the reference for rate and quality) or predicted by a small network trained on the search's
 labels.  The decoder does not change.
 
     python -m paper_1805_06019_amd.control [--rows N] [--epochs E] [--quick]
