@@ -2,6 +2,7 @@
 
     python -m paper_1805_06019_amd.prof_summary trace <kernel_trace.db> [command]
     python -m paper_1805_06019_amd.prof_summary traffic <fetch.db> <write.db> <out.json> [command]
+    python -m paper_1805_06019_amd.prof_summary counters <counters.db>...
 
 ``trace`` prints a markdown table of per-kernel dispatch counts and durations.
 ``traffic`` reads one FETCH_SIZE run and one WRITE_SIZE run (KiB per
@@ -9,6 +10,8 @@ dispatch), scales each by what the same counter reads for a device-to-device
 copy of 256 MiB in the same run (the copy moves exactly 256 MiB each way),
 and writes the per-launch HBM bytes of the whole-field decode kernel,
 together with a hash of the kernel source it was measured on.
+``counters`` prints, for the whole-field decode kernel, the mean per dispatch
+of every counter in the given runs.
 """
 from __future__ import annotations
 
@@ -58,15 +61,19 @@ def trace_rows(db: str):
 
 def counter_per_dispatch(db: str, counter: str):
     """{kernel short name: [value per dispatch]} for one counter."""
+    return {n: d[counter] for n, d in counters_per_dispatch(db).items() if counter in d}
+
+
+def counters_per_dispatch(db: str):
+    """{kernel name: {counter: [value per dispatch]}} (a counter's instances summed)."""
     con = sqlite3.connect(db)
     table = [r[0] for r in con.execute("select name from sqlite_master where type in ('table','view')")
              if "counters_collection" in r[0]][0]
-    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    per = collections.defaultdict(lambda: collections.defaultdict(lambda: collections.defaultdict(float)))
     for name, disp, cname, val in con.execute(
             f"select kernel_name, dispatch_id, counter_name, value from {table}"):
-        if cname == counter:
-            per[name][disp] += val
-    return {n: list(d.values()) for n, d in per.items()}
+        per[name][cname][disp] += val
+    return {n: {c: list(v.values()) for c, v in d.items()} for n, d in per.items()}
 
 
 def copy_kernel_value(per: dict) -> float:
@@ -120,6 +127,15 @@ def main(argv):
             json.dump(rec, fh, indent=1)
             fh.write("\n")
         print(json.dumps(rec, indent=1))
+    elif mode == "counters":
+        print("| counter | dispatches | mean per dispatch |")
+        print("|---|---|---|")
+        for db in argv[2:]:
+            for name, d in counters_per_dispatch(db).items():
+                if short_name(name) != DECODE_KERNEL:
+                    continue
+                for c in sorted(d):
+                    print(f"| {c} | {len(d[c])} | {sum(d[c]) / len(d[c]):,.0f} |")
     else:
         raise SystemExit(__doc__)
 
