@@ -9,8 +9,11 @@ stream equals the paper's global encoder with both thresholds 0; at the
 largest lambda every block is dropped; on a two-level tree (parents are
 the lossless key views, so the blocks' choices are independent) the total
 rate falls and the weighted distortion rises as lambda grows, and the
-search's total cost is at most that of any single global pixel threshold.
-The features are pinned on blocks whose statistics are known by hand.
+search's total cost is at most that of any single global pixel threshold;
+a block with a single unit residual is kept exactly while lambda is below
+the closed form w 2^16 / (5 + payload bits).  The features are pinned on
+blocks whose statistics are known by hand (residual spread, a flat parent, a
+horizontal ramp).
 
 The network's oracle (oracle/mlp.py) is pinned by bfloat16 rounding cases,
 a forward pass on hand-set weights, the gradient against central finite
@@ -140,6 +143,45 @@ def test_features_on_blocks_with_known_statistics():
     assert np.allclose(chroma[..., 1:13], 0)
 
 
+def test_single_unit_residuals_are_kept_exactly_below_their_closed_form_lambda():
+    # two grey views in one cluster differ at one pixel (100 vs 102): the key
+    # view holds 101 there, so each view's block carries one unit residual in
+    # Y.  -1 has zigzag value 1: range code 0 (2 values, 16 payload bits); +1
+    # has zigzag value 2: code 12 (a trit and no low bits, 3 values, ceil(8 *
+    # 16 / 5) = 26 bits).  Keeping costs lambda * (5 + payload bits), dropping
+    # costs 6 * 1 * 2^16, so a block is kept exactly while lambda < 393216 / 21
+    # = 18724.6 (view 0) or 393216 / 31 = 12684.4 (view 1).
+    rgb = np.full((1, 2, 4, 4, 3), 100, dtype=np.uint8)
+    rgb[0, 1, 2, 1] = 102
+    p = oracle.Params(2, 1, 4, 4, block=4, levels=2, cluster=(2,))
+    for lam, keep0, keep1 in ((10000, True, True), (12684, True, True), (12685, True, False),
+                              (13500, True, False), (18724, True, False), (18725, False, False),
+                              (20000, False, False)):
+        _, cls, rng, _ = oracle.encode_ctl(rgb, p, oracle.CTL_SEARCH, lam)
+        y = rng.reshape(2, 1, 3)[:, 0, 0]          # node, block, channel
+        assert (y[0] != 26) == keep0 and (y[1] != 26) == keep1, lam
+        if keep0:
+            assert y[0] == 0
+        if keep1:
+            assert y[1] == 12
+
+
+def test_gradient_features_follow_the_parent_axes():
+    # identical views of a horizontal ramp (Y = 10 + 4x): zero residuals, the
+    # parent has horizontal steps of 4 and no vertical change
+    x = np.arange(8)
+    img = np.repeat((10 + 4 * x)[None, :, None], 8, axis=0).repeat(3, axis=2).astype(np.uint8)
+    rgb = np.stack([img, img])[None]
+    p = oracle.Params(2, 1, 8, 8, block=4, levels=2, cluster=(2,))
+    _, _, _, f = oracle.encode_ctl(rgb, p, oracle.CTL_SEARCH, 0, want_features=True)
+    y = f.reshape(2, 4, 3, 16)[:, :, 0]
+    assert np.allclose(y[..., 2:9], 0)                               # no residual
+    assert np.allclose(y[..., 9], np.log2(5) / 8) and np.allclose(y[..., 10], 0)
+    assert np.allclose(y[..., 11], np.log2(5) / 8)
+    # variance of a 4-wide ramp with steps of 4 (values a, a+4, a+8, a+12 on every row): 20
+    assert np.allclose(y[..., 12], np.log2(21) / 16)
+
+
 @pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}x{c[2]}x{c[3]}-B{c[4]['block']}" for c in CASES])
 def test_library_search_table_and_features_equal_the_oracle(case):
     U, V, W, H, kw = case
@@ -214,10 +256,21 @@ def test_forward_on_hand_set_weights():
     p["W3"][:10, :10] = np.eye(10)
     p["W3"][10:, 0] = 2.0
     p["b3"][10:] = -np.arange(27)
+    # biases: unit 20 of layer 2 is its bias 0.75, unit 21 twice layer 1's
+    # unit 30 (bias 0.5); they feed threshold logits 9 and 8
+    p["b2"][20] = 0.75
+    p["b1"][30] = 0.5
+    p["W2"][21, 30] = 2.0
+    p["W3"][9, 9], p["W3"][9, 20] = 0.0, 1.0
+    p["W3"][8, 8], p["W3"][8, 21] = 0.0, 1.0
     w = omlp.pack(p)
     x = np.abs(np.random.default_rng(1).normal(size=(5, 16))) + 0.1
     z, h1, h2 = omlp.forward(w, x)
-    assert np.allclose(z[:, :10], x[:, :10]) and np.allclose(z[:, 10:], 2 * x[:, :1] - np.arange(27))
+    assert np.allclose(z[:, :8], x[:, :8]) and np.allclose(z[:, 10:], 2 * x[:, :1] - np.arange(27))
+    assert np.allclose(z[:, 9], 0.75) and np.allclose(z[:, 8], 1.0)
+    p["W3"][9, 9], p["W3"][9, 20] = 1.0, 0.0
+    p["W3"][8, 8], p["W3"][8, 21] = 1.0, 0.0
+    w = omlp.pack(p)
     x2 = x.copy()
     x2[:, 3] = -1.0     # ReLU cuts it
     assert np.allclose(omlp.forward(w, x2)[0][:, 3], 0.0)

@@ -112,6 +112,13 @@ def test_refocus_leaves_grid_cameras_and_zero_disparity_unchanged():
         ref = oracle.render(dec, U, V, W, H, grid, 20, 9)
         assert np.array_equal(got[inner], ref[inner])
         assert np.abs(got - ref).max() <= 1e-6
+    # a camera off the grid is the camera clamped to the grid, shift included
+    off = np.array([[-1.5, 0.5, 0.3, 0.0], [U + 0.7, V - 1.2, -0.4, 1.0]], dtype=np.float32)
+    on = off.copy()
+    on[:, 0] = np.clip(on[:, 0], 0, U - 1)
+    on[:, 1] = np.clip(on[:, 1], 0, V - 1)
+    assert np.array_equal(oracle.render(dec, U, V, W, H, off, 20, 9, disparity=2.5),
+                          oracle.render(dec, U, V, W, H, on, 20, 9, disparity=2.5))
     views = synth.novel_views(6, U, V, seed=4, pan=2.0)
     a = oracle.render(dec, U, V, W, H, views, 20, 9)
     b = oracle.render(dec, U, V, W, H, views, 20, 9, disparity=1e-30)   # the general path, vanishing shift
