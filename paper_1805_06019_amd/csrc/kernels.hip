@@ -776,8 +776,16 @@ __device__ __forceinline__ uint32_t rgb_pack(int32_t yv, int32_t co, int32_t cg)
 // footprint and one set of fractions.
 template <bool FOCAL>
 __device__ __forceinline__ float focal_shift(float d, float x, int n, int i) {
+#pragma clang fp contract(off)
   if constexpr (!FOCAL) return 0.0f;
   return d * ((float)i - fminf(fmaxf(x, 0.0f), (float)(n - 1)));
+}
+
+// Source-image position of output pixel X: each operation rounded on its
+// own (no fused multiply-add), so every renderer samples the same positions.
+__device__ __forceinline__ float src_pos(float s, int X, float scale) {
+#pragma clang fp contract(off)
+  return s + ((float)X + 0.5f) * scale - 0.5f;
 }
 
 // quadrilinear interpolation of the 16 RGB taps P[view][tap] (taps 00, 01,
@@ -829,10 +837,10 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const lfc_view 
   for (int k = 0; k < 4; k++) {
     shx[k] = focal_shift<FOCAL>(a.disp, vw.u, a.U, (k & 1) ? iu1 : iu0);
     shy[k] = focal_shift<FOCAL>(a.disp, vw.v, a.V, (k & 2) ? jv1 : jv0);
-    const float sa = fminf(fmaxf(vw.s + ((float)tx0 + 0.5f) * sxs - 0.5f + shx[k], 0.0f), (float)(a.W - 1));
-    const float sb = fminf(fmaxf(vw.s + ((float)tx1 + 0.5f) * sxs - 0.5f + shx[k], 0.0f), (float)(a.W - 1));
-    const float ta = fminf(fmaxf(vw.t + ((float)ty0 + 0.5f) * tys - 0.5f + shy[k], 0.0f), (float)(a.H - 1));
-    const float tb = fminf(fmaxf(vw.t + ((float)ty1 + 0.5f) * tys - 0.5f + shy[k], 0.0f), (float)(a.H - 1));
+    const float sa = fminf(fmaxf(src_pos(vw.s, tx0, sxs) + shx[k], 0.0f), (float)(a.W - 1));
+    const float sb = fminf(fmaxf(src_pos(vw.s, tx1, sxs) + shx[k], 0.0f), (float)(a.W - 1));
+    const float ta = fminf(fmaxf(src_pos(vw.t, ty0, tys) + shy[k], 0.0f), (float)(a.H - 1));
+    const float tb = fminf(fmaxf(src_pos(vw.t, ty1, tys) + shy[k], 0.0f), (float)(a.H - 1));
     const int xlo = max((int)floorf(sa) - 1, 0), xhi = min((int)floorf(sb) + 2, a.W - 1);
     const int ylo = max((int)floorf(ta) - 1, 0), yhi = min((int)floorf(tb) + 2, a.H - 1);
     fbx0[k] = xlo / B;
@@ -916,7 +924,7 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const lfc_view 
   for (int p = tid; p < a.TX * a.TY; p += kThreads) {
     const int X = tx0 + p % a.TX, Yp = ty0 + p / a.TX;
     if (X >= a.wo || Yp >= a.ho) continue;
-    const float sx = vw.s + ((float)X + 0.5f) * sxs - 0.5f, ty = vw.t + ((float)Yp + 0.5f) * tys - 0.5f;
+    const float sx = src_pos(vw.s, X, sxs), ty = src_pos(vw.t, Yp, tys);
     uint32_t P[4][4];
     float fs[4], ft[4];
 #pragma unroll
@@ -961,7 +969,7 @@ __global__ __launch_bounds__(kThreads) void k_interp(InterpArgs a) {
   cell(vw.u, a.U, iu0, iu1, fu);
   cell(vw.v, a.V, jv0, jv1, fv);
   const float sxs = (float)a.W / (float)a.wo, tys = (float)a.H / (float)a.ho;
-  const float sx = vw.s + ((float)X + 0.5f) * sxs - 0.5f, ty = vw.t + ((float)Yp + 0.5f) * tys - 0.5f;
+  const float sx = src_pos(vw.s, X, sxs), ty = src_pos(vw.t, Yp, tys);
   const int vis[4] = {jv0 * a.U + iu0, jv0 * a.U + iu1, jv1 * a.U + iu0, jv1 * a.U + iu1};
   const size_t cplane = (size_t)a.hp * a.wp;
   uint32_t P[4][4];

@@ -177,3 +177,23 @@ def test_refocus_on_a_plane_is_sharp_on_the_gpu(gpu):
     with pytest.raises(lfc.LFCError):
         lfc.lfc_render_views(lf, views, W, H, disparity=float("nan"))
     lf.close()
+
+
+def test_refocused_64_view_batch_on_lenslet40(gpu):
+    # the full-size batch (64 novel 512x512 views of the 9x9 lenslet-like field),
+    # refocused, in the launch shape the automatic choice takes (decode then
+    # interpolate) and in tiles (the same bytes: both compute each sample
+    # position with the same roundings); the oracle renders 4 of the views
+    say("refocused batch lenslet40")
+    w, enc = _workload_enc("lenslet40")
+    s = w.spec
+    lf = lfc.lfc_open(enc.stream)
+    views = synth.novel_views(64, s.grid_u, s.grid_v, seed=303)
+    tv = torch.from_numpy(views).cuda()
+    auto = lfc.lfc_render_views(lf, tv, 512, 512, disparity=0.8)
+    tiles = lfc.lfc_render_views(lf, tv, 512, 512, cfg=(lfc.RENDER_TILES, 0, 0, 0.8))
+    assert torch.equal(auto, tiles)
+    pick = [0, 17, 40, 63]
+    ref = oracle.render(enc.r0, s.grid_u, s.grid_v, s.width, s.height, views[pick], 512, 512, disparity=0.8)
+    assert max_abs(auto[pick].cpu().numpy(), ref) <= TOL
+    lf.close()
