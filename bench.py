@@ -40,16 +40,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic():
+def measured_traffic(tile_blocks: int):
     """HBM bytes per launch from the committed rocprofv3 counter runs, if they
-    were taken on the current kernel source; else None."""
+    were taken on the current kernel source at this decode tile capacity;
+    else None."""
     from paper_1805_06019_amd.prof_summary import kernel_source_hash
     path = os.path.join(ROOT, "profiles", "traffic_decode_lf_full40.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("kernel_source_hash") != kernel_source_hash():
+    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("tile_blocks") != tile_blocks:
         return None
     return rec.get("bytes_per_launch")
 
@@ -173,6 +174,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--tile-blocks", type=int, default=0,
+                    help="decode tile capacity to use instead of measuring the choice (profiling runs "
+                         "take the value a default run chose, so that every traced launch is the timed kernel)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -198,11 +202,19 @@ def main():
     t0 = time.time()
     stream40, st40 = lfc.lfc_encode_ex(rgb, w40.params())
     log(f"encoded full40 in {time.time() - t0:.1f}s: {len(stream40) / 1e6:.1f} MB, {st40['psnr']:.3f} dB")
+    if args.tile_blocks:
+        os.environ["LFC_TILE_BLOCKS"] = str(args.tile_blocks)
     lf = lfc.lfc_open(stream40)
     info = lf.info
     nv, hp, wp, nb = 289, info.padded_height, info.padded_width, info.n_blocks
     samples = nv * 3 * hp * wp
     out = torch.empty((nv, 3, hp, wp), dtype=torch.int16, device="cuda")
+    # setup (untimed): the library's measured choice of the decode tile capacity
+    if args.tile_blocks:
+        tile_blocks, tile_tried = args.tile_blocks, []
+    else:
+        tile_blocks, tile_tried = lfc.lfc_tune_decode(lf, reps=5, out=out)
+    log(f"decode tuning: {tile_tried} -> {tile_blocks}")
 
     def step():
         lfc.lfc_decode_blocks(lf, None, lfc.LAYOUT_IMAGES, out=out)
@@ -240,7 +252,7 @@ def main():
                  + 4 * nv * 4)                     # leaf schedule
     achieved = alg_bytes / (per_launch.mean() * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(),
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(tile_blocks),
                     kernel="k_decode_lf<4>", algorithmic_bytes_per_launch=alg_bytes,
                     launch_ms_mean=round(float(per_launch.mean()), 5),
                     launch_ms_p50=round(float(np.median(per_launch)), 5))
@@ -322,10 +334,11 @@ def main():
         stream50, st50 = lfc.lfc_encode_ex(rgb, w50.params())
         lf50 = lfc.lfc_open(stream50)
         out50 = torch.empty_like(out)
+        tile50, _ = lfc.lfc_tune_decode(lf50, reps=5, out=out50)
         d50 = time_launches(lambda: lfc.lfc_decode_blocks(lf50, None, lfc.LAYOUT_IMAGES, out=out50), 20, torch)
         del out50
         extra["full50"] = dict(psnr_db=round(st50["psnr"], 3), bpp=round(8 * len(stream50) / (nv * 512 * 512), 4),
-                               ms_per_decode=round(float(d50.mean()), 4),
+                               ms_per_decode=round(float(d50.mean()), 4), tile_blocks=tile50,
                                gsamples_per_s=round(samples / (d50.mean() * 1e-3) / 1e9, 1))
         lf50.close()
         # lenslet-like 9x9 x 625x434, 64 views per launch
@@ -402,7 +415,8 @@ def main():
                              "(17->9->3), 4x4 blocks, q=2, T_blk=67",
                     psnr_db=round(st40["psnr"], 3), bpp=round(8 * len(stream40) / (nv * 512 * 512), 4),
                     samples_per_step=samples, stream_bytes=len(stream40),
-                    present_blocks=int(st40["present_blocks"])),
+                    present_blocks=int(st40["present_blocks"]), tile_blocks=tile_blocks,
+                    tile_tuning={str(c): round(ms, 4) for c, ms in tile_tried}),
         roofline=roofline, cpu_baseline=cpu, device=dict(name=dev_props.name, cus=dev_props.multi_processor_count,
                                                         gcn_arch=getattr(dev_props, "gcnArchName", ""),
                                                         lds_per_block=getattr(dev_props, "shared_memory_per_block", None),

@@ -312,6 +312,30 @@ lfc_status lfc_decode_blocks(const lfc_lf *lf, const int32_t *d_req, int64_t n, 
                              int16_t *d_out, hipStream_t s);
 
 /*
+ * Measured tuning of the whole-field decode (LFC_LAYOUT_IMAGES): the
+ * kernel decodes each strip's residual blocks in chunks that fit a tile of
+ * stored blocks in LDS; a larger tile means fewer chunks but less LDS for
+ * staging the strip.  This call times the decode (one warm-up, then `reps`
+ * launches, events on stream s, output to d_out: int16, as the images
+ * layout) with the handle's current tile capacity and with 3/4, 5/4, 6/4
+ * and 7/4 of the default (those that fit), rebuilding the strip tables for
+ * each, and keeps the fastest in the handle; res reports what was tried.
+ * Blocks until done.  The handle must not be in use by another call
+ * meanwhile.  Decoded samples do not depend on the choice.
+ * Errors: LFC_E_INVALID (null pointer, reps outside 1..1000, handle of
+ * another device), LFC_E_NOMEM, LFC_E_HIP; on error the handle keeps the
+ * tables it had.
+ */
+#define LFC_TUNE_DECODE_MAX 8
+typedef struct {
+  int32_t n_tried;
+  int32_t best;                              /* index of the capacity kept */
+  int32_t tile_blocks[LFC_TUNE_DECODE_MAX];  /* stored blocks per tile */
+  float ms[LFC_TUNE_DECODE_MAX];             /* mean ms per decode */
+} lfc_decode_tuning;
+lfc_status lfc_tune_decode(lfc_lf *lf, int16_t *d_out, int32_t reps, lfc_decode_tuning *res, hipStream_t s);
+
+/*
  * Progressive decompression (Sec. 3.6): the tree traversal of
  * DecompressLFIBlock (Alg. 2) stopped at tree level `level`, which yields the
  * filtered key-view value of the view's ancestor on that level: for each

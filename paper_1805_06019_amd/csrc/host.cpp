@@ -361,6 +361,43 @@ static void build_schedule(const Geometry &g, const std::vector<uint32_t> &off, 
   for (int st = 0; st < nstrip; st++) std::copy(per[(size_t)st].begin(), per[(size_t)st].end(), sched.begin() + strip_off[(size_t)st]);
 }
 
+// Everything the whole-field kernel needs per strip for one tile capacity:
+// the decode schedule, the order in which workgroups take the strips
+// (costliest first, staged words as the cost, so that short strips fill the
+// tail of the launch), and per strip the LDS words of groups + schedule and
+// of the schedule alone.
+struct StripTables {
+  std::vector<uint32_t> sched, strip_off, order, need;
+  uint32_t max_words = 0;
+};
+
+static void make_strip_tables(const Geometry &g, const std::vector<uint32_t> &off, const std::vector<uint32_t> &srv,
+                              const std::vector<uint32_t> &dbase, const std::vector<uint32_t> &poff,
+                              const std::vector<int32_t> &batch, int cap, StripTables &t) {
+  build_schedule(g, off, srv, dbase, poff, batch, t.sched, t.strip_off, cap);
+  const int nblk = 64 / g.B, nsx = (g.nbx + nblk - 1) / nblk;
+  const size_t nst = t.strip_off.size() - 1;
+  std::vector<uint64_t> cost(nst);
+  t.need.assign(2 * nst, 0);
+  t.max_words = 0;
+  for (size_t st = 0; st < nst; st++) {
+    const int sx = (int)(st % nsx), by = (int)((st / nsx) % g.nby), c = (int)(st / ((size_t)nsx * g.nby));
+    const uint64_t sw = t.strip_off[st + 1] - t.strip_off[st];
+    uint64_t w = sw;
+    for (int bx = sx * nblk; bx < std::min(sx * nblk + nblk, g.nbx); bx++) {
+      const size_t gi = 3 * ((size_t)by * g.nbx + bx) + c;
+      w += off[gi + 1] - off[gi];
+    }
+    cost[st] = w;
+    t.need[2 * st] = (uint32_t)std::min<uint64_t>(w, 1u << 30);
+    t.need[2 * st + 1] = (uint32_t)sw;
+    t.max_words = std::max(t.max_words, t.need[2 * st]);
+  }
+  t.order.resize(nst);
+  for (size_t i = 0; i < nst; i++) t.order[i] = (uint32_t)i;
+  std::stable_sort(t.order.begin(), t.order.end(), [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
+}
+
 // ---------------------------------------------------------------------------
 // encoder
 // ---------------------------------------------------------------------------
@@ -1227,34 +1264,18 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
     size_t at;
   };
   static const uint32_t zeros[64] = {0};
-  std::vector<uint32_t> sched, strip_off;
-  // tile capacity (LFC_TILE_BLOCKS overrides it for tuning): at least one run
-  // of kBatch leaves with four ancestors, 8 nodes of 64/B blocks
+  // tile capacity (LFC_TILE_BLOCKS overrides it for tuning; lfc_tune_decode
+  // measures the choice): at least one run of kBatch leaves with four
+  // ancestors, 8 nodes of 64/B blocks
   int tile_cap = tile_blocks(ps.g.B);
   if (const char *e = getenv("LFC_TILE_BLOCKS")) tile_cap = std::min(2048, std::max(512 / ps.g.B, atoi(e) / 8 * 8));
+  StripTables stt;
   try {
-    build_schedule(ps.g, ps.off, ps.srv, ps.dbase, ps.poff, tt.batch, sched, strip_off, tile_cap);
+    make_strip_tables(ps.g, ps.off, ps.srv, ps.dbase, ps.poff, tt.batch, tile_cap, stt);
   } catch (const std::bad_alloc &) {
     return fail(LFC_E_NOMEM, "lfc_open: out of host memory");
   }
-  // the whole-field kernel takes strips costliest first (staged words as the
-  // cost), so that short strips fill the tail of the launch
-  std::vector<uint32_t> order(strip_off.size() - 1);
-  for (size_t i = 0; i < order.size(); i++) order[i] = (uint32_t)i;
-  {
-    const int nblk = 64 / ps.g.B, nsx = (ps.g.nbx + nblk - 1) / nblk;
-    std::vector<uint64_t> cost(order.size());
-    for (size_t st = 0; st < order.size(); st++) {
-      const int sx = (int)(st % nsx), by = (int)((st / nsx) % ps.g.nby), c = (int)(st / ((size_t)nsx * ps.g.nby));
-      uint64_t w = strip_off[st + 1] - strip_off[st];
-      for (int bx = sx * nblk; bx < std::min(sx * nblk + nblk, ps.g.nbx); bx++) {
-        const size_t gi = 3 * ((size_t)by * ps.g.nbx + bx) + c;
-        w += ps.off[gi + 1] - ps.off[gi];
-      }
-      cost[st] = w;
-    }
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
-  }
+  const std::vector<uint32_t> &sched = stt.sched, &strip_off = stt.strip_off, &order = stt.order;
   Part parts[13] = {
       {ps.rkv, ps.rkv_bytes, 0},
       {ps.off.data(), ps.off.size() * 4, 0},
@@ -1324,20 +1345,8 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
   lf->d_err = reinterpret_cast<int32_t *>(d + parts[8].at);
   // LDS staging of the whole-field kernel is sized by the largest strip:
   // group words plus the strip's decode schedule
-  const int nblk = 64 / g.B, nsx = (g.nbx + nblk - 1) / nblk;
-  for (int c = 0; c < 3; c++)
-    for (int by = 0; by < g.nby; by++)
-      for (int sx = 0; sx < nsx; sx++) {
-        const size_t st = ((size_t)c * g.nby + by) * nsx + sx;
-        uint64_t words = strip_off[st + 1] - strip_off[st];
-        for (int bx = sx * nblk; bx < std::min(sx * nblk + nblk, g.nbx); bx++) {
-          const int gi = 3 * (by * g.nbx + bx) + c;
-          words += ps.off[gi + 1] - ps.off[gi];
-        }
-        lf->max_strip_words = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(lf->max_strip_words, words), 1u << 30);
-        lf->strip_need.push_back((uint32_t)std::min<uint64_t>(words, 1u << 30));
-        lf->strip_need.push_back(strip_off[st + 1] - strip_off[st]);
-      }
+  lf->max_strip_words = stt.max_words;
+  lf->strip_need = std::move(stt.need);
   *out = lf;
   return LFC_OK;
 }
@@ -1380,8 +1389,161 @@ extern "C" lfc_status lfc_check(const lfc_lf *lf, hipStream_t s) {
   return LFC_OK;
 }
 
+// Measured choice of the whole-field kernel's tile capacity: the strip
+// tables are rebuilt on the host for each candidate (the directory and run
+// table come back from the device) and the decode is timed with each.
+extern "C" lfc_status lfc_tune_decode(lfc_lf *lf, int16_t *d_out, int32_t reps, lfc_decode_tuning *res,
+                                      hipStream_t s) {
+  if (!lf || !d_out || !res) return fail(LFC_E_INVALID, "lfc_tune_decode: null argument");
+  if (reps < 1 || reps > 1000) return fail(LFC_E_INVALID, "lfc_tune_decode: reps must be 1..1000");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != lf->device)
+    return fail(LFC_E_INVALID, "lfc_tune_decode: the light field was opened on another device");
+  std::memset(res, 0, sizeof *res);
+  const Geometry &g = lf->geo;
+  const int nv = g.nv();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(LFC_E_HIP, "lfc_tune_decode: events");
+  }
+  // time the current tables
+  auto timed = [&](float *ms) -> lfc_status {
+    lfc_status st = lfc_decode_blocks(lf, nullptr, nv, LFC_LAYOUT_IMAGES, d_out, s);
+    if (st != LFC_OK) return st;
+    if (hipEventRecord(e0, s) != hipSuccess) return fail(LFC_E_HIP, "lfc_tune_decode: event record");
+    for (int r = 0; r < reps && st == LFC_OK; r++) st = lfc_decode_blocks(lf, nullptr, nv, LFC_LAYOUT_IMAGES, d_out, s);
+    if (st != LFC_OK) return st;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+      return fail(LFC_E_HIP, "lfc_tune_decode: timing");
+    *ms /= (float)reps;
+    return LFC_OK;
+  };
+  struct Saved {
+    int cap;
+    const uint32_t *sched, *strip_off, *order;
+    std::vector<uint32_t> need;
+    uint32_t max_words;
+    void *own;
+  };
+  auto save = [&]() {
+    return Saved{lf->tile_cap, lf->d_sched, lf->d_strip_off, lf->d_order, lf->strip_need, lf->max_strip_words,
+                 lf->d_sched_own};
+  };
+  auto restore = [&](const Saved &v) {
+    lf->tile_cap = v.cap;
+    lf->d_sched = v.sched;
+    lf->d_strip_off = v.strip_off;
+    lf->d_order = v.order;
+    lf->strip_need = v.need;
+    lf->max_strip_words = v.max_words;
+    lf->d_sched_own = v.own;
+  };
+  std::vector<Saved> cands;
+  lfc_status st = LFC_OK;
+  float ms = 0.0f;
+  cands.push_back(save());
+  st = timed(&ms);
+  if (st == LFC_OK) {
+    res->tile_blocks[0] = lf->tile_cap;
+    res->ms[0] = ms;
+    res->n_tried = 1;
+  }
+  try {
+    // host copies of what the strip tables are built from
+    std::vector<uint32_t> off, srv, dbase, poff;
+    std::vector<int32_t> batch((size_t)lf->n_batch * kBatchWords);
+    off.resize((size_t)g.ng + 1);
+    if (st == LFC_OK && hipMemcpy(off.data(), lf->d_off, 4 * off.size(), hipMemcpyDeviceToHost) != hipSuccess)
+      st = fail(LFC_E_HIP, "lfc_tune_decode: copy of the offsets");
+    if (st == LFC_OK) {
+      srv.resize((size_t)off[g.ng] + 2);
+      dbase.resize((size_t)g.ng * g.nbw);
+      poff.resize(std::max<uint64_t>(lf->present, 1));
+      if (hipMemcpy(srv.data(), lf->d_srv, 4 * srv.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(dbase.data(), lf->d_dbase, 4 * dbase.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(poff.data(), lf->d_poff, 4 * poff.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+          (!batch.empty() &&
+           hipMemcpy(batch.data(), lf->d_batch, 4 * batch.size(), hipMemcpyDeviceToHost) != hipSuccess))
+        st = fail(LFC_E_HIP, "lfc_tune_decode: copy of the directory");
+    }
+    const int c0 = tile_blocks(g.B);
+    const int fr[4] = {3, 5, 6, 7};   // quarters of the default capacity besides 4/4
+    for (int fi = 0; fi < 4 && st == LFC_OK && res->n_tried < LFC_TUNE_DECODE_MAX; fi++) {
+      const int cap = std::min(2048, std::max(512 / g.B, c0 * fr[fi] / 4 / 8 * 8));
+      bool seen = false;
+      for (const Saved &v : cands) seen |= v.cap == cap;
+      if (seen || g.L < 2) continue;
+      StripTables t;
+      make_strip_tables(g, off, srv, dbase, poff, batch, cap, t);
+      const size_t a0 = 0, a1 = align256(4 * t.sched.size()), a2 = a1 + align256(4 * t.strip_off.size());
+      const size_t total = a2 + align256(4 * t.order.size());
+      void *buf = nullptr;
+      if (hipMalloc(&buf, total) != hipSuccess) {
+        (void)hipGetLastError();
+        break;   // no room for another table set: keep what was measured
+      }
+      char *d = static_cast<char *>(buf);
+      if (hipMemcpy(d + a0, t.sched.data(), 4 * t.sched.size(), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(d + a1, t.strip_off.data(), 4 * t.strip_off.size(), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(d + a2, t.order.data(), 4 * t.order.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(buf);
+        st = fail(LFC_E_HIP, "lfc_tune_decode: copy of the strip tables");
+        break;
+      }
+      lf->tile_cap = cap;
+      lf->d_sched = reinterpret_cast<const uint32_t *>(d + a0);
+      lf->d_strip_off = reinterpret_cast<const uint32_t *>(d + a1);
+      lf->d_order = reinterpret_cast<const uint32_t *>(d + a2);
+      lf->strip_need = std::move(t.need);
+      lf->max_strip_words = t.max_words;
+      lf->d_sched_own = buf;
+      cands.push_back(save());
+      lfc_status ts = timed(&ms);
+      if (ts == LFC_E_UNSUPPORTED) {   // the tile does not fit the LDS: not a candidate
+        (void)hipGetLastError();
+        (void)hipFree(buf);
+        cands.pop_back();
+        restore(cands[0]);
+        continue;
+      }
+      if (ts != LFC_OK) {
+        st = ts;
+        break;
+      }
+      const int k = res->n_tried++;
+      res->tile_blocks[k] = cap;
+      res->ms[k] = ms;
+    }
+  } catch (const std::bad_alloc &) {
+    st = fail(LFC_E_NOMEM, "lfc_tune_decode: out of host memory");
+  }
+  (void)hipStreamSynchronize(s);
+  if (st != LFC_OK) {
+    // back to the tables the handle had; free every set built here
+    for (size_t k = 1; k < cands.size(); k++)
+      if (cands[k].own) (void)hipFree(cands[k].own);
+    restore(cands[0]);
+  } else {
+    // keep the fastest; free the others (and an earlier tuning's tables if replaced)
+    int best = 0;
+    for (int k = 1; k < res->n_tried; k++)
+      if (res->ms[k] < res->ms[best]) best = k;
+    res->best = best;
+    for (size_t k = 1; k < cands.size(); k++)
+      if ((int)k != best && cands[k].own) (void)hipFree(cands[k].own);
+    if (best != 0 && cands[0].own) (void)hipFree(cands[0].own);
+    restore(cands[(size_t)best]);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
 extern "C" lfc_status lfc_close(lfc_lf *lf) {
   if (!lf) return LFC_OK;
+  if (lf->d_sched_own) (void)hipFree(lf->d_sched_own);
   hipError_t he = hipFree(lf->d_base);
   delete lf;
   if (he != hipSuccess) return fail(LFC_E_HIP, std::string("lfc_close: ") + hipGetErrorString(he));

@@ -85,6 +85,7 @@ struct lfc_lf {
   const uint32_t *d_order = nullptr;     // [n_strips] strips in the order the whole-field kernel takes them
   int32_t *d_err = nullptr;          // device error flag
   int tile_cap = 0;                  // blocks of the whole-field kernel's compact residual tile
+  void *d_sched_own = nullptr;       // strip tables chosen by lfc_tune_decode (else inside d_base)
   uint32_t max_strip_words = 0;      // largest group words + decode schedule of a strip of 64/B blocks of
                                      // one channel
   std::vector<uint32_t> strip_need;  // per strip: group words + schedule words, schedule words

@@ -94,6 +94,10 @@ class c_render_tuning(C.Structure):
 RENDER_AUTO, RENDER_TILES, RENDER_DECODED = 0, 1, 2
 
 
+class c_decode_tuning(C.Structure):
+    _fields_ = [("n_tried", C.c_int32), ("best", C.c_int32), ("tile_blocks", C.c_int32 * 8), ("ms", C.c_float * 8)]
+
+
 class c_server_config(C.Structure):
     _fields_ = [("max_batch", C.c_int32), ("streams", C.c_int32), ("out_pool_bytes", C.c_int64)]
 
@@ -158,6 +162,7 @@ def load() -> C.CDLL:
         L.lfc_stage_needs.argtypes = [vp, vp, i64]
         L.lfc_stage_needs.restype = i64
         L.lfc_render_views.argtypes = [vp, vp, i32, i32, i32, vp, vp]
+        L.lfc_tune_decode.argtypes = [vp, vp, i32, C.POINTER(c_decode_tuning), vp]
         L.lfc_control_rows.argtypes = [C.POINTER(c_params)]
         L.lfc_control_rows.restype = i64
         L.lfc_encode_ctl.argtypes = [vp, C.POINTER(c_params), C.POINTER(c_control), C.POINTER(vp), C.POINTER(sz),
@@ -191,7 +196,7 @@ def load() -> C.CDLL:
         L.lfc_server_get_stats.argtypes = [vp, C.POINTER(c_server_stats)]
         L.lfc_server_destroy.argtypes = [vp]
         for f in ("lfc_encode", "lfc_encode_ex", "lfc_validate", "lfc_open", "lfc_info", "lfc_decode_blocks",
-                  "lfc_render_views", "lfc_render_views_ex", "lfc_encode_ctl", "lfc_mlp_infer", "lfc_mlp_grad",
+                  "lfc_render_views", "lfc_render_views_ex", "lfc_encode_ctl", "lfc_tune_decode", "lfc_mlp_infer", "lfc_mlp_grad",
                   "lfc_mlp_adam", "lfc_render_tune", "lfc_render_plan_create",
                   "lfc_render_plan_launch", "lfc_render_plan_info", "lfc_check", "lfc_close", "lfc_decode_progressive", "lfc_batch_create",
                   "lfc_batch_decode", "lfc_batch_check", "lfc_batch_render",
@@ -411,6 +416,20 @@ def lfc_decode_blocks(lf: LightField, req=None, layout: int = LAYOUT_BLOCKS, out
     _check(load().lfc_decode_blocks(lf.handle, req.data_ptr() if req is not None else None, n, layout,
                                     out.data_ptr(), _stream_ptr(cuda_stream)))
     return out
+
+
+def lfc_tune_decode(lf: LightField, reps: int = 5, out=None, cuda_stream=None):
+    """Times the whole-field decode at several tile capacities and keeps the
+    fastest in the handle; returns (kept capacity, [(capacity, ms)])."""
+    import torch
+    i = lf.info
+    nv = i.params.grid_u * i.params.grid_v
+    if out is None:
+        out = torch.empty((nv, 3, i.padded_height, i.padded_width), dtype=torch.int16, device="cuda")
+    res = c_decode_tuning()
+    _check(load().lfc_tune_decode(lf.handle, out.data_ptr(), reps, C.byref(res), _stream_ptr(cuda_stream)))
+    tried = [(int(res.tile_blocks[k]), float(res.ms[k])) for k in range(res.n_tried)]
+    return tried[res.best][0], tried
 
 
 def lfc_stage_needs(lf: LightField) -> np.ndarray:

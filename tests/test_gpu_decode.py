@@ -243,3 +243,38 @@ def test_progressive_decode_full_size_and_errors(gpu, full40):
     assert lib.lfc_decode_progressive(lf.handle, dreq.data_ptr(), 4, -1, out.data_ptr(), s) == -1
     assert lib.lfc_decode_progressive(lf.handle, dreq.data_ptr(), 0, 2, out.data_ptr(), s) == 0
     lfc.lfc_check(lf)
+
+
+@pytest.mark.parametrize("case", [GEOMS[0], GEOMS[3], GEOMS[5], GEOMS[6], GEOMS[7], GEOMS[1]],
+                         ids=["8x8-B4", "17x17-L3", "B8", "B2", "L4", "L1"])
+def test_decode_tuner_keeps_the_output(gpu, case):
+    # every tile capacity decodes the same samples; the tuner keeps one of
+    # those it timed, and a second tuning replaces the first one's tables
+    U, V, W, H, kw = case
+    say("tune decode", case)
+    rgb = make_lf(U, V, W, H, seed=U * 13 + W)
+    enc = oracle_encode(rgb, **kw)
+    lf = gpu_open(enc.stream)
+    n_strips = lfc.lfc_stage_needs(lf).shape[0]
+    for _ in range(2):
+        best, tried = lfc.lfc_tune_decode(lf, reps=2)
+        say("tried", tried, "kept", best)
+        assert best in [c for c, _ in tried] and all(ms > 0 for _, ms in tried)
+        if kw["levels"] >= 2:
+            assert len(tried) >= 2
+        assert lfc.lfc_stage_needs(lf).shape[0] == n_strips
+        got = lfc.lfc_decode_blocks(lf, None, lfc.LAYOUT_IMAGES).cpu().numpy()
+        assert np.array_equal(got, enc.r0)
+    lfc.lfc_check(lf)
+    lf.close()
+
+
+def test_decode_tuner_on_full40(gpu, full40):
+    w, rgb, enc = full40
+    say("full40: tuning the whole-field decode")
+    lf = gpu_open(enc.stream)
+    best, tried = lfc.lfc_tune_decode(lf, reps=3)
+    say("tried", tried, "kept", best)
+    got = lfc.lfc_decode_blocks(lf, None, lfc.LAYOUT_IMAGES).cpu().numpy()
+    assert np.array_equal(got, enc.r0)
+    lf.close()

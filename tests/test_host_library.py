@@ -246,3 +246,9 @@ def test_render_plan_and_tune_argument_errors_on_host():
     assert lib.lfc_render_tune(None, None, 1, 8, 8, None, 5, C.byref(res), None) == -1
     assert lib.lfc_render_tune(None, None, 1, 8, 8, None, 5, None, None) == -1
     assert lib.lfc_render_views_ex(None, None, 0, 1, 1, None, None, None) == -1
+
+
+def test_decode_tuner_argument_errors_on_host():
+    lib = lfc.load()
+    res = lfc.c_decode_tuning()
+    assert lib.lfc_tune_decode(None, None, 5, C.byref(res), None) == -1
