@@ -45,7 +45,7 @@ def measured_traffic(tile_blocks: int):
     were taken on the current kernel source at this decode tile capacity;
     else None."""
     from paper_1805_06019_amd.prof_summary import kernel_source_hash
-    path = os.path.join(ROOT, "profiles", "traffic_decode_lf_full40.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_decode_lf_full40_t{tile_blocks}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
