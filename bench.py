@@ -205,7 +205,8 @@ def main():
     if args.tile_blocks:
         os.environ["LFC_TILE_BLOCKS"] = str(args.tile_blocks)
     lf = lfc.lfc_open(stream40)
-    os.environ.pop("LFC_TILE_BLOCKS", None)   # only this light field
+    if args.tile_blocks:
+        os.environ.pop("LFC_TILE_BLOCKS", None)   # only this light field
     info = lf.info
     nv, hp, wp, nb = 289, info.padded_height, info.padded_width, info.n_blocks
     samples = nv * 3 * hp * wp
