@@ -1,7 +1,9 @@
 // Host side of liblfc.so: parameters and geometry, the encoder (CompressLFI,
-// Alg. 1), the stream validator, and decoder initialisation (Alg. 2
-// "Initialization"), which also builds the block directory used for random
-// access.  See include/lfc.h for the contract of every exported call.
+// Alg. 1) with its per-block control modes, the stream validator, decoder
+// initialisation (Alg. 2 "Initialization"), which also builds the block
+// directory used for random access and the whole-field kernel's strip
+// tables, and the measured tuning of those tables.  See include/lfc.h for
+// the contract of every exported call.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

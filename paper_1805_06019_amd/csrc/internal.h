@@ -1,5 +1,5 @@
-// Internal declarations shared by the host side (host.cpp) and the HIP
-// kernels (kernels.hip) of liblfc.so.
+// Internal declarations shared by the host side (host.cpp), the HIP kernels
+// (kernels.hip, mlp.hip) and the runtime (serve.cpp) of liblfc.so.
 #pragma once
 
 #include <cstddef>

@@ -1,5 +1,7 @@
-// HIP kernels for gfx950 (CDNA4, wave64) and the exported launch calls
-// lfc_decode_blocks and lfc_render_views.
+// HIP kernels for gfx950 (CDNA4, wave64) and the exported calls that launch
+// them: decoding (lfc_decode_blocks, lfc_decode_progressive), rendering
+// (lfc_render_views, lfc_render_views_ex, lfc_render_tune, the render
+// plans), and the launchers the batch context and server use.
 //
 // Decoding a block (Alg. 2, Sec. 3.5) is: read the top-level key-view block,
 // then for every level below, locate the node's residual block inside the
@@ -7,12 +9,14 @@
 // block offsets, Sec. 3.4), unpack its BISE values (Sec. 3.3), undo the
 // zigzag and the quantiser step, and add it.  All integer work; no MFMA.
 //
-// Work mapping: one lane owns one row of B samples of one block of one
-// channel, so a wave covers a 64-pixel-wide strip of B rows and its stores
-// are full 128-byte row segments.  Samples travel as packed int16 pairs:
-// the residual tail (zigzag undo, step 2^q, adding the parent) runs on both
-// halves of a register at once, and the sums wrap modulo 2^16 exactly as the
-// final int16 store of a 32-bit sum would.
+// Work mapping of the whole-field kernel: a workgroup owns a strip of 64/B
+// blocks of one block row and channel; one lane decodes a whole stored
+// residual block into LDS, then each lane gathers and stores 16 bytes of an
+// output row (key view + ancestors + leaf).  Random access and rendering
+// give one lane one row of B samples of a block.  Samples travel as packed
+// int16 pairs: the residual tail (zigzag undo, step 2^q, adding the parent)
+// runs on both halves of a register at once, and the sums wrap modulo 2^16
+// exactly as the final int16 store of a 32-bit sum would.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

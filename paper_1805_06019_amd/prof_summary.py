@@ -29,20 +29,28 @@ COPY_BYTES = 256 << 20
 DECODE_KERNEL = "k_decode_lf<4>"
 
 
+def _code_only(src: str) -> str:
+    """C++ source without comments and blank-line or indentation changes."""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(" ".join(line.split()) for line in src.splitlines() if line.strip())
+
+
 def kernel_source_hash() -> str:
-    """Hash of the source of the whole-field decode kernel: the device code
-    of kernels.hip up to the random-access section, its host launcher, and
-    internal.h (a change elsewhere, e.g. in the render kernels, keeps it)."""
+    """Hash of the code of the whole-field decode kernel, comments left out:
+    the device code of kernels.hip up to the random-access section, its host
+    launcher, and internal.h (a change elsewhere, e.g. in the render kernels,
+    or in a comment, keeps it)."""
     with open(os.path.join(HERE, "csrc", "kernels.hip")) as fh:
         src = fh.read()
     device = src[:src.index("// random access: one (view, block) at a time")]
     i = src.index("lfc_status decode_images(")
     launcher = src[i:src.index("\n}\n", i)]
     h = hashlib.sha256()
-    h.update(device.encode())
-    h.update(launcher.encode())
-    with open(os.path.join(HERE, "csrc", "internal.h"), "rb") as fh:
-        h.update(fh.read())
+    h.update(_code_only(device).encode())
+    h.update(_code_only(launcher).encode())
+    with open(os.path.join(HERE, "csrc", "internal.h")) as fh:
+        h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
