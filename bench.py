@@ -201,7 +201,8 @@ def main():
     log(f"generated {w40.spec} in {time.time() - t0:.1f}s")
     t0 = time.time()
     stream40, st40 = lfc.lfc_encode_ex(rgb, w40.params())
-    log(f"encoded full40 in {time.time() - t0:.1f}s: {len(stream40) / 1e6:.1f} MB, {st40['psnr']:.3f} dB")
+    host_encode_s = time.time() - t0
+    log(f"encoded full40 in {host_encode_s:.1f}s: {len(stream40) / 1e6:.1f} MB, {st40['psnr']:.3f} dB")
     if args.tile_blocks:
         os.environ["LFC_TILE_BLOCKS"] = str(args.tile_blocks)
     lf = lfc.lfc_open(stream40)
@@ -365,6 +366,16 @@ def main():
                                                   views_per_s=round(64 / (gl.mean() * 1e-3), 1))
         lfl.close()
         del imgl
+        # the encoder on the GPU (same stream as the host encoder's)
+        d_rgb = torch.from_numpy(rgb).cuda()
+        lfc.lfc_encode_gpu(d_rgb, w40.params(), want_stream=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gstream, _ = lfc.lfc_encode_gpu(d_rgb, w40.params())
+        gpu_encode_s = time.perf_counter() - t0
+        extra["encode_full40"] = dict(gpu_s=round(gpu_encode_s, 4), host_s=round(host_encode_s, 3),
+                                      host_threads=os.cpu_count(), same_stream=gstream == stream40)
+        del d_rgb, gstream
         # learned encoder control: the per-block network over every control
         # row of the 40 dB field (features from the search mode), and its
         # training step (batch gradient + Adam on 1024 rows)

@@ -252,6 +252,21 @@ lfc_status lfc_mlp_grad(const uint16_t *d_w, const float *d_x, const int8_t *d_c
 lfc_status lfc_mlp_adam(float *d_master, uint16_t *d_w, float *d_m, float *d_v, const float *d_grad, int32_t step,
                         float lr, float beta1, float beta2, float eps, hipStream_t s);
 
+/*
+ * lfc_encode_ex on the GPU (the global thresholds of the parameters):
+ * level 0, the key-view filters, the closed-loop residual levels and the
+ * packing of every group run as kernels on stream s; the host turns the
+ * group sizes into offsets and assembles the stream.  The stream and the
+ * statistics equal lfc_encode_ex's byte for byte.
+ *  d_rgb  device uint8 [grid_v][grid_u][height][width][3] (as lfc_encode).
+ * Blocks until done.  Device memory for the tree's levels and tables is
+ * allocated and freed by the call.
+ * Errors: as lfc_encode, plus LFC_E_INVALID (d_rgb not device memory of that
+ * size), LFC_E_NOMEM (device), LFC_E_HIP.
+ */
+lfc_status lfc_encode_gpu(const uint8_t *d_rgb, const lfc_params *p, void **stream_out, size_t *bytes_out,
+                          lfc_encode_stats *stats, hipStream_t s);
+
 /* Frees a buffer returned by lfc_encode.  NULL is ignored. */
 void lfc_free(void *ptr);
 

@@ -11,7 +11,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU ops
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["host.cpp", "kernels.hip", "serve.cpp", "mlp.hip"]
+SOURCES = ["host.cpp", "kernels.hip", "serve.cpp", "mlp.hip", "encode_gpu.hip"]
 
 
 def build(verbose: bool = False) -> str:

@@ -17,6 +17,7 @@
 #include <new>
 #include <thread>
 
+#include "encode.h"
 #include "internal.h"
 
 namespace lfc {
@@ -436,8 +437,8 @@ static uint64_t pack_block(uint32_t *w, uint64_t pos, const uint16_t *z, int S, 
   return pos;
 }
 
-static void put_header(uint8_t *h, const Geometry &g, const lfc_params &p, uint32_t mask,
-                       uint64_t rkv_off, uint64_t off_off, uint64_t srv_off) {
+void put_stream_header(uint8_t *h, const Geometry &g, const lfc_params &p, uint32_t mask, uint64_t rkv_off,
+                       uint64_t off_off, uint64_t srv_off) {
   std::memset(h, 0, kHeaderBytes);
   std::memcpy(h, "RLFC", 4);
   const uint16_t ver[2] = {1, (uint16_t)kHeaderBytes};
@@ -448,6 +449,25 @@ static void put_header(uint8_t *h, const Geometry &g, const lfc_params &p, uint3
   std::memcpy(h + 8, f, sizeof f);
   const uint64_t o[3] = {rkv_off, off_off, srv_off};
   std::memcpy(h + 104, o, sizeof o);
+}
+
+void encode_stats_from_sse(const std::vector<double> &se, int nv, int W, int H, lfc_encode_stats *stats) {
+  std::vector<double> ps(se.size());
+  for (size_t r = 0; r < se.size(); r++) {
+    const double mse = se[r] / ((double)W * H);
+    ps[r] = mse > 0 ? std::min(100.0, 10.0 * std::log10(255.0 * 255.0 / mse)) : 100.0;
+  }
+  double sy = 0, sco = 0, scg = 0, sall = 0;
+  for (int vi = 0; vi < nv; vi++) {
+    sy += ps[3 * vi];
+    sco += ps[3 * vi + 1];
+    scg += ps[3 * vi + 2];
+    sall += (6 * ps[3 * vi] + ps[3 * vi + 1] + ps[3 * vi + 2]) / 8;
+  }
+  stats->psnr = sall / nv;
+  stats->psnr_y = sy / nv;
+  stats->psnr_co = sco / nv;
+  stats->psnr_cg = scg / nv;
 }
 
 // Per-block encoder control (learned encoder control; the paper applies one
@@ -861,7 +881,7 @@ static lfc_status encode_impl(const uint8_t *rgb, const lfc_params &p, std::vect
   if (stats) {
     // eq. 5 per view and channel on the unpadded area, eq. 4, mean over views
     const std::vector<int16_t> &r0 = L > 1 ? rec[0] : lvl[0];
-    std::vector<double> ps((size_t)nv * 3);
+    std::vector<double> sse((size_t)nv * 3);
     parallel_for(nv * 3, 1, [&](int64_t a, int64_t e) {
       for (int64_t r = a; r < e; r++) {
         const size_t o = (size_t)r * plane;
@@ -871,21 +891,10 @@ static lfc_status encode_impl(const uint8_t *rgb, const lfc_params &p, std::vect
             const double d = (double)r0[o + (size_t)y * g.wp + x] - (double)lvl[0][o + (size_t)y * g.wp + x];
             se += d * d;
           }
-        const double mse = se / ((double)g.W * g.H);
-        ps[r] = mse > 0 ? std::min(100.0, 10.0 * std::log10(255.0 * 255.0 / mse)) : 100.0;
+        sse[r] = se;
       }
     });
-    double sy = 0, sco = 0, scg = 0, sall = 0;
-    for (int vi = 0; vi < nv; vi++) {
-      sy += ps[3 * vi];
-      sco += ps[3 * vi + 1];
-      scg += ps[3 * vi + 2];
-      sall += (6 * ps[3 * vi] + ps[3 * vi + 1] + ps[3 * vi + 2]) / 8;
-    }
-    stats->psnr = sall / nv;
-    stats->psnr_y = sy / nv;
-    stats->psnr_co = sco / nv;
-    stats->psnr_cg = scg / nv;
+    encode_stats_from_sse(sse, nv, g.W, g.H, stats);
     std::fill(stats->code_hist, stats->code_hist + kNumCodes, 0);
     stats->present_blocks = 0;
     for (size_t i = 0; i < nsg; i++)
@@ -933,7 +942,7 @@ static lfc_status encode_impl(const uint8_t *rgb, const lfc_params &p, std::vect
   } catch (const std::bad_alloc &) {
     return fail(LFC_E_NOMEM, "lfc_encode: out of host memory");
   }
-  put_header(out->data(), g, p, mask, rkv_off, off_off, srv_off);
+  put_stream_header(out->data(), g, p, mask, rkv_off, off_off, srv_off);
   // RKVStream: the top level, stored raw as int16 [n_top][nb][3][B*B]
   {
     int16_t *dst = reinterpret_cast<int16_t *>(out->data() + rkv_off);

@@ -163,6 +163,7 @@ def load() -> C.CDLL:
         L.lfc_stage_needs.restype = i64
         L.lfc_render_views.argtypes = [vp, vp, i32, i32, i32, vp, vp]
         L.lfc_tune_decode.argtypes = [vp, vp, i32, C.POINTER(c_decode_tuning), vp]
+        L.lfc_encode_gpu.argtypes = [vp, C.POINTER(c_params), C.POINTER(vp), C.POINTER(sz), C.POINTER(c_stats), vp]
         L.lfc_control_rows.argtypes = [C.POINTER(c_params)]
         L.lfc_control_rows.restype = i64
         L.lfc_encode_ctl.argtypes = [vp, C.POINTER(c_params), C.POINTER(c_control), C.POINTER(vp), C.POINTER(sz),
@@ -196,7 +197,7 @@ def load() -> C.CDLL:
         L.lfc_server_get_stats.argtypes = [vp, C.POINTER(c_server_stats)]
         L.lfc_server_destroy.argtypes = [vp]
         for f in ("lfc_encode", "lfc_encode_ex", "lfc_validate", "lfc_open", "lfc_info", "lfc_decode_blocks",
-                  "lfc_render_views", "lfc_render_views_ex", "lfc_encode_ctl", "lfc_tune_decode", "lfc_mlp_infer", "lfc_mlp_grad",
+                  "lfc_render_views", "lfc_render_views_ex", "lfc_encode_ctl", "lfc_tune_decode", "lfc_encode_gpu", "lfc_mlp_infer", "lfc_mlp_grad",
                   "lfc_mlp_adam", "lfc_render_tune", "lfc_render_plan_create",
                   "lfc_render_plan_launch", "lfc_render_plan_info", "lfc_check", "lfc_close", "lfc_decode_progressive", "lfc_batch_create",
                   "lfc_batch_decode", "lfc_batch_check", "lfc_batch_render",
@@ -351,6 +352,34 @@ def mlp_grad(w, x, cls, rng, part=None, cuda_stream=None):
 def mlp_adam(master, w, m, v, grad, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, cuda_stream=None):
     _check(load().lfc_mlp_adam(master.data_ptr(), w.data_ptr(), m.data_ptr(), v.data_ptr(), grad.data_ptr(), step,
                                lr, beta1, beta2, eps, _stream_ptr(cuda_stream)))
+
+
+def lfc_encode_gpu(rgb, params: Params, want_stream: bool = True, cuda_stream=None):
+    """lfc_encode_ex on the GPU.  rgb: uint8 [V][U][H][W][3], a CUDA tensor
+    or a host array (copied to the device).  Returns (stream or None, stats)."""
+    import torch
+    if not isinstance(rgb, torch.Tensor):
+        rgb = torch.from_numpy(np.ascontiguousarray(rgb, dtype=np.uint8)).cuda()
+    assert rgb.dtype == torch.uint8 and rgb.is_cuda and rgb.is_contiguous()
+    if tuple(rgb.shape) != (params.grid_v, params.grid_u, params.height, params.width, 3):
+        raise ValueError(f"rgb shape {tuple(rgb.shape)} does not match the parameters")
+    st = c_stats()
+    out, n = C.c_void_p(), C.c_size_t()
+    if want_stream:
+        _check(load().lfc_encode_gpu(rgb.data_ptr(), C.byref(params.to_c()), C.byref(out), C.byref(n), C.byref(st),
+                                     _stream_ptr(cuda_stream)))
+    else:
+        _check(load().lfc_encode_gpu(rgb.data_ptr(), C.byref(params.to_c()), None, None, C.byref(st),
+                                     _stream_ptr(cuda_stream)))
+    data = None
+    if want_stream:
+        try:
+            data = C.string_at(out.value, n.value)
+        finally:
+            load().lfc_free(out)
+    stats = dict(psnr=st.psnr, psnr_y=st.psnr_y, psnr_co=st.psnr_co, psnr_cg=st.psnr_cg,
+                 present_blocks=st.present_blocks, code_hist=list(st.code_hist), stream_bytes=st.stream_bytes)
+    return data, stats
 
 
 def lfc_validate(stream: bytes) -> Params:
