@@ -374,7 +374,9 @@ def main():
         gstream, _ = lfc.lfc_encode_gpu(d_rgb, w40.params())
         gpu_encode_s = time.perf_counter() - t0
         extra["encode_full40"] = dict(gpu_s=round(gpu_encode_s, 4), host_s=round(host_encode_s, 3),
-                                      host_threads=os.cpu_count(), same_stream=gstream == stream40)
+                                      host_threads=min(16, os.cpu_count() or 1,
+                                                       int(os.environ.get("OMP_NUM_THREADS", "0")) or 16),
+                                      same_stream=gstream == stream40)
         del d_rgb, gstream
         # learned encoder control: the per-block network over every control
         # row of the 40 dB field (features from the search mode), and its
