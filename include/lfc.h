@@ -232,6 +232,18 @@ lfc_status lfc_mlp_infer(const uint16_t *d_w, const float *d_x, int64_t n, int8_
                          float *d_conf, float *d_logits, hipStream_t s);
 
 /*
+ * lfc_mlp_infer at a chosen precision.  LFC_MLP_FP32: float32 activations
+ * (= lfc_mlp_infer).  LFC_MLP_BF16: the three layers on the matrix cores
+ * (bf16 x bf16 products, float32 accumulation), the inputs and the two
+ * hidden layers' outputs rounded to bf16 (to nearest, ties to even); d_w must
+ * then be 16-byte aligned.  Errors: as lfc_mlp_infer, plus LFC_E_INVALID
+ * (unknown precision, misaligned weights).
+ */
+enum { LFC_MLP_FP32 = 0, LFC_MLP_BF16 = 1 };
+lfc_status lfc_mlp_infer_ex(const uint16_t *d_w, const float *d_x, int64_t n, int8_t *d_cls, int8_t *d_rng,
+                            float *d_conf, float *d_logits, int32_t precision, hipStream_t s);
+
+/*
  * Mean gradient over a batch of n rows of the loss cross-entropy(threshold
  * head, d_cls) + cross-entropy(range head, d_rng), at the bf16 weights d_w.
  * d_part: device float [ceil(n/128)][LFC_MLP_PARAMS] scratch (per-workgroup
@@ -553,7 +565,9 @@ lfc_status lfc_server_submit(lfc_server *sv, const lfc_render_request *req, uint
 lfc_status lfc_server_wait(lfc_server *sv, uint64_t ticket, int32_t timeout_ms, const float **d_img,
                            double *latency_ms);
 
-/* Returns the request's result memory to the pool and forgets the ticket. */
+/* Returns the request's result memory to the pool and forgets the ticket.
+ * The memory may be handed to the next request at once: every read of the
+ * result (a copy included) must have completed before this call. */
 lfc_status lfc_server_release(lfc_server *sv, uint64_t ticket);
 
 /* Submits reqs[i] at arrival_ms[i] after the call starts (non-decreasing

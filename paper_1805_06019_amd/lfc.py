@@ -169,6 +169,7 @@ def load() -> C.CDLL:
         L.lfc_encode_ctl.argtypes = [vp, C.POINTER(c_params), C.POINTER(c_control), C.POINTER(vp), C.POINTER(sz),
                                      C.POINTER(c_stats)]
         L.lfc_mlp_infer.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
+        L.lfc_mlp_infer_ex.argtypes = [vp, vp, i64, vp, vp, vp, vp, i32, vp]
         L.lfc_mlp_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp]
         L.lfc_mlp_adam.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
         L.lfc_render_views_ex.argtypes = [vp, vp, i32, i32, i32, vp, C.POINTER(c_render_config), vp]
@@ -197,7 +198,7 @@ def load() -> C.CDLL:
         L.lfc_server_get_stats.argtypes = [vp, C.POINTER(c_server_stats)]
         L.lfc_server_destroy.argtypes = [vp]
         for f in ("lfc_encode", "lfc_encode_ex", "lfc_validate", "lfc_open", "lfc_info", "lfc_decode_blocks",
-                  "lfc_render_views", "lfc_render_views_ex", "lfc_encode_ctl", "lfc_tune_decode", "lfc_encode_gpu", "lfc_mlp_infer", "lfc_mlp_grad",
+                  "lfc_render_views", "lfc_render_views_ex", "lfc_encode_ctl", "lfc_tune_decode", "lfc_encode_gpu", "lfc_mlp_infer", "lfc_mlp_infer_ex", "lfc_mlp_grad",
                   "lfc_mlp_adam", "lfc_render_tune", "lfc_render_plan_create",
                   "lfc_render_plan_launch", "lfc_render_plan_info", "lfc_check", "lfc_close", "lfc_decode_progressive", "lfc_batch_create",
                   "lfc_batch_decode", "lfc_batch_check", "lfc_batch_render",
@@ -319,7 +320,10 @@ def lfc_encode_ctl(rgb: np.ndarray, params: Params, mode: int, lambda_q16: int =
     return data, stats
 
 
-def mlp_infer(w, x, logits: bool = False, cuda_stream=None):
+MLP_FP32, MLP_BF16 = 0, 1
+
+
+def mlp_infer(w, x, logits: bool = False, cuda_stream=None, precision: int = MLP_FP32):
     """Network inference on the GPU: w bf16 bits (CUDA int16/uint16
     [LFC_MLP_PARAMS]), x float32 CUDA [n][16].  Returns (threshold class,
     range class, confidence[, logits]) CUDA tensors."""
@@ -329,8 +333,8 @@ def mlp_infer(w, x, logits: bool = False, cuda_stream=None):
     rng = torch.empty(n, dtype=torch.int8, device="cuda")
     conf = torch.empty(n, dtype=torch.float32, device="cuda")
     z = torch.empty((n, 37), dtype=torch.float32, device="cuda") if logits else None
-    _check(load().lfc_mlp_infer(w.data_ptr(), x.data_ptr(), n, cls.data_ptr(), rng.data_ptr(), conf.data_ptr(),
-                                z.data_ptr() if z is not None else None, _stream_ptr(cuda_stream)))
+    _check(load().lfc_mlp_infer_ex(w.data_ptr(), x.data_ptr(), n, cls.data_ptr(), rng.data_ptr(), conf.data_ptr(),
+                                   z.data_ptr() if z is not None else None, precision, _stream_ptr(cuda_stream)))
     return (cls, rng, conf, z) if logits else (cls, rng, conf)
 
 
@@ -671,16 +675,24 @@ class Server:
         return p.value, lat.value
 
     def fetch(self, ticket: int, out_w: int, out_h: int, timeout_ms: int = -1):
-        """Waits, copies the result into a new CUDA tensor, releases it."""
+        """Waits, copies the result into a new CUDA tensor, releases it.
+
+        The copy has finished before the release: a device-to-device
+        hipMemcpy may return while it is still running, and the server may
+        hand the released pool memory to the next request at once."""
         import torch
         ptr, lat = self.wait(ticket, timeout_ms)
         out = torch.empty((3, out_h, out_w), dtype=torch.float32, device="cuda")
         hip = C.CDLL("libamdhip64.so")
-        hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
-        st = hip.hipMemcpy(out.data_ptr(), ptr, out.numel() * 4, 3)   # device to device
+        hip.hipMemcpyAsync.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+        hip.hipStreamSynchronize.argtypes = [C.c_void_p]
+        stream = torch.cuda.current_stream().cuda_stream
+        st = hip.hipMemcpyAsync(out.data_ptr(), ptr, out.numel() * 4, 3, stream)   # device to device
+        if st == 0:
+            st = hip.hipStreamSynchronize(stream)
         self.release(ticket)
         if st != 0:
-            raise LFCError(-4, f"hipMemcpy failed ({st})")
+            raise LFCError(-4, f"device copy failed ({st})")
         return out, lat
 
     def release(self, ticket: int) -> None:
