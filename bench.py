@@ -395,11 +395,16 @@ def main():
         tr.part = torch.empty(8 * (lfc.MLP_PARAMS + 1), dtype=torch.float32, device="cuda")
         tr.step(xb, cb, rb)
         ts = time_launches(lambda: tr.step(xb, cb, rb), 50, torch)
+        lfc.mlp_infer(tr.w, feats, precision=lfc.MLP_BF16)
+        mb = time_launches(lambda: lfc.mlp_infer(tr.w, feats, precision=lfc.MLP_BF16), 5, torch)
         extra["encoder_control"] = dict(
             infer_rows=int(rows), infer_ms=round(float(mi.mean()), 4),
             infer_rows_per_s=round(rows / (mi.mean() * 1e-3), 1),
             infer_tflops=round(flops / (mi.mean() * 1e-3) / 1e12, 2),
             infer_frac_of_fp32_peak=round(flops / (mi.mean() * 1e-3) / 157.3e12, 4),
+            infer_bf16_ms=round(float(mb.mean()), 4),
+            infer_bf16_tflops=round(flops / (mb.mean() * 1e-3) / 1e12, 2),
+            infer_bf16_frac_of_mfma_peak=round(flops / (mb.mean() * 1e-3) / 2.5e15, 4),
             train_step_ms_1024_rows=round(float(ts.mean()), 4))
         del feats, tr
         if not args.no_serving:

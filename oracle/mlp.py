@@ -64,6 +64,16 @@ def forward(w: np.ndarray, x: np.ndarray, dtype=np.float64):
     return z, h1, h2
 
 
+def forward_bf16(w: np.ndarray, x: np.ndarray):
+    """Logits with the inputs and both hidden layers' outputs rounded to
+    bfloat16 (to nearest, ties to even) and every sum in float64."""
+    p = {k: v.astype(np.float64) for k, v in unpack(np.asarray(w, dtype=np.float64)).items()}
+    r = lambda a: bf16_round(np.asarray(a, dtype=np.float32)).astype(np.float64)
+    h1 = r(np.maximum(r(x) @ p["W1"].T + p["b1"], 0))
+    h2 = r(np.maximum(h1 @ p["W2"].T + p["b2"], 0))
+    return h2 @ p["W3"].T + p["b3"]
+
+
 def predict(w: np.ndarray, x: np.ndarray, dtype=np.float32):
     """Argmax of each head (first maximum) and the threshold head's top
     softmax probability."""

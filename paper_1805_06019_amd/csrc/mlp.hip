@@ -131,6 +131,132 @@ __global__ __launch_bounds__(kThreads) void k_mlp_infer(InferArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// inference on the matrix cores: bf16 operands, fp32 accumulation
+// ---------------------------------------------------------------------------
+// Each wave runs tiles of 32 rows through v_mfma_f32_32x32x16_bf16: lane l
+// supplies row l%32 of A with K elements 8*(l/32)..+7, column l%32 of B with
+// the same K elements, and receives D[8*(r/4) + 4*(l/32) + r%4][l%32] in its
+// register r.  The weights (as B operands) stay in registers for the wave's
+// life; each layer's output goes through the wave's LDS (bias, ReLU, rounded
+// to bf16) to become the next layer's A operand.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int kMfmaWaves = 4;
+
+__device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t *p) {
+  const uint4 v = *reinterpret_cast<const uint4 *>(p);
+  bf16x8 r;
+  __builtin_memcpy(&r, &v, sizeof r);
+  return r;
+}
+
+__global__ __launch_bounds__(64 * kMfmaWaves) void k_mlp_infer_mfma(InferArgs a, const uint16_t *w) {
+  __shared__ __attribute__((aligned(16))) __bf16 sh[kMfmaWaves][2][32][kH];   // layer outputs
+  __shared__ float sz[kMfmaWaves][32][kOut + 3];   // logits
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 31, kh = lane >> 5;
+  // B operands: W1 (K 16) as 2 column tiles; W2, W3 (K 64) as 4 K steps x 2 tiles
+  bf16x8 b1[2], b2[4][2], b3[4][2];
+  float bias1[2], bias2[2], bias3[2];
+  const bf16x8 zero8 = {};
+#pragma unroll
+  for (int t = 0; t < 2; t++) {
+    const int j = t * 32 + col;
+    b1[t] = load_bf16x8(w + oW1 + j * kIn + kh * 8);
+    bias1[t] = bf16_to_f32(w[oB1 + j]);
+    bias2[t] = bf16_to_f32(w[oB2 + j]);
+    bias3[t] = j < kOut ? bf16_to_f32(w[oB3 + j]) : 0.0f;
+#pragma unroll
+    for (int ks = 0; ks < 4; ks++) {
+      b2[ks][t] = load_bf16x8(w + oW2 + j * kH + ks * 16 + kh * 8);
+      b3[ks][t] = j < kOut ? load_bf16x8(w + oW3 + j * kH + ks * 16 + kh * 8) : zero8;
+    }
+  }
+  const int64_t tiles = (a.n + 31) / 32;
+  for (int64_t tile = (int64_t)blockIdx.x * kMfmaWaves + wv; tile < tiles; tile += (int64_t)gridDim.x * kMfmaWaves) {
+    const int64_t r0 = tile * 32, row = r0 + col;
+    // layer 1: A = this lane's row, features 8*kh..+7, rounded to bf16
+    bf16x8 a1;
+    if (row < a.n) {
+      const float4 u = *reinterpret_cast<const float4 *>(a.x + row * kIn + kh * 8);
+      const float4 v = *reinterpret_cast<const float4 *>(a.x + row * kIn + kh * 8 + 4);
+      a1[0] = (__bf16)u.x, a1[1] = (__bf16)u.y, a1[2] = (__bf16)u.z, a1[3] = (__bf16)u.w;
+      a1[4] = (__bf16)v.x, a1[5] = (__bf16)v.y, a1[6] = (__bf16)v.z, a1[7] = (__bf16)v.w;
+    } else {
+      a1 = zero8;
+    }
+    // d -> bias, ReLU, bf16 into the wave's LDS rows
+    auto store_act = [&](const f32x16 &d, float bias, int t, int buf) {
+#pragma unroll
+      for (int r = 0; r < 16; r++) sh[wv][buf][8 * (r / 4) + 4 * kh + (r % 4)][t * 32 + col] = (__bf16)fmaxf(d[r] + bias, 0.0f);
+    };
+#pragma unroll
+    for (int t = 0; t < 2; t++) {
+      f32x16 d = {};
+      d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1[t], d, 0, 0, 0);
+      store_act(d, bias1[t], t, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // LDS writes of this wave done before its reads
+    __builtin_amdgcn_wave_barrier();
+    // layer 2
+    f32x16 d2[2] = {{}, {}};
+#pragma unroll
+    for (int ks = 0; ks < 4; ks++) {
+      const bf16x8 a2 = *reinterpret_cast<const bf16x8 *>(&sh[wv][0][col][ks * 16 + kh * 8]);
+#pragma unroll
+      for (int t = 0; t < 2; t++) d2[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b2[ks][t], d2[t], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; t++) store_act(d2[t], bias2[t], t, 1);
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+    // layer 3 (columns 37..63 are zero weights)
+    f32x16 d3[2] = {{}, {}};
+#pragma unroll
+    for (int ks = 0; ks < 4; ks++) {
+      const bf16x8 a3 = *reinterpret_cast<const bf16x8 *>(&sh[wv][1][col][ks * 16 + kh * 8]);
+#pragma unroll
+      for (int t = 0; t < 2; t++) d3[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3, b3[ks][t], d3[t], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; t++)
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int j = t * 32 + col;
+        if (j < kOut) sz[wv][8 * (r / 4) + 4 * kh + (r % 4)][j] = d3[t][r] + bias3[t];
+      }
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+    // heads: lane i < 32 takes row i
+    if (lane < 32 && r0 + lane < a.n) {
+      const float *z = sz[wv][lane];
+      const int64_t rr = r0 + lane;
+      float bt = z[0], br = z[kCls];
+      int ct = 0, cr = 0;
+      for (int o = 1; o < kCls; o++)
+        if (z[o] > bt) {
+          bt = z[o];
+          ct = o;
+        }
+      for (int o = 1; o < kRng; o++)
+        if (z[kCls + o] > br) {
+          br = z[kCls + o];
+          cr = o;
+        }
+      a.cls[rr] = (int8_t)ct;
+      a.rng[rr] = (int8_t)cr;
+      if (a.conf) {
+        float den = 0.0f;
+        for (int o = 0; o < kCls; o++) den += expf(z[o] - bt);
+        a.conf[rr] = 1.0f / den;
+      }
+      if (a.logits)
+        for (int o = 0; o < kOut; o++) a.logits[rr * kOut + o] = z[o];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // batch gradient: 128 rows per workgroup, activations in LDS
 // ---------------------------------------------------------------------------
 struct GradArgs {
@@ -343,7 +469,14 @@ lfc_status infer_launch(const uint16_t *w, const float *x, int64_t n, int8_t *cl
 
 extern "C" lfc_status lfc_mlp_infer(const uint16_t *d_w, const float *d_x, int64_t n, int8_t *d_cls, int8_t *d_rng,
                                     float *d_conf, float *d_logits, hipStream_t s) {
+  return lfc_mlp_infer_ex(d_w, d_x, n, d_cls, d_rng, d_conf, d_logits, LFC_MLP_FP32, s);
+}
+
+extern "C" lfc_status lfc_mlp_infer_ex(const uint16_t *d_w, const float *d_x, int64_t n, int8_t *d_cls, int8_t *d_rng,
+                                       float *d_conf, float *d_logits, int32_t precision, hipStream_t s) {
   const char *who = "lfc_mlp_infer";
+  if (precision != LFC_MLP_FP32 && precision != LFC_MLP_BF16)
+    return lfc::fail(LFC_E_INVALID, "lfc_mlp_infer: unknown precision");
   if (n < 0) return lfc::fail(LFC_E_INVALID, "lfc_mlp_infer: n < 0");
   if (lfc_status st = mlp_check(d_w, sizeof(uint16_t) * kParams, 2, who, "d_w")) return st;
   if (n == 0) return LFC_OK;
@@ -354,7 +487,14 @@ extern "C" lfc_status lfc_mlp_infer(const uint16_t *d_w, const float *d_x, int64
     if (lfc_status st = mlp_check(d_conf, sizeof(float) * (size_t)n, 4, who, "d_conf")) return st;
   if (d_logits)
     if (lfc_status st = mlp_check(d_logits, sizeof(float) * kOut * (size_t)n, 4, who, "d_logits")) return st;
-  return infer_launch(d_w, d_x, n, d_cls, d_rng, d_conf, d_logits, s);
+  if (precision == LFC_MLP_FP32) return infer_launch(d_w, d_x, n, d_cls, d_rng, d_conf, d_logits, s);
+  if (reinterpret_cast<uintptr_t>(d_w) % 16)
+    return lfc::fail(LFC_E_INVALID, "lfc_mlp_infer: bf16 inference needs 16-byte aligned weights");
+  const int64_t tiles = (n + 31) / 32;
+  const int64_t blocks = std::min<int64_t>((tiles + kMfmaWaves - 1) / kMfmaWaves, 4096);
+  InferArgs a{nullptr, d_x, n, d_cls, d_rng, d_conf, d_logits};
+  hipLaunchKernelGGL(k_mlp_infer_mfma, dim3((unsigned)blocks), dim3(64 * kMfmaWaves), 0, s, a, d_w);
+  return mlp_launched(who);
 }
 
 extern "C" lfc_status lfc_mlp_grad(const uint16_t *d_w, const float *d_x, const int8_t *d_cls, const int8_t *d_rng,

@@ -149,3 +149,34 @@ def test_network_mode_stream_is_the_oracles_replay_and_decodes_bit_exactly(gpu):
     data3, st3 = lfc.lfc_encode_ctl(rgb, P, lfc.CTL_MLP, lam, mlp=tr.w, min_confidence=1.01)
     ref, _ = lfc.lfc_encode_ctl(rgb, P, lfc.CTL_SEARCH, lam)
     assert data3 == ref and st3["fallbacks"] == lfc.lfc_control_rows(P)
+
+
+@pytest.mark.parametrize("n", [1, 31, 33, 1000, 100_003])
+def test_bf16_matrix_core_inference_matches_oracle(gpu, n):
+    # the oracle rounds the inputs and both hidden layers to bf16 as the
+    # kernel does and sums in float64; the kernel's float32 sums can put a
+    # hidden value on the other side of a bf16 rounding boundary (one bf16
+    # step, 2^-8 relative), so most logits agree to 1e-3 of their scale and
+    # all to 2e-2; decisions agree wherever the oracle's margin is clear
+    say("mlp infer bf16", n)
+    wt, w = rand_net(13)
+    x, _, _ = rand_rows(n, 14)
+    cls, rng, conf, z = lfc.mlp_infer(wt, torch.from_numpy(x).cuda(), logits=True, precision=lfc.MLP_BF16)
+    z = z.cpu().numpy().astype(np.float64)
+    ref = omlp.forward_bf16(w, x)
+    scale = max(1.0, float(np.abs(ref).max()))
+    err = np.abs(z - ref)
+    assert err.max() <= 2e-2 * scale and np.quantile(err, 0.99) <= 1e-3 * scale
+    for got, head in ((cls.cpu().numpy(), ref[:, :10]), (rng.cpu().numpy(), ref[:, 10:])):
+        top2 = np.sort(head, axis=1)[:, -2:]
+        clear = top2[:, 1] - top2[:, 0] > 0.05 * scale
+        assert (got[clear] == np.argmax(head, axis=1)[clear]).all()
+    e = np.exp(ref[:, :10] - ref[:, :10].max(axis=1, keepdims=True))
+    assert np.abs(conf.cpu().numpy() - 1 / e.sum(axis=1)).max() <= 2e-2
+    # the fp32 path agrees on clear decisions too
+    c32, _, _ = lfc.mlp_infer(wt, torch.from_numpy(x).cuda())
+    top2 = np.sort(ref[:, :10], axis=1)[:, -2:]
+    clear = top2[:, 1] - top2[:, 0] > 0.05 * scale
+    assert (c32.cpu().numpy()[clear] == cls.cpu().numpy()[clear]).all()
+    with pytest.raises(lfc.LFCError):
+        lfc.mlp_infer(wt, torch.from_numpy(x).cuda(), precision=7)
