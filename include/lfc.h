@@ -492,10 +492,12 @@ lfc_status lfc_batch_create(lfc_batch **out);
  *  reqs    host array of n requests (n >= 0); reqs[i].lf indexes lfs.
  *  d_outs  host array of n device pointers, 4-byte aligned; d_outs[i]
  *          receives float32 [3][out_h][out_w], RGB / 255.
- * The request table is packed on the host and copied to the device on s;
- * the context double-buffers it, so two calls may be in flight, and a third
- * waits for the first to finish its copy.  The staging grows on demand (a
- * call with more requests than any before allocates).  Errors:
+ * The request table is packed on the host and copied to the device on s.
+ * The context keeps four tables: four calls may be in flight, on any
+ * streams, and a fifth waits until the kernels of the first have finished
+ * (a table is never rewritten while a launch may still read it).  The
+ * staging grows on demand (a call with more requests than any before
+ * allocates).  Errors:
  * LFC_E_INVALID (null pointer, index or size out of range, more than 65535
  * requests of one block size), LFC_E_UNSUPPORTED, LFC_E_NOMEM, LFC_E_HIP.
  */

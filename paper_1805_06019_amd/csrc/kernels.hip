@@ -237,6 +237,34 @@ __device__ __forceinline__ void store_row(int16_t *p, const uint32_t x[B / 2]) {
   }
 }
 
+// Stores of output that no kernel of the same call reads again, with the
+// non-temporal hint when NT: streamed to HBM without displacing what L2 and
+// the Infinity Cache hold (the compressed input of the next call).
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+template <bool NT>
+__device__ __forceinline__ void put4(int16_t *p, const uint32_t x[4]) {
+  if constexpr (NT) {
+    const u32x4_t v = {x[0], x[1], x[2], x[3]};
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x4_t *>(p));
+  } else {
+    *reinterpret_cast<uint4 *>(p) = make_uint4(x[0], x[1], x[2], x[3]);
+  }
+}
+template <int B, bool NT>
+__device__ __forceinline__ void put_row(int16_t *p, const uint32_t x[B / 2]) {
+  if constexpr (!NT) {
+    store_row<B>(p, x);
+  } else if constexpr (B == 2) {
+    __builtin_nontemporal_store(x[0], reinterpret_cast<uint32_t *>(p));
+  } else if constexpr (B == 4) {
+    const u32x2_t v = {x[0], x[1]};
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x2_t *>(p));
+  } else {
+    put4<true>(p, x);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // whole light field, images layout
 // ---------------------------------------------------------------------------
@@ -260,6 +288,7 @@ struct LFArgs {
   int vec_store;              // output rows may be stored 16 bytes at a time
   int n_top, key_words;       // key views; LDS words of the strip's key-view rows (0: not staged)
   int tile_cap;               // blocks of the compact residual tile
+  int stream_out;             // store the output with the non-temporal hint
 };
 
 // A whole block of a known kind (0 plain bits, 1 trit, 2 quint) decoded by one
@@ -445,11 +474,17 @@ __device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, c
       return a.out + ((uint64_t)vi * vstride + lane_off);
     };
     // two loops, so that the 16-byte stores stay whole
-    if (wide) {
+    if (wide && a.stream_out) {
       for (int i = so; i < nsib; i += SPP) {
         uint32_t x[4];
         int16_t *dst = leaf(i, x);
-        *reinterpret_cast<uint4 *>(dst) = make_uint4(x[0], x[1], x[2], x[3]);
+        put4<true>(dst, x);
+      }
+    } else if (wide) {
+      for (int i = so; i < nsib; i += SPP) {
+        uint32_t x[4];
+        int16_t *dst = leaf(i, x);
+        put4<false>(dst, x);
       }
     } else if (nact > 0) {
       for (int i = so; i < nsib; i += SPP) {
@@ -457,7 +492,10 @@ __device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, c
         int16_t *dst = leaf(i, x);
 #pragma unroll
         for (int k = 0; k < PB; k++)
-          if (k < nact) store_row<B>(dst + k * B, x + k * H);
+          if (k < nact) {
+            if (a.stream_out) put_row<B, true>(dst + k * B, x + k * H);
+            else put_row<B, false>(dst + k * B, x + k * H);
+          }
       }
     }
   }
@@ -561,7 +599,9 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
       const uniform_i32 rec = as_uniform(a.batch + (size_t)qb * lfc::kBatchWords);
       uint32_t x[H];
       load_row<B>(a.rkv + ((size_t)(rec[5] * a.nb + b) * 3 + c) * S + y * B, x);
-      store_row<B>(a.out + (size_t)rec[1] * vstride + cplane + (size_t)(by * B + y) * a.wp + bx * B, x);
+      int16_t *dst = a.out + (size_t)rec[1] * vstride + cplane + (size_t)(by * B + y) * a.wp + bx * B;
+      if (a.stream_out) put_row<B, true>(dst, x);
+      else put_row<B, false>(dst, x);
     }
     return;
   }
@@ -704,7 +744,8 @@ __global__ __launch_bounds__(kThreads) void k_decode_multi(MultiArgs a) {
 #pragma unroll
     for (int i = 0; i < B / 2; i++) x[i] = 0;
   } else {
-    gather_row<B>(a.lfs[li], vi, b, c, y, 0, digit_plan<B>(y, true), digit_plan<B>(y, false), lut, x);
+    const RAArgs la = a.lfs[li];   // the light field's record, read once
+    gather_row<B>(la, vi, b, c, y, 0, digit_plan<B>(y, true), digit_plan<B>(y, false), lut, x);
   }
   store_row<B>(a.out + ((size_t)r * 3 + c) * S + y * B, x);
 }
@@ -1013,7 +1054,9 @@ struct RenderReq {
 template <int B>
 __global__ __launch_bounds__(kThreads) void k_render_multi(const RenderReq *reqs) {
   extern __shared__ uint32_t smem[];
-  const RenderReq &r = reqs[blockIdx.y];
+  // one read of the record, at the start: every wave then works from the
+  // same copy, however late it uses a field
+  const RenderReq r = reqs[blockIdx.y];
   const int t = blockIdx.x;
   if (t >= r.ntiles) return;
   render_tile<B, false>(r.a, r.view, r.a.out, t % r.ntx, t / r.ntx, smem);
@@ -1076,6 +1119,11 @@ int max_lds_bytes() {
 // LDS of the whole-field kernel: the fixed part (LUT and extents, residual
 // tile, key-view rows) plus staging for the strip's groups and decode
 // schedule, up to 80 KB so that two workgroups share a compute unit.
+// Output larger than this (the MI355X's 256 MiB Infinity Cache) cannot stay
+// cached for a consumer, and stored normally it would evict the compressed
+// input; it is stored with the non-temporal hint.
+constexpr uint64_t kStreamOutBytes = (uint64_t)256 << 20;
+
 template <int B>
 lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s) {
   const lfc::Geometry &g = lf->geo;
@@ -1096,7 +1144,7 @@ lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s) {
   LFArgs a{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_sched, lf->d_strip_off, lf->d_order, lf->d_batch, out,
            g.nbx, g.nv(), g.L, g.q, g.wp, g.hp, g.nb, lf->n_batch, (int)cap,
            (int)(g.wp % 8 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0), g.n_top, (int)key_words,
-           lf->tile_cap};
+           lf->tile_cap, (int)((uint64_t)g.nv() * 3 * g.hp * g.wp * 2 > kStreamOutBytes)};
   dim3 grid((g.nbx + NBLK - 1) / NBLK, g.nby, 3);
   hipLaunchKernelGGL(k_decode_lf<B>, grid, dim3(kLFThreads), lds, s, a);
   return launched("lfc_decode_blocks");

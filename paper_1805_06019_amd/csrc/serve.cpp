@@ -27,13 +27,16 @@ using lfc::fail;
 
 namespace {
 
-constexpr int kSlots = 2;   // request tables in flight per batch context
+constexpr int kSlots = 4;   // request tables in flight per batch context
 
+// A request table: pinned host staging and its device copy.  `done` is
+// recorded after the launches that read the table; the slot is rewritten
+// only once it has fired, whatever stream the next call uses.
 struct Slot {
   char *host = nullptr;     // pinned
   char *dev = nullptr;
   size_t cap = 0;           // bytes of each
-  hipEvent_t copied = nullptr;
+  hipEvent_t done = nullptr;
   bool used = false;
 };
 
@@ -59,7 +62,8 @@ lfc_status grow_slot(Slot &sl, size_t need) {
   if (need <= sl.cap) return LFC_OK;
   size_t cap = std::max<size_t>(need, 64 * lfc::render_req_bytes());
   cap = std::max(cap, sl.cap * 2);
-  if (sl.used && hipEventSynchronize(sl.copied) != hipSuccess) return fail(LFC_E_HIP, "lfc_batch_render: event wait");
+  if (sl.used && hipEventSynchronize(sl.done) != hipSuccess) return fail(LFC_E_HIP, "lfc_batch_render: event wait");
+  sl.used = false;
   free_slot(sl);
   if (hipHostMalloc(reinterpret_cast<void **>(&sl.host), cap, hipHostMallocDefault) != hipSuccess) {
     sl.host = nullptr;
@@ -74,6 +78,18 @@ lfc_status grow_slot(Slot &sl, size_t need) {
   return LFC_OK;
 }
 
+// Marks the slot's table in use until the work just queued on s (the copy
+// and the launches that read it) has finished.  If the mark cannot be
+// recorded, waits for s instead, so that the slot is free again.
+lfc_status release_slot(Slot &sl, lfc_status st, hipStream_t s, const char *who) {
+  if (hipEventRecord(sl.done, s) == hipSuccess) {
+    sl.used = true;
+    return st;
+  }
+  (void)hipStreamSynchronize(s);
+  return st != LFC_OK ? st : fail(LFC_E_HIP, std::string(who) + ": event record");
+}
+
 }  // namespace
 
 extern "C" lfc_status lfc_batch_create(lfc_batch **out) {
@@ -86,7 +102,7 @@ extern "C" lfc_status lfc_batch_create(lfc_batch **out) {
     return fail(LFC_E_HIP, "lfc_batch_create: no current device");
   }
   for (Slot &sl : b->slot) {
-    if (hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming) != hipSuccess) {
+    if (hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
       (void)lfc_batch_destroy(b);
       return fail(LFC_E_HIP, "lfc_batch_create: event");
     }
@@ -103,9 +119,9 @@ extern "C" lfc_status lfc_batch_create(lfc_batch **out) {
 extern "C" lfc_status lfc_batch_destroy(lfc_batch *b) {
   if (!b) return LFC_OK;
   for (Slot &sl : b->slot) {
-    if (sl.copied) {
-      if (sl.used) (void)hipEventSynchronize(sl.copied);
-      (void)hipEventDestroy(sl.copied);
+    if (sl.done) {
+      if (sl.used) (void)hipEventSynchronize(sl.done);
+      (void)hipEventDestroy(sl.done);
     }
     free_slot(sl);
   }
@@ -163,23 +179,22 @@ extern "C" lfc_status lfc_batch_render(lfc_batch *b, const lfc_lf *const *lfs, i
       if (bs[i] == block) order.push_back(i);
   Slot &sl = b->slot[b->next];
   if (lfc_status st = grow_slot(sl, (size_t)n * rb)) return st;
-  // the slot's previous table must have reached the device before it is rewritten
-  if (sl.used && hipEventSynchronize(sl.copied) != hipSuccess) return fail(LFC_E_HIP, "lfc_batch_render: event wait");
+  // the kernels that read the slot's previous table must have finished
+  if (sl.used && hipEventSynchronize(sl.done) != hipSuccess) return fail(LFC_E_HIP, "lfc_batch_render: event wait");
+  sl.used = false;
   for (int k = 0; k < n; k++) std::memcpy(sl.host + (size_t)k * rb, &packed[(size_t)order[k] * rb], rb);
-  if (hipMemcpyAsync(sl.dev, sl.host, (size_t)n * rb, hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipEventRecord(sl.copied, s) != hipSuccess)
+  if (hipMemcpyAsync(sl.dev, sl.host, (size_t)n * rb, hipMemcpyHostToDevice, s) != hipSuccess)
     return fail(LFC_E_HIP, std::string(who) + ": copy of the request table");
-  sl.used = true;
   b->next = (b->next + 1) % kSlots;
+  lfc_status st = LFC_OK;
   int at = 0;
   for (int block : {2, 4, 8}) {
     const Group &gp = grp[block];
     if (!gp.count) continue;
-    if (lfc_status st = lfc::render_multi_launch(block, sl.dev + (size_t)at * rb, gp.count, gp.max_tiles, gp.lds, s))
-      return st;
+    if (st == LFC_OK) st = lfc::render_multi_launch(block, sl.dev + (size_t)at * rb, gp.count, gp.max_tiles, gp.lds, s);
     at += gp.count;
   }
-  return LFC_OK;
+  return release_slot(sl, st, s, who);
 }
 
 extern "C" lfc_status lfc_batch_decode(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf, const int32_t *d_req,
@@ -204,14 +219,14 @@ extern "C" lfc_status lfc_batch_decode(lfc_batch *b, const lfc_lf *const *lfs, i
   const size_t tb = lfc::lf_table_bytes();
   Slot &sl = b->slot[b->next];
   if (lfc_status st = grow_slot(sl, (size_t)n_lf * tb)) return st;
-  if (sl.used && hipEventSynchronize(sl.copied) != hipSuccess) return fail(LFC_E_HIP, "lfc_batch_decode: event wait");
+  if (sl.used && hipEventSynchronize(sl.done) != hipSuccess) return fail(LFC_E_HIP, "lfc_batch_decode: event wait");
+  sl.used = false;
   for (int i = 0; i < n_lf; i++) lfc::lf_table_fill(lfs[i], sl.host + (size_t)i * tb);
-  if (hipMemcpyAsync(sl.dev, sl.host, (size_t)n_lf * tb, hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipEventRecord(sl.copied, s) != hipSuccess)
+  if (hipMemcpyAsync(sl.dev, sl.host, (size_t)n_lf * tb, hipMemcpyHostToDevice, s) != hipSuccess)
     return fail(LFC_E_HIP, "lfc_batch_decode: copy of the light-field table");
-  sl.used = true;
   b->next = (b->next + 1) % kSlots;
-  return lfc::decode_multi_launch(block, sl.dev, n_lf, d_req, n, d_out, b->d_err, s);
+  return release_slot(sl, lfc::decode_multi_launch(block, sl.dev, n_lf, d_req, n, d_out, b->d_err, s), s,
+                      "lfc_batch_decode");
 }
 
 extern "C" lfc_status lfc_batch_check(lfc_batch *b, hipStream_t s) {

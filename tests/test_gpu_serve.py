@@ -122,6 +122,45 @@ def test_server_results_match_single_renders(fields):
     sv.close()
 
 
+def test_server_results_repeatable(fields):
+    # the whole mix several times over, two lanes: every result of every
+    # round must be the lone render's bytes (a request table rewritten under
+    # a running launch showed up here as rare residual-sized errors)
+    _, lfs = fields
+    reqs = mixed_requests(60, seed=7)
+    refs = [single(lfs, r) for r in reqs]
+    for rnd in range(6):
+        say("round", rnd)
+        sv = lfc.Server(lfs, max_batch=16, streams=2, out_pool_bytes=64 << 20)
+        tickets = [sv.submit(*r) for r in reqs]
+        for t, r, ref in zip(tickets, reqs, refs):
+            got, _ = sv.fetch(t, r[1], r[2], timeout_ms=60000)
+            assert torch.equal(got, ref), (rnd, r)
+        sv.close()
+
+
+def test_batch_contexts_across_streams(fields):
+    # one context, calls alternating between two streams with no waits in
+    # between: each call's table must survive until its own launches finish
+    _, lfs = fields
+    reqs = mixed_requests(200, seed=11)
+    refs = [single(lfs, r) for r in reqs]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    b = lfc.Batch()
+    pending = []
+    for k in range(0, len(reqs), 10):
+        part = list(range(k, min(k + 10, len(reqs))))
+        st = streams[(k // 10) % 2]
+        with torch.cuda.stream(st):
+            outs = b.render(lfs, [reqs[i] for i in part], cuda_stream=st)
+        pending.append((part, outs))
+    torch.cuda.synchronize()
+    for part, outs in pending:
+        for i, o in zip(part, outs):
+            assert torch.equal(o, refs[i]), reqs[i]
+    b.close()
+
+
 def test_server_memory_admission(fields):
     # a pool that holds two 64x64 results: the queue waits for releases
     _, lfs = fields
