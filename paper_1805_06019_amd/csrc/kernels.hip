@@ -410,6 +410,7 @@ __device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, c
   int root_cached = -1;                      // key-view row read from global memory (keys not staged)
   uint4 key = make_uint4(0u, 0u, 0u, 0u);
   const int per = (nq + kLFWaves - 1) / kLFWaves;
+  const uint32_t cap1 = (uint32_t)a.tile_cap - 1u;   // last slot of the tile
   for (int qi = wave * per; qi < min(nq, wave * per + per); qi++) {
     const uniform_i32 rec = as_uniform(a.batch + (size_t)(q0 + qi) * lfc::kBatchWords);
     const int root = rec[5];
@@ -434,27 +435,29 @@ __device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, c
       anc[2] = key.z;
       anc[3] = key.w;
     }
-    // row y of the lane's PB blocks of node ln, for the blocks that are stored
-    auto add_node = [&](int ln, uint32_t x[4]) {
-      const uint32_t mk = masks[ln], f = firsts[ln];
+    // row y of the lane's PB blocks of a node (mask mk of its stored blocks,
+    // first tile slot f) added to x.  Every row is read, from a clamped slot,
+    // and an absent block's row is masked to zero: no branch, so the reads of
+    // all the nodes a lane needs are in flight together.
+    auto add_rows = [&](uint32_t mk, uint32_t f, uint32_t x[4]) {
 #pragma unroll
       for (int k = 0; k < PB; k++) {
         const uint32_t j = (uint32_t)(jq * PB + k);
-        if ((mk >> j) & 1u) {
-          const uint32_t *row = tile + (f + (uint32_t)__popc(mk & ((1u << j) - 1u))) * (S / 2) + y * H;
-          if constexpr (H == 1) {
-            x[k] = add_pk(x[k], row[0]);
-          } else if constexpr (H == 2) {
-            const uint2 v = *reinterpret_cast<const uint2 *>(row);
-            x[2 * k] = add_pk(x[2 * k], v.x);
-            x[2 * k + 1] = add_pk(x[2 * k + 1], v.y);
-          } else {
-            const uint4 v = *reinterpret_cast<const uint4 *>(row);
-            x[0] = add_pk(x[0], v.x);
-            x[1] = add_pk(x[1], v.y);
-            x[2] = add_pk(x[2], v.z);
-            x[3] = add_pk(x[3], v.w);
-          }
+        const uint32_t keep = 0u - ((mk >> j) & 1u);
+        const uint32_t slot = min(f + (uint32_t)__popc(mk & ((1u << j) - 1u)), cap1);
+        const uint32_t *row = tile + slot * (S / 2) + y * H;
+        if constexpr (H == 1) {
+          x[k] = add_pk(x[k], row[0] & keep);
+        } else if constexpr (H == 2) {
+          const uint2 v = *reinterpret_cast<const uint2 *>(row);
+          x[2 * k] = add_pk(x[2 * k], v.x & keep);
+          x[2 * k + 1] = add_pk(x[2 * k + 1], v.y & keep);
+        } else {
+          const uint4 v = *reinterpret_cast<const uint4 *>(row);
+          x[0] = add_pk(x[0], v.x & keep);
+          x[1] = add_pk(x[1], v.y & keep);
+          x[2] = add_pk(x[2], v.z & keep);
+          x[3] = add_pk(x[3], v.w & keep);
         }
       }
     };
@@ -462,39 +465,49 @@ __device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, c
     const uint32_t anc_ln[4] = {w0 >> 16, w1 & 0xFFFFu, w1 >> 16, w2 & 0xFFFFu};
 #pragma unroll
     for (int k = 0; k < 4; k++)
-      if (k < L - 2) add_node((int)anc_ln[k], anc);
+      if (k < L - 2) add_rows(masks[anc_ln[k]], firsts[anc_ln[k]], anc);
     const int nsib = rec[0], ls0 = (int)(w0 & 0xFFFFu);
     const int v0 = rec[1], v1 = rec[2], v2 = rec[3], v3 = rec[4];
-    // sibling i of the run: its leaf row plus the ancestors
-    auto leaf = [&](int i, uint32_t x[4]) -> int16_t * {
+    // the lane's siblings so, so + SPP, ...: every leaf record and row read
+    // first, then the stores
+    constexpr int NI = lfc::kBatch / SPP;
+    uint32_t lmk[NI], lfirst[NI], xs[NI][4];
 #pragma unroll
-      for (int w = 0; w < 4; w++) x[w] = anc[w];
-      add_node(ls0 + i, x);
+    for (int t = 0; t < NI; t++) {
+      const int i = so + t * SPP;
+      const int ln = ls0 + (i < nsib ? i : 0);
+      lmk[t] = masks[ln];
+      lfirst[t] = firsts[ln];
+    }
+#pragma unroll
+    for (int t = 0; t < NI; t++) {
+#pragma unroll
+      for (int w = 0; w < 4; w++) xs[t][w] = anc[w];
+      add_rows(lmk[t], lfirst[t], xs[t]);
+    }
+    auto dst_of = [&](int i) -> int16_t * {
       const uint32_t vi = (uint32_t)(i == 0 ? v0 : (i == 1 ? v1 : (i == 2 ? v2 : v3)));
       return a.out + ((uint64_t)vi * vstride + lane_off);
     };
-    // two loops, so that the 16-byte stores stay whole
+    // separate loops, so that the 16-byte stores stay whole
     if (wide && a.stream_out) {
-      for (int i = so; i < nsib; i += SPP) {
-        uint32_t x[4];
-        int16_t *dst = leaf(i, x);
-        put4<true>(dst, x);
-      }
+#pragma unroll
+      for (int t = 0; t < NI; t++)
+        if (so + t * SPP < nsib) put4<true>(dst_of(so + t * SPP), xs[t]);
     } else if (wide) {
-      for (int i = so; i < nsib; i += SPP) {
-        uint32_t x[4];
-        int16_t *dst = leaf(i, x);
-        put4<false>(dst, x);
-      }
+#pragma unroll
+      for (int t = 0; t < NI; t++)
+        if (so + t * SPP < nsib) put4<false>(dst_of(so + t * SPP), xs[t]);
     } else if (nact > 0) {
-      for (int i = so; i < nsib; i += SPP) {
-        uint32_t x[4];
-        int16_t *dst = leaf(i, x);
+#pragma unroll
+      for (int t = 0; t < NI; t++) {
+        if (so + t * SPP >= nsib) continue;
+        int16_t *dst = dst_of(so + t * SPP);
 #pragma unroll
         for (int k = 0; k < PB; k++)
           if (k < nact) {
-            if (a.stream_out) put_row<B, true>(dst + k * B, x + k * H);
-            else put_row<B, false>(dst + k * B, x + k * H);
+            if (a.stream_out) put_row<B, true>(dst + k * B, xs[t] + k * H);
+            else put_row<B, false>(dst + k * B, xs[t] + k * H);
           }
       }
     }
