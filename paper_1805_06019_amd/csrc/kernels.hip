@@ -546,30 +546,36 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
   const int sx = st % (int)gridDim.x, by = (st / (int)gridDim.x) % (int)gridDim.y, c = st / ((int)gridDim.x * (int)gridDim.y);
   const uint32_t sched0 = a.strip_off[st], sched_len = a.strip_off[st + 1] - sched0;
   for (int t = tid; t < kLutEntries; t += kLFThreads) lut[t] = lut_entry(t);
-  if (tid < NBLK) {
-    const int bx = sx * NBLK + tid;
-    uint32_t o0 = 0, o1 = 0;
-    if (bx < a.nbx) {
+  if (tid < 64) {
+    // wave 0: the strip's group offsets and lengths, their exclusive prefix
+    // sum (a wave scan) and the staging tier
+    const int bx = sx * NBLK + lane;
+    uint32_t o0 = 0, len = 0;
+    if (lane < NBLK && bx < a.nbx) {
       const int g = 3 * (by * a.nbx + bx) + c;
       o0 = a.off[g];
-      o1 = a.off[g + 1];
+      len = a.off[g + 1] - o0;
     }
-    s_o0[tid] = o0;
-    s_len[tid] = o1 - o0;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t words = 0;
-    for (int j = 0; j < NBLK; j++) {
-      s_wo[j] = words;
-      words += s_len[j];
+    uint32_t incl = len;
+#pragma unroll
+    for (int d = 1; d < NBLK; d <<= 1) {
+      const uint32_t v = __shfl_up(incl, d);
+      if (lane >= d) incl += v;
     }
-    // tier 1: [group words][pad][schedule]; tier 2: [schedule]
-    const uint32_t tier = words + kStagePad + sched_len <= (uint32_t)a.stage_cap ? 1u
-                          : (sched_len <= (uint32_t)a.stage_cap ? 2u : 3u);
-    s_cnt[0] = tier;
-    s_cnt[1] = tier == 1u ? words : 0u;
-    s_cnt[2] = tier == 1u ? words + kStagePad : 0u;
+    const uint32_t words = __shfl(incl, NBLK - 1);
+    if (lane < NBLK) {
+      s_o0[lane] = o0;
+      s_len[lane] = len;
+      s_wo[lane] = incl - len;
+    }
+    if (lane == 0) {
+      // tier 1: [group words][pad][schedule]; tier 2: [schedule]
+      const uint32_t tier = words + kStagePad + sched_len <= (uint32_t)a.stage_cap ? 1u
+                            : (sched_len <= (uint32_t)a.stage_cap ? 2u : 3u);
+      s_cnt[0] = tier;
+      s_cnt[1] = tier == 1u ? words : 0u;
+      s_cnt[2] = tier == 1u ? words + kStagePad : 0u;
+    }
   }
   __syncthreads();
   const uint32_t tier = s_cnt[0], sched_at = s_cnt[2];
