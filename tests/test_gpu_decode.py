@@ -227,6 +227,24 @@ def test_progressive_decode_matches_oracle(gpu, case):
     lfc.lfc_check(lf)
 
 
+def test_full_size_render_paths_agree(gpu, full40, monkeypatch):
+    # 64 views of 512^2: the decode-then-interpolate path decodes full40 into
+    # 454.6 MB of scratch, more than the Infinity Cache, so that decode streams
+    # its output with the non-temporal hint; the tile path decodes footprints
+    w, _, enc = full40
+    s = w.spec
+    lf = gpu_open(enc.stream)
+    views = torch.from_numpy(synth.novel_views(64, s.grid_u, s.grid_v, seed=303)).cuda()
+    outs = []
+    for path in ("decoded", "tiles"):
+        say("full40: 64-view render,", path)
+        monkeypatch.setenv("LFC_RENDER_PATH", path)
+        outs.append(lfc.lfc_render_views(lf, views, 512, 512))
+    assert torch.equal(outs[0], outs[1])
+    ref = oracle.render(enc.r0, s.grid_u, s.grid_v, s.width, s.height, views[:2].cpu().numpy(), 512, 512)
+    assert np.abs(outs[0][:2].cpu().numpy() - ref).max() <= 1e-5
+
+
 def test_progressive_decode_full_size_and_errors(gpu, full40):
     _, _, enc = full40
     lf = gpu_open(enc.stream)
