@@ -42,6 +42,8 @@ CASES = [
     (9, 1, 40, 30, dict(block=4, levels=2, cluster=(3,)), 41, 31, 0.5),
     (1, 1, 24, 20, dict(block=4, levels=1, cluster=()), 48, 40, 0.5),
     (4, 4, 200, 120, dict(block=4, levels=2, cluster=(2,), blk_threshold=10), 50, 30, 4.0),
+    # odd width (padded to 48): the staged source rows reach into the padding
+    (5, 5, 45, 27, dict(block=4, levels=2, cluster=(2,), blk_threshold=5), 60, 40, 1.0),
     # strong minification: a whole view into one or a few output pixels
     (4, 4, 200, 120, dict(block=4, levels=2, cluster=(2,), blk_threshold=10), 1, 1, 4.0),
     (6, 3, 130, 10, dict(block=2, levels=3, cluster=(2, 2), blk_threshold=3), 3, 2, 1.0),
