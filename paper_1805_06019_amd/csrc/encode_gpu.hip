@@ -231,18 +231,31 @@ __global__ __launch_bounds__(kT) void k_enc_top_blocks(const int16_t *top, int16
   dst[r] = top[(size_t)n * 3 * plane + (size_t)ch * plane + (size_t)(by * g.B + i / g.B) * g.wp + bx * g.B + i % g.B];
 }
 
-// squared error of every (view, channel) on the unpadded area
+// squared error of every (view, channel) on the unpadded area: a workgroup
+// sums kSseRows rows of one plane in registers, then across its waves, and
+// adds once (one atomic per wave per row made the adds to a plane's counter
+// queue behind each other)
+constexpr int kSseRows = 64;
 __global__ __launch_bounds__(kT) void k_enc_sse(const int16_t *rec0, const int16_t *lvl0, unsigned long long *sse,
                                                 EncGeo g) {
-  const int x = blockIdx.x * kT + threadIdx.x, y = blockIdx.y, vc = blockIdx.z;
+  __shared__ unsigned long long part[kT / 64];
+  const int vc = blockIdx.y, y0 = blockIdx.x * kSseRows, y1 = min(y0 + kSseRows, g.H);
+  const size_t plane = (size_t)vc * g.hp * g.wp;
   int64_t e = 0;
-  if (x < g.W) {
-    const size_t o = (size_t)vc * g.hp * g.wp + (size_t)y * g.wp + x;
-    const int64_t d = (int64_t)rec0[o] - (int64_t)lvl0[o];
-    e = d * d;
-  }
+  for (int y = y0; y < y1; y++)
+    for (int x = threadIdx.x; x < g.W; x += kT) {
+      const size_t o = plane + (size_t)y * g.wp + x;
+      const int64_t d = (int64_t)rec0[o] - (int64_t)lvl0[o];
+      e += d * d;
+    }
   for (int off = 32; off > 0; off >>= 1) e += __shfl_down(e, off, 64);
-  if ((threadIdx.x & 63) == 0 && e) atomicAdd(sse + vc, (unsigned long long)e);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = (unsigned long long)e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < kT / 64; w++) t += part[w];
+    if (t) atomicAdd(sse + vc, t);
+  }
 }
 
 lfc_status launched(const char *what) {
@@ -375,7 +388,7 @@ extern "C" lfc_status lfc_encode_gpu(const uint8_t *d_rgb, const lfc_params *p, 
     unsigned long long *sse = nullptr;
     if (lfc_status st = db.alloc(&sse, (size_t)nv * 3)) return st;
     if (hipMemsetAsync(sse, 0, 8ull * nv * 3, s) != hipSuccess) return fail(LFC_E_HIP, "lfc_encode_gpu: clearing");
-    hipLaunchKernelGGL(k_enc_sse, dim3((geo.W + kT - 1) / kT, geo.H, nv * 3), dim3(kT), 0, s,
+    hipLaunchKernelGGL(k_enc_sse, dim3((geo.H + kSseRows - 1) / kSseRows, nv * 3), dim3(kT), 0, s,
                        (const int16_t *)(L > 1 ? rec[0] : lvl[0]), (const int16_t *)lvl[0], sse, g);
     if (lfc_status st = launched("squared error")) return st;
     std::vector<unsigned long long> hs((size_t)nv * 3);
