@@ -245,6 +245,39 @@ def test_full_size_render_paths_agree(gpu, full40, monkeypatch):
     assert np.abs(outs[0][:2].cpu().numpy() - ref).max() <= 1e-5
 
 
+def test_largest_light_field_of_the_workloads(gpu):
+    # 17 x 17 views of 1024 x 1024 (the serving mix's largest light fields):
+    # 909 M samples, a 1.8 GB decode; whole field, random access and two
+    # novel views against the oracle's encoder, reconstruction and renderer
+    w = WORKLOADS["serve_large40"]
+    s = w.spec
+    say("serve_large40: generating")
+    rgb = synth.light_field(s)
+    say("serve_large40: encoding with the oracle")
+    p = w.params()
+    enc = oracle.encode(rgb, oracle.Params(p.grid_u, p.grid_v, p.width, p.height, p.block, p.levels,
+                                           p.cluster, p.pix_threshold, p.blk_threshold, p.quant_bits))
+    del rgb
+    lf = gpu_open(enc.stream)
+    say("serve_large40: whole field on the GPU")
+    out = lfc.lfc_decode_blocks(lf, None, lfc.LAYOUT_IMAGES)
+    assert np.array_equal(out.cpu().numpy(), enc.r0)
+    del out
+    say("serve_large40: random access")
+    nb = lf.info.n_blocks
+    req = synth.block_requests(4096, s.grid_u * s.grid_v, nb, seed=404)
+    got = lfc.lfc_decode_blocks(lf, torch.from_numpy(req).cuda(), lfc.LAYOUT_BLOCKS).cpu().numpy()
+    nbx = (s.width + 3) // 4
+    for (vi, b), blk in zip(req, got):
+        by, bx = divmod(int(b), nbx)
+        assert np.array_equal(blk, enc.r0[vi, :, by * 4:by * 4 + 4, bx * 4:bx * 4 + 4])
+    say("serve_large40: two novel views")
+    views = synth.novel_views(2, s.grid_u, s.grid_v, seed=405)
+    img = lfc.lfc_render_views(lf, torch.from_numpy(views).cuda(), 512, 512).cpu().numpy()
+    ref = oracle.render(enc.r0, s.grid_u, s.grid_v, s.width, s.height, views, 512, 512)
+    assert np.abs(img - ref).max() <= 1e-5
+
+
 def test_progressive_decode_full_size_and_errors(gpu, full40):
     _, _, enc = full40
     lf = gpu_open(enc.stream)
