@@ -1025,7 +1025,10 @@ struct InterpArgs {
 
 template <bool FOCAL>
 __global__ __launch_bounds__(kThreads) void k_interp(InterpArgs a) {
-  const int X = blockIdx.x * kThreads + threadIdx.x, Yp = blockIdx.y, n = blockIdx.z;
+  // grid (row pieces, view, row): the workgroups that run together render one
+  // output row of every view, whose taps come from nearby rows of the same
+  // few source views, so the caches serve those rows once for all views
+  const int X = blockIdx.x * kThreads + threadIdx.x, n = blockIdx.y, Yp = blockIdx.z;
   if (X >= a.wo) return;
   const lfc_view vw = a.views[n];
   int iu0, iu1, jv0, jv1, x0, x1, y0, y1;
@@ -1276,7 +1279,7 @@ lfc_status render_with(const lfc_lf *lf, const lfc_view *views, int32_t n, int32
     lfc_status st = decode_images<B>(lf, dec, s);
     if (st == LFC_OK) {
       InterpArgs ia{dec, views, out, wo, ho, g.U, g.V, g.W, g.H, g.wp, g.hp, rc.disp};
-      const dim3 grid((wo + kThreads - 1) / kThreads, ho, n);
+      const dim3 grid((wo + kThreads - 1) / kThreads, n, ho);
       if (rc.disp != 0.0f)
         hipLaunchKernelGGL(k_interp<true>, grid, dim3(kThreads), 0, s, ia);
       else
