@@ -181,7 +181,7 @@ def main():
                     help="also run one 256 MiB device-to-device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(groups and views shard with no exchange; see the design notes)", file=sys.stderr)
         sys.exit(2)
 

@@ -36,7 +36,7 @@ typedef enum {
   LFC_E_NOMEM = -3,        /* host or device allocation failed */
   LFC_E_HIP = -4,          /* a HIP runtime call or kernel launch failed */
   LFC_E_RANGE = -5,        /* a residual needs a BISE range above 4096 values */
-  LFC_E_UNSUPPORTED = -6   /* valid request this build cannot serve */
+  LFC_E_UNSUPPORTED = -6   /* valid request the library cannot serve */
 } lfc_status;
 
 #define LFC_MAX_LEVELS 6
