@@ -405,7 +405,10 @@ __device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, c
     }
   }
   __syncthreads();
-  // (4) gather and store, waves taking consecutive runs of the chunk
+  // (4) gather and store, waves taking consecutive runs of the chunk; their
+  // issue goes first, the decode of a workgroup sharing the compute unit
+  // fills the gaps
+  __builtin_amdgcn_s_setprio(2);
   const int L = a.L;
   int root_cached = -1;                      // key-view row read from global memory (keys not staged)
   uint4 key = make_uint4(0u, 0u, 0u, 0u);
@@ -512,6 +515,7 @@ __device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, c
       }
     }
   }
+  __builtin_amdgcn_s_setprio(0);
   __syncthreads();
 }
 
