@@ -67,30 +67,102 @@ def time_launches(fn, n, torch):
     return np.array([a.elapsed_time(b) for a, b in ev])
 
 
-def cpu_baseline(stream: bytes, nv: int, hp: int, wp: int, nb: int, min_cpu_s: float = 10.0):
-    """The oracle's whole-field decoder, blocks split over the host's threads."""
+def _cpu_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+def _threaded(fn, parts):
+    """Runs fn(*part) for every part on its own thread (the oracle's C calls
+    release the GIL); returns the wall time."""
     import threading
+    ths = [threading.Thread(target=fn, args=p) for p in parts]
+    t0 = time.perf_counter()
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(streams: dict, nv: int, hp: int, wp: int, nb: int, min_cpu_s: float = 8.0):
+    """The oracle on the host's cores (16 threads at most: the GPU's share of
+    the host), bounded samples of each workload the GPU runs:
+    whole-field decode at 40 dB (the headline leg, repeated for about
+    min_cpu_s of CPU time), the same single-threaded, the 50 dB whole field,
+    per-block decodes (Alg. 2 literally) of the first requests of the 10^6
+    random accesses, and 64 novel 512x512 views of the tiny and lenslet-like
+    light fields.  Returns the 40 dB decode (for the parity check) and the
+    record."""
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
+    from paper_1805_06019_amd import synth
+    model, ncpu, usable = _cpu_info()
+    threads = max(1, min(16, usable))
     out = np.zeros((nv, 3, hp, wp), dtype=np.int16)
     chunks = np.linspace(0, nb, threads + 1).astype(int)
+    parts = [(streams["full40"], int(chunks[i]), int(chunks[i + 1]), out) for i in range(threads)
+             if chunks[i] < chunks[i + 1]]
     passes, wall, t_start = 0, 0.0, time.time()
     while True:
-        t0 = time.perf_counter()
-        ths = [threading.Thread(target=oracle.decode_all, args=(stream, int(chunks[i]), int(chunks[i + 1]), out))
-               for i in range(threads) if chunks[i] < chunks[i + 1]]
-        for t in ths:
-            t.start()
-        for t in ths:
-            t.join()
-        wall += time.perf_counter() - t0
+        wall += _threaded(oracle.decode_all, parts)
         passes += 1
         if wall * threads >= min_cpu_s or time.time() - t_start > 60:
             break
     samples = passes * nv * 3 * hp * wp
-    return out, dict(value=samples / wall / 1e9, unit="Gsamples/s", cores=threads, kind="oracle",
-                     sample=f"{passes} whole-field decode pass(es) of the 17x17x512x512 40 dB stream, "
-                            f"blocks split over {threads} threads, {wall:.2f} s wall")
+    rec = dict(value=samples / wall / 1e9, unit="Gsamples/s", cores=threads, kind="oracle",
+               sample=f"{passes} whole-field decode pass(es) of the 17x17x512x512 40 dB stream, "
+                      f"blocks split over {threads} threads, {wall:.2f} s wall",
+               cpu_model=model, cpu_count=ncpu, cpu_usable=usable, legs={})
+    legs = rec["legs"]
+    # one thread, one pass over a quarter of the blocks (into the buffer the
+    # threaded passes wrote, so that no page is touched for the first time)
+    t0 = time.perf_counter()
+    oracle.decode_all(streams["full40"], 0, nb // 4, out)
+    dt = time.perf_counter() - t0
+    legs["decode_full40_1thread"] = dict(gsamples_per_s=round(nv * 3 * hp * wp / 4 / dt / 1e9, 4), threads=1,
+                                         sample="blocks 0..NB/4 of every view, one pass")
+    # 50 dB, one threaded pass
+    out50 = np.zeros_like(out)
+    parts50 = [(streams["full50"], a, b, out50) for _, a, b, _ in parts]
+    dt = _threaded(oracle.decode_all, parts50)
+    legs["decode_full50"] = dict(gsamples_per_s=round(nv * 3 * hp * wp / dt / 1e9, 4), threads=threads,
+                                 sample="one whole-field pass")
+    del out50
+    # Alg. 2 per block: the first k of the 10^6 uniformly random accesses
+    req = synth.block_requests(1_000_000, nv, nb, seed=202)
+    k = 32_000 * threads
+    blk = np.zeros((k, 3, 4, 4), dtype=np.int16)
+    cuts = np.linspace(0, k, threads + 1).astype(int)
+    dt = _threaded(lambda a, b: oracle.decode_requests(streams["full40"], req[a:b], blk[a:b]),
+                   [(int(cuts[i]), int(cuts[i + 1])) for i in range(threads)])
+    legs["random_access_full40"] = dict(ns_per_access=round(dt * 1e9 / k, 1),
+                                        gsamples_per_s=round(k * 48 / dt / 1e9, 5), threads=threads,
+                                        sample=f"first {k} of the 10^6 accesses (seed 202), all 3 channels")
+    # 64 novel 512x512 views (seed 302) from the decoded tiny and lenslet-like fields
+    for name, key, U, V, W, H in (("render_tiny", "tiny", 8, 8, 64, 64),
+                                  ("render_lenslet40", "lenslet40", 9, 9, 625, 434)):
+        dec = oracle.decode_all(streams[key])
+        views = synth.novel_views(64, U, V, seed=302)
+        img = np.zeros((64, 3, 512, 512), dtype=np.float32)
+
+        def rend(a, b, dec=dec, views=views, img=img, U=U, V=V, W=W, H=H):
+            img[a:b] = oracle.render(dec, U, V, W, H, views[a:b], 512, 512)
+        cuts = np.linspace(0, 64, threads + 1).astype(int)
+        dt = _threaded(rend, [(int(cuts[i]), int(cuts[i + 1])) for i in range(threads) if cuts[i] < cuts[i + 1]])
+        legs[name] = dict(views_per_s=round(64 / dt, 2), threads=threads, sample="64 views of 512x512, one pass")
+    return out, rec
 
 
 def serving(lfc, synth, torch, n_req: int = 20000):
@@ -203,11 +275,7 @@ def main():
     stream40, st40 = lfc.lfc_encode_ex(rgb, w40.params())
     host_encode_s = time.time() - t0
     log(f"encoded full40 in {host_encode_s:.1f}s: {len(stream40) / 1e6:.1f} MB, {st40['psnr']:.3f} dB")
-    if args.tile_blocks:
-        os.environ["LFC_TILE_BLOCKS"] = str(args.tile_blocks)
-    lf = lfc.lfc_open(stream40)
-    if args.tile_blocks:
-        os.environ.pop("LFC_TILE_BLOCKS", None)   # only this light field
+    lf = lfc.lfc_open(stream40, tile_blocks=args.tile_blocks)
     info = lf.info
     nv, hp, wp, nb = 289, info.padded_height, info.padded_width, info.n_blocks
     samples = nv * 3 * hp * wp
@@ -271,6 +339,7 @@ def main():
     roofline["frac_cold"] = round(alg_bytes / (np.mean(cold) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
     extra = {}
+    stream50 = streaml = dec50 = None
     if not args.quick:
         # batched render: 64 novel 512x512 views per launch (fused decode)
         views = torch.from_numpy(synth.novel_views(64, 17, 17, seed=302)).cuda()
@@ -339,6 +408,7 @@ def main():
         out50 = torch.empty_like(out)
         tile50, _ = lfc.lfc_tune_decode(lf50, reps=5, out=out50)
         d50 = time_launches(lambda: lfc.lfc_decode_blocks(lf50, None, lfc.LAYOUT_IMAGES, out=out50), 20, torch)
+        dec50 = out50.cpu().numpy()   # compared with the oracle's decode with the CPU baseline
         del out50
         extra["full50"] = dict(psnr_db=round(st50["psnr"], 3), bpp=round(8 * len(stream50) / (nv * 512 * 512), 4),
                                ms_per_decode=round(float(d50.mean()), 4), tile_blocks=tile50,
@@ -421,11 +491,22 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
-        ref, cpu = cpu_baseline(stream40, nv, hp, wp, nb)
+        streams = dict(full40=stream40)
+        streams["full50"] = stream50 if stream50 is not None else lfc.lfc_encode(rgb, WORKLOADS["full50"].params())
+        streams["tiny"] = lfc.lfc_encode(synth.light_field(WORKLOADS["tiny"].spec), WORKLOADS["tiny"].params())
+        streams["lenslet40"] = streaml if streaml is not None else \
+            lfc.lfc_encode(synth.light_field(WORKLOADS["lenslet40"].spec), WORKLOADS["lenslet40"].params())
+        ref, cpu = cpu_baseline(streams, nv, hp, wp, nb)
         ok = bool(np.array_equal(ref, out.cpu().numpy()))
         cpu["matches_gpu"] = ok
         if not ok:
             log("WARNING: oracle and GPU whole-field decodes differ")
+        if dec50 is not None:
+            import oracle
+            ok50 = bool(np.array_equal(oracle.decode_all(streams["full50"]), dec50))
+            extra["full50"]["matches_oracle"] = ok50
+            if not ok50:
+                log("WARNING: oracle and GPU 50 dB whole-field decodes differ")
 
     rec = dict(
         metric="decoded Gsamples/s", value=round(value, 2), unit="Gsamples/s", n_gpus=1,

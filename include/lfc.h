@@ -302,6 +302,23 @@ lfc_status lfc_validate(const void *stream, size_t bytes, lfc_params *p_out);
  */
 lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, lfc_lf **out);
 
+/*
+ * lfc_open with explicit settings of the handle (cfg NULL: the defaults).
+ *  tile_blocks  capacity, in stored residual blocks, of the compact tile the
+ *               whole-field decode fills per chunk of a strip (Sec. 3.5-3.6:
+ *               blocks decode in parallel; a chunk's blocks are decoded once
+ *               each, then gathered).  0: the default (2048 / 1024 / 256 for
+ *               B = 2 / 4 / 8); else a multiple of 8 in 512/B..2048.  It
+ *               changes the launch shape only: decoded samples do not depend
+ *               on it.  lfc_tune_decode measures the choice.
+ * Errors: as lfc_open, plus LFC_E_INVALID (tile_blocks out of range).
+ */
+typedef struct {
+  int32_t tile_blocks;
+} lfc_open_config;
+lfc_status lfc_open_ex(const void *stream, size_t bytes, const lfc_open_config *cfg, hipStream_t s,
+                       lfc_lf **out);
+
 /* Fills *info.  Errors: LFC_E_INVALID. */
 lfc_status lfc_info(const lfc_lf *lf, lfc_info_t *info);
 
@@ -311,7 +328,7 @@ lfc_status lfc_info(const lfc_lf *lf, lfc_info_t *info);
  * need[2i] = its groups plus its part of the decode schedule, need[2i+1] =
  * the schedule alone.  Fills min(n, strips) pairs (need may be NULL) and
  * returns the number of strips, or a negative lfc_status.  For tuning and
- * tests: the environment variable LFC_STAGE_CAP_WORDS caps the staging.
+ * tests (lfc_decode_blocks_ex can cap the staging).
  */
 int64_t lfc_stage_needs(const lfc_lf *lf, uint32_t *need, int64_t n);
 
@@ -337,6 +354,22 @@ int64_t lfc_stage_needs(const lfc_lf *lf, uint32_t *need, int64_t n);
  */
 lfc_status lfc_decode_blocks(const lfc_lf *lf, const int32_t *d_req, int64_t n, int32_t layout,
                              int16_t *d_out, hipStream_t s);
+
+/*
+ * lfc_decode_blocks with explicit launch settings (cfg NULL: automatic).
+ *  stage_cap_words  LFC_LAYOUT_IMAGES only: at most this many 32-bit words
+ *                   of LDS per workgroup for staging a strip's groups and
+ *                   decode schedule (a strip whose need exceeds it reads them
+ *                   from global memory); -1: as the strips need, within the
+ *                   workgroup's LDS budget.  Decoded samples do not depend on
+ *                   it.
+ * Errors: as lfc_decode_blocks, plus LFC_E_INVALID (stage_cap_words < -1).
+ */
+typedef struct {
+  int64_t stage_cap_words;
+} lfc_decode_config;
+lfc_status lfc_decode_blocks_ex(const lfc_lf *lf, const int32_t *d_req, int64_t n, int32_t layout,
+                                int16_t *d_out, const lfc_decode_config *cfg, hipStream_t s);
 
 /*
  * Measured tuning of the whole-field decode (LFC_LAYOUT_IMAGES): the

@@ -128,6 +128,7 @@ def lib() -> C.CDLL:
         L.orc_free.restype = None
         L.orc_read_header.argtypes = [vp, i64, C.POINTER(_Params), C.POINTER(_Geom)]
         L.orc_decode_block.argtypes = [vp, i64, i32, i32, vp]
+        L.orc_decode_requests.argtypes = [vp, i64, i64, vp, vp]
         L.orc_decode_block_level.argtypes = [vp, i64, i32, i32, i32, vp]
         L.orc_decode_all.argtypes = [vp, i64, i32, i32, vp]
         L.orc_render.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, i32, i32, i32, vp]
@@ -340,6 +341,19 @@ def decode_block(stream: bytes, vi: int, b: int) -> np.ndarray:
     s = _sbuf(stream)
     out = np.zeros((3, p.block, p.block), dtype=np.int16)
     _check(lib().orc_decode_block(_ptr(s), s.size, vi, b, _ptr(out)), "orc_decode_block")
+    return out
+
+
+def decode_requests(stream: bytes, req: np.ndarray, out: np.ndarray | None = None) -> np.ndarray:
+    """decode_block for every (view, block) row of req (int32 [n][2]), in C:
+    [n][3][B][B]."""
+    p, _ = read_header(stream)
+    s = _sbuf(stream)
+    req = np.ascontiguousarray(req, dtype=np.int32).reshape(-1, 2)
+    if out is None:
+        out = np.zeros((req.shape[0], 3, p.block, p.block), dtype=np.int16)
+    assert out.dtype == np.int16 and out.flags.c_contiguous and out.shape[0] == req.shape[0]
+    _check(lib().orc_decode_requests(_ptr(s), s.size, req.shape[0], _ptr(req), _ptr(out)), "orc_decode_requests")
     return out
 
 

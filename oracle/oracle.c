@@ -950,6 +950,18 @@ int orc_decode_block(const uint8_t *stream, int64_t bytes, int32_t vi, int32_t b
   return ORC_OK;
 }
 
+int orc_decode_requests(const uint8_t *stream, int64_t bytes, int64_t n, const int32_t *req, int16_t *out) {
+  stream_view v;
+  int st = parse_stream(stream, bytes, &v);
+  if (st) return st;
+  const int64_t S3 = 3LL * v.p.block * v.p.block;
+  for (int64_t i = 0; i < n; i++) {
+    st = orc_decode_block(stream, bytes, req[2 * i], req[2 * i + 1], out + S3 * i);
+    if (st) return st;
+  }
+  return ORC_OK;
+}
+
 /* Progressive decompression (Sec. 3.6): the same traversal as
  * orc_decode_block, stopped at tree level `level` -- the key-view block plus
  * the residuals of the view's ancestors on levels L-2 down to `level`, which

@@ -128,6 +128,11 @@ int orc_read_header(const uint8_t *stream, int64_t bytes, orc_params *p, orc_geo
  * out is [3][B*B] int16. */
 int orc_decode_block(const uint8_t *stream, int64_t bytes, int32_t vi, int32_t b, int16_t *out);
 
+/* orc_decode_block for each of n requests req[2i] = view, req[2i+1] = block in
+ * turn, block i into out + 3 B^2 i (a loop for timing and parity runs; no
+ * arithmetic of its own). */
+int orc_decode_requests(const uint8_t *stream, int64_t bytes, int64_t n, const int32_t *req, int16_t *out);
+
 /* Progressive decompression (Sec. 3.6): the traversal of orc_decode_block
  * stopped at tree level `level` (0 = the view, L-1 = its key view). */
 int orc_decode_block_level(const uint8_t *stream, int64_t bytes, int32_t vi, int32_t b, int32_t level,

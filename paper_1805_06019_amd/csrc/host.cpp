@@ -1256,6 +1256,11 @@ extern "C" lfc_status lfc_validate(const void *stream, size_t bytes, lfc_params 
 static size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
 extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, lfc_lf **out) {
+  return lfc_open_ex(stream, bytes, nullptr, s, out);
+}
+
+extern "C" lfc_status lfc_open_ex(const void *stream, size_t bytes, const lfc_open_config *cfg, hipStream_t s,
+                                  lfc_lf **out) {
   if (!stream || !out) return fail(LFC_E_INVALID, "lfc_open: null argument");
   *out = nullptr;
   Parsed ps;
@@ -1275,11 +1280,15 @@ extern "C" lfc_status lfc_open(const void *stream, size_t bytes, hipStream_t s, 
     size_t at;
   };
   static const uint32_t zeros[64] = {0};
-  // tile capacity (LFC_TILE_BLOCKS overrides it for tuning; lfc_tune_decode
-  // measures the choice): at least one run of kBatch leaves with four
-  // ancestors, 8 nodes of 64/B blocks
+  // tile capacity of the whole-field kernel (the caller's, else the default;
+  // lfc_tune_decode measures the choice): at least one run of kBatch leaves
+  // with four ancestors, 8 nodes of 64/B blocks
   int tile_cap = tile_blocks(ps.g.B);
-  if (const char *e = getenv("LFC_TILE_BLOCKS")) tile_cap = std::min(2048, std::max(512 / ps.g.B, atoi(e) / 8 * 8));
+  if (cfg && cfg->tile_blocks) {
+    if (cfg->tile_blocks < 512 / ps.g.B || cfg->tile_blocks > 2048 || cfg->tile_blocks % 8)
+      return fail(LFC_E_INVALID, "lfc_open: tile_blocks must be a multiple of 8 in 512/B..2048 (or 0)");
+    tile_cap = cfg->tile_blocks;
+  }
   StripTables stt;
   try {
     make_strip_tables(ps.g, ps.off, ps.srv, ps.dbase, ps.poff, tt.batch, tile_cap, stt);

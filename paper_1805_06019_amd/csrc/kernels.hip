@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -1130,16 +1131,21 @@ lfc_status launched(const char *who) {
   return LFC_OK;
 }
 
+// LDS a workgroup may use on the current device (queried once per device).
 int max_lds_bytes() {
-  static int cached = 0;
-  if (!cached) {
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
-      v = 64 * 1024;
-    cached = v;
+  constexpr int kDevices = 64;
+  static std::atomic<int> cached[kDevices];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 64 * 1024;
+  if (dev < kDevices)
+    if (const int v = cached[dev].load(std::memory_order_relaxed)) return v;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) {
+    (void)hipGetLastError();
+    v = 64 * 1024;
   }
-  return cached;
+  if (dev < kDevices) cached[dev].store(v, std::memory_order_relaxed);
+  return v;
 }
 
 // LDS of the whole-field kernel: the fixed part (LUT and extents, residual
@@ -1150,8 +1156,10 @@ int max_lds_bytes() {
 // input; it is stored with the non-temporal hint.
 constexpr uint64_t kStreamOutBytes = (uint64_t)256 << 20;
 
+// stage_cap < 0: as much LDS staging as the strips need, up to the 80 KB
+// workgroup budget; else at most stage_cap words (tests of the tiers).
 template <int B>
-lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s) {
+lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s, int64_t stage_cap = -1) {
   const lfc::Geometry &g = lf->geo;
   constexpr int NBLK = 64 / B;
 
@@ -1165,7 +1173,7 @@ lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s) {
     return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: tree too large for the whole-field kernel; use BLOCKS layout");
   const int64_t target = std::min<int64_t>(limit, std::max<int64_t>(80 * 1024 / 4, fixed));
   int64_t cap = std::min<int64_t>(target - fixed, (int64_t)lf->max_strip_words + kStagePad);
-  if (const char *e = getenv("LFC_STAGE_CAP_WORDS")) cap = std::min<int64_t>(cap, std::max(0, atoi(e)));
+  if (stage_cap >= 0) cap = std::min<int64_t>(cap, stage_cap);
   const size_t lds = 4 * (size_t)(fixed + cap);
   LFArgs a{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_sched, lf->d_strip_off, lf->d_order, lf->d_batch, out,
            g.nbx, g.nv(), g.L, g.q, g.wp, g.hp, g.nb, lf->n_batch, (int)cap,
@@ -1221,12 +1229,8 @@ bool plan_render(const lfc::Geometry &g, int wo, int ho, RenderPlan &pl, int TX 
 // pays off when the batch's footprints together cover about as many blocks as
 // the light field holds: each output pixel reads four views, and the
 // whole-field decode is several times cheaper per block than decoding tile
-// footprints.  LFC_RENDER_PATH=tiles|decoded overrides the choice.
+// footprints.  lfc_render_views_ex forces either path.
 bool render_decoded(const lfc::Geometry &g, int32_t n, int32_t wo, int32_t ho) {
-  if (const char *e = getenv("LFC_RENDER_PATH")) {
-    if (!strcmp(e, "tiles")) return false;
-    if (!strcmp(e, "decoded")) return true;
-  }
   return 20.0 * n * wo * ho >= (double)g.nv() * g.hp * g.wp;
 }
 
@@ -1330,7 +1334,14 @@ lfc_status check_render(const lfc_lf *lf, const lfc_view *d_views, int32_t n, in
 
 extern "C" lfc_status lfc_decode_blocks(const lfc_lf *lf, const int32_t *d_req, int64_t n, int32_t layout,
                                         int16_t *d_out, hipStream_t s) {
+  return lfc_decode_blocks_ex(lf, d_req, n, layout, d_out, nullptr, s);
+}
+
+extern "C" lfc_status lfc_decode_blocks_ex(const lfc_lf *lf, const int32_t *d_req, int64_t n, int32_t layout,
+                                           int16_t *d_out, const lfc_decode_config *cfg, hipStream_t s) {
   const char *who = "lfc_decode_blocks";
+  const int64_t stage_cap = cfg ? cfg->stage_cap_words : -1;
+  if (stage_cap < -1) return fail(LFC_E_INVALID, "lfc_decode_blocks: stage_cap_words must be >= -1");
   if (!lf) return fail(LFC_E_INVALID, "lfc_decode_blocks: null handle");
   if (lfc_status st = check_device(lf, who)) return st;
   const lfc::Geometry &g = lf->geo;
@@ -1340,9 +1351,9 @@ extern "C" lfc_status lfc_decode_blocks(const lfc_lf *lf, const int32_t *d_req, 
     if (n != g.nv()) return fail(LFC_E_INVALID, "lfc_decode_blocks: images layout needs n == grid_u*grid_v");
     if (lfc_status st = check_buffer(d_out, (size_t)g.nv() * 3 * g.hp * g.wp * 2, 16, who, "d_out")) return st;
     switch (g.B) {
-      case 2: return decode_images<2>(lf, d_out, s);
-      case 4: return decode_images<4>(lf, d_out, s);
-      default: return decode_images<8>(lf, d_out, s);
+      case 2: return decode_images<2>(lf, d_out, s, stage_cap);
+      case 4: return decode_images<4>(lf, d_out, s, stage_cap);
+      default: return decode_images<8>(lf, d_out, s, stage_cap);
     }
   }
   if (layout != LFC_LAYOUT_BLOCKS) return fail(LFC_E_INVALID, "lfc_decode_blocks: unknown layout");
@@ -1541,6 +1552,10 @@ extern "C" lfc_status lfc_render_plan_info(const lfc_render_plan *p, lfc_render_
 }
 
 namespace lfc {
+
+lfc_status device_buffer(const void *p, size_t need, size_t align, const char *who, const char *what) {
+  return check_buffer(p, need, align, who, what);
+}
 
 size_t render_req_bytes() { return sizeof(RenderReq); }
 

@@ -130,9 +130,12 @@ extern "C" lfc_status lfc_batch_destroy(lfc_batch *b) {
   return LFC_OK;
 }
 
-extern "C" lfc_status lfc_batch_render(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf,
-                                       const lfc_render_request *reqs, int32_t n, float *const *d_outs,
-                                       hipStream_t s) {
+namespace {
+
+// lfc_batch_render; with check_outs false the output pointers are trusted to
+// hold their results (the server's pool offsets, sized when admitted).
+lfc_status batch_render(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf, const lfc_render_request *reqs,
+                        int32_t n, float *const *d_outs, hipStream_t s, bool check_outs) {
   const char *who = "lfc_batch_render";
   if (!b) return fail(LFC_E_INVALID, "lfc_batch_render: null batch");
   if (n < 0) return fail(LFC_E_INVALID, "lfc_batch_render: n < 0");
@@ -160,6 +163,10 @@ extern "C" lfc_status lfc_batch_render(lfc_batch *b, const lfc_lf *const *lfs, i
       return fail(LFC_E_INVALID, "lfc_batch_render: out_w and out_h must be 1..16384");
     if (!d_outs[i] || reinterpret_cast<uintptr_t>(d_outs[i]) % 4)
       return fail(LFC_E_INVALID, "lfc_batch_render: null or unaligned output pointer");
+    if (check_outs)
+      if (lfc_status st = lfc::device_buffer(d_outs[i], (size_t)3 * r.out_w * r.out_h * sizeof(float), 4, who,
+                                             "d_outs[i]"))
+        return st;
     int block = 0, nt = 0;
     size_t lds = 0;
     if (lfc_status st = lfc::render_req_fill(lfs[r.lf], r.view, r.out_w, r.out_h, d_outs[i], &packed[(size_t)i * rb],
@@ -197,6 +204,14 @@ extern "C" lfc_status lfc_batch_render(lfc_batch *b, const lfc_lf *const *lfs, i
   return release_slot(sl, st, s, who);
 }
 
+}  // namespace
+
+extern "C" lfc_status lfc_batch_render(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf,
+                                       const lfc_render_request *reqs, int32_t n, float *const *d_outs,
+                                       hipStream_t s) {
+  return batch_render(b, lfs, n_lf, reqs, n, d_outs, s, true);
+}
+
 extern "C" lfc_status lfc_batch_decode(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf, const int32_t *d_req,
                                        int64_t n, int16_t *d_out, hipStream_t s) {
   if (!b) return fail(LFC_E_INVALID, "lfc_batch_decode: null batch");
@@ -214,8 +229,11 @@ extern "C" lfc_status lfc_batch_decode(lfc_batch *b, const lfc_lf *const *lfs, i
     else if (lfc::lf_block(lfs[i]) != block)
       return fail(LFC_E_UNSUPPORTED, "lfc_batch_decode: the light fields of one call must share the block size");
   }
-  if (reinterpret_cast<uintptr_t>(d_req) % 4 || reinterpret_cast<uintptr_t>(d_out) % 16)
-    return fail(LFC_E_INVALID, "lfc_batch_decode: d_req must be 4-byte and d_out 16-byte aligned");
+  if (lfc_status st = lfc::device_buffer(d_req, (size_t)n * 3 * sizeof(int32_t), 4, "lfc_batch_decode", "d_req"))
+    return st;
+  if (lfc_status st = lfc::device_buffer(d_out, (size_t)n * 3 * block * block * sizeof(int16_t), 16,
+                                         "lfc_batch_decode", "d_out"))
+    return st;
   const size_t tb = lfc::lf_table_bytes();
   Slot &sl = b->slot[b->next];
   if (lfc_status st = grow_slot(sl, (size_t)n_lf * tb)) return st;
@@ -415,14 +433,18 @@ void engine_loop(lfc_server *sv) {
         sv->stats.batches++;
         sv->stats.max_batch_seen = std::max<int64_t>(sv->stats.max_batch_seen, (int64_t)ids.size());
         lk.unlock();
-        lfc_status st = lfc_batch_render(ln.batch, lfs.data(), (int32_t)lfs.size(), reqs.data(), (int32_t)reqs.size(),
-                                         outs.data(), ln.stream);
+        lfc_status st = batch_render(ln.batch, lfs.data(), (int32_t)lfs.size(), reqs.data(), (int32_t)reqs.size(),
+                                     outs.data(), ln.stream, false);
         if (st == LFC_OK && hipEventRecord(ln.done, ln.stream) != hipSuccess) st = LFC_E_HIP;
-        lk.lock();
         if (st != LFC_OK) {
+          // a failure after some of the batch's launches were queued (one per
+          // block size): those still write into the batch's pool regions, so
+          // the regions are freed only once the lane's stream has drained
           sv->engine_error = lfc_last_error();
-          finish_lane(sv, ln, st);
+          (void)hipStreamSynchronize(ln.stream);
         }
+        lk.lock();
+        if (st != LFC_OK) finish_lane(sv, ln, st);
         continue;
       }
     }

@@ -16,6 +16,10 @@ namespace lfc {
 
 size_t render_req_bytes();
 
+// LFC_OK if p is device memory holding at least `need` bytes (within one
+// allocation) at the given alignment; else LFC_E_INVALID naming who and what.
+lfc_status device_buffer(const void *p, size_t need, size_t align, const char *who, const char *what);
+
 // Packs request (view v of lf at wo x ho into out, [3][ho][wo] floats) into
 // dst; reports the light field's block size, the request's tile count and
 // the LDS bytes its tiles need.

@@ -98,6 +98,14 @@ class c_decode_tuning(C.Structure):
     _fields_ = [("n_tried", C.c_int32), ("best", C.c_int32), ("tile_blocks", C.c_int32 * 8), ("ms", C.c_float * 8)]
 
 
+class c_open_config(C.Structure):
+    _fields_ = [("tile_blocks", C.c_int32)]
+
+
+class c_decode_config(C.Structure):
+    _fields_ = [("stage_cap_words", C.c_int64)]
+
+
 class c_server_config(C.Structure):
     _fields_ = [("max_batch", C.c_int32), ("streams", C.c_int32), ("out_pool_bytes", C.c_int64)]
 
@@ -156,6 +164,8 @@ def load() -> C.CDLL:
         L.lfc_free.restype = None
         L.lfc_validate.argtypes = [vp, sz, C.POINTER(c_params)]
         L.lfc_open.argtypes = [vp, sz, vp, C.POINTER(vp)]
+        L.lfc_open_ex.argtypes = [vp, sz, C.POINTER(c_open_config), vp, C.POINTER(vp)]
+        L.lfc_decode_blocks_ex.argtypes = [vp, vp, i64, i32, vp, C.POINTER(c_decode_config), vp]
         L.lfc_info.argtypes = [vp, C.POINTER(c_info)]
         L.lfc_decode_blocks.argtypes = [vp, vp, i64, i32, vp, vp]
         L.lfc_decode_progressive.argtypes = [vp, vp, i64, i32, vp, vp]
@@ -197,7 +207,8 @@ def load() -> C.CDLL:
         L.lfc_server_replay.argtypes = [vp, C.POINTER(c_render_request), dp, i32, dp]
         L.lfc_server_get_stats.argtypes = [vp, C.POINTER(c_server_stats)]
         L.lfc_server_destroy.argtypes = [vp]
-        for f in ("lfc_encode", "lfc_encode_ex", "lfc_validate", "lfc_open", "lfc_info", "lfc_decode_blocks",
+        for f in ("lfc_encode", "lfc_encode_ex", "lfc_validate", "lfc_open", "lfc_open_ex", "lfc_info",
+                  "lfc_decode_blocks", "lfc_decode_blocks_ex",
                   "lfc_render_views", "lfc_render_views_ex", "lfc_encode_ctl", "lfc_tune_decode", "lfc_encode_gpu", "lfc_mlp_infer", "lfc_mlp_infer_ex", "lfc_mlp_grad",
                   "lfc_mlp_adam", "lfc_render_tune", "lfc_render_plan_create",
                   "lfc_render_plan_launch", "lfc_render_plan_info", "lfc_check", "lfc_close", "lfc_decode_progressive", "lfc_batch_create",
@@ -415,10 +426,16 @@ class LightField:
             pass
 
 
-def lfc_open(stream: bytes, cuda_stream=None) -> LightField:
+def lfc_open(stream: bytes, cuda_stream=None, tile_blocks: int = 0) -> LightField:
+    """Opens a stream on the current device; tile_blocks: the whole-field
+    decode's tile capacity (0: the default)."""
     buf = np.frombuffer(stream, dtype=np.uint8)
     h = C.c_void_p()
-    _check(load().lfc_open(buf.ctypes.data, buf.size, _stream_ptr(cuda_stream), C.byref(h)))
+    if tile_blocks:
+        cfg = c_open_config(tile_blocks)
+        _check(load().lfc_open_ex(buf.ctypes.data, buf.size, C.byref(cfg), _stream_ptr(cuda_stream), C.byref(h)))
+    else:
+        _check(load().lfc_open(buf.ctypes.data, buf.size, _stream_ptr(cuda_stream), C.byref(h)))
     return LightField(h.value)
 
 
@@ -428,9 +445,11 @@ def lfc_info(lf: LightField) -> c_info:
     return info
 
 
-def lfc_decode_blocks(lf: LightField, req=None, layout: int = LAYOUT_BLOCKS, out=None, cuda_stream=None):
+def lfc_decode_blocks(lf: LightField, req=None, layout: int = LAYOUT_BLOCKS, out=None, cuda_stream=None,
+                      stage_cap_words: int = -1):
     """Decodes blocks on the GPU.  req: int32 CUDA tensor [n][2] = (view, block)
-    or None for every block.  Returns the int16 CUDA output tensor."""
+    or None for every block.  Returns the int16 CUDA output tensor.
+    stage_cap_words >= 0 caps the whole-field decode's LDS staging."""
     import torch
     i = lf.info
     nv = i.params.grid_u * i.params.grid_v
@@ -446,8 +465,13 @@ def lfc_decode_blocks(lf: LightField, req=None, layout: int = LAYOUT_BLOCKS, out
     if out is None:
         out = torch.empty(shape, dtype=torch.int16, device="cuda")
     assert out.dtype == torch.int16 and out.is_cuda and out.is_contiguous() and tuple(out.shape) == shape
-    _check(load().lfc_decode_blocks(lf.handle, req.data_ptr() if req is not None else None, n, layout,
-                                    out.data_ptr(), _stream_ptr(cuda_stream)))
+    if stage_cap_words == -1:
+        _check(load().lfc_decode_blocks(lf.handle, req.data_ptr() if req is not None else None, n, layout,
+                                        out.data_ptr(), _stream_ptr(cuda_stream)))
+    else:
+        cfg = c_decode_config(stage_cap_words)
+        _check(load().lfc_decode_blocks_ex(lf.handle, req.data_ptr() if req is not None else None, n, layout,
+                                           out.data_ptr(), C.byref(cfg), _stream_ptr(cuda_stream)))
     return out
 
 

@@ -61,8 +61,8 @@ def test_whole_field_images_layout(gpu, case):
 @pytest.mark.parametrize("tiers", ["global", "no-payload", "mixed"])
 @pytest.mark.parametrize("case", [GEOMS[0], GEOMS[3], GEOMS[5], GEOMS[6]],
                          ids=["8x8x64x64-B4-L2", "17x17x20x12-B4-L3", "5x4x72x24-B8-L2", "6x3x130x10-B2-L3"])
-def test_whole_field_staging_tiers(gpu, case, tiers, monkeypatch):
-    # LFC_STAGE_CAP_WORDS bounds the LDS the whole-field kernel may use to
+def test_whole_field_staging_tiers(gpu, case, tiers):
+    # stage_cap_words bounds the LDS the whole-field kernel may use to
     # stage a strip: 0 reads everything from global memory; a cap that holds
     # the schedule but not the payload of most strips stages the schedule
     # only; the median strip's full need mixes the tiers in one launch
@@ -81,8 +81,7 @@ def test_whole_field_staging_tiers(gpu, case, tiers, monkeypatch):
     else:
         cap = int(np.median(t1))
     say("images staging", case, tiers, cap)
-    monkeypatch.setenv("LFC_STAGE_CAP_WORDS", str(cap))
-    got = lfc.lfc_decode_blocks(lf, None, lfc.LAYOUT_IMAGES).cpu().numpy()
+    got = lfc.lfc_decode_blocks(lf, None, lfc.LAYOUT_IMAGES, stage_cap_words=cap).cpu().numpy()
     assert np.array_equal(got, enc.r0)
 
 
@@ -174,14 +173,28 @@ def test_tiny_workload_whole_field(gpu):
 
 
 @pytest.fixture(scope="module")
-def full40():
-    w = WORKLOADS["full40"]
-    say("full40: generating and encoding with the oracle")
-    rgb = synth.light_field(w.spec)
+def full_rgb():
+    say("full: generating the 17x17x512x512 light field")
+    return synth.light_field(WORKLOADS["full40"].spec)
+
+
+def _oracle_workload(name, rgb):
+    w = WORKLOADS[name]
+    say(f"{name}: encoding with the oracle")
     p = w.params()
     enc = oracle.encode(rgb, oracle.Params(p.grid_u, p.grid_v, p.width, p.height, p.block, p.levels,
                                            p.cluster, p.pix_threshold, p.blk_threshold, p.quant_bits))
     return w, rgb, enc
+
+
+@pytest.fixture(scope="module")
+def full40(full_rgb):
+    return _oracle_workload("full40", full_rgb)
+
+
+@pytest.fixture(scope="module")
+def full50(full_rgb):
+    return _oracle_workload("full50", full_rgb)
 
 
 def test_full_size_whole_field_and_random_access(gpu, full40):
@@ -203,6 +216,35 @@ def test_full_size_whole_field_and_random_access(gpu, full40):
     expect = blocks_of(enc.r0, 4)
     assert np.array_equal(blk, expect[req[:, 0], req[:, 1]])
     lfc.lfc_check(lf)
+
+
+def test_full50_whole_field_and_random_access(gpu, full50):
+    # the 50 dB coding of the same light field (more stored blocks per strip,
+    # more chunks, mostly schedule-only staging), at the tile capacity the
+    # tuner keeps, as the benchmark decodes it
+    w, rgb, enc = full50
+    lf = gpu_open(enc.stream)
+    say("full50: tuning the whole-field decode")
+    best, tried = lfc.lfc_tune_decode(lf, reps=2)
+    say("tried", tried, "kept", best)
+    say("full50: whole field on the GPU")
+    out = lfc.lfc_decode_blocks(lf, None, lfc.LAYOUT_IMAGES)
+    got = out.cpu().numpy()
+    assert np.array_equal(got, enc.r0)
+    del out
+    nb = lf.info.n_blocks
+    req = synth.block_requests(1_000_000, 289, nb, seed=202)
+    for vi, b in req[:64]:
+        by, bx = divmod(int(b), 128)
+        assert np.array_equal(got[vi, :, by * 4:by * 4 + 4, bx * 4:bx * 4 + 4],
+                              oracle.decode_block(enc.stream, int(vi), int(b)))
+    del got
+    say("full50: 10^6 random block accesses on the GPU")
+    blk = lfc.lfc_decode_blocks(lf, torch.from_numpy(req).cuda(), lfc.LAYOUT_BLOCKS).cpu().numpy()
+    expect = blocks_of(enc.r0, 4)
+    assert np.array_equal(blk, expect[req[:, 0], req[:, 1]])
+    lfc.lfc_check(lf)
+    lf.close()
 
 
 @pytest.mark.parametrize("case", GEOMS[:8], ids=[f"{c[0]}x{c[1]}x{c[2]}x{c[3]}-B{c[4]['block']}-L{c[4]['levels']}"
@@ -227,7 +269,7 @@ def test_progressive_decode_matches_oracle(gpu, case):
     lfc.lfc_check(lf)
 
 
-def test_full_size_render_paths_agree(gpu, full40, monkeypatch):
+def test_full_size_render_paths_agree(gpu, full40):
     # 64 views of 512^2: the decode-then-interpolate path decodes full40 into
     # 454.6 MB of scratch, more than the Infinity Cache, so that decode streams
     # its output with the non-temporal hint; the tile path decodes footprints
@@ -238,8 +280,8 @@ def test_full_size_render_paths_agree(gpu, full40, monkeypatch):
     outs = []
     for path in ("decoded", "tiles"):
         say("full40: 64-view render,", path)
-        monkeypatch.setenv("LFC_RENDER_PATH", path)
-        outs.append(lfc.lfc_render_views(lf, views, 512, 512))
+        cfg = (lfc.RENDER_DECODED, 0, 0) if path == "decoded" else (lfc.RENDER_TILES, 0, 0)
+        outs.append(lfc.lfc_render_views(lf, views, 512, 512, cfg=cfg))
     assert torch.equal(outs[0], outs[1])
     ref = oracle.render(enc.r0, s.grid_u, s.grid_v, s.width, s.height, views[:2].cpu().numpy(), 512, 512)
     assert np.abs(outs[0][:2].cpu().numpy() - ref).max() <= 1e-5
@@ -271,11 +313,16 @@ def test_largest_light_field_of_the_workloads(gpu):
     for (vi, b), blk in zip(req, got):
         by, bx = divmod(int(b), nbx)
         assert np.array_equal(blk, enc.r0[vi, :, by * 4:by * 4 + 4, bx * 4:bx * 4 + 4])
-    say("serve_large40: two novel views")
+    say("serve_large40: two novel views at 512^2 and two at 1024^2")
     views = synth.novel_views(2, s.grid_u, s.grid_v, seed=405)
     img = lfc.lfc_render_views(lf, torch.from_numpy(views).cuda(), 512, 512).cpu().numpy()
     ref = oracle.render(enc.r0, s.grid_u, s.grid_v, s.width, s.height, views, 512, 512)
     assert np.abs(img - ref).max() <= 1e-5
+    views = synth.novel_views(2, s.grid_u, s.grid_v, seed=406)
+    for path in (lfc.RENDER_TILES, lfc.RENDER_DECODED):
+        img = lfc.lfc_render_views(lf, torch.from_numpy(views).cuda(), 1024, 1024, cfg=(path, 0, 0)).cpu().numpy()
+        ref = oracle.render(enc.r0, s.grid_u, s.grid_v, s.width, s.height, views, 1024, 1024)
+        assert np.abs(img - ref).max() <= 1e-5, path
 
 
 def test_progressive_decode_full_size_and_errors(gpu, full40):

@@ -25,9 +25,12 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-5
 
 
-def render_both(enc, U, V, W, H, views, wo, ho):
+PATHS = {"tiles": (lfc.RENDER_TILES, 0, 0), "decoded": (lfc.RENDER_DECODED, 0, 0), "auto": None}
+
+
+def render_both(enc, U, V, W, H, views, wo, ho, path="auto"):
     lf = lfc.lfc_open(enc.stream)
-    got = lfc.lfc_render_views(lf, torch.from_numpy(views).cuda(), wo, ho).cpu().numpy()
+    got = lfc.lfc_render_views(lf, torch.from_numpy(views).cuda(), wo, ho, cfg=PATHS[path]).cpu().numpy()
     ref = oracle.render(enc.r0, U, V, W, H, views, wo, ho)
     return got, ref
 
@@ -52,11 +55,10 @@ CASES = [
 
 @pytest.mark.parametrize("path", ["tiles", "decoded"])
 @pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}x{c[2]}x{c[3]}-to-{c[5]}x{c[6]}" for c in CASES])
-def test_render_matches_oracle(gpu, case, path, monkeypatch):
+def test_render_matches_oracle(gpu, case, path):
     # both renderers: footprint decode per output tile, and whole-field decode
     # followed by per-pixel interpolation (chosen by batch size unless forced)
     U, V, W, H, kw, wo, ho, pan = case
-    monkeypatch.setenv("LFC_RENDER_PATH", path)
     say("render", case, path)
     rgb = make_lf(U, V, W, H, seed=U * 19 + W)
     enc = oracle_encode(rgb, **kw)
@@ -64,7 +66,7 @@ def test_render_matches_oracle(gpu, case, path, monkeypatch):
     views[0] = (0, 0, 0, 0)                       # a corner camera
     views[1] = (U - 1, V - 1, 0.25, -0.5)         # the far corner
     views[2] = (-3.0, V + 2.0, pan, pan)          # outside the grid: clamped
-    got, ref = render_both(enc, U, V, W, H, views, wo, ho)
+    got, ref = render_both(enc, U, V, W, H, views, wo, ho, path)
     assert max_abs(got, ref) <= TOL
 
 
@@ -122,7 +124,7 @@ def test_batched_render_workload(gpu, name):
 
 
 @pytest.mark.parametrize("case", CASES[:5], ids=[f"{c[0]}x{c[1]}x{c[2]}x{c[3]}-to-{c[5]}x{c[6]}" for c in CASES[:5]])
-def test_render_paths_are_bit_identical(gpu, case, monkeypatch):
+def test_render_paths_are_bit_identical(gpu, case):
     U, V, W, H, kw, wo, ho, pan = case
     rgb = make_lf(U, V, W, H, seed=U * 19 + W)
     enc = oracle_encode(rgb, **kw)
@@ -130,8 +132,7 @@ def test_render_paths_are_bit_identical(gpu, case, monkeypatch):
     views = torch.from_numpy(synth.novel_views(9, U, V, seed=W + 7, pan=pan)).cuda()
     outs = []
     for path in ("tiles", "decoded"):
-        monkeypatch.setenv("LFC_RENDER_PATH", path)
-        outs.append(lfc.lfc_render_views(lf, views, wo, ho))
+        outs.append(lfc.lfc_render_views(lf, views, wo, ho, cfg=PATHS[path]))
     assert torch.equal(outs[0], outs[1])
 
 

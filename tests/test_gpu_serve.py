@@ -194,7 +194,8 @@ def test_server_replay_and_plain_mode(fields):
 
 
 def test_server_workload_sizes(gpu):
-    # the serving mix's two output sizes on a 17x17 light field
+    # the serving mix's two output sizes on a 17x17 light field; every result
+    # equals the lone render's bytes and the oracle's renderer to 1e-5
     lfspec = synth.LFSpec(17, 17, 128, 128, 3, 2.0, 1.5, 77)
     enc = oracle_encode(synth.light_field(lfspec), block=4, levels=3, cluster=(2, 3), blk_threshold=30, quant_bits=1)
     lf = lfc.lfc_open(enc.stream)
@@ -205,8 +206,47 @@ def test_server_workload_sizes(gpu):
     for t, r in zip(tickets, reqs):
         got, _ = sv.fetch(t, r[1], r[2], timeout_ms=60000)
         assert torch.equal(got, single([lf], r))
+        ref = oracle.render(enc.r0, 17, 17, 128, 128, np.array([r[3]], dtype=np.float32), r[1], r[2])[0]
+        assert max_abs(got.cpu().numpy(), ref) <= 1e-5, r
     sv.close()
     lf.close()
+
+
+def test_batch_calls_check_buffer_sizes(fields):
+    # outputs and request lists too small for the call are refused before any
+    # launch (exact-size raw allocations: a torch tensor sits inside a larger
+    # caching-allocator segment, and the library sees only the allocation)
+    _, lfs = fields
+    lib = lfc.load()
+    s = torch.cuda.current_stream().cuda_stream
+    hip = C.CDLL("libamdhip64.so")
+    small = C.c_void_p()
+    assert hip.hipMalloc(C.byref(small), C.c_size_t(3 * 8 * 8 * 4)) == 0
+    b = lfc.Batch()
+    try:
+        handles = (C.c_void_p * len(lfs))(*[lf.handle for lf in lfs])
+        ptrs = (C.c_void_p * 1)(small.value)
+        fits = lfc._requests([(0, 8, 8, (0, 0, 0, 0))])
+        too_big = lfc._requests([(0, 9, 8, (0, 0, 0, 0))])
+        assert lib.lfc_batch_render(b.handle, handles, len(lfs), too_big, 1, ptrs, s) == -1
+        assert b"too small" in lib.lfc_last_error()
+        host = np.zeros(3 * 8 * 8, dtype=np.float32)
+        host_ptr = (C.c_void_p * 1)(host.ctypes.data)
+        assert lib.lfc_batch_render(b.handle, handles, len(lfs), fits, 1, host_ptr, s) == -1
+        assert lib.lfc_batch_render(b.handle, handles, len(lfs), fits, 1, ptrs, s) == 0
+        torch.cuda.synchronize()
+        # batched random access: 16 requests need 16 x 3 x 16 int16 out, 16 x 3 int32 in
+        pick = (C.c_void_p * 2)(lfs[0].handle, lfs[3].handle)
+        req = torch.zeros((16, 3), dtype=torch.int32, device="cuda")
+        out = torch.zeros((16, 3, 4, 4), dtype=torch.int16, device="cuda")
+        assert lib.lfc_batch_decode(b.handle, pick, 2, req.data_ptr(), 16, small.value, s) == -1
+        assert lib.lfc_batch_decode(b.handle, pick, 2, small.value, 65, out.data_ptr(), s) == -1
+        assert lib.lfc_batch_decode(b.handle, pick, 2, req.data_ptr(), 16, out.data_ptr(), s) == 0
+        b.check()
+    finally:
+        torch.cuda.synchronize()
+        b.close()
+        hip.hipFree(small)
 
 
 def test_batch_decode_across_light_fields(fields):

@@ -118,6 +118,11 @@ def test_per_block_decoder_matches_whole_field(geom):
             blk = oracle.decode_block(enc.stream, vi, b)
             by, bx = divmod(b, g.nbx)
             assert np.array_equal(blk, dec[vi, :, by * B:(by + 1) * B, bx * B:(bx + 1) * B])
+    # the request loop returns the same blocks in request order
+    req = np.array([(vi, b) for vi in range(U * V) for b in range(g.nb)][::-1], dtype=np.int32)
+    got = oracle.decode_requests(enc.stream, req)
+    for k in range(0, len(req), 7):
+        assert np.array_equal(got[k], oracle.decode_block(enc.stream, int(req[k, 0]), int(req[k, 1])))
 
 
 def test_whole_field_block_ranges_compose():
