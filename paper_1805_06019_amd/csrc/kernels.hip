@@ -275,6 +275,10 @@ constexpr int kLFWaves = kLFThreads / 64;
 constexpr int kLFHeadWords = 448;     // LDS words before the residual tile (LUT, per-block extents)
 constexpr int kStagePad = 8;          // zero words after the staged group words
 
+// LDS words of the whole-field kernel's compact tile: tile_cap slots of
+// stored blocks and one zero slot, rounded up to 16 bytes.
+__host__ __device__ constexpr int lf_tile_words(int tile_cap, int S) { return ((tile_cap + 1) * (S / 2) + 3) & ~3; }
+
 struct LFArgs {
   const int16_t *rkv;
   const uint32_t *off;
@@ -374,15 +378,18 @@ __device__ __forceinline__ uniform_i32 as_uniform(const int32_t *p) { return (un
 // whole, by one lane, with the decoder of its range kind, into its slot of
 // the compact tile; step (4): per sibling run, key-view row + ancestor rows +
 // leaf row (absent blocks add nothing), stored 16 bytes per lane.
-template <int B>
+template <int B, bool KEYS>
 __device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, const uint32_t *pw,
                                          const uint32_t *s_po, uint32_t *tile, const uint32_t *keys,
-                                         const uint16_t *lut, int tid, int wave, int lane, int so, int y, int jq,
+                                         const uint16_t *lut, int tid, int wave, int lane, int so, int jq,
                                          int bx0, int nact, bool wide, uint64_t lane_off, uint32_t vstride, int by,
                                          int c) {
-  constexpr int S = B * B, NBLK = 64 / B, H = B / 2, PB = 8 / B, SPP = 64 / (8 * B);
-  const int q0 = (int)sch[0], nq = (int)sch[1], nn = (int)sch[2];
-  const uint32_t n0 = sch[3], n01 = sch[4], n = sch[5];
+  constexpr int S = B * B, NBLK = 64 / B, H = B / 2, PB = 8 / B;
+  // the chunk's header fields, the same for every lane (made scalar)
+  const int q0 = __builtin_amdgcn_readfirstlane((int)sch[0]), nq = __builtin_amdgcn_readfirstlane((int)sch[1]);
+  const int nn = __builtin_amdgcn_readfirstlane((int)sch[2]);
+  const uint32_t n0 = __builtin_amdgcn_readfirstlane(sch[3]), n01 = __builtin_amdgcn_readfirstlane(sch[4]);
+  const uint32_t n = __builtin_amdgcn_readfirstlane(sch[5]);
   const uint32_t *masks = sch + 6;
   const uint16_t *firsts = reinterpret_cast<const uint16_t *>(masks + nn);
   const uint32_t *runs = masks + nn + (nn + 1) / 2;
@@ -406,114 +413,114 @@ __device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, c
     }
   }
   __syncthreads();
-  // (4) gather and store, waves taking consecutive runs of the chunk; their
-  // issue goes first, the decode of a workgroup sharing the compute unit
-  // fills the gaps
+  // (4) gather and store.  A wave takes two runs at a time, one per half; a
+  // lane owns one sibling of its run and one 16-byte segment (PB blocks) of
+  // the strip's rows, and walks the B rows of its blocks: each node's tile
+  // slots are found once per lane, and an absent block reads the zeroed slot
+  // at the end of the tile (no masking).  Gather issue goes first; the
+  // decode of a workgroup sharing the compute unit fills the gaps.
   __builtin_amdgcn_s_setprio(2);
   const int L = a.L;
-  int root_cached = -1;                      // key-view row read from global memory (keys not staged)
-  uint4 key = make_uint4(0u, 0u, 0u, 0u);
-  const int per = (nq + kLFWaves - 1) / kLFWaves;
-  const uint32_t cap1 = (uint32_t)a.tile_cap - 1u;   // last slot of the tile
-  for (int qi = wave * per; qi < min(nq, wave * per + per); qi++) {
-    const uniform_i32 rec = as_uniform(a.batch + (size_t)(q0 + qi) * lfc::kBatchWords);
-    const int root = rec[5];
-    uint32_t anc[4];
-    if (a.key_words) {
-      const uint4 k4 = reinterpret_cast<const uint4 *>(keys)[(((root * B + y) * NBLK + jq * PB) * H) / 4];
-      anc[0] = k4.x;
-      anc[1] = k4.y;
-      anc[2] = k4.z;
-      anc[3] = k4.w;
+  const int half = lane >> 5;
+  const uint32_t zslot = (uint32_t)a.tile_cap;       // the zeroed slot
+  const int pairs = (nq + 1) / 2, per = (pairs + kLFWaves - 1) / kLFWaves;
+  // tile words of this lane's block k of a node (mask mk of its stored
+  // blocks, first slot f)
+  auto slot_of = [&](uint32_t mk, uint32_t f, int k) -> const uint32_t * {
+    const uint32_t j = (uint32_t)(jq * PB + k);
+    const uint32_t s = ((mk >> j) & 1u) ? f + (uint32_t)__popc(mk & ((1u << j) - 1u)) : zslot;
+    return tile + s * (S / 2);
+  };
+  for (int qp = wave * per; qp < min(pairs, wave * per + per); qp++) {
+    const int q_a = 2 * qp, q_b = min(2 * qp + 1, nq - 1);
+    const uniform_i32 ra = as_uniform(a.batch + (size_t)(q0 + q_a) * lfc::kBatchWords);
+    const uniform_i32 rb = as_uniform(a.batch + (size_t)(q0 + q_b) * lfc::kBatchWords);
+    // both records through the scalar unit (each field made wave-uniform
+    // before the per-half choice, so that the choice is not moved into the
+    // address of a vector load)
+    int fa[6], fb[6];
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+      fa[k] = __builtin_amdgcn_readfirstlane(ra[k]);
+      fb[k] = __builtin_amdgcn_readfirstlane(rb[k]);
+    }
+    const int qi = half ? q_b : q_a;
+    const bool run_live = !half || 2 * qp + 1 < nq;
+    const int nsib = half ? fb[0] : fa[0], root = half ? fb[5] : fa[5];
+    const int va = so == 0 ? fa[1] : (so == 1 ? fa[2] : (so == 2 ? fa[3] : fa[4]));
+    const int vb = so == 0 ? fb[1] : (so == 1 ? fb[2] : (so == 2 ? fb[3] : fb[4]));
+    const int vi = half ? vb : va;
+    const bool live = run_live && so < nsib;
+    // key-view rows
+    uint32_t x[B][4];
+    if constexpr (KEYS) {
+#pragma unroll
+      for (int y = 0; y < B; y++) {
+        const uint4 k4 = reinterpret_cast<const uint4 *>(keys)[(((root * B + y) * NBLK + jq * PB) * H) / 4];
+        x[y][0] = k4.x;
+        x[y][1] = k4.y;
+        x[y][2] = k4.z;
+        x[y][3] = k4.w;
+      }
     } else {
-      if (root != root_cached) {
-        root_cached = root;
-        uint32_t kk[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int y = 0; y < B; y++) {
+#pragma unroll
+        for (int w = 0; w < 4; w++) x[y][w] = 0;
 #pragma unroll
         for (int k = 0; k < PB; k++)
-          if (k < nact) load_row<B>(a.rkv + ((size_t)(root * a.nb + by * a.nbx + bx0 + k) * 3 + c) * S + y * B, kk + k * H);
-        key = make_uint4(kk[0], kk[1], kk[2], kk[3]);
+          if (k < nact)
+            load_row<B>(a.rkv + ((size_t)(root * a.nb + by * a.nbx + bx0 + k) * 3 + c) * S + y * B, x[y] + k * H);
       }
-      anc[0] = key.x;
-      anc[1] = key.y;
-      anc[2] = key.z;
-      anc[3] = key.w;
     }
-    // row y of the lane's PB blocks of a node (mask mk of its stored blocks,
-    // first tile slot f) added to x.  Every row is read, from a clamped slot,
-    // and an absent block's row is masked to zero: no branch, so the reads of
-    // all the nodes a lane needs are in flight together.
-    auto add_rows = [&](uint32_t mk, uint32_t f, uint32_t x[4]) {
+    // node rows added to every row of the lane's blocks
+    auto add_node = [&](int ln) {
+      const uint32_t mk = masks[ln], f = firsts[ln];
 #pragma unroll
       for (int k = 0; k < PB; k++) {
-        const uint32_t j = (uint32_t)(jq * PB + k);
-        const uint32_t keep = 0u - ((mk >> j) & 1u);
-        const uint32_t slot = min(f + (uint32_t)__popc(mk & ((1u << j) - 1u)), cap1);
-        const uint32_t *row = tile + slot * (S / 2) + y * H;
-        if constexpr (H == 1) {
-          x[k] = add_pk(x[k], row[0] & keep);
-        } else if constexpr (H == 2) {
-          const uint2 v = *reinterpret_cast<const uint2 *>(row);
-          x[2 * k] = add_pk(x[2 * k], v.x & keep);
-          x[2 * k + 1] = add_pk(x[2 * k + 1], v.y & keep);
-        } else {
-          const uint4 v = *reinterpret_cast<const uint4 *>(row);
-          x[0] = add_pk(x[0], v.x & keep);
-          x[1] = add_pk(x[1], v.y & keep);
-          x[2] = add_pk(x[2], v.z & keep);
-          x[3] = add_pk(x[3], v.w & keep);
+        const uint32_t *t = slot_of(mk, f, k);
+#pragma unroll
+        for (int y = 0; y < B; y++) {
+          if constexpr (H == 1) {
+            x[y][k] = add_pk(x[y][k], t[y]);
+          } else if constexpr (H == 2) {
+            const uint2 v = *reinterpret_cast<const uint2 *>(t + y * 2);
+            x[y][2 * k] = add_pk(x[y][2 * k], v.x);
+            x[y][2 * k + 1] = add_pk(x[y][2 * k + 1], v.y);
+          } else {
+            const uint4 v = *reinterpret_cast<const uint4 *>(t + y * 4);
+            x[y][0] = add_pk(x[y][0], v.x);
+            x[y][1] = add_pk(x[y][1], v.y);
+            x[y][2] = add_pk(x[y][2], v.z);
+            x[y][3] = add_pk(x[y][3], v.w);
+          }
         }
       }
     };
     const uint32_t w0 = runs[3 * qi], w1 = runs[3 * qi + 1], w2 = runs[3 * qi + 2];
-    const uint32_t anc_ln[4] = {w0 >> 16, w1 & 0xFFFFu, w1 >> 16, w2 & 0xFFFFu};
+    const int anc_ln[4] = {(int)(w0 >> 16), (int)(w1 & 0xFFFFu), (int)(w1 >> 16), (int)(w2 & 0xFFFFu)};
 #pragma unroll
     for (int k = 0; k < 4; k++)
-      if (k < L - 2) add_rows(masks[anc_ln[k]], firsts[anc_ln[k]], anc);
-    const int nsib = rec[0], ls0 = (int)(w0 & 0xFFFFu);
-    const int v0 = rec[1], v1 = rec[2], v2 = rec[3], v3 = rec[4];
-    // the lane's siblings so, so + SPP, ...: every leaf record and row read
-    // first, then the stores
-    constexpr int NI = lfc::kBatch / SPP;
-    uint32_t lmk[NI], lfirst[NI], xs[NI][4];
-#pragma unroll
-    for (int t = 0; t < NI; t++) {
-      const int i = so + t * SPP;
-      const int ln = ls0 + (i < nsib ? i : 0);
-      lmk[t] = masks[ln];
-      lfirst[t] = firsts[ln];
-    }
-#pragma unroll
-    for (int t = 0; t < NI; t++) {
-#pragma unroll
-      for (int w = 0; w < 4; w++) xs[t][w] = anc[w];
-      add_rows(lmk[t], lfirst[t], xs[t]);
-    }
-    auto dst_of = [&](int i) -> int16_t * {
-      const uint32_t vi = (uint32_t)(i == 0 ? v0 : (i == 1 ? v1 : (i == 2 ? v2 : v3)));
-      return a.out + ((uint64_t)vi * vstride + lane_off);
-    };
+      if (k < L - 2) add_node(anc_ln[k]);
+    add_node((int)(w0 & 0xFFFFu) + (live ? so : 0));
+    if (!live) continue;
+    int16_t *dst = a.out + ((uint64_t)(uint32_t)vi * vstride + lane_off);
     // separate loops, so that the 16-byte stores stay whole
     if (wide && a.stream_out) {
 #pragma unroll
-      for (int t = 0; t < NI; t++)
-        if (so + t * SPP < nsib) put4<true>(dst_of(so + t * SPP), xs[t]);
+      for (int y = 0; y < B; y++) put4<true>(dst + (size_t)y * a.wp, x[y]);
     } else if (wide) {
 #pragma unroll
-      for (int t = 0; t < NI; t++)
-        if (so + t * SPP < nsib) put4<false>(dst_of(so + t * SPP), xs[t]);
+      for (int y = 0; y < B; y++) put4<false>(dst + (size_t)y * a.wp, x[y]);
     } else if (nact > 0) {
 #pragma unroll
-      for (int t = 0; t < NI; t++) {
-        if (so + t * SPP >= nsib) continue;
-        int16_t *dst = dst_of(so + t * SPP);
+      for (int y = 0; y < B; y++)
 #pragma unroll
         for (int k = 0; k < PB; k++)
           if (k < nact) {
-            if (a.stream_out) put_row<B, true>(dst + k * B, xs[t] + k * H);
-            else put_row<B, false>(dst + k * B, xs[t] + k * H);
+            if (a.stream_out) put_row<B, true>(dst + (size_t)y * a.wp + k * B, x[y] + k * H);
+            else put_row<B, false>(dst + (size_t)y * a.wp + k * B, x[y] + k * H);
           }
-      }
     }
   }
   __builtin_amdgcn_s_setprio(0);
@@ -533,15 +540,14 @@ template <int B>
 __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
   constexpr int S = B * B, NBLK = 64 / B, H = B / 2;
   constexpr int PB = 8 / B;                            // blocks per 16-byte row segment (1 for B = 8)
-  constexpr int LPS = 8 * B;                           // lanes per sibling: 8 segments x B rows
   extern __shared__ uint32_t smem[];
   uint16_t *lut = reinterpret_cast<uint16_t *>(smem);  // 384 x u16 = 192 words
   uint32_t *s_o0 = smem + 192;                         // group start word in the SRV section
   uint32_t *s_len = smem + 256;                        // group length in words
   uint32_t *s_wo = smem + 320;                         // staged group words
   uint32_t *s_cnt = smem + 384;                        // [0] tier, [1] staged group words, [2] schedule words
-  uint32_t *tile = smem + kLFHeadWords;                // compact tile: [tile_cap][S/2]
-  uint32_t *keys = tile + a.tile_cap * (S / 2);        // [n_top][B][NBLK][H]
+  uint32_t *tile = smem + kLFHeadWords;                // compact tile: [tile_cap + 1][S/2], the last slot zero
+  uint32_t *keys = tile + lf_tile_words(a.tile_cap, S); // [n_top][B][NBLK][H]
   uint32_t *stage = keys + a.key_words;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -551,6 +557,7 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
   const int sx = st % (int)gridDim.x, by = (st / (int)gridDim.x) % (int)gridDim.y, c = st / ((int)gridDim.x * (int)gridDim.y);
   const uint32_t sched0 = a.strip_off[st], sched_len = a.strip_off[st + 1] - sched0;
   for (int t = tid; t < kLutEntries; t += kLFThreads) lut[t] = lut_entry(t);
+  if (tid < S / 2) tile[a.tile_cap * (S / 2) + tid] = 0u;   // the slot of every absent block
   if (tid < 64) {
     // wave 0: the strip's group offsets and lengths, their exclusive prefix
     // sum (a wave scan) and the staging tier
@@ -629,26 +636,34 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
     }
     return;
   }
-  // store-side lane mapping: sibling slot, row, segment of PB blocks
-  const int so = lane / LPS, r = lane % LPS, y = r / 8, jq = r % 8;
+  // store-side lane mapping: run of the wave's pair (lane / 32), sibling in
+  // the run, segment of PB blocks (16 bytes of each of the B rows)
+  const int so = (lane >> 3) & 3, jq = lane & 7;
   const int bx0 = sx * NBLK + jq * PB;
   const int nact = max(0, min(PB, a.nbx - bx0));       // blocks of the segment inside the image
   const bool wide = nact == PB && a.vec_store;          // a 16-byte store is aligned
-  const uint64_t lane_off = cplane + (uint64_t)(by * B + y) * a.wp + (uint64_t)bx0 * B;
+  const uint64_t lane_off = cplane + (uint64_t)(by * B) * a.wp + (uint64_t)bx0 * B;
   const uint32_t *gsched = a.sched + sched0;
   const uint32_t *lsched = stage + sched_at;
   const int nck = (int)(tier < 3u ? lsched[0] : gsched[0]);
-  for (int ci = 0; ci < nck; ci++) {
-    if (tier == 1u)
-      lf_chunk<B>(a, lsched + lsched[1 + ci], stage, s_wo, tile, keys, lut, tid, wave, lane, so, y, jq, bx0, nact, wide,
-                  lane_off, vstride, by, c);
-    else if (tier == 2u)
-      lf_chunk<B>(a, lsched + lsched[1 + ci], a.srv, s_o0, tile, keys, lut, tid, wave, lane, so, y, jq, bx0, nact, wide,
-                  lane_off, vstride, by, c);
-    else
-      lf_chunk<B>(a, gsched + gsched[1 + ci], a.srv, s_o0, tile, keys, lut, tid, wave, lane, so, y, jq, bx0, nact, wide,
-                  lane_off, vstride, by, c);
-  }
+  // one code path per staging tier and key-row placement, so that no path
+  // carries loads it never issues
+  auto chunks = [&](auto keys_staged) {
+    constexpr bool K = decltype(keys_staged)::value;
+    for (int ci = 0; ci < nck; ci++) {
+      if (tier == 1u)
+        lf_chunk<B, K>(a, lsched + lsched[1 + ci], stage, s_wo, tile, keys, lut, tid, wave, lane, so, jq, bx0, nact,
+                       wide, lane_off, vstride, by, c);
+      else if (tier == 2u)
+        lf_chunk<B, K>(a, lsched + lsched[1 + ci], a.srv, s_o0, tile, keys, lut, tid, wave, lane, so, jq, bx0, nact,
+                       wide, lane_off, vstride, by, c);
+      else
+        lf_chunk<B, K>(a, gsched + gsched[1 + ci], a.srv, s_o0, tile, keys, lut, tid, wave, lane, so, jq, bx0, nact,
+                       wide, lane_off, vstride, by, c);
+    }
+  };
+  if (a.key_words) chunks(std::true_type{});
+  else chunks(std::false_type{});
 }
 
 // ---------------------------------------------------------------------------
@@ -1167,7 +1182,7 @@ lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s, int64_t 
   const int64_t key_words = (int64_t)g.n_top * NBLK * (B * B / 2) <= 4096 ? (int64_t)g.n_top * NBLK * (B * B / 2) : 0;
   if ((int64_t)3 * g.hp * g.wp >= ((int64_t)1 << 32))
     return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: view too large for the whole-field kernel");
-  const int64_t fixed = kLFHeadWords + (int64_t)lf->tile_cap * (B * B / 2) + key_words;
+  const int64_t fixed = kLFHeadWords + (int64_t)lf_tile_words(lf->tile_cap, B * B) + key_words;
   const int64_t limit = max_lds_bytes() / 4;
   if (fixed > limit)
     return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: tree too large for the whole-field kernel; use BLOCKS layout");
