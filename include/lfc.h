@@ -459,6 +459,31 @@ lfc_status lfc_render_views_ex(const lfc_lf *lf, const lfc_view *d_views, int32_
                                int32_t out_h, float *d_out, const lfc_render_config *cfg, hipStream_t s);
 
 /*
+ * lfc_render_views_ex for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * no allocation of any kind.  The decode-then-interpolate path decodes the
+ * source views into a static device array of LFC_NOALLOC_SCRATCH_BYTES
+ * (32 MiB), one per device, held from the first call on that device until
+ * the process ends; the tile path needs no scratch.  Results are the bytes
+ * lfc_render_views_ex gives for the same arguments.
+ *  cfg  as lfc_render_views_ex.  The automatic choice takes the decoded path
+ *       only when the light field's decoded views fit the scratch, else
+ *       tiles; an explicit LFC_RENDER_DECODED whose decoded views do not fit
+ *       fails with LFC_E_RANGE.
+ * Every decoded-path call on one device shares that device's array, and
+ * each call overwrites all of the part it reads before reading it: calls
+ * that overlap in time on one device (different streams or threads) race,
+ * so run them on one stream.
+ * Errors: as lfc_render_views_ex, plus LFC_E_RANGE (decoded views larger
+ * than the scratch), LFC_E_UNSUPPORTED (the automatic choice fell back to
+ * tiles and the tile footprint does not fit), LFC_E_HIP (the scratch's
+ * address cannot be found).
+ */
+#define LFC_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+lfc_status lfc_render_views_noalloc(const lfc_lf *lf, const lfc_view *d_views, int32_t n, int32_t out_w,
+                                    int32_t out_h, float *d_out, const lfc_render_config *cfg, hipStream_t s);
+
+/*
  * Measured tuning of the render's launch shape for one (light field, batch
  * size, output size): the decoded path and each tile shape of 32 x 8 up to
  * 256 x 8 pixels whose footprint fits are run once, then timed over `reps`

@@ -24,6 +24,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -31,6 +32,13 @@
 
 #include "internal.h"
 #include "serve.h"
+
+// Device memory of lfc_render_views_noalloc: the decoded source views of
+// its decode-then-interpolate path, for callers that cannot allocate.  Each
+// device that runs the library holds its own copy until the process ends;
+// host code reaches it only through the address hipGetSymbolAddress returns
+// on that device.
+static __device__ __align__(256) uint8_t scratch[LFC_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -1419,6 +1427,61 @@ extern "C" lfc_status lfc_render_views_ex(const lfc_lf *lf, const lfc_view *d_vi
   RenderChoice rc;
   if (lfc_status st = choose_render(lf, n, out_w, out_h, cfg, rc, who)) return st;
   return render_any(lf, d_views, n, out_w, out_h, d_out, rc, nullptr, s);
+}
+
+namespace {
+
+// Device address of `scratch` on the current device, looked up once per
+// device (the first call on a device) and kept.
+lfc_status noalloc_scratch(void **out, const char *who) {
+  constexpr int kDevices = 64;
+  static std::atomic<void *> ptrs[kDevices];
+  static std::mutex mu;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return fail(LFC_E_HIP, std::string(who) + ": no current device");
+  if (dev >= kDevices) return fail(LFC_E_UNSUPPORTED, std::string(who) + ": device index above 63");
+  void *p = ptrs[dev].load(std::memory_order_acquire);
+  if (!p) {
+    std::lock_guard<std::mutex> lock(mu);
+    p = ptrs[dev].load(std::memory_order_relaxed);
+    if (!p) {
+      const hipError_t he = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (he != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return fail(LFC_E_HIP, std::string(who) + ": address of the static scratch: " + hipGetErrorString(he));
+      }
+      ptrs[dev].store(p, std::memory_order_release);
+    }
+  }
+  *out = p;
+  return LFC_OK;
+}
+
+}  // namespace
+
+extern "C" lfc_status lfc_render_views_noalloc(const lfc_lf *lf, const lfc_view *d_views, int32_t n, int32_t out_w,
+                                               int32_t out_h, float *d_out, const lfc_render_config *cfg,
+                                               hipStream_t s) {
+  const char *who = "lfc_render_views_noalloc";
+  if (lfc_status st = check_render(lf, d_views, n, out_w, out_h, d_out, who)) return st;
+  if (n == 0) return LFC_OK;
+  RenderChoice rc;
+  if (lfc_status st = choose_render(lf, n, out_w, out_h, cfg, rc, who)) return st;
+  const size_t need = decoded_bytes(lf->geo);
+  if (rc.decoded && need > (size_t)LFC_NOALLOC_SCRATCH_BYTES) {
+    if (cfg && cfg->path == LFC_RENDER_DECODED)
+      return fail(LFC_E_RANGE, std::string(who) + ": the decoded views need " + std::to_string(need) +
+                                   " bytes; the static scratch holds " + std::to_string(LFC_NOALLOC_SCRATCH_BYTES));
+    // the automatic choice falls back to the tile path, which needs no scratch
+    RenderChoice tiles = rc;
+    lfc_render_config tc{LFC_RENDER_TILES, 0, 0, rc.disp};
+    if (lfc_status st = choose_render(lf, n, out_w, out_h, &tc, tiles, who)) return st;
+    rc = tiles;
+  }
+  void *ws = nullptr;
+  if (rc.decoded)
+    if (lfc_status st = noalloc_scratch(&ws, who)) return st;
+  return render_any(lf, d_views, n, out_w, out_h, d_out, rc, static_cast<int16_t *>(ws), s);
 }
 
 // Measured tuning: every candidate launch shape timed on the caller's views.

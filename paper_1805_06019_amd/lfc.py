@@ -17,6 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblfc.so")
 MAX_LEVELS = 6
+NOALLOC_SCRATCH_BYTES = 32 << 20   # LFC_NOALLOC_SCRATCH_BYTES
 LAYOUT_BLOCKS = 0
 LAYOUT_IMAGES = 1
 
@@ -183,6 +184,7 @@ def load() -> C.CDLL:
         L.lfc_mlp_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp]
         L.lfc_mlp_adam.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
         L.lfc_render_views_ex.argtypes = [vp, vp, i32, i32, i32, vp, C.POINTER(c_render_config), vp]
+        L.lfc_render_views_noalloc.argtypes = [vp, vp, i32, i32, i32, vp, C.POINTER(c_render_config), vp]
         L.lfc_render_tune.argtypes = [vp, vp, i32, i32, i32, vp, i32, C.POINTER(c_render_tuning), vp]
         L.lfc_render_plan_create.argtypes = [vp, C.POINTER(c_render_config), vp, i32, i32, i32, vp, i32,
                                              C.POINTER(vp)]
@@ -209,7 +211,7 @@ def load() -> C.CDLL:
         L.lfc_server_destroy.argtypes = [vp]
         for f in ("lfc_encode", "lfc_encode_ex", "lfc_validate", "lfc_open", "lfc_open_ex", "lfc_info",
                   "lfc_decode_blocks", "lfc_decode_blocks_ex",
-                  "lfc_render_views", "lfc_render_views_ex", "lfc_encode_ctl", "lfc_tune_decode", "lfc_encode_gpu", "lfc_mlp_infer", "lfc_mlp_infer_ex", "lfc_mlp_grad",
+                  "lfc_render_views", "lfc_render_views_ex", "lfc_render_views_noalloc", "lfc_encode_ctl", "lfc_tune_decode", "lfc_encode_gpu", "lfc_mlp_infer", "lfc_mlp_infer_ex", "lfc_mlp_grad",
                   "lfc_mlp_adam", "lfc_render_tune", "lfc_render_plan_create",
                   "lfc_render_plan_launch", "lfc_render_plan_info", "lfc_check", "lfc_close", "lfc_decode_progressive", "lfc_batch_create",
                   "lfc_batch_decode", "lfc_batch_check", "lfc_batch_render",
@@ -553,6 +555,17 @@ def lfc_render_views(lf: LightField, views, out_w: int, out_h: int, out=None, cu
     else:
         _check(load().lfc_render_views_ex(lf.handle, views.data_ptr(), n, out_w, out_h, out.data_ptr(),
                                           _config(cfg, disparity), _stream_ptr(cuda_stream)))
+    return out
+
+
+def lfc_render_views_noalloc(lf: LightField, views, out_w: int, out_h: int, out, cuda_stream=None, cfg=None,
+                             disparity: float = 0.0):
+    """lfc_render_views through the entry point that allocates nothing: the
+    decoded path uses the library's static device scratch.  out must be given
+    (float32 CUDA [n][3][out_h][out_w]); cfg and disparity as lfc_render_views."""
+    n, out = _render_buffers(views, out_w, out_h, out)
+    _check(load().lfc_render_views_noalloc(lf.handle, views.data_ptr(), n, out_w, out_h, out.data_ptr(),
+                                           _config(cfg, disparity), _stream_ptr(cuda_stream)))
     return out
 
 
