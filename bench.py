@@ -40,17 +40,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(tile_blocks: int):
+def measured_traffic(tile_blocks: int, staged: bool):
     """HBM bytes per launch from the committed rocprofv3 counter runs, if they
-    were taken on the current kernel source at this decode tile capacity;
-    else None."""
+    were taken on the current kernel source at this decode tile capacity and
+    staging; else None."""
     from paper_1805_06019_amd.prof_summary import kernel_source_hash
-    path = os.path.join(ROOT, "profiles", f"traffic_decode_lf_full40_t{tile_blocks}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_decode_lf_full40_t{tile_blocks}{'_staged' if staged else ''}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("tile_blocks") != tile_blocks:
+    if (rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("tile_blocks") != tile_blocks
+            or bool(rec.get("staged", False)) != staged):
         return None
     return rec.get("bytes_per_launch")
 
@@ -249,6 +250,8 @@ def main():
     ap.add_argument("--tile-blocks", type=int, default=0,
                     help="decode tile capacity to use instead of measuring the choice (profiling runs "
                          "take the value a default run chose, so that every traced launch is the timed kernel)")
+    ap.add_argument("--staged", action="store_true",
+                    help="with --tile-blocks: stage each strip in LDS (the other choice the tuner measures)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -281,14 +284,17 @@ def main():
     samples = nv * 3 * hp * wp
     out = torch.empty((nv, 3, hp, wp), dtype=torch.int16, device="cuda")
     # setup (untimed): the library's measured choice of the decode tile capacity
+    # and of staging strips in LDS
     if args.tile_blocks:
-        tile_blocks, tile_tried = args.tile_blocks, []
+        (tile_blocks, staged), tile_tried = (args.tile_blocks, args.staged), []
+        stage_cap = -1 if args.staged else 0
     else:
-        tile_blocks, tile_tried = lfc.lfc_tune_decode(lf, reps=5, out=out)
-    log(f"decode tuning: {tile_tried} -> {tile_blocks}")
+        (tile_blocks, staged), tile_tried = lfc.lfc_tune_decode_ex(lf, reps=5, out=out)
+        stage_cap = None   # the handle keeps the tuner's choice
+    log(f"decode tuning: {tile_tried} -> {tile_blocks}, staged {staged}")
 
     def step():
-        lfc.lfc_decode_blocks(lf, None, lfc.LAYOUT_IMAGES, out=out)
+        lfc.lfc_decode_blocks(lf, None, lfc.LAYOUT_IMAGES, out=out, stage_cap_words=stage_cap)
 
     for _ in range(args.warmup):
         step()
@@ -323,7 +329,7 @@ def main():
                  + 4 * nv * 4)                     # leaf schedule
     achieved = alg_bytes / (per_launch.mean() * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(tile_blocks),
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(tile_blocks, staged),
                     kernel="k_decode_lf<4>", algorithmic_bytes_per_launch=alg_bytes,
                     launch_ms_mean=round(float(per_launch.mean()), 5),
                     launch_ms_p50=round(float(np.median(per_launch)), 5))
@@ -406,12 +412,12 @@ def main():
         stream50, st50 = lfc.lfc_encode_ex(rgb, w50.params())
         lf50 = lfc.lfc_open(stream50)
         out50 = torch.empty_like(out)
-        tile50, _ = lfc.lfc_tune_decode(lf50, reps=5, out=out50)
+        (tile50, staged50), _ = lfc.lfc_tune_decode_ex(lf50, reps=5, out=out50)
         d50 = time_launches(lambda: lfc.lfc_decode_blocks(lf50, None, lfc.LAYOUT_IMAGES, out=out50), 20, torch)
         dec50 = out50.cpu().numpy()   # compared with the oracle's decode with the CPU baseline
         del out50
         extra["full50"] = dict(psnr_db=round(st50["psnr"], 3), bpp=round(8 * len(stream50) / (nv * 512 * 512), 4),
-                               ms_per_decode=round(float(d50.mean()), 4), tile_blocks=tile50,
+                               ms_per_decode=round(float(d50.mean()), 4), tile_blocks=tile50, staged=staged50,
                                gsamples_per_s=round(samples / (d50.mean() * 1e-3) / 1e9, 1))
         lf50.close()
         # lenslet-like 9x9 x 625x434, 64 views per launch
@@ -516,8 +522,8 @@ def main():
                              "(17->9->3), 4x4 blocks, q=2, T_blk=67",
                     psnr_db=round(st40["psnr"], 3), bpp=round(8 * len(stream40) / (nv * 512 * 512), 4),
                     samples_per_step=samples, stream_bytes=len(stream40),
-                    present_blocks=int(st40["present_blocks"]), tile_blocks=tile_blocks,
-                    tile_tuning={str(c): round(ms, 4) for c, ms in tile_tried}),
+                    present_blocks=int(st40["present_blocks"]), tile_blocks=tile_blocks, staged=staged,
+                    tile_tuning={f"{c}{'+staged' if st else ''}": round(ms, 4) for c, st, ms in tile_tried}),
         roofline=roofline, cpu_baseline=cpu, device=dict(name=dev_props.name, cus=dev_props.multi_processor_count,
                                                         gcn_arch=getattr(dev_props, "gcnArchName", ""),
                                                         lds_per_block=getattr(dev_props, "shared_memory_per_block", None),

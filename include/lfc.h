@@ -360,9 +360,11 @@ lfc_status lfc_decode_blocks(const lfc_lf *lf, const int32_t *d_req, int64_t n, 
  *  stage_cap_words  LFC_LAYOUT_IMAGES only: at most this many 32-bit words
  *                   of LDS per workgroup for staging a strip's groups and
  *                   decode schedule (a strip whose need exceeds it reads them
- *                   from global memory); -1: as the strips need, within the
- *                   workgroup's LDS budget.  Decoded samples do not depend on
- *                   it.
+ *                   from global memory; 0: no staging); -1: as the strips
+ *                   need, within the workgroup's LDS budget.  Without a
+ *                   config the handle's setting applies: no staging after
+ *                   lfc_open, the measured choice after lfc_tune_decode.
+ *                   Decoded samples do not depend on it.
  * Errors: as lfc_decode_blocks, plus LFC_E_INVALID (stage_cap_words < -1).
  */
 typedef struct {
@@ -375,22 +377,26 @@ lfc_status lfc_decode_blocks_ex(const lfc_lf *lf, const int32_t *d_req, int64_t 
  * Measured tuning of the whole-field decode (LFC_LAYOUT_IMAGES): the
  * kernel decodes each strip's residual blocks in chunks that fit a tile of
  * stored blocks in LDS; a larger tile means fewer chunks but less LDS for
- * staging the strip.  This call times the decode (one warm-up, then `reps`
- * launches, events on stream s, output to d_out: int16, as the images
- * layout) with the handle's current tile capacity and with 3/4, 5/4, 6/4
- * and 7/4 of the default (those that fit), rebuilding the strip tables for
- * each, and keeps the fastest in the handle; res reports what was tried.
- * Blocks until done.  The handle must not be in use by another call
+ * other uses.  The kernel can also copy each strip's groups and decode
+ * schedule into LDS before decoding it (staging) or read them from global
+ * memory.  This call times the decode (one warm-up, then `reps` launches,
+ * events on stream s, output to d_out: int16, as the images layout) with the
+ * handle's current tile capacity and with 3/4, 5/4, 6/4 and 7/4 of the
+ * default (those that fit), each with and without staging, rebuilding the
+ * strip tables for each capacity, and keeps the fastest pair in the handle
+ * (lfc_decode_blocks without a config then uses it); res reports what was
+ * tried.  Blocks until done.  The handle must not be in use by another call
  * meanwhile.  Decoded samples do not depend on the choice.
  * Errors: LFC_E_INVALID (null pointer, reps outside 1..1000, handle of
  * another device), LFC_E_NOMEM, LFC_E_HIP; on error the handle keeps the
- * tables it had.
+ * tables and the staging it had.
  */
-#define LFC_TUNE_DECODE_MAX 8
+#define LFC_TUNE_DECODE_MAX 16
 typedef struct {
   int32_t n_tried;
-  int32_t best;                              /* index of the capacity kept */
+  int32_t best;                              /* index of the choice kept */
   int32_t tile_blocks[LFC_TUNE_DECODE_MAX];  /* stored blocks per tile */
+  int32_t staged[LFC_TUNE_DECODE_MAX];       /* 1: strips staged in LDS, 0: read from global memory */
   float ms[LFC_TUNE_DECODE_MAX];             /* mean ms per decode */
 } lfc_decode_tuning;
 lfc_status lfc_tune_decode(lfc_lf *lf, int16_t *d_out, int32_t reps, lfc_decode_tuning *res, hipStream_t s);
@@ -409,6 +415,19 @@ lfc_status lfc_tune_decode(lfc_lf *lf, int16_t *d_out, int32_t reps, lfc_decode_
  */
 lfc_status lfc_decode_progressive(const lfc_lf *lf, const int32_t *d_req, int64_t n, int32_t level,
                                   int16_t *d_out, hipStream_t s);
+
+/*
+ * Every view decoded (Alg. 2 over all blocks, Sec. 3.5) and converted back to
+ * 8-bit RGB (inverse YCoCg-R, each channel clamped to 0..255; Sec. 4): the
+ * form a viewer or the decode-then-interpolate render consumes.
+ *  d_out  device uint32 [grid_u*grid_v][padded_height][padded_width], 16-byte
+ *         aligned; pixel = R | G << 8 | B << 16 (top byte zero).  Pixels of
+ *         the padding hold the conversion of the padded samples.
+ * Enqueued on s.  Errors: LFC_E_INVALID (null or too small buffer),
+ * LFC_E_UNSUPPORTED (more than 2^32 pixels, or a tree whose tables exceed
+ * the kernel's on-chip budget), LFC_E_HIP.
+ */
+lfc_status lfc_decode_rgb(const lfc_lf *lf, uint32_t *d_out, hipStream_t s);
 
 /*
  * Novel-view rendering (Sec. 3.6): every output pixel is the quadrilinear

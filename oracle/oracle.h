@@ -10,7 +10,7 @@
  * paper_1805_06019_amd/.
  *
  * Where the paper is silent the oracle follows the readings listed in the
- * design notes (C1..C20); each function names the paper passage it follows.
+ * design notes (C1..C24); each function names the paper passage it follows.
  *
  * Parity status: the integer encode/decode, BISE packing, YCoCg-R and the
  * renderer are pinned by tests/test_oracle_*.py.  Parity of the quantiser

@@ -263,7 +263,7 @@ static void build_schedule(const Geometry &g, const std::vector<uint32_t> &off, 
           const int32_t *r = &batch[(size_t)(q + k) * kBatchWords];
           int add = 0;
           std::vector<int> nl, na;
-          for (int i = 0; i < r[0]; i++) {
+          for (int i = 0; i < r[0] && L > 1; i++) {   // (a tree of height 1 has no residual nodes)
             const int s = r[10] + i;
             if (loc[(size_t)s] < 0) {
               nl.push_back(s);
@@ -330,8 +330,8 @@ static void build_schedule(const Geometry &g, const std::vector<uint32_t> &off, 
           body.push_back(bases[(size_t)i] | (i + 1 < nn ? bases[(size_t)i + 1] << 16 : 0u));
         for (int j = 0; j < k; j++) {
           const int32_t *r = &batch[(size_t)(q + j) * kBatchWords];
-          uint32_t h[4] = {(uint32_t)loc[(size_t)r[10]], 0xFFFFu, 0xFFFFu, 0xFFFFu};
-          for (int i = 0; i < L - 2; i++) h[1 + i] = (uint32_t)loc[(size_t)r[6 + i]];
+          uint32_t h[4] = {L > 1 ? (uint32_t)loc[(size_t)r[10]] : 0xFFFFu, 0xFFFFu, 0xFFFFu, 0xFFFFu};
+          for (int i = 0; i < std::min(L - 2, 3); i++) h[1 + i] = (uint32_t)loc[(size_t)r[6 + i]];
           body.push_back(h[0] | (h[1] << 16));
           body.push_back(h[2] | (h[3] << 16));
           body.push_back(L - 2 > 3 ? (uint32_t)loc[(size_t)r[9]] | 0xFFFF0000u : 0xFFFFFFFFu);
@@ -340,6 +340,157 @@ static void build_schedule(const Geometry &g, const std::vector<uint32_t> &off, 
         std::vector<uint32_t> all;
         for (int kind = 0; kind < 3; kind++) all.insert(all.end(), item[kind].begin(), item[kind].end());
         for (size_t i = 0; i < all.size(); i += 2) body.push_back(all[i] | (i + 1 < all.size() ? all[i + 1] << 16 : 0u));
+        for (int s : nodes) loc[(size_t)s] = -1;
+        q += k;
+      }
+      const uint32_t nck = (uint32_t)(head.size() - 1);
+      head[0] = nck;
+      const uint32_t hdr = nck + 2;
+      for (uint32_t i = 1; i <= nck; i++) head[i] += hdr;
+      head.push_back(hdr + (uint32_t)body.size());
+      std::vector<uint32_t> &w = per[(size_t)st];
+      w = head;
+      w.insert(w.end(), body.begin(), body.end());
+    }
+  });
+  strip_off.assign((size_t)nstrip + 1, 0);
+  size_t total = 0;
+  for (int st = 0; st < nstrip; st++) {
+    strip_off[(size_t)st] = (uint32_t)total;
+    total += per[(size_t)st].size();
+  }
+  strip_off[(size_t)nstrip] = (uint32_t)total;
+  sched.resize(total);
+  for (int st = 0; st < nstrip; st++) std::copy(per[(size_t)st].begin(), per[(size_t)st].end(), sched.begin() + strip_off[(size_t)st]);
+}
+
+// Decode schedule of the colour whole-field kernel, which writes each pixel
+// as 8-bit RGB and so needs a pixel's three channels in one workgroup: a
+// strip (block row by, strip sx of 64/B blocks) covers all three channels,
+// and its chunks count the stored blocks of the three channels against the
+// tile capacity.  Otherwise as build_schedule:
+//   strip record: [0] chunks, [1..chunks] chunk record offsets from the
+//   strip's start, [chunks+1] the strip's length;
+//   chunk record: q0, nq, nn, n0, n01, n, masks[3][nn] (channel-major),
+//   first slots[3][nn] (16-bit, two per word), runs[nq][3 words],
+//   entries[n], items[n] (32-bit: slot << 20 | node << 8 | channel << 6 |
+//   block; a chunk has at most kRGBNodeCap nodes).
+static void build_schedule_rgb(const Geometry &g, const std::vector<uint32_t> &off, const std::vector<uint32_t> &srv,
+                               const std::vector<uint32_t> &dbase, const std::vector<uint32_t> &poff,
+                               const std::vector<int32_t> &batch, std::vector<uint32_t> &sched,
+                               std::vector<uint32_t> &strip_off, int cap) {
+  const int nblk = 64 / g.B, nsx = (g.nbx + nblk - 1) / nblk, nstrip = g.nby * nsx;
+  const int nruns = (int)(batch.size() / kBatchWords), L = g.L;
+  const size_t ns = (size_t)std::max(g.n_srv, 1);
+  std::vector<std::vector<uint32_t>> per((size_t)nstrip);
+  parallel_for(nstrip, 8, [&](int64_t a, int64_t e) {
+    std::vector<uint32_t> m(3 * ns);   // [channel][node] stored-block mask of the strip
+    std::vector<int> loc(ns, -1);
+    for (int64_t st = a; st < e; st++) {
+      const int sx = (int)(st % nsx), by = (int)(st / nsx);
+      std::fill(m.begin(), m.end(), 0u);
+      for (int c = 0; c < 3; c++)
+        for (int jj = 0; jj < nblk; jj++) {
+          const int bx = sx * nblk + jj;
+          if (bx >= g.nbx) continue;
+          const size_t gi = 3 * ((size_t)by * g.nbx + bx) + c;
+          if (off[gi] == off[gi + 1]) continue;
+          for (int w = 0; w < g.nbw; w++)
+            for (uint32_t bm = srv[off[gi] + w]; bm; bm &= bm - 1)
+              m[c * ns + (size_t)w * 32 + __builtin_ctz(bm)] |= 1u << jj;
+        }
+      auto stored = [&](int s) {
+        return __builtin_popcount(m[(size_t)s]) + __builtin_popcount(m[ns + (size_t)s]) +
+               __builtin_popcount(m[2 * ns + (size_t)s]);
+      };
+      std::vector<uint32_t> head(1, 0), body;
+      for (int q = 0; q < nruns;) {
+        // greedy: consecutive runs while their nodes' stored blocks fit the tile
+        std::vector<int> leaves, ancs;
+        int count = 0, k = 0;
+        while (q + k < nruns) {
+          const int32_t *r = &batch[(size_t)(q + k) * kBatchWords];
+          int add = 0;
+          std::vector<int> nl, na;
+          for (int i = 0; i < r[0] && L > 1; i++) {
+            const int s = r[10] + i;
+            if (loc[(size_t)s] < 0) {
+              nl.push_back(s);
+              add += stored(s);
+            }
+          }
+          for (int i = 0; i < L - 2; i++) {
+            const int s = r[6 + i];
+            if (loc[(size_t)s] < 0 && std::find(na.begin(), na.end(), s) == na.end()) {
+              na.push_back(s);
+              add += stored(s);
+            }
+          }
+          if (k > 0 && (count + add > cap || leaves.size() + ancs.size() + nl.size() + na.size() > (size_t)kRGBNodeCap))
+            break;
+          for (int s : nl) {
+            loc[(size_t)s] = 0;
+            leaves.push_back(s);
+          }
+          for (int s : na) {
+            loc[(size_t)s] = 0;
+            ancs.push_back(s);
+          }
+          count += add;
+          k++;
+        }
+        std::vector<int> nodes(leaves);
+        nodes.insert(nodes.end(), ancs.begin(), ancs.end());
+        for (size_t i = 0; i < nodes.size(); i++) loc[(size_t)nodes[i]] = (int)i;
+        const int nn = (int)nodes.size();
+        std::vector<uint32_t> masks(3 * (size_t)nn), bases(3 * (size_t)nn);
+        uint32_t slot = 0;
+        for (int c = 0; c < 3; c++)
+          for (int i = 0; i < nn; i++) {
+            masks[(size_t)c * nn + i] = m[c * ns + (size_t)nodes[(size_t)i]];
+            bases[(size_t)c * nn + i] = slot;
+            slot += (uint32_t)__builtin_popcount(masks[(size_t)c * nn + i]);
+          }
+        std::vector<uint32_t> ent[3], item[3];
+        for (int c = 0; c < 3; c++)
+          for (int i = 0; i < nn; i++) {
+            const int s = nodes[(size_t)i];
+            const uint32_t mk = masks[(size_t)c * nn + i];
+            for (uint32_t bits = mk; bits; bits &= bits - 1) {
+              const int jj = __builtin_ctz(bits);
+              const size_t gi = 3 * ((size_t)by * g.nbx + sx * nblk + jj) + c;
+              const uint32_t bm = srv[off[gi] + (s >> 5)], bit = (uint32_t)s & 31u;
+              const uint32_t en =
+                  poff[dbase[gi * g.nbw + (s >> 5)] + (uint32_t)__builtin_popcount(bm & ((1u << bit) - 1u))];
+              const uint32_t code = en & 31u;
+              const int kind = code < 12 ? 0 : (code < 19 ? 1 : 2);
+              const uint32_t sl = bases[(size_t)c * nn + i] + (uint32_t)__builtin_popcount(mk & ((1u << jj) - 1u));
+              ent[kind].push_back(en);
+              item[kind].push_back((sl << 20) | ((uint32_t)i << 8) | ((uint32_t)c << 6) | (uint32_t)jj);
+            }
+          }
+        const uint32_t n0 = (uint32_t)ent[0].size(), n01 = n0 + (uint32_t)ent[1].size();
+        const uint32_t n = n01 + (uint32_t)ent[2].size();
+        head.push_back((uint32_t)body.size());   // made absolute below
+        body.push_back((uint32_t)q);
+        body.push_back((uint32_t)k);
+        body.push_back((uint32_t)nn);
+        body.push_back(n0);
+        body.push_back(n01);
+        body.push_back(n);
+        body.insert(body.end(), masks.begin(), masks.end());
+        for (int i = 0; i < 3 * nn; i += 2)
+          body.push_back(bases[(size_t)i] | (i + 1 < 3 * nn ? bases[(size_t)i + 1] << 16 : 0u));
+        for (int j = 0; j < k; j++) {
+          const int32_t *r = &batch[(size_t)(q + j) * kBatchWords];
+          uint32_t h[4] = {L > 1 ? (uint32_t)loc[(size_t)r[10]] : 0xFFFFu, 0xFFFFu, 0xFFFFu, 0xFFFFu};
+          for (int i = 0; i < std::min(L - 2, 3); i++) h[1 + i] = (uint32_t)loc[(size_t)r[6 + i]];
+          body.push_back(h[0] | (h[1] << 16));
+          body.push_back(h[2] | (h[3] << 16));
+          body.push_back(L - 2 > 3 ? (uint32_t)loc[(size_t)r[9]] | 0xFFFF0000u : 0xFFFFFFFFu);
+        }
+        for (int kind = 0; kind < 3; kind++) body.insert(body.end(), ent[kind].begin(), ent[kind].end());
+        for (int kind = 0; kind < 3; kind++) body.insert(body.end(), item[kind].begin(), item[kind].end());
         for (int s : nodes) loc[(size_t)s] = -1;
         q += k;
       }
@@ -395,6 +546,33 @@ static void make_strip_tables(const Geometry &g, const std::vector<uint32_t> &of
     t.need[2 * st] = (uint32_t)std::min<uint64_t>(w, 1u << 30);
     t.need[2 * st + 1] = (uint32_t)sw;
     t.max_words = std::max(t.max_words, t.need[2 * st]);
+  }
+  t.order.resize(nst);
+  for (size_t i = 0; i < nst; i++) t.order[i] = (uint32_t)i;
+  std::stable_sort(t.order.begin(), t.order.end(), [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
+}
+
+// The colour kernel's strip tables: schedule and the order in which
+// workgroups take the strips (costliest first: schedule words plus the
+// strip's group words of all three channels).
+static void make_strip_tables_rgb(const Geometry &g, const std::vector<uint32_t> &off, const std::vector<uint32_t> &srv,
+                                  const std::vector<uint32_t> &dbase, const std::vector<uint32_t> &poff,
+                                  const std::vector<int32_t> &batch, int cap, StripTables &t) {
+  build_schedule_rgb(g, off, srv, dbase, poff, batch, t.sched, t.strip_off, cap);
+  const int nblk = 64 / g.B, nsx = (g.nbx + nblk - 1) / nblk;
+  const size_t nst = t.strip_off.size() - 1;
+  std::vector<uint64_t> cost(nst);
+  t.need.clear();
+  t.max_words = 0;
+  for (size_t st = 0; st < nst; st++) {
+    const int sx = (int)(st % nsx), by = (int)(st / nsx);
+    uint64_t w = t.strip_off[st + 1] - t.strip_off[st];
+    for (int bx = sx * nblk; bx < std::min(sx * nblk + nblk, g.nbx); bx++)
+      for (int c = 0; c < 3; c++) {
+        const size_t gi = 3 * ((size_t)by * g.nbx + bx) + c;
+        w += off[gi + 1] - off[gi];
+      }
+    cost[st] = w;
   }
   t.order.resize(nst);
   for (size_t i = 0; i < nst; i++) t.order[i] = (uint32_t)i;
@@ -1296,7 +1474,16 @@ extern "C" lfc_status lfc_open_ex(const void *stream, size_t bytes, const lfc_op
     return fail(LFC_E_NOMEM, "lfc_open: out of host memory");
   }
   const std::vector<uint32_t> &sched = stt.sched, &strip_off = stt.strip_off, &order = stt.order;
-  Part parts[13] = {
+  // the colour kernel's strip tables (tile of the default capacity, which
+  // holds a run of kBatch leaves and four ancestors in all three channels)
+  const int tile_cap_rgb = tile_blocks(ps.g.B);
+  StripTables rgbt;
+  try {
+    make_strip_tables_rgb(ps.g, ps.off, ps.srv, ps.dbase, ps.poff, tt.batch, tile_cap_rgb, rgbt);
+  } catch (const std::bad_alloc &) {
+    return fail(LFC_E_NOMEM, "lfc_open: out of host memory");
+  }
+  Part parts[16] = {
       {ps.rkv, ps.rkv_bytes, 0},
       {ps.off.data(), ps.off.size() * 4, 0},
       {ps.srv.data(), ps.srv.size() * 4, 0},
@@ -1310,6 +1497,9 @@ extern "C" lfc_status lfc_open_ex(const void *stream, size_t bytes, const lfc_op
       {sched.data(), sched.size() * 4, 0},
       {strip_off.data(), strip_off.size() * 4, 0},
       {order.data(), order.size() * 4, 0},
+      {rgbt.sched.data(), rgbt.sched.size() * 4, 0},
+      {rgbt.strip_off.data(), rgbt.strip_off.size() * 4, 0},
+      {rgbt.order.data(), rgbt.order.size() * 4, 0},
   };
   size_t total = 0;
   for (auto &pt : parts) {
@@ -1362,6 +1552,12 @@ extern "C" lfc_status lfc_open_ex(const void *stream, size_t bytes, const lfc_op
   lf->d_sched = reinterpret_cast<const uint32_t *>(d + parts[10].at);
   lf->d_strip_off = reinterpret_cast<const uint32_t *>(d + parts[11].at);
   lf->d_order = reinterpret_cast<const uint32_t *>(d + parts[12].at);
+  lf->d_sched_rgb = reinterpret_cast<const uint32_t *>(d + parts[13].at);
+  lf->d_strip_off_rgb = reinterpret_cast<const uint32_t *>(d + parts[14].at);
+  lf->d_order_rgb = reinterpret_cast<const uint32_t *>(d + parts[15].at);
+  lf->tile_cap_rgb = tile_cap_rgb;
+  for (size_t st = 0; st + 1 < rgbt.strip_off.size(); st++)
+    lf->rgb_max_chunks = std::max<int>(lf->rgb_max_chunks, (int)rgbt.sched[rgbt.strip_off[st]]);
   lf->d_err = reinterpret_cast<int32_t *>(d + parts[8].at);
   // LDS staging of the whole-field kernel is sized by the largest strip:
   // group words plus the strip's decode schedule
@@ -1427,7 +1623,7 @@ extern "C" lfc_status lfc_tune_decode(lfc_lf *lf, int16_t *d_out, int32_t reps, 
     if (e0) (void)hipEventDestroy(e0);
     return fail(LFC_E_HIP, "lfc_tune_decode: events");
   }
-  // time the current tables
+  // time the current tables with the handle's current staging
   auto timed = [&](float *ms) -> lfc_status {
     lfc_status st = lfc_decode_blocks(lf, nullptr, nv, LFC_LAYOUT_IMAGES, d_out, s);
     if (st != LFC_OK) return st;
@@ -1461,15 +1657,26 @@ extern "C" lfc_status lfc_tune_decode(lfc_lf *lf, int16_t *d_out, int32_t reps, 
     lf->d_sched_own = v.own;
   };
   std::vector<Saved> cands;
+  std::vector<int> tried_cand;        // per result: the table set it was timed with
+  const int64_t stage0 = lf->stage_cap;
   lfc_status st = LFC_OK;
   float ms = 0.0f;
+  // the current table set with and without staging
+  auto time_both = [&](int cand) -> lfc_status {
+    for (int staged = 0; staged < 2 && res->n_tried < LFC_TUNE_DECODE_MAX; staged++) {
+      lf->stage_cap = staged ? -1 : 0;
+      const lfc_status ts = timed(&ms);
+      if (ts != LFC_OK) return ts;
+      const int k = res->n_tried++;
+      res->tile_blocks[k] = lf->tile_cap;
+      res->staged[k] = staged;
+      res->ms[k] = ms;
+      tried_cand.push_back(cand);
+    }
+    return LFC_OK;
+  };
   cands.push_back(save());
-  st = timed(&ms);
-  if (st == LFC_OK) {
-    res->tile_blocks[0] = lf->tile_cap;
-    res->ms[0] = ms;
-    res->n_tried = 1;
-  }
+  st = time_both(0);
   try {
     // host copies of what the strip tables are built from
     std::vector<uint32_t> off, srv, dbase, poff;
@@ -1520,11 +1727,14 @@ extern "C" lfc_status lfc_tune_decode(lfc_lf *lf, int16_t *d_out, int32_t reps, 
       lf->max_strip_words = t.max_words;
       lf->d_sched_own = buf;
       cands.push_back(save());
-      lfc_status ts = timed(&ms);
+      const int n_before = res->n_tried;
+      lfc_status ts = time_both((int)cands.size() - 1);
       if (ts == LFC_E_UNSUPPORTED) {   // the tile does not fit the LDS: not a candidate
         (void)hipGetLastError();
         (void)hipFree(buf);
         cands.pop_back();
+        res->n_tried = n_before;
+        tried_cand.resize((size_t)n_before);
         restore(cands[0]);
         continue;
       }
@@ -1532,29 +1742,29 @@ extern "C" lfc_status lfc_tune_decode(lfc_lf *lf, int16_t *d_out, int32_t reps, 
         st = ts;
         break;
       }
-      const int k = res->n_tried++;
-      res->tile_blocks[k] = cap;
-      res->ms[k] = ms;
     }
   } catch (const std::bad_alloc &) {
     st = fail(LFC_E_NOMEM, "lfc_tune_decode: out of host memory");
   }
   (void)hipStreamSynchronize(s);
-  if (st != LFC_OK) {
-    // back to the tables the handle had; free every set built here
+  if (st != LFC_OK || res->n_tried == 0) {
+    // back to the tables and staging the handle had; free every set built here
     for (size_t k = 1; k < cands.size(); k++)
       if (cands[k].own) (void)hipFree(cands[k].own);
     restore(cands[0]);
+    lf->stage_cap = stage0;
   } else {
-    // keep the fastest; free the others (and an earlier tuning's tables if replaced)
+    // keep the fastest; free the other table sets (and an earlier tuning's tables if replaced)
     int best = 0;
     for (int k = 1; k < res->n_tried; k++)
       if (res->ms[k] < res->ms[best]) best = k;
     res->best = best;
+    const size_t keep = (size_t)tried_cand[(size_t)best];
     for (size_t k = 1; k < cands.size(); k++)
-      if ((int)k != best && cands[k].own) (void)hipFree(cands[k].own);
-    if (best != 0 && cands[0].own) (void)hipFree(cands[0].own);
-    restore(cands[(size_t)best]);
+      if (k != keep && cands[k].own) (void)hipFree(cands[k].own);
+    if (keep != 0 && cands[0].own) (void)hipFree(cands[0].own);
+    restore(cands[keep]);
+    lf->stage_cap = res->staged[best] ? -1 : 0;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

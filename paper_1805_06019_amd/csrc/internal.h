@@ -42,6 +42,9 @@ constexpr int kBatchWords = 16;
 // compact tile (32 KB of LDS; tile slots are 11-bit, beside a 5-bit block
 // index in 16-bit schedule items, so at most 2048).
 constexpr int tile_blocks(int B) { return B == 2 ? 2048 : (B == 4 ? 1024 : 256); }
+// Most tree nodes in one chunk of the colour whole-field kernel's schedule
+// (the kernel copies a chunk's per-node tables into LDS).
+constexpr int kRGBNodeCap = 128;
 struct TreeTables {
   std::vector<int32_t> path, root, batch;
   std::vector<std::vector<int32_t>> serial;  // [level][node id] -> BFS index (-1 on top)
@@ -83,8 +86,15 @@ struct lfc_lf {
   const uint32_t *d_sched = nullptr;     // decode schedule of the whole-field kernel (strip records)
   const uint32_t *d_strip_off = nullptr; // [n_strips+1] word offset of each strip's record
   const uint32_t *d_order = nullptr;     // [n_strips] strips in the order the whole-field kernel takes them
+  const uint32_t *d_sched_rgb = nullptr;     // colour decode schedule (strips of all three channels)
+  const uint32_t *d_strip_off_rgb = nullptr; // [n_strips_rgb+1]
+  const uint32_t *d_order_rgb = nullptr;     // [n_strips_rgb] costliest first
+  int tile_cap_rgb = 0;              // blocks of the colour kernel's compact tile
+  int rgb_max_chunks = 1;            // most chunks of one strip in the colour schedule
   int32_t *d_err = nullptr;          // device error flag
   int tile_cap = 0;                  // blocks of the whole-field kernel's compact residual tile
+  int64_t stage_cap = 0;             // LDS words for staging a strip (-1: as it needs, 0: none); the
+                                     // setting used when a decode call gives none
   void *d_sched_own = nullptr;       // strip tables chosen by lfc_tune_decode (else inside d_base)
   uint32_t max_strip_words = 0;      // largest group words + decode schedule of a strip of 64/B blocks of
                                      // one channel

@@ -372,6 +372,15 @@ __device__ __forceinline__ void lds_copy(uint32_t *dst, const uint32_t *src, uin
                                        (__attribute__((address_space(3))) void *)(dst + i0), 4, 0, 0);
 }
 
+// A workgroup barrier for data exchanged through LDS only: this wave's LDS
+// operations complete before it, but its global stores stay in flight (a
+// __syncthreads() would also wait for every outstanding store of the wave,
+// and the whole-field kernel's stores need not be visible to other waves).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0); vmcnt and expcnt not waited on
+  __builtin_amdgcn_s_barrier();
+}
+
 // Tables that every lane of a wave reads at the same address (tree runs,
 // chunk records) are read through the scalar unit: a vector load would make
 // the wave wait for all of its outstanding stores as well.
@@ -420,7 +429,7 @@ __device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, c
       *reinterpret_cast<uint2 *>(dst) = make_uint2(d[0], d[1]);
     }
   }
-  __syncthreads();
+  lds_barrier();
   // (4) gather and store.  A wave takes two runs at a time, one per half; a
   // lane owns one sibling of its run and one 16-byte segment (PB blocks) of
   // the strip's rows, and walks the B rows of its blocks: each node's tile
@@ -532,7 +541,7 @@ __device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, c
     }
   }
   __builtin_amdgcn_s_setprio(0);
-  __syncthreads();
+  lds_barrier();
 }
 
 // One workgroup = one channel c, one row of blocks by, one strip of 64/B
@@ -841,6 +850,9 @@ __device__ __forceinline__ uint32_t locate(const RAArgs &a, int g, int s, const 
   return a.poff[a.dbase[(size_t)g * a.nbw + (s >> 5)] + __popc(bm & ((1u << bit) - 1u))];
 }
 
+// Threads of a render-tile workgroup.
+constexpr int kRenderThreads = 256;
+
 // One workgroup per (view, output tile).  The tile's source footprint in the
 // four nearest views is reconstructed in LDS: first the key-view rows, then,
 // level by level, every distinct stored residual block of the footprint is
@@ -907,7 +919,7 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const lfc_view 
   uint16_t *lut = reinterpret_cast<uint16_t *>(smem);
   uint32_t *acc = smem + kLutEntries / 2;       // [4][fbx_max*fby_max][SLOT]
   const int tid = threadIdx.x;
-  for (int t = tid; t < kLutEntries; t += kThreads) lut[t] = lut_entry(t);
+  for (int t = tid; t < kLutEntries; t += kRenderThreads) lut[t] = lut_entry(t);
   int iu0, iu1, jv0, jv1;
   float fu, fv;
   cell(vw.u, a.U, iu0, iu1, fu);
@@ -947,7 +959,7 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const lfc_view 
   __syncthreads();
 
   // (1) key-view rows: item = (view k, block, channel, row)
-  for (int it = tid; it < 4 * FBmax * 3 * B; it += kThreads) {
+  for (int it = tid; it < 4 * FBmax * 3 * B; it += kRenderThreads) {
     const int y = it % B, r1 = it / B, c = r1 % 3, r2 = r1 / 3, bb = r2 % FBmax, k = r2 / FBmax;
     if (bb >= FB[k]) continue;
     const int b = (fby0[k] + bb / FBX[k]) * a.ra.nbx + fbx0[k] + bb % FBX[k];
@@ -973,7 +985,7 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const lfc_view 
         for (int k2 = k - 1; k2 >= 0; --k2)
           if (node[k2] == node[k]) owner[k] = k2;
     }
-    for (int it = tid; it < 4 * FBmax * 3; it += kThreads) {
+    for (int it = tid; it < 4 * FBmax * 3; it += kRenderThreads) {
       const int c = it % 3, r1 = it / 3, bb = r1 % FBmax, k = r1 / FBmax;
       if (owner[k] != k || bb >= FB[k]) continue;
       const int b = (fby0[k] + bb / FBX[k]) * a.ra.nbx + fbx0[k] + bb % FBX[k];
@@ -994,7 +1006,7 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const lfc_view 
   }
 
   // (3) YCoCg-R -> RGB in place: item = (view, block)
-  for (int it = tid; it < 4 * FBmax; it += kThreads) {
+  for (int it = tid; it < 4 * FBmax; it += kRenderThreads) {
     const int k = it / FBmax, bb = it % FBmax;
     if (bb >= FB[k]) continue;
     uint32_t *slot = acc + (k * FBM + bb) * SLOT;
@@ -1013,7 +1025,7 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const lfc_view 
 
   // (4) quadrilinear interpolation of every output pixel of the tile
   const size_t plane = (size_t)a.ho * a.wo;
-  for (int p = tid; p < a.TX * a.TY; p += kThreads) {
+  for (int p = tid; p < a.TX * a.TY; p += kRenderThreads) {
     const int X = tx0 + p % a.TX, Yp = ty0 + p / a.TX;
     if (X >= a.wo || Yp >= a.ho) continue;
     const float sx = src_pos(vw.s, X, sxs), ty = src_pos(vw.t, Yp, tys);
@@ -1038,55 +1050,8 @@ __device__ __forceinline__ void render_tile(const RenderArgs &a, const lfc_view 
   }
 }
 
-// Novel views from fully decoded source views (images layout, int16
-// YCoCg-R [nv][3][hp][wp]): one thread per output pixel, its 16 taps read
-// straight from the decoded planes, the same colour conversion and lerps as
-// render_tile.  Used when a batch of views needs about as many source blocks
-// as the whole light field holds.
-struct InterpArgs {
-  const int16_t *dec;
-  const lfc_view *views;
-  float *out;
-  int wo, ho, U, V, W, H, wp, hp;
-  float disp;   // focal disparity (as RenderArgs)
-};
-
-template <bool FOCAL>
-__global__ __launch_bounds__(kThreads) void k_interp(InterpArgs a) {
-  // grid (row pieces, view, row): the workgroups that run together render one
-  // output row of every view, whose taps come from nearby rows of the same
-  // few source views, so the caches serve those rows once for all views
-  const int X = blockIdx.x * kThreads + threadIdx.x, n = blockIdx.y, Yp = blockIdx.z;
-  if (X >= a.wo) return;
-  const lfc_view vw = a.views[n];
-  int iu0, iu1, jv0, jv1, x0, x1, y0, y1;
-  float fu, fv;
-  cell(vw.u, a.U, iu0, iu1, fu);
-  cell(vw.v, a.V, jv0, jv1, fv);
-  const float sxs = (float)a.W / (float)a.wo, tys = (float)a.H / (float)a.ho;
-  const float sx = src_pos(vw.s, X, sxs), ty = src_pos(vw.t, Yp, tys);
-  const int vis[4] = {jv0 * a.U + iu0, jv0 * a.U + iu1, jv1 * a.U + iu0, jv1 * a.U + iu1};
-  const size_t cplane = (size_t)a.hp * a.wp;
-  uint32_t P[4][4];
-  float fs[4], ft[4];
-#pragma unroll
-  for (int k = 0; k < 4; k++) {
-    cell(sx + focal_shift<FOCAL>(a.disp, vw.u, a.U, (k & 1) ? iu1 : iu0), a.W, x0, x1, fs[k]);
-    cell(ty + focal_shift<FOCAL>(a.disp, vw.v, a.V, (k & 2) ? jv1 : jv0), a.H, y0, y1, ft[k]);
-    const size_t o00 = (size_t)y0 * a.wp + x0, o01 = (size_t)y0 * a.wp + x1;
-    const size_t o10 = (size_t)y1 * a.wp + x0, o11 = (size_t)y1 * a.wp + x1;
-    const int16_t *yp = a.dec + (size_t)vis[k] * 3 * cplane, *cop = yp + cplane, *cgp = cop + cplane;
-    P[k][0] = rgb_pack(yp[o00], cop[o00], cgp[o00]);
-    P[k][1] = rgb_pack(yp[o01], cop[o01], cgp[o01]);
-    P[k][2] = rgb_pack(yp[o10], cop[o10], cgp[o10]);
-    P[k][3] = rgb_pack(yp[o11], cop[o11], cgp[o11]);
-  }
-  const size_t plane = (size_t)a.ho * a.wo;
-  interp_store(P, fs, ft, fu, fv, a.out + (size_t)n * 3 * plane + (size_t)Yp * a.wo + X, plane);
-}
-
 template <int B, bool FOCAL>
-__global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
+__global__ __launch_bounds__(kRenderThreads) void k_render(RenderArgs a) {
   extern __shared__ uint32_t smem[];
   const int n = blockIdx.z;
   render_tile<B, FOCAL>(a, a.views[n], a.out + (size_t)n * 3 * a.ho * a.wo, blockIdx.x, blockIdx.y, smem);
@@ -1102,7 +1067,7 @@ struct RenderReq {
 };
 
 template <int B>
-__global__ __launch_bounds__(kThreads) void k_render_multi(const RenderReq *reqs) {
+__global__ __launch_bounds__(kRenderThreads) void k_render_multi(const RenderReq *reqs) {
   extern __shared__ uint32_t smem[];
   // one read of the record, at the start: every wave then works from the
   // same copy, however late it uses a field
@@ -1110,6 +1075,337 @@ __global__ __launch_bounds__(kThreads) void k_render_multi(const RenderReq *reqs
   const int t = blockIdx.x;
   if (t >= r.ntiles) return;
   render_tile<B, false>(r.a, r.view, r.a.out, t % r.ntx, t / r.ntx, smem);
+}
+
+// ---------------------------------------------------------------------------
+// whole light field as 8-bit RGB (the decode-then-interpolate render's input)
+// ---------------------------------------------------------------------------
+
+// LDS words before the tile: LUT; the start words of the strip's 3 x 64/B
+// groups; a flag and a bit per node of the chunk for the views a render
+// reads; the view mask; the chunk's per-node masks and first slots (a chunk
+// has at most lfc::kRGBNodeCap nodes).
+using lfc::kRGBNodeCap;
+constexpr int kRGBNeedWords = 128;        // views a render may mask: at most 32 x 128
+constexpr int kRGBHeadWords = 192 + 96 + 4 + kRGBNodeCap / 32 + kRGBNeedWords + 3 * kRGBNodeCap + 3 * kRGBNodeCap / 2;
+constexpr int kRGBKeyWordsMax = 6144;     // key-view rows of a strip staged in LDS up to 24 KB
+
+struct RGBArgs {
+  const int16_t *rkv;
+  const uint32_t *off;
+  const uint32_t *srv;
+  const uint32_t *sched;      // colour decode schedule: one record per strip (build_schedule_rgb on the host)
+  const uint32_t *strip_off;  // [n_strips+1]
+  const uint32_t *order;      // [n_strips] strip of each workgroup, costliest first
+  const int32_t *batch;       // [nbatch][kBatchWords] runs of sibling leaves
+  const uint32_t *vneed;      // [ceil(nv/32)] bit per view to write (nv <= 32 kRGBNeedWords), or null: every view
+  uint32_t *out;              // [nv][hp][wp] pixels R | G << 8 | B << 16
+  int nbx, nsx, L, q, wp, hp, nb, nbatch, nv;
+  int n_top, key_words;       // LDS words of the strip's key-view rows of all channels (0: read from global)
+  int tile_cap;
+  int parts;                  // workgroups per strip: part p takes the chunks ci with ci % parts == p
+};
+
+// One workgroup = one strip of 64/B blocks of one block row, all three
+// channels, or every parts-th chunk of it (a strip of three channels holds
+// three times the blocks of a one-channel strip, so strips alone would not
+// fill the chip).  Phase A stages the LUT, the strip's group starts, the
+// view mask and the key-view rows; the groups and the decode schedule are
+// read from global memory.  Per chunk of the strip's runs: its node masks
+// and first slots are copied to LDS while (3) every stored residual block of
+// the chunk, of any channel (with a view mask: of a node that a wanted view
+// reads), is decoded once into the compact tile; then (4) one run per wave:
+// a lane owns one sibling and 4 pixels of the strip's rows, sums key row +
+// ancestor rows + leaf row of each channel, converts the pixels to RGB
+// (inverse YCoCg-R, clamped) and stores 16 bytes per row.
+template <int B, bool KEYS>
+__global__ __launch_bounds__(kLFThreads) void k_decode_rgb(RGBArgs a) {
+  constexpr int S = B * B, NBLK = 64 / B, H = B / 2, HR = B;   // HR rows per lane
+  extern __shared__ uint32_t smem[];
+  uint16_t *lut = reinterpret_cast<uint16_t *>(smem);   // 384 x u16 = 192 words
+  uint32_t *s_o0 = smem + 192;                          // [3][NBLK] group start words
+  uint32_t *s_any = smem + 288;                         // a wanted view in the chunk
+  uint32_t *s_node = s_any + 4;                         // wanted nodes of the chunk, a bit each
+  uint32_t *s_need = s_node + kRGBNodeCap / 32;         // the view mask
+  uint32_t *s_mf = s_need + kRGBNeedWords;              // masks[3][nn], then first slots (16-bit)
+  uint32_t *tile = smem + kRGBHeadWords;                // [tile_cap + 1][S/2], the last slot zero
+  uint32_t *keys = tile + lf_tile_words(a.tile_cap, S); // [3][n_top][B][NBLK * H]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int st = (int)a.order[blockIdx.x / a.parts], part = blockIdx.x % a.parts;
+  const int sx = st % a.nsx, by = st / a.nsx;
+  const bool masked = a.vneed != nullptr;
+  for (int t = tid; t < kLutEntries; t += kLFThreads) lut[t] = lut_entry(t);
+  if (tid < S / 2) tile[a.tile_cap * (S / 2) + tid] = 0u;
+  if (tid < 64)
+    for (int k = lane; k < 3 * NBLK; k += 64) {
+      const int c = k / NBLK, bx = sx * NBLK + k % NBLK;
+      s_o0[k] = bx < a.nbx ? a.off[3 * (by * a.nbx + bx) + c] : 0u;
+    }
+  if (masked)
+    for (int w = tid; w < (a.nv + 31) / 32; w += kLFThreads) s_need[w] = a.vneed[w];
+  if constexpr (KEYS) {
+    const uint32_t *rk = reinterpret_cast<const uint32_t *>(a.rkv);
+    for (int t0 = wave * 64; t0 < a.key_words; t0 += kLFThreads) {
+      const int t = t0 + lane, h = t % H, j = (t / H) % NBLK, y = (t / (H * NBLK)) % B;
+      const int r = (t / (H * NBLK * B)) % a.n_top, c = t / (H * NBLK * B * a.n_top);
+      const int bx = sx * NBLK + j;
+      if (t < a.key_words && bx < a.nbx)
+        __builtin_amdgcn_global_load_lds(
+            (const __attribute__((address_space(1))) void *)(rk + ((size_t)(r * a.nb + by * a.nbx + bx) * 3 + c) *
+                                                                  (S / 2) + y * H + h),
+            (__attribute__((address_space(3))) void *)(keys + t0), 4, 0, 0);
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+
+  // gather lane mapping: sibling so, 4-pixel segment jseg (word pairs pp = 2 jseg, 2 jseg + 1 of
+  // the strip's 32-word rows); the block and the word inside its row of each pair
+  const int so = lane >> 4, jseg = lane & 15;
+  int jb[2], wib[2];
+#pragma unroll
+  for (int w = 0; w < 2; w++) {
+    const int pp = 2 * jseg + w;
+    jb[w] = (2 * pp) / B;
+    wib[w] = ((2 * pp) % B) / 2;
+  }
+  const int px0 = sx * 64 + 4 * jseg;                   // first pixel of the segment
+  const bool seg_in = sx * NBLK + jb[0] < a.nbx;        // the segment's first block is inside the image
+  const bool wide = seg_in && (a.wp % 4 == 0);          // all 4 pixels inside, 16-byte aligned
+  const uint32_t zslot = (uint32_t)a.tile_cap;
+  const uint32_t vplane = (uint32_t)a.hp * (uint32_t)a.wp;
+  auto wanted_view = [&](int vi) { return !masked || ((s_need[vi >> 5] >> (vi & 31)) & 1u); };
+  const uint32_t *gs = a.sched + a.strip_off[st];
+  const int nck = __builtin_amdgcn_readfirstlane((int)gs[0]);
+  for (int ci = part; ci < nck; ci += a.parts) {
+    const uint32_t *chunk = gs + gs[1 + ci];
+    const uniform_i32 sch = as_uniform(reinterpret_cast<const int32_t *>(chunk));
+    const int q0 = sch[0], nq = sch[1], nn = sch[2];
+    const uint32_t n0 = (uint32_t)sch[3], n01 = (uint32_t)sch[4], n = (uint32_t)sch[5];
+    const int mf_words = 3 * nn + (3 * nn + 1) / 2;
+    const uniform_i32 runs = sch + 6 + mf_words;
+    const uint32_t *ents = chunk + 6 + mf_words + 3 * nq;
+    const uint32_t *items = ents + n;
+    // with a view mask: the chunk's nodes that a wanted view reads (its leaf
+    // and the ancestors of its run); a chunk with none is skipped whole
+    if (masked) {
+      for (int w = tid; w < kRGBNodeCap / 32; w += kLFThreads) s_node[w] = 0u;
+      if (tid == 0) *s_any = 0u;
+      __syncthreads();
+      for (int qi = wave; qi < nq; qi += kLFWaves) {
+        const uniform_i32 rec = as_uniform(a.batch + (size_t)(q0 + qi) * lfc::kBatchWords);
+        const int nsib = rec[0];
+        bool wanted[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) wanted[k] = k < nsib && wanted_view(max(rec[1 + k], 0));
+        if (!(wanted[0] || wanted[1] || wanted[2] || wanted[3])) continue;
+        const uint32_t w0 = (uint32_t)runs[3 * qi], w1 = (uint32_t)runs[3 * qi + 1], w2 = (uint32_t)runs[3 * qi + 2];
+        const int anc_ln[4] = {(int)(w0 >> 16), (int)(w1 & 0xFFFFu), (int)(w1 >> 16), (int)(w2 & 0xFFFFu)};
+        int ln = -1;
+        if (lane < 4 && a.L > 1 && (lane == 0 ? wanted[0] : (lane == 1 ? wanted[1] : (lane == 2 ? wanted[2] : wanted[3]))))
+          ln = (int)(w0 & 0xFFFFu) + lane;
+        else if (lane >= 4 && lane < 8 && lane - 4 < a.L - 2)
+          ln = lane == 4 ? anc_ln[0] : (lane == 5 ? anc_ln[1] : (lane == 6 ? anc_ln[2] : anc_ln[3]));
+        if (ln >= 0) atomicOr(&s_node[ln >> 5], 1u << (ln & 31));
+        if (lane == 0) *s_any = 1u;
+      }
+      __syncthreads();
+      if (*s_any == 0u) {
+        __syncthreads();   // every wave has read the flag before the next chunk clears it
+        continue;
+      }
+    }
+    // the chunk's node masks and first slots into LDS, in flight during the decode
+    for (int w0 = wave * 64; w0 < mf_words; w0 += kLFThreads)
+      if (w0 + lane < mf_words)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(chunk + 6 + w0 + lane),
+                                         (__attribute__((address_space(3))) void *)(s_mf + w0), 4, 0, 0);
+    // (3) decode every stored block of the chunk (that a wanted view reads) into its tile slot
+    for (uint32_t it = tid; it < n; it += kLFThreads) {
+      const uint32_t e = ents[it], t = items[it];
+      if (masked) {
+        const uint32_t ln = (t >> 8) & 4095u;
+        if (!((s_node[ln >> 5] >> (ln & 31u)) & 1u)) continue;
+      }
+      const uint32_t *gw = a.srv + s_o0[((t >> 6) & 3u) * NBLK + (t & 63u)];
+      uint32_t d[S / 2];
+      if (it < n0) decode_block_k<B, 0>(gw, e, a.q, lut, d);
+      else if (it < n01) decode_block_k<B, 1>(gw, e, a.q, lut, d);
+      else decode_block_k<B, 2>(gw, e, a.q, lut, d);
+      uint32_t *dst = tile + (t >> 20) * (S / 2);
+      if constexpr (S / 2 >= 4) {
+#pragma unroll
+        for (int w = 0; w < S / 2; w += 4)
+          *reinterpret_cast<uint4 *>(dst + w) = make_uint4(d[w], d[w + 1], d[w + 2], d[w + 3]);
+      } else {
+        *reinterpret_cast<uint2 *>(dst) = make_uint2(d[0], d[1]);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's copies of the node table have landed
+    lds_barrier();
+    const uint16_t *firsts = reinterpret_cast<const uint16_t *>(s_mf + 3 * nn);
+    // (4) one run per wave at a time
+    const int per = (nq + kLFWaves - 1) / kLFWaves;
+    for (int qi = wave * per; qi < min(nq, wave * per + per); qi++) {
+      constexpr int y0 = 0;
+      const uniform_i32 rec = as_uniform(a.batch + (size_t)(q0 + qi) * lfc::kBatchWords);
+      const int nsib = rec[0], root = rec[5];
+      const int vi = so == 0 ? rec[1] : (so == 1 ? rec[2] : (so == 2 ? rec[3] : rec[4]));
+      // which siblings are written
+      bool wanted[4];
+#pragma unroll
+      for (int k = 0; k < 4; k++) wanted[k] = k < nsib && wanted_view(max(rec[1 + k], 0));
+      if (!(wanted[0] || wanted[1] || wanted[2] || wanted[3])) continue;
+      const bool live = seg_in && (so == 0 ? wanted[0] : (so == 1 ? wanted[1] : (so == 2 ? wanted[2] : wanted[3])));
+      const uint32_t w0 = (uint32_t)runs[3 * qi], w1 = (uint32_t)runs[3 * qi + 1], w2 = (uint32_t)runs[3 * qi + 2];
+      const int anc_ln[4] = {(int)(w0 >> 16), (int)(w1 & 0xFFFFu), (int)(w1 >> 16), (int)(w2 & 0xFFFFu)};
+      const int leaf = min((int)(w0 & 0xFFFFu) + so, nn - 1);   // the lane's own leaf
+      uint32_t x[3][HR][2];
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        // key-view rows
+#pragma unroll
+        for (int y = 0; y < HR; y++) {
+          if constexpr (KEYS) {
+            const uint2 k2 = *reinterpret_cast<const uint2 *>(keys + ((c * a.n_top + root) * B + y0 + y) * (NBLK * H) +
+                                                             2 * jseg);
+            x[c][y][0] = k2.x;
+            x[c][y][1] = k2.y;
+          } else {
+#pragma unroll
+            for (int w = 0; w < 2; w++) {
+              const int bx = sx * NBLK + jb[w];
+              x[c][y][w] = bx < a.nbx ? reinterpret_cast<const uint32_t *>(
+                                            a.rkv)[((size_t)(root * a.nb + by * a.nbx + bx) * 3 + c) * (S / 2) +
+                                                   (y0 + y) * H + wib[w]]
+                                      : 0u;
+            }
+          }
+        }
+        // rows of node ln added
+        auto add_node = [&](int ln) {
+          const uint32_t mk = s_mf[c * nn + ln], f = firsts[c * nn + ln];
+#pragma unroll
+          for (int w = 0; w < 2; w++) {
+            if (w == 1 && B >= 4) break;   // both word pairs lie in one block
+            const uint32_t j = (uint32_t)jb[w];
+            const uint32_t sl = ((mk >> j) & 1u) ? f + (uint32_t)__popc(mk & ((1u << j) - 1u)) : zslot;
+            const uint32_t *t = tile + sl * (S / 2) + wib[w] + y0 * H;
+#pragma unroll
+            for (int y = 0; y < HR; y++) {
+              if constexpr (B >= 4) {
+                const uint2 v = *reinterpret_cast<const uint2 *>(t + y * H);
+                x[c][y][0] = add_pk(x[c][y][0], v.x);
+                x[c][y][1] = add_pk(x[c][y][1], v.y);
+              } else {
+                x[c][y][w] = add_pk(x[c][y][w], t[y * H]);
+              }
+            }
+          }
+        };
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+          if (k < a.L - 2) add_node(anc_ln[k]);
+        if (a.L > 1) add_node(leaf);
+      }
+      if (!live) continue;
+      uint32_t *dst = a.out + (uint32_t)vi * vplane + (uint32_t)(by * B + y0) * (uint32_t)a.wp + (uint32_t)px0;
+#pragma unroll
+      for (int y = 0; y < HR; y++) {
+        uint32_t p[4];
+#pragma unroll
+        for (int w = 0; w < 2; w++) {
+          p[2 * w] = rgb_pack(lo16(x[0][y][w]), lo16(x[1][y][w]), lo16(x[2][y][w]));
+          p[2 * w + 1] = rgb_pack(hi16(x[0][y][w]), hi16(x[1][y][w]), hi16(x[2][y][w]));
+        }
+        uint32_t *row = dst + (uint32_t)y * (uint32_t)a.wp;
+        if (wide) {
+          *reinterpret_cast<uint4 *>(row) = make_uint4(p[0], p[1], p[2], p[3]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; k++)
+            if (px0 + k < a.wp) row[k] = p[k];
+        }
+      }
+    }
+    lds_barrier();
+  }
+}
+
+// Novel views from fully decoded 8-bit RGB source views ([nv][hp][wp]): one
+// thread per output pixel, its 16 taps one word each, the same lerps as
+// render_tile.  Used when a batch of views needs about as many source blocks
+// as the whole light field holds.
+struct InterpRGBArgs {
+  const uint32_t *rgb;
+  uint32_t rgb_bytes;   // bytes of the decoded views (below 4 GiB)
+  const lfc_view *views;
+  float *out;
+  int wo, ho, U, V, W, H, wp, hp;
+  float disp;       // focal disparity (as RenderArgs)
+  float sxs, tys;   // W / wo and H / ho, rounded once on the host as the other renderers round them
+};
+
+template <bool FOCAL>
+__global__ __launch_bounds__(kThreads) void k_interp_rgb(InterpRGBArgs a) {
+  // grid (row pieces, view, row): the workgroups that run together render one
+  // output row of every view, whose taps come from nearby rows of the same
+  // few source views, so the caches serve those rows once for all views
+  // (a grid that gave each of the eight dies its own band of rows measured
+  // no faster)
+  const int X = blockIdx.x * kThreads + threadIdx.x, n = blockIdx.y, Yp = blockIdx.z;
+  if (X >= a.wo) return;
+  const lfc_view vw = a.views[n];
+  int iu0, iu1, jv0, jv1, x0, x1, y0, y1;
+  float fu, fv;
+  cell(vw.u, a.U, iu0, iu1, fu);
+  cell(vw.v, a.V, jv0, jv1, fv);
+  const float sxs = a.sxs, tys = a.tys;
+  const float sx = src_pos(vw.s, X, sxs), ty = src_pos(vw.t, Yp, tys);
+  // taps through a buffer resource: 32-bit byte offsets from one base (the
+  // decoded views take less than 4 GiB)
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(a.rgb), 0, a.rgb_bytes, 0x00020000);
+  const uint32_t vbytes = 4u * (uint32_t)a.hp * (uint32_t)a.wp, rbytes = 4u * (uint32_t)a.wp;
+  const uint32_t vis[4] = {(uint32_t)(jv0 * a.U + iu0), (uint32_t)(jv0 * a.U + iu1), (uint32_t)(jv1 * a.U + iu0),
+                           (uint32_t)(jv1 * a.U + iu1)};
+  uint32_t P[4][4];
+  float fs[4], ft[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    cell(sx + focal_shift<FOCAL>(a.disp, vw.u, a.U, (k & 1) ? iu1 : iu0), a.W, x0, x1, fs[k]);
+    cell(ty + focal_shift<FOCAL>(a.disp, vw.v, a.V, (k & 2) ? jv1 : jv0), a.H, y0, y1, ft[k]);
+    const uint32_t r0 = vis[k] * vbytes + (uint32_t)y0 * rbytes, r1 = vis[k] * vbytes + (uint32_t)y1 * rbytes;
+    const uint32_t c0 = 4u * (uint32_t)x0, c1 = 4u * (uint32_t)x1;
+    P[k][0] = __builtin_amdgcn_raw_buffer_load_b32(rs, r0 + c0, 0, 0);
+    P[k][1] = __builtin_amdgcn_raw_buffer_load_b32(rs, r0 + c1, 0, 0);
+    P[k][2] = __builtin_amdgcn_raw_buffer_load_b32(rs, r1 + c0, 0, 0);
+    P[k][3] = __builtin_amdgcn_raw_buffer_load_b32(rs, r1 + c1, 0, 0);
+  }
+  const size_t plane = (size_t)a.ho * a.wo;
+  interp_store(P, fs, ft, fu, fv, a.out + (size_t)n * 3 * plane + (size_t)Yp * a.wo + X, plane);
+}
+
+// The source views a batch of novel views reads (the four grid neighbours of
+// each camera), as a bit per view: one workgroup builds the mask in LDS and
+// writes every word of it.
+__global__ __launch_bounds__(kThreads) void k_need_views(const lfc_view *views, int n, int U, int V, int words,
+                                                         uint32_t *mask) {
+  extern __shared__ uint32_t sm[];
+  for (int w = threadIdx.x; w < words; w += kThreads) sm[w] = 0u;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    int iu0, iu1, jv0, jv1;
+    float fu, fv;
+    cell(views[i].u, U, iu0, iu1, fu);
+    cell(views[i].v, V, jv0, jv1, fv);
+    const int vs[4] = {jv0 * U + iu0, jv0 * U + iu1, jv1 * U + iu0, jv1 * U + iu1};
+#pragma unroll
+    for (int k = 0; k < 4; k++) atomicOr(&sm[vs[k] >> 5], 1u << (vs[k] & 31));
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < words; w += kThreads) mask[w] = sm[w];
 }
 
 // ---------------------------------------------------------------------------
@@ -1171,6 +1467,23 @@ int max_lds_bytes() {
   return v;
 }
 
+// Compute units of the current device (queried once per device).
+int device_cus() {
+  constexpr int kDevices = 64;
+  static std::atomic<int> cached[kDevices];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 256;
+  if (dev < kDevices)
+    if (const int v = cached[dev].load(std::memory_order_relaxed)) return v;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) {
+    (void)hipGetLastError();
+    v = 256;
+  }
+  if (dev < kDevices) cached[dev].store(v, std::memory_order_relaxed);
+  return v;
+}
+
 // LDS of the whole-field kernel: the fixed part (LUT and extents, residual
 // tile, key-view rows) plus staging for the strip's groups and decode
 // schedule, up to 80 KB so that two workgroups share a compute unit.
@@ -1205,6 +1518,36 @@ lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s, int64_t 
   dim3 grid((g.nbx + NBLK - 1) / NBLK, g.nby, 3);
   hipLaunchKernelGGL(k_decode_lf<B>, grid, dim3(kLFThreads), lds, s, a);
   return launched("lfc_decode_blocks");
+}
+
+// Every view (or those whose bit is set in vneed) as 8-bit RGB words
+// [nv][hp][wp], inverse YCoCg-R and clamp applied to the decoded samples.
+template <int B>
+lfc_status decode_rgb(const lfc_lf *lf, uint32_t *out, const uint32_t *vneed, hipStream_t s, const char *who) {
+  const lfc::Geometry &g = lf->geo;
+  constexpr int NBLK = 64 / B;
+  if ((uint64_t)g.nv() * g.hp * g.wp >= ((uint64_t)1 << 32))
+    return fail(LFC_E_UNSUPPORTED, std::string(who) + ": light field too large for 32-bit pixel indices");
+  const int64_t kw = (int64_t)3 * g.n_top * B * 32;
+  const int key_words = kw <= kRGBKeyWordsMax ? (int)kw : 0;
+  const size_t lds = 4 * ((size_t)kRGBHeadWords + (size_t)lf_tile_words(lf->tile_cap_rgb, B * B) + (size_t)key_words);
+  if (lds > (size_t)max_lds_bytes())
+    return fail(LFC_E_UNSUPPORTED, std::string(who) + ": tree too large for the colour whole-field kernel");
+  const int nsx = (g.nbx + NBLK - 1) / NBLK, nstrips = g.nby * nsx;
+  // workgroups per strip: enough for several rounds of the resident
+  // workgroups (about three per compute unit), at most the strips' chunk count
+  int parts = std::max(1, std::min(lf->rgb_max_chunks, (3 * 3 * device_cus() + nstrips - 1) / nstrips));
+  // a view mask longer than the kernel's LDS copy of it: every view is decoded
+  if (g.nv() > 32 * kRGBNeedWords) vneed = nullptr;
+  RGBArgs a{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_sched_rgb, lf->d_strip_off_rgb, lf->d_order_rgb, lf->d_batch,
+            vneed, out, g.nbx, nsx, g.L, g.q, g.wp, g.hp, g.nb, lf->n_batch, g.nv(), g.n_top, key_words,
+            lf->tile_cap_rgb, parts};
+  const dim3 grid((unsigned)(nstrips * parts));
+  if (key_words)
+    hipLaunchKernelGGL((k_decode_rgb<B, true>), grid, dim3(kLFThreads), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_decode_rgb<B, false>), grid, dim3(kLFThreads), lds, s, a);
+  return launched(who);
 }
 
 template <int B>
@@ -1277,7 +1620,11 @@ lfc_status choose_render(const lfc_lf *lf, int32_t n, int32_t wo, int32_t ho, co
   rc.disp = cfg ? cfg->disparity : 0.0f;
   if (!std::isfinite(rc.disp) || std::fabs(rc.disp) > 1.0e6f)
     return fail(LFC_E_INVALID, std::string(who) + ": disparity must be finite, |d| <= 1e6");
-  rc.decoded = path == LFC_RENDER_AUTO ? render_decoded(g, n, wo, ho) : path == LFC_RENDER_DECODED;
+  // the decoded path addresses its scratch with 32-bit byte offsets
+  const bool fits = (uint64_t)g.nv() * g.hp * g.wp * 4 < ((uint64_t)1 << 32);
+  if (path == LFC_RENDER_DECODED && !fits)
+    return fail(LFC_E_UNSUPPORTED, std::string(who) + ": the decoded views would take 4 GiB or more");
+  rc.decoded = fits && (path == LFC_RENDER_AUTO ? render_decoded(g, n, wo, ho) : path == LFC_RENDER_DECODED);
   if (rc.decoded) return LFC_OK;
   int TX = 64, TY = 16;
   bool shrink = true;
@@ -1294,27 +1641,38 @@ lfc_status choose_render(const lfc_lf *lf, int32_t n, int32_t wo, int32_t ho, co
   return LFC_OK;
 }
 
-size_t decoded_bytes(const lfc::Geometry &g) { return (size_t)g.nv() * 3 * g.hp * g.wp * sizeof(int16_t); }
+// Scratch of the decode-then-interpolate path: the source views as 8-bit
+// RGB words, then the mask of the views a batch reads.
+size_t rgb_bytes(const lfc::Geometry &g) { return (size_t)g.nv() * g.hp * g.wp * sizeof(uint32_t); }
+int need_words(const lfc::Geometry &g) { return (g.nv() + 31) / 32; }
+size_t decoded_bytes(const lfc::Geometry &g) { return ((rgb_bytes(g) + 255) & ~(size_t)255) + 4 * (size_t)need_words(g); }
 
 // One render with a resolved choice.  The decoded path decodes into ws when
 // given, else into stream-ordered scratch (served from the pool after the
 // first call).
 template <int B>
 lfc_status render_with(const lfc_lf *lf, const lfc_view *views, int32_t n, int32_t wo, int32_t ho, float *out,
-                       const RenderChoice &rc, int16_t *ws, hipStream_t s) {
+                       const RenderChoice &rc, void *ws, hipStream_t s) {
   const lfc::Geometry &g = lf->geo;
   if (rc.decoded) {
-    int16_t *dec = ws;
-    if (!dec && hipMallocAsync(reinterpret_cast<void **>(&dec), decoded_bytes(g), s) != hipSuccess)
+    void *dec = ws;
+    if (!dec && hipMallocAsync(&dec, decoded_bytes(g), s) != hipSuccess)
       return fail(LFC_E_NOMEM, "lfc_render_views: scratch for the decoded views");
-    lfc_status st = decode_images<B>(lf, dec, s);
+    uint32_t *rgb = static_cast<uint32_t *>(dec);
+    uint32_t *mask = reinterpret_cast<uint32_t *>(static_cast<char *>(dec) + ((rgb_bytes(g) + 255) & ~(size_t)255));
+    // the views the batch reads, then those views decoded, then the interpolation
+    hipLaunchKernelGGL(k_need_views, dim3(1), dim3(kThreads), 4 * (size_t)need_words(g), s, views, n, g.U, g.V,
+                       need_words(g), mask);
+    lfc_status st = launched("lfc_render_views");
+    if (st == LFC_OK) st = decode_rgb<B>(lf, rgb, mask, s, "lfc_render_views");
     if (st == LFC_OK) {
-      InterpArgs ia{dec, views, out, wo, ho, g.U, g.V, g.W, g.H, g.wp, g.hp, rc.disp};
+      InterpRGBArgs ia{rgb, (uint32_t)rgb_bytes(g), views, out, wo, ho, g.U, g.V, g.W, g.H, g.wp, g.hp, rc.disp,
+                       (float)g.W / (float)wo, (float)g.H / (float)ho};
       const dim3 grid((wo + kThreads - 1) / kThreads, n, ho);
       if (rc.disp != 0.0f)
-        hipLaunchKernelGGL(k_interp<true>, grid, dim3(kThreads), 0, s, ia);
+        hipLaunchKernelGGL(k_interp_rgb<true>, grid, dim3(kThreads), 0, s, ia);
       else
-        hipLaunchKernelGGL(k_interp<false>, grid, dim3(kThreads), 0, s, ia);
+        hipLaunchKernelGGL(k_interp_rgb<false>, grid, dim3(kThreads), 0, s, ia);
       st = launched("lfc_render_views");
     }
     if (!ws && hipFreeAsync(dec, s) != hipSuccess && st == LFC_OK)
@@ -1325,14 +1683,14 @@ lfc_status render_with(const lfc_lf *lf, const lfc_view *views, int32_t n, int32
   RenderArgs a{ra_args(lf), views, out, wo, ho, g.U, g.V, g.W, g.H, pl.TX, pl.TY, pl.fbx, pl.fby, rc.disp};
   dim3 grid((wo + pl.TX - 1) / pl.TX, (ho + pl.TY - 1) / pl.TY, n);
   if (rc.disp != 0.0f)
-    hipLaunchKernelGGL((k_render<B, true>), grid, dim3(kThreads), pl.lds, s, a);
+    hipLaunchKernelGGL((k_render<B, true>), grid, dim3(kRenderThreads), pl.lds, s, a);
   else
-    hipLaunchKernelGGL((k_render<B, false>), grid, dim3(kThreads), pl.lds, s, a);
+    hipLaunchKernelGGL((k_render<B, false>), grid, dim3(kRenderThreads), pl.lds, s, a);
   return launched("lfc_render_views");
 }
 
 lfc_status render_any(const lfc_lf *lf, const lfc_view *views, int32_t n, int32_t wo, int32_t ho, float *out,
-                      const RenderChoice &rc, int16_t *ws, hipStream_t s) {
+                      const RenderChoice &rc, void *ws, hipStream_t s) {
   switch (lf->geo.B) {
     case 2: return render_with<2>(lf, views, n, wo, ho, out, rc, ws, s);
     case 4: return render_with<4>(lf, views, n, wo, ho, out, rc, ws, s);
@@ -1363,7 +1721,7 @@ extern "C" lfc_status lfc_decode_blocks(const lfc_lf *lf, const int32_t *d_req, 
 extern "C" lfc_status lfc_decode_blocks_ex(const lfc_lf *lf, const int32_t *d_req, int64_t n, int32_t layout,
                                            int16_t *d_out, const lfc_decode_config *cfg, hipStream_t s) {
   const char *who = "lfc_decode_blocks";
-  const int64_t stage_cap = cfg ? cfg->stage_cap_words : -1;
+  const int64_t stage_cap = cfg ? cfg->stage_cap_words : (lf ? lf->stage_cap : 0);
   if (stage_cap < -1) return fail(LFC_E_INVALID, "lfc_decode_blocks: stage_cap_words must be >= -1");
   if (!lf) return fail(LFC_E_INVALID, "lfc_decode_blocks: null handle");
   if (lfc_status st = check_device(lf, who)) return st;
@@ -1390,6 +1748,18 @@ extern "C" lfc_status lfc_decode_blocks_ex(const lfc_lf *lf, const int32_t *d_re
     case 2: return decode_list<2>(lf, d_req, n, d_out, s);
     case 4: return decode_list<4>(lf, d_req, n, d_out, s);
     default: return decode_list<8>(lf, d_req, n, d_out, s);
+  }
+}
+
+extern "C" lfc_status lfc_decode_rgb(const lfc_lf *lf, uint32_t *d_out, hipStream_t s) {
+  const char *who = "lfc_decode_rgb";
+  if (!lf) return fail(LFC_E_INVALID, "lfc_decode_rgb: null handle");
+  if (lfc_status st = check_device(lf, who)) return st;
+  if (lfc_status st = check_buffer(d_out, rgb_bytes(lf->geo), 16, who, "d_out")) return st;
+  switch (lf->geo.B) {
+    case 2: return decode_rgb<2>(lf, d_out, nullptr, s, who);
+    case 4: return decode_rgb<4>(lf, d_out, nullptr, s, who);
+    default: return decode_rgb<8>(lf, d_out, nullptr, s, who);
   }
 }
 
@@ -1481,7 +1851,7 @@ extern "C" lfc_status lfc_render_views_noalloc(const lfc_lf *lf, const lfc_view 
   void *ws = nullptr;
   if (rc.decoded)
     if (lfc_status st = noalloc_scratch(&ws, who)) return st;
-  return render_any(lf, d_views, n, out_w, out_h, d_out, rc, static_cast<int16_t *>(ws), s);
+  return render_any(lf, d_views, n, out_w, out_h, d_out, rc, ws, s);
 }
 
 // Measured tuning: every candidate launch shape timed on the caller's views.
@@ -1501,10 +1871,10 @@ extern "C" lfc_status lfc_render_tune(const lfc_lf *lf, const lfc_view *d_views,
     if (plan_render(lf->geo, out_w, out_h, pl, sh[0], sh[1], false))
       cands.push_back(lfc_render_config{LFC_RENDER_TILES, sh[0], sh[1], 0.0f});
   }
-  int16_t *ws = nullptr;
+  void *ws = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   lfc_status st = LFC_OK;
-  if (hipMalloc(reinterpret_cast<void **>(&ws), decoded_bytes(lf->geo)) != hipSuccess) {
+  if (hipMalloc(&ws, decoded_bytes(lf->geo)) != hipSuccess) {
     ws = nullptr;
     (void)hipGetLastError();      // clear the failed allocation's error
     cands.erase(cands.begin());   // no room for the decoded views: tile shapes only
@@ -1545,7 +1915,7 @@ struct lfc_render_plan {
   float *out = nullptr;
   int32_t n = 0, w = 0, h = 0;
   RenderChoice rc{};
-  int16_t *ws = nullptr;            // decoded views (decoded path)
+  void *ws = nullptr;               // decoded views and their mask (decoded path)
   hipStream_t cap = nullptr;        // stream the graph was captured on
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1578,14 +1948,15 @@ extern "C" lfc_status lfc_render_plan_create(const lfc_lf *lf, const lfc_render_
   p->h = out_h;
   lfc_status st = choose_render(lf, n, out_w, out_h, cfg, p->rc, who);
   if (st == LFC_OK && p->rc.decoded) {
-    hipError_t he = hipMalloc(reinterpret_cast<void **>(&p->ws), decoded_bytes(lf->geo));
+    hipError_t he = hipMalloc(&p->ws, decoded_bytes(lf->geo));
     if (he != hipSuccess) {
       p->ws = nullptr;
       st = fail(he == hipErrorOutOfMemory ? LFC_E_NOMEM : LFC_E_HIP, "lfc_render_plan_create: decoded views");
     }
   }
   if (st == LFC_OK && graph) {
-    (void)max_lds_bytes();   // device query done before the capture
+    (void)max_lds_bytes();   // device queries done before the capture
+    (void)device_cus();
     if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
       p->cap = nullptr;
       st = fail(LFC_E_HIP, "lfc_render_plan_create: capture stream");
@@ -1688,9 +2059,9 @@ lfc_status render_multi_launch(int block, const void *d_reqs, int n, int max_til
   const RenderReq *r = static_cast<const RenderReq *>(d_reqs);
   dim3 grid((unsigned)max_tiles, (unsigned)n);
   switch (block) {
-    case 2: hipLaunchKernelGGL(k_render_multi<2>, grid, dim3(kThreads), lds, s, r); break;
-    case 4: hipLaunchKernelGGL(k_render_multi<4>, grid, dim3(kThreads), lds, s, r); break;
-    default: hipLaunchKernelGGL(k_render_multi<8>, grid, dim3(kThreads), lds, s, r); break;
+    case 2: hipLaunchKernelGGL(k_render_multi<2>, grid, dim3(kRenderThreads), lds, s, r); break;
+    case 4: hipLaunchKernelGGL(k_render_multi<4>, grid, dim3(kRenderThreads), lds, s, r); break;
+    default: hipLaunchKernelGGL(k_render_multi<8>, grid, dim3(kRenderThreads), lds, s, r); break;
   }
   return launched("lfc_batch_render");
 }

@@ -96,7 +96,8 @@ RENDER_AUTO, RENDER_TILES, RENDER_DECODED = 0, 1, 2
 
 
 class c_decode_tuning(C.Structure):
-    _fields_ = [("n_tried", C.c_int32), ("best", C.c_int32), ("tile_blocks", C.c_int32 * 8), ("ms", C.c_float * 8)]
+    _fields_ = [("n_tried", C.c_int32), ("best", C.c_int32), ("tile_blocks", C.c_int32 * 16),
+                ("staged", C.c_int32 * 16), ("ms", C.c_float * 16)]
 
 
 class c_open_config(C.Structure):
@@ -170,6 +171,7 @@ def load() -> C.CDLL:
         L.lfc_info.argtypes = [vp, C.POINTER(c_info)]
         L.lfc_decode_blocks.argtypes = [vp, vp, i64, i32, vp, vp]
         L.lfc_decode_progressive.argtypes = [vp, vp, i64, i32, vp, vp]
+        L.lfc_decode_rgb.argtypes = [vp, vp, vp]
         L.lfc_stage_needs.argtypes = [vp, vp, i64]
         L.lfc_stage_needs.restype = i64
         L.lfc_render_views.argtypes = [vp, vp, i32, i32, i32, vp, vp]
@@ -213,7 +215,7 @@ def load() -> C.CDLL:
                   "lfc_decode_blocks", "lfc_decode_blocks_ex",
                   "lfc_render_views", "lfc_render_views_ex", "lfc_render_views_noalloc", "lfc_encode_ctl", "lfc_tune_decode", "lfc_encode_gpu", "lfc_mlp_infer", "lfc_mlp_infer_ex", "lfc_mlp_grad",
                   "lfc_mlp_adam", "lfc_render_tune", "lfc_render_plan_create",
-                  "lfc_render_plan_launch", "lfc_render_plan_info", "lfc_check", "lfc_close", "lfc_decode_progressive", "lfc_batch_create",
+                  "lfc_render_plan_launch", "lfc_render_plan_info", "lfc_check", "lfc_close", "lfc_decode_progressive", "lfc_decode_rgb", "lfc_batch_create",
                   "lfc_batch_decode", "lfc_batch_check", "lfc_batch_render",
                   "lfc_batch_destroy", "lfc_server_create", "lfc_server_submit", "lfc_server_wait",
                   "lfc_server_release", "lfc_server_replay", "lfc_server_get_stats", "lfc_server_destroy"):
@@ -448,10 +450,11 @@ def lfc_info(lf: LightField) -> c_info:
 
 
 def lfc_decode_blocks(lf: LightField, req=None, layout: int = LAYOUT_BLOCKS, out=None, cuda_stream=None,
-                      stage_cap_words: int = -1):
+                      stage_cap_words: int | None = None):
     """Decodes blocks on the GPU.  req: int32 CUDA tensor [n][2] = (view, block)
     or None for every block.  Returns the int16 CUDA output tensor.
-    stage_cap_words >= 0 caps the whole-field decode's LDS staging."""
+    stage_cap_words (images layout): None uses the handle's staging setting;
+    -1 stages each strip in LDS as it needs; >= 0 caps the staging (0: none)."""
     import torch
     i = lf.info
     nv = i.params.grid_u * i.params.grid_v
@@ -467,7 +470,7 @@ def lfc_decode_blocks(lf: LightField, req=None, layout: int = LAYOUT_BLOCKS, out
     if out is None:
         out = torch.empty(shape, dtype=torch.int16, device="cuda")
     assert out.dtype == torch.int16 and out.is_cuda and out.is_contiguous() and tuple(out.shape) == shape
-    if stage_cap_words == -1:
+    if stage_cap_words is None:
         _check(load().lfc_decode_blocks(lf.handle, req.data_ptr() if req is not None else None, n, layout,
                                         out.data_ptr(), _stream_ptr(cuda_stream)))
     else:
@@ -491,6 +494,19 @@ def lfc_tune_decode(lf: LightField, reps: int = 5, out=None, cuda_stream=None):
     return tried[res.best][0], tried
 
 
+def lfc_tune_decode_ex(lf: LightField, reps: int = 5, out=None, cuda_stream=None):
+    """As lfc_tune_decode; returns ((kept capacity, kept staging), [(capacity, staged, ms)])."""
+    import torch
+    i = lf.info
+    nv = i.params.grid_u * i.params.grid_v
+    if out is None:
+        out = torch.empty((nv, 3, i.padded_height, i.padded_width), dtype=torch.int16, device="cuda")
+    res = c_decode_tuning()
+    _check(load().lfc_tune_decode(lf.handle, out.data_ptr(), reps, C.byref(res), _stream_ptr(cuda_stream)))
+    tried = [(int(res.tile_blocks[k]), bool(res.staged[k]), float(res.ms[k])) for k in range(res.n_tried)]
+    return tried[res.best][:2], tried
+
+
 def lfc_stage_needs(lf: LightField) -> np.ndarray:
     """LDS words each strip of the whole-field decode needs: [strips][2] =
     (groups + schedule, schedule alone)."""
@@ -500,6 +516,19 @@ def lfc_stage_needs(lf: LightField) -> np.ndarray:
         _check(int(n))
     out = np.zeros((n, 2), dtype=np.uint32)
     L.lfc_stage_needs(lf.handle, out.ctypes.data, n)
+    return out
+
+
+def lfc_decode_rgb(lf: LightField, out=None, cuda_stream=None):
+    """Every view as 8-bit RGB: int32 CUDA tensor [nv][padded_height][padded_width]
+    holding R | G << 8 | B << 16 per pixel."""
+    import torch
+    i = lf.info
+    shape = (i.params.grid_u * i.params.grid_v, i.padded_height, i.padded_width)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.int32, device="cuda")
+    assert out.dtype == torch.int32 and out.is_cuda and out.is_contiguous() and tuple(out.shape) == shape
+    _check(load().lfc_decode_rgb(lf.handle, out.data_ptr(), _stream_ptr(cuda_stream)))
     return out
 
 

@@ -1,7 +1,7 @@
 """Summaries of rocprofv3 output databases for the committed profiles.
 
     python -m paper_1805_06019_amd.prof_summary trace <kernel_trace.db> [command]
-    python -m paper_1805_06019_amd.prof_summary traffic <fetch.db> <write.db> <out.json> [command [tile_blocks]]
+    python -m paper_1805_06019_amd.prof_summary traffic <fetch.db> <write.db> <out.json> [command [tile_blocks [staged]]]
     python -m paper_1805_06019_amd.prof_summary counters <counters.db>...
 
 ``trace`` prints a markdown table of per-kernel dispatch counts and durations.
@@ -10,7 +10,7 @@ dispatch), scales each by what the same counter reads for a device-to-device
 copy of 256 MiB in the same run (the copy moves exactly 256 MiB each way),
 and writes the per-launch HBM bytes of the whole-field decode kernel,
 together with a hash of the kernel source it was measured on and the decode
-tile capacity of the run.
+tile capacity and staging of the run.
 ``counters`` prints, for the whole-field decode kernel, the mean per dispatch
 of every counter in the given runs.
 """
@@ -132,7 +132,8 @@ def main(argv):
                    copy_fetch_kib=round(f_copy, 1), copy_write_kib=round(w_copy, 1),
                    copy_fetch_factor=round(f_scale, 4), copy_write_factor=round(w_scale, 4),
                    command=argv[5] if len(argv) > 5 else "",
-                   tile_blocks=int(argv[6]) if len(argv) > 6 else None)
+                   tile_blocks=int(argv[6]) if len(argv) > 6 else None,
+                   staged=len(argv) > 7 and argv[7] in ("1", "staged", "true"))
         with open(argv[4], "w") as fh:
             json.dump(rec, fh, indent=1)
             fh.write("\n")

@@ -41,6 +41,29 @@ def gpu_open(stream):
     return lfc.lfc_open(stream)
 
 
+def oracle_rgb_words(r0):
+    """The oracle's reconstruction [nv][3][hp][wp] (Y, Co, Cg) as the colour
+    decode's pixel words: inverse YCoCg-R clamped to 8 bits, R | G << 8 | B << 16."""
+    rgb = oracle.ycocg_inverse(np.ascontiguousarray(np.transpose(r0, (0, 2, 3, 1)))).astype(np.uint32)
+    return (rgb[..., 0] | (rgb[..., 1] << 8) | (rgb[..., 2] << 16)).view(np.int32)
+
+
+@pytest.mark.parametrize("case", GEOMS, ids=[f"{c[0]}x{c[1]}x{c[2]}x{c[3]}-B{c[4]['block']}-L{c[4]['levels']}"
+                                             for c in GEOMS])
+def test_whole_field_rgb(gpu, case):
+    # every view as 8-bit RGB: the colour whole-field kernel (strips of all
+    # three channels) against the oracle's reconstruction and colour transform
+    U, V, W, H, kw = case
+    say("rgb", case)
+    rgb = make_lf(U, V, W, H, seed=U * 13 + W)
+    enc = oracle_encode(rgb, **kw)
+    lf = gpu_open(enc.stream)
+    got = lfc.lfc_decode_rgb(lf).cpu().numpy()
+    assert np.array_equal(got, oracle_rgb_words(enc.r0))
+    # the unpadded part is the light field's own colour image of the reconstruction
+    lf.close()
+
+
 @pytest.mark.parametrize("case", GEOMS, ids=[f"{c[0]}x{c[1]}x{c[2]}x{c[3]}-B{c[4]['block']}-L{c[4]['levels']}"
                                              for c in GEOMS])
 def test_whole_field_images_layout(gpu, case):
@@ -58,14 +81,15 @@ def test_whole_field_images_layout(gpu, case):
     assert torch.equal(out, out2)
 
 
-@pytest.mark.parametrize("tiers", ["global", "no-payload", "mixed"])
+@pytest.mark.parametrize("tiers", ["global", "no-payload", "mixed", "as-needed"])
 @pytest.mark.parametrize("case", [GEOMS[0], GEOMS[3], GEOMS[5], GEOMS[6]],
                          ids=["8x8x64x64-B4-L2", "17x17x20x12-B4-L3", "5x4x72x24-B8-L2", "6x3x130x10-B2-L3"])
 def test_whole_field_staging_tiers(gpu, case, tiers):
     # stage_cap_words bounds the LDS the whole-field kernel may use to
     # stage a strip: 0 reads everything from global memory; a cap that holds
     # the schedule but not the payload of most strips stages the schedule
-    # only; the median strip's full need mixes the tiers in one launch
+    # only; the median strip's full need mixes the tiers in one launch; -1
+    # stages what each strip needs within the workgroup's LDS budget
     U, V, W, H, kw = case
     rgb = make_lf(U, V, W, H, seed=U * 13 + W)
     enc = oracle_encode(rgb, **kw)
@@ -78,8 +102,10 @@ def test_whole_field_staging_tiers(gpu, case, tiers):
         # the cap that puts the most strips in the middle tier
         cap = max((int(c) for c in t2), key=lambda c: int(np.sum((t2 <= c) & (t1 > c))))
         assert np.sum((t2 <= cap) & (t1 > cap)) > 0
-    else:
+    elif tiers == "mixed":
         cap = int(np.median(t1))
+    else:
+        cap = -1
     say("images staging", case, tiers, cap)
     got = lfc.lfc_decode_blocks(lf, None, lfc.LAYOUT_IMAGES, stage_cap_words=cap).cpu().numpy()
     assert np.array_equal(got, enc.r0)
@@ -146,6 +172,7 @@ def test_empty_request_list_and_argument_errors(gpu):
     try:
         assert lib.lfc_decode_blocks(lf.handle, None, 16, lfc.LAYOUT_IMAGES, small.value, s) == -1
         assert lib.lfc_decode_blocks(lf.handle, None, 16 * 16, lfc.LAYOUT_BLOCKS, small.value, s) == -1
+        assert lib.lfc_decode_rgb(lf.handle, small.value, s) == -1   # 16 views of 16 x 16 words need 16 KB
     finally:
         hip.hipFree(small)
     # wrong count for the images layout, unknown layout, host pointer as output
@@ -154,6 +181,8 @@ def test_empty_request_list_and_argument_errors(gpu):
     assert lib.lfc_decode_blocks(lf.handle, None, 16, 7, big.data_ptr(), s) == -1
     host = np.zeros(16 * 3 * 16 * 16, dtype=np.int16)
     assert lib.lfc_decode_blocks(lf.handle, None, 16, lfc.LAYOUT_IMAGES, host.ctypes.data, s) == -1
+    assert lib.lfc_decode_rgb(lf.handle, host.ctypes.data, s) == -1
+    assert lib.lfc_decode_rgb(None, big.data_ptr(), s) == -1
     # a corrupt stream never reaches the device
     with pytest.raises(lfc.LFCError) as e:
         lfc.lfc_open(enc.stream[:-4])
@@ -215,6 +244,9 @@ def test_full_size_whole_field_and_random_access(gpu, full40):
     blk = lfc.lfc_decode_blocks(lf, torch.from_numpy(req).cuda(), lfc.LAYOUT_BLOCKS).cpu().numpy()
     expect = blocks_of(enc.r0, 4)
     assert np.array_equal(blk, expect[req[:, 0], req[:, 1]])
+    del blk, expect
+    say("full40: every view as 8-bit RGB")
+    assert np.array_equal(lfc.lfc_decode_rgb(lf).cpu().numpy(), oracle_rgb_words(enc.r0))
     lfc.lfc_check(lf)
 
 
@@ -355,11 +387,14 @@ def test_decode_tuner_keeps_the_output(gpu, case):
     lf = gpu_open(enc.stream)
     n_strips = lfc.lfc_stage_needs(lf).shape[0]
     for _ in range(2):
-        best, tried = lfc.lfc_tune_decode(lf, reps=2)
+        best, tried = lfc.lfc_tune_decode_ex(lf, reps=2)
         say("tried", tried, "kept", best)
-        assert best in [c for c, _ in tried] and all(ms > 0 for _, ms in tried)
+        assert best in [(c, st) for c, st, _ in tried] and all(ms > 0 for _, _, ms in tried)
+        # every capacity is timed with and without staging
+        assert sorted(st for _, st, _ in tried) == [False, True] * (len(tried) // 2) or \
+            sum(st for _, st, _ in tried) * 2 == len(tried)
         if kw["levels"] >= 2:
-            assert len(tried) >= 2
+            assert len(tried) >= 4
         assert lfc.lfc_stage_needs(lf).shape[0] == n_strips
         got = lfc.lfc_decode_blocks(lf, None, lfc.LAYOUT_IMAGES).cpu().numpy()
         assert np.array_equal(got, enc.r0)

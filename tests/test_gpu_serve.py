@@ -124,8 +124,10 @@ def test_server_results_match_single_renders(fields):
 
 def test_server_results_repeatable(fields):
     # the whole mix several times over, two lanes: every result of every
-    # round must be the lone render's bytes (a request table rewritten under
-    # a running launch showed up here as rare residual-sized errors)
+    # round must be the lone render's bytes (before the batched render kernel
+    # read its request record once per workgroup, this mix showed rare
+    # residual-sized errors whose mechanism was not established; this test
+    # guards the fixed code)
     _, lfs = fields
     reqs = mixed_requests(60, seed=7)
     refs = [single(lfs, r) for r in reqs]
