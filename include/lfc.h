@@ -574,7 +574,19 @@ lfc_status lfc_batch_create(lfc_batch **out);
  * streams, and a fifth waits until the kernels of the first have finished
  * (a table is never rewritten while a launch may still read it).  The
  * staging grows on demand (a call with more requests than any before
- * allocates).  Errors:
+ * allocates).
+ * Paths (Sec. 3.6: decode the blocks a view needs, then interpolate): a
+ * light field whose requests in the call cover at least a twentieth of the
+ * pixels it holds is decoded once, only the views its requests read, as
+ * 8-bit RGB, by one persistent launch over every such light field of a block
+ * size (workgroups take (strip, part) items of all of them from a device
+ * counter), then one launch interpolates all those requests; the other
+ * requests render by output tiles, each decoding its footprint.  Both give
+ * the bytes lfc_render_views gives for the request alone.  The decoded views
+ * live in device buffers the context allocates on first use per light field
+ * (4 x views x padded pixels bytes) and keeps until it is destroyed; a
+ * light field for which no buffer can be allocated renders by tiles.
+ * Errors:
  * LFC_E_INVALID (null pointer, index or size out of range, more than 65535
  * requests of one block size), LFC_E_UNSUPPORTED, LFC_E_NOMEM, LFC_E_HIP.
  */

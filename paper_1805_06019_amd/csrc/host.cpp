@@ -220,7 +220,8 @@ void build_tree_tables(const Geometry &g, TreeTables &t) {
 // Decode schedule of the whole-field kernel, derived once from the directory.
 // Per strip (channel c, block row by, strip sx of 64/B blocks) the runs of
 // sibling leaves are cut into chunks whose stored blocks fit the kernel's
-// compact residual tile (cap blocks, stored blocks only); per
+// compact residual tile (cap blocks, stored blocks only) and whose gather
+// table (masks, first slots, run records) fits kLFTabWords words; per
 // chunk: its runs, its nodes (leaves first, then ancestors), per node a mask
 // of the stored blocks and the tile slot of the first one (slots follow node
 // order, then block order), per run the positions of its first leaf and of
@@ -277,7 +278,9 @@ static void build_schedule(const Geometry &g, const std::vector<uint32_t> &off, 
               add += __builtin_popcount(m[(size_t)s]);
             }
           }
-          if (k > 0 && (count + add > cap || leaves.size() + ancs.size() + nl.size() + na.size() > 65535)) break;
+          const size_t nn_new = leaves.size() + ancs.size() + nl.size() + na.size();
+          if (k > 0 && (count + add > cap || nn_new + (nn_new + 1) / 2 + 3 * (size_t)(k + 1) > (size_t)kLFTabWords))
+            break;
           for (int s : nl) {
             loc[(size_t)s] = 0;
             leaves.push_back(s);

@@ -42,6 +42,10 @@ constexpr int kBatchWords = 16;
 // compact tile (32 KB of LDS; tile slots are 11-bit, beside a 5-bit block
 // index in 16-bit schedule items, so at most 2048).
 constexpr int tile_blocks(int B) { return B == 2 ? 2048 : (B == 4 ? 1024 : 256); }
+// Most words of a chunk's gather table (per-node masks and first slots,
+// per-run node positions) in the whole-field kernel's schedule: the kernel
+// copies a chunk's table into LDS when the strip is read from global memory.
+constexpr int kLFTabWords = 1024;
 // Most tree nodes in one chunk of the colour whole-field kernel's schedule
 // (the kernel copies a chunk's per-node tables into LDS).
 constexpr int kRGBNodeCap = 128;

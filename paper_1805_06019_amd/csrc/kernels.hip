@@ -395,23 +395,37 @@ __device__ __forceinline__ uniform_i32 as_uniform(const int32_t *p) { return (un
 // whole, by one lane, with the decoder of its range kind, into its slot of
 // the compact tile; step (4): per sibling run, key-view row + ancestor rows +
 // leaf row (absent blocks add nothing), stored 16 bytes per lane.
-template <int B, bool KEYS>
+template <int B, bool KEYS, bool TAB>
 __device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, const uint32_t *pw,
                                          const uint32_t *s_po, uint32_t *tile, const uint32_t *keys,
-                                         const uint16_t *lut, int tid, int wave, int lane, int so, int jq,
-                                         int bx0, int nact, bool wide, uint64_t lane_off, uint32_t vstride, int by,
-                                         int c) {
+                                         uint32_t *s_tab, const uint16_t *lut, int tid, int wave, int lane, int so,
+                                         int jq, int bx0, int nact, bool wide, uint64_t lane_off, uint32_t vstride,
+                                         int by, int c) {
   constexpr int S = B * B, NBLK = 64 / B, H = B / 2, PB = 8 / B;
   // the chunk's header fields, the same for every lane (made scalar)
   const int q0 = __builtin_amdgcn_readfirstlane((int)sch[0]), nq = __builtin_amdgcn_readfirstlane((int)sch[1]);
   const int nn = __builtin_amdgcn_readfirstlane((int)sch[2]);
   const uint32_t n0 = __builtin_amdgcn_readfirstlane(sch[3]), n01 = __builtin_amdgcn_readfirstlane(sch[4]);
   const uint32_t n = __builtin_amdgcn_readfirstlane(sch[5]);
-  const uint32_t *masks = sch + 6;
+  const uint32_t *ents = sch + 6 + nn + (nn + 1) / 2 + 3 * nq;
+  const uint16_t *items = reinterpret_cast<const uint16_t *>(ents + n);
+  // the gather's table (per-node masks and first slots, per-run node
+  // positions): read where the schedule is (LDS in the staging tiers), or,
+  // with TAB, copied from global memory into LDS during the decode, so that
+  // the gather issues no vector load (each would wait for the wave's
+  // outstanding stores)
+  const uint32_t *tab = sch + 6;
+  if constexpr (TAB) {
+    const int tw = nn + (nn + 1) / 2 + 3 * nq;
+    for (int w0 = wave * 64; w0 < tw; w0 += kLFThreads)
+      if (w0 + lane < tw)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(sch + 6 + w0 + lane),
+                                         (__attribute__((address_space(3))) void *)(s_tab + w0), 4, 0, 0);
+    tab = s_tab;
+  }
+  const uint32_t *masks = tab;
   const uint16_t *firsts = reinterpret_cast<const uint16_t *>(masks + nn);
   const uint32_t *runs = masks + nn + (nn + 1) / 2;
-  const uint32_t *ents = runs + 3 * nq;
-  const uint16_t *items = reinterpret_cast<const uint16_t *>(ents + n);
   // (3) decode; the three kinds are laid end to end, so a wave mostly sees one kind
   for (uint32_t it = tid; it < n; it += kLFThreads) {
     const uint32_t e = ents[it], t = items[it];
@@ -429,6 +443,7 @@ __device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, c
       *reinterpret_cast<uint2 *>(dst) = make_uint2(d[0], d[1]);
     }
   }
+  if constexpr (TAB) __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): the table copies have landed
   lds_barrier();
   // (4) gather and store.  A wave takes two runs at a time, one per half; a
   // lane owns one sibling of its run and one 16-byte segment (PB blocks) of
@@ -565,7 +580,8 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
   uint32_t *s_cnt = smem + 384;                        // [0] tier, [1] staged group words, [2] schedule words
   uint32_t *tile = smem + kLFHeadWords;                // compact tile: [tile_cap + 1][S/2], the last slot zero
   uint32_t *keys = tile + lf_tile_words(a.tile_cap, S); // [n_top][B][NBLK][H]
-  uint32_t *stage = keys + a.key_words;
+  uint32_t *s_tab = keys + a.key_words;                 // a chunk's gather table (strips read from global memory)
+  uint32_t *stage = s_tab + lfc::kLFTabWords;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   // the workgroup's strip (strips are taken costliest first, so the last
@@ -669,14 +685,14 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
     constexpr bool K = decltype(keys_staged)::value;
     for (int ci = 0; ci < nck; ci++) {
       if (tier == 1u)
-        lf_chunk<B, K>(a, lsched + lsched[1 + ci], stage, s_wo, tile, keys, lut, tid, wave, lane, so, jq, bx0, nact,
-                       wide, lane_off, vstride, by, c);
+        lf_chunk<B, K, false>(a, lsched + lsched[1 + ci], stage, s_wo, tile, keys, s_tab, lut, tid, wave, lane, so, jq,
+                              bx0, nact, wide, lane_off, vstride, by, c);
       else if (tier == 2u)
-        lf_chunk<B, K>(a, lsched + lsched[1 + ci], a.srv, s_o0, tile, keys, lut, tid, wave, lane, so, jq, bx0, nact,
-                       wide, lane_off, vstride, by, c);
+        lf_chunk<B, K, false>(a, lsched + lsched[1 + ci], a.srv, s_o0, tile, keys, s_tab, lut, tid, wave, lane, so, jq,
+                              bx0, nact, wide, lane_off, vstride, by, c);
       else
-        lf_chunk<B, K>(a, gsched + gsched[1 + ci], a.srv, s_o0, tile, keys, lut, tid, wave, lane, so, jq, bx0, nact,
-                       wide, lane_off, vstride, by, c);
+        lf_chunk<B, K, true>(a, gsched + gsched[1 + ci], a.srv, s_o0, tile, keys, s_tab, lut, tid, wave, lane, so, jq,
+                             bx0, nact, wide, lane_off, vstride, by, c);
     }
   };
   if (a.key_words) chunks(std::true_type{});
@@ -850,8 +866,10 @@ __device__ __forceinline__ uint32_t locate(const RAArgs &a, int g, int s, const 
   return a.poff[a.dbase[(size_t)g * a.nbw + (s >> 5)] + __popc(bm & ((1u << bit) - 1u))];
 }
 
-// Threads of a render-tile workgroup.
-constexpr int kRenderThreads = 256;
+// Threads of a render-tile workgroup: 8 waves, so that a tile's footprint
+// decode (a chain of dependent reads per level) and its interpolation run
+// in half the passes of a 4-wave workgroup at the same LDS per tile.
+constexpr int kRenderThreads = 512;
 
 // One workgroup per (view, output tile).  The tile's source footprint in the
 // four nearest views is reconstructed in LDS: first the key-view rows, then,
@@ -1118,11 +1136,12 @@ struct RGBArgs {
 // a lane owns one sibling and 4 pixels of the strip's rows, sums key row +
 // ancestor rows + leaf row of each channel, converts the pixels to RGB
 // (inverse YCoCg-R, clamped) and stores 16 bytes per row.
+// The work of one workgroup (strip st, part) of the colour kernel; the LUT
+// in the first 192 words of smem is already filled.
 template <int B, bool KEYS>
-__global__ __launch_bounds__(kLFThreads) void k_decode_rgb(RGBArgs a) {
+__device__ __forceinline__ void rgb_strip(const RGBArgs &a, int st, int part, uint32_t *smem) {
   constexpr int S = B * B, NBLK = 64 / B, H = B / 2, HR = B;   // HR rows per lane
-  extern __shared__ uint32_t smem[];
-  uint16_t *lut = reinterpret_cast<uint16_t *>(smem);   // 384 x u16 = 192 words
+  const uint16_t *lut = reinterpret_cast<const uint16_t *>(smem);   // 384 x u16 = 192 words
   uint32_t *s_o0 = smem + 192;                          // [3][NBLK] group start words
   uint32_t *s_any = smem + 288;                         // a wanted view in the chunk
   uint32_t *s_node = s_any + 4;                         // wanted nodes of the chunk, a bit each
@@ -1132,10 +1151,8 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_rgb(RGBArgs a) {
   uint32_t *keys = tile + lf_tile_words(a.tile_cap, S); // [3][n_top][B][NBLK * H]
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int st = (int)a.order[blockIdx.x / a.parts], part = blockIdx.x % a.parts;
   const int sx = st % a.nsx, by = st / a.nsx;
   const bool masked = a.vneed != nullptr;
-  for (int t = tid; t < kLutEntries; t += kLFThreads) lut[t] = lut_entry(t);
   if (tid < S / 2) tile[a.tile_cap * (S / 2) + tid] = 0u;
   if (tid < 64)
     for (int k = lane; k < 3 * NBLK; k += 64) {
@@ -1333,6 +1350,55 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_rgb(RGBArgs a) {
   }
 }
 
+template <int B, bool KEYS>
+__global__ __launch_bounds__(kLFThreads) void k_decode_rgb(RGBArgs a) {
+  extern __shared__ uint32_t smem[];
+  uint16_t *lut = reinterpret_cast<uint16_t *>(smem);
+  for (int t = threadIdx.x; t < kLutEntries; t += kLFThreads) lut[t] = lut_entry(t);
+  rgb_strip<B, KEYS>(a, (int)a.order[blockIdx.x / a.parts], blockIdx.x % a.parts, smem);
+}
+
+// The colour decode of several light fields in one persistent launch: the
+// work items are every light field's (strip, part) pairs, each light field's
+// strips costliest first; workgroups stay resident and take the next item
+// from a device counter until none is left.  The last workgroup to finish
+// puts the counters back to zero, so the next launch (or graph replay) needs
+// no clearing; launches that share counters must not overlap.
+struct RGBMultiArgs {
+  const RGBArgs *lfs;      // [n_lf], every one of block size B
+  const int32_t *first;    // [n_lf + 1] first work item of each light field (items = strips x parts)
+  int n_lf, n_items;
+  uint32_t *ctr;           // [2]: next work item, finished workgroups
+};
+
+template <int B, bool KEYS>
+__global__ __launch_bounds__(kLFThreads) void k_decode_rgb_multi(RGBMultiArgs m) {
+  extern __shared__ uint32_t smem[];
+  uint16_t *lut = reinterpret_cast<uint16_t *>(smem);
+  uint32_t *s_item = smem + 288 + 2;   // a free word of the chunk flags
+  for (int t = threadIdx.x; t < kLutEntries; t += kLFThreads) lut[t] = lut_entry(t);
+  const uniform_i32 first = as_uniform(m.first);
+  for (;;) {
+    __syncthreads();   // every wave is done with the previous item's LDS
+    if (threadIdx.x == 0) *s_item = atomicAdd(&m.ctr[0], 1u);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane((int)*s_item);
+    if (item >= m.n_items) break;
+    int lf = 0;
+    while (lf + 1 < m.n_lf && first[lf + 1] <= item) lf++;
+    const RGBArgs a = m.lfs[lf];
+    const int local = item - first[lf];
+    rgb_strip<B, KEYS>(a, (int)a.order[local / a.parts], local % a.parts, smem);
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&m.ctr[1], 1u) == gridDim.x - 1) {
+      atomicExch(&m.ctr[0], 0u);
+      atomicExch(&m.ctr[1], 0u);
+    }
+  }
+}
+
 // Novel views from fully decoded 8-bit RGB source views ([nv][hp][wp]): one
 // thread per output pixel, its 16 taps one word each, the same lerps as
 // render_tile.  Used when a batch of views needs about as many source blocks
@@ -1347,22 +1413,15 @@ struct InterpRGBArgs {
   float sxs, tys;   // W / wo and H / ho, rounded once on the host as the other renderers round them
 };
 
+// Output pixel (X, Yp) of view vw into o (its view's [3][ho][wo] planes).
 template <bool FOCAL>
-__global__ __launch_bounds__(kThreads) void k_interp_rgb(InterpRGBArgs a) {
-  // grid (row pieces, view, row): the workgroups that run together render one
-  // output row of every view, whose taps come from nearby rows of the same
-  // few source views, so the caches serve those rows once for all views
-  // (a grid that gave each of the eight dies its own band of rows measured
-  // no faster)
-  const int X = blockIdx.x * kThreads + threadIdx.x, n = blockIdx.y, Yp = blockIdx.z;
-  if (X >= a.wo) return;
-  const lfc_view vw = a.views[n];
+__device__ __forceinline__ void interp_rgb_pixel(const InterpRGBArgs &a, const lfc_view &vw, float *o, int X,
+                                                 int Yp) {
   int iu0, iu1, jv0, jv1, x0, x1, y0, y1;
   float fu, fv;
   cell(vw.u, a.U, iu0, iu1, fu);
   cell(vw.v, a.V, jv0, jv1, fv);
-  const float sxs = a.sxs, tys = a.tys;
-  const float sx = src_pos(vw.s, X, sxs), ty = src_pos(vw.t, Yp, tys);
+  const float sx = src_pos(vw.s, X, a.sxs), ty = src_pos(vw.t, Yp, a.tys);
   // taps through a buffer resource: 32-bit byte offsets from one base (the
   // decoded views take less than 4 GiB)
   const __amdgpu_buffer_rsrc_t rs =
@@ -1383,8 +1442,35 @@ __global__ __launch_bounds__(kThreads) void k_interp_rgb(InterpRGBArgs a) {
     P[k][2] = __builtin_amdgcn_raw_buffer_load_b32(rs, r1 + c0, 0, 0);
     P[k][3] = __builtin_amdgcn_raw_buffer_load_b32(rs, r1 + c1, 0, 0);
   }
-  const size_t plane = (size_t)a.ho * a.wo;
-  interp_store(P, fs, ft, fu, fv, a.out + (size_t)n * 3 * plane + (size_t)Yp * a.wo + X, plane);
+  interp_store(P, fs, ft, fu, fv, o + (size_t)Yp * a.wo + X, (size_t)a.ho * a.wo);
+}
+
+template <bool FOCAL>
+__global__ __launch_bounds__(kThreads) void k_interp_rgb(InterpRGBArgs a) {
+  // grid (row pieces, view, row): the workgroups that run together render one
+  // output row of every view, whose taps come from nearby rows of the same
+  // few source views, so the caches serve those rows once for all views
+  // (a grid that gave each of the eight dies its own band of rows measured
+  // no faster)
+  const int X = blockIdx.x * kThreads + threadIdx.x, n = blockIdx.y, Yp = blockIdx.z;
+  if (X >= a.wo) return;
+  interp_rgb_pixel<FOCAL>(a, a.views[n], a.out + (size_t)n * 3 * a.ho * a.wo, X, Yp);
+}
+
+// Requests of several light fields and output sizes interpolated in one
+// launch: workgroup (piece, request, row) exits when the request's output is
+// smaller.  A request's record carries its light field's decoded views
+// (views unused; the camera is in the record).
+struct InterpReq {
+  InterpRGBArgs a;
+  lfc_view view;
+};
+
+__global__ __launch_bounds__(kThreads) void k_interp_multi(const InterpReq *reqs) {
+  const InterpReq r = reqs[blockIdx.y];
+  const int X = blockIdx.x * kThreads + threadIdx.x, Yp = blockIdx.z;
+  if (X >= r.a.wo || Yp >= r.a.ho) return;
+  interp_rgb_pixel<false>(r.a, r.view, r.a.out, X, Yp);
 }
 
 // The source views a batch of novel views reads (the four grid neighbours of
@@ -1503,7 +1589,7 @@ lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s, int64_t 
   const int64_t key_words = (int64_t)g.n_top * NBLK * (B * B / 2) <= 4096 ? (int64_t)g.n_top * NBLK * (B * B / 2) : 0;
   if ((int64_t)3 * g.hp * g.wp >= ((int64_t)1 << 32))
     return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: view too large for the whole-field kernel");
-  const int64_t fixed = kLFHeadWords + (int64_t)lf_tile_words(lf->tile_cap, B * B) + key_words;
+  const int64_t fixed = kLFHeadWords + (int64_t)lf_tile_words(lf->tile_cap, B * B) + key_words + lfc::kLFTabWords;
   const int64_t limit = max_lds_bytes() / 4;
   if (fixed > limit)
     return fail(LFC_E_UNSUPPORTED, "lfc_decode_blocks: tree too large for the whole-field kernel; use BLOCKS layout");
@@ -2051,6 +2137,128 @@ lfc_status render_req_fill(const lfc_lf *lf, const lfc_view &v, int wo, int ho, 
   *ntiles = r.ntiles;
   *lds = pl.lds;
   return LFC_OK;
+}
+
+// ---- the colour decode-then-interpolate path of a batch -------------------
+
+namespace {
+
+// LDS words of the key-view rows of a colour strip, or 0 when they exceed the
+// kernel's staging budget (then read from global memory)
+int rgb_key_words(const lfc::Geometry &g) {
+  const int64_t kw = (int64_t)3 * g.n_top * g.B * 32;
+  return kw <= kRGBKeyWordsMax ? (int)kw : 0;
+}
+
+int rgb_parts(const lfc_lf *lf) {
+  const lfc::Geometry &g = lf->geo;
+  const int nblk = 64 / g.B, nstrips = g.nby * ((g.nbx + nblk - 1) / nblk);
+  return std::max(1, std::min(lf->rgb_max_chunks, (3 * 3 * device_cus() + nstrips - 1) / nstrips));
+}
+
+}  // namespace
+
+bool lf_rgb_batchable(const lfc_lf *lf, double out_pixels) {
+  const Geometry &g = lf->geo;
+  const size_t lds = 4 * ((size_t)kRGBHeadWords + (size_t)lf_tile_words(lf->tile_cap_rgb, g.B * g.B) +
+                          (size_t)rgb_key_words(g));
+  return (uint64_t)g.nv() * g.hp * g.wp * 4 < ((uint64_t)1 << 32) && g.nv() <= 32 * kRGBNeedWords &&
+         lds <= (size_t)max_lds_bytes() && 20.0 * out_pixels >= (double)g.nv() * g.hp * g.wp;
+}
+
+size_t lf_rgb_bytes(const lfc_lf *lf) { return rgb_bytes(lf->geo); }
+
+int lf_rgb_items(const lfc_lf *lf) {
+  const Geometry &g = lf->geo;
+  const int nblk = 64 / g.B;
+  return g.nby * ((g.nbx + nblk - 1) / nblk) * rgb_parts(lf);
+}
+
+int lf_views(const lfc_lf *lf) { return lf->geo.nv(); }
+
+size_t rgb_args_bytes() { return sizeof(RGBArgs); }
+
+void rgb_args_fill(const lfc_lf *lf, bool keys, uint32_t *d_rgb, const uint32_t *d_mask, void *dst) {
+  const Geometry &g = lf->geo;
+  const int nblk = 64 / g.B;
+  RGBArgs a{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_sched_rgb, lf->d_strip_off_rgb, lf->d_order_rgb, lf->d_batch,
+            d_mask, d_rgb, g.nbx, (g.nbx + nblk - 1) / nblk, g.L, g.q, g.wp, g.hp, g.nb, lf->n_batch, g.nv(),
+            g.n_top, keys ? rgb_key_words(g) : 0, lf->tile_cap_rgb, rgb_parts(lf)};
+  std::memcpy(dst, &a, sizeof a);
+}
+
+size_t rgb_lds_bytes(const lfc_lf *lf, bool keys) {
+  const Geometry &g = lf->geo;
+  return 4 * ((size_t)kRGBHeadWords + (size_t)lf_tile_words(lf->tile_cap_rgb, g.B * g.B) +
+              (size_t)(keys ? rgb_key_words(g) : 0));
+}
+
+bool rgb_keys_fit(const lfc_lf *lf) { return rgb_key_words(lf->geo) > 0; }
+
+void need_mask_host(const lfc_lf *lf, const lfc_view &v, uint32_t *mask) {
+  const Geometry &g = lf->geo;
+  // the grid cell the renderers read (cell() on the device, the same float
+  // clamp and floor)
+  auto cell_host = [](float x, int n, int &i0, int &i1) {
+    x = std::fmin(std::fmax(x, 0.0f), (float)(n - 1));
+    if (n == 1) {
+      i0 = i1 = 0;
+      return;
+    }
+    int i = (int)std::floor(x);
+    i = std::min(std::max(i, 0), n - 2);
+    i0 = i;
+    i1 = i + 1;
+  };
+  int iu0, iu1, jv0, jv1;
+  cell_host(v.u, g.U, iu0, iu1);
+  cell_host(v.v, g.V, jv0, jv1);
+  for (int vi : {jv0 * g.U + iu0, jv0 * g.U + iu1, jv1 * g.U + iu0, jv1 * g.U + iu1}) mask[vi >> 5] |= 1u << (vi & 31);
+}
+
+size_t interp_req_bytes() { return sizeof(InterpReq); }
+
+void interp_req_fill(const lfc_lf *lf, const uint32_t *d_rgb, const lfc_view &v, int wo, int ho, float *out,
+                     void *dst) {
+  const Geometry &g = lf->geo;
+  InterpReq r{};
+  r.a = InterpRGBArgs{d_rgb, (uint32_t)rgb_bytes(g), nullptr, out, wo, ho, g.U, g.V, g.W, g.H, g.wp, g.hp, 0.0f,
+                      (float)g.W / (float)wo, (float)g.H / (float)ho};
+  r.view = v;
+  std::memcpy(dst, &r, sizeof r);
+}
+
+lfc_status rgb_multi_launch(int block, bool keys, const void *d_args, const int32_t *d_first, int n_lf, int n_items,
+                            size_t lds, uint32_t *d_ctr, hipStream_t s) {
+  if (n_items <= 0) return LFC_OK;
+  RGBMultiArgs m{static_cast<const RGBArgs *>(d_args), d_first, n_lf, n_items, d_ctr};
+  // resident workgroups: as many as the compute units hold at this LDS size
+  auto launch = [&](auto kern) -> lfc_status {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kLFThreads, lds) != hipSuccess || per_cu < 1) {
+      (void)hipGetLastError();
+      per_cu = 1;
+    }
+    const int grid = std::max(1, std::min(n_items, per_cu * device_cus()));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kLFThreads), lds, s, m);
+    return launched("lfc_batch_render");
+  };
+  switch (block * 2 + (keys ? 1 : 0)) {
+    case 5: return launch(k_decode_rgb_multi<2, true>);
+    case 4: return launch(k_decode_rgb_multi<2, false>);
+    case 9: return launch(k_decode_rgb_multi<4, true>);
+    case 8: return launch(k_decode_rgb_multi<4, false>);
+    case 17: return launch(k_decode_rgb_multi<8, true>);
+    default: return launch(k_decode_rgb_multi<8, false>);
+  }
+}
+
+lfc_status interp_multi_launch(const void *d_reqs, int n, int max_wo, int max_ho, hipStream_t s) {
+  if (n <= 0) return LFC_OK;
+  if (n > 65535) return fail(LFC_E_INVALID, "lfc_batch_render: at most 65535 interpolated requests per batch");
+  const dim3 grid((unsigned)((max_wo + kThreads - 1) / kThreads), (unsigned)n, (unsigned)max_ho);
+  hipLaunchKernelGGL(k_interp_multi, grid, dim3(kThreads), 0, s, static_cast<const InterpReq *>(d_reqs));
+  return launched("lfc_batch_render");
 }
 
 lfc_status render_multi_launch(int block, const void *d_reqs, int n, int max_tiles, size_t lds, hipStream_t s) {

@@ -27,7 +27,8 @@ using lfc::fail;
 
 namespace {
 
-constexpr int kSlots = 4;   // request tables in flight per batch context
+constexpr int kSlots = 4;       // request tables in flight per batch context
+constexpr int kCtrStride = 16;  // words between two slots' counters (one cache line each)
 
 // A request table: pinned host staging and its device copy.  `done` is
 // recorded after the launches that read the table; the slot is rewritten
@@ -40,6 +41,18 @@ struct Slot {
   bool used = false;
 };
 
+// Decoded views of one light field (8-bit RGB words) for the colour path of
+// a batch, kept by the context for later batches.  `done` is recorded after
+// the launches that read it; a later batch, on any stream, waits for it
+// before decoding into the same buffer.
+struct Scratch {
+  const lfc_lf *lf = nullptr;
+  void *buf = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+  bool used = false;
+};
+
 }  // namespace
 
 struct lfc_batch {
@@ -47,6 +60,8 @@ struct lfc_batch {
   Slot slot[kSlots];
   int next = 0;
   int32_t *d_err = nullptr;   // set by a batched decode that saw an out-of-range request
+  uint32_t *d_ctr = nullptr;  // per slot, the persistent colour decode's two counters (zero between launches)
+  std::deque<Scratch> scratch;   // (a deque: adding one keeps the others' addresses)
 };
 
 namespace {
@@ -108,7 +123,9 @@ extern "C" lfc_status lfc_batch_create(lfc_batch **out) {
     }
   }
   if (hipMalloc(reinterpret_cast<void **>(&b->d_err), sizeof(int32_t)) != hipSuccess ||
-      hipMemset(b->d_err, 0, sizeof(int32_t)) != hipSuccess) {
+      hipMemset(b->d_err, 0, sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void **>(&b->d_ctr), kSlots * kCtrStride * sizeof(uint32_t)) != hipSuccess ||
+      hipMemset(b->d_ctr, 0, kSlots * kCtrStride * sizeof(uint32_t)) != hipSuccess) {
     (void)lfc_batch_destroy(b);
     return fail(LFC_E_NOMEM, "lfc_batch_create: error flag");
   }
@@ -125,12 +142,42 @@ extern "C" lfc_status lfc_batch_destroy(lfc_batch *b) {
     }
     free_slot(sl);
   }
+  for (Scratch &sc : b->scratch) {
+    if (sc.used) (void)hipEventSynchronize(sc.done);
+    if (sc.done) (void)hipEventDestroy(sc.done);
+    if (sc.buf) (void)hipFree(sc.buf);
+  }
   if (b->d_err) (void)hipFree(b->d_err);
+  if (b->d_ctr) (void)hipFree(b->d_ctr);
   delete b;
   return LFC_OK;
 }
 
 namespace {
+
+// The context's scratch for lf's decoded views: an existing buffer that
+// holds them, else a new one; nullptr if there is no room (the caller then
+// renders that light field by tiles).
+Scratch *get_scratch(lfc_batch *b, const lfc_lf *lf) {
+  const size_t need = lfc::lf_rgb_bytes(lf);
+  for (Scratch &sc : b->scratch)
+    if (sc.lf == lf && sc.bytes >= need) return &sc;
+  Scratch sc;
+  sc.lf = lf;
+  sc.bytes = need;
+  if (hipMalloc(&sc.buf, need) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (hipEventCreateWithFlags(&sc.done, hipEventDisableTiming) != hipSuccess) {
+    (void)hipFree(sc.buf);
+    return nullptr;
+  }
+  b->scratch.push_back(sc);
+  return &b->scratch.back();
+}
+
+size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 // lfc_batch_render; with check_outs false the output pointers are trusted to
 // hold their results (the server's pool offsets, sized when admitted).
@@ -147,15 +194,8 @@ lfc_status batch_render(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf, co
   for (int i = 0; i < n_lf; i++)
     if (!lfs[i] || lfc::lf_device(lfs[i]) != dev)
       return fail(LFC_E_INVALID, "lfc_batch_render: null handle or handle of another device");
-  // pack, grouped by block size (one launch each)
-  const size_t rb = lfc::render_req_bytes();
-  std::vector<char> packed((size_t)n * rb);
-  struct Group {
-    int count = 0, max_tiles = 0;
-    size_t lds = 0;
-  } grp[9];
-  std::vector<int> bs(n), order;
-  order.reserve(n);
+  // requests checked; output pixels per light field
+  std::vector<double> px(n_lf, 0.0);
   for (int i = 0; i < n; i++) {
     const lfc_render_request &r = reqs[i];
     if (r.lf < 0 || r.lf >= n_lf) return fail(LFC_E_INVALID, "lfc_batch_render: request lf index out of range");
@@ -167,6 +207,40 @@ lfc_status batch_render(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf, co
       if (lfc_status st = lfc::device_buffer(d_outs[i], (size_t)3 * r.out_w * r.out_h * sizeof(float), 4, who,
                                              "d_outs[i]"))
         return st;
+    px[(size_t)r.lf] += (double)r.out_w * r.out_h;
+  }
+  // a light field whose requests cover about as many pixels as it holds is
+  // decoded once (the views they read, as 8-bit RGB) and interpolated; the
+  // others render by tiles, each tile decoding its own footprint
+  std::vector<Scratch *> scr((size_t)n_lf, nullptr);
+  for (int l = 0; l < n_lf; l++)
+    if (px[(size_t)l] > 0.0 && lfc::lf_rgb_batchable(lfs[l], px[(size_t)l])) scr[(size_t)l] = get_scratch(b, lfs[l]);
+  // the table: tile requests grouped by block size; per block size the colour
+  // decode's light-field records and first work items; the view masks; the
+  // interpolated requests
+  const size_t rb = lfc::render_req_bytes(), ab = lfc::rgb_args_bytes(), ib = lfc::interp_req_bytes();
+  struct Group {
+    int count = 0, max_tiles = 0;
+    size_t lds = 0;
+    std::vector<int> lf;       // colour-decoded light fields of this block size
+    bool keys = true;
+    size_t rgb_lds = 0;
+    int items = 0;
+    size_t at_args = 0, at_first = 0;
+  } grp[9];
+  std::vector<char> packed;
+  std::vector<int> bs(n, 0), order;
+  order.reserve(n);
+  int n_interp = 0, max_wo = 0, max_ho = 0;
+  packed.resize((size_t)n * rb);
+  for (int i = 0; i < n; i++) {
+    const lfc_render_request &r = reqs[i];
+    if (scr[(size_t)r.lf]) {
+      n_interp++;
+      max_wo = std::max(max_wo, r.out_w);
+      max_ho = std::max(max_ho, r.out_h);
+      continue;
+    }
     int block = 0, nt = 0;
     size_t lds = 0;
     if (lfc_status st = lfc::render_req_fill(lfs[r.lf], r.view, r.out_w, r.out_h, d_outs[i], &packed[(size_t)i * rb],
@@ -184,23 +258,95 @@ lfc_status batch_render(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf, co
   for (int block : {2, 4, 8})
     for (int i = 0; i < n; i++)
       if (bs[i] == block) order.push_back(i);
+  size_t at = align16(order.size() * rb);
+  for (int l = 0; l < n_lf; l++)
+    if (scr[(size_t)l]) grp[lfc::lf_block(lfs[l])].lf.push_back(l);
+  for (int block : {2, 4, 8}) {
+    Group &gp = grp[block];
+    if (gp.lf.empty()) continue;
+    for (int l : gp.lf) gp.keys = gp.keys && lfc::rgb_keys_fit(lfs[l]);
+    for (int l : gp.lf) gp.rgb_lds = std::max(gp.rgb_lds, lfc::rgb_lds_bytes(lfs[l], gp.keys));
+    gp.at_args = at;
+    at = align16(at + gp.lf.size() * ab);
+    gp.at_first = at;
+    at = align16(at + 4 * (gp.lf.size() + 1));
+  }
+  std::vector<size_t> at_mask((size_t)n_lf, 0);
+  for (int l = 0; l < n_lf; l++)
+    if (scr[(size_t)l]) {
+      at_mask[(size_t)l] = at;
+      at = align16(at + 4 * (size_t)((lfc::lf_views(lfs[l]) + 31) / 32));
+    }
+  const size_t at_interp = at;
+  at = align16(at + (size_t)n_interp * ib);
   Slot &sl = b->slot[b->next];
-  if (lfc_status st = grow_slot(sl, (size_t)n * rb)) return st;
+  if (lfc_status st = grow_slot(sl, at)) return st;
   // the kernels that read the slot's previous table must have finished
   if (sl.used && hipEventSynchronize(sl.done) != hipSuccess) return fail(LFC_E_HIP, "lfc_batch_render: event wait");
   sl.used = false;
-  for (int k = 0; k < n; k++) std::memcpy(sl.host + (size_t)k * rb, &packed[(size_t)order[k] * rb], rb);
-  if (hipMemcpyAsync(sl.dev, sl.host, (size_t)n * rb, hipMemcpyHostToDevice, s) != hipSuccess)
+  for (size_t k = 0; k < order.size(); k++) std::memcpy(sl.host + k * rb, &packed[(size_t)order[k] * rb], rb);
+  for (int block : {2, 4, 8}) {
+    Group &gp = grp[block];
+    int32_t *first = reinterpret_cast<int32_t *>(sl.host + gp.at_first);
+    int items = 0;
+    for (size_t k = 0; k < gp.lf.size(); k++) {
+      const int l = gp.lf[k];
+      lfc::rgb_args_fill(lfs[l], gp.keys, static_cast<uint32_t *>(scr[(size_t)l]->buf),
+                         reinterpret_cast<const uint32_t *>(sl.dev + at_mask[(size_t)l]), sl.host + gp.at_args + k * ab);
+      first[k] = items;
+      items += lfc::lf_rgb_items(lfs[l]);
+    }
+    if (!gp.lf.empty()) first[gp.lf.size()] = items;
+    gp.items = items;
+  }
+  for (int l = 0; l < n_lf; l++)
+    if (scr[(size_t)l])
+      std::memset(sl.host + at_mask[(size_t)l], 0, 4 * (size_t)((lfc::lf_views(lfs[l]) + 31) / 32));
+  int k_interp = 0;
+  for (int i = 0; i < n; i++) {
+    const lfc_render_request &r = reqs[i];
+    if (!scr[(size_t)r.lf]) continue;
+    lfc::need_mask_host(lfs[r.lf], r.view, reinterpret_cast<uint32_t *>(sl.host + at_mask[(size_t)r.lf]));
+    lfc::interp_req_fill(lfs[r.lf], static_cast<uint32_t *>(scr[(size_t)r.lf]->buf), r.view, r.out_w, r.out_h,
+                         d_outs[i], sl.host + at_interp + (size_t)k_interp * ib);
+    k_interp++;
+  }
+  if (hipMemcpyAsync(sl.dev, sl.host, at, hipMemcpyHostToDevice, s) != hipSuccess)
     return fail(LFC_E_HIP, std::string(who) + ": copy of the request table");
+  uint32_t *ctr = b->d_ctr + (size_t)b->next * kCtrStride;
   b->next = (b->next + 1) % kSlots;
   lfc_status st = LFC_OK;
-  int at = 0;
+  size_t tile_at = 0;
   for (int block : {2, 4, 8}) {
     const Group &gp = grp[block];
     if (!gp.count) continue;
-    if (st == LFC_OK) st = lfc::render_multi_launch(block, sl.dev + (size_t)at * rb, gp.count, gp.max_tiles, gp.lds, s);
-    at += gp.count;
+    if (st == LFC_OK)
+      st = lfc::render_multi_launch(block, sl.dev + tile_at, gp.count, gp.max_tiles, gp.lds, s);
+    tile_at += (size_t)gp.count * rb;
   }
+  // the colour path: a decoded-views buffer is rewritten only after the
+  // launches of an earlier batch that read it (on any stream) have finished
+  for (int l = 0; l < n_lf && st == LFC_OK; l++)
+    if (scr[(size_t)l] && scr[(size_t)l]->used && hipStreamWaitEvent(s, scr[(size_t)l]->done, 0) != hipSuccess)
+      st = fail(LFC_E_HIP, std::string(who) + ": wait for an earlier use of the decoded views");
+  for (int block : {2, 4, 8}) {
+    const Group &gp = grp[block];
+    if (gp.lf.empty() || st != LFC_OK) continue;
+    st = lfc::rgb_multi_launch(block, gp.keys, sl.dev + gp.at_args,
+                               reinterpret_cast<const int32_t *>(sl.dev + gp.at_first), (int)gp.lf.size(), gp.items,
+                               gp.rgb_lds, ctr, s);
+  }
+  if (st == LFC_OK && n_interp) st = lfc::interp_multi_launch(sl.dev + at_interp, n_interp, max_wo, max_ho, s);
+  for (int l = 0; l < n_lf; l++)
+    if (scr[(size_t)l]) {
+      if (hipEventRecord(scr[(size_t)l]->done, s) == hipSuccess) {
+        scr[(size_t)l]->used = true;
+      } else {
+        (void)hipStreamSynchronize(s);
+        scr[(size_t)l]->used = false;
+        if (st == LFC_OK) st = fail(LFC_E_HIP, std::string(who) + ": event record");
+      }
+    }
   return release_slot(sl, st, s, who);
 }
 

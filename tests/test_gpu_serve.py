@@ -84,6 +84,46 @@ def test_batch_matches_single_renders_and_oracle(fields):
     b.close()
 
 
+def test_dense_batch_over_two_light_fields(gpu):
+    # a batch that covers most of two light fields (an 8x8 light field of
+    # 64x64 views and a 9x9 lenslet-like one, 64 novel 128x96 views): each is
+    # decoded once by the persistent colour kernel (both in one launch) and
+    # interpolated in one launch; every result equals the light field's own
+    # render of it, and the oracle's to 1e-5.  Six calls in a row reuse every
+    # table slot and its work counters.
+    specs = [(8, 8, 64, 64, dict(block=4, levels=2, cluster=(2,), blk_threshold=2)),
+             (9, 9, 125, 87, dict(block=4, levels=3, cluster=(2, 2), blk_threshold=40, quant_bits=2))]
+    encs = [oracle_encode(make_lf(U, V, W, H, seed=300 + U, vignetting=U == 9), **kw) for U, V, W, H, kw in specs]
+    lfs = [lfc.lfc_open(e.stream) for e in encs]
+    rng = np.random.default_rng(302)
+    reqs = []
+    for k in range(64):
+        li = k % 2
+        U, V = specs[li][0], specs[li][1]
+        reqs.append((li, 128, 96, (rng.uniform(0, U - 1), rng.uniform(0, V - 1), rng.uniform(-1, 1),
+                                   rng.uniform(-1, 1))))
+    say("dense batch over two light fields")
+    b = lfc.Batch()
+    outs = b.render(lfs, reqs)
+    for li in range(2):
+        mine = [(r, o) for r, o in zip(reqs, outs) if r[0] == li]
+        views = torch.tensor([r[3] for r, _ in mine], dtype=torch.float32, device="cuda")
+        own = lfc.lfc_render_views(lfs[li], views, 128, 96)
+        for (r, o), ref in zip(mine, own):
+            assert torch.equal(o, ref), r
+        U, V, W, H, _ = specs[li]
+        got = torch.stack([o for _, o in mine[:4]]).cpu().numpy()
+        ref = oracle.render(encs[li].r0, U, V, W, H, np.array([r[3] for r, _ in mine[:4]], dtype=np.float32), 128, 96)
+        assert max_abs(got, ref) <= 1e-5
+    for call in range(6):
+        again = b.render(lfs, reqs)
+        for o, o2 in zip(outs, again):
+            assert torch.equal(o, o2), call
+    b.close()
+    for lf in lfs:
+        lf.close()
+
+
 def test_batch_argument_errors(fields):
     _, lfs = fields
     lib = lfc.load()
