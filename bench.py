@@ -355,9 +355,14 @@ def main():
             rfn()
         r = time_launches(rfn, 10, torch)
         out_bytes = 64 * 3 * 512 * 512 * 4
+        # algorithmic bytes of the launch: the float output written once and
+        # the compressed light field (key views, offsets, SRV section) read once
+        render_bytes = out_bytes + len(stream40)
         extra["render_full40"] = dict(views_per_launch=64, ms_per_launch=round(float(r.mean()), 4),
                                       views_per_s=round(64 / (r.mean() * 1e-3), 1),
-                                      output_write_frac_of_hbm=round(out_bytes / (r.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+                                      output_write_frac_of_hbm=round(out_bytes / (r.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                      roofline=dict(bound="hbm", algorithmic_bytes=render_bytes,
+                                                    frac=round(render_bytes / (r.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)))
         # plain kernel: one launch per 512x512 view request
         one = torch.from_numpy(synth.novel_views(200, 17, 17, seed=303)).cuda()
         img1 = torch.empty((1, 3, 512, 512), dtype=torch.float32, device="cuda")
@@ -402,9 +407,22 @@ def main():
         afn = lambda: lfc.lfc_decode_blocks(lf, req, lfc.LAYOUT_BLOCKS, out=blk)
         afn()
         a = time_launches(afn, 10, torch)
+        # algorithmic bytes of one access (Alg. 2 for the three channels of one
+        # block): per channel the group's two offsets (8 B) and the key-view
+        # block (2 B^2), and per residual level the bitmap word, the two
+        # directory words and, with the stream's presence rate, a stored
+        # block's mean payload; then the int16 output (3 x 2 B^2)
+        n_levels = max(0, w40.levels - 1)
+        presence = int(st40["present_blocks"]) / max(1, info.n_groups * info.n_srv)
+        pay = srv_bytes / max(1, int(st40["present_blocks"]))
+        per_access = 3 * (8 + 2 * 16 + n_levels * (4 + 8 + presence * pay)) + 3 * 2 * 16
+        ra_bytes = per_access * 1_000_000
         extra["random_access"] = dict(requests=1_000_000, ms=round(float(a.mean()), 4),
                                       ns_per_access=round(float(a.mean()) * 1e6 / 1e6, 3),
-                                      gsamples_per_s=round(48e6 / (a.mean() * 1e-3) / 1e9, 2))
+                                      gsamples_per_s=round(48e6 / (a.mean() * 1e-3) / 1e9, 2),
+                                      roofline=dict(bound="hbm", algorithmic_bytes_per_access=round(per_access, 1),
+                                                    achieved_gbs=round(ra_bytes / (a.mean() * 1e-3) / 1e9, 1),
+                                                    frac=round(ra_bytes / (a.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)))
         lfc.lfc_check(lf)
         del blk, req
         # 50 dB coding of the same light field
@@ -430,9 +448,13 @@ def main():
         lfn = lambda: lfc.lfc_render_views(lfl, vl, 512, 512, out=imgl)
         lfn()
         rl = time_launches(lfn, 10, torch)
+        render_bytes_l = 64 * 3 * 512 * 512 * 4 + len(streaml)
         extra["render_lenslet40"] = dict(psnr_db=round(stl["psnr"], 3), views_per_launch=64,
                                          ms_per_launch=round(float(rl.mean()), 4),
-                                         views_per_s=round(64 / (rl.mean() * 1e-3), 1))
+                                         views_per_s=round(64 / (rl.mean() * 1e-3), 1),
+                                         roofline=dict(bound="hbm", algorithmic_bytes=render_bytes_l,
+                                                       frac=round(render_bytes_l / (rl.mean() * 1e-3) / 1e9
+                                                                  / HBM_PEAK_GBS, 4)))
         bestl, _ = lfc.lfc_render_tune(lfl, vl, 512, 512, out=imgl, reps=5)
         planl = lfc.RenderPlan(lfl, vl, 512, 512, out=imgl, cfg=bestl, graph=True)
         planl.launch()

@@ -630,6 +630,14 @@ typedef struct {
   int32_t max_batch;        /* requests per launch, 1..65535 */
   int32_t streams;          /* launches in flight, 1..8; each on a stream of its own */
   int64_t out_pool_bytes;   /* device bytes for results, >= 256 */
+  int64_t max_queue;        /* requests waiting for admission at most (0: no limit); a submit
+                               beyond it is refused with LFC_E_NOMEM */
+  int64_t device_bytes_cap; /* device memory the server may count on (0: no cap): the resident
+                               light fields (lfc_info device_bytes) plus the output pool must fit
+                               (else lfc_server_create refuses with LFC_E_NOMEM); the decoded-view
+                               buffers of the batches' colour path (one per light field and
+                               stream) are granted from what remains, light field by light field
+                               in order, and a light field without one renders by tiles */
 } lfc_server_config;
 
 typedef struct {
@@ -640,12 +648,14 @@ typedef struct {
 } lfc_server_stats;
 
 /* Copies the lfs array (the handles must outlive the server).  Errors:
- * LFC_E_INVALID, LFC_E_NOMEM, LFC_E_HIP. */
+ * LFC_E_INVALID, LFC_E_NOMEM (no host memory, no output pool, or the light
+ * fields and pool exceed device_bytes_cap), LFC_E_HIP. */
 lfc_status lfc_server_create(const lfc_lf *const *lfs, int32_t n_lf, const lfc_server_config *cfg,
                              lfc_server **out);
 
 /* Queues one request; *ticket identifies it.  Thread-safe.  Errors:
- * LFC_E_INVALID (bad index or size, or an output larger than the pool). */
+ * LFC_E_INVALID (bad index or size, or an output larger than the pool),
+ * LFC_E_NOMEM (max_queue requests already wait for admission). */
 lfc_status lfc_server_submit(lfc_server *sv, const lfc_render_request *req, uint64_t *ticket);
 
 /* Blocks until the request is done (timeout_ms < 0: no limit); *d_img is
@@ -663,7 +673,8 @@ lfc_status lfc_server_release(lfc_server *sv, uint64_t ticket);
 
 /* Submits reqs[i] at arrival_ms[i] after the call starts (non-decreasing
  * times), results discarded on completion, and returns once all are done
- * with latency_ms[i] (host array of n) from each arrival to completion. */
+ * with latency_ms[i] (host array of n) from each arrival to completion;
+ * a request refused because the queue was full gets latency -1. */
 lfc_status lfc_server_replay(lfc_server *sv, const lfc_render_request *reqs, const double *arrival_ms, int32_t n,
                              double *latency_ms);
 

@@ -550,9 +550,28 @@ static void make_strip_tables(const Geometry &g, const std::vector<uint32_t> &of
     t.need[2 * st + 1] = (uint32_t)sw;
     t.max_words = std::max(t.max_words, t.need[2 * st]);
   }
-  t.order.resize(nst);
-  for (size_t i = 0; i < nst; i++) t.order[i] = (uint32_t)i;
-  std::stable_sort(t.order.begin(), t.order.end(), [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
+  std::vector<uint32_t> perm(nst);
+  for (size_t i = 0; i < nst; i++) perm[i] = (uint32_t)i;
+  std::stable_sort(perm.begin(), perm.end(), [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
+  // one order entry per workgroup (order_words): strip, schedule start and
+  // length, then the strip's group starts and lengths
+  const int ow = order_words(g.B);
+  t.order.assign(nst * (size_t)ow, 0u);
+  for (size_t i = 0; i < nst; i++) {
+    const uint32_t st = perm[i];
+    uint32_t *e = &t.order[i * (size_t)ow];
+    const int sx = (int)(st % nsx), by = (int)((st / nsx) % g.nby), c = (int)(st / ((size_t)nsx * g.nby));
+    e[0] = st;
+    e[1] = t.strip_off[st];
+    e[2] = t.strip_off[st + 1] - t.strip_off[st];
+    for (int j = 0; j < nblk; j++) {
+      const int bx = sx * nblk + j;
+      if (bx >= g.nbx) continue;
+      const size_t gi = 3 * ((size_t)by * g.nbx + bx) + c;
+      e[4 + j] = off[gi];
+      e[4 + nblk + j] = off[gi + 1] - off[gi];
+    }
+  }
 }
 
 // The colour kernel's strip tables: schedule and the order in which

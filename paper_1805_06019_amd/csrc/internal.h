@@ -42,6 +42,11 @@ constexpr int kBatchWords = 16;
 // compact tile (32 KB of LDS; tile slots are 11-bit, beside a 5-bit block
 // index in 16-bit schedule items, so at most 2048).
 constexpr int tile_blocks(int B) { return B == 2 ? 2048 : (B == 4 ? 1024 : 256); }
+// Words per entry of the whole-field kernel's strip order: the strip, its
+// decode schedule's first word and length, a spare word, then its 64/B
+// groups' start words and lengths (zero past the image's right edge), so a
+// workgroup reads everything it needs to start a strip in one load.
+constexpr int order_words(int B) { return 4 + 2 * (64 / B); }
 // Most words of a chunk's gather table (per-node masks and first slots,
 // per-run node positions) in the whole-field kernel's schedule: the kernel
 // copies a chunk's table into LDS when the strip is read from global memory.

@@ -66,18 +66,29 @@ __device__ __forceinline__ uint32_t block_bits(uint32_t code) {
 // Digits of a trit field (entries 0..255: five 2-bit digits) or of a quint
 // field (entries 256..383: three 3-bit digits).  Out-of-range fields map to 0;
 // streams holding them are rejected before upload.
-__device__ __forceinline__ uint16_t lut_entry(int t) {
+constexpr uint32_t lut_value(int t) {
   uint32_t v = 0;
   if (t < 256) {
     if (t < 243)
-      for (int r = 0, x = t; r < 5; r++, x /= 3) v |= (uint32_t)(x % 3) << (2 * r);
-  } else {
-    const int q = t - 256;
-    if (q < 125)
-      for (int r = 0, x = q; r < 3; r++, x /= 5) v |= (uint32_t)(x % 5) << (3 * r);
+      for (int r = 0, x = t, p = 0; r < 5; r++, x /= 3, p += 2) v |= (uint32_t)(x % 3) << p;
+  } else if (t - 256 < 125) {
+    for (int r = 0, x = t - 256, p = 0; r < 3; r++, x /= 5, p += 3) v |= (uint32_t)(x % 5) << p;
   }
-  return (uint16_t)v;
+  return v;
 }
+__device__ __forceinline__ uint16_t lut_entry(int t) { return (uint16_t)lut_value(t); }
+
+// The LUT, two entries per word, as a table in device memory (the
+// whole-field kernel copies it into LDS instead of computing it).
+struct LutWords {
+  uint32_t w[kLutEntries / 2];
+};
+constexpr LutWords make_lut_words() {
+  LutWords l{};
+  for (int t = 0; t < kLutEntries; t++) l.w[t / 2] |= lut_value(t) << (16 * (t & 1));
+  return l;
+}
+__device__ constexpr LutWords kLutTable = make_lut_words();
 
 // 64 bits of a group's bit stream starting at bit pos (bit p is bit p%32 of word p/32).
 __device__ __forceinline__ uint64_t window64(const uint32_t *gw, uint32_t pos) {
@@ -586,20 +597,25 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   // the workgroup's strip (strips are taken costliest first, so the last
   // workgroups to start are short ones)
-  const int st = (int)a.order[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x];
+  // (its order entry: the strip, its schedule, its groups; one load)
+  constexpr int OW = lfc::order_words(B);
+  const uint32_t *ent = a.order + (size_t)((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * OW;
+  const uniform_i32 uent = as_uniform(reinterpret_cast<const int32_t *>(ent));
+  const int st = uent[0];
   const int sx = st % (int)gridDim.x, by = (st / (int)gridDim.x) % (int)gridDim.y, c = st / ((int)gridDim.x * (int)gridDim.y);
-  const uint32_t sched0 = a.strip_off[st], sched_len = a.strip_off[st + 1] - sched0;
-  for (int t = tid; t < kLutEntries; t += kLFThreads) lut[t] = lut_entry(t);
+  const uint32_t sched0 = (uint32_t)uent[1], sched_len = (uint32_t)uent[2];
+  // the LUT from its table (a copy straight into LDS)
+  if (tid < kLutEntries / 2) __builtin_amdgcn_global_load_lds(
+      (const __attribute__((address_space(1))) void *)(kLutTable.w + tid),
+      (__attribute__((address_space(3))) void *)(smem + (tid & ~63)), 4, 0, 0);
   if (tid < S / 2) tile[a.tile_cap * (S / 2) + tid] = 0u;   // the slot of every absent block
   if (tid < 64) {
     // wave 0: the strip's group offsets and lengths, their exclusive prefix
     // sum (a wave scan) and the staging tier
-    const int bx = sx * NBLK + lane;
     uint32_t o0 = 0, len = 0;
-    if (lane < NBLK && bx < a.nbx) {
-      const int g = 3 * (by * a.nbx + bx) + c;
-      o0 = a.off[g];
-      len = a.off[g + 1] - o0;
+    if (lane < NBLK) {
+      o0 = ent[4 + lane];
+      len = ent[4 + NBLK + lane];
     }
     uint32_t incl = len;
 #pragma unroll

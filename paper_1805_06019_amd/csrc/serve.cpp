@@ -182,7 +182,8 @@ size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 // lfc_batch_render; with check_outs false the output pointers are trusted to
 // hold their results (the server's pool offsets, sized when admitted).
 lfc_status batch_render(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf, const lfc_render_request *reqs,
-                        int32_t n, float *const *d_outs, hipStream_t s, bool check_outs) {
+                        int32_t n, float *const *d_outs, hipStream_t s, bool check_outs,
+                        const char *allow_rgb = nullptr) {
   const char *who = "lfc_batch_render";
   if (!b) return fail(LFC_E_INVALID, "lfc_batch_render: null batch");
   if (n < 0) return fail(LFC_E_INVALID, "lfc_batch_render: n < 0");
@@ -214,7 +215,8 @@ lfc_status batch_render(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf, co
   // others render by tiles, each tile decoding its own footprint
   std::vector<Scratch *> scr((size_t)n_lf, nullptr);
   for (int l = 0; l < n_lf; l++)
-    if (px[(size_t)l] > 0.0 && lfc::lf_rgb_batchable(lfs[l], px[(size_t)l])) scr[(size_t)l] = get_scratch(b, lfs[l]);
+    if (px[(size_t)l] > 0.0 && (!allow_rgb || allow_rgb[l]) && lfc::lf_rgb_batchable(lfs[l], px[(size_t)l]))
+      scr[(size_t)l] = get_scratch(b, lfs[l]);
   // the table: tile requests grouped by block size; per block size the colour
   // decode's light-field records and first work items; the view masks; the
   // interpolated requests
@@ -483,6 +485,7 @@ struct Lane {                  // one launch slot: a stream, its batch context, 
 
 struct lfc_server {
   std::vector<const lfc_lf *> lfs;
+  std::vector<char> allow_rgb;   // per light field: its batches may use the colour path (memory granted)
   lfc_server_config cfg{};
   int device = 0;
   char *d_pool = nullptr;
@@ -580,7 +583,7 @@ void engine_loop(lfc_server *sv) {
         sv->stats.max_batch_seen = std::max<int64_t>(sv->stats.max_batch_seen, (int64_t)ids.size());
         lk.unlock();
         lfc_status st = batch_render(ln.batch, lfs.data(), (int32_t)lfs.size(), reqs.data(), (int32_t)reqs.size(),
-                                     outs.data(), ln.stream, false);
+                                     outs.data(), ln.stream, false, sv->allow_rgb.data());
         if (st == LFC_OK && hipEventRecord(ln.done, ln.stream) != hipSuccess) st = LFC_E_HIP;
         if (st != LFC_OK) {
           // a failure after some of the batch's launches were queued (one per
@@ -629,6 +632,8 @@ lfc_status submit_locked(lfc_server *sv, const lfc_render_request &r, bool disca
   const size_t bytes = result_bytes(r);
   if (((bytes + 255) & ~(size_t)255) > (size_t)sv->cfg.out_pool_bytes)
     return fail(LFC_E_INVALID, "lfc_server_submit: result larger than the output pool");
+  if (sv->cfg.max_queue > 0 && (int64_t)sv->queue.size() >= sv->cfg.max_queue)
+    return fail(LFC_E_NOMEM, "lfc_server_submit: the queue is full (max_queue requests wait for admission)");
   const uint64_t t_id = sv->next_ticket++;
   Ticket &t = sv->tickets[t_id];
   t.req = r;
@@ -650,8 +655,9 @@ extern "C" lfc_status lfc_server_create(const lfc_lf *const *lfs, int32_t n_lf, 
   *out = nullptr;
   if (!lfs || n_lf < 1 || !cfg) return fail(LFC_E_INVALID, "lfc_server_create: null argument or no light field");
   if (cfg->max_batch < 1 || cfg->max_batch > 65535 || cfg->streams < 1 || cfg->streams > 8 ||
-      cfg->out_pool_bytes < 256)
-    return fail(LFC_E_INVALID, "lfc_server_create: max_batch 1..65535, streams 1..8, out_pool_bytes >= 256");
+      cfg->out_pool_bytes < 256 || cfg->max_queue < 0 || cfg->device_bytes_cap < 0)
+    return fail(LFC_E_INVALID, "lfc_server_create: max_batch 1..65535, streams 1..8, out_pool_bytes >= 256, "
+                               "max_queue and device_bytes_cap >= 0");
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(LFC_E_HIP, "lfc_server_create: no current device");
   for (int i = 0; i < n_lf; i++)
@@ -662,6 +668,28 @@ extern "C" lfc_status lfc_server_create(const lfc_lf *const *lfs, int32_t n_lf, 
   sv->lfs.assign(lfs, lfs + n_lf);
   sv->cfg = *cfg;
   sv->device = dev;
+  // memory admission: the resident light fields and the output pool first,
+  // then the colour path's decoded-view buffers (one per light field and
+  // stream), light field by light field, while they fit
+  sv->allow_rgb.assign((size_t)n_lf, 1);
+  if (cfg->device_bytes_cap > 0) {
+    int64_t used = cfg->out_pool_bytes;
+    for (int i = 0; i < n_lf; i++) {
+      lfc_info_t info;
+      (void)lfc_info(lfs[i], &info);
+      used += (int64_t)info.device_bytes;
+    }
+    if (used > cfg->device_bytes_cap) {
+      delete sv;
+      return fail(LFC_E_NOMEM, "lfc_server_create: the light fields and the output pool need " + std::to_string(used) +
+                                   " device bytes, more than device_bytes_cap");
+    }
+    for (int i = 0; i < n_lf; i++) {
+      const int64_t need = (int64_t)cfg->streams * (int64_t)lfc::lf_rgb_bytes(lfs[i]);
+      if (used + need <= cfg->device_bytes_cap) used += need;
+      else sv->allow_rgb[(size_t)i] = 0;
+    }
+  }
   if (hipMalloc(reinterpret_cast<void **>(&sv->d_pool), (size_t)cfg->out_pool_bytes) != hipSuccess) {
     delete sv;
     return fail(LFC_E_NOMEM, "lfc_server_create: output pool");
@@ -752,6 +780,12 @@ extern "C" lfc_status lfc_server_replay(lfc_server *sv, const lfc_render_request
     }
     std::lock_guard<std::mutex> lk(sv->mu);
     lfc_status st = submit_locked(sv, reqs[i], true, &latency_ms[i], nullptr);
+    if (st == LFC_E_NOMEM) {   // refused: the queue is full
+      latency_ms[i] = -1.0;
+      sv->replay_left--;
+      sv->cv_done.notify_all();
+      continue;
+    }
     if (st != LFC_OK) return st;
     // latency counts from the scheduled arrival, so a late submit is not hidden
     sv->tickets[sv->next_ticket - 1].t_submit = due;

@@ -109,7 +109,8 @@ class c_decode_config(C.Structure):
 
 
 class c_server_config(C.Structure):
-    _fields_ = [("max_batch", C.c_int32), ("streams", C.c_int32), ("out_pool_bytes", C.c_int64)]
+    _fields_ = [("max_batch", C.c_int32), ("streams", C.c_int32), ("out_pool_bytes", C.c_int64),
+                ("max_queue", C.c_int64), ("device_bytes_cap", C.c_int64)]
 
 
 class c_server_stats(C.Structure):
@@ -722,9 +723,10 @@ class Batch:
 class Server:
     """Serving loop over resident light fields (wraps lfc_server*)."""
 
-    def __init__(self, lfs, max_batch: int = 64, streams: int = 2, out_pool_bytes: int = 1 << 30):
+    def __init__(self, lfs, max_batch: int = 64, streams: int = 2, out_pool_bytes: int = 1 << 30,
+                 max_queue: int = 0, device_bytes_cap: int = 0):
         self.lfs = list(lfs)   # the handles must outlive the server
-        cfg = c_server_config(max_batch, streams, out_pool_bytes)
+        cfg = c_server_config(max_batch, streams, out_pool_bytes, max_queue, device_bytes_cap)
         h = C.c_void_p()
         _check(load().lfc_server_create(_handles(self.lfs), len(self.lfs), C.byref(cfg), C.byref(h)))
         self.handle = h.value

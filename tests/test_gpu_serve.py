@@ -221,6 +221,43 @@ def test_server_memory_admission(fields):
     sv.close()
 
 
+def test_server_device_memory_cap_and_queue_limit(fields):
+    # memory admission of the resident light fields: a cap below their device
+    # bytes plus the pool refuses the server; a cap that holds them but not
+    # the decoded-view buffers serves every request by tiles, the same bytes
+    _, lfs = fields
+    resident = sum(int(lf.info.device_bytes) for lf in lfs)
+    pool = 8 << 20
+    with pytest.raises(lfc.LFCError) as e:
+        lfc.Server(lfs, max_batch=8, streams=2, out_pool_bytes=pool, device_bytes_cap=resident + pool - 1)
+    assert e.value.status == -3
+    reqs = mixed_requests(40, seed=11)
+    sv = lfc.Server(lfs, max_batch=16, streams=2, out_pool_bytes=pool, device_bytes_cap=resident + pool)
+    tickets = [sv.submit(*r) for r in reqs]
+    for t, r in zip(tickets, reqs):
+        got, _ = sv.fetch(t, r[1], r[2], timeout_ms=60000)
+        assert torch.equal(got, single(lfs, r)), r
+    sv.close()
+    # queue overflow: a pool that holds one 64x64 result and nothing released,
+    # so requests pile up; submits beyond max_queue waiting ones are refused
+    one = 3 * 64 * 64 * 4
+    sv = lfc.Server(lfs, max_batch=1, streams=1, out_pool_bytes=one, max_queue=2)
+    accepted, refused = [], 0
+    for i in range(8):
+        try:
+            accepted.append(sv.submit(0, 64, 64, (0.5, 0.5, 0.0, 0.0)))
+        except lfc.LFCError as err:
+            assert err.status == -3
+            refused += 1
+    assert refused >= 8 - 3 and len(accepted) <= 3
+    for t in accepted:   # each release admits the next waiting one
+        got, _ = sv.fetch(t, 64, 64, timeout_ms=60000)
+        assert torch.equal(got, single(lfs, (0, 64, 64, (0.5, 0.5, 0.0, 0.0))))
+    sv.close()
+    with pytest.raises(lfc.LFCError):
+        lfc.Server(lfs, max_batch=1, streams=1, out_pool_bytes=one, max_queue=-1)
+
+
 def test_server_replay_and_plain_mode(fields):
     _, lfs = fields
     reqs = mixed_requests(300, seed=8)
