@@ -250,6 +250,8 @@ def main():
     ap.add_argument("--tile-blocks", type=int, default=0,
                     help="decode tile capacity to use instead of measuring the choice (profiling runs "
                          "take the value a default run chose, so that every traced launch is the timed kernel)")
+    ap.add_argument("--no-cold", action="store_true",
+                    help="skip the cold-cache launches (profiling runs, so that every traced launch is a warm one)")
     ap.add_argument("--staged", action="store_true",
                     help="with --tile-blocks: stage each strip in LDS (the other choice the tuner measures)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -335,14 +337,15 @@ def main():
                     launch_ms_p50=round(float(np.median(per_launch)), 5))
 
     # cold L2/MALL: a 1 GiB write between launches, outside the timed events
-    flush = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
-    cold = []
-    for _ in range(10):
-        flush.fill_(1)
-        cold.append(time_launches(step, 1, torch)[0])
-    del flush
-    roofline["launch_ms_cold_mean"] = round(float(np.mean(cold)), 5)
-    roofline["frac_cold"] = round(alg_bytes / (np.mean(cold) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    if not args.no_cold:
+        flush = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+        cold = []
+        for _ in range(10):
+            flush.fill_(1)
+            cold.append(time_launches(step, 1, torch)[0])
+        del flush
+        roofline["launch_ms_cold_mean"] = round(float(np.mean(cold)), 5)
+        roofline["frac_cold"] = round(alg_bytes / (np.mean(cold) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
     extra = {}
     stream50 = streaml = dec50 = None

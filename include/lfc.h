@@ -614,6 +614,29 @@ lfc_status lfc_batch_check(lfc_batch *b, hipStream_t s);
 lfc_status lfc_batch_destroy(lfc_batch *b);
 
 /*
+ * A batch plan: one lfc_batch_render call fixed once (the same light fields,
+ * requests and output pointers at every launch), with its request table
+ * copied to the device at creation, its decoded-view buffers allocated then
+ * and held by the plan, and, with graph != 0, its launches captured once
+ * into a HIP graph, so that each lfc_batch_plan_launch is one graph launch
+ * (the graph holds kernels only; the persistent colour decode leaves its
+ * work counters at zero for the next launch).  Each launch writes what
+ * lfc_batch_render of the same arguments writes.  Launches of one plan must
+ * not overlap (use one stream); the light fields and the output buffers
+ * must outlive the plan.  lfc_batch_plan_destroy waits for the device (it
+ * frees device memory); NULL is ignored.  lfc_batch_plan_info reports how
+ * many light fields take the decoded colour path and whether a graph is
+ * used.  Errors: as lfc_batch_render (n must be at least 1), plus LFC_E_HIP
+ * (capture or instantiation).
+ */
+typedef struct lfc_batch_plan lfc_batch_plan;
+lfc_status lfc_batch_plan_create(const lfc_lf *const *lfs, int32_t n_lf, const lfc_render_request *reqs, int32_t n,
+                                 float *const *d_outs, int32_t graph, lfc_batch_plan **plan);
+lfc_status lfc_batch_plan_launch(lfc_batch_plan *plan, hipStream_t s);
+lfc_status lfc_batch_plan_info(const lfc_batch_plan *plan, int32_t *n_decoded_lf, int32_t *graph);
+void lfc_batch_plan_destroy(lfc_batch_plan *plan);
+
+/*
  * Serving loop over resident light fields (the access pattern the paper
  * designs for: many novel views of compressed light fields kept in GPU
  * memory, Sec. 1 and 3.5).  Requests are queued on submit; one engine thread

@@ -179,31 +179,52 @@ Scratch *get_scratch(lfc_batch *b, const lfc_lf *lf) {
 
 size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-// lfc_batch_render; with check_outs false the output pointers are trusted to
-// hold their results (the server's pool offsets, sized when admitted).
-lfc_status batch_render(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf, const lfc_render_request *reqs,
-                        int32_t n, float *const *d_outs, hipStream_t s, bool check_outs,
-                        const char *allow_rgb = nullptr) {
-  const char *who = "lfc_batch_render";
-  if (!b) return fail(LFC_E_INVALID, "lfc_batch_render: null batch");
-  if (n < 0) return fail(LFC_E_INVALID, "lfc_batch_render: n < 0");
-  if (n == 0) return LFC_OK;
-  if (!lfs || n_lf < 1 || !reqs || !d_outs) return fail(LFC_E_INVALID, "lfc_batch_render: null array");
+// A batch resolved on the host: which path each light field takes, the
+// decoded-view buffers, and where each part of its table goes.  The table:
+// tile requests grouped by block size; per block size the colour decode's
+// light-field records and first work items; the view masks; the
+// interpolated requests.
+struct BatchLayout {
+  struct Group {
+    int count = 0, max_tiles = 0;   // tile requests
+    size_t lds = 0;
+    size_t at_tiles = 0;
+    std::vector<int> lf;            // colour-decoded light fields of this block size
+    bool keys = true;
+    size_t rgb_lds = 0;
+    int items = 0;
+    size_t at_args = 0, at_first = 0;
+  } grp[9];
+  std::vector<char> tiles;          // packed tile requests, in table order
+  std::vector<Scratch *> scr;       // per light field: its decoded views (colour path) or null (tiles)
+  std::vector<size_t> at_mask;
+  size_t at_interp = 0, bytes = 0;
+  int n_interp = 0, max_wo = 0, max_ho = 0;
+};
+
+// Validates a batch and lays out its table (see BatchLayout); with
+// check_outs false the output pointers are trusted to hold their results
+// (the server's pool offsets, sized when admitted); allow_rgb (null: every
+// light field) limits the colour path.
+lfc_status plan_batch(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf, const lfc_render_request *reqs, int32_t n,
+                      float *const *d_outs, bool check_outs, const char *allow_rgb, BatchLayout &L,
+                      const char *who) {
+  if (!lfs || n_lf < 1 || !reqs || !d_outs) return fail(LFC_E_INVALID, std::string(who) + ": null array");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
-    return fail(LFC_E_INVALID, "lfc_batch_render: the current device is not the batch's");
+    return fail(LFC_E_INVALID, std::string(who) + ": the current device is not the batch's");
   for (int i = 0; i < n_lf; i++)
     if (!lfs[i] || lfc::lf_device(lfs[i]) != dev)
-      return fail(LFC_E_INVALID, "lfc_batch_render: null handle or handle of another device");
+      return fail(LFC_E_INVALID, std::string(who) + ": null handle or handle of another device");
   // requests checked; output pixels per light field
   std::vector<double> px(n_lf, 0.0);
   for (int i = 0; i < n; i++) {
     const lfc_render_request &r = reqs[i];
-    if (r.lf < 0 || r.lf >= n_lf) return fail(LFC_E_INVALID, "lfc_batch_render: request lf index out of range");
+    if (r.lf < 0 || r.lf >= n_lf) return fail(LFC_E_INVALID, std::string(who) + ": request lf index out of range");
     if (r.out_w < 1 || r.out_h < 1 || r.out_w > 16384 || r.out_h > 16384)
-      return fail(LFC_E_INVALID, "lfc_batch_render: out_w and out_h must be 1..16384");
+      return fail(LFC_E_INVALID, std::string(who) + ": out_w and out_h must be 1..16384");
     if (!d_outs[i] || reinterpret_cast<uintptr_t>(d_outs[i]) % 4)
-      return fail(LFC_E_INVALID, "lfc_batch_render: null or unaligned output pointer");
+      return fail(LFC_E_INVALID, std::string(who) + ": null or unaligned output pointer");
     if (check_outs)
       if (lfc_status st = lfc::device_buffer(d_outs[i], (size_t)3 * r.out_w * r.out_h * sizeof(float), 4, who,
                                              "d_outs[i]"))
@@ -213,34 +234,19 @@ lfc_status batch_render(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf, co
   // a light field whose requests cover about as many pixels as it holds is
   // decoded once (the views they read, as 8-bit RGB) and interpolated; the
   // others render by tiles, each tile decoding its own footprint
-  std::vector<Scratch *> scr((size_t)n_lf, nullptr);
+  L.scr.assign((size_t)n_lf, nullptr);
   for (int l = 0; l < n_lf; l++)
     if (px[(size_t)l] > 0.0 && (!allow_rgb || allow_rgb[l]) && lfc::lf_rgb_batchable(lfs[l], px[(size_t)l]))
-      scr[(size_t)l] = get_scratch(b, lfs[l]);
-  // the table: tile requests grouped by block size; per block size the colour
-  // decode's light-field records and first work items; the view masks; the
-  // interpolated requests
+      L.scr[(size_t)l] = get_scratch(b, lfs[l]);
   const size_t rb = lfc::render_req_bytes(), ab = lfc::rgb_args_bytes(), ib = lfc::interp_req_bytes();
-  struct Group {
-    int count = 0, max_tiles = 0;
-    size_t lds = 0;
-    std::vector<int> lf;       // colour-decoded light fields of this block size
-    bool keys = true;
-    size_t rgb_lds = 0;
-    int items = 0;
-    size_t at_args = 0, at_first = 0;
-  } grp[9];
-  std::vector<char> packed;
-  std::vector<int> bs(n, 0), order;
-  order.reserve(n);
-  int n_interp = 0, max_wo = 0, max_ho = 0;
-  packed.resize((size_t)n * rb);
+  std::vector<char> packed((size_t)n * rb);
+  std::vector<int> bs(n, 0);
   for (int i = 0; i < n; i++) {
     const lfc_render_request &r = reqs[i];
-    if (scr[(size_t)r.lf]) {
-      n_interp++;
-      max_wo = std::max(max_wo, r.out_w);
-      max_ho = std::max(max_ho, r.out_h);
+    if (L.scr[(size_t)r.lf]) {
+      L.n_interp++;
+      L.max_wo = std::max(L.max_wo, r.out_w);
+      L.max_ho = std::max(L.max_ho, r.out_h);
       continue;
     }
     int block = 0, nt = 0;
@@ -249,103 +255,136 @@ lfc_status batch_render(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf, co
                                              &block, &nt, &lds))
       return st;
     bs[i] = block;
-    Group &gp = grp[block];
+    BatchLayout::Group &gp = L.grp[block];
     gp.count++;
     gp.max_tiles = std::max(gp.max_tiles, nt);
     gp.lds = std::max(gp.lds, lds);
   }
   for (int block : {2, 4, 8})
-    if (grp[block].count > 65535)
-      return fail(LFC_E_INVALID, "lfc_batch_render: more than 65535 requests of one block size");
-  for (int block : {2, 4, 8})
-    for (int i = 0; i < n; i++)
-      if (bs[i] == block) order.push_back(i);
-  size_t at = align16(order.size() * rb);
-  for (int l = 0; l < n_lf; l++)
-    if (scr[(size_t)l]) grp[lfc::lf_block(lfs[l])].lf.push_back(l);
+    if (L.grp[block].count > 65535)
+      return fail(LFC_E_INVALID, std::string(who) + ": more than 65535 requests of one block size");
+  size_t at = 0;
   for (int block : {2, 4, 8}) {
-    Group &gp = grp[block];
+    L.grp[block].at_tiles = at;
+    for (int i = 0; i < n; i++)
+      if (bs[i] == block) {
+        L.tiles.insert(L.tiles.end(), packed.begin() + (ptrdiff_t)((size_t)i * rb),
+                       packed.begin() + (ptrdiff_t)((size_t)(i + 1) * rb));
+        at += rb;
+      }
+  }
+  at = align16(at);
+  for (int l = 0; l < n_lf; l++)
+    if (L.scr[(size_t)l]) L.grp[lfc::lf_block(lfs[l])].lf.push_back(l);
+  for (int block : {2, 4, 8}) {
+    BatchLayout::Group &gp = L.grp[block];
     if (gp.lf.empty()) continue;
     for (int l : gp.lf) gp.keys = gp.keys && lfc::rgb_keys_fit(lfs[l]);
     for (int l : gp.lf) gp.rgb_lds = std::max(gp.rgb_lds, lfc::rgb_lds_bytes(lfs[l], gp.keys));
+    for (int l : gp.lf) gp.items += lfc::lf_rgb_items(lfs[l]);
     gp.at_args = at;
     at = align16(at + gp.lf.size() * ab);
     gp.at_first = at;
     at = align16(at + 4 * (gp.lf.size() + 1));
   }
-  std::vector<size_t> at_mask((size_t)n_lf, 0);
+  L.at_mask.assign((size_t)n_lf, 0);
   for (int l = 0; l < n_lf; l++)
-    if (scr[(size_t)l]) {
-      at_mask[(size_t)l] = at;
+    if (L.scr[(size_t)l]) {
+      L.at_mask[(size_t)l] = at;
       at = align16(at + 4 * (size_t)((lfc::lf_views(lfs[l]) + 31) / 32));
     }
-  const size_t at_interp = at;
-  at = align16(at + (size_t)n_interp * ib);
-  Slot &sl = b->slot[b->next];
-  if (lfc_status st = grow_slot(sl, at)) return st;
-  // the kernels that read the slot's previous table must have finished
-  if (sl.used && hipEventSynchronize(sl.done) != hipSuccess) return fail(LFC_E_HIP, "lfc_batch_render: event wait");
-  sl.used = false;
-  for (size_t k = 0; k < order.size(); k++) std::memcpy(sl.host + k * rb, &packed[(size_t)order[k] * rb], rb);
+  L.at_interp = at;
+  L.bytes = align16(at + (size_t)L.n_interp * ib);
+  return LFC_OK;
+}
+
+// Writes a planned batch's table into host (bytes L.bytes) for a device
+// copy at dev.
+void fill_batch(const BatchLayout &L, const lfc_lf *const *lfs, int32_t n_lf, const lfc_render_request *reqs,
+                int32_t n, float *const *d_outs, char *host, const char *dev) {
+  const size_t ab = lfc::rgb_args_bytes(), ib = lfc::interp_req_bytes();
+  std::memset(host, 0, L.bytes);
+  if (!L.tiles.empty()) std::memcpy(host, L.tiles.data(), L.tiles.size());
   for (int block : {2, 4, 8}) {
-    Group &gp = grp[block];
-    int32_t *first = reinterpret_cast<int32_t *>(sl.host + gp.at_first);
+    const BatchLayout::Group &gp = L.grp[block];
+    int32_t *first = reinterpret_cast<int32_t *>(host + gp.at_first);
     int items = 0;
     for (size_t k = 0; k < gp.lf.size(); k++) {
       const int l = gp.lf[k];
-      lfc::rgb_args_fill(lfs[l], gp.keys, static_cast<uint32_t *>(scr[(size_t)l]->buf),
-                         reinterpret_cast<const uint32_t *>(sl.dev + at_mask[(size_t)l]), sl.host + gp.at_args + k * ab);
+      lfc::rgb_args_fill(lfs[l], gp.keys, static_cast<uint32_t *>(L.scr[(size_t)l]->buf),
+                         reinterpret_cast<const uint32_t *>(dev + L.at_mask[(size_t)l]), host + gp.at_args + k * ab);
       first[k] = items;
       items += lfc::lf_rgb_items(lfs[l]);
     }
     if (!gp.lf.empty()) first[gp.lf.size()] = items;
-    gp.items = items;
   }
-  for (int l = 0; l < n_lf; l++)
-    if (scr[(size_t)l])
-      std::memset(sl.host + at_mask[(size_t)l], 0, 4 * (size_t)((lfc::lf_views(lfs[l]) + 31) / 32));
-  int k_interp = 0;
+  int k = 0;
   for (int i = 0; i < n; i++) {
     const lfc_render_request &r = reqs[i];
-    if (!scr[(size_t)r.lf]) continue;
-    lfc::need_mask_host(lfs[r.lf], r.view, reinterpret_cast<uint32_t *>(sl.host + at_mask[(size_t)r.lf]));
-    lfc::interp_req_fill(lfs[r.lf], static_cast<uint32_t *>(scr[(size_t)r.lf]->buf), r.view, r.out_w, r.out_h,
-                         d_outs[i], sl.host + at_interp + (size_t)k_interp * ib);
-    k_interp++;
+    if (!L.scr[(size_t)r.lf]) continue;
+    lfc::need_mask_host(lfs[r.lf], r.view, reinterpret_cast<uint32_t *>(host + L.at_mask[(size_t)r.lf]));
+    lfc::interp_req_fill(lfs[r.lf], static_cast<uint32_t *>(L.scr[(size_t)r.lf]->buf), r.view, r.out_w, r.out_h,
+                         d_outs[i], host + L.at_interp + (size_t)k * ib);
+    k++;
   }
-  if (hipMemcpyAsync(sl.dev, sl.host, at, hipMemcpyHostToDevice, s) != hipSuccess)
+  (void)n_lf;
+}
+
+// The launches of a batch whose table is at dev: tile groups, then the
+// colour decode of each block size (persistent, counters ctr[2]), then the
+// interpolation.  No copies, memsets or event operations: a stream capture
+// of it is a graph of kernels only.
+lfc_status launch_batch(const BatchLayout &L, const char *dev, uint32_t *ctr, hipStream_t s) {
+  lfc_status st = LFC_OK;
+  for (int block : {2, 4, 8}) {
+    const BatchLayout::Group &gp = L.grp[block];
+    if (gp.count && st == LFC_OK)
+      st = lfc::render_multi_launch(block, dev + gp.at_tiles, gp.count, gp.max_tiles, gp.lds, s);
+  }
+  for (int block : {2, 4, 8}) {
+    const BatchLayout::Group &gp = L.grp[block];
+    if (gp.lf.empty() || st != LFC_OK) continue;
+    st = lfc::rgb_multi_launch(block, gp.keys, dev + gp.at_args, reinterpret_cast<const int32_t *>(dev + gp.at_first),
+                               (int)gp.lf.size(), gp.items, gp.rgb_lds, ctr, s);
+  }
+  if (st == LFC_OK && L.n_interp) st = lfc::interp_multi_launch(dev + L.at_interp, L.n_interp, L.max_wo, L.max_ho, s);
+  return st;
+}
+
+// lfc_batch_render (see plan_batch for check_outs and allow_rgb).
+lfc_status batch_render(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf, const lfc_render_request *reqs,
+                        int32_t n, float *const *d_outs, hipStream_t s, bool check_outs,
+                        const char *allow_rgb = nullptr) {
+  const char *who = "lfc_batch_render";
+  if (!b) return fail(LFC_E_INVALID, "lfc_batch_render: null batch");
+  if (n < 0) return fail(LFC_E_INVALID, "lfc_batch_render: n < 0");
+  if (n == 0) return LFC_OK;
+  BatchLayout L;
+  if (lfc_status st = plan_batch(b, lfs, n_lf, reqs, n, d_outs, check_outs, allow_rgb, L, who)) return st;
+  Slot &sl = b->slot[b->next];
+  if (lfc_status st = grow_slot(sl, L.bytes)) return st;
+  // the kernels that read the slot's previous table must have finished
+  if (sl.used && hipEventSynchronize(sl.done) != hipSuccess) return fail(LFC_E_HIP, "lfc_batch_render: event wait");
+  sl.used = false;
+  fill_batch(L, lfs, n_lf, reqs, n, d_outs, sl.host, sl.dev);
+  if (hipMemcpyAsync(sl.dev, sl.host, L.bytes, hipMemcpyHostToDevice, s) != hipSuccess)
     return fail(LFC_E_HIP, std::string(who) + ": copy of the request table");
   uint32_t *ctr = b->d_ctr + (size_t)b->next * kCtrStride;
   b->next = (b->next + 1) % kSlots;
+  // a decoded-views buffer is rewritten only after the launches of an
+  // earlier batch that read it (on any stream) have finished
   lfc_status st = LFC_OK;
-  size_t tile_at = 0;
-  for (int block : {2, 4, 8}) {
-    const Group &gp = grp[block];
-    if (!gp.count) continue;
-    if (st == LFC_OK)
-      st = lfc::render_multi_launch(block, sl.dev + tile_at, gp.count, gp.max_tiles, gp.lds, s);
-    tile_at += (size_t)gp.count * rb;
-  }
-  // the colour path: a decoded-views buffer is rewritten only after the
-  // launches of an earlier batch that read it (on any stream) have finished
   for (int l = 0; l < n_lf && st == LFC_OK; l++)
-    if (scr[(size_t)l] && scr[(size_t)l]->used && hipStreamWaitEvent(s, scr[(size_t)l]->done, 0) != hipSuccess)
+    if (L.scr[(size_t)l] && L.scr[(size_t)l]->used && hipStreamWaitEvent(s, L.scr[(size_t)l]->done, 0) != hipSuccess)
       st = fail(LFC_E_HIP, std::string(who) + ": wait for an earlier use of the decoded views");
-  for (int block : {2, 4, 8}) {
-    const Group &gp = grp[block];
-    if (gp.lf.empty() || st != LFC_OK) continue;
-    st = lfc::rgb_multi_launch(block, gp.keys, sl.dev + gp.at_args,
-                               reinterpret_cast<const int32_t *>(sl.dev + gp.at_first), (int)gp.lf.size(), gp.items,
-                               gp.rgb_lds, ctr, s);
-  }
-  if (st == LFC_OK && n_interp) st = lfc::interp_multi_launch(sl.dev + at_interp, n_interp, max_wo, max_ho, s);
+  if (st == LFC_OK) st = launch_batch(L, sl.dev, ctr, s);
   for (int l = 0; l < n_lf; l++)
-    if (scr[(size_t)l]) {
-      if (hipEventRecord(scr[(size_t)l]->done, s) == hipSuccess) {
-        scr[(size_t)l]->used = true;
+    if (L.scr[(size_t)l]) {
+      if (hipEventRecord(L.scr[(size_t)l]->done, s) == hipSuccess) {
+        L.scr[(size_t)l]->used = true;
       } else {
         (void)hipStreamSynchronize(s);
-        scr[(size_t)l]->used = false;
+        L.scr[(size_t)l]->used = false;
         if (st == LFC_OK) st = fail(LFC_E_HIP, std::string(who) + ": event record");
       }
     }
@@ -358,6 +397,105 @@ extern "C" lfc_status lfc_batch_render(lfc_batch *b, const lfc_lf *const *lfs, i
                                        const lfc_render_request *reqs, int32_t n, float *const *d_outs,
                                        hipStream_t s) {
   return batch_render(b, lfs, n_lf, reqs, n, d_outs, s, true);
+}
+
+// A batch fixed once: its table on the device, its decoded-view buffers
+// (in a context of its own) and the colour decode's counters, and with a
+// graph its launches captured once.
+struct lfc_batch_plan {
+  lfc_batch *b = nullptr;
+  BatchLayout L;
+  char *dev = nullptr;
+  uint32_t *ctr = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" void lfc_batch_plan_destroy(lfc_batch_plan *p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  if (p->dev || p->ctr) (void)hipDeviceSynchronize();
+  if (p->dev) (void)hipFree(p->dev);
+  if (p->ctr) (void)hipFree(p->ctr);
+  (void)lfc_batch_destroy(p->b);
+  delete p;
+}
+
+extern "C" lfc_status lfc_batch_plan_create(const lfc_lf *const *lfs, int32_t n_lf, const lfc_render_request *reqs,
+                                            int32_t n, float *const *d_outs, int32_t graph, lfc_batch_plan **out) {
+  const char *who = "lfc_batch_plan_create";
+  if (!out) return fail(LFC_E_INVALID, "lfc_batch_plan_create: null result");
+  *out = nullptr;
+  if (n < 1) return fail(LFC_E_INVALID, "lfc_batch_plan_create: n must be at least 1");
+  lfc_batch_plan *p = new (std::nothrow) lfc_batch_plan;
+  if (!p) return fail(LFC_E_NOMEM, "lfc_batch_plan_create: out of host memory");
+  lfc_status st = lfc_batch_create(&p->b);
+  if (st == LFC_OK) st = plan_batch(p->b, lfs, n_lf, reqs, n, d_outs, true, nullptr, p->L, who);
+  std::vector<char> host;
+  if (st == LFC_OK) {
+    host.resize(p->L.bytes);
+    if (hipMalloc(reinterpret_cast<void **>(&p->dev), p->L.bytes) != hipSuccess) {
+      p->dev = nullptr;
+      st = fail(LFC_E_NOMEM, "lfc_batch_plan_create: request table");
+    } else if (hipMalloc(reinterpret_cast<void **>(&p->ctr), 2 * sizeof(uint32_t)) != hipSuccess) {
+      p->ctr = nullptr;
+      st = fail(LFC_E_NOMEM, "lfc_batch_plan_create: counters");
+    }
+  }
+  if (st == LFC_OK) {
+    fill_batch(p->L, lfs, n_lf, reqs, n, d_outs, host.data(), p->dev);
+    if (hipMemcpy(p->dev, host.data(), p->L.bytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(p->ctr, 0, 2 * sizeof(uint32_t)) != hipSuccess)
+      st = fail(LFC_E_HIP, "lfc_batch_plan_create: copy of the request table");
+  }
+  if (st == LFC_OK && graph) {
+    if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
+      p->cap = nullptr;
+      st = fail(LFC_E_HIP, "lfc_batch_plan_create: capture stream");
+    } else if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed) != hipSuccess) {
+      st = fail(LFC_E_HIP, "lfc_batch_plan_create: begin capture");
+    } else {
+      st = launch_batch(p->L, p->dev, p->ctr, p->cap);
+      hipGraph_t g = nullptr;
+      const hipError_t he = hipStreamEndCapture(p->cap, &g);
+      p->graph = g;
+      if (st == LFC_OK && (he != hipSuccess || !g)) st = fail(LFC_E_HIP, "lfc_batch_plan_create: end capture");
+      if (st == LFC_OK && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) {
+        p->exec = nullptr;
+        st = fail(LFC_E_HIP, "lfc_batch_plan_create: graph instantiation");
+      }
+    }
+  }
+  if (st != LFC_OK) {
+    lfc_batch_plan_destroy(p);
+    return st;
+  }
+  *out = p;
+  return LFC_OK;
+}
+
+extern "C" lfc_status lfc_batch_plan_launch(lfc_batch_plan *p, hipStream_t s) {
+  if (!p) return fail(LFC_E_INVALID, "lfc_batch_plan_launch: null plan");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->b->device)
+    return fail(LFC_E_INVALID, "lfc_batch_plan_launch: the current device is not the plan's");
+  if (p->exec) {
+    if (hipGraphLaunch(p->exec, s) != hipSuccess) return fail(LFC_E_HIP, "lfc_batch_plan_launch: graph launch");
+    return LFC_OK;
+  }
+  return launch_batch(p->L, p->dev, p->ctr, s);
+}
+
+extern "C" lfc_status lfc_batch_plan_info(const lfc_batch_plan *p, int32_t *n_decoded_lf, int32_t *graph) {
+  if (!p || !n_decoded_lf || !graph) return fail(LFC_E_INVALID, "lfc_batch_plan_info: null argument");
+  int k = 0;
+  for (const Scratch *sc : p->L.scr) k += sc != nullptr;
+  *n_decoded_lf = k;
+  *graph = p->exec != nullptr;
+  return LFC_OK;
 }
 
 extern "C" lfc_status lfc_batch_decode(lfc_batch *b, const lfc_lf *const *lfs, int32_t n_lf, const int32_t *d_req,

@@ -205,6 +205,12 @@ def load() -> C.CDLL:
         L.lfc_batch_destroy.argtypes = [vp]
         L.lfc_batch_decode.argtypes = [vp, C.POINTER(vp), i32, vp, i64, vp, vp]
         L.lfc_batch_check.argtypes = [vp, vp]
+        L.lfc_batch_plan_create.argtypes = [C.POINTER(vp), i32, C.POINTER(c_render_request), i32, C.POINTER(vp), i32,
+                                            C.POINTER(vp)]
+        L.lfc_batch_plan_launch.argtypes = [vp, vp]
+        L.lfc_batch_plan_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
+        L.lfc_batch_plan_destroy.argtypes = [vp]
+        L.lfc_batch_plan_destroy.restype = None
         L.lfc_server_create.argtypes = [C.POINTER(vp), i32, C.POINTER(c_server_config), C.POINTER(vp)]
         L.lfc_server_submit.argtypes = [vp, C.POINTER(c_render_request), u64p]
         L.lfc_server_wait.argtypes = [vp, C.c_uint64, i32, C.POINTER(vp), dp]
@@ -217,7 +223,8 @@ def load() -> C.CDLL:
                   "lfc_render_views", "lfc_render_views_ex", "lfc_render_views_noalloc", "lfc_encode_ctl", "lfc_tune_decode", "lfc_encode_gpu", "lfc_mlp_infer", "lfc_mlp_infer_ex", "lfc_mlp_grad",
                   "lfc_mlp_adam", "lfc_render_tune", "lfc_render_plan_create",
                   "lfc_render_plan_launch", "lfc_render_plan_info", "lfc_check", "lfc_close", "lfc_decode_progressive", "lfc_decode_rgb", "lfc_batch_create",
-                  "lfc_batch_decode", "lfc_batch_check", "lfc_batch_render",
+                  "lfc_batch_decode", "lfc_batch_check", "lfc_batch_render", "lfc_batch_plan_create",
+                  "lfc_batch_plan_launch", "lfc_batch_plan_info",
                   "lfc_batch_destroy", "lfc_server_create", "lfc_server_submit", "lfc_server_wait",
                   "lfc_server_release", "lfc_server_replay", "lfc_server_get_stats", "lfc_server_destroy"):
             getattr(L, f).restype = C.c_int
@@ -712,6 +719,47 @@ class Batch:
         h, self.handle = self.handle, None
         if h:
             _check(load().lfc_batch_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchPlan:
+    """One batched render across light fields fixed once (wraps
+    lfc_batch_plan*): the request table is built at creation and, with
+    graph, the launches are captured in a HIP graph (launch() is then one
+    graph launch).  reqs as Batch.render."""
+
+    def __init__(self, lfs, reqs, outs=None, graph: bool = True):
+        import torch
+        if outs is None:
+            outs = [torch.empty((3, h, w), dtype=torch.float32, device="cuda") for _, w, h, _ in reqs]
+        for o, (_, w, h, _) in zip(outs, reqs):
+            assert o.dtype == torch.float32 and o.is_cuda and o.is_contiguous() and tuple(o.shape) == (3, h, w)
+        self.lfs, self.outs = list(lfs), outs
+        ptrs = (C.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        h = C.c_void_p()
+        _check(load().lfc_batch_plan_create(_handles(lfs), len(lfs), _requests(reqs), len(reqs), ptrs, int(graph),
+                                            C.byref(h)))
+        self.handle = h.value
+
+    def launch(self, cuda_stream=None):
+        _check(load().lfc_batch_plan_launch(self.handle, _stream_ptr(cuda_stream)))
+        return self.outs
+
+    def info(self):
+        """(light fields on the decoded colour path, graph in use)."""
+        k, g = C.c_int32(), C.c_int32()
+        _check(load().lfc_batch_plan_info(self.handle, C.byref(k), C.byref(g)))
+        return int(k.value), bool(g.value)
+
+    def close(self) -> None:
+        h, self.handle = self.handle, None
+        if h:
+            load().lfc_batch_plan_destroy(h)
 
     def __del__(self):
         try:

@@ -84,24 +84,34 @@ def test_batch_matches_single_renders_and_oracle(fields):
     b.close()
 
 
-def test_dense_batch_over_two_light_fields(gpu):
-    # a batch that covers most of two light fields (an 8x8 light field of
-    # 64x64 views and a 9x9 lenslet-like one, 64 novel 128x96 views): each is
-    # decoded once by the persistent colour kernel (both in one launch) and
-    # interpolated in one launch; every result equals the light field's own
-    # render of it, and the oracle's to 1e-5.  Six calls in a row reuse every
-    # table slot and its work counters.
-    specs = [(8, 8, 64, 64, dict(block=4, levels=2, cluster=(2,), blk_threshold=2)),
-             (9, 9, 125, 87, dict(block=4, levels=3, cluster=(2, 2), blk_threshold=40, quant_bits=2))]
-    encs = [oracle_encode(make_lf(U, V, W, H, seed=300 + U, vignetting=U == 9), **kw) for U, V, W, H, kw in specs]
+DENSE = [(8, 8, 64, 64, dict(block=4, levels=2, cluster=(2,), blk_threshold=2)),
+         (9, 9, 125, 87, dict(block=4, levels=3, cluster=(2, 2), blk_threshold=40, quant_bits=2))]
+
+
+@pytest.fixture(scope="module")
+def dense_pair(gpu):
+    # an 8x8 light field of 64x64 views and a 9x9 lenslet-like one, with 64
+    # novel 128x96 views that cover most of both
+    encs = [oracle_encode(make_lf(U, V, W, H, seed=300 + U, vignetting=U == 9), **kw) for U, V, W, H, kw in DENSE]
     lfs = [lfc.lfc_open(e.stream) for e in encs]
     rng = np.random.default_rng(302)
     reqs = []
     for k in range(64):
         li = k % 2
-        U, V = specs[li][0], specs[li][1]
+        U, V = DENSE[li][0], DENSE[li][1]
         reqs.append((li, 128, 96, (rng.uniform(0, U - 1), rng.uniform(0, V - 1), rng.uniform(-1, 1),
                                    rng.uniform(-1, 1))))
+    yield encs, lfs, reqs
+    for lf in lfs:
+        lf.close()
+
+
+def test_dense_batch_over_two_light_fields(dense_pair):
+    # each light field is decoded once by the persistent colour kernel (both
+    # in one launch) and interpolated in one launch; every result equals the
+    # light field's own render of it, and the oracle's to 1e-5.  Six calls in
+    # a row reuse every table slot and its work counters.
+    encs, lfs, reqs = dense_pair
     say("dense batch over two light fields")
     b = lfc.Batch()
     outs = b.render(lfs, reqs)
@@ -111,7 +121,7 @@ def test_dense_batch_over_two_light_fields(gpu):
         own = lfc.lfc_render_views(lfs[li], views, 128, 96)
         for (r, o), ref in zip(mine, own):
             assert torch.equal(o, ref), r
-        U, V, W, H, _ = specs[li]
+        U, V, W, H, _ = DENSE[li]
         got = torch.stack([o for _, o in mine[:4]]).cpu().numpy()
         ref = oracle.render(encs[li].r0, U, V, W, H, np.array([r[3] for r, _ in mine[:4]], dtype=np.float32), 128, 96)
         assert max_abs(got, ref) <= 1e-5
@@ -120,8 +130,48 @@ def test_dense_batch_over_two_light_fields(gpu):
         for o, o2 in zip(outs, again):
             assert torch.equal(o, o2), call
     b.close()
-    for lf in lfs:
-        lf.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_plan_replays(fields, dense_pair, graph):
+    # a batch plan writes what lfc_batch_render writes for the same requests,
+    # at every launch: a sparse batch (every light field by tiles), a mixed
+    # one and the dense pair (both decoded by the colour path in one
+    # persistent launch, whose counters the graph never clears).  The outputs
+    # are filled with NaN before each launch, and eager work and
+    # synchronisations run between the launches.
+    _, lfs = fields
+    rng = np.random.default_rng(77)
+    sparse = [(li, 30, 20, (rng.uniform(0, FIELDS[li][0] - 1), rng.uniform(0, FIELDS[li][1] - 1), 0.3, -0.2))
+              for li in range(len(FIELDS))]
+    cases = [("sparse", lfs, sparse, 0), ("mixed", lfs, mixed_requests(48, 911), None),
+             ("dense", dense_pair[1], dense_pair[2], 2)]
+    side = torch.zeros(1 << 20, device="cuda")
+    for name, lf_list, reqs, n_dec in cases:
+        say(f"batch plan {name}, graph={graph}, {len(reqs)} requests")
+        b = lfc.Batch()
+        ref = [o.clone() for o in b.render(lf_list, reqs)]
+        b.close()
+        plan = lfc.BatchPlan(lf_list, reqs, graph=graph)
+        k, g = plan.info()
+        assert g == graph
+        if n_dec is not None:
+            assert k == n_dec, name
+        for rep in range(4):
+            for o in plan.outs:
+                o.fill_(float("nan"))
+            torch.cuda.synchronize()
+            plan.launch()
+            side.add_(1.0)
+            torch.cuda.synchronize()
+            for i, (o, r) in enumerate(zip(plan.outs, ref)):
+                assert torch.equal(o, r), (name, rep, i, reqs[i])
+        plan.close()
+    assert float(side[0]) == 4.0 * len(cases)
+    with pytest.raises(lfc.LFCError):
+        lfc.BatchPlan(lfs, [])
+    with pytest.raises(lfc.LFCError):
+        lfc.BatchPlan(lfs, [(len(lfs), 8, 8, (0.0, 0.0, 0.0, 0.0))])
 
 
 def test_batch_argument_errors(fields):
