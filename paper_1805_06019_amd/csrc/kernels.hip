@@ -926,6 +926,16 @@ __device__ __forceinline__ float src_pos(float s, int X, float scale) {
   return s + ((float)X + 0.5f) * scale - 0.5f;
 }
 
+// x / 255 for 0 <= x <= 255, rounded as the IEEE quotient: the product with
+// the rounded reciprocal, corrected by one fused residual step (checked
+// against the division for every float of the range, both signs give the
+// same result by symmetry); three VALU operations instead of a full division.
+__device__ __forceinline__ float div255(float x) {
+  constexpr float r = 1.0f / 255.0f;
+  const float q = x * r;
+  return __builtin_fmaf(__builtin_fmaf(-q, 255.0f, x), r, q);
+}
+
 // quadrilinear interpolation of the 16 RGB taps P[view][tap] (taps 00, 01,
 // 10, 11 of each view, at that view's fractions fs[k], ft[k])
 __device__ __forceinline__ void interp_store(const uint32_t P[4][4], const float fs[4], const float ft[4], float fu,
@@ -940,7 +950,7 @@ __device__ __forceinline__ void interp_store(const uint32_t P[4][4], const float
       lt[k] = lerpf(lerpf(p00, p01, fs[k]), lerpf(p10, p11, fs[k]), ft[k]);
     }
     const float lv0 = lerpf(lt[0], lt[2], fv), lv1 = lerpf(lt[1], lt[3], fv);
-    o[ch * plane] = lerpf(lv0, lv1, fu) / 255.0f;
+    o[ch * plane] = div255(lerpf(lv0, lv1, fu));
   }
 }
 
@@ -1164,7 +1174,7 @@ __device__ __forceinline__ void rgb_strip(const RGBArgs &a, int st, int part, ui
   uint32_t *s_need = s_node + kRGBNodeCap / 32;         // the view mask
   uint32_t *s_mf = s_need + kRGBNeedWords;              // masks[3][nn], then first slots (16-bit)
   uint32_t *tile = smem + kRGBHeadWords;                // [tile_cap + 1][S/2], the last slot zero
-  uint32_t *keys = tile + lf_tile_words(a.tile_cap, S); // [3][n_top][B][NBLK * H]
+  uint32_t *keys = tile + lf_tile_words(a.tile_cap, S); // [3][n_top][NBLK][S/2], blocks as in the tile
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int sx = st % a.nsx, by = st / a.nsx;
@@ -1180,13 +1190,13 @@ __device__ __forceinline__ void rgb_strip(const RGBArgs &a, int st, int part, ui
   if constexpr (KEYS) {
     const uint32_t *rk = reinterpret_cast<const uint32_t *>(a.rkv);
     for (int t0 = wave * 64; t0 < a.key_words; t0 += kLFThreads) {
-      const int t = t0 + lane, h = t % H, j = (t / H) % NBLK, y = (t / (H * NBLK)) % B;
-      const int r = (t / (H * NBLK * B)) % a.n_top, c = t / (H * NBLK * B * a.n_top);
+      const int t = t0 + lane, wd = t % (S / 2), j = (t / (S / 2)) % NBLK;
+      const int r = (t / (S / 2 * NBLK)) % a.n_top, c = t / (S / 2 * NBLK * a.n_top);
       const int bx = sx * NBLK + j;
       if (t < a.key_words && bx < a.nbx)
         __builtin_amdgcn_global_load_lds(
             (const __attribute__((address_space(1))) void *)(rk + ((size_t)(r * a.nb + by * a.nbx + bx) * 3 + c) *
-                                                                  (S / 2) + y * H + h),
+                                                                  (S / 2) + wd),
             (__attribute__((address_space(3))) void *)(keys + t0), 4, 0, 0);
     }
   }
@@ -1295,17 +1305,42 @@ __device__ __forceinline__ void rgb_strip(const RGBArgs &a, int st, int part, ui
       const int anc_ln[4] = {(int)(w0 >> 16), (int)(w1 & 0xFFFFu), (int)(w1 >> 16), (int)(w2 & 0xFFFFu)};
       const int leaf = min((int)(w0 & 0xFFFFu) + so, nn - 1);   // the lane's own leaf
       uint32_t x[3][HR][2];
+      // the lane's words of a block slot (tile or key rows, same layout):
+      // B = 4, the whole 4 x 4 block in two 16-byte reads; B = 2, both rows
+      // of each of its two blocks in one 8-byte read; B = 8, half of each row
+      auto read_slot = [&](const uint32_t *slot0, const uint32_t *slot1, bool add, uint32_t (&xc)[HR][2]) {
+        if constexpr (B == 4) {
+          const uint4 v0 = *reinterpret_cast<const uint4 *>(slot0), v1 = *reinterpret_cast<const uint4 *>(slot0 + 4);
+          const uint32_t w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+          for (int y = 0; y < 4; y++)
+#pragma unroll
+            for (int k = 0; k < 2; k++) xc[y][k] = add ? add_pk(xc[y][k], w[2 * y + k]) : w[2 * y + k];
+        } else if constexpr (B == 2) {
+          const uint2 v0 = *reinterpret_cast<const uint2 *>(slot0), v1 = *reinterpret_cast<const uint2 *>(slot1);
+          const uint32_t w[2][2] = {{v0.x, v1.x}, {v0.y, v1.y}};
+#pragma unroll
+          for (int y = 0; y < 2; y++)
+#pragma unroll
+            for (int k = 0; k < 2; k++) xc[y][k] = add ? add_pk(xc[y][k], w[y][k]) : w[y][k];
+        } else {
+#pragma unroll
+          for (int y = 0; y < HR; y++) {
+            const uint2 v = *reinterpret_cast<const uint2 *>(slot0 + y * H + wib[0]);
+            xc[y][0] = add ? add_pk(xc[y][0], v.x) : v.x;
+            xc[y][1] = add ? add_pk(xc[y][1], v.y) : v.y;
+          }
+        }
+      };
 #pragma unroll
       for (int c = 0; c < 3; c++) {
         // key-view rows
+        if constexpr (KEYS) {
+          const uint32_t *kb = keys + (c * a.n_top + root) * (NBLK * (S / 2));
+          read_slot(kb + jb[0] * (S / 2), kb + jb[1] * (S / 2), false, x[c]);
+        } else {
 #pragma unroll
-        for (int y = 0; y < HR; y++) {
-          if constexpr (KEYS) {
-            const uint2 k2 = *reinterpret_cast<const uint2 *>(keys + ((c * a.n_top + root) * B + y0 + y) * (NBLK * H) +
-                                                             2 * jseg);
-            x[c][y][0] = k2.x;
-            x[c][y][1] = k2.y;
-          } else {
+          for (int y = 0; y < HR; y++) {
 #pragma unroll
             for (int w = 0; w < 2; w++) {
               const int bx = sx * NBLK + jb[w];
@@ -1319,23 +1354,12 @@ __device__ __forceinline__ void rgb_strip(const RGBArgs &a, int st, int part, ui
         // rows of node ln added
         auto add_node = [&](int ln) {
           const uint32_t mk = s_mf[c * nn + ln], f = firsts[c * nn + ln];
-#pragma unroll
-          for (int w = 0; w < 2; w++) {
-            if (w == 1 && B >= 4) break;   // both word pairs lie in one block
+          auto slot = [&](int w) {
             const uint32_t j = (uint32_t)jb[w];
             const uint32_t sl = ((mk >> j) & 1u) ? f + (uint32_t)__popc(mk & ((1u << j) - 1u)) : zslot;
-            const uint32_t *t = tile + sl * (S / 2) + wib[w] + y0 * H;
-#pragma unroll
-            for (int y = 0; y < HR; y++) {
-              if constexpr (B >= 4) {
-                const uint2 v = *reinterpret_cast<const uint2 *>(t + y * H);
-                x[c][y][0] = add_pk(x[c][y][0], v.x);
-                x[c][y][1] = add_pk(x[c][y][1], v.y);
-              } else {
-                x[c][y][w] = add_pk(x[c][y][w], t[y * H]);
-              }
-            }
-          }
+            return tile + sl * (S / 2);
+          };
+          read_slot(slot(0), B == 2 ? slot(1) : nullptr, true, x[c]);
         };
 #pragma unroll
         for (int k = 0; k < 4; k++)
@@ -1451,12 +1475,19 @@ __device__ __forceinline__ void interp_rgb_pixel(const InterpRGBArgs &a, const l
   for (int k = 0; k < 4; k++) {
     cell(sx + focal_shift<FOCAL>(a.disp, vw.u, a.U, (k & 1) ? iu1 : iu0), a.W, x0, x1, fs[k]);
     cell(ty + focal_shift<FOCAL>(a.disp, vw.v, a.V, (k & 2) ? jv1 : jv0), a.H, y0, y1, ft[k]);
-    const uint32_t r0 = vis[k] * vbytes + (uint32_t)y0 * rbytes, r1 = vis[k] * vbytes + (uint32_t)y1 * rbytes;
+    // a row's offset goes in the load's scalar offset, the column in the
+    // per-lane one, and the hardware adds them
+    if constexpr (FOCAL) {   // (the shifted row is computed per lane otherwise)
+      y0 = __builtin_amdgcn_readfirstlane(y0);
+      y1 = __builtin_amdgcn_readfirstlane(y1);
+    }
+    const uint32_t r0 = __builtin_amdgcn_readfirstlane(vis[k] * vbytes + (uint32_t)y0 * rbytes);
+    const uint32_t r1 = __builtin_amdgcn_readfirstlane(vis[k] * vbytes + (uint32_t)y1 * rbytes);
     const uint32_t c0 = 4u * (uint32_t)x0, c1 = 4u * (uint32_t)x1;
-    P[k][0] = __builtin_amdgcn_raw_buffer_load_b32(rs, r0 + c0, 0, 0);
-    P[k][1] = __builtin_amdgcn_raw_buffer_load_b32(rs, r0 + c1, 0, 0);
-    P[k][2] = __builtin_amdgcn_raw_buffer_load_b32(rs, r1 + c0, 0, 0);
-    P[k][3] = __builtin_amdgcn_raw_buffer_load_b32(rs, r1 + c1, 0, 0);
+    P[k][0] = __builtin_amdgcn_raw_buffer_load_b32(rs, c0, r0, 0);
+    P[k][1] = __builtin_amdgcn_raw_buffer_load_b32(rs, c1, r0, 0);
+    P[k][2] = __builtin_amdgcn_raw_buffer_load_b32(rs, c0, r1, 0);
+    P[k][3] = __builtin_amdgcn_raw_buffer_load_b32(rs, c1, r1, 0);
   }
   interp_store(P, fs, ft, fu, fv, o + (size_t)Yp * a.wo + X, (size_t)a.ho * a.wo);
 }
