@@ -377,7 +377,7 @@ static void build_schedule(const Geometry &g, const std::vector<uint32_t> &off, 
 //   chunk record: q0, nq, nn, n0, n01, n, masks[3][nn] (channel-major),
 //   first slots[3][nn] (16-bit, two per word), runs[nq][3 words],
 //   entries[n], items[n] (32-bit: slot << 20 | node << 8 | channel << 6 |
-//   block; a chunk has at most kRGBNodeCap nodes).
+//   block; a chunk has at most kRGBNodeCap nodes and kRGBNodeCap runs).
 static void build_schedule_rgb(const Geometry &g, const std::vector<uint32_t> &off, const std::vector<uint32_t> &srv,
                                const std::vector<uint32_t> &dbase, const std::vector<uint32_t> &poff,
                                const std::vector<int32_t> &batch, std::vector<uint32_t> &sched,
@@ -429,7 +429,8 @@ static void build_schedule_rgb(const Geometry &g, const std::vector<uint32_t> &o
               add += stored(s);
             }
           }
-          if (k > 0 && (count + add > cap || leaves.size() + ancs.size() + nl.size() + na.size() > (size_t)kRGBNodeCap))
+          if (k > 0 && (count + add > cap || k >= kRGBNodeCap ||
+                        leaves.size() + ancs.size() + nl.size() + na.size() > (size_t)kRGBNodeCap))
             break;
           for (int s : nl) {
             loc[(size_t)s] = 0;

@@ -1131,7 +1131,8 @@ __global__ __launch_bounds__(kRenderThreads) void k_render_multi(const RenderReq
 // has at most lfc::kRGBNodeCap nodes).
 using lfc::kRGBNodeCap;
 constexpr int kRGBNeedWords = 128;        // views a render may mask: at most 32 x 128
-constexpr int kRGBHeadWords = 192 + 96 + 4 + kRGBNodeCap / 32 + kRGBNeedWords + 3 * kRGBNodeCap + 3 * kRGBNodeCap / 2;
+constexpr int kRGBHeadWords = 192 + 96 + 4 + kRGBNodeCap / 32 + kRGBNeedWords + 3 * kRGBNodeCap +
+                               3 * kRGBNodeCap / 2 + 3 * kRGBNodeCap + 4 * kRGBNodeCap / 2;
 constexpr int kRGBKeyWordsMax = 6144;     // key-view rows of a strip staged in LDS up to 24 KB
 
 struct RGBArgs {
@@ -1169,10 +1170,12 @@ __device__ __forceinline__ void rgb_strip(const RGBArgs &a, int st, int part, ui
   constexpr int S = B * B, NBLK = 64 / B, H = B / 2, HR = B;   // HR rows per lane
   const uint16_t *lut = reinterpret_cast<const uint16_t *>(smem);   // 384 x u16 = 192 words
   uint32_t *s_o0 = smem + 192;                          // [3][NBLK] group start words
-  uint32_t *s_any = smem + 288;                         // a wanted view in the chunk
-  uint32_t *s_node = s_any + 4;                         // wanted nodes of the chunk, a bit each
+  uint32_t *s_nlist = smem + 288;                       // [0] listed pairs of the chunk ([2] is the multi kernel's)
+  uint32_t *s_node = s_nlist + 4;                       // wanted nodes of the chunk, a bit each
   uint32_t *s_need = s_node + kRGBNodeCap / 32;         // the view mask
-  uint32_t *s_mf = s_need + kRGBNeedWords;              // masks[3][nn], then first slots (16-bit)
+  uint32_t *s_mf = s_need + kRGBNeedWords;              // masks[3][nn], first slots (16-bit), run node positions[nq][3]
+  uint16_t *s_list = reinterpret_cast<uint16_t *>(s_mf + 3 * kRGBNodeCap + 3 * kRGBNodeCap / 2 + 3 * kRGBNodeCap);
+                                                        // (run << 2 | sibling) pairs of the chunk
   uint32_t *tile = smem + kRGBHeadWords;                // [tile_cap + 1][S/2], the last slot zero
   uint32_t *keys = tile + lf_tile_words(a.tile_cap, S); // [3][n_top][NBLK][S/2], blocks as in the tile
   const int tid = threadIdx.x, lane = tid & 63;
@@ -1203,9 +1206,9 @@ __device__ __forceinline__ void rgb_strip(const RGBArgs &a, int st, int part, ui
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
-  // gather lane mapping: sibling so, 4-pixel segment jseg (word pairs pp = 2 jseg, 2 jseg + 1 of
-  // the strip's 32-word rows); the block and the word inside its row of each pair
-  const int so = lane >> 4, jseg = lane & 15;
+  // gather lane mapping: listed pair lane / 16, 4-pixel segment jseg (word pairs pp = 2 jseg,
+  // 2 jseg + 1 of the strip's 32-word rows); the block and the word inside its row of each pair
+  const int jseg = lane & 15;
   int jb[2], wib[2];
 #pragma unroll
   for (int w = 0; w < 2; w++) {
@@ -1230,38 +1233,45 @@ __device__ __forceinline__ void rgb_strip(const RGBArgs &a, int st, int part, ui
     const uniform_i32 runs = sch + 6 + mf_words;
     const uint32_t *ents = chunk + 6 + mf_words + 3 * nq;
     const uint32_t *items = ents + n;
-    // with a view mask: the chunk's nodes that a wanted view reads (its leaf
-    // and the ancestors of its run); a chunk with none is skipped whole
-    if (masked) {
+    // the chunk's (run, sibling) pairs to write, listed in LDS (with a view
+    // mask only those of wanted views, and the nodes they read are marked);
+    // a chunk with none is skipped whole
+    if (masked)
       for (int w = tid; w < kRGBNodeCap / 32; w += kLFThreads) s_node[w] = 0u;
-      if (tid == 0) *s_any = 0u;
-      __syncthreads();
-      for (int qi = wave; qi < nq; qi += kLFWaves) {
-        const uniform_i32 rec = as_uniform(a.batch + (size_t)(q0 + qi) * lfc::kBatchWords);
-        const int nsib = rec[0];
-        bool wanted[4];
+    if (tid == 0) *s_nlist = 0u;
+    __syncthreads();
+    for (int qi = wave; qi < nq; qi += kLFWaves) {
+      const uniform_i32 rec = as_uniform(a.batch + (size_t)(q0 + qi) * lfc::kBatchWords);
+      const int nsib = rec[0];
+      bool wanted[4];
 #pragma unroll
-        for (int k = 0; k < 4; k++) wanted[k] = k < nsib && wanted_view(max(rec[1 + k], 0));
-        if (!(wanted[0] || wanted[1] || wanted[2] || wanted[3])) continue;
+      for (int k = 0; k < 4; k++) wanted[k] = k < nsib && wanted_view(max(rec[1 + k], 0));
+      if (!(wanted[0] || wanted[1] || wanted[2] || wanted[3])) continue;
+      const bool mine = lane == 0 ? wanted[0] : (lane == 1 ? wanted[1] : (lane == 2 ? wanted[2] : wanted[3]));
+      if (lane < 4 && mine) s_list[atomicAdd(s_nlist, 1u)] = (uint16_t)(qi << 2 | lane);
+      if (masked) {
         const uint32_t w0 = (uint32_t)runs[3 * qi], w1 = (uint32_t)runs[3 * qi + 1], w2 = (uint32_t)runs[3 * qi + 2];
         const int anc_ln[4] = {(int)(w0 >> 16), (int)(w1 & 0xFFFFu), (int)(w1 >> 16), (int)(w2 & 0xFFFFu)};
         int ln = -1;
-        if (lane < 4 && a.L > 1 && (lane == 0 ? wanted[0] : (lane == 1 ? wanted[1] : (lane == 2 ? wanted[2] : wanted[3]))))
+        if (lane < 4 && a.L > 1 && mine)
           ln = (int)(w0 & 0xFFFFu) + lane;
         else if (lane >= 4 && lane < 8 && lane - 4 < a.L - 2)
           ln = lane == 4 ? anc_ln[0] : (lane == 5 ? anc_ln[1] : (lane == 6 ? anc_ln[2] : anc_ln[3]));
         if (ln >= 0) atomicOr(&s_node[ln >> 5], 1u << (ln & 31));
-        if (lane == 0) *s_any = 1u;
-      }
-      __syncthreads();
-      if (*s_any == 0u) {
-        __syncthreads();   // every wave has read the flag before the next chunk clears it
-        continue;
       }
     }
-    // the chunk's node masks and first slots into LDS, in flight during the decode
-    for (int w0 = wave * 64; w0 < mf_words; w0 += kLFThreads)
-      if (w0 + lane < mf_words)
+    __syncthreads();
+    const int n_list = __builtin_amdgcn_readfirstlane((int)*s_nlist);
+    if (n_list == 0) {
+      __syncthreads();   // every wave has read the count before the next chunk clears it
+      continue;
+    }
+    // the chunk's node masks, first slots and run records into LDS, in
+    // flight during the decode (the gather then reads no global memory but
+    // the run's view list)
+    const int tab_words = mf_words + 3 * nq;
+    for (int w0 = wave * 64; w0 < tab_words; w0 += kLFThreads)
+      if (w0 + lane < tab_words)
         __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(chunk + 6 + w0 + lane),
                                          (__attribute__((address_space(3))) void *)(s_mf + w0), 4, 0, 0);
     // (3) decode every stored block of the chunk (that a wanted view reads) into its tile slot
@@ -1288,22 +1298,31 @@ __device__ __forceinline__ void rgb_strip(const RGBArgs &a, int st, int part, ui
     __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's copies of the node table have landed
     lds_barrier();
     const uint16_t *firsts = reinterpret_cast<const uint16_t *>(s_mf + 3 * nn);
-    // (4) one run per wave at a time
-    const int per = (nq + kLFWaves - 1) / kLFWaves;
-    for (int qi = wave * per; qi < min(nq, wave * per + per); qi++) {
+    const uint32_t *s_runs = s_mf + mf_words;
+    // (4) four listed (run, sibling) pairs per wave at a time, one per
+    // 16-lane group; each pair's view and key view come through the scalar
+    // unit (no vector load, which would wait for the wave's stores)
+    for (int e0 = wave * 4; e0 < n_list; e0 += 4 * kLFWaves) {
       constexpr int y0 = 0;
-      const uniform_i32 rec = as_uniform(a.batch + (size_t)(q0 + qi) * lfc::kBatchWords);
-      const int nsib = rec[0], root = rec[5];
-      const int vi = so == 0 ? rec[1] : (so == 1 ? rec[2] : (so == 2 ? rec[3] : rec[4]));
-      // which siblings are written
-      bool wanted[4];
+      const uint2 pr = *reinterpret_cast<const uint2 *>(s_list + e0);
+      const uint32_t ens[4] = {pr.x & 0xFFFFu, pr.x >> 16, pr.y & 0xFFFFu, pr.y >> 16};
+      int f_vi[4], f_root[4], f_q[4], f_so[4];
 #pragma unroll
-      for (int k = 0; k < 4; k++) wanted[k] = k < nsib && wanted_view(max(rec[1 + k], 0));
-      if (!(wanted[0] || wanted[1] || wanted[2] || wanted[3])) continue;
-      const bool live = seg_in && (so == 0 ? wanted[0] : (so == 1 ? wanted[1] : (so == 2 ? wanted[2] : wanted[3])));
-      const uint32_t w0 = (uint32_t)runs[3 * qi], w1 = (uint32_t)runs[3 * qi + 1], w2 = (uint32_t)runs[3 * qi + 2];
+      for (int g = 0; g < 4; g++) {
+        const int en = e0 + g < n_list ? __builtin_amdgcn_readfirstlane((int)ens[g]) : 0;
+        f_q[g] = en >> 2;
+        f_so[g] = en & 3;
+        const uniform_i32 rec = as_uniform(a.batch + (size_t)(q0 + f_q[g]) * lfc::kBatchWords);
+        f_vi[g] = rec[1 + f_so[g]];
+        f_root[g] = rec[5];
+      }
+      const int grp = lane >> 4;
+      auto pick = [&](const int (&f)[4]) { return grp == 0 ? f[0] : (grp == 1 ? f[1] : (grp == 2 ? f[2] : f[3])); };
+      const int vi = pick(f_vi), root = pick(f_root), qi = pick(f_q), so = pick(f_so);
+      const bool live = seg_in && e0 + grp < n_list;
+      const uint32_t w0 = s_runs[3 * qi], w1 = s_runs[3 * qi + 1], w2 = s_runs[3 * qi + 2];
       const int anc_ln[4] = {(int)(w0 >> 16), (int)(w1 & 0xFFFFu), (int)(w1 >> 16), (int)(w2 & 0xFFFFu)};
-      const int leaf = min((int)(w0 & 0xFFFFu) + so, nn - 1);   // the lane's own leaf
+      const int leaf = min((int)(w0 & 0xFFFFu) + so, max(nn - 1, 0));   // the lane's own leaf
       uint32_t x[3][HR][2];
       // the lane's words of a block slot (tile or key rows, same layout):
       // B = 4, the whole 4 x 4 block in two 16-byte reads; B = 2, both rows
