@@ -437,9 +437,20 @@ __device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, c
   const uint32_t *masks = tab;
   const uint16_t *firsts = reinterpret_cast<const uint16_t *>(masks + nn);
   const uint32_t *runs = masks + nn + (nn + 1) / 2;
-  // (3) decode; the three kinds are laid end to end, so a wave mostly sees one kind
+  // (3) decode; the three kinds are laid end to end, so a wave mostly sees one kind.
+  // A lane's next entry is requested before its current block's payload, so
+  // the two reads overlap.
+  uint32_t e_nx = 0, t_nx = 0;
+  if ((uint32_t)tid < n) {
+    e_nx = ents[tid];
+    t_nx = items[tid];
+  }
   for (uint32_t it = tid; it < n; it += kLFThreads) {
-    const uint32_t e = ents[it], t = items[it];
+    const uint32_t e = e_nx, t = t_nx;
+    if (it + kLFThreads < n) {
+      e_nx = ents[it + kLFThreads];
+      t_nx = items[it + kLFThreads];
+    }
     const uint32_t *gw = pw + s_po[t & 31u];
     uint32_t d[S / 2];
     if (it < n0) decode_block_k<B, 0>(gw, e, a.q, lut, d);
@@ -1233,23 +1244,25 @@ __device__ __forceinline__ void rgb_strip(const RGBArgs &a, int st, int part, ui
     const uniform_i32 runs = sch + 6 + mf_words;
     const uint32_t *ents = chunk + 6 + mf_words + 3 * nq;
     const uint32_t *items = ents + n;
-    // the chunk's (run, sibling) pairs to write, listed in LDS (with a view
-    // mask only those of wanted views, and the nodes they read are marked);
-    // a chunk with none is skipped whole
-    if (masked)
+    // with a view mask, the chunk's (run, sibling) pairs of wanted views are
+    // listed in LDS and the nodes they read are marked (a chunk with none is
+    // skipped whole); without one, pair e is sibling e % 4 of run e / 4
+    int n_list = 4 * nq;
+    if (masked) {
       for (int w = tid; w < kRGBNodeCap / 32; w += kLFThreads) s_node[w] = 0u;
-    if (tid == 0) *s_nlist = 0u;
-    __syncthreads();
-    for (int qi = wave; qi < nq; qi += kLFWaves) {
-      const uniform_i32 rec = as_uniform(a.batch + (size_t)(q0 + qi) * lfc::kBatchWords);
-      const int nsib = rec[0];
-      bool wanted[4];
+      if (tid == 0) *s_nlist = 0u;
+      // (barriers on LDS only: a full barrier would also wait for the stores
+      // of the previous chunk's gather)
+      lds_barrier();
+      for (int qi = wave; qi < nq; qi += kLFWaves) {
+        const uniform_i32 rec = as_uniform(a.batch + (size_t)(q0 + qi) * lfc::kBatchWords);
+        const int nsib = rec[0];
+        bool wanted[4];
 #pragma unroll
-      for (int k = 0; k < 4; k++) wanted[k] = k < nsib && wanted_view(max(rec[1 + k], 0));
-      if (!(wanted[0] || wanted[1] || wanted[2] || wanted[3])) continue;
-      const bool mine = lane == 0 ? wanted[0] : (lane == 1 ? wanted[1] : (lane == 2 ? wanted[2] : wanted[3]));
-      if (lane < 4 && mine) s_list[atomicAdd(s_nlist, 1u)] = (uint16_t)(qi << 2 | lane);
-      if (masked) {
+        for (int k = 0; k < 4; k++) wanted[k] = k < nsib && wanted_view(max(rec[1 + k], 0));
+        if (!(wanted[0] || wanted[1] || wanted[2] || wanted[3])) continue;
+        const bool mine = lane == 0 ? wanted[0] : (lane == 1 ? wanted[1] : (lane == 2 ? wanted[2] : wanted[3]));
+        if (lane < 4 && mine) s_list[atomicAdd(s_nlist, 1u)] = (uint16_t)(qi << 2 | lane);
         const uint32_t w0 = (uint32_t)runs[3 * qi], w1 = (uint32_t)runs[3 * qi + 1], w2 = (uint32_t)runs[3 * qi + 2];
         const int anc_ln[4] = {(int)(w0 >> 16), (int)(w1 & 0xFFFFu), (int)(w1 >> 16), (int)(w2 & 0xFFFFu)};
         int ln = -1;
@@ -1259,12 +1272,12 @@ __device__ __forceinline__ void rgb_strip(const RGBArgs &a, int st, int part, ui
           ln = lane == 4 ? anc_ln[0] : (lane == 5 ? anc_ln[1] : (lane == 6 ? anc_ln[2] : anc_ln[3]));
         if (ln >= 0) atomicOr(&s_node[ln >> 5], 1u << (ln & 31));
       }
-    }
-    __syncthreads();
-    const int n_list = __builtin_amdgcn_readfirstlane((int)*s_nlist);
-    if (n_list == 0) {
-      __syncthreads();   // every wave has read the count before the next chunk clears it
-      continue;
+      lds_barrier();
+      n_list = __builtin_amdgcn_readfirstlane((int)*s_nlist);
+      if (n_list == 0) {
+        lds_barrier();   // every wave has read the count before the next chunk clears it
+        continue;
+      }
     }
     // the chunk's node masks, first slots and run records into LDS, in
     // flight during the decode (the gather then reads no global memory but
@@ -1275,8 +1288,17 @@ __device__ __forceinline__ void rgb_strip(const RGBArgs &a, int st, int part, ui
         __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(chunk + 6 + w0 + lane),
                                          (__attribute__((address_space(3))) void *)(s_mf + w0), 4, 0, 0);
     // (3) decode every stored block of the chunk (that a wanted view reads) into its tile slot
+    uint32_t e_nx = 0, t_nx = 0;   // the lane's next entry, requested ahead (as in the one-channel kernel)
+    if ((uint32_t)tid < n) {
+      e_nx = ents[tid];
+      t_nx = items[tid];
+    }
     for (uint32_t it = tid; it < n; it += kLFThreads) {
-      const uint32_t e = ents[it], t = items[it];
+      const uint32_t e = e_nx, t = t_nx;
+      if (it + kLFThreads < n) {
+        e_nx = ents[it + kLFThreads];
+        t_nx = items[it + kLFThreads];
+      }
       if (masked) {
         const uint32_t ln = (t >> 8) & 4095u;
         if (!((s_node[ln >> 5] >> (ln & 31u)) & 1u)) continue;
@@ -1304,9 +1326,18 @@ __device__ __forceinline__ void rgb_strip(const RGBArgs &a, int st, int part, ui
     // unit (no vector load, which would wait for the wave's stores)
     for (int e0 = wave * 4; e0 < n_list; e0 += 4 * kLFWaves) {
       constexpr int y0 = 0;
-      const uint2 pr = *reinterpret_cast<const uint2 *>(s_list + e0);
-      const uint32_t ens[4] = {pr.x & 0xFFFFu, pr.x >> 16, pr.y & 0xFFFFu, pr.y >> 16};
-      int f_vi[4], f_root[4], f_q[4], f_so[4];
+      uint32_t ens[4];
+      if (masked) {
+        const uint2 pr = *reinterpret_cast<const uint2 *>(s_list + e0);
+        ens[0] = pr.x & 0xFFFFu;
+        ens[1] = pr.x >> 16;
+        ens[2] = pr.y & 0xFFFFu;
+        ens[3] = pr.y >> 16;
+      } else {
+#pragma unroll
+        for (int g = 0; g < 4; g++) ens[g] = (uint32_t)(e0 + g);
+      }
+      int f_vi[4], f_root[4], f_q[4], f_so[4], f_ok[4];
 #pragma unroll
       for (int g = 0; g < 4; g++) {
         const int en = e0 + g < n_list ? __builtin_amdgcn_readfirstlane((int)ens[g]) : 0;
@@ -1315,11 +1346,12 @@ __device__ __forceinline__ void rgb_strip(const RGBArgs &a, int st, int part, ui
         const uniform_i32 rec = as_uniform(a.batch + (size_t)(q0 + f_q[g]) * lfc::kBatchWords);
         f_vi[g] = rec[1 + f_so[g]];
         f_root[g] = rec[5];
+        f_ok[g] = e0 + g < n_list && f_so[g] < rec[0];   // (listed pairs are always present siblings)
       }
       const int grp = lane >> 4;
       auto pick = [&](const int (&f)[4]) { return grp == 0 ? f[0] : (grp == 1 ? f[1] : (grp == 2 ? f[2] : f[3])); };
       const int vi = pick(f_vi), root = pick(f_root), qi = pick(f_q), so = pick(f_so);
-      const bool live = seg_in && e0 + grp < n_list;
+      const bool live = seg_in && pick(f_ok);
       const uint32_t w0 = s_runs[3 * qi], w1 = s_runs[3 * qi + 1], w2 = s_runs[3 * qi + 2];
       const int anc_ln[4] = {(int)(w0 >> 16), (int)(w1 & 0xFFFFu), (int)(w1 >> 16), (int)(w2 & 0xFFFFu)};
       const int leaf = min((int)(w0 & 0xFFFFu) + so, max(nn - 1, 0));   // the lane's own leaf
@@ -1438,9 +1470,9 @@ __global__ __launch_bounds__(kLFThreads) void k_decode_rgb_multi(RGBMultiArgs m)
   for (int t = threadIdx.x; t < kLutEntries; t += kLFThreads) lut[t] = lut_entry(t);
   const uniform_i32 first = as_uniform(m.first);
   for (;;) {
-    __syncthreads();   // every wave is done with the previous item's LDS
+    lds_barrier();   // every wave is done with the previous item's LDS (its stores may still be in flight)
     if (threadIdx.x == 0) *s_item = atomicAdd(&m.ctr[0], 1u);
-    __syncthreads();
+    lds_barrier();
     const int item = __builtin_amdgcn_readfirstlane((int)*s_item);
     if (item >= m.n_items) break;
     int lf = 0;
