@@ -2,7 +2,8 @@
 
     python -m paper_1805_06019_amd.prof_summary trace <kernel_trace.db> [command]
     python -m paper_1805_06019_amd.prof_summary traffic <fetch.db> <write.db> <out.json> [command [tile_blocks [staged]]]
-    python -m paper_1805_06019_amd.prof_summary counters <counters.db>...
+    python -m paper_1805_06019_amd.prof_summary counters <counters.db>... [--kernel NAME]...
+    python -m paper_1805_06019_amd.prof_summary kernel_traffic <fetch.db> <write.db> NAME...
 
 ``trace`` prints a markdown table of per-kernel dispatch counts and durations.
 ``traffic`` reads one FETCH_SIZE run and one WRITE_SIZE run (KiB per
@@ -11,8 +12,10 @@ copy of 256 MiB in the same run (the copy moves exactly 256 MiB each way),
 and writes the per-launch HBM bytes of the whole-field decode kernel,
 together with a hash of the kernel source it was measured on and the decode
 tile capacity and staging of the run.
-``counters`` prints, for the whole-field decode kernel, the mean per dispatch
-of every counter in the given runs.
+``counters`` prints, for the whole-field decode kernel (or the kernels named
+with --kernel, short names as ``k_interp_rgb<0>``), the mean per dispatch
+of every counter in the given runs.  ``kernel_traffic`` prints the
+copy-calibrated FETCH and WRITE bytes per dispatch of the named kernels.
 """
 from __future__ import annotations
 
@@ -55,9 +58,14 @@ def kernel_source_hash() -> str:
 
 
 def short_name(name: str) -> str:
-    m = re.search(r"(k_\w+)(?:<(\d)>|ILi(\d)E)", name)
+    """A kernel's name with its template arguments (k_decode_lf<4>,
+    k_decode_rgb<4, true>, k_interp_rgb<false>), else the first 60 characters."""
+    m = re.search(r"(k_\w+)ILi(\d)E", name)
     if m:
-        return f"{m.group(1)}<{m.group(2) or m.group(3)}>"
+        return f"{m.group(1)}<{m.group(2)}>"
+    m = re.search(r"(k_\w+)(<[^()]*>)?", name)
+    if m:
+        return m.group(1) + (m.group(2) or "")
     return name[:60]
 
 
@@ -139,14 +147,41 @@ def main(argv):
             fh.write("\n")
         print(json.dumps(rec, indent=1))
     elif mode == "counters":
-        print("| counter | dispatches | mean per dispatch |")
-        print("|---|---|---|")
-        for db in argv[2:]:
-            for name, d in counters_per_dispatch(db).items():
-                if short_name(name) != DECODE_KERNEL:
-                    continue
-                for c in sorted(d):
-                    print(f"| {c} | {len(d[c])} | {sum(d[c]) / len(d[c]):,.0f} |")
+        dbs, kernels, rest = [], [], argv[2:]
+        while rest:
+            if rest[0] == "--kernel":
+                kernels.append(rest[1])
+                rest = rest[2:]
+            else:
+                dbs.append(rest[0])
+                rest = rest[1:]
+        kernels = kernels or [DECODE_KERNEL]
+        print("| kernel | counter | dispatches | mean per dispatch |")
+        print("|---|---|---|---|")
+        for k in kernels:
+            for db in dbs:
+                for name, d in counters_per_dispatch(db).items():
+                    if short_name(name) != k:
+                        continue
+                    for c in sorted(d):
+                        print(f"| {k} | {c} | {len(d[c])} | {sum(d[c]) / len(d[c]):,.0f} |")
+    elif mode == "kernel_traffic":
+        fetch = counter_per_dispatch(argv[2], "FETCH_SIZE")
+        write = counter_per_dispatch(argv[3], "WRITE_SIZE")
+        f_scale = copy_kernel_value(fetch) * 1024 / COPY_BYTES
+        w_scale = copy_kernel_value(write) * 1024 / COPY_BYTES
+        print(f"copy calibration: FETCH_SIZE x {f_scale:.4f}, WRITE_SIZE x {w_scale:.4f} of the bytes moved")
+        print("| kernel | dispatches | HBM read MB | HBM write MB |")
+        print("|---|---|---|---|")
+        by_short = lambda per: {short_name(n): v for n, v in per.items()}
+        fetch_s, write_s = by_short(fetch), by_short(write)
+        for k in argv[4:]:
+            fv, wv = fetch_s.get(k, []), write_s.get(k, [])
+            if not fv or not wv:
+                print(f"| {k} | 0 | - | - |")
+                continue
+            print(f"| {k} | {len(fv)} | {sum(fv) / len(fv) * 1024 / f_scale / 1e6:.1f} | "
+                  f"{sum(wv) / len(wv) * 1024 / w_scale / 1e6:.1f} |")
     else:
         raise SystemExit(__doc__)
 
