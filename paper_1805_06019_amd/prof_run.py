@@ -1,6 +1,6 @@
 """Workloads run alone, for rocprofv3 runs behind the committed profiles.
 
-    python -m paper_1805_06019_amd.prof_run [--reps N] [--calib-copy] WORKLOAD...
+    python paper_1805_06019_amd/prof_run.py [--reps N] [--calib-copy] WORKLOAD...
 
 WORKLOAD is one of
   render64_full40     64 novel 512 x 512 views of the 17 x 17 field at 40 dB
@@ -17,9 +17,13 @@ per workload gives the mean and median per launch.  --calib-copy adds one
 from __future__ import annotations
 
 import argparse
+import os
 import sys
 
 import numpy as np
+
+if __package__ in (None, ""):   # run as a script (e.g. under rocprofv3 from another directory)
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
 
 def _timed(fn, n, torch):

@@ -171,6 +171,7 @@ def main(argv):
         f_scale = copy_kernel_value(fetch) * 1024 / COPY_BYTES
         w_scale = copy_kernel_value(write) * 1024 / COPY_BYTES
         print(f"copy calibration: FETCH_SIZE x {f_scale:.4f}, WRITE_SIZE x {w_scale:.4f} of the bytes moved")
+        print()
         print("| kernel | dispatches | HBM read MB | HBM write MB |")
         print("|---|---|---|---|")
         by_short = lambda per: {short_name(n): v for n, v in per.items()}
