@@ -1668,6 +1668,34 @@ int device_cus() {
   return v;
 }
 
+// Stream-ordered scratch from a memory pool of the library's own per device,
+// which keeps up to 1 GiB of freed memory for the next call instead of
+// returning it at each synchronisation (the default pool's release threshold
+// is zero); the process's default pool is left as it is.
+hipMemPool_t scratch_pool() {
+  constexpr int kDevices = 64;
+  static std::mutex mu;
+  static hipMemPool_t pools[kDevices] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!pools[dev]) {
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pl = nullptr;
+    if (hipMemPoolCreate(&pl, &props) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    uint64_t keep = (uint64_t)1 << 30;
+    if (hipMemPoolSetAttribute(pl, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) (void)hipGetLastError();
+    pools[dev] = pl;
+  }
+  return pools[dev];
+}
+
 // LDS of the whole-field kernel: the fixed part (LUT and extents, residual
 // tile, key-view rows) plus staging for the strip's groups and decode
 // schedule, up to 80 KB so that two workgroups share a compute unit.
@@ -1832,15 +1860,14 @@ int need_words(const lfc::Geometry &g) { return (g.nv() + 31) / 32; }
 size_t decoded_bytes(const lfc::Geometry &g) { return ((rgb_bytes(g) + 255) & ~(size_t)255) + 4 * (size_t)need_words(g); }
 
 // One render with a resolved choice.  The decoded path decodes into ws when
-// given, else into stream-ordered scratch (served from the pool after the
-// first call).
+// given, else into stream-ordered scratch from the library's pool.
 template <int B>
 lfc_status render_with(const lfc_lf *lf, const lfc_view *views, int32_t n, int32_t wo, int32_t ho, float *out,
                        const RenderChoice &rc, void *ws, hipStream_t s) {
   const lfc::Geometry &g = lf->geo;
   if (rc.decoded) {
     void *dec = ws;
-    if (!dec && hipMallocAsync(&dec, decoded_bytes(g), s) != hipSuccess)
+    if (!dec && lfc::scratch_alloc(&dec, decoded_bytes(g), s) != LFC_OK)
       return fail(LFC_E_NOMEM, "lfc_render_views: scratch for the decoded views");
     uint32_t *rgb = static_cast<uint32_t *>(dec);
     uint32_t *mask = reinterpret_cast<uint32_t *>(static_cast<char *>(dec) + ((rgb_bytes(g) + 255) & ~(size_t)255));
@@ -2185,6 +2212,18 @@ extern "C" lfc_status lfc_render_plan_info(const lfc_render_plan *p, lfc_render_
 }
 
 namespace lfc {
+
+lfc_status scratch_alloc(void **p, size_t bytes, hipStream_t s) {
+  *p = nullptr;
+  hipMemPool_t pl = scratch_pool();
+  const hipError_t he = pl ? hipMallocFromPoolAsync(p, bytes, pl, s) : hipMallocAsync(p, bytes, s);
+  if (he != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return LFC_E_NOMEM;
+  }
+  return LFC_OK;
+}
 
 lfc_status device_buffer(const void *p, size_t need, size_t align, const char *who, const char *what) {
   return check_buffer(p, need, align, who, what);

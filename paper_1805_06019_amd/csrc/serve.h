@@ -19,6 +19,9 @@ size_t render_req_bytes();
 // LFC_OK if p is device memory holding at least `need` bytes (within one
 // allocation) at the given alignment; else LFC_E_INVALID naming who and what.
 lfc_status device_buffer(const void *p, size_t need, size_t align, const char *who, const char *what);
+// Stream-ordered device scratch from the library's pool (freed with hipFreeAsync
+// on the same stream); LFC_E_NOMEM if it cannot be had.
+lfc_status scratch_alloc(void **p, size_t bytes, hipStream_t s);
 
 // Packs request (view v of lf at wo x ho into out, [3][ho][wo] floats) into
 // dst; reports the light field's block size, the request's tile count and
