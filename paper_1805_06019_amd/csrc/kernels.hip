@@ -112,14 +112,22 @@ __device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(
 // two samples at once: a + b modulo 2^16 per half
 __device__ __forceinline__ uint32_t add_pk(uint32_t a, uint32_t b) { return as_u32(as_u16x2(a) + as_u16x2(b)); }
 
-// two zigzagged values (0,1,2,3,.. -> 0,-1,1,-2,..) back to signed, times 2^q
-__device__ __forceinline__ uint32_t unzigzag_pk(uint32_t pr, int q) {
-  const u16x2 x = as_u16x2(pr);
-  const u16x2 one = {1, 1};
-  const u16x2 zero = {0, 0};
-  u16x2 r = (x >> one) ^ (zero - (x & one));
-  const u16x2 sh = {(unsigned short)q, (unsigned short)q};
-  return as_u32(r << sh);
+// Two zigzagged values (0,1,2,3,.. -> 0,-1,1,-2,..) in the 16-bit halves of
+// z, back to signed and times 2^q (0 <= q <= 4), as int16 pairs.  A value's
+// magnitude times 2^q is (z >> 1) << q = z rotated left by q - 1 (right by
+// 1 for q = 0) with the low half's top bit and the word's top bit cleared;
+// a negative value's bits from q - 1 up are then inverted, which also clears
+// bit q - 1 (its zigzag parity bit).  Every zigzag value of a valid stream is
+// below 2^12 (at most 12 plain bits, or 6 bits below a trit or quint digit),
+// so nothing crosses between the halves; equal, for all such pairs and every
+// q, to unzigzagging each half and shifting it left by q (checked
+// exhaustively on the host).  Five VALU operations per pair against seven
+// with packed 16-bit shifts.
+__device__ __forceinline__ uint32_t unzigzag_pk(uint32_t z, int q) {
+  const uint32_t rot = (uint32_t)(33 - q) & 31u;
+  const uint32_t inv = q ? (0xFFFFu << (q - 1)) & 0xFFFFu : 0xFFFFu;   // the bits a negative value inverts
+  const uint32_t t = __builtin_amdgcn_alignbit(z, z, rot) & 0x7FFF7FFFu;
+  return t ^ ((z & 0x00010001u) * inv);
 }
 
 // Where the digits of row y (values y*B .. y*B+B-1) sit in a trit or quint
@@ -590,8 +598,10 @@ __device__ __forceinline__ void lf_chunk(const LFArgs &a, const uint32_t *sch, c
 // stored blocks fit the compact tile): decode every stored residual block of
 // the chunk once into the tile, then write the chunk's leaves (key view +
 // ancestors + leaf), 16 bytes per lane.
+// (B <= 4: at most 80 VGPRs, six waves per SIMD, so three workgroups share a
+// compute unit whenever their LDS fits; B = 8 keeps its registers)
 template <int B>
-__global__ __launch_bounds__(kLFThreads) void k_decode_lf(LFArgs a) {
+__global__ __launch_bounds__(kLFThreads, B <= 4 ? 6 : 1) void k_decode_lf(LFArgs a) {
   constexpr int S = B * B, NBLK = 64 / B, H = B / 2;
   constexpr int PB = 8 / B;                            // blocks per 16-byte row segment (1 for B = 8)
   extern __shared__ uint32_t smem[];
