@@ -1196,6 +1196,7 @@ struct Parsed {
   std::vector<uint32_t> off, srv;       // aligned copies; srv ends with the 2 zero words
   std::vector<uint32_t> dbase, poff;    // directory (built on request)
   std::vector<uint32_t> pbase;          // [ng+1] index in poff of each group's first stored block
+  std::vector<uint32_t> dir2;           // [nb][nbw][3] (bitmap word, dbase) pairs, the three channels together
   uint64_t present = 0;
 };
 
@@ -1350,6 +1351,19 @@ static lfc_status parse_validate(const void *stream, size_t bytes, Parsed &ps, b
         rel += bise_block_bits((int)k, S);
       }
     }
+  });
+  // the same lookups laid out for random access: for block b and bitmap word
+  // w, the three channels' (bitmap word, directory index) pairs side by side,
+  // so one access reads them from one cache line instead of four
+  ps.dir2.assign((size_t)g.nb * g.nbw * 3 * 2, 0);
+  parallel_for(g.nb, 1024, [&](int64_t a, int64_t e) {
+    for (int64_t b = a; b < e; b++)
+      for (int w = 0; w < g.nbw; w++)
+        for (int c = 0; c < 3; c++) {
+          const size_t gi = 3 * (size_t)b + c, at = (((size_t)b * g.nbw + w) * 3 + c) * 2;
+          ps.dir2[at] = ps.off[gi + 1] == ps.off[gi] ? 0u : ps.srv[ps.off[gi] + w];
+          ps.dir2[at + 1] = ps.dbase[gi * g.nbw + w];
+        }
   });
   return LFC_OK;
 }
@@ -1506,7 +1520,7 @@ extern "C" lfc_status lfc_open_ex(const void *stream, size_t bytes, const lfc_op
   } catch (const std::bad_alloc &) {
     return fail(LFC_E_NOMEM, "lfc_open: out of host memory");
   }
-  Part parts[16] = {
+  Part parts[17] = {
       {ps.rkv, ps.rkv_bytes, 0},
       {ps.off.data(), ps.off.size() * 4, 0},
       {ps.srv.data(), ps.srv.size() * 4, 0},
@@ -1523,6 +1537,7 @@ extern "C" lfc_status lfc_open_ex(const void *stream, size_t bytes, const lfc_op
       {rgbt.sched.data(), rgbt.sched.size() * 4, 0},
       {rgbt.strip_off.data(), rgbt.strip_off.size() * 4, 0},
       {rgbt.order.data(), rgbt.order.size() * 4, 0},
+      {ps.dir2.data(), ps.dir2.size() * 4, 0},
   };
   size_t total = 0;
   for (auto &pt : parts) {
@@ -1578,6 +1593,7 @@ extern "C" lfc_status lfc_open_ex(const void *stream, size_t bytes, const lfc_op
   lf->d_sched_rgb = reinterpret_cast<const uint32_t *>(d + parts[13].at);
   lf->d_strip_off_rgb = reinterpret_cast<const uint32_t *>(d + parts[14].at);
   lf->d_order_rgb = reinterpret_cast<const uint32_t *>(d + parts[15].at);
+  lf->d_dir2 = reinterpret_cast<const uint32_t *>(d + parts[16].at);
   lf->tile_cap_rgb = tile_cap_rgb;
   for (size_t st = 0; st + 1 < rgbt.strip_off.size(); st++)
     lf->rgb_max_chunks = std::max<int>(lf->rgb_max_chunks, (int)rgbt.sched[rgbt.strip_off[st]]);

@@ -88,6 +88,7 @@ struct lfc_lf {
   const uint32_t *d_dbase = nullptr; // [ng][nbw] directory index of each bitmap word's first node
   const uint32_t *d_poff = nullptr;  // [present] (payload bit offset in group << 5) | code
   const uint32_t *d_pbase = nullptr; // [ng+1] index in d_poff of each group's first stored block
+  const uint32_t *d_dir2 = nullptr;  // [nb][nbw][3][2] per block, bitmap word and channel: (bitmap word, d_dbase entry)
   const int32_t *d_path = nullptr;   // [nv][L-1]
   const int32_t *d_root = nullptr;   // [nv]
   const int32_t *d_batch = nullptr;  // [n_batch][kBatchWords]

@@ -749,6 +749,7 @@ struct RAArgs {
   const int32_t *path;
   const int32_t *root;
   int nb, nbx, nv, nbw, L, q;
+  const uint32_t *dir2;   // [nb][nbw][3] (bitmap word, dbase entry) pairs
 };
 
 // Row y of block b, channel c, of view vi (Alg. 2): key-view row plus the
@@ -768,10 +769,12 @@ __device__ __forceinline__ void gather_row(const RAArgs &a, int vi, int b, int c
   const int depth = a.L - 1;
   for (int l = depth - 1; l >= stop; --l) {
     const int s = a.path[vi * depth + l];
-    const uint32_t bm = gw[s >> 5];
+    // the bitmap word and the directory index of its first stored node, read together
+    const uint2 bd = *reinterpret_cast<const uint2 *>(a.dir2 + (((size_t)b * a.nbw + (s >> 5)) * 3 + c) * 2);
+    const uint32_t bm = bd.x;
     const uint32_t bit = (uint32_t)s & 31u;
     if ((bm >> bit) & 1u) {
-      const uint32_t idx = a.dbase[(size_t)g * a.nbw + (s >> 5)] + __popc(bm & ((1u << bit) - 1u));
+      const uint32_t idx = bd.y + __popc(bm & ((1u << bit) - 1u));
       uint32_t d[B / 2];
       decode_row<B>(gw, a.poff[idx], plan_t, plan_q, y, a.q, lut, d);
 #pragma unroll
@@ -896,11 +899,11 @@ __device__ __forceinline__ int32_t hi16(uint32_t w) { return (int32_t)(int16_t)(
 __device__ __forceinline__ uint32_t locate(const RAArgs &a, int g, int s, const uint32_t **gw_out) {
   const uint32_t o0 = a.off[g], o1 = a.off[g + 1];
   if (o0 == o1) return kAbsent;
-  const uint32_t *gw = a.srv + o0;
-  const uint32_t bm = gw[s >> 5], bit = (uint32_t)s & 31u;
+  const uint2 bd = *reinterpret_cast<const uint2 *>(a.dir2 + ((size_t)(g / 3 * a.nbw + (s >> 5)) * 3 + g % 3) * 2);
+  const uint32_t bm = bd.x, bit = (uint32_t)s & 31u;
   if (!((bm >> bit) & 1u)) return kAbsent;
-  *gw_out = gw;
-  return a.poff[a.dbase[(size_t)g * a.nbw + (s >> 5)] + __popc(bm & ((1u << bit) - 1u))];
+  *gw_out = a.srv + o0;
+  return a.poff[bd.y + __popc(bm & ((1u << bit) - 1u))];
 }
 
 // Threads of a render-tile workgroup: 8 waves, so that a tile's footprint
@@ -1635,7 +1638,7 @@ lfc_status check_buffer(const void *p, size_t need, size_t align, const char *wh
 RAArgs ra_args(const lfc_lf *lf) {
   const lfc::Geometry &g = lf->geo;
   return RAArgs{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_dbase, lf->d_poff, lf->d_path, lf->d_root,
-                g.nb, g.nbx, g.nv(), g.nbw, g.L, g.q};
+                g.nb, g.nbx, g.nv(), g.nbw, g.L, g.q, lf->d_dir2};
 }
 
 lfc_status launched(const char *who) {
