@@ -350,7 +350,10 @@ def main():
     extra = {}
     stream50 = streaml = dec50 = None
     if not args.quick:
-        # batched render: 64 novel 512x512 views per launch (fused decode)
+        # batched render: 64 novel 512x512 views per launch (fused decode); the
+        # colour kernel's tile capacity measured first (untimed setup)
+        rgb_tile40, rgb_tried40 = lfc.lfc_tune_decode_rgb(lf, reps=3)
+        log(f"colour decode tuning: {rgb_tried40} -> {rgb_tile40}")
         views = torch.from_numpy(synth.novel_views(64, 17, 17, seed=302)).cuda()
         img = torch.empty((64, 3, 512, 512), dtype=torch.float32, device="cuda")
         rfn = lambda: lfc.lfc_render_views(lf, views, 512, 512, out=img)
@@ -365,7 +368,9 @@ def main():
                                       views_per_s=round(64 / (r.mean() * 1e-3), 1),
                                       output_write_frac_of_hbm=round(out_bytes / (r.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                       roofline=dict(bound="hbm", algorithmic_bytes=render_bytes,
-                                                    frac=round(render_bytes / (r.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)))
+                                                    frac=round(render_bytes / (r.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)),
+                                      rgb_tile_blocks=rgb_tile40,
+                                      rgb_tile_tuning={str(c): round(ms, 4) for c, ms in rgb_tried40})
         # plain kernel: one launch per 512x512 view request
         one = torch.from_numpy(synth.novel_views(200, 17, 17, seed=303)).cuda()
         img1 = torch.empty((1, 3, 512, 512), dtype=torch.float32, device="cuda")
@@ -446,6 +451,8 @@ def main():
         rgbl = synth.light_field(wl.spec)
         streaml, stl = lfc.lfc_encode_ex(rgbl, wl.params())
         lfl = lfc.lfc_open(streaml)
+        rgb_tilel, rgb_triedl = lfc.lfc_tune_decode_rgb(lfl, reps=3)
+        log(f"lenslet40 colour decode tuning: {rgb_triedl} -> {rgb_tilel}")
         vl = torch.from_numpy(synth.novel_views(64, 9, 9, seed=302)).cuda()
         imgl = torch.empty((64, 3, 512, 512), dtype=torch.float32, device="cuda")
         lfn = lambda: lfc.lfc_render_views(lfl, vl, 512, 512, out=imgl)
@@ -457,7 +464,9 @@ def main():
                                          views_per_s=round(64 / (rl.mean() * 1e-3), 1),
                                          roofline=dict(bound="hbm", algorithmic_bytes=render_bytes_l,
                                                        frac=round(render_bytes_l / (rl.mean() * 1e-3) / 1e9
-                                                                  / HBM_PEAK_GBS, 4)))
+                                                                  / HBM_PEAK_GBS, 4)),
+                                         rgb_tile_blocks=rgb_tilel,
+                                         rgb_tile_tuning={str(c): round(ms, 4) for c, ms in rgb_triedl})
         bestl, _ = lfc.lfc_render_tune(lfl, vl, 512, 512, out=imgl, reps=5)
         planl = lfc.RenderPlan(lfl, vl, 512, 512, out=imgl, cfg=bestl, graph=True)
         planl.launch()

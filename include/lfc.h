@@ -430,6 +430,25 @@ lfc_status lfc_decode_progressive(const lfc_lf *lf, const int32_t *d_req, int64_
 lfc_status lfc_decode_rgb(const lfc_lf *lf, uint32_t *d_out, hipStream_t s);
 
 /*
+ * Measured choice of the colour whole-field kernel's tile capacity (the
+ * kernel behind lfc_decode_rgb, the decode-then-interpolate renders and the
+ * dense light fields of lfc_batch_render): times lfc_decode_rgb of every view
+ * (one warm-up, then `reps` launches, events on stream s, output to d_out as
+ * lfc_decode_rgb) with the handle's current capacity and with 4/8, 5/8, 6/8,
+ * 7/8 and 10/8 of the default (those whose tile fits the LDS), rebuilding the
+ * colour strip tables for each, and keeps the fastest in the handle; res
+ * reports the capacities tried (staged[] all 0).  A smaller tile leaves room
+ * for more workgroups per compute unit, a larger one needs fewer chunks per
+ * strip; which wins depends on the light field.  Blocks until done.  The
+ * handle must not be in use by another call (renders, batches) meanwhile.
+ * Decoded and rendered results do not depend on the choice.
+ * Errors: LFC_E_INVALID (null pointer, reps outside 1..1000, handle of
+ * another device), LFC_E_UNSUPPORTED (a tree of one level), LFC_E_NOMEM,
+ * LFC_E_HIP; on error the handle keeps the tables it had.
+ */
+lfc_status lfc_tune_decode_rgb(lfc_lf *lf, uint32_t *d_out, int32_t reps, lfc_decode_tuning *res, hipStream_t s);
+
+/*
  * Novel-view rendering (Sec. 3.6): every output pixel is the quadrilinear
  * interpolation, over the two nearest camera columns, the two nearest
  * camera rows and the 2 x 2 nearest source pixels, of decoded samples

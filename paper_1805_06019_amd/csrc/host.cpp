@@ -1810,9 +1810,157 @@ extern "C" lfc_status lfc_tune_decode(lfc_lf *lf, int16_t *d_out, int32_t reps, 
   return st;
 }
 
+// Measured choice of the colour whole-field kernel's tile capacity, as
+// lfc_tune_decode for the one-channel kernel: the colour strip tables are
+// rebuilt for each candidate and lfc_decode_rgb of every view is timed.
+extern "C" lfc_status lfc_tune_decode_rgb(lfc_lf *lf, uint32_t *d_out, int32_t reps, lfc_decode_tuning *res,
+                                          hipStream_t s) {
+  if (!lf || !d_out || !res) return fail(LFC_E_INVALID, "lfc_tune_decode_rgb: null argument");
+  if (reps < 1 || reps > 1000) return fail(LFC_E_INVALID, "lfc_tune_decode_rgb: reps must be 1..1000");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != lf->device)
+    return fail(LFC_E_INVALID, "lfc_tune_decode_rgb: the light field was opened on another device");
+  std::memset(res, 0, sizeof *res);
+  const Geometry &g = lf->geo;
+  if (g.L < 2) return fail(LFC_E_UNSUPPORTED, "lfc_tune_decode_rgb: no residual levels to tile");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(LFC_E_HIP, "lfc_tune_decode_rgb: events");
+  }
+  auto timed = [&](float *ms) -> lfc_status {
+    lfc_status st = lfc_decode_rgb(lf, d_out, s);
+    if (st != LFC_OK) return st;
+    if (hipEventRecord(e0, s) != hipSuccess) return fail(LFC_E_HIP, "lfc_tune_decode_rgb: event record");
+    for (int r = 0; r < reps && st == LFC_OK; r++) st = lfc_decode_rgb(lf, d_out, s);
+    if (st != LFC_OK) return st;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+      return fail(LFC_E_HIP, "lfc_tune_decode_rgb: timing");
+    *ms /= (float)reps;
+    return LFC_OK;
+  };
+  struct Saved {
+    int cap, max_chunks;
+    const uint32_t *sched, *strip_off, *order;
+    void *own;
+  };
+  auto save = [&]() {
+    return Saved{lf->tile_cap_rgb, lf->rgb_max_chunks, lf->d_sched_rgb, lf->d_strip_off_rgb, lf->d_order_rgb,
+                 lf->d_sched_rgb_own};
+  };
+  auto restore = [&](const Saved &v) {
+    lf->tile_cap_rgb = v.cap;
+    lf->rgb_max_chunks = v.max_chunks;
+    lf->d_sched_rgb = v.sched;
+    lf->d_strip_off_rgb = v.strip_off;
+    lf->d_order_rgb = v.order;
+    lf->d_sched_rgb_own = v.own;
+  };
+  std::vector<Saved> cands;
+  cands.push_back(save());
+  float ms = 0.0f;
+  lfc_status st = timed(&ms);
+  if (st == LFC_OK) {
+    res->tile_blocks[0] = lf->tile_cap_rgb;
+    res->ms[0] = ms;
+    res->n_tried = 1;
+  }
+  try {
+    std::vector<uint32_t> off, srv, dbase, poff;
+    std::vector<int32_t> batch((size_t)lf->n_batch * kBatchWords);
+    off.resize((size_t)g.ng + 1);
+    if (st == LFC_OK && hipMemcpy(off.data(), lf->d_off, 4 * off.size(), hipMemcpyDeviceToHost) != hipSuccess)
+      st = fail(LFC_E_HIP, "lfc_tune_decode_rgb: copy of the offsets");
+    if (st == LFC_OK) {
+      srv.resize((size_t)off[g.ng] + 2);
+      dbase.resize((size_t)g.ng * g.nbw);
+      poff.resize(std::max<uint64_t>(lf->present, 1));
+      if (hipMemcpy(srv.data(), lf->d_srv, 4 * srv.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(dbase.data(), lf->d_dbase, 4 * dbase.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(poff.data(), lf->d_poff, 4 * poff.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+          (!batch.empty() &&
+           hipMemcpy(batch.data(), lf->d_batch, 4 * batch.size(), hipMemcpyDeviceToHost) != hipSuccess))
+        st = fail(LFC_E_HIP, "lfc_tune_decode_rgb: copy of the directory");
+    }
+    const int c0 = tile_blocks(g.B);
+    const int fr[5] = {4, 5, 6, 7, 10};   // eighths of the default capacity besides 8/8
+    for (int fi = 0; fi < 5 && st == LFC_OK && res->n_tried < LFC_TUNE_DECODE_MAX; fi++) {
+      const int cap = std::min(2048, std::max(512 / g.B, c0 * fr[fi] / 8 / 8 * 8));
+      bool seen = false;
+      for (const Saved &v : cands) seen |= v.cap == cap;
+      if (seen) continue;
+      StripTables t;
+      make_strip_tables_rgb(g, off, srv, dbase, poff, batch, cap, t);
+      const size_t a1 = align256(4 * t.sched.size()), a2 = a1 + align256(4 * t.strip_off.size());
+      const size_t total = a2 + align256(4 * t.order.size());
+      void *buf = nullptr;
+      if (hipMalloc(&buf, total) != hipSuccess) {
+        (void)hipGetLastError();
+        break;   // no room for another table set: keep what was measured
+      }
+      char *d = static_cast<char *>(buf);
+      if (hipMemcpy(d, t.sched.data(), 4 * t.sched.size(), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(d + a1, t.strip_off.data(), 4 * t.strip_off.size(), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(d + a2, t.order.data(), 4 * t.order.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(buf);
+        st = fail(LFC_E_HIP, "lfc_tune_decode_rgb: copy of the strip tables");
+        break;
+      }
+      int max_chunks = 1;
+      for (size_t k = 0; k + 1 < t.strip_off.size(); k++)
+        max_chunks = std::max<int>(max_chunks, (int)t.sched[t.strip_off[k]]);
+      lf->tile_cap_rgb = cap;
+      lf->rgb_max_chunks = max_chunks;
+      lf->d_sched_rgb = reinterpret_cast<const uint32_t *>(d);
+      lf->d_strip_off_rgb = reinterpret_cast<const uint32_t *>(d + a1);
+      lf->d_order_rgb = reinterpret_cast<const uint32_t *>(d + a2);
+      lf->d_sched_rgb_own = buf;
+      cands.push_back(save());
+      const lfc_status ts = timed(&ms);
+      if (ts == LFC_E_UNSUPPORTED) {   // the tile does not fit the LDS: not a candidate
+        (void)hipGetLastError();
+        (void)hipFree(buf);
+        cands.pop_back();
+        restore(cands[0]);
+        continue;
+      }
+      if (ts != LFC_OK) {
+        st = ts;
+        break;
+      }
+      res->tile_blocks[res->n_tried] = cap;
+      res->ms[res->n_tried] = ms;
+      res->n_tried++;
+    }
+  } catch (const std::bad_alloc &) {
+    st = fail(LFC_E_NOMEM, "lfc_tune_decode_rgb: out of host memory");
+  }
+  (void)hipStreamSynchronize(s);
+  if (st != LFC_OK || res->n_tried == 0) {
+    for (size_t k = 1; k < cands.size(); k++)
+      if (cands[k].own) (void)hipFree(cands[k].own);
+    restore(cands[0]);
+  } else {
+    int best = 0;
+    for (int k = 1; k < res->n_tried; k++)
+      if (res->ms[k] < res->ms[best]) best = k;
+    res->best = best;
+    // candidate k of the results is table set k (every timed set was kept)
+    for (size_t k = 1; k < cands.size(); k++)
+      if ((int)k != best && cands[k].own) (void)hipFree(cands[k].own);
+    if (best != 0 && cands[0].own) (void)hipFree(cands[0].own);
+    restore(cands[(size_t)best]);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
 extern "C" lfc_status lfc_close(lfc_lf *lf) {
   if (!lf) return LFC_OK;
   if (lf->d_sched_own) (void)hipFree(lf->d_sched_own);
+  if (lf->d_sched_rgb_own) (void)hipFree(lf->d_sched_rgb_own);
   hipError_t he = hipFree(lf->d_base);
   delete lf;
   if (he != hipSuccess) return fail(LFC_E_HIP, std::string("lfc_close: ") + hipGetErrorString(he));

@@ -106,6 +106,7 @@ struct lfc_lf {
   int64_t stage_cap = 0;             // LDS words for staging a strip (-1: as it needs, 0: none); the
                                      // setting used when a decode call gives none
   void *d_sched_own = nullptr;       // strip tables chosen by lfc_tune_decode (else inside d_base)
+  void *d_sched_rgb_own = nullptr;   // colour strip tables chosen by lfc_tune_decode_rgb (else inside d_base)
   uint32_t max_strip_words = 0;      // largest group words + decode schedule of a strip of 64/B blocks of
                                      // one channel
   std::vector<uint32_t> strip_need;  // per strip: group words + schedule words, schedule words

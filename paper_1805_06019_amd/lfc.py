@@ -177,6 +177,7 @@ def load() -> C.CDLL:
         L.lfc_stage_needs.restype = i64
         L.lfc_render_views.argtypes = [vp, vp, i32, i32, i32, vp, vp]
         L.lfc_tune_decode.argtypes = [vp, vp, i32, C.POINTER(c_decode_tuning), vp]
+        L.lfc_tune_decode_rgb.argtypes = [vp, vp, i32, C.POINTER(c_decode_tuning), vp]
         L.lfc_encode_gpu.argtypes = [vp, C.POINTER(c_params), C.POINTER(vp), C.POINTER(sz), C.POINTER(c_stats), vp]
         L.lfc_control_rows.argtypes = [C.POINTER(c_params)]
         L.lfc_control_rows.restype = i64
@@ -220,7 +221,7 @@ def load() -> C.CDLL:
         L.lfc_server_destroy.argtypes = [vp]
         for f in ("lfc_encode", "lfc_encode_ex", "lfc_validate", "lfc_open", "lfc_open_ex", "lfc_info",
                   "lfc_decode_blocks", "lfc_decode_blocks_ex",
-                  "lfc_render_views", "lfc_render_views_ex", "lfc_render_views_noalloc", "lfc_encode_ctl", "lfc_tune_decode", "lfc_encode_gpu", "lfc_mlp_infer", "lfc_mlp_infer_ex", "lfc_mlp_grad",
+                  "lfc_render_views", "lfc_render_views_ex", "lfc_render_views_noalloc", "lfc_encode_ctl", "lfc_tune_decode", "lfc_tune_decode_rgb", "lfc_encode_gpu", "lfc_mlp_infer", "lfc_mlp_infer_ex", "lfc_mlp_grad",
                   "lfc_mlp_adam", "lfc_render_tune", "lfc_render_plan_create",
                   "lfc_render_plan_launch", "lfc_render_plan_info", "lfc_check", "lfc_close", "lfc_decode_progressive", "lfc_decode_rgb", "lfc_batch_create",
                   "lfc_batch_decode", "lfc_batch_check", "lfc_batch_render", "lfc_batch_plan_create",
@@ -513,6 +514,21 @@ def lfc_tune_decode_ex(lf: LightField, reps: int = 5, out=None, cuda_stream=None
     _check(load().lfc_tune_decode(lf.handle, out.data_ptr(), reps, C.byref(res), _stream_ptr(cuda_stream)))
     tried = [(int(res.tile_blocks[k]), bool(res.staged[k]), float(res.ms[k])) for k in range(res.n_tried)]
     return tried[res.best][:2], tried
+
+
+def lfc_tune_decode_rgb(lf: LightField, reps: int = 5, out=None, cuda_stream=None):
+    """Measured choice of the colour whole-field kernel's tile capacity (kept
+    in the handle); returns (kept capacity, [(capacity, ms)])."""
+    import torch
+    i = lf.info
+    shape = (i.params.grid_u * i.params.grid_v, i.padded_height, i.padded_width)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.int32, device="cuda")
+    assert out.dtype == torch.int32 and out.is_cuda and out.is_contiguous() and tuple(out.shape) == shape
+    res = c_decode_tuning()
+    _check(load().lfc_tune_decode_rgb(lf.handle, out.data_ptr(), reps, C.byref(res), _stream_ptr(cuda_stream)))
+    tried = [(int(res.tile_blocks[k]), float(res.ms[k])) for k in range(res.n_tried)]
+    return tried[res.best][0], tried
 
 
 def lfc_stage_needs(lf: LightField) -> np.ndarray:

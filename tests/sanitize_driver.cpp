@@ -21,7 +21,7 @@ extern "C" {
 #include "../oracle/oracle.h"
 }
 
-// stubs for the two GPU calls of host.cpp (never reached without a device)
+// stubs for the GPU calls of host.cpp (never reached without a device)
 namespace lfc {
 lfc_status mlp_infer_rows(const void *, const float *, int64_t, int8_t *, int8_t *, float *, hipStream_t) {
   return LFC_E_UNSUPPORTED;
@@ -30,6 +30,7 @@ lfc_status mlp_infer_rows(const void *, const float *, int64_t, int8_t *, int8_t
 extern "C" lfc_status lfc_decode_blocks(const lfc_lf *, const int32_t *, int64_t, int32_t, int16_t *, hipStream_t) {
   return LFC_E_UNSUPPORTED;
 }
+extern "C" lfc_status lfc_decode_rgb(const lfc_lf *, uint32_t *, hipStream_t) { return LFC_E_UNSUPPORTED; }
 
 namespace {
 

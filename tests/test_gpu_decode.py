@@ -402,6 +402,39 @@ def test_decode_tuner_keeps_the_output(gpu, case):
     lf.close()
 
 
+@pytest.mark.parametrize("case", [GEOMS[0], GEOMS[3], GEOMS[5], GEOMS[6], GEOMS[7]],
+                         ids=["8x8-B4", "17x17-L3", "B8", "B2", "L4"])
+def test_rgb_tuner_keeps_the_output(gpu, case):
+    # the colour kernel's tile capacity: every capacity the tuner times gives
+    # the oracle's RGB words, and a decode-then-interpolate render gives the
+    # same bytes before and after; a second tuning replaces the first's tables
+    U, V, W, H, kw = case
+    say("tune rgb", case)
+    rgb = make_lf(U, V, W, H, seed=U * 13 + W)
+    enc = oracle_encode(rgb, **kw)
+    lf = gpu_open(enc.stream)
+    want = oracle_rgb_words(enc.r0)
+    views = torch.from_numpy(synth.novel_views(6, U, V, seed=U + 5)).cuda()
+    before = lfc.lfc_render_views(lf, views, 40, 30, cfg=(lfc.RENDER_DECODED, 0, 0, 0.0))
+    for _ in range(2):
+        best, tried = lfc.lfc_tune_decode_rgb(lf, reps=2)
+        say("tried", tried, "kept", best)
+        assert best in [c for c, _ in tried] and all(ms > 0 for _, ms in tried) and len(tried) >= 3
+        assert np.array_equal(lfc.lfc_decode_rgb(lf).cpu().numpy(), want)
+        after = lfc.lfc_render_views(lf, views, 40, 30, cfg=(lfc.RENDER_DECODED, 0, 0, 0.0))
+        assert torch.equal(before, after)
+    lf.close()
+
+
+def test_rgb_tuner_errors(gpu):
+    U, V, W, H, kw = GEOMS[1]
+    assert kw["levels"] == 1
+    lf = gpu_open(oracle_encode(make_lf(U, V, W, H, seed=3), **kw).stream)
+    with pytest.raises(lfc.LFCError):
+        lfc.lfc_tune_decode_rgb(lf, reps=2)
+    lf.close()
+
+
 def test_decode_tuner_on_full40(gpu, full40):
     w, rgb, enc = full40
     say("full40: tuning the whole-field decode")
