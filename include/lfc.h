@@ -436,8 +436,9 @@ lfc_status lfc_decode_rgb(const lfc_lf *lf, uint32_t *d_out, hipStream_t s);
  * (one warm-up, then `reps` launches, events on stream s, output to d_out as
  * lfc_decode_rgb) with the handle's current capacity and with 4/8, 5/8, 6/8,
  * 7/8 and 10/8 of the default (those whose tile fits the LDS), rebuilding the
- * colour strip tables for each, and keeps the fastest in the handle; res
- * reports the capacities tried (staged[] all 0).  A smaller tile leaves room
+ * colour strip tables for each, and keeps the fastest in the handle unless it
+ * is within 2 % of the current one (then the current stays); res reports
+ * the capacities tried (staged[] all 0).  A smaller tile leaves room
  * for more workgroups per compute unit, a larger one needs fewer chunks per
  * strip; which wins depends on the light field.  Blocks until done.  The
  * handle must not be in use by another call (renders, batches) meanwhile.
