@@ -456,13 +456,16 @@ lfc_status lfc_tune_decode_rgb(lfc_lf *lf, uint32_t *d_out, int32_t reps, lfc_de
  * converted to RGB (inverse YCoCg-R, clamped to 0..255).  Source pixel
  * coordinates of output pixel (X, Y) are s + (X+0.5)*width/out_w - 0.5 and
  * t + (Y+0.5)*height/out_h - 0.5, clamped to the image.  The blocks under
- * each output tile are decoded on the fly, or, for large batches, every
- * source view is decoded once and the pixels interpolated from the decoded
- * planes; both give the same bytes.
+ * each output tile are decoded on the fly, or, for large batches, the
+ * source views the batch reads are decoded once (as 8-bit RGB) and the
+ * pixels interpolated from them; both give the same bytes.  The decoded
+ * views go to stream-ordered device scratch (4 x views x padded pixels
+ * bytes) from a memory pool of the library's own per device, which keeps up
+ * to 1 GiB of freed scratch for later calls until the process ends.
  *  d_views  device lfc_view [n].
  *  d_out    device float32 [n][3][out_h][out_w], RGB / 255.
  * Errors: LFC_E_INVALID (null pointer, n < 0, out_w or out_h < 1 or
- * > 16384), LFC_E_HIP.
+ * > 16384), LFC_E_NOMEM (scratch), LFC_E_HIP.
  */
 lfc_status lfc_render_views(const lfc_lf *lf, const lfc_view *d_views, int32_t n, int32_t out_w,
                             int32_t out_h, float *d_out, hipStream_t s);
