@@ -338,6 +338,40 @@ __device__ __forceinline__ void decode_block_k(const uint32_t *gw, uint32_t e, i
   const uint32_t code = e & 31u, rel = e >> 5;
   const uint32_t m = KIND == 0 ? code + 1u : (KIND == 1 ? code - 12u : code - 19u);
   const uint32_t lmask = (1u << m) - 1u;
+  if constexpr (B <= 4 && KIND != 0) {
+    // Trits and quints at B <= 4: a row's low bits (B*m <= 24) lie in one
+    // 32-bit window of two words, and the digit plane (at most 38 bits) is
+    // read once, in two or three words, and expanded field by field: every
+    // field is looked up once instead of once per row that shares it.
+    constexpr uint32_t DPG = KIND == 1 ? 5u : 3u;   // digits per field
+    constexpr int NG = (int)((S + DPG - 1) / DPG);
+    using AllDigits = std::conditional_t<(KIND == 2 && S > 10), uint64_t, uint32_t>;
+    const uint32_t *qd = gw + (rel >> 5);
+    const uint32_t sh = rel & 31u;
+    uint64_t plane = __builtin_amdgcn_alignbit(qd[1], qd[0], sh);
+    if constexpr (HDR > 32) plane |= (uint64_t)__builtin_amdgcn_alignbit(qd[2], qd[1], sh) << 32;
+    AllDigits D = 0;
+#pragma unroll
+    for (int g = 0; g < NG; g++) {
+      const uint32_t off = (uint32_t)g * FW;
+      const uint32_t wdt = HDR - off < FW ? HDR - off : FW;
+      D |= (AllDigits)lut[LB + ((uint32_t)(plane >> off) & ((1u << wdt) - 1u))] << (g * GB);
+    }
+#pragma unroll
+    for (int y = 0; y < B; y++) {
+      const uint32_t p = rel + HDR + (uint32_t)(y * B) * m;
+      const uint32_t *qr = gw + (p >> 5);
+      const uint32_t lo = __builtin_amdgcn_alignbit(qr[1], qr[0], p & 31u);
+      uint32_t u[B];
+#pragma unroll
+      for (int k = 0; k < B; k++)
+        u[k] = __builtin_amdgcn_ubfe(lo, (uint32_t)k * m, m) |
+               ((((uint32_t)(D >> ((y * B + k) * DB))) & DMASK) << m);
+#pragma unroll
+      for (int i = 0; i < B / 2; i++) d[y * (B / 2) + i] = unzigzag_pk(u[2 * i] | (u[2 * i + 1] << 16), q);
+    }
+    return;
+  }
 #pragma unroll
   for (int y = 0; y < B; y++) {
     uint32_t u[B];
