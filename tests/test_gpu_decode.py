@@ -4,7 +4,8 @@ Bit-exact: every decoded int16 sample equals the oracle's closed-loop
 reconstruction R^0, which its own decoders reproduce (pinned in
 test_oracle_codec.py).  Covers the whole-field kernel (images layout), the
 random-access kernel (blocks layout, all blocks or a request list), ragged
-images, block sizes 2/4/8, tree heights 1-6, empty and out-of-range requests,
+images, block sizes 2/4/8, tree heights 1-6, every range code of each kind
+(plain bits, trits, quints) that 8-bit views reach, empty and out-of-range requests,
 the staging tiers of the whole-field kernel, progressive decompression at
 every tree level (Sec. 3.6), and the full 17x17x512x512 workload in the
 launch configuration the benchmark times.
@@ -79,6 +80,48 @@ def test_whole_field_images_layout(gpu, case):
     # repeatable: a second run is bit-identical
     out2 = lfc.lfc_decode_blocks(lf, None, lfc.LAYOUT_IMAGES)
     assert torch.equal(out, out2)
+
+
+# Range codes restricted to one kind (Sec. 3.3: plain bits, trits, quints),
+# on light fields whose residuals reach the largest codes of the kind: views
+# of uniform noise of a given amplitude (and the smooth synthetic field for
+# the small codes), with the quantiser shift q.  Per kind: the noise
+# amplitudes and shifts used, and the code every block size must reach.
+KIND_CASES = {
+    "plain": ((1 << 12) - 1, [(64, 0), (256, 0), (0, 0)], 8),
+    "trit": (0x7F000, [(64, 0), (128, 1), (256, 2), (0, 0)], 18),
+    "quint": (0x3F80000, [(64, 0), (128, 0), (256, 1), (0, 0)], 25),
+}
+
+
+@pytest.mark.parametrize("B", [2, 4, 8])
+@pytest.mark.parametrize("kind", list(KIND_CASES))
+def test_every_range_code_of_a_kind(gpu, kind, B):
+    # the whole-field kernel, the colour kernel and random access against the
+    # oracle, block by block, with every code of the kind that 8-bit views
+    # reach: trits and quints up to m = 6, plain bits up to m = 10 (over 32
+    # bits per row at B = 4)
+    mask, configs, top = KIND_CASES[kind]
+    rs = np.random.default_rng(1000 + B)
+    seen = set()
+    for amp, q in configs:
+        say("kind", kind, "B", B, "noise", amp, "q", q)
+        if amp:
+            rgb = (rs.integers(0, amp, size=(3, 3, 40, 48, 3)) + (128 - amp // 2)).clip(0, 255).astype(np.uint8)
+        else:
+            rgb = make_lf(3, 3, 48, 40, seed=7, sigma=2.0)
+        enc = oracle_encode(rgb, block=B, levels=2, cluster=(2,), range_mask=mask, quant_bits=q)
+        seen |= {c for c in range(26) if enc.hist[c]}
+        lf = gpu_open(enc.stream)
+        assert np.array_equal(lfc.lfc_decode_blocks(lf, None, lfc.LAYOUT_IMAGES).cpu().numpy(), enc.r0)
+        assert np.array_equal(lfc.lfc_decode_rgb(lf).cpu().numpy(), oracle_rgb_words(enc.r0))
+        allb = lfc.lfc_decode_blocks(lf, None, lfc.LAYOUT_BLOCKS).cpu().numpy()
+        assert np.array_equal(allb, blocks_of(enc.r0, B).reshape(-1, 3, B, B))
+        lfc.lfc_check(lf)
+        lf.close()
+    lo, hi = {"plain": (0, 11), "trit": (12, 18), "quint": (19, 25)}[kind]
+    assert seen and min(seen) >= lo and max(seen) <= hi
+    assert top in seen, (kind, B, sorted(seen))
 
 
 @pytest.mark.parametrize("tiers", ["global", "no-payload", "mixed", "as-needed"])
