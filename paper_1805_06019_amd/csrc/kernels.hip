@@ -121,8 +121,8 @@ __device__ __forceinline__ uint32_t add_pk(uint32_t a, uint32_t b) { return as_u
 // below 2^12 (at most 12 plain bits, or 6 bits below a trit or quint digit),
 // so nothing crosses between the halves; equal, for all such pairs and every
 // q, to unzigzagging each half and shifting it left by q (checked
-// exhaustively on the host).  Five VALU operations per pair against seven
-// with packed 16-bit shifts.
+// exhaustively on the host by tests/arith_identities.c).  Five VALU
+// operations per pair against seven with packed 16-bit shifts.
 __device__ __forceinline__ uint32_t unzigzag_pk(uint32_t z, int q) {
   const uint32_t rot = (uint32_t)(33 - q) & 31u;
   const uint32_t inv = q ? (0xFFFFu << (q - 1)) & 0xFFFFu : 0xFFFFu;   // the bits a negative value inverts
@@ -985,9 +985,10 @@ __device__ __forceinline__ float src_pos(float s, int X, float scale) {
 }
 
 // x / 255 for 0 <= x <= 255, rounded as the IEEE quotient: the product with
-// the rounded reciprocal, corrected by one fused residual step (checked
-// against the division for every float of the range, both signs give the
-// same result by symmetry); three VALU operations instead of a full division.
+// the rounded reciprocal, corrected by one fused residual step (equal to the
+// division for every float of the range, checked on the host by
+// tests/arith_identities.c; negative inputs mirror it); three VALU operations
+// instead of a full division.
 __device__ __forceinline__ float div255(float x) {
   constexpr float r = 1.0f / 255.0f;
   const float q = x * r;
