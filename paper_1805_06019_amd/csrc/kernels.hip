@@ -1208,6 +1208,10 @@ struct RGBArgs {
   int n_top, key_words;       // LDS words of the strip's key-view rows of all channels (0: read from global)
   int tile_cap;
   int parts;                  // workgroups per strip: part p takes the chunks ci with ci % parts == p
+  // with vneed null: the cameras of a render, whose four grid neighbours
+  // each workgroup marks itself (null: every view, unless vneed is given)
+  const lfc_view *views = nullptr;
+  int nviews = 0, U = 0, V = 0;
 };
 
 // One workgroup = one strip of 64/B blocks of one block row, all three
@@ -1240,15 +1244,29 @@ __device__ __forceinline__ void rgb_strip(const RGBArgs &a, int st, int part, ui
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int sx = st % a.nsx, by = st / a.nsx;
-  const bool masked = a.vneed != nullptr;
+  const bool masked = a.vneed != nullptr || a.views != nullptr;
   if (tid < S / 2) tile[a.tile_cap * (S / 2) + tid] = 0u;
   if (tid < 64)
     for (int k = lane; k < 3 * NBLK; k += 64) {
       const int c = k / NBLK, bx = sx * NBLK + k % NBLK;
       s_o0[k] = bx < a.nbx ? a.off[3 * (by * a.nbx + bx) + c] : 0u;
     }
-  if (masked)
+  if (a.vneed) {
     for (int w = tid; w < (a.nv + 31) / 32; w += kLFThreads) s_need[w] = a.vneed[w];
+  } else if (a.views) {
+    // the source views the cameras read: each camera's four grid neighbours
+    for (int w = tid; w < (a.nv + 31) / 32; w += kLFThreads) s_need[w] = 0u;
+    lds_barrier();
+    for (int i = tid; i < a.nviews; i += kLFThreads) {
+      int iu0, iu1, jv0, jv1;
+      float fu, fv;
+      cell(a.views[i].u, a.U, iu0, iu1, fu);
+      cell(a.views[i].v, a.V, jv0, jv1, fv);
+      const int vs[4] = {jv0 * a.U + iu0, jv0 * a.U + iu1, jv1 * a.U + iu0, jv1 * a.U + iu1};
+#pragma unroll
+      for (int k = 0; k < 4; k++) atomicOr(&s_need[vs[k] >> 5], 1u << (vs[k] & 31));
+    }
+  }
   if constexpr (KEYS) {
     const uint32_t *rk = reinterpret_cast<const uint32_t *>(a.rkv);
     for (int t0 = wave * 64; t0 < a.key_words; t0 += kLFThreads) {
@@ -1619,27 +1637,6 @@ __global__ __launch_bounds__(kThreads) void k_interp_multi(const InterpReq *reqs
   interp_rgb_pixel<false>(r.a, r.view, r.a.out, X, Yp);
 }
 
-// The source views a batch of novel views reads (the four grid neighbours of
-// each camera), as a bit per view: one workgroup builds the mask in LDS and
-// writes every word of it.
-__global__ __launch_bounds__(kThreads) void k_need_views(const lfc_view *views, int n, int U, int V, int words,
-                                                         uint32_t *mask) {
-  extern __shared__ uint32_t sm[];
-  for (int w = threadIdx.x; w < words; w += kThreads) sm[w] = 0u;
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += kThreads) {
-    int iu0, iu1, jv0, jv1;
-    float fu, fv;
-    cell(views[i].u, U, iu0, iu1, fu);
-    cell(views[i].v, V, jv0, jv1, fv);
-    const int vs[4] = {jv0 * U + iu0, jv0 * U + iu1, jv1 * U + iu0, jv1 * U + iu1};
-#pragma unroll
-    for (int k = 0; k < 4; k++) atomicOr(&sm[vs[k] >> 5], 1u << (vs[k] & 31));
-  }
-  __syncthreads();
-  for (int w = threadIdx.x; w < words; w += kThreads) mask[w] = sm[w];
-}
-
 // ---------------------------------------------------------------------------
 // host-side checks and launches
 // ---------------------------------------------------------------------------
@@ -1783,7 +1780,8 @@ lfc_status decode_images(const lfc_lf *lf, int16_t *out, hipStream_t s, int64_t 
 // Every view (or those whose bit is set in vneed) as 8-bit RGB words
 // [nv][hp][wp], inverse YCoCg-R and clamp applied to the decoded samples.
 template <int B>
-lfc_status decode_rgb(const lfc_lf *lf, uint32_t *out, const uint32_t *vneed, hipStream_t s, const char *who) {
+lfc_status decode_rgb(const lfc_lf *lf, uint32_t *out, const uint32_t *vneed, hipStream_t s, const char *who,
+                      const lfc_view *views = nullptr, int nviews = 0) {
   const lfc::Geometry &g = lf->geo;
   constexpr int NBLK = 64 / B;
   if ((uint64_t)g.nv() * g.hp * g.wp >= ((uint64_t)1 << 32))
@@ -1798,10 +1796,16 @@ lfc_status decode_rgb(const lfc_lf *lf, uint32_t *out, const uint32_t *vneed, hi
   // workgroups (about three per compute unit), at most the strips' chunk count
   int parts = std::max(1, std::min(lf->rgb_max_chunks, (3 * 3 * device_cus() + nstrips - 1) / nstrips));
   // a view mask longer than the kernel's LDS copy of it: every view is decoded
-  if (g.nv() > 32 * kRGBNeedWords) vneed = nullptr;
+  if (g.nv() > 32 * kRGBNeedWords) vneed = nullptr, views = nullptr;
   RGBArgs a{lf->d_rkv, lf->d_off, lf->d_srv, lf->d_sched_rgb, lf->d_strip_off_rgb, lf->d_order_rgb, lf->d_batch,
             vneed, out, g.nbx, nsx, g.L, g.q, g.wp, g.hp, g.nb, lf->n_batch, g.nv(), g.n_top, key_words,
             lf->tile_cap_rgb, parts};
+  if (!vneed && views && nviews > 0) {
+    a.views = views;
+    a.nviews = nviews;
+    a.U = g.U;
+    a.V = g.V;
+  }
   const dim3 grid((unsigned)(nstrips * parts));
   if (key_words)
     hipLaunchKernelGGL((k_decode_rgb<B, true>), grid, dim3(kLFThreads), lds, s, a);
@@ -1902,10 +1906,9 @@ lfc_status choose_render(const lfc_lf *lf, int32_t n, int32_t wo, int32_t ho, co
 }
 
 // Scratch of the decode-then-interpolate path: the source views as 8-bit
-// RGB words, then the mask of the views a batch reads.
+// RGB words.
 size_t rgb_bytes(const lfc::Geometry &g) { return (size_t)g.nv() * g.hp * g.wp * sizeof(uint32_t); }
-int need_words(const lfc::Geometry &g) { return (g.nv() + 31) / 32; }
-size_t decoded_bytes(const lfc::Geometry &g) { return ((rgb_bytes(g) + 255) & ~(size_t)255) + 4 * (size_t)need_words(g); }
+size_t decoded_bytes(const lfc::Geometry &g) { return rgb_bytes(g); }
 
 // One render with a resolved choice.  The decoded path decodes into ws when
 // given, else into stream-ordered scratch from the library's pool.
@@ -1918,12 +1921,9 @@ lfc_status render_with(const lfc_lf *lf, const lfc_view *views, int32_t n, int32
     if (!dec && lfc::scratch_alloc(&dec, decoded_bytes(g), s) != LFC_OK)
       return fail(LFC_E_NOMEM, "lfc_render_views: scratch for the decoded views");
     uint32_t *rgb = static_cast<uint32_t *>(dec);
-    uint32_t *mask = reinterpret_cast<uint32_t *>(static_cast<char *>(dec) + ((rgb_bytes(g) + 255) & ~(size_t)255));
-    // the views the batch reads, then those views decoded, then the interpolation
-    hipLaunchKernelGGL(k_need_views, dim3(1), dim3(kThreads), 4 * (size_t)need_words(g), s, views, n, g.U, g.V,
-                       need_words(g), mask);
-    lfc_status st = launched("lfc_render_views");
-    if (st == LFC_OK) st = decode_rgb<B>(lf, rgb, mask, s, "lfc_render_views");
+    // the views the batch reads (found by each workgroup of the colour
+    // decode from the cameras) decoded, then the interpolation
+    lfc_status st = decode_rgb<B>(lf, rgb, nullptr, s, "lfc_render_views", views, n);
     if (st == LFC_OK) {
       InterpRGBArgs ia{rgb, (uint32_t)rgb_bytes(g), views, out, wo, ho, g.U, g.V, g.W, g.H, g.wp, g.hp, rc.disp,
                        (float)g.W / (float)wo, (float)g.H / (float)ho};
